@@ -1,0 +1,210 @@
+/*
+ * sky.h -- C ABI of libsky: skyline over partitioned data and grid resistance (gres) of the
+ * skyline tuples, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Parallelizing the Computation of Robustness for Measuring the Strength of Tuples"
+ * (arXiv 2412.02274). Definitions used below:
+ *   Def. 1 (Sec. 2)   dominance s < t: s[A] <= t[A] for every attribute, < for at least one
+ *                     (smaller is better); Sky(r) = tuples of r dominated by no tuple of r.
+ *   Def. 2 (Sec. 2)   grid projection gproj(t,g) = < floor(t[i]*g)/g >; grid resistance
+ *                     gres(t;r) = min { 1/g : gproj(t,g) not in Sky(gproj(r,g)) }, 1 if none.
+ *   Sec. 3            two-phase parallel skyline: local skylines of partitions, then the
+ *                     skyline of their union.
+ *   Sec. 3.1          Grid (with grid dominance, Def. 3), Angle-based (Eq. (1)) and Sliced
+ *                     partitioning; Sec. 4: Grid/Angular use the closest achievable p > 1.
+ *   Alg. 1 (Sec. 3.2) gres of every skyline tuple, scanning g from g_max down to 2.
+ *
+ * Conventions shared by every entry point
+ *   - Relations are FP32 in structure-of-arrays layout: attribute k of row i at x[k*ld + i],
+ *     ld >= n. Row indices are 0-based. Values must be finite and in [0, 1) (the domain the
+ *     paper assumes for its data and for Grid numbering); -0.0 is accepted and treated as 0.
+ *   - Quantisation contract: the projected key of value v at level g is
+ *     (int)floorf(v * (float)g) with ONE IEEE FP32 multiply rounded to nearest even (no FMA,
+ *     no fast-math); dominance between projections compares these integer keys.
+ *   - All pointers named dev_* / x / ws / outputs are DEVICE pointers; the caller owns them
+ *     (typically torch tensors) and keeps them alive until the work on `stream` has finished
+ *     (and, for a plan, until sky_plan_destroy). The library never allocates or frees device
+ *     memory and never changes the current device.
+ *   - Argument errors are returned synchronously with no device work queued. Data-dependent
+ *     errors (a value outside the domain, an output capacity that is too small) are written
+ *     to the device word *dev_status (first error wins; the caller zeroes it beforehand and
+ *     reads it after synchronising the stream). Outputs are defined only when both are SKY_OK.
+ *   - Work is queued on `stream` (a hipStream_t passed as void*; NULL = the null stream).
+ *     sky_local_skylines and sky_merge read small counters back to the host between rounds
+ *     (they synchronise `stream`); sky_ingest, sky_build and gres_compute never synchronise.
+ *   - Thread safety: plans are independent; a plan must not be used by two threads at once.
+ *     No global mutable state.
+ */
+#ifndef SKY_H
+#define SKY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sky_status {
+    SKY_OK = 0,
+    SKY_ERR_INVALID_ARG = 1, /* null pointer, bad size, bad option */
+    SKY_ERR_DOMAIN = 2,      /* a value is NaN/inf or outside [0, 1) (device-side) */
+    SKY_ERR_WORKSPACE = 3,   /* ws_bytes below the size returned by the *_workspace_bytes call */
+    SKY_ERR_CAPACITY = 4,    /* output capacity too small (device-side; size in *dev_count) */
+    SKY_ERR_HIP = 5,         /* a HIP runtime call failed */
+    SKY_ERR_STATE = 6,       /* call out of order on a plan */
+    SKY_ERR_UNSUPPORTED = 7  /* valid request outside the implemented limits */
+} sky_status;
+
+typedef enum sky_scheme {
+    SKY_NONE = 0,    /* one partition: plain skyline */
+    SKY_GRID = 1,    /* Sec. 3.1 Grid: p = m^d cells, cell pruning by grid dominance (Def. 3) */
+    SKY_ANGULAR = 2, /* Sec. 3.1 Angle-based, Eq. (1): p = m^(d-1) */
+    SKY_SLICED = 3   /* Sec. 3.1 Sliced: sort on one attribute, p equal-size slices */
+} sky_scheme;
+
+/* Limits of this implementation. */
+#define SKY_MAX_D 16           /* attributes per tuple */
+#define SKY_MAX_CELLS 4096     /* Grid / Angular partitions (m^d or m^(d-1)) */
+#define SKY_MAX_G 1048576      /* largest g_max accepted by gres_compute */
+
+/* gres_compute mapping choice (sky_gres_opts.mapping). */
+#define SKY_GRES_AUTO 0         /* pick by shape */
+#define SKY_GRES_TILES 1        /* one wave per tuple, lanes over candidate tiles */
+#define SKY_GRES_LEVELS 2       /* one wave per tuple, lanes over 64 consecutive levels g */
+
+typedef struct sky_params {
+    int32_t scheme;    /* sky_scheme */
+    int32_t target_p;  /* requested partitions; Grid/Angular take the closest m^e > 1 (Sec. 4),
+                          Sliced takes exactly min(target_p, n); ignored for SKY_NONE */
+    int32_t slice_dim; /* Sliced: attribute to sort on (0-based) */
+    int32_t flags;     /* reserved, must be 0 */
+} sky_params;
+
+typedef struct sky_info {
+    int64_t n;                /* rows */
+    int32_t d;                /* attributes */
+    int32_t scheme;           /* sky_scheme */
+    int32_t p;                /* actual number of partitions */
+    int32_t m;                /* slices per (angular) dimension for Grid/Angular, else 0 */
+    int32_t pruned_cells;     /* Grid: cells disregarded by grid dominance (after sky_local_skylines) */
+    int32_t rounds_local;     /* filter rounds run by sky_local_skylines */
+    int32_t rounds_merge;     /* filter rounds run by sky_merge */
+    int32_t state;            /* 1 built, 2 local skylines done, 3 merged */
+    int64_t pruned_rows;      /* Grid: rows inside pruned cells */
+    int64_t local_count;      /* size of the union of the local skylines */
+    int64_t sky_count;        /* size of the final skyline */
+    int64_t tests_local;      /* dominance tests evaluated in the local phase (counted on device) */
+    int64_t tests_merge;      /* dominance tests evaluated in the final phase */
+    int64_t max_partition;    /* rows in the largest partition */
+} sky_info;
+
+typedef struct sky_gres_opts {
+    int32_t mapping;   /* SKY_GRES_AUTO / SKY_GRES_TILES / SKY_GRES_LEVELS */
+    int32_t reserved[3];
+} sky_gres_opts;
+
+typedef struct sky_plan sky_plan; /* opaque, host-side; refers to caller memory */
+
+/* Human-readable name of a status code (static string). */
+const char* sky_status_string(sky_status s);
+
+/* Library version, as major*10000 + minor*100 + patch. */
+int32_t sky_version(void);
+
+/*
+ * sky_ingest -- the input step: validate a row-major relation and write it as SoA.
+ * x_rows: device float[n*d], row i at x_rows[i*d .. i*d+d). x_soa: device float[d*ld],
+ * written as x_soa[k*ld + i] with -0.0 replaced by +0.0. Values that are NaN/inf or outside
+ * [0, 1) raise SKY_ERR_DOMAIN in *dev_status (the copy is still written). n may be 0.
+ * Returns SKY_ERR_INVALID_ARG for null pointers (when n > 0), d outside [1, SKY_MAX_D],
+ * n < 0 or ld < n.
+ */
+sky_status sky_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, int64_t ld,
+                      int32_t* dev_status, void* stream);
+
+/*
+ * Workspace for sky_build / sky_local_skylines / sky_merge on one plan, in bytes (device
+ * memory, any alignment >= 256). Returns 0 for invalid arguments.
+ */
+size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params);
+
+/*
+ * sky_build -- partition assignment (Sec. 3.1) and the partition-contiguous copy.
+ * Validates the values (SKY_ERR_DOMAIN on device), computes the partition of every row
+ * (Grid: sum floor(x_k*m) m^k; Angular: Eq. (1); Sliced: rank on slice_dim, ties by row
+ * index, part = floor(rank*p/n); None: one partition), the Grid cells pruned by grid
+ * dominance, and a stable partition-contiguous SoA copy in the workspace.
+ * x_soa must stay valid until sky_merge returns. On success *out receives a new plan
+ * (host memory owned by the library; release it with sky_plan_destroy).
+ * n must be in [1, 2^31-1]; Grid/Angular need m^e <= SKY_MAX_CELLS (else SKY_ERR_UNSUPPORTED);
+ * Angular needs d >= 2.
+ */
+sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld,
+                     const sky_params* params, void* ws, size_t ws_bytes, int32_t* dev_status,
+                     void* stream, sky_plan** out);
+
+/*
+ * sky_local_skylines -- Sec. 3, phase 1: the skyline of every partition, all partitions at
+ * once. Rows of Grid cells pruned by grid dominance take no part. The result stays in the
+ * plan's workspace. Synchronises `stream` between filter rounds. SKY_ERR_STATE unless the
+ * plan is freshly built.
+ */
+sky_status sky_local_skylines(sky_plan* plan, void* stream);
+
+/*
+ * sky_merge -- Sec. 3, phase 2: the skyline of the union of the local skylines, which is
+ * Sky(r). Writes the row indices of Sky(r) in ascending order to sky_idx[0..count) (device
+ * int64[cap]), the count to *dev_count (device int64), and, if member is non-null, member[i]
+ * = 1 iff row i is in Sky(r) (device uint8[n]). If count > cap, SKY_ERR_CAPACITY goes to
+ * *dev_status, *dev_count holds the required size and sky_idx is left undefined.
+ * SKY_ERR_STATE unless sky_local_skylines has run on the plan.
+ */
+sky_status sky_merge(sky_plan* plan, int64_t* sky_idx, int64_t cap, int64_t* dev_count,
+                     uint8_t* member, void* stream);
+
+/*
+ * sky_plan_partitions -- inspection: part[i] = the partition of row i (device int32[n]),
+ * as assigned by sky_build (Sec. 3.1). Any state >= built.
+ */
+sky_status sky_plan_partitions(const sky_plan* plan, int32_t* part, void* stream);
+
+/*
+ * sky_plan_local -- inspection: local[i] = 1 iff row i belongs to the skyline of its own
+ * partition and its partition was not pruned (device uint8[n]). SKY_ERR_STATE before
+ * sky_local_skylines.
+ */
+sky_status sky_plan_local(const sky_plan* plan, uint8_t* local, void* stream);
+
+/* Plan inspection (host-side copy of the counters listed in sky_info). */
+sky_status sky_plan_info(const sky_plan* plan, sky_info* out);
+
+/* Releases a plan (host memory only). Null is accepted. */
+void sky_plan_destroy(sky_plan* plan);
+
+/*
+ * Workspace for gres_compute, in bytes. Returns 0 for invalid arguments.
+ */
+size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max);
+
+/*
+ * gres_compute -- Def. 2 through Alg. 1 for the tuples t = rows sky_idx[0..s) of x, with the
+ * same rows as the candidate set (gres is stable: dominated tuples never change it, so
+ * Sky(r) suffices; any superset gives the same answer).
+ * For each j: g_exit[j] = the largest g in [2, g_max] such that the projection of some other
+ * candidate dominates the projection of row sky_idx[j] at level g, or 1 if there is none;
+ * gres[j] = 1.0f / (float)g_exit[j]. g_exit and gres are device arrays of s entries; either
+ * may be null. sky_idx: device int64[s], each in [0, n) (checked on device:
+ * SKY_ERR_INVALID_ARG in *dev_status). s may be 0. g_max in [2, SKY_MAX_G].
+ * opts may be null (automatic mapping). Never synchronises.
+ */
+sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld,
+                        const int64_t* sky_idx, int64_t s, int32_t g_max, int32_t* g_exit,
+                        float* gres, void* ws, size_t ws_bytes, int32_t* dev_status,
+                        const sky_gres_opts* opts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKY_H */

@@ -138,14 +138,29 @@ int64_t orc_skyline_sfs(const float* x, int64_t n, int32_t d, int64_t ld, uint8_
 /* ------------------------------------------------------------------------------------------ */
 void orc_local_skylines(const float* x, int64_t n, int32_t d, int64_t ld, const int32_t* part,
                         const uint8_t* skip /* nullable, indexed by partition */, uint8_t* local) {
+    /* rows grouped by partition (a counting sort; bookkeeping only) so that each row is
+     * compared with the rows of its own partition */
+    int32_t p = 0;
+    for (int64_t i = 0; i < n; ++i) if (part[i] + 1 > p) p = part[i] + 1;
+    int64_t* start = (int64_t*)calloc((size_t)p + 1, sizeof(int64_t));
+    int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) start[part[i] + 1]++;
+    for (int32_t j = 0; j < p; ++j) start[j + 1] += start[j];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(p > 0 ? p : 1));
+    for (int32_t j = 0; j < p; ++j) fill[j] = start[j];
+    for (int64_t i = 0; i < n; ++i) rows[fill[part[i]]++] = i;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t t = 0; t < n; ++t) {
-        if (skip && skip[part[t]]) { local[t] = 0; continue; }
+        int32_t pt = part[t];
+        if (skip && skip[pt]) { local[t] = 0; continue; }
         uint8_t in = 1;
-        for (int64_t s = 0; s < n; ++s)
-            if (s != t && part[s] == part[t] && dominates(x, ld, d, s, t)) { in = 0; break; }
+        for (int64_t q = start[pt]; q < start[pt + 1]; ++q) {
+            int64_t s = rows[q];
+            if (s != t && dominates(x, ld, d, s, t)) { in = 0; break; }
+        }
         local[t] = in;
     }
+    free(start); free(rows); free(fill);
 }
 
 /* ------------------------------------------------------------------------------------------ */

@@ -1,0 +1,114 @@
+"""ctypes binding of libsky.so (the C ABI in include/sky.h). Argument marshalling only.
+
+The library is loaded from this package directory; there is no fallback: if it is missing the
+import of the compute entry points fails loudly (build it with ``python -m
+paper_2412_02274_amd.build`` or ``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsky.so")
+
+SKY_OK = 0
+SKY_ERR_INVALID_ARG = 1
+SKY_ERR_DOMAIN = 2
+SKY_ERR_WORKSPACE = 3
+SKY_ERR_CAPACITY = 4
+SKY_ERR_HIP = 5
+SKY_ERR_STATE = 6
+SKY_ERR_UNSUPPORTED = 7
+
+SKY_NONE, SKY_GRID, SKY_ANGULAR, SKY_SLICED = 0, 1, 2, 3
+SCHEMES = {"none": SKY_NONE, "grid": SKY_GRID, "angular": SKY_ANGULAR, "sliced": SKY_SLICED}
+
+SKY_GRES_AUTO, SKY_GRES_TILES, SKY_GRES_LEVELS = 0, 1, 2
+MAPPINGS = {"auto": SKY_GRES_AUTO, "tiles": SKY_GRES_TILES, "levels": SKY_GRES_LEVELS}
+
+SKY_MAX_D = 16
+SKY_MAX_CELLS = 4096
+SKY_MAX_G = 1048576
+
+# every function the header declares (checked against the header by the tests)
+EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspace_bytes",
+           "sky_build", "sky_local_skylines", "sky_merge", "sky_plan_partitions", "sky_plan_local",
+           "sky_plan_info", "sky_plan_destroy",
+           "gres_workspace_bytes", "gres_compute")
+
+
+class SkyParams(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("target_p", C.c_int32), ("slice_dim", C.c_int32),
+                ("flags", C.c_int32)]
+
+
+class SkyInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("scheme", C.c_int32), ("p", C.c_int32),
+                ("m", C.c_int32), ("pruned_cells", C.c_int32), ("rounds_local", C.c_int32),
+                ("rounds_merge", C.c_int32), ("state", C.c_int32), ("pruned_rows", C.c_int64),
+                ("local_count", C.c_int64), ("sky_count", C.c_int64), ("tests_local", C.c_int64),
+                ("tests_merge", C.c_int64), ("max_partition", C.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class GresOpts(C.Structure):
+    _fields_ = [("mapping", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class SkyError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = int(code)
+        super().__init__(f"{where}: {status_string(code)}")
+
+
+_lib = None
+
+
+def load():
+    """Load libsky.so and declare the signatures. Raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsky.so not found at {LIB_PATH}; build it first "
+                          "(python -m paper_2412_02274_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, i32, sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+    sig = {
+        "sky_status_string": (C.c_char_p, [i32]),
+        "sky_version": (i32, []),
+        "sky_ingest": (i32, [vp, i64, i32, vp, i64, vp, vp]),
+        "sky_build_workspace_bytes": (sz, [i64, i32, C.POINTER(SkyParams)]),
+        "sky_build": (i32, [vp, i64, i32, i64, C.POINTER(SkyParams), vp, sz, vp, vp,
+                            C.POINTER(vp)]),
+        "sky_local_skylines": (i32, [vp, vp]),
+        "sky_merge": (i32, [vp, vp, i64, vp, vp, vp]),
+        "sky_plan_partitions": (i32, [vp, vp, vp]),
+        "sky_plan_local": (i32, [vp, vp, vp]),
+        "sky_plan_info": (i32, [vp, C.POINTER(SkyInfo)]),
+        "sky_plan_destroy": (None, [vp]),
+        "gres_workspace_bytes": (sz, [i64, i32, i32]),
+        "gres_compute": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, vp, vp, sz, vp,
+                               C.POINTER(GresOpts), vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return load().sky_status_string(int(code)).decode()
+    except ImportError:
+        return f"status {code}"
+
+
+def check(code: int, where: str):
+    if code != SKY_OK:
+        raise SkyError(code, where)

@@ -1,0 +1,204 @@
+"""Python entry points over libsky, with torch owning device memory and streams.
+
+Every step of the path runs in libsky's HIP kernels; this module only allocates tensors,
+marshals pointers and reads back counts. Names follow the C ABI in include/sky.h:
+
+    x_soa  = ingest(x_rows)                                   # validate + [N, d] -> SoA [d, N]
+    plan   = build(x_soa, scheme="grid", target_p=64)         # partitions (Sec. 3.1)
+    plan.local_skylines()                                     # Sec. 3, phase 1
+    sky    = plan.merge()                                     # Sec. 3, phase 2 -> Sky(r) rows
+    g_exit, gres_v = gres(x_soa, sky, g_max=25)               # Def. 2 via Alg. 1
+
+Data-dependent errors are raised after the stream is synchronised (``check_status``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import SkyError
+
+__all__ = ["ingest", "build", "Plan", "gres", "skyline", "gres_workspace_bytes",
+           "build_workspace_bytes", "check_status", "SkyError"]
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def new_status(device="cuda") -> torch.Tensor:
+    return torch.zeros(1, dtype=torch.int32, device=device)
+
+
+def check_status(status: torch.Tensor, where: str = "device"):
+    code = int(status.item())
+    if code != _lib.SKY_OK:
+        raise SkyError(code, where)
+
+
+def ingest(x_rows: torch.Tensor, status: torch.Tensor | None = None, stream=None,
+           out: torch.Tensor | None = None) -> torch.Tensor:
+    """Validate a row-major float32 [N, d] device tensor and return its SoA copy [d, N]."""
+    lib = _lib.load()
+    if x_rows.dtype != torch.float32 or x_rows.dim() != 2 or not x_rows.is_cuda:
+        raise ValueError("x_rows must be a float32 [N, d] CUDA tensor")
+    x_rows = x_rows.contiguous()
+    n, d = x_rows.shape
+    if out is None:
+        out = torch.empty((d, n), dtype=torch.float32, device=x_rows.device)
+    st = status if status is not None else new_status(x_rows.device)
+    _lib.check(lib.sky_ingest(_ptr(x_rows), n, d, _ptr(out), n, _ptr(st), _stream_ptr(stream)),
+               "sky_ingest")
+    if status is None:
+        check_status(st, "sky_ingest")
+    return out
+
+
+def _params(scheme, target_p, slice_dim):
+    code = _lib.SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+    return _lib.SkyParams(code, int(target_p), int(slice_dim), 0)
+
+
+def build_workspace_bytes(n: int, d: int, scheme="none", target_p: int = 16,
+                          slice_dim: int = 0) -> int:
+    prm = _params(scheme, target_p, slice_dim)
+    return int(_lib.load().sky_build_workspace_bytes(n, d, C.byref(prm)))
+
+
+class Plan:
+    """A built partitioning of one relation (owns its workspace tensor)."""
+
+    def __init__(self, handle, ws, status, x_soa, stream):
+        self._h = handle
+        self.ws = ws
+        self.status = status
+        self.x_soa = x_soa
+        self.stream = stream
+        self.sky_idx = None
+        self.count = None
+
+    def local_skylines(self):
+        _lib.check(_lib.load().sky_local_skylines(self._h, _stream_ptr(self.stream)),
+                   "sky_local_skylines")
+        return self
+
+    def merge(self, member: bool = False, cap: int | None = None):
+        lib = _lib.load()
+        n = self.x_soa.shape[1]
+        cap = n if cap is None else cap
+        dev = self.x_soa.device
+        self.sky_idx = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        mem = torch.empty(n, dtype=torch.uint8, device=dev) if member else None
+        _lib.check(lib.sky_merge(self._h, _ptr(self.sky_idx), cap, _ptr(self.count), _ptr(mem),
+                                 _stream_ptr(self.stream)), "sky_merge")
+        s = int(self.count.item())  # synchronises
+        check_status(self.status, "sky_merge")
+        out = self.sky_idx[:s]
+        return (out, mem) if member else out
+
+    def partitions(self) -> torch.Tensor:
+        """Partition of every original row (int32[n])."""
+        part = torch.empty(self.x_soa.shape[1], dtype=torch.int32, device=self.x_soa.device)
+        _lib.check(_lib.load().sky_plan_partitions(self._h, _ptr(part), _stream_ptr(self.stream)),
+                   "sky_plan_partitions")
+        return part
+
+    def local_members(self) -> torch.Tensor:
+        """1 for rows in the skyline of their own (non-pruned) partition (uint8[n])."""
+        loc = torch.empty(self.x_soa.shape[1], dtype=torch.uint8, device=self.x_soa.device)
+        _lib.check(_lib.load().sky_plan_local(self._h, _ptr(loc), _stream_ptr(self.stream)),
+                   "sky_plan_local")
+        return loc
+
+    def info(self) -> dict:
+        inf = _lib.SkyInfo()
+        _lib.check(_lib.load().sky_plan_info(self._h, C.byref(inf)), "sky_plan_info")
+        return inf.as_dict()
+
+    def close(self):
+        if self._h:
+            _lib.load().sky_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0,
+          status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None) -> Plan:
+    """Partition assignment + partition-contiguous copy (sky_build)."""
+    lib = _lib.load()
+    if x_soa.dtype != torch.float32 or x_soa.dim() != 2 or not x_soa.is_cuda:
+        raise ValueError("x_soa must be a float32 [d, N] CUDA tensor")
+    d, n = x_soa.shape
+    ld = x_soa.stride(0)
+    if x_soa.stride(1) != 1:
+        raise ValueError("x_soa rows must be contiguous")
+    prm = _params(scheme, target_p, slice_dim)
+    need = int(lib.sky_build_workspace_bytes(n, d, C.byref(prm)))
+    if need == 0:
+        raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_build_workspace_bytes")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=x_soa.device)
+    st = status if status is not None else new_status(x_soa.device)
+    h = C.c_void_p()
+    _lib.check(lib.sky_build(_ptr(x_soa), n, d, ld, C.byref(prm), _ptr(ws), need, _ptr(st),
+                             _stream_ptr(stream), C.byref(h)), "sky_build")
+    return Plan(h, ws, st, x_soa, stream)
+
+
+def gres_workspace_bytes(s: int, d: int, g_max: int) -> int:
+    return int(_lib.load().gres_workspace_bytes(s, d, g_max))
+
+
+def gres(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, mapping="auto",
+         status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
+         g_exit: torch.Tensor | None = None, gres_out: torch.Tensor | None = None):
+    """gres_compute: (g_exit int32[s], gres float32[s]) for the rows sky_idx of x_soa."""
+    lib = _lib.load()
+    d, n = x_soa.shape
+    s = sky_idx.numel()
+    dev = x_soa.device
+    if sky_idx.dtype != torch.int64:
+        raise ValueError("sky_idx must be int64")
+    sky_idx = sky_idx.contiguous()
+    need = int(lib.gres_workspace_bytes(s, d, g_max))
+    if need == 0:
+        raise SkyError(_lib.SKY_ERR_INVALID_ARG, "gres_workspace_bytes")
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    if g_exit is None:
+        g_exit = torch.empty(s, dtype=torch.int32, device=dev)
+    if gres_out is None:
+        gres_out = torch.empty(s, dtype=torch.float32, device=dev)
+    st = status if status is not None else new_status(dev)
+    opts = _lib.GresOpts(_lib.MAPPINGS[mapping] if isinstance(mapping, str) else int(mapping))
+    _lib.check(lib.gres_compute(_ptr(x_soa), n, d, x_soa.stride(0), _ptr(sky_idx), s, g_max,
+                                _ptr(g_exit), _ptr(gres_out), _ptr(ws), need, _ptr(st),
+                                C.byref(opts), _stream_ptr(stream)), "gres_compute")
+    if status is None:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        check_status(st, "gres_compute")
+    return g_exit, gres_out
+
+
+def skyline(x_rows: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0):
+    """Whole skyline path on a row-major [N, d] device tensor: (sky_idx, plan info)."""
+    x_soa = ingest(x_rows)
+    plan = build(x_soa, scheme, target_p, slice_dim)
+    plan.local_skylines()
+    idx = plan.merge()
+    info = plan.info()
+    plan.close()
+    return idx, info

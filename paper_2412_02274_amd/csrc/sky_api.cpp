@@ -1,0 +1,387 @@
+// C ABI of libsky (declared in include/sky.h): argument checks, workspace layout, plans and
+// the order of the device steps. All device work is in the .hip files.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "sky_internal.hpp"
+
+using namespace sky;
+
+struct sky_plan {
+    // input
+    const float* x = nullptr;
+    int64_t n = 0, ld = 0;
+    int32_t d = 0;
+    int32_t scheme = 0, p = 1, m = 0, slice_dim = 0;
+    int32_t* dev_status = nullptr;
+    int32_t state = 0;
+    // workspace regions
+    float* xp = nullptr; int64_t ldp = 0;
+    int32_t *rowid = nullptr, *seg = nullptr;
+    float* fsum = nullptr;
+    int32_t* part_off = nullptr;
+    uint8_t* pruned = nullptr;
+    double* tan2_dev = nullptr;
+    int32_t *part_of_row = nullptr, *phist = nullptr, *scan_tmp = nullptr;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    int32_t* radix_tmp = nullptr;
+    EngineBuffers eng{};
+    uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;
+    int32_t *local_list = nullptr, *final_list = nullptr, *pos_tmp = nullptr, *count_tmp = nullptr;
+    // host copies
+    double* tan2_host = nullptr;
+    sky_info info{};
+};
+
+namespace {
+
+constexpr int32_t kMaxRows = 0x7FFFFFFF;
+
+bool valid_d(int32_t d) { return d >= 1 && d <= SKY_MAX_D; }
+
+// m >= 2 minimising |m^e - target| (ties to the smaller m); -1 if no m keeps m^e <= cap
+int32_t closest_m(int64_t target, int32_t e, int64_t cap) {
+    int32_t best = -1;
+    int64_t bestdiff = 0;
+    for (int32_t m = 2; m <= 65536; ++m) {
+        int64_t v = 1;
+        bool over = false;
+        for (int32_t i = 0; i < e; ++i) {
+            v *= m;
+            if (v > (int64_t(1) << 40)) { over = true; break; }
+        }
+        if (over) break;
+        int64_t diff = v > target ? v - target : target - v;
+        if (best < 0 || diff < bestdiff) { best = m; bestdiff = diff; }
+        if (v > target) break;
+    }
+    if (best < 0) return -1;
+    int64_t v = 1;
+    for (int32_t i = 0; i < e; ++i) v *= best;
+    return v <= cap ? best : -1;
+}
+
+int64_t ipow(int64_t b, int32_t e) {
+    int64_t v = 1;
+    for (int32_t i = 0; i < e; ++i) v *= b;
+    return v;
+}
+
+// Resolve scheme -> (p, m); returns SKY_OK or an error.
+sky_status resolve_partitions(int64_t n, int32_t d, const sky_params* prm, int32_t* p, int32_t* m) {
+    switch (prm->scheme) {
+        case SKY_NONE:
+            *p = 1; *m = 0;
+            return SKY_OK;
+        case SKY_GRID: {
+            if (prm->target_p < 1) return SKY_ERR_INVALID_ARG;
+            int32_t mm = closest_m(prm->target_p, d, SKY_MAX_CELLS);
+            if (mm < 0) return SKY_ERR_UNSUPPORTED;
+            *m = mm; *p = (int32_t)ipow(mm, d);
+            return SKY_OK;
+        }
+        case SKY_ANGULAR: {
+            if (prm->target_p < 1 || d < 2) return SKY_ERR_INVALID_ARG;
+            int32_t mm = closest_m(prm->target_p, d - 1, SKY_MAX_CELLS);
+            if (mm < 0) return SKY_ERR_UNSUPPORTED;
+            *m = mm; *p = (int32_t)ipow(mm, d - 1);
+            return SKY_OK;
+        }
+        case SKY_SLICED:
+            if (prm->target_p < 1 || prm->slice_dim < 0 || prm->slice_dim >= d) return SKY_ERR_INVALID_ARG;
+            *m = 0;
+            *p = (int32_t)(prm->target_p < n ? prm->target_p : n);
+            return SKY_OK;
+        default:
+            return SKY_ERR_INVALID_ARG;
+    }
+}
+
+// One layout routine serves both sizing (base == nullptr) and carving.
+void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, int32_t p, int32_t m) {
+    const int64_t ldp = round_up(n, 64);
+    P->ldp = ldp;
+    P->xp = c.take<float>((size_t)(d * ldp));
+    P->rowid = c.take<int32_t>((size_t)n);
+    P->seg = c.take<int32_t>((size_t)n);
+    P->fsum = c.take<float>((size_t)n);
+    P->part_off = c.take<int32_t>((size_t)p + 1);
+    P->pruned = c.take<uint8_t>((size_t)p);
+    P->tan2_dev = c.take<double>((size_t)(scheme == SKY_ANGULAR ? m + 1 : 1));
+    int64_t hist_elems = (scheme == SKY_GRID || scheme == SKY_ANGULAR) ? partition_hist_elems(n, p) : 64;
+    P->part_of_row = c.take<int32_t>((size_t)((scheme == SKY_GRID || scheme == SKY_ANGULAR) ? n : 1));
+    P->phist = c.take<int32_t>((size_t)hist_elems);
+    int64_t scan_n = hist_elems > n ? hist_elems : n;
+    P->scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(scan_n));
+    const int64_t sn = scheme == SKY_SLICED ? n : 1;
+    P->k0 = c.take<uint32_t>((size_t)sn);
+    P->v0 = c.take<uint32_t>((size_t)sn);
+    P->k1 = c.take<uint32_t>((size_t)sn);
+    P->v1 = c.take<uint32_t>((size_t)sn);
+    P->radix_tmp = c.take<int32_t>((size_t)(scheme == SKY_SLICED ? radix_tmp_elems(n) : 1));
+    EngineBuffers& e = P->eng;
+    e.w0 = c.take<int32_t>((size_t)n);
+    e.w1 = c.take<int32_t>((size_t)n);
+    e.head = c.take<int32_t>((size_t)n);
+    e.rest = c.take<int32_t>((size_t)n);
+    e.fsky = c.take<int32_t>((size_t)n);
+    e.out_list = nullptr;
+    e.seg_min = c.take<uint32_t>((size_t)p);
+    e.seg_max = c.take<uint32_t>((size_t)p);
+    e.hist = c.take<int32_t>((size_t)p * kBins);
+    e.seg_info = c.take<int32_t>((size_t)p * 9);
+    e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
+    e.counters = c.take<int32_t>(16);
+    e.tests = c.take<unsigned long long>(2);
+    e.scan_tmp = nullptr;
+    P->local_flag = c.take<uint8_t>((size_t)n);
+    P->final_flag = c.take<uint8_t>((size_t)n);
+    P->member_tmp = c.take<uint8_t>((size_t)n);
+    P->local_list = c.take<int32_t>((size_t)n);
+    P->final_list = c.take<int32_t>((size_t)n);
+    P->pos_tmp = c.take<int32_t>((size_t)n);
+    P->count_tmp = c.take<int32_t>(64);
+}
+
+void carve_gres(Carver& c, GresWork& w, int64_t s, int32_t d) {
+    const int64_t s_pad = round_up(s > 0 ? s : 1, 64);
+    const int64_t ntile = ceil_div(s > 0 ? s : 1, 64);
+    const int64_t t_pad = round_up(ntile, 64);
+    w.s_pad = s_pad;
+    w.t_pad = t_pad;
+    w.cand = c.take<float>((size_t)(d * s_pad));
+    w.lo = c.take<float>((size_t)(d * t_pad));
+    w.k0 = c.take<uint32_t>((size_t)s_pad);
+    w.v0 = c.take<uint32_t>((size_t)s_pad);
+    w.k1 = c.take<uint32_t>((size_t)s_pad);
+    w.v1 = c.take<uint32_t>((size_t)s_pad);
+    w.radix_tmp = c.take<int32_t>((size_t)radix_tmp_elems(s > 0 ? s : 1));
+    w.ge_sorted = c.take<int32_t>((size_t)s_pad);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sky_status_string(sky_status s) {
+    switch (s) {
+        case SKY_OK: return "SKY_OK";
+        case SKY_ERR_INVALID_ARG: return "SKY_ERR_INVALID_ARG: invalid argument";
+        case SKY_ERR_DOMAIN: return "SKY_ERR_DOMAIN: a value is NaN/inf or outside [0, 1)";
+        case SKY_ERR_WORKSPACE: return "SKY_ERR_WORKSPACE: workspace too small";
+        case SKY_ERR_CAPACITY: return "SKY_ERR_CAPACITY: output capacity too small";
+        case SKY_ERR_HIP: return "SKY_ERR_HIP: HIP runtime error";
+        case SKY_ERR_STATE: return "SKY_ERR_STATE: call out of order on a plan";
+        case SKY_ERR_UNSUPPORTED: return "SKY_ERR_UNSUPPORTED: outside the implemented limits";
+    }
+    return "unknown sky_status";
+}
+
+int32_t sky_version(void) { return 10000; }
+
+sky_status sky_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, int64_t ld,
+                      int32_t* dev_status, void* stream) {
+    if (n < 0 || !valid_d(d) || ld < n || n > kMaxRows) return SKY_ERR_INVALID_ARG;
+    if (n > 0 && (!x_rows || !x_soa || !dev_status)) return SKY_ERR_INVALID_ARG;
+    return launch_ingest(x_rows, n, d, x_soa, ld, dev_status, (hipStream_t)stream);
+}
+
+size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params) {
+    if (!params || n < 1 || n > kMaxRows || !valid_d(d) || params->flags != 0) return 0;
+    int32_t p = 1, m = 0;
+    if (resolve_partitions(n, d, params, &p, &m) != SKY_OK) return 0;
+    sky_plan tmp;
+    Carver c(nullptr, 0);
+    carve_plan(c, &tmp, n, d, params->scheme, p, m);
+    return c.used;
+}
+
+sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const sky_params* params,
+                     void* ws, size_t ws_bytes, int32_t* dev_status, void* stream, sky_plan** out) {
+    if (!out) return SKY_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!x_soa || !params || !ws || !dev_status) return SKY_ERR_INVALID_ARG;
+    if (n < 1 || n > kMaxRows || !valid_d(d) || ld < n || params->flags != 0) return SKY_ERR_INVALID_ARG;
+    int32_t p = 1, m = 0;
+    SKY_TRY(resolve_partitions(n, d, params, &p, &m));
+    size_t need = sky_build_workspace_bytes(n, d, params);
+    if (need == 0) return SKY_ERR_INVALID_ARG;
+    if (ws_bytes < need) return SKY_ERR_WORKSPACE;
+    sky_plan* P = new (std::nothrow) sky_plan();
+    if (!P) return SKY_ERR_INVALID_ARG;
+    Carver c(ws, ws_bytes);
+    carve_plan(c, P, n, d, params->scheme, p, m);
+    if (c.overflow) { delete P; return SKY_ERR_WORKSPACE; }
+    P->x = x_soa; P->n = n; P->ld = ld; P->d = d;
+    P->scheme = params->scheme; P->p = p; P->m = m; P->slice_dim = params->slice_dim;
+    P->dev_status = dev_status;
+    hipStream_t st = (hipStream_t)stream;
+    if (P->scheme == SKY_ANGULAR) {
+        P->tan2_host = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+        if (!P->tan2_host) { delete P; return SKY_ERR_INVALID_ARG; }
+        const double pi = 3.14159265358979323846;
+        for (int32_t k = 0; k <= m; ++k) {
+            double t = tan((double)k * pi / (2.0 * (double)m));
+            P->tan2_host[k] = t * t;
+        }
+        P->tan2_host[0] = 0.0;
+        hipError_t e = hipMemcpyAsync(P->tan2_dev, P->tan2_host, sizeof(double) * (size_t)(m + 1),
+                                      hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) { free(P->tan2_host); delete P; return SKY_ERR_HIP; }
+    }
+    PartitionArgs a{};
+    a.x = x_soa; a.n = n; a.d = d; a.ld = ld;
+    a.scheme = P->scheme; a.p = p; a.m = m; a.slice_dim = P->slice_dim;
+    a.tan2 = P->tan2_dev;
+    a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
+    a.part_off = P->part_off; a.pruned = P->pruned;
+    a.part_of_row = P->part_of_row; a.hist = P->phist; a.scan_tmp = P->scan_tmp;
+    a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
+    a.dev_status = dev_status;
+    sky_status s = launch_partition(a, st);
+    if (s != SKY_OK) { free(P->tan2_host); delete P; return s; }
+    P->state = 1;
+    P->info.n = n; P->info.d = d; P->info.scheme = P->scheme; P->info.p = p; P->info.m = m;
+    P->info.state = 1;
+    *out = P;
+    return SKY_OK;
+}
+
+sky_status sky_local_skylines(sky_plan* P, void* stream) {
+    if (!P) return SKY_ERR_INVALID_ARG;
+    if (P->state != 1) return SKY_ERR_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = (int32_t)P->n;
+    // partition statistics (sizes, pruned Grid cells)
+    {
+        int32_t* off = (int32_t*)malloc(sizeof(int32_t) * (size_t)(P->p + 1));
+        uint8_t* pr = (uint8_t*)malloc((size_t)P->p);
+        if (!off || !pr) { free(off); free(pr); return SKY_ERR_INVALID_ARG; }
+        hipError_t e1 = hipMemcpyAsync(off, P->part_off, sizeof(int32_t) * (size_t)(P->p + 1),
+                                       hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(pr, P->pruned, (size_t)P->p, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) { free(off); free(pr); return SKY_ERR_HIP; }
+        int64_t prow = 0, maxp = 0;
+        int32_t pcells = 0;
+        for (int32_t j = 0; j < P->p; ++j) {
+            int64_t sz = off[j + 1] - off[j];
+            if (sz > maxp) maxp = sz;
+            if (pr[j] && sz > 0) { ++pcells; prow += sz; }
+        }
+        P->info.pruned_cells = pcells;
+        P->info.pruned_rows = prow;
+        P->info.max_partition = maxp;
+        free(off);
+        free(pr);
+    }
+    SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
+    SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID ? P->pruned : nullptr, P->seg, n, P->eng.w1,
+                                 P->count_tmp, st));
+    int32_t live = 0;
+    SKY_HIP(hipMemcpyAsync(&live, P->count_tmp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SKY_HIP(hipStreamSynchronize(st));
+    EngineProblem pb{};
+    pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
+    pb.seg_of_pos = P->p > 1 ? P->seg : nullptr;
+    pb.nseg = P->p;
+    pb.items = P->eng.w1; pb.n_items = live;
+    pb.flag_out = P->local_flag;
+    EngineResult r{};
+    SKY_TRY(run_engine(pb, P->eng, P->local_list, &r, st));
+    P->info.local_count = r.count;
+    P->info.rounds_local = r.rounds;
+    P->info.tests_local = r.tests;
+    P->state = 2;
+    P->info.state = 2;
+    return SKY_OK;
+}
+
+sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_count,
+                     uint8_t* member, void* stream) {
+    if (!P || !dev_count || cap < 0 || (cap > 0 && !sky_idx)) return SKY_ERR_INVALID_ARG;
+    if (P->state != 2) return SKY_ERR_STATE;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = (int32_t)P->n;
+    const int32_t* final_list = P->local_list;
+    int32_t count = (int32_t)P->info.local_count;
+    if (P->p > 1) {
+        SKY_TRY(launch_fill_u8(P->final_flag, n, 0, st));
+        EngineProblem pb{};
+        pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
+        pb.seg_of_pos = nullptr;
+        pb.nseg = 1;
+        pb.items = P->local_list; pb.n_items = count;
+        pb.flag_out = P->final_flag;
+        EngineResult r{};
+        SKY_TRY(run_engine(pb, P->eng, P->final_list, &r, st));
+        final_list = P->final_list;
+        count = r.count;
+        P->info.rounds_merge = r.rounds;
+        P->info.tests_merge = r.tests;
+    }
+    P->info.sky_count = count;
+    SKY_TRY(launch_final_output(final_list, count, P->rowid, P->n, P->member_tmp, member, sky_idx,
+                                cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st));
+    P->state = 3;
+    P->info.state = 3;
+    return SKY_OK;
+}
+
+sky_status sky_plan_partitions(const sky_plan* P, int32_t* part, void* stream) {
+    if (!P || !part) return SKY_ERR_INVALID_ARG;
+    if (P->state < 1) return SKY_ERR_STATE;
+    return launch_scatter_rows(P->seg, nullptr, P->rowid, P->n, part, nullptr, (hipStream_t)stream);
+}
+
+sky_status sky_plan_local(const sky_plan* P, uint8_t* local, void* stream) {
+    if (!P || !local) return SKY_ERR_INVALID_ARG;
+    if (P->state < 2) return SKY_ERR_STATE;
+    return launch_scatter_rows(nullptr, P->local_flag, P->rowid, P->n, nullptr, local,
+                               (hipStream_t)stream);
+}
+
+sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
+    if (!P || !out) return SKY_ERR_INVALID_ARG;
+    *out = P->info;
+    return SKY_OK;
+}
+
+void sky_plan_destroy(sky_plan* P) {
+    if (!P) return;
+    free(P->tan2_host);
+    delete P;
+}
+
+size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max) {
+    if (s < 0 || s > kMaxRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return 0;
+    GresWork w{};
+    Carver c(nullptr, 0);
+    carve_gres(c, w, s, d);
+    return c.used;
+}
+
+sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
+                        int64_t s, int32_t g_max, int32_t* g_exit, float* gres, void* ws,
+                        size_t ws_bytes, int32_t* dev_status, const sky_gres_opts* opts,
+                        void* stream) {
+    if (s < 0 || s > kMaxRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
+    if (!dev_status) return SKY_ERR_INVALID_ARG;
+    int32_t mapping = opts ? opts->mapping : SKY_GRES_AUTO;
+    if (mapping < SKY_GRES_AUTO || mapping > SKY_GRES_LEVELS) return SKY_ERR_INVALID_ARG;
+    if (s == 0) return SKY_OK;
+    if (!x_soa || !sky_idx || n < 1 || n > kMaxRows || ld < n || !ws) return SKY_ERR_INVALID_ARG;
+    size_t need = gres_workspace_bytes(s, d, g_max);
+    if (ws_bytes < need) return SKY_ERR_WORKSPACE;
+    GresWork w{};
+    Carver c(ws, ws_bytes);
+    carve_gres(c, w, s, d);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    return launch_gres(x_soa, n, d, ld, sky_idx, s, g_max, mapping, g_exit, gres, w, dev_status,
+                       (hipStream_t)stream);
+}
+
+}  // extern "C"

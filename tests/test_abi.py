@@ -1,0 +1,106 @@
+"""The C-ABI library: it loads, exports every function include/sky.h declares, and rejects bad
+arguments synchronously (paths that return before any device work, so no GPU is needed)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2412_02274_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sky.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libsky.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_header_declarations_exported(lib):
+    declared = _declared_functions()
+    assert set(declared) == set(_lib.EXPORTS), declared
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        s = lib.sky_status_string(code).decode()
+        assert s.startswith("SKY_")
+    assert lib.sky_version() >= 10000
+
+
+def test_workspace_sizes(lib):
+    prm = _lib.SkyParams(_lib.SKY_GRID, 64, 0, 0)
+    assert lib.sky_build_workspace_bytes(10000, 4, C.byref(prm)) > 10000 * 4 * 4
+    assert lib.sky_build_workspace_bytes(0, 4, C.byref(prm)) == 0
+    assert lib.sky_build_workspace_bytes(100, 0, C.byref(prm)) == 0
+    assert lib.sky_build_workspace_bytes(100, 17, C.byref(prm)) == 0
+    bad = _lib.SkyParams(9, 64, 0, 0)
+    assert lib.sky_build_workspace_bytes(100, 4, C.byref(bad)) == 0
+    flags = _lib.SkyParams(_lib.SKY_NONE, 1, 0, 7)
+    assert lib.sky_build_workspace_bytes(100, 4, C.byref(flags)) == 0
+    ang1 = _lib.SkyParams(_lib.SKY_ANGULAR, 16, 0, 0)
+    assert lib.sky_build_workspace_bytes(100, 1, C.byref(ang1)) == 0  # Angular needs d >= 2
+    big = _lib.SkyParams(_lib.SKY_GRID, 1 << 20, 0, 0)
+    assert lib.sky_build_workspace_bytes(100, 8, C.byref(big)) == 0  # m^d above the cell limit
+    assert lib.gres_workspace_bytes(1000, 6, 25) > 1000 * 6 * 4
+    assert lib.gres_workspace_bytes(1000, 6, 1) == 0
+    assert lib.gres_workspace_bytes(-1, 6, 25) == 0
+    assert lib.gres_workspace_bytes(0, 6, 25) > 0
+
+
+def test_argument_errors_return_synchronously(lib):
+    fake = C.c_void_p(0x1000)  # never dereferenced: every call below fails its checks first
+    prm = _lib.SkyParams(_lib.SKY_NONE, 1, 0, 0)
+    h = C.c_void_p()
+    E = _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_build(None, 10, 2, 10, C.byref(prm), fake, 1 << 20, fake, None, C.byref(h)) == E
+    assert lib.sky_build(fake, 0, 2, 10, C.byref(prm), fake, 1 << 20, fake, None, C.byref(h)) == E
+    assert lib.sky_build(fake, 10, 2, 5, C.byref(prm), fake, 1 << 20, fake, None, C.byref(h)) == E
+    assert lib.sky_build(fake, 10, 2, 10, C.byref(prm), fake, 1 << 20, None, None, C.byref(h)) == E
+    assert lib.sky_build(fake, 10, 2, 10, C.byref(prm), fake, 1, fake, None,
+                         C.byref(h)) == _lib.SKY_ERR_WORKSPACE
+    sl = _lib.SkyParams(_lib.SKY_SLICED, 4, 3, 0)  # slice_dim outside [0, d)
+    assert lib.sky_build(fake, 10, 2, 10, C.byref(sl), fake, 1 << 20, fake, None, C.byref(h)) == E
+    assert h.value is None
+    assert lib.sky_local_skylines(None, None) == E
+    assert lib.sky_merge(None, fake, 1, fake, None, None) == E
+    assert lib.sky_plan_info(None, None) == E
+    assert lib.sky_plan_partitions(None, fake, None) == E
+    assert lib.sky_plan_local(None, fake, None) == E
+    lib.sky_plan_destroy(None)
+    assert lib.sky_ingest(fake, -1, 2, fake, 10, fake, None) == E
+    assert lib.sky_ingest(fake, 10, 2, fake, 9, fake, None) == E
+    assert lib.sky_ingest(None, 10, 2, fake, 10, fake, None) == E
+    assert lib.sky_ingest(None, 0, 2, None, 0, None, None) == _lib.SKY_OK  # nothing to do
+    o = _lib.GresOpts(0)
+    assert lib.gres_compute(fake, 10, 2, 10, fake, 5, 1, fake, fake, fake, 1 << 20, fake,
+                            C.byref(o), None) == E  # g_max < 2
+    assert lib.gres_compute(fake, 10, 2, 10, fake, 5, 25, fake, fake, fake, 1 << 20, None,
+                            C.byref(o), None) == E  # no status word
+    assert lib.gres_compute(fake, 10, 2, 10, fake, 5, 25, fake, fake, fake, 16, fake,
+                            C.byref(o), None) == _lib.SKY_ERR_WORKSPACE
+    bad = _lib.GresOpts(9)
+    assert lib.gres_compute(fake, 10, 2, 10, fake, 5, 25, fake, fake, fake, 1 << 20, fake,
+                            C.byref(bad), None) == E
+    assert lib.gres_compute(None, 0, 2, 0, None, 0, 25, None, None, None, 0, fake, None,
+                            None) == _lib.SKY_OK  # s = 0: nothing to do
