@@ -1,0 +1,130 @@
+"""Benchmark: one step = the whole hot path on one synthetic relation already resident in HBM:
+ingest (validate, SoA) -> partition assignment -> local skylines -> merge (final skyline) ->
+gres of every skyline tuple.
+
+Default workload: anticorrelated 1,000,000 x 6 FP32 (seed 0), plain method (one partition),
+g_max = 25. Prints ONE JSON line.
+
+value = dominance tests per second, counting the tests of the plain sequential method the
+paper measures (SFS for the skyline, Alg. 1's per-tuple descending scan for gres; recorded by
+the oracle in tests/golden/workload_counts.json) over the measured step time.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "dominance tests/s + skyline tuples' gres/s at 1 GPU; p50/p99 query latency"
+
+
+def _hip():
+    lib = C.CDLL("libamdhip64.so")
+    lib.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+    lib.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
+    lib.hipEventSynchronize.argtypes = [C.c_void_p]
+    lib.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+    lib.hipEventDestroy.argtypes = [C.c_void_p]
+    return lib
+
+
+def cpu_baseline(x, g_max, rows):
+    """The oracle as it stands on a bounded sample: the first `rows` rows of the workload."""
+    import numpy as np
+    import oracle
+    sub = np.ascontiguousarray(x[:rows])
+    t0 = time.perf_counter()
+    mem, t_sfs = oracle.skyline_sfs(sub)
+    sky = np.flatnonzero(mem)
+    _, t_gres = oracle.gres(sub, sky, g_max)
+    dt = time.perf_counter() - t0
+    return {"value": (t_sfs + t_gres) / dt, "unit": "dominance tests/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {rows} rows of the workload: SFS skyline ({t_sfs} tests, 1 thread) "
+                      f"+ Alg. 1 gres of its {len(sky)} skyline tuples ({t_gres} tests, OpenMP); "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ant_1m_d6")
+    ap.add_argument("--scheme", default="none", choices=["none", "grid", "angular", "sliced"])
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--mapping", default="auto", choices=["auto", "tiles", "levels"])
+    ap.add_argument("--cpu-rows", type=int, default=200_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2412_02274_amd import api
+    from tests.golden import workloads as W
+
+    counts = W.load_counts()[args.workload]
+    kind, n, d, seed, g_max = W.WORKLOADS[args.workload]
+    x = W.make(args.workload)
+    dev = torch.device("cuda:0")
+    xr = torch.from_numpy(x).to(dev)
+    pipe = api.Pipeline(n, d, args.scheme, args.p, 0, g_max, args.mapping, dev)
+    for _ in range(args.warmup):
+        pipe.run(xr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sky, ge, gr = pipe.run(xr, check=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    api.check_status(pipe.status, "pipeline")
+    s = int(sky.numel())
+    if s != counts["sky_size"]:
+        raise SystemExit(f"skyline size {s} differs from the oracle's {counts['sky_size']}")
+    # per-phase breakdown (one more, separately timed run)
+    pipe.run(xr, timing=True)
+    phases = pipe.phase_ms()
+    info = pipe.last_info
+    tests = counts["sfs_tests"] + counts["gres_tests"]
+    line = {
+        "metric": METRIC,
+        "value": tests / dt,
+        "unit": "dominance tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "generator": kind, "n": n, "d": d, "seed": seed,
+                   "g_max": g_max, "scheme": args.scheme,
+                   "target_p": args.p if args.scheme != "none" else 1},
+        "sky_size": s,
+        "gres_tuples_per_s": s / dt,
+        "algorithmic_tests": {"skyline_sfs": counts["sfs_tests"], "gres_alg1": counts["gres_tests"]},
+        "executed_skyline_tests": info["tests_local"] + info["tests_merge"],
+        "phase_ms": phases,
+        "plan": {k: info[k] for k in ("p", "m", "rounds_local", "rounds_merge", "local_count",
+                                      "pruned_cells", "pruned_rows", "max_partition")},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(x, g_max, min(args.cpu_rows, n))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import SkyError
 
-__all__ = ["ingest", "build", "Plan", "gres", "skyline", "gres_workspace_bytes",
+__all__ = ["ingest", "build", "Plan", "Pipeline", "gres", "skyline", "gres_workspace_bytes",
            "build_workspace_bytes", "check_status", "SkyError"]
 
 
@@ -202,3 +202,89 @@ def skyline(x_rows: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: 
     info = plan.info()
     plan.close()
     return idx, info
+
+
+class Pipeline:
+    """The whole hot path on one relation shape with every buffer allocated once:
+
+        ingest (validate, SoA) -> build (partitions) -> local skylines -> merge -> gres
+
+    ``run(x_rows)`` executes one pass on torch's current stream and returns
+    ``(sky_idx, g_exit, gres)`` views (valid until the next run). The plan is rebuilt on every
+    run (host-side struct only)."""
+
+    def __init__(self, n: int, d: int, scheme="none", target_p: int = 16, slice_dim: int = 0,
+                 g_max: int = 25, mapping="auto", device="cuda"):
+        lib = _lib.load()
+        self.n, self.d, self.g_max = int(n), int(d), int(g_max)
+        self.scheme, self.target_p, self.slice_dim, self.mapping = scheme, target_p, slice_dim, mapping
+        dev = torch.device(device)
+        self.device = dev
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.x_soa = torch.empty((d, n), dtype=torch.float32, device=dev)
+        prm = _params(scheme, target_p, slice_dim)
+        self.build_bytes = int(lib.sky_build_workspace_bytes(n, d, C.byref(prm)))
+        if self.build_bytes == 0:
+            raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_build_workspace_bytes")
+        self.build_ws = torch.empty(self.build_bytes, dtype=torch.uint8, device=dev)
+        self.gres_bytes = int(lib.gres_workspace_bytes(n, d, g_max))  # worst case s = n
+        self.gres_ws = torch.empty(self.gres_bytes, dtype=torch.uint8, device=dev)
+        self.sky_buf = torch.empty(n, dtype=torch.int64, device=dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.g_exit = torch.empty(n, dtype=torch.int32, device=dev)
+        self.gres_v = torch.empty(n, dtype=torch.float32, device=dev)
+        self.last_info = None
+        self.events = None
+
+    def run(self, x_rows: torch.Tensor, check: bool = True, timing: bool = False):
+        lib = _lib.load()
+        st = torch.cuda.current_stream()
+        sp = C.c_void_p(st.cuda_stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if timing else None
+        if ev:
+            ev[0].record(st)
+        self.status.zero_()
+        _lib.check(lib.sky_ingest(_ptr(x_rows), self.n, self.d, _ptr(self.x_soa), self.n,
+                                  _ptr(self.status), sp), "sky_ingest")
+        if ev:
+            ev[1].record(st)
+        prm = _params(self.scheme, self.target_p, self.slice_dim)
+        h = C.c_void_p()
+        _lib.check(lib.sky_build(_ptr(self.x_soa), self.n, self.d, self.n, C.byref(prm),
+                                 _ptr(self.build_ws), self.build_bytes, _ptr(self.status), sp,
+                                 C.byref(h)), "sky_build")
+        try:
+            if ev:
+                ev[2].record(st)
+            _lib.check(lib.sky_local_skylines(h, sp), "sky_local_skylines")
+            if ev:
+                ev[3].record(st)
+            _lib.check(lib.sky_merge(h, _ptr(self.sky_buf), self.n, _ptr(self.count), None, sp),
+                       "sky_merge")
+            s = int(self.count.item())
+            if ev:
+                ev[4].record(st)
+            inf = _lib.SkyInfo()
+            lib.sky_plan_info(h, C.byref(inf))
+            self.last_info = inf.as_dict()
+        finally:
+            lib.sky_plan_destroy(h)
+        opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
+                             else int(self.mapping))
+        _lib.check(lib.gres_compute(_ptr(self.x_soa), self.n, self.d, self.n, _ptr(self.sky_buf), s,
+                                    self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
+                                    _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),
+                                    C.byref(opts), sp), "gres_compute")
+        if ev:
+            ev[5].record(st)
+            self.events = ev
+        if check:
+            check_status(self.status, "pipeline")
+        return self.sky_buf[:s], self.g_exit[:s], self.gres_v[:s]
+
+    def phase_ms(self):
+        """Per-phase milliseconds of the last timed run: ingest, build, local, merge, gres."""
+        ev = self.events
+        ev[5].synchronize()
+        names = ("ingest", "build", "local", "merge", "gres")
+        return {names[i]: ev[i].elapsed_time(ev[i + 1]) for i in range(5)}

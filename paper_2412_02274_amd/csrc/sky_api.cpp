@@ -132,7 +132,8 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.seg_min = c.take<uint32_t>((size_t)p);
     e.seg_max = c.take<uint32_t>((size_t)p);
     e.hist = c.take<int32_t>((size_t)p * kBins);
-    e.seg_info = c.take<int32_t>((size_t)p * 9);
+    e.seg_info = c.take<int32_t>((size_t)p * 12);
+    e.dom = c.take<uint8_t>((size_t)n);
     e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
     e.counters = c.take<int32_t>(16);
     e.tests = c.take<unsigned long long>(2);

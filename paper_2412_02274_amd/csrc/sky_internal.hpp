@@ -136,7 +136,8 @@ struct EngineBuffers {
     int32_t* out_list;             // confirmed skyline items (capacity n)
     uint32_t* seg_min; uint32_t* seg_max;   // [nseg]
     int32_t* hist;                 // [nseg * kBins]
-    int32_t* seg_info;             // [nseg * 8] per-segment counters / offsets
+    int32_t* seg_info;             // [nseg * 12] per-segment counters / offsets
+    uint8_t* dom;                  // [n] dominated flags
     int32_t* tile_off;             // [2 * (nseg + 1)] tile offsets for head / rest
     int32_t* counters;             // [16] global counters
     unsigned long long* tests;     // [2] dominance-test counters
