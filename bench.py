@@ -25,14 +25,57 @@ if ROOT not in sys.path:
 METRIC = "dominance tests/s + skyline tuples' gres/s at 1 GPU; p50/p99 query latency"
 
 
-def _hip():
-    lib = C.CDLL("libamdhip64.so")
-    lib.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
-    lib.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
-    lib.hipEventSynchronize.argtypes = [C.c_void_p]
-    lib.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
-    lib.hipEventDestroy.argtypes = [C.c_void_p]
-    return lib
+# MI355X published peaks used for the roofline
+PEAK_HBM_GBS = 8000.0
+PEAK_ALU_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes x 2.4 GHz: 32-bit lane-ops
+
+
+class HipEvents:
+    """A pool of hipEvent_t handles (libamdhip64 through ctypes) for kernel-level timing on the
+    stream the library launches on."""
+
+    def __init__(self, count):
+        self.lib = C.CDLL("libamdhip64.so")
+        self.lib.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.lib.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.lib.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [C.c_void_p]
+        self.ev = []
+        for _ in range(count):
+            e = C.c_void_p()
+            if self.lib.hipEventCreate(C.byref(e)) != 0:
+                raise RuntimeError("hipEventCreate failed")
+            self.ev.append(e.value)
+
+    def elapsed_ms(self, a, b):
+        self.lib.hipEventSynchronize(b)
+        ms = C.c_float()
+        if self.lib.hipEventElapsedTime(C.byref(ms), a, b) != 0:
+            raise RuntimeError("hipEventElapsedTime failed")
+        return float(ms.value)
+
+    def close(self):
+        for e in self.ev:
+            self.lib.hipEventDestroy(e)
+        self.ev = []
+
+
+def stored_traffic(workload, kernel_src):
+    """HBM bytes per step of the dominance-test kernel from the committed PMC summary
+    (profiles/traffic_<workload>.txt), or None when the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if kv.get("src_sha256_16") != sha:
+        return None
+    return int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])
 
 
 def cpu_baseline(x, g_max, rows):
@@ -82,13 +125,30 @@ def main():
     pipe = api.Pipeline(n, d, args.scheme, args.p, 0, g_max, args.mapping, dev)
     for _ in range(args.warmup):
         pipe.run(xr)
+    # kernel-level events for every timed step: dominance-test launches and the gres search
+    max_pairs = 256
+    pool = HipEvents(args.steps * (2 * max_pairs + 2))
+    per_step = []
+    for k in range(args.steps):
+        base = k * (2 * max_pairs + 2)
+        tb = pool.ev[base: base + max_pairs]
+        te = pool.ev[base + max_pairs: base + 2 * max_pairs]
+        gb, ge_ = pool.ev[base + 2 * max_pairs], pool.ev[base + 2 * max_pairs + 1]
+        per_step.append((tb, te, gb, ge_))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sky, ge, gr = pipe.run(xr, check=False)
+    used = []
+    for k in range(args.steps):
+        tb, te, gb, ge_ = per_step[k]
+        sky, ge, gr = pipe.run(xr, check=False, test_events=(tb, te), gres_events=(gb, ge_))
+        used.append(pipe.last_info["events_used"])
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     api.check_status(pipe.status, "pipeline")
+    test_ms = sum(sum(pool.elapsed_ms(per_step[k][0][i], per_step[k][1][i]) for i in range(used[k]))
+                  for k in range(args.steps)) / args.steps
+    gres_ms = sum(pool.elapsed_ms(per_step[k][2], per_step[k][3]) for k in range(args.steps)) / args.steps
+    launches = sum(used) / args.steps
     s = int(sky.numel())
     if s != counts["sky_size"]:
         raise SystemExit(f"skyline size {s} differs from the oracle's {counts['sky_size']}")
@@ -97,6 +157,21 @@ def main():
     phases = pipe.phase_ms()
     info = pipe.last_info
     tests = counts["sfs_tests"] + counts["gres_tests"]
+    executed = info["tests_local"] + info["tests_merge"]
+    ops_per_test = 2 * d  # one <= and one < comparison per attribute (Def. 1)
+    test_tops = executed * ops_per_test / (test_ms * 1e-3) / 1e12
+    kernels = {
+        "dominance_test": {"ms_per_step": test_ms, "launches_per_step": launches,
+                           "tests_per_step": executed, "ops_per_test": ops_per_test,
+                           "achieved_TOPs": test_tops},
+        "gres_search": {"ms_per_step": gres_ms, "launches_per_step": 1},
+    }
+    roofline = {"kernel": "dominance_test", "bound": "alu", "achieved": test_tops,
+                "peak": PEAK_ALU_TOPS, "unit": "TOP/s", "frac": test_tops / PEAK_ALU_TOPS,
+                "traffic": stored_traffic(args.workload, os.path.join(
+                    ROOT, "paper_2412_02274_amd", "csrc", "sky_skyline.hip")),
+                "note": "achieved = dominance tests the test kernel evaluated (device counter) x 2d "
+                        "32-bit compares / its HIP-event time per step"}
     line = {
         "metric": METRIC,
         "value": tests / dt,
@@ -116,13 +191,16 @@ def main():
         "sky_size": s,
         "gres_tuples_per_s": s / dt,
         "algorithmic_tests": {"skyline_sfs": counts["sfs_tests"], "gres_alg1": counts["gres_tests"]},
-        "executed_skyline_tests": info["tests_local"] + info["tests_merge"],
+        "executed_skyline_tests": executed,
         "phase_ms": phases,
+        "roofline": roofline,
+        "kernels": kernels,
         "plan": {k: info[k] for k in ("p", "m", "rounds_local", "rounds_merge", "local_count",
                                       "pruned_cells", "pruned_rows", "max_partition")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, g_max, min(args.cpu_rows, n))
+    pool.close()
     print(json.dumps(line), flush=True)
 
 

@@ -97,11 +97,15 @@ typedef struct sky_info {
     int64_t tests_local;      /* dominance tests evaluated in the local phase (counted on device) */
     int64_t tests_merge;      /* dominance tests evaluated in the final phase */
     int64_t max_partition;    /* rows in the largest partition */
+    int32_t events_used;      /* timing-hook event pairs recorded (sky_plan_set_events) */
+    int32_t reserved0;
 } sky_info;
 
 typedef struct sky_gres_opts {
     int32_t mapping;   /* SKY_GRES_AUTO / SKY_GRES_TILES / SKY_GRES_LEVELS */
-    int32_t reserved[3];
+    int32_t reserved;  /* must be 0 */
+    void* ev_begin;    /* optional hipEvent_t recorded on the stream just before the search kernel */
+    void* ev_end;      /* optional hipEvent_t recorded just after it (both or neither) */
 } sky_gres_opts;
 
 typedef struct sky_plan sky_plan; /* opaque, host-side; refers to caller memory */
@@ -175,6 +179,16 @@ sky_status sky_plan_partitions(const sky_plan* plan, int32_t* part, void* stream
  * sky_local_skylines.
  */
 sky_status sky_plan_local(const sky_plan* plan, uint8_t* local, void* stream);
+
+/*
+ * sky_plan_set_events -- optional timing hooks, to measure the dominance-test kernels alone.
+ * ev_begin/ev_end: host arrays of cap hipEvent_t handles (as void*) created by the caller.
+ * sky_local_skylines and sky_merge then record ev_begin[i] / ev_end[i] on the stream around
+ * their i-th dominance-test launch (i counted across both calls, at most cap pairs) and report
+ * the number of pairs recorded in sky_info.events_used. Null arrays or cap = 0 disable it.
+ */
+sky_status sky_plan_set_events(sky_plan* plan, void* const* ev_begin, void* const* ev_end,
+                               int32_t cap);
 
 /* Plan inspection (host-side copy of the counters listed in sky_info). */
 sky_status sky_plan_info(const sky_plan* plan, sky_info* out);

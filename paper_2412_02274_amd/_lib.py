@@ -34,6 +34,7 @@ SKY_MAX_G = 1048576
 # every function the header declares (checked against the header by the tests)
 EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspace_bytes",
            "sky_build", "sky_local_skylines", "sky_merge", "sky_plan_partitions", "sky_plan_local",
+           "sky_plan_set_events",
            "sky_plan_info", "sky_plan_destroy",
            "gres_workspace_bytes", "gres_compute")
 
@@ -48,14 +49,16 @@ class SkyInfo(C.Structure):
                 ("m", C.c_int32), ("pruned_cells", C.c_int32), ("rounds_local", C.c_int32),
                 ("rounds_merge", C.c_int32), ("state", C.c_int32), ("pruned_rows", C.c_int64),
                 ("local_count", C.c_int64), ("sky_count", C.c_int64), ("tests_local", C.c_int64),
-                ("tests_merge", C.c_int64), ("max_partition", C.c_int64)]
+                ("tests_merge", C.c_int64), ("max_partition", C.c_int64),
+                ("events_used", C.c_int32), ("reserved0", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class GresOpts(C.Structure):
-    _fields_ = [("mapping", C.c_int32), ("reserved", C.c_int32 * 3)]
+    _fields_ = [("mapping", C.c_int32), ("reserved", C.c_int32), ("ev_begin", C.c_void_p),
+                ("ev_end", C.c_void_p)]
 
 
 class SkyError(RuntimeError):
@@ -88,6 +91,7 @@ def load():
         "sky_merge": (i32, [vp, vp, i64, vp, vp, vp]),
         "sky_plan_partitions": (i32, [vp, vp, vp]),
         "sky_plan_local": (i32, [vp, vp, vp]),
+        "sky_plan_set_events": (i32, [vp, vp, vp, i32]),
         "sky_plan_info": (i32, [vp, C.POINTER(SkyInfo)]),
         "sky_plan_destroy": (None, [vp]),
         "gres_workspace_bytes": (sz, [i64, i32, i32]),

@@ -236,7 +236,10 @@ class Pipeline:
         self.last_info = None
         self.events = None
 
-    def run(self, x_rows: torch.Tensor, check: bool = True, timing: bool = False):
+    def run(self, x_rows: torch.Tensor, check: bool = True, timing: bool = False,
+            test_events=None, gres_events=None):
+        """test_events: optional (begin[], end[]) lists of hipEvent_t handles recorded around the
+        dominance-test launches; gres_events: optional (begin, end) around the gres search."""
         lib = _lib.load()
         st = torch.cuda.current_stream()
         sp = C.c_void_p(st.cuda_stream)
@@ -254,6 +257,12 @@ class Pipeline:
                                  _ptr(self.build_ws), self.build_bytes, _ptr(self.status), sp,
                                  C.byref(h)), "sky_build")
         try:
+            if test_events is not None:
+                nb = len(test_events[0])
+                arr_b = (C.c_void_p * nb)(*test_events[0])
+                arr_e = (C.c_void_p * nb)(*test_events[1])
+                self._ev_keep = (arr_b, arr_e)
+                _lib.check(lib.sky_plan_set_events(h, arr_b, arr_e, nb), "sky_plan_set_events")
             if ev:
                 ev[2].record(st)
             _lib.check(lib.sky_local_skylines(h, sp), "sky_local_skylines")
@@ -271,6 +280,8 @@ class Pipeline:
             lib.sky_plan_destroy(h)
         opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
                              else int(self.mapping))
+        if gres_events is not None:
+            opts.ev_begin, opts.ev_end = gres_events
         _lib.check(lib.gres_compute(_ptr(self.x_soa), self.n, self.d, self.n, _ptr(self.sky_buf), s,
                                     self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
                                     _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),

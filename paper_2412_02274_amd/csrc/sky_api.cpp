@@ -33,6 +33,10 @@ struct sky_plan {
     int32_t *local_list = nullptr, *final_list = nullptr, *pos_tmp = nullptr, *count_tmp = nullptr;
     // host copies
     double* tan2_host = nullptr;
+    void* const* ev_begin = nullptr;
+    void* const* ev_end = nullptr;
+    int32_t ev_cap = 0;
+    int32_t ev_used = 0;
     sky_info info{};
 };
 
@@ -291,8 +295,10 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     pb.nseg = P->p;
     pb.items = P->eng.w1; pb.n_items = live;
     pb.flag_out = P->local_flag;
+    pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
     EngineResult r{};
     SKY_TRY(run_engine(pb, P->eng, P->local_list, &r, st));
+    P->info.events_used = P->ev_used;
     P->info.local_count = r.count;
     P->info.rounds_local = r.rounds;
     P->info.tests_local = r.tests;
@@ -317,12 +323,14 @@ sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_co
         pb.nseg = 1;
         pb.items = P->local_list; pb.n_items = count;
         pb.flag_out = P->final_flag;
+        pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
         EngineResult r{};
         SKY_TRY(run_engine(pb, P->eng, P->final_list, &r, st));
         final_list = P->final_list;
         count = r.count;
         P->info.rounds_merge = r.rounds;
         P->info.tests_merge = r.tests;
+        P->info.events_used = P->ev_used;
     }
     P->info.sky_count = count;
     SKY_TRY(launch_final_output(final_list, count, P->rowid, P->n, P->member_tmp, member, sky_idx,
@@ -343,6 +351,17 @@ sky_status sky_plan_local(const sky_plan* P, uint8_t* local, void* stream) {
     if (P->state < 2) return SKY_ERR_STATE;
     return launch_scatter_rows(nullptr, P->local_flag, P->rowid, P->n, nullptr, local,
                                (hipStream_t)stream);
+}
+
+sky_status sky_plan_set_events(sky_plan* P, void* const* ev_begin, void* const* ev_end, int32_t cap) {
+    if (!P || cap < 0) return SKY_ERR_INVALID_ARG;
+    if (cap > 0 && (!ev_begin || !ev_end)) return SKY_ERR_INVALID_ARG;
+    P->ev_begin = cap > 0 ? ev_begin : nullptr;
+    P->ev_end = cap > 0 ? ev_end : nullptr;
+    P->ev_cap = cap;
+    P->ev_used = 0;
+    P->info.events_used = 0;
+    return SKY_OK;
 }
 
 sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
@@ -373,6 +392,7 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
     if (!dev_status) return SKY_ERR_INVALID_ARG;
     int32_t mapping = opts ? opts->mapping : SKY_GRES_AUTO;
     if (mapping < SKY_GRES_AUTO || mapping > SKY_GRES_LEVELS) return SKY_ERR_INVALID_ARG;
+    if (opts && (opts->reserved != 0 || (!opts->ev_begin) != (!opts->ev_end))) return SKY_ERR_INVALID_ARG;
     if (s == 0) return SKY_OK;
     if (!x_soa || !sky_idx || n < 1 || n > kMaxRows || ld < n || !ws) return SKY_ERR_INVALID_ARG;
     size_t need = gres_workspace_bytes(s, d, g_max);
@@ -382,6 +402,7 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
     carve_gres(c, w, s, d);
     if (c.overflow) return SKY_ERR_WORKSPACE;
     return launch_gres(x_soa, n, d, ld, sky_idx, s, g_max, mapping, g_exit, gres, w, dev_status,
+                       opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                        (hipStream_t)stream);
 }
 

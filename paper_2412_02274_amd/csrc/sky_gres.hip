@@ -292,7 +292,8 @@ int64_t gres_pad(int64_t s) { return round_up(s > 0 ? s : 1, kWave * kTileC); }
 
 sky_status launch_gres(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
                        int64_t s64, int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres,
-                       const GresWork& w, int32_t* dev_status, hipStream_t st) {
+                       const GresWork& w, int32_t* dev_status, void* ev_begin, void* ev_end,
+                       hipStream_t st) {
     if (s64 <= 0) return SKY_OK;
     const int32_t s = (int32_t)s64;
     const int32_t ntile = (int32_t)ceil_div(s, kTileC);
@@ -311,6 +312,7 @@ sky_status launch_gres(const float* x, int64_t n, int32_t d, int64_t ld, const i
     SKY_HIP(hipGetLastError());
     if (mapping == SKY_GRES_AUTO) mapping = (g_max > 64 && s <= 8192) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
     const uint32_t wblocks = (uint32_t)ceil_div(s, kBlock / kWave);
+    if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (mapping == SKY_GRES_LEVELS) {
         SKY_DISPATCH_D(d, gres_levels_kernel, dim3(wblocks), dim3(kBlock), 0, st,
                        (const float*)w.cand, w.s_pad, s, d, (const float*)w.lo, w.t_pad, ntile, g_max,
@@ -321,6 +323,7 @@ sky_status launch_gres(const float* x, int64_t n, int32_t d, int64_t ld, const i
                        w.ge_sorted);
     }
     SKY_HIP(hipGetLastError());
+    if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));
     hipLaunchKernelGGL(gres_output_kernel, dim3(sblocks), dim3(kBlock), 0, st,
                        (const int32_t*)w.ge_sorted, (const uint32_t*)w.v0, s, g_exit, gres);
     SKY_HIP(hipGetLastError());

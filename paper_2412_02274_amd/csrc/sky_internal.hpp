@@ -151,6 +151,10 @@ struct EngineProblem {
     int32_t nseg;
     const int32_t* items; int32_t n_items;  // initial work list (positions)
     uint8_t* flag_out;             // [n_pos] set to 1 for skyline items (must be zeroed)
+    void* const* ev_begin;         // optional timing events around the test launches
+    void* const* ev_end;
+    int32_t ev_cap;
+    int32_t* ev_used;              // host counter, advanced per recorded pair
 };
 struct EngineResult { int32_t count; int32_t rounds; int64_t tests; };
 sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,
@@ -181,6 +185,7 @@ struct GresWork {
 int64_t gres_pad(int64_t s);
 sky_status launch_gres(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
                        int64_t s, int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres,
-                       const GresWork& w, int32_t* dev_status, hipStream_t st);
+                       const GresWork& w, int32_t* dev_status, void* ev_begin, void* ev_end,
+                       hipStream_t st);
 
 }  // namespace sky

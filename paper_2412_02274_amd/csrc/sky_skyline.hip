@@ -543,6 +543,14 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         *span = (int32_t)sp;
         return (uint32_t)ceil_div(maxc, sp);
     };
+    // optional timing hooks around the dominance-test launches
+    auto ev_rec = [&](bool begin) -> hipError_t {
+        if (!pb.ev_begin || !pb.ev_end || !pb.ev_used || *pb.ev_used >= pb.ev_cap) return hipSuccess;
+        hipEvent_t e = (hipEvent_t)(begin ? pb.ev_begin[*pb.ev_used] : pb.ev_end[*pb.ev_used]);
+        hipError_t r = hipEventRecord(e, st);
+        if (!begin) ++*pb.ev_used;
+        return r;
+    };
     int guard = 0;
     while (live > 0) {
         if (++guard > 1000000) return SKY_ERR_HIP;
@@ -574,10 +582,12 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         // head skyline: all pairs inside every segment's head
         int32_t span = chunk;
         uint32_t ychunks = split(htiles, maxh, &span);
+        SKY_HIP(ev_rec(true));
         SKY_DISPATCH_D(pb.d, test_kernel, dim3((uint32_t)htiles, ychunks), dim3(kBlock), lds, st, 0,
                        pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
                        (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.head,
                        span, chunk, b.dom, b.tests);
+        SKY_HIP(ev_rec(false));
         hipLaunchKernelGGL(compact_head_kernel, dim3((uint32_t)ceil_div(htot, kBlock)), dim3(kBlock), 0,
                            st, (const int32_t*)b.head, (const int32_t*)b.counters, pb.seg_of_pos,
                            (const uint8_t*)b.dom, b.seg_info, b.fsky, pb.flag_out, out_list,
@@ -586,10 +596,12 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         if (rtot > 0) {
             // filter the rest against the head skylines
             ychunks = split(rtiles, maxh, &span);
+            SKY_HIP(ev_rec(true));
             SKY_DISPATCH_D(pb.d, test_kernel, dim3((uint32_t)rtiles, ychunks), dim3(kBlock), lds, st, 1,
                            pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
                            (const int32_t*)b.seg_info, (const int32_t*)b.rest,
                            (const int32_t*)b.fsky, span, chunk, b.dom, b.tests);
+            SKY_HIP(ev_rec(false));
             hipLaunchKernelGGL(compact_rest_kernel, dim3((uint32_t)ceil_div(rtot, kBlock)), dim3(kBlock),
                                0, st, (const int32_t*)b.rest, b.counters, (const uint8_t*)b.dom, next);
             SKY_HIP(hipGetLastError());
