@@ -141,7 +141,7 @@ size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params)
  * dominance, and a stable partition-contiguous SoA copy in the workspace.
  * x_soa must stay valid until sky_merge returns. On success *out receives a new plan
  * (host memory owned by the library; release it with sky_plan_destroy).
- * n must be in [1, 2^31-1]; Grid/Angular need m^e <= SKY_MAX_CELLS (else SKY_ERR_UNSUPPORTED);
+ * n must be in [1, 2^30 - 2^20]; Grid/Angular need m^e <= SKY_MAX_CELLS (else SKY_ERR_UNSUPPORTED);
  * Angular needs d >= 2.
  */
 sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld,

@@ -43,6 +43,7 @@ struct sky_plan {
 namespace {
 
 constexpr int32_t kMaxRows = 0x7FFFFFFF;
+constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset within 32 bits
 
 bool valid_d(int32_t d) { return d >= 1 && d <= SKY_MAX_D; }
 
@@ -116,32 +117,36 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->pruned = c.take<uint8_t>((size_t)p);
     P->tan2_dev = c.take<double>((size_t)(scheme == SKY_ANGULAR ? m + 1 : 1));
     int64_t hist_elems = (scheme == SKY_GRID || scheme == SKY_ANGULAR) ? partition_hist_elems(n, p) : 64;
-    P->part_of_row = c.take<int32_t>((size_t)((scheme == SKY_GRID || scheme == SKY_ANGULAR) ? n : 1));
+    P->part_of_row = c.take<int32_t>((size_t)(scheme != SKY_NONE ? n : 1));
     P->phist = c.take<int32_t>((size_t)hist_elems);
     int64_t scan_n = hist_elems > n ? hist_elems : n;
     P->scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(scan_n));
-    const int64_t sn = scheme == SKY_SLICED ? n : 1;
-    P->k0 = c.take<uint32_t>((size_t)sn);
-    P->v0 = c.take<uint32_t>((size_t)sn);
-    P->k1 = c.take<uint32_t>((size_t)sn);
-    P->v1 = c.take<uint32_t>((size_t)sn);
-    P->radix_tmp = c.take<int32_t>((size_t)(scheme == SKY_SLICED ? radix_tmp_elems(n) : 1));
+    P->k0 = c.take<uint32_t>((size_t)n);
+    P->v0 = c.take<uint32_t>((size_t)n);
+    P->k1 = c.take<uint32_t>((size_t)n);
+    P->v1 = c.take<uint32_t>((size_t)n);
+    P->radix_tmp = c.take<int32_t>((size_t)radix_tmp_elems(n));
     EngineBuffers& e = P->eng;
+    e.hcap = engine_head_capacity(n, p);
+    e.tcap = round_up(ceil_div(e.hcap, 64), 64);
     e.w0 = c.take<int32_t>((size_t)n);
     e.w1 = c.take<int32_t>((size_t)n);
-    e.head = c.take<int32_t>((size_t)n);
+    e.head = c.take<int32_t>((size_t)e.hcap);
     e.rest = c.take<int32_t>((size_t)n);
-    e.fsky = c.take<int32_t>((size_t)n);
-    e.out_list = nullptr;
+    e.hval = c.take<uint32_t>((size_t)(d * e.hcap));
+    e.hlo = c.take<uint32_t>((size_t)(d * e.tcap));
+    e.hhi = c.take<uint32_t>((size_t)(d * e.tcap));
     e.seg_min = c.take<uint32_t>((size_t)p);
     e.seg_max = c.take<uint32_t>((size_t)p);
     e.hist = c.take<int32_t>((size_t)p * kBins);
-    e.seg_info = c.take<int32_t>((size_t)p * 12);
+    e.seg_info = c.take<int32_t>((size_t)p * 8);
     e.dom = c.take<uint8_t>((size_t)n);
     e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
     e.counters = c.take<int32_t>(16);
     e.tests = c.take<unsigned long long>(2);
-    e.scan_tmp = nullptr;
+    e.flag = c.take<int32_t>((size_t)n);
+    e.scan = c.take<int32_t>((size_t)n);
+    e.scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(n));
     P->local_flag = c.take<uint8_t>((size_t)n);
     P->final_flag = c.take<uint8_t>((size_t)n);
     P->member_tmp = c.take<uint8_t>((size_t)n);
@@ -159,6 +164,7 @@ void carve_gres(Carver& c, GresWork& w, int64_t s, int32_t d) {
     w.t_pad = t_pad;
     w.cand = c.take<float>((size_t)(d * s_pad));
     w.lo = c.take<float>((size_t)(d * t_pad));
+    w.hi = c.take<float>((size_t)(d * t_pad));
     w.k0 = c.take<uint32_t>((size_t)s_pad);
     w.v0 = c.take<uint32_t>((size_t)s_pad);
     w.k1 = c.take<uint32_t>((size_t)s_pad);
@@ -195,7 +201,7 @@ sky_status sky_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, i
 }
 
 size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params) {
-    if (!params || n < 1 || n > kMaxRows || !valid_d(d) || params->flags != 0) return 0;
+    if (!params || n < 1 || n > kMaxBuildRows || !valid_d(d) || params->flags != 0) return 0;
     int32_t p = 1, m = 0;
     if (resolve_partitions(n, d, params, &p, &m) != SKY_OK) return 0;
     sky_plan tmp;
@@ -209,7 +215,7 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
     if (!out) return SKY_ERR_INVALID_ARG;
     *out = nullptr;
     if (!x_soa || !params || !ws || !dev_status) return SKY_ERR_INVALID_ARG;
-    if (n < 1 || n > kMaxRows || !valid_d(d) || ld < n || params->flags != 0) return SKY_ERR_INVALID_ARG;
+    if (n < 1 || n > kMaxBuildRows || !valid_d(d) || ld < n || params->flags != 0) return SKY_ERR_INVALID_ARG;
     int32_t p = 1, m = 0;
     SKY_TRY(resolve_partitions(n, d, params, &p, &m));
     size_t need = sky_build_workspace_bytes(n, d, params);
@@ -285,7 +291,7 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     }
     SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
     SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID ? P->pruned : nullptr, P->seg, n, P->eng.w1,
-                                 P->count_tmp, st));
+                                 P->count_tmp, P->eng.flag, P->eng.scan, P->eng.scan_tmp, st));
     int32_t live = 0;
     SKY_HIP(hipMemcpyAsync(&live, P->count_tmp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SKY_HIP(hipStreamSynchronize(st));
@@ -316,12 +322,15 @@ sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_co
     const int32_t* final_list = P->local_list;
     int32_t count = (int32_t)P->info.local_count;
     if (P->p > 1) {
+        // the union of the local skylines, in position order (spatially coherent)
+        SKY_TRY(launch_compact_flags(P->local_flag, n, P->eng.w1, P->count_tmp, P->eng.flag,
+                                     P->eng.scan, P->eng.scan_tmp, st));
         SKY_TRY(launch_fill_u8(P->final_flag, n, 0, st));
         EngineProblem pb{};
         pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
         pb.seg_of_pos = nullptr;
         pb.nseg = 1;
-        pb.items = P->local_list; pb.n_items = count;
+        pb.items = P->eng.w1; pb.n_items = count;
         pb.flag_out = P->final_flag;
         pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
         EngineResult r{};

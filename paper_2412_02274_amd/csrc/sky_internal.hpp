@@ -53,6 +53,51 @@ __device__ __forceinline__ uint64_t match_any(uint32_t key, int bits, uint64_t a
     return m;
 }
 
+// Hilbert-curve key of a point of canonical values in [0, 1): `bits` bits per attribute,
+// bits * d <= 32. Coordinates are the top bits of the values (v * 2^bits, exact), mapped to
+// the curve with J. Skilling's transposition algorithm ("Programming the Hilbert curve",
+// AIP Conf. Proc. 707, 2004) and the transposed form is bit-interleaved into one integer.
+// Points that are close on the curve are close in space, which keeps the boxes of tiles of
+// consecutive points small.
+__device__ __forceinline__ uint32_t hilbert_key(const float* v, int d, int bits) {
+    uint32_t X[SKY_MAX_D];
+    const float scale = (float)(1u << bits);
+    const uint32_t cap = (1u << bits) - 1u;
+    for (int k = 0; k < d; ++k) {
+        const float t = v[k];
+        uint32_t c = (t >= 0.0f && t < 1.0f) ? (uint32_t)(t * scale) : 0u;
+        X[k] = c > cap ? cap : c;
+    }
+    const uint32_t M = 1u << (bits - 1);
+    for (uint32_t Q = M; Q > 1; Q >>= 1) {  // inverse undo
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < d; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < d; ++i) X[i] ^= X[i - 1];  // Gray encode
+    uint32_t t = 0;
+    for (uint32_t Q = M; Q > 1; Q >>= 1)
+        if (X[d - 1] & Q) t ^= Q - 1;
+    for (int i = 0; i < d; ++i) X[i] ^= t;
+    uint32_t code = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int i = 0; i < d; ++i) code = (code << 1) | ((X[i] >> b) & 1u);
+    return code;
+}
+
+// bits per attribute of the curve keys (bits * d <= 32)
+__host__ __device__ __forceinline__ int curve_bits(int d) {
+    int b = 32 / d;
+    return b > 16 ? 16 : (b < 1 ? 1 : b);
+}
+
 // ----------------------------------------------------------------------------------------
 // host helpers
 // ----------------------------------------------------------------------------------------
@@ -130,19 +175,23 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st);
 // sky_skyline.hip: segmented skyline engine (see the file header)
 struct EngineBuffers {
     int32_t* w0; int32_t* w1;      // work lists (capacity n)
-    int32_t* head;                 // head items, segment-grouped (capacity n)
-    int32_t* rest;                 // rest items, segment-grouped (capacity n)
-    int32_t* fsky;                 // head skyline items, segment-grouped (capacity n)
-    int32_t* out_list;             // confirmed skyline items (capacity n)
+    int32_t* head;                 // head groups, 64-aligned per segment (capacity hcap)
+    int32_t* rest;                 // rest groups (capacity n)
+    uint32_t* hval;                // [d][hcap] head candidate bit patterns (pads = all ones)
+    uint32_t* hlo;                 // [d][tcap] per-tile lower corners
+    uint32_t* hhi;                 // [d][tcap] per-tile upper corners
+    int64_t hcap, tcap;
     uint32_t* seg_min; uint32_t* seg_max;   // [nseg]
     int32_t* hist;                 // [nseg * kBins]
-    int32_t* seg_info;             // [nseg * 12] per-segment counters / offsets
+    int32_t* seg_info;             // [nseg * 8] per-segment counters / offsets
     uint8_t* dom;                  // [n] dominated flags
-    int32_t* tile_off;             // [2 * (nseg + 1)] tile offsets for head / rest
+    int32_t* tile_off;             // [2 * (nseg + 1)] item-tile offsets for head / rest
     int32_t* counters;             // [16] global counters
     unsigned long long* tests;     // [2] dominance-test counters
-    int32_t* scan_tmp;
+    int32_t* flag; int32_t* scan;  // [n] stable-compaction scratch
+    int32_t* scan_tmp;             // scan scratch for n values
 };
+int64_t engine_head_capacity(int64_t n, int32_t nseg);
 constexpr int kBins = 1024;
 struct EngineProblem {
     const float* xp; int64_t ldp; int32_t d; int32_t n_pos;  // rows live at positions [0, n_pos)
@@ -161,13 +210,14 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                       EngineResult* res, hipStream_t st);
 // helpers used by the API layer
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
-                                int32_t* out, int32_t* count, hipStream_t st);
+                                int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
+                                int32_t* scan_tmp, hipStream_t st);
 sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 // dst[rowid[q]] = src[q] for q < n (int32 and/or uint8 arrays)
 sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
                                int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st);
 sky_status launch_compact_flags(const uint8_t* flags, int32_t n, int32_t* out, int32_t* count,
-                                hipStream_t st);
+                                int32_t* flag, int32_t* scan, int32_t* scan_tmp, hipStream_t st);
 sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t* rowid,
                                int64_t n, uint8_t* member_tmp, uint8_t* member_out,
                                int64_t* sky_idx, int64_t cap, int64_t* dev_count,
@@ -178,6 +228,7 @@ sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t
 struct GresWork {
     float* cand;          // [d * s_pad] canonical candidates in spatial order
     float* lo;            // [d * t_pad] per-tile lower corner
+    float* hi;            // [d * t_pad] per-tile upper corner
     uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp;
     int32_t* ge_sorted;   // [s]
     int64_t s_pad, t_pad;

@@ -13,10 +13,12 @@
 //  Sliced   rows ordered by (t[dim], row index); the i-th (0-based) goes to floor(i p / n).
 //  None     one partition.
 //
-// Every path validates the domain (SKY_ERR_DOMAIN), writes a canonical SoA copy in
-// partition order (stable: rows of a partition keep their input order), the original row of
-// every position, its partition, and the FP32 attribute sum used as the monotone score that
-// orders the skyline filter (Sec. 2, scoring function).
+// Every path validates the domain (SKY_ERR_DOMAIN) and writes a canonical SoA copy in partition
+// order, with the rows of each partition along a Hilbert curve (a stable radix sort of the
+// Hilbert keys followed by a stable counting sort by partition), the original row of every
+// position, its partition, and the FP32 attribute sum used as the monotone score that orders
+// the skyline filter (Sec. 2, scoring function). The spatial order inside partitions keeps
+// the tile boxes of the dominance tests tight.
 //
 // Grid/Angular use a counting sort: per wave-tile histograms of the partition ids, one
 // exclusive scan of the partition-major table, then a stable scatter where each wave ranks
@@ -101,6 +103,7 @@ __global__ void __launch_bounds__(kBlock) part_id_kernel(const float* __restrict
 
 // ---- wave-tile histogram of partition ids ----------------------------------------------------
 __global__ void __launch_bounds__(kBlock) part_hist_kernel(const int32_t* __restrict__ part,
+                                                            const uint32_t* __restrict__ order,
                                                             int64_t n, int32_t p, int chunks,
                                                             int32_t* __restrict__ hist,
                                                             int64_t ntiles) {
@@ -115,7 +118,7 @@ __global__ void __launch_bounds__(kBlock) part_hist_kernel(const int32_t* __rest
         const int64_t base = tile * (int64_t)chunks * kWave;
         for (int c = 0; c < chunks; ++c) {
             int64_t idx = base + (int64_t)c * kWave + lane;
-            if (idx < n) atomicAdd(&my[part[idx]], 1);
+            if (idx < n) atomicAdd(&my[part[order ? (int64_t)order[idx] : idx]], 1);
         }
     }
     __syncthreads();
@@ -127,8 +130,8 @@ __global__ void __launch_bounds__(kBlock) part_hist_kernel(const int32_t* __rest
 template <int D>
 __global__ void __launch_bounds__(kBlock) part_scatter_kernel(
     const float* __restrict__ x, int64_t n, int32_t d_rt, int64_t ld,
-    const int32_t* __restrict__ part, int32_t p, int pbits, int chunks,
-    const int32_t* __restrict__ offs, int64_t ntiles, float* __restrict__ xp, int64_t ldp,
+    const int32_t* __restrict__ part, const uint32_t* __restrict__ order, int32_t p, int pbits,
+    int chunks, const int32_t* __restrict__ offs, int64_t ntiles, float* __restrict__ xp, int64_t ldp,
     int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
     extern __shared__ int32_t base[];  // [kWavesPerBlock][p]
     const int d = dget<D>(d_rt);
@@ -143,10 +146,11 @@ __global__ void __launch_bounds__(kBlock) part_scatter_kernel(
     const uint64_t lt = __lanemask_lt();
     const int64_t tbase = tile * (int64_t)chunks * kWave;
     for (int c = 0; c < chunks; ++c) {
-        int64_t i = tbase + (int64_t)c * kWave + lane;
-        bool valid = i < n;
+        const int64_t q = tbase + (int64_t)c * kWave + lane;
+        bool valid = q < n;
         uint64_t act = __ballot(valid);
         if (act == 0) break;
+        const int64_t i = valid ? (order ? (int64_t)order[q] : q) : 0;
         int32_t id = valid ? part[i] : 0;
         uint64_t peers = match_any((uint32_t)id, pbits, act);
         int32_t b = valid ? my[id] : 0;
@@ -217,6 +221,37 @@ __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restr
         }
         pruned[h] = (all_pos && A[h - diag]) ? 1 : 0;
     }
+}
+
+// ---- Hilbert key of every row (canonical values), with validation ----------------------------
+// Used to order the rows of each partition along a space-filling curve, so that consecutive
+// rows are close in space (tight tile boxes for the dominance tests).
+__global__ void __launch_bounds__(kBlock) curve_rows_kernel(const float* __restrict__ x, int64_t n,
+                                                             int32_t d, int64_t ld, int bits,
+                                                             uint32_t* __restrict__ keys,
+                                                             uint32_t* __restrict__ vals,
+                                                             int32_t* dev_status) {
+    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        float v[SKY_MAX_D];
+        for (int k = 0; k < d; ++k) {
+            float t = x[(int64_t)k * ld + i];
+            bad |= !in_domain(t);
+            v[k] = canon(t);
+        }
+        keys[i] = hilbert_key(v, d, bits);
+        vals[i] = (uint32_t)i;
+    }
+    if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
+}
+
+// Sliced: the row at rank q of the (value, row) order goes to partition floor(q p / n)
+__global__ void __launch_bounds__(kBlock) slice_parts_kernel(const uint32_t* __restrict__ order,
+                                                              int64_t n, int32_t p,
+                                                              int32_t* __restrict__ part) {
+    int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < n) part[order[q]] = (int32_t)((q * (int64_t)p) / n);
 }
 
 // ---- None: identity copy ------------------------------------------------------------------------
@@ -331,44 +366,48 @@ int64_t partition_hist_elems(int64_t n, int32_t p) {
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const int64_t n = a.n;
     const uint32_t rblocks = (uint32_t)ceil_div(n, kBlock);
-    if (a.scheme == SKY_NONE) {
-        SKY_DISPATCH_D(a.d, copy_identity_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d,
-                       a.ld, a.xp, a.ldp, a.rowid, a.seg, a.fsum, a.dev_status);
+    // 1. partition of every row (Grid / Angular directly, Sliced from the rank order)
+    if (a.scheme == SKY_GRID || a.scheme == SKY_ANGULAR) {
+        SKY_DISPATCH_D(a.d, part_id_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld,
+                       a.scheme, a.m, a.tan2, a.part_of_row, a.dev_status);
         SKY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(slice_offsets_kernel, dim3(1), dim3(64), 0, st, n, 1, a.part_off,
-                           a.pruned);
-        SKY_HIP(hipGetLastError());
-        return SKY_OK;
-    }
-    if (a.scheme == SKY_SLICED) {
+    } else if (a.scheme == SKY_SLICED) {
         hipLaunchKernelGGL(slice_keys_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld,
                            a.slice_dim, a.k0, a.v0, a.dev_status);
         SKY_HIP(hipGetLastError());
         SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, 32, a.radix_tmp, st));
-        SKY_DISPATCH_D(a.d, slice_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d,
-                       a.ld, a.p, (const uint32_t*)a.v0, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
+        hipLaunchKernelGGL(slice_parts_kernel, dim3(rblocks), dim3(kBlock), 0, st,
+                           (const uint32_t*)a.v0, n, a.p, a.part_of_row);
         SKY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(slice_offsets_kernel, dim3((uint32_t)ceil_div(a.p + 1, 256)), dim3(256),
-                           0, st, n, a.p, a.part_off, a.pruned);
+    }
+    // 2. every row in Hilbert order (stable): the order rows take inside their partition
+    const int bits = curve_bits(a.d);
+    hipLaunchKernelGGL(curve_rows_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld, bits,
+                       a.k0, a.v0, a.dev_status);
+    SKY_HIP(hipGetLastError());
+    SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, bits * a.d, a.radix_tmp, st));
+    const uint32_t* order = a.v0;
+    if (a.p == 1) {
+        SKY_DISPATCH_D(a.d, slice_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d,
+                       a.ld, 1, order, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
+        SKY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(slice_offsets_kernel, dim3(1), dim3(64), 0, st, n, 1, a.part_off, a.pruned);
         SKY_HIP(hipGetLastError());
         return SKY_OK;
     }
-    // Grid / Angular: counting sort by partition id
-    SKY_DISPATCH_D(a.d, part_id_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld,
-                   a.scheme, a.m, a.tan2, a.part_of_row, a.dev_status);
-    SKY_HIP(hipGetLastError());
+    // 3. stable counting sort by partition over the curve order
     const int chunks = part_chunks(n, a.p);
     const int64_t ntiles = ceil_div(n, (int64_t)chunks * kWave);
     const uint32_t tblocks = (uint32_t)ceil_div(ntiles, kWavesPerBlock);
     const size_t lds = sizeof(int32_t) * (size_t)kWavesPerBlock * (size_t)a.p;
     hipLaunchKernelGGL(part_hist_kernel, dim3(tblocks), dim3(kBlock), lds, st,
-                       (const int32_t*)a.part_of_row, n, a.p, chunks, a.hist, ntiles);
+                       (const int32_t*)a.part_of_row, order, n, a.p, chunks, a.hist, ntiles);
     SKY_HIP(hipGetLastError());
     SKY_TRY(launch_exclusive_scan(a.hist, a.hist, (int64_t)a.p * ntiles, a.scan_tmp, st));
     const int pbits = bits_for(a.p);
     SKY_DISPATCH_D(a.d, part_scatter_kernel, dim3(tblocks), dim3(kBlock), lds, st, a.x, n, a.d,
-                   a.ld, (const int32_t*)a.part_of_row, a.p, pbits, chunks, (const int32_t*)a.hist,
-                   ntiles, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
+                   a.ld, (const int32_t*)a.part_of_row, order, a.p, pbits, chunks,
+                   (const int32_t*)a.hist, ntiles, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
     SKY_HIP(hipGetLastError());
     hipLaunchKernelGGL(part_offsets_kernel, dim3((uint32_t)ceil_div(a.p + 1, 256)), dim3(256), 0,
                        st, (const int32_t*)a.hist, ntiles, a.p, n, a.part_off);

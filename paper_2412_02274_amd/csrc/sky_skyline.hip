@@ -8,20 +8,29 @@
 //      segment's min and max; the head is the set of rows in the lowest bins holding at
 //      least kHead rows. f is monotone: a row dominating another has f <= the other's f
 //      (FP32 additions are monotone), so every dominator of a head row is itself in the head.
-//   2. head skyline: every head row is tested against every other head row of its segment
-//      (all pairs, early exit). The survivors are exactly the segment's skyline rows inside
-//      the head (their dominators would be in the head), so they are final.
-//   3. filter: every other live row is tested against the head skyline of its segment; the
-//      survivors form the next round's live set. A row dominated by some row of the head is
-//      dominated by a head skyline row (transitivity), so no skyline row is ever dropped, and
-//      every row of the head leaves the live set, so the rounds terminate.
+//   2. head skyline: every head row is tested against the other head rows of its segment.
+//      The survivors are exactly the segment's skyline rows inside the head (their
+//      dominators would be in the head), so they are final.
+//   3. filter: every other live row is tested against the head rows of its segment (a row
+//      dominated by a head row is dominated by a head skyline row, by transitivity, so
+//      testing against all head rows is exact); the survivors form the next live set. Every
+//      head row leaves the live set, so the rounds terminate.
 // Rows are compared through their canonical FP32 bit patterns (exact for [0, 1) data).
 //
-// Layout: positions index a partition-contiguous SoA copy xp[k*ldp + pos]; lists hold
-// positions. Head/rest lists are grouped by segment (offsets from a scan over segments);
-// the test kernels run one workgroup per tile of <= 256 items of one segment, stage 256
-// candidate rows at a time in LDS, and stop as soon as every item of the tile is dominated.
-// Bound: VALU compares (skyline-heavy data) or the filter's HBM reads (uniform data).
+// Spatial pruning. Positions index a partition-contiguous copy whose rows are in Hilbert-curve
+// order inside each partition, and every list of the engine stays in position order
+// (stable scan-based compactions). So each segment's head group is a spatially coherent
+// sequence; it is stored 64-aligned (values and positions) and cut into tiles of 64 with the
+// componentwise minimum `lo` and maximum `hi` of each tile. A tile can hold a dominator of t
+// only if lo <= t in every attribute; if moreover hi <= t everywhere and hi < t somewhere,
+// every row of the (non-empty) tile dominates t. So each test first checks 64 tile boxes per
+// ballot, decides at once when a box dominates, and otherwise tests only the candidates of
+// the surviving tiles (exact: no dominator is ever skipped, none is ever invented).
+//
+// Test kernels take one item at a time per wavefront: the 64 lanes test 64 candidates (or
+// 64 tile boxes) at once and a ballot ends the item at its first dominator, so no lane waits
+// behind another item. No LDS, no workgroup barriers.
+// Bound: VALU compares and L2 latency (candidate values are a few hundred KB per segment).
 #include "sky_internal.hpp"
 
 namespace sky {
@@ -29,18 +38,26 @@ namespace sky {
 namespace {
 
 constexpr int kHead = 8192;   // head rows per segment and round (target)
-constexpr int kItems = kBlock; // items per test tile
-constexpr int kLdsBytes = 40 * 1024;  // LDS for the staged candidate chunk
-constexpr int kMinBlocks = 2048; // test grids are split along candidates up to this many blocks
+constexpr int kTargetWaves = 8192;  // waves per test launch the item split aims at
+constexpr int kTile = 64;     // candidates per tile box
+constexpr int kBatch = 4;     // candidate tiles fetched per round trip
+constexpr uint32_t kPad = 0xFFFFFFFFu;  // value of padding candidates: never <= a real value
+constexpr int kBoxLds = 4096;           // uint32 tile-box values cached in LDS per workgroup
+constexpr uint32_t kMaxGrid = 8192;     // workgroups of the grid-stride kernels
 
 // seg_info layout per segment (int32 x kInfo)
-enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_HCUR, SI_RCUR,
-       SI_FCUR, kInfo = 12 };
+enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, kInfo = 8 };
 // global counters
 enum { C_NEXT = 0, C_OUT, C_HTILES, C_RTILES, C_MAXH, C_HTOT, C_RTOT, kCounters = 16 };
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
+
+// base[idx] with a 32-bit byte offset (a wave-uniform base plus a per-lane offset); callers
+// keep idx below 2^30 (rows are capped accordingly).
+__device__ __forceinline__ uint32_t ld32(const uint32_t* base, uint32_t idx) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (idx << 2));
+}
 
 __device__ __forceinline__ int32_t seg_of(const int32_t* seg_of_pos, int32_t pos) {
     return seg_of_pos ? seg_of_pos[pos] : 0;
@@ -129,6 +146,11 @@ __device__ __forceinline__ float seg_scale(uint32_t lo, uint32_t hi) {
     return span > 0.0f ? (float)kBins / span : 0.0f;
 }
 
+__device__ __forceinline__ int32_t item_bin(const float* fsum, const uint32_t* smin,
+                                            const uint32_t* smax, int32_t s, int32_t pos) {
+    return bin_of(fsum[pos], __uint_as_float(smin[s]), seg_scale(smin[s], smax[s]));
+}
+
 __global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict__ items, int32_t n,
                                                        const float* __restrict__ fsum,
                                                        const int32_t* __restrict__ seg_of_pos,
@@ -139,8 +161,64 @@ __global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict_
     if (i >= n) return;
     int32_t pos = items[i];
     int32_t s = seg_of(seg_of_pos, pos);
-    int32_t b = bin_of(fsum[pos], __uint_as_float(smin[s]), seg_scale(smin[s], smax[s]));
-    atomicAdd(&hist[(int64_t)s * kBins + b], 1);
+    atomicAdd(&hist[(int64_t)s * kBins + item_bin(fsum, smin, smax, s, pos)], 1);
+}
+
+// Single-segment variants (the merge phase and unpartitioned data): grid-stride loops with
+// block-private LDS bins / block reductions, so that global atomics stay few.
+__global__ void __launch_bounds__(kBlock) minmax1_kernel(const int32_t* __restrict__ items, int32_t n,
+                                                          const float* __restrict__ fsum,
+                                                          uint32_t* __restrict__ smin,
+                                                          uint32_t* __restrict__ smax,
+                                                          int32_t* __restrict__ info) {
+    __shared__ uint32_t rmin[kBlock / kWave], rmax[kBlock / kWave];
+    __shared__ int32_t rcnt[kBlock / kWave];
+    uint32_t vmin = 0xFFFFFFFFu, vmax = 0u;
+    int32_t cnt = 0;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        uint32_t fb = fbits(fsum[items[i]]);
+        vmin = fb < vmin ? fb : vmin;
+        vmax = fb > vmax ? fb : vmax;
+        ++cnt;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        uint32_t a = __shfl_xor(vmin, off, kWave), b = __shfl_xor(vmax, off, kWave);
+        vmin = a < vmin ? a : vmin;
+        vmax = b > vmax ? b : vmax;
+        cnt += __shfl_xor(cnt, off, kWave);
+    }
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) { rmin[wave] = vmin; rmax[wave] = vmax; rcnt[wave] = cnt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            vmin = rmin[w] < vmin ? rmin[w] : vmin;
+            vmax = rmax[w] > vmax ? rmax[w] : vmax;
+            cnt += rcnt[w];
+        }
+        if (cnt) {
+            atomicMin(&smin[0], vmin);
+            atomicMax(&smax[0], vmax);
+            atomicAdd(&info[SI_LIVE], cnt);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict__ items, int32_t n,
+                                                        const float* __restrict__ fsum,
+                                                        const uint32_t* __restrict__ smin,
+                                                        const uint32_t* __restrict__ smax,
+                                                        int32_t* __restrict__ hist) {
+    __shared__ int32_t h[kBins];
+    for (int b = threadIdx.x; b < kBins; b += kBlock) h[b] = 0;
+    __syncthreads();
+    const float lo = __uint_as_float(smin[0]);
+    const float scale = seg_scale(smin[0], smax[0]);
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
+        atomicAdd(&h[bin_of(fsum[items[i]], lo, scale)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += kBlock)
+        if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
 // One wave per segment: smallest bin b* whose cumulative count reaches kHead.
@@ -176,30 +254,41 @@ __global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32
     }
 }
 
-// Offsets of every segment's head / rest group, their tile offsets, and round totals
-// (single workgroup, sequential over blocks of 256 segments).
-__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32_t* __restrict__ info,
+// Per segment: list offset (scan of live counts), 64-aligned head offset (scan of head counts
+// rounded up to 64), rest offset, and the item-tile offsets of both groups; round totals.
+// Single workgroup, sequential over blocks of 256 segments.
+__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32_t hitems,
+                                                              int32_t ritems,
+                                                              int32_t* __restrict__ info,
                                                               int32_t* __restrict__ tile_off,
                                                               int32_t* __restrict__ counters) {
-    __shared__ int32_t carry[4];
-    __shared__ int32_t wsum[4][kBlock / kWave];
+    constexpr int Q = 5;
+    __shared__ int32_t carry[Q];
+    __shared__ int32_t wsum[Q][kBlock / kWave];
     __shared__ int32_t wmax[kBlock / kWave];
     __shared__ int32_t maxh;
-    if (threadIdx.x == 0) { carry[0] = carry[1] = carry[2] = carry[3] = 0; maxh = 0; }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < Q; ++q) carry[q] = 0;
+        maxh = 0;
+    }
     __syncthreads();
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
     for (int base = 0; base < nseg; base += kBlock) {
         int32_t s = base + threadIdx.x;
-        int32_t hn = 0, rn = 0, ht = 0, rt = 0;
+        int32_t v[Q] = {0, 0, 0, 0, 0};
+        int32_t hn = 0;
         if (s < nseg) {
             hn = info[s * kInfo + SI_HEADN];
-            rn = info[s * kInfo + SI_RESTN];
-            ht = (hn + kItems - 1) / kItems;
-            rt = (rn + kItems - 1) / kItems;
+            int32_t rn = info[s * kInfo + SI_RESTN];
+            v[0] = (hn + kTile - 1) / kTile * kTile;    // aligned head slots
+            v[1] = rn;                                   // rest items
+            v[2] = (hn + hitems - 1) / hitems;          // head item tiles
+            v[3] = (rn + ritems - 1) / ritems;          // rest item tiles
+            v[4] = info[s * kInfo + SI_LIVE];            // list items
         }
-        int32_t v[4] = {hn, rn, ht, rt}, inc[4];
-        for (int q = 0; q < 4; ++q) {
+        int32_t inc[Q];
+        for (int q = 0; q < Q; ++q) {
             inc[q] = v[q];
             for (int off = 1; off < kWave; off <<= 1) {
                 int32_t o = __shfl_up(inc[q], off, kWave);
@@ -214,8 +303,8 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
         }
         if (lane == 0) wmax[wave] = mh;
         __syncthreads();
-        int32_t excl[4];
-        for (int q = 0; q < 4; ++q) {
+        int32_t excl[Q];
+        for (int q = 0; q < Q; ++q) {
             int32_t before = carry[q];
             for (int w = 0; w < wave; ++w) before += wsum[q][w];
             excl[q] = before + inc[q] - v[q];
@@ -223,15 +312,13 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
         if (s < nseg) {
             info[s * kInfo + SI_HEADOFF] = excl[0];
             info[s * kInfo + SI_RESTOFF] = excl[1];
+            info[s * kInfo + SI_LISTOFF] = excl[4];
             tile_off[s] = excl[2];
             tile_off[(nseg + 1) + s] = excl[3];
-            info[s * kInfo + SI_HCUR] = 0;
-            info[s * kInfo + SI_RCUR] = 0;
-            info[s * kInfo + SI_FCUR] = 0;
         }
         __syncthreads();
         if (threadIdx.x == kBlock - 1)
-            for (int q = 0; q < 4; ++q) carry[q] = excl[q] + v[q];
+            for (int q = 0; q < Q; ++q) carry[q] = excl[q] + v[q];
         if (threadIdx.x == 0)
             for (int w = 0; w < kBlock / kWave; ++w) maxh = wmax[w] > maxh ? wmax[w] : maxh;
         __syncthreads();
@@ -247,35 +334,94 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
     }
 }
 
+// is_head flag per list item (for the stable split)
+__global__ void __launch_bounds__(kBlock) head_flag_kernel(const int32_t* __restrict__ items, int32_t n,
+                                                            const float* __restrict__ fsum,
+                                                            const int32_t* __restrict__ seg_of_pos,
+                                                            const uint32_t* __restrict__ smin,
+                                                            const uint32_t* __restrict__ smax,
+                                                            const int32_t* __restrict__ info,
+                                                            int32_t* __restrict__ flag) {
+    int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int32_t pos = items[i];
+    int32_t s = seg_of(seg_of_pos, pos);
+    flag[i] = item_bin(fsum, smin, smax, s, pos) <= info[s * kInfo + SI_BSTAR] ? 1 : 0;
+}
+
+// Stable split: the list is in position order, hence grouped by segment; hscan is the
+// exclusive scan of the head flags over the list.
 __global__ void __launch_bounds__(kBlock) split_kernel(const int32_t* __restrict__ items, int32_t n,
-                                                        const float* __restrict__ fsum,
                                                         const int32_t* __restrict__ seg_of_pos,
-                                                        const uint32_t* __restrict__ smin,
-                                                        const uint32_t* __restrict__ smax,
-                                                        int32_t* __restrict__ info,
+                                                        const int32_t* __restrict__ info,
+                                                        const int32_t* __restrict__ flag,
+                                                        const int32_t* __restrict__ hscan,
                                                         int32_t* __restrict__ head,
                                                         int32_t* __restrict__ rest,
                                                         uint8_t* __restrict__ dom) {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < n;
-    int32_t pos = 0, s = 0;
-    bool is_head = false;
-    if (valid) {
-        pos = items[i];
-        s = seg_of(seg_of_pos, pos);
-        int32_t b = bin_of(fsum[pos], __uint_as_float(smin[s]), seg_scale(smin[s], smax[s]));
-        is_head = b <= info[s * kInfo + SI_BSTAR];
-        dom[pos] = 0;
+    int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int32_t pos = items[i];
+    const int32_t s = seg_of(seg_of_pos, pos);
+    const int32_t* si = info + s * kInfo;
+    const int32_t lo = si[SI_LISTOFF];
+    const int32_t hr = hscan[i] - hscan[lo];
+    if (flag[i]) head[si[SI_HEADOFF] + hr] = pos;
+    else rest[si[SI_RESTOFF] + (i - lo) - hr] = pos;
+    dom[pos] = 0;
+}
+
+// largest s with info[s].field <= v (the field ascending in s)
+__device__ __forceinline__ int32_t find_segment(const int32_t* info, int32_t nseg, int field,
+                                                int32_t v) {
+    int32_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) >> 1;
+        if (info[mid * kInfo + field] <= v) lo = mid; else hi = mid - 1;
     }
-    const int32_t hs = wave_slot(info + SI_HCUR, kInfo, s, valid && is_head);
-    const int32_t rs = wave_slot(info + SI_RCUR, kInfo, s, valid && !is_head);
-    if (valid) {
-        if (is_head) head[info[s * kInfo + SI_HEADOFF] + hs] = pos;
-        else rest[info[s * kInfo + SI_RESTOFF] + rs] = pos;
+    return lo;
+}
+
+// One wave per 64-slot tile of the aligned head buffer: candidate values (pads = kPad, pad
+// positions = -1) and the tile box: componentwise minimum lo and maximum hi of its rows.
+template <int D>
+__global__ void __launch_bounds__(kBlock) head_values_kernel(
+    const float* __restrict__ xp, int64_t ldp, int32_t d_rt, int32_t nseg,
+    const int32_t* __restrict__ info, const int32_t* __restrict__ counters,
+    int32_t* __restrict__ head, uint32_t* __restrict__ hval, int64_t hcap,
+    uint32_t* __restrict__ hlo, uint32_t* __restrict__ hhi, int64_t tcap) {
+    constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    const int d = dget<D>(d_rt);
+    const int lane = (int)lane_id();
+    const int32_t htot = counters[C_HTOT];
+    for (int32_t tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; tile * kTile < htot;
+         tile += gridDim.x * (kBlock / kWave)) {
+        const int32_t j0 = tile * kTile;
+        const int32_t j = j0 + lane;
+        const int32_t s = find_segment(info, nseg, SI_HEADOFF, j0);
+        const bool valid = j < info[s * kInfo + SI_HEADOFF] + info[s * kInfo + SI_HEADN];
+        const int32_t pos = valid ? head[j] : -1;
+        if (!valid) head[j] = -1;
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) {
+                uint32_t v = valid ? fbits(xp[(int64_t)k * ldp + pos]) : kPad;
+                hval[(int64_t)k * hcap + j] = v;
+                uint32_t h = valid ? v : 0u;
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    uint32_t o = __shfl_xor(v, off, kWave), q = __shfl_xor(h, off, kWave);
+                    v = o < v ? o : v;
+                    h = q > h ? q : h;
+                }
+                if (lane == 0) {
+                    hlo[(int64_t)k * tcap + tile] = v;
+                    hhi[(int64_t)k * tcap + tile] = h;
+                }
+            }
     }
 }
 
-// Locate the segment of a tile: largest s with tile_off[s] <= t (tile_off[0..nseg] ascending).
+// Locate the segment of an item tile: largest s with tile_off[s] <= t.
 __device__ __forceinline__ int32_t tile_segment(const int32_t* tile_off, int32_t nseg, int32_t t) {
     int32_t lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -285,127 +431,200 @@ __device__ __forceinline__ int32_t tile_segment(const int32_t* tile_off, int32_t
     return lo;
 }
 
-// Items of one segment tile (blockIdx.x, 256 items, 64 per wave) against a range of that
-// segment's candidates (blockIdx.y selects the range when the grid is split along
-// candidates). mode 0: items and candidates = the head group; mode 1: items = the rest group,
-// candidates = the head-skyline group (count in SI_FCUR).
-// The candidate range is staged in LDS chunk by chunk (structure of arrays, lane-consecutive).
-// Each wave takes its items one at a time; the 64 lanes test 64 candidates at once and a
-// ballot ends the item at its first dominator, so lanes never idle behind other items.
-// A dominated item gets dom[pos] = 1 (idempotent; items already flagged are skipped).
+// One item t (values tv, uniform across the wave) against the head group of its segment:
+// returns true when some head row dominates t. Lanes test 64 tile boxes per step (from LDS
+// when cached, else from global memory), then up to kBatch passing tiles per round trip.
+// All loads are unconditional: lanes past the end read the padding slot (all ones, never a
+// dominator), so the loop has no divergent branches. Addresses are a wave-uniform base per
+// attribute plus an unsigned 32-bit lane offset.
+template <int DM, bool kLds>
+__device__ __forceinline__ bool dominated_in_head(const uint32_t* tv, int d, const uint32_t* box,
+                                                  const uint32_t* __restrict__ hlo,
+                                                  const uint32_t* __restrict__ hhi, int64_t tcap,
+                                                  uint32_t t0, const uint32_t* __restrict__ hval,
+                                                  int64_t hcap, uint32_t hoff, int32_t ntile,
+                                                  uint32_t padslot, unsigned long long& ntests) {
+    const int lane = (int)lane_id();
+    const int32_t nb = ntile * d;
+    for (int32_t c = 0; c < ntile; c += kWave) {
+        const int32_t tl = c + lane;
+        const bool inr = tl < ntile;
+        const uint32_t ti = inr ? (uint32_t)tl : 0u;
+        bool pass = inr, hle = true, hlt = false;
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) {
+                const uint32_t lo = kLds ? box[k * ntile + ti] : ld32(hlo + k * tcap, t0 + ti);
+                const uint32_t hi = kLds ? box[nb + k * ntile + ti] : ld32(hhi + k * tcap, t0 + ti);
+                pass &= lo <= tv[k];
+                hle &= hi <= tv[k];
+                hlt |= hi < tv[k];
+            }
+        ntests += kWave;  // 64 box tests
+        // a non-empty tile whose upper corner dominates t: every row of it dominates t
+        if (__ballot(pass && hle && hlt)) return true;
+        uint64_t mask = __ballot(pass);
+        while (mask) {
+            uint32_t jb[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                jb[b] = padslot + (uint32_t)lane;
+                if (mask) {
+                    const int tb = __ffsll((unsigned long long)mask) - 1;
+                    mask &= mask - 1;
+                    jb[b] = hoff + (uint32_t)(c + tb) * kTile + (uint32_t)lane;
+                    ntests += kTile;  // 64 candidate tests
+                }
+            }
+            uint32_t cv[kBatch][DM];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) cv[b][k] = ld32(hval + k * hcap, jb[b]);
+            bool dm = false;
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                bool le = true, lt = false;
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) {
+                        le &= cv[b][k] <= tv[k];
+                        lt |= cv[b][k] < tv[k];
+                    }
+                dm |= le && lt;
+            }
+            if (__ballot(dm)) return true;
+        }
+    }
+    return false;
+}
+
+// Items of one segment tile (ipw items per wave, 4 waves) against the head group of the
+// segment; ipw <= 64 shrinks with the item count so that small rounds still fill the chip.
+// mode 0: items = the head group itself; mode 1: items = the rest group. A dominated item
+// gets dom[pos] = 1.
 template <int D>
 __global__ void __launch_bounds__(kBlock) test_kernel(
     int mode, const float* __restrict__ xp, int64_t ldp, int32_t d_rt, int32_t nseg,
     const int32_t* __restrict__ tile_off, const int32_t* __restrict__ info,
-    const int32_t* __restrict__ items_all, const int32_t* __restrict__ cand_all, int32_t span,
-    int32_t chunk, uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
-    extern __shared__ uint32_t cvs[];  // [d][chunk]
+    const int32_t* __restrict__ items_all, const uint32_t* __restrict__ hval, int64_t hcap,
+    const uint32_t* __restrict__ hlo, const uint32_t* __restrict__ hhi, int64_t tcap, int32_t ipw,
+    uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    __shared__ uint32_t box[kBoxLds];  // [2][k][ntile] tile boxes (lo, hi) of the current segment
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
     const int32_t* toff = tile_off + (mode == 0 ? 0 : (nseg + 1));
-    const int32_t t = blockIdx.x;
-    if (t >= toff[nseg]) return;  // uniform per workgroup
-    const int32_t s = tile_segment(toff, nseg, t);
-    const int32_t* si = info + s * kInfo;
-    const int32_t ioff = mode == 0 ? si[SI_HEADOFF] : si[SI_RESTOFF];
-    const int32_t icnt = mode == 0 ? si[SI_HEADN] : si[SI_RESTN];
-    const int32_t coff = si[SI_HEADOFF];
-    const int32_t ccnt = mode == 0 ? si[SI_HEADN] : si[SI_FCUR];
-    const int32_t r0 = (int32_t)blockIdx.y * span;
-    if (r0 >= ccnt) return;  // uniform
-    const int32_t r1 = (ccnt - r0) < span ? ccnt : r0 + span;
-    const int32_t ibase = (t - toff[s]) * kItems + wave * kWave;
-    const int32_t nmine = icnt - ibase < kWave ? (icnt - ibase > 0 ? icnt - ibase : 0) : kWave;
-    // this wave's items: position held by lane i (uniform reads below via shuffles)
-    const int32_t mypos = lane < nmine ? items_all[ioff + ibase + lane] : 0;
-    uint64_t done = __ballot(lane < nmine ? dom[mypos] != 0 : true);  // bit i: item i finished
+    const int32_t ntiles_items = toff[nseg];
+    const uint32_t padslot = (uint32_t)(hcap - kTile);
+    int32_t cached = -1;  // segment whose boxes are in LDS (uniform per workgroup)
     unsigned long long ntests = 0;
-    for (int32_t c0 = r0; c0 < r1; c0 += chunk) {
-        const int32_t nc = (r1 - c0) < chunk ? (r1 - c0) : chunk;
-        // barrier: the previous chunk is fully consumed; stop when every item is finished
-        if (__syncthreads_or(done != ~0ull) == 0) break;
-        for (int32_t j = threadIdx.x; j < nc; j += kBlock) {
-            const int32_t cp = cand_all[coff + c0 + j];
-#pragma unroll
-            for (int k = 0; k < DM; ++k)
-                if (k < d) cvs[k * chunk + j] = fbits(xp[(int64_t)k * ldp + cp]);
+    for (int32_t t = blockIdx.x; t < ntiles_items; t += gridDim.x) {
+        const int32_t s = tile_segment(toff, nseg, t);
+        const int32_t* si = info + s * kInfo;
+        const int32_t hoff = si[SI_HEADOFF];
+        const int32_t hn = si[SI_HEADN];
+        const int32_t ntile = (hn + kTile - 1) / kTile;
+        const int32_t t0 = hoff / kTile;
+        const int32_t nb = ntile * d;
+        const bool in_lds = 2 * nb <= kBoxLds;
+        if (in_lds && s != cached) {
+            __syncthreads();  // every wave is done with the previous boxes
+            for (int32_t e = threadIdx.x; e < nb; e += kBlock) {
+                const int32_t k = e / ntile, tl = e - k * ntile;
+                box[e] = hlo[(int64_t)k * tcap + t0 + tl];
+                box[nb + e] = hhi[(int64_t)k * tcap + t0 + tl];
+            }
+            __syncthreads();
+            cached = s;
         }
-        __syncthreads();
-        uint64_t todo = ~done;
+        const int32_t ioff = mode == 0 ? hoff : si[SI_RESTOFF];
+        const int32_t icnt = mode == 0 ? hn : si[SI_RESTN];
+        const int32_t ibase = (t - toff[s]) * (ipw * (kBlock / kWave)) + wave * ipw;
+        const int32_t nmine = icnt - ibase < ipw ? (icnt - ibase > 0 ? icnt - ibase : 0) : ipw;
+        // lane i holds item i of this wave
+        const bool have = lane < nmine;
+        const uint32_t myidx = (uint32_t)(ioff + ibase + (have ? lane : 0));
+        const uint32_t mypos = have ? (uint32_t)items_all[myidx] : 0u;
+        uint32_t mv[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d)
+                mv[k] = !have ? 0u
+                              : (mode == 0 ? ld32(hval + k * hcap, myidx)
+                                           : ld32(reinterpret_cast<const uint32_t*>(xp) + k * ldp, mypos));
+        uint64_t todo = __ballot(have && dom[mypos] == 0);
         while (todo) {
             const int i = __ffsll((unsigned long long)todo) - 1;
             todo &= todo - 1;
-            const int32_t pos = __shfl(mypos, i, kWave);
             uint32_t tv[DM];
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d) tv[k] = fbits(xp[(int64_t)k * ldp + pos]);
-            int32_t j0 = 0;
-            bool found = false;
-            for (; j0 < nc; j0 += kWave) {
-                const int32_t j = j0 + lane;
-                bool le = j < nc, lt = false;
-#pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) {
-                        const uint32_t c = le ? cvs[k * chunk + j] : 0u;
-                        le &= c <= tv[k];
-                        lt |= c < tv[k];
-                    }
-                if (__ballot(le && lt)) { found = true; break; }
-            }
-            ntests += (unsigned long long)((j0 + kWave) < nc ? (j0 + kWave) : nc);
-            if (found) {
-                done |= 1ull << i;
-                if (lane == 0) dom[pos] = 1;
-            }
+                if (k < d) tv[k] = __shfl(mv[k], i, kWave);
+            const bool found =
+                in_lds ? dominated_in_head<DM, true>(tv, d, box, hlo, hhi, tcap, (uint32_t)t0, hval, hcap,
+                                                     (uint32_t)hoff, ntile, padslot, ntests)
+                       : dominated_in_head<DM, false>(tv, d, box, hlo, hhi, tcap, (uint32_t)t0, hval,
+                                                      hcap, (uint32_t)hoff, ntile, padslot, ntests);
+            if (found && lane == i) dom[mypos] = 1;
         }
     }
-    // per-wave tally (lane 0 holds the wave's count)
     if (lane == 0 && ntests) atomicAdd(&tests[mode], ntests);
 }
 
-// Head survivors -> head-skyline group of their segment, output flags and output list.
+// Head survivors -> output flags and output list (order irrelevant).
 __global__ void __launch_bounds__(kBlock) compact_head_kernel(
     const int32_t* __restrict__ head, const int32_t* __restrict__ counters,
-    const int32_t* __restrict__ seg_of_pos, const uint8_t* __restrict__ dom,
-    int32_t* __restrict__ info, int32_t* __restrict__ fsky, uint8_t* __restrict__ flag_out,
+    const uint8_t* __restrict__ dom, uint8_t* __restrict__ flag_out,
     int32_t* __restrict__ out_list, int32_t* __restrict__ out_counter) {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < counters[C_HTOT];
-    int32_t pos = 0, s = 0;
-    bool keep = false;
-    if (valid) {
-        pos = head[i];
-        s = seg_of(seg_of_pos, pos);
-        keep = dom[pos] == 0;
-    }
-    const int32_t fs = wave_slot(info + SI_FCUR, kInfo, s, keep);
-    const int32_t os = wave_slot(out_counter, 0, 0, keep);
-    if (keep) {
-        fsky[info[s * kInfo + SI_HEADOFF] + fs] = pos;
-        flag_out[pos] = 1;
-        out_list[os] = pos;
+    const int32_t htot = counters[C_HTOT];
+    for (int32_t base = blockIdx.x * kBlock; base < htot; base += gridDim.x * kBlock) {
+        const int32_t i = base + threadIdx.x;
+        bool keep = false;
+        int32_t pos = -1;
+        if (i < htot) {
+            pos = head[i];
+            keep = pos >= 0 && dom[pos] == 0;
+        }
+        const int32_t os = wave_slot(out_counter, 0, 0, keep);
+        if (keep) {
+            flag_out[pos] = 1;
+            out_list[os] = pos;
+        }
     }
 }
 
-// Rest survivors -> next work list.
-__global__ void __launch_bounds__(kBlock) compact_rest_kernel(const int32_t* __restrict__ rest,
+// keep flags of the rest items for i < n_bound (0 beyond the rest count)
+__global__ void __launch_bounds__(kBlock) rest_flag_kernel(const int32_t* __restrict__ rest,
+                                                            const int32_t* __restrict__ counters,
+                                                            const uint8_t* __restrict__ dom,
+                                                            int32_t n_bound, int32_t* __restrict__ flag) {
+    const int32_t rtot = counters[C_RTOT];
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n_bound; i += gridDim.x * kBlock)
+        flag[i] = (i < rtot && dom[rest[i]] == 0) ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) rest_compact_kernel(const int32_t* __restrict__ rest,
                                                                int32_t* __restrict__ counters,
-                                                               const uint8_t* __restrict__ dom,
+                                                               const int32_t* __restrict__ flag,
+                                                               const int32_t* __restrict__ scan,
                                                                int32_t* __restrict__ next) {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < counters[C_RTOT];
-    int32_t pos = 0;
-    bool keep = false;
-    if (valid) {
-        pos = rest[i];
-        keep = dom[pos] == 0;
+    const int32_t n = counters[C_RTOT];
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        if (flag[i]) next[scan[i]] = rest[i];
+        if (i == n - 1) counters[C_NEXT] = scan[i] + flag[i];
     }
-    const int32_t slot = wave_slot(counters + C_NEXT, 0, 0, keep);
-    if (keep) next[slot] = pos;
+}
+
+// the padding slots at the end of the head buffer: all ones in every attribute
+__global__ void pad_slots_kernel(uint32_t* __restrict__ hval, int64_t hcap, int32_t d) {
+    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < d * kTile) {
+        const int32_t k = e / kTile, l = e - k * kTile;
+        hval[(int64_t)k * hcap + (hcap - kTile) + l] = kPad;
+    }
 }
 
 __global__ void zero_i32_kernel(int32_t* __restrict__ p, int32_t n) {
@@ -419,30 +638,7 @@ __global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int32_t n) {
 }
 
 // positions [0, n) whose segment is not skipped
-__global__ void __launch_bounds__(kBlock) iota_filtered_kernel(const uint8_t* __restrict__ skip,
-                                                                const int32_t* __restrict__ seg,
-                                                                int32_t n, int32_t* __restrict__ out,
-                                                                int32_t* __restrict__ count) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    bool keep = i < n && !(skip && skip[seg[i]]);
-    uint64_t m = __ballot(keep);
-    int32_t base = 0;
-    if (lane_id() == 0 && m) base = atomicAdd(count, (int32_t)__popcll(m));
-    base = __shfl(base, 0, kWave);
-    if (keep) out[base + (int32_t)__popcll(m & __lanemask_lt())] = i;
-}
 
-__global__ void __launch_bounds__(kBlock) compact_flags_kernel(const uint8_t* __restrict__ flags,
-                                                                int32_t n, int32_t* __restrict__ out,
-                                                                int32_t* __restrict__ count) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    bool keep = i < n && flags[i];
-    uint64_t m = __ballot(keep);
-    int32_t base = 0;
-    if (lane_id() == 0 && m) base = atomicAdd(count, (int32_t)__popcll(m));
-    base = __shfl(base, 0, kWave);
-    if (keep) out[base + (int32_t)__popcll(m & __lanemask_lt())] = i;
-}
 
 // ---- final output: ascending original row ids ------------------------------------------------
 __global__ void __launch_bounds__(kBlock) mark_rows_kernel(const int32_t* __restrict__ list,
@@ -501,6 +697,29 @@ __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
     if (i < n) p[i] = v;
 }
 
+// stable compaction helpers: flags, then out[scan[i]] = i
+__global__ void __launch_bounds__(kBlock) keep_flag_kernel(const uint8_t* __restrict__ skip_seg,
+                                                            const int32_t* __restrict__ seg,
+                                                            const uint8_t* __restrict__ flags_u8,
+                                                            int32_t n, int32_t* __restrict__ flag) {
+    int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    bool keep = flags_u8 ? flags_u8[i] != 0 : true;
+    if (skip_seg && skip_seg[seg[i]]) keep = false;
+    flag[i] = keep ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) index_compact_kernel(const int32_t* __restrict__ flag,
+                                                                const int32_t* __restrict__ scan,
+                                                                int32_t n, int32_t* __restrict__ out,
+                                                                int32_t* __restrict__ count) {
+    int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (flag[i]) out[scan[i]] = i;
+    if (i == n - 1) *count = scan[i] + flag[i];
+}
+
+
 }  // namespace
 
 #define SKY_DISPATCH_D(d, KERNEL, ...)                                            \
@@ -516,6 +735,8 @@ __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
         default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;               \
     }
 
+int64_t engine_head_capacity(int64_t n, int32_t nseg) { return n + (int64_t)kTile * nseg + kTile; }
+
 sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,
                       EngineResult* res, hipStream_t st) {
     res->count = 0;
@@ -528,21 +749,9 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
     int32_t* other = b.w1;
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, b.counters, (int32_t)kCounters);
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, b.tests, 2);
+    hipLaunchKernelGGL(pad_slots_kernel, dim3((uint32_t)ceil_div(pb.d * kTile, 256)), dim3(256), 0, st,
+                       b.hval, b.hcap, pb.d);
     SKY_HIP(hipGetLastError());
-    // LDS chunk of candidates (d x chunk uint32) and the split of the candidate range across
-    // workgroups (grid.y) so that tiles x splits reaches kMinBlocks
-    const int32_t chunk = (int32_t)((kLdsBytes / (4 * pb.d)) / kWave * kWave);
-    const size_t lds = (size_t)pb.d * (size_t)chunk * sizeof(uint32_t);
-    auto split = [&](int64_t tiles, int64_t maxc, int32_t* span) -> uint32_t {
-        if (tiles <= 0 || maxc <= 0) { *span = chunk; return 1; }
-        int64_t y = ceil_div(kMinBlocks, tiles);
-        int64_t ymax = ceil_div(maxc, kWave * 8);  // at least 512 candidates per split
-        if (y > ymax) y = ymax;
-        if (y < 1) y = 1;
-        int64_t sp = round_up(ceil_div(maxc, y), kWave);
-        *span = (int32_t)sp;
-        return (uint32_t)ceil_div(maxc, sp);
-    };
     // optional timing hooks around the dominance-test launches
     auto ev_rec = [&](bool begin) -> hipError_t {
         if (!pb.ev_begin || !pb.ev_end || !pb.ev_used || *pb.ev_used >= pb.ev_cap) return hipSuccess;
@@ -560,59 +769,85 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         hipLaunchKernelGGL(init_segments_kernel, dim3((uint32_t)ceil_div(hn > nseg ? hn : nseg, 256)),
                            dim3(256), 0, st, nseg, b.seg_min, b.seg_max, b.hist, b.seg_info,
                            b.counters);
-        hipLaunchKernelGGL(minmax_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                           pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
-        hipLaunchKernelGGL(hist_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                           pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                           b.hist);
+        if (nseg == 1) {
+            const uint32_t sblocks = iblocks < 256 ? iblocks : 256;
+            hipLaunchKernelGGL(minmax1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+                               b.seg_min, b.seg_max, b.seg_info);
+            hipLaunchKernelGGL(hist1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+                               (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist);
+        } else {
+            hipLaunchKernelGGL(minmax_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+                               pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
+            hipLaunchKernelGGL(hist_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+                               pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
+                               b.hist);
+        }
         hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)nseg), dim3(kWave), 0, st, nseg,
                            (const int32_t*)b.hist, b.seg_info);
-        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg, b.seg_info,
+        // items per wave: enough waves to fill the chip (kTargetWaves), at most 64
+        auto ipw_for = [](int64_t items) -> int32_t {
+            int64_t v = ceil_div(items, kTargetWaves);
+            return (int32_t)(v < 1 ? 1 : (v > kWave ? kWave : v));
+        };
+        const int64_t head_est = (int64_t)nseg * kHead < live ? (int64_t)nseg * kHead : live;
+        const int32_t ipw_h = ipw_for(head_est), ipw_r = ipw_for(live);
+        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg,
+                           ipw_h * (kBlock / kWave), ipw_r * (kBlock / kWave), b.seg_info,
                            b.tile_off, b.counters);
-        hipLaunchKernelGGL(split_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+        hipLaunchKernelGGL(head_flag_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
                            pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                           b.seg_info, b.head, b.rest, b.dom);
+                           (const int32_t*)b.seg_info, b.flag);
+        SKY_HIP(hipGetLastError());
+        SKY_TRY(launch_exclusive_scan(b.flag, b.scan, live, b.scan_tmp, st));
+        hipLaunchKernelGGL(split_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.seg_of_pos,
+                           (const int32_t*)b.seg_info, (const int32_t*)b.flag, (const int32_t*)b.scan,
+                           b.head, b.rest, b.dom);
+        SKY_HIP(hipGetLastError());
+        // grid sizes from host-side bounds; the kernels read the exact counts on the device
+        auto grid = [](int64_t want) -> uint32_t {
+            return (uint32_t)(want < 1 ? 1 : (want > kMaxGrid ? kMaxGrid : want));
+        };
+        const int64_t slot_bound = live + (int64_t)kTile * nseg;
+        SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
+                       dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.seg_info,
+                       (const int32_t*)b.counters, b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
+        SKY_HIP(hipGetLastError());
+        // head skyline: every head row against the head rows of its segment
+        SKY_HIP(ev_rec(true));
+        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(ceil_div(head_est, ipw_h * (kBlock / kWave)) + nseg)),
+                       dim3(kBlock), 0, st, 0, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
+                       (const int32_t*)b.seg_info, (const int32_t*)b.head, (const uint32_t*)b.hval,
+                       b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi, b.tcap, ipw_h, b.dom,
+                       b.tests);
+        SKY_HIP(ev_rec(false));
+        hipLaunchKernelGGL(compact_head_kernel, dim3(grid(ceil_div(slot_bound, kBlock))), dim3(kBlock), 0,
+                           st, (const int32_t*)b.head, (const int32_t*)b.counters,
+                           (const uint8_t*)b.dom, pb.flag_out, out_list, b.counters + C_OUT);
+        SKY_HIP(hipGetLastError());
+        // filter the rest against the head rows of its segment
+        SKY_HIP(ev_rec(true));
+        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(ceil_div(live, ipw_r * (kBlock / kWave)) + nseg)),
+                       dim3(kBlock), 0, st, 1, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
+                       (const int32_t*)b.seg_info, (const int32_t*)b.rest, (const uint32_t*)b.hval,
+                       b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi, b.tcap, ipw_r, b.dom,
+                       b.tests);
+        SKY_HIP(ev_rec(false));
+        hipLaunchKernelGGL(rest_flag_kernel, dim3(grid(ceil_div(live, kBlock))), dim3(kBlock), 0, st,
+                           (const int32_t*)b.rest, (const int32_t*)b.counters, (const uint8_t*)b.dom,
+                           live, b.flag);
+        SKY_HIP(hipGetLastError());
+        SKY_TRY(launch_exclusive_scan(b.flag, b.scan, live, b.scan_tmp, st));
+        hipLaunchKernelGGL(rest_compact_kernel, dim3(grid(ceil_div(live, kBlock))), dim3(kBlock), 0, st,
+                           (const int32_t*)b.rest, b.counters, (const int32_t*)b.flag,
+                           (const int32_t*)b.scan, next);
         SKY_HIP(hipGetLastError());
         int32_t cnt[kCounters];
         SKY_HIP(hipMemcpyAsync(cnt, b.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
         SKY_HIP(hipStreamSynchronize(st));
-        const int32_t htiles = cnt[C_HTILES], rtiles = cnt[C_RTILES], maxh = cnt[C_MAXH];
-        const int32_t htot = cnt[C_HTOT], rtot = cnt[C_RTOT];
-        if (htot <= 0 || htot + rtot != live) return SKY_ERR_HIP;  // internal consistency
-        // head skyline: all pairs inside every segment's head
-        int32_t span = chunk;
-        uint32_t ychunks = split(htiles, maxh, &span);
-        SKY_HIP(ev_rec(true));
-        SKY_DISPATCH_D(pb.d, test_kernel, dim3((uint32_t)htiles, ychunks), dim3(kBlock), lds, st, 0,
-                       pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
-                       (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.head,
-                       span, chunk, b.dom, b.tests);
-        SKY_HIP(ev_rec(false));
-        hipLaunchKernelGGL(compact_head_kernel, dim3((uint32_t)ceil_div(htot, kBlock)), dim3(kBlock), 0,
-                           st, (const int32_t*)b.head, (const int32_t*)b.counters, pb.seg_of_pos,
-                           (const uint8_t*)b.dom, b.seg_info, b.fsky, pb.flag_out, out_list,
-                           b.counters + C_OUT);
-        SKY_HIP(hipGetLastError());
-        if (rtot > 0) {
-            // filter the rest against the head skylines
-            ychunks = split(rtiles, maxh, &span);
-            SKY_HIP(ev_rec(true));
-            SKY_DISPATCH_D(pb.d, test_kernel, dim3((uint32_t)rtiles, ychunks), dim3(kBlock), lds, st, 1,
-                           pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
-                           (const int32_t*)b.seg_info, (const int32_t*)b.rest,
-                           (const int32_t*)b.fsky, span, chunk, b.dom, b.tests);
-            SKY_HIP(ev_rec(false));
-            hipLaunchKernelGGL(compact_rest_kernel, dim3((uint32_t)ceil_div(rtot, kBlock)), dim3(kBlock),
-                               0, st, (const int32_t*)b.rest, b.counters, (const uint8_t*)b.dom, next);
-            SKY_HIP(hipGetLastError());
-        }
-        int32_t nl = 0;
-        if (rtot > 0) {
-            SKY_HIP(hipMemcpyAsync(&nl, b.counters + C_NEXT, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-            SKY_HIP(hipStreamSynchronize(st));
-        }
+        const int32_t htot = cnt[C_HTOT], rtot = cnt[C_RTOT], nl = cnt[C_NEXT];
+        if (htot <= 0 || htot > b.hcap || rtot < 0 || rtot >= live) return SKY_ERR_HIP;
         // every round removes the head rows from the live set
-        if (nl >= live) return SKY_ERR_HIP;
+        if (nl < 0 || nl >= live || nl > rtot) return SKY_ERR_HIP;
         live = nl;
         cur = next;
         int32_t* t = next; next = other; other = t;
@@ -627,25 +862,40 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
     return SKY_OK;
 }
 
+// Positions [0, n) in order, without those whose segment is skipped (stable).
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
-                                int32_t* out, int32_t* count, hipStream_t st) {
+                                int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
+                                int32_t* scan_tmp, hipStream_t st) {
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, count, 1);
-    if (n > 0)
-        hipLaunchKernelGGL(iota_filtered_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0,
-                           st, skip_seg, seg_of_pos, n, out, count);
+    if (n <= 0) { SKY_HIP(hipGetLastError()); return SKY_OK; }
+    const uint32_t nb = (uint32_t)ceil_div(n, kBlock);
+    hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, skip_seg, seg_of_pos,
+                       (const uint8_t*)nullptr, n, flag);
+    SKY_HIP(hipGetLastError());
+    SKY_TRY(launch_exclusive_scan(flag, scan, n, scan_tmp, st));
+    hipLaunchKernelGGL(index_compact_kernel, dim3(nb), dim3(kBlock), 0, st, (const int32_t*)flag,
+                       (const int32_t*)scan, n, out, count);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
 
+// Positions i with flags[i] != 0, in order (stable).
 sky_status launch_compact_flags(const uint8_t* flags, int32_t n, int32_t* out, int32_t* count,
-                                hipStream_t st) {
+                                int32_t* flag, int32_t* scan, int32_t* scan_tmp, hipStream_t st) {
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, count, 1);
-    if (n > 0)
-        hipLaunchKernelGGL(compact_flags_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0,
-                           st, flags, n, out, count);
+    if (n <= 0) { SKY_HIP(hipGetLastError()); return SKY_OK; }
+    const uint32_t nb = (uint32_t)ceil_div(n, kBlock);
+    hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, (const uint8_t*)nullptr,
+                       (const int32_t*)nullptr, flags, n, flag);
+    SKY_HIP(hipGetLastError());
+    SKY_TRY(launch_exclusive_scan(flag, scan, n, scan_tmp, st));
+    hipLaunchKernelGGL(index_compact_kernel, dim3(nb), dim3(kBlock), 0, st, (const int32_t*)flag,
+                       (const int32_t*)scan, n, out, count);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
+
+
 
 sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
                                int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st) {
