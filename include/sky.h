@@ -65,7 +65,7 @@ typedef enum sky_scheme {
 
 /* Limits of this implementation. */
 #define SKY_MAX_D 16           /* attributes per tuple */
-#define SKY_MAX_CELLS 4096     /* Grid / Angular partitions (m^d or m^(d-1)) */
+#define SKY_MAX_CELLS 4096     /* partitions of any scheme (Grid m^d, Angular m^(d-1), Sliced p) */
 #define SKY_MAX_G 1048576      /* largest g_max accepted by gres_compute */
 
 /* gres_compute mapping choice (sky_gres_opts.mapping). */
@@ -141,7 +141,7 @@ size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params)
  * dominance, and a stable partition-contiguous SoA copy in the workspace.
  * x_soa must stay valid until sky_merge returns. On success *out receives a new plan
  * (host memory owned by the library; release it with sky_plan_destroy).
- * n must be in [1, 2^30 - 2^20]; Grid/Angular need m^e <= SKY_MAX_CELLS (else SKY_ERR_UNSUPPORTED);
+ * n must be in [1, 2^30 - 2^20]; every scheme needs p <= SKY_MAX_CELLS (else SKY_ERR_UNSUPPORTED);
  * Angular needs d >= 2.
  */
 sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld,
@@ -216,6 +216,37 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld,
                         const int64_t* sky_idx, int64_t s, int32_t g_max, int32_t* g_exit,
                         float* gres, void* ws, size_t ws_bytes, int32_t* dev_status,
                         const sky_gres_opts* opts, void* stream);
+
+/*
+ * Two-phase form of gres_compute, for candidate sets that are queried many times (a resident
+ * dataset serving requests): the candidates are prepared once, then any tuples are searched.
+ *
+ * gres_prepare -- orders the candidate rows cand_idx[0..s) of x (normally Sky(r)) for the
+ * search and keeps them, with their tile boxes, in `prep` (device memory of
+ * gres_prepare_bytes(s, d) bytes, owned by the caller; it stays valid as long as the caller
+ * keeps it, independently of x). Checks indices (SKY_ERR_INVALID_ARG) and values
+ * (SKY_ERR_DOMAIN) on device. Never synchronises.
+ */
+size_t gres_prepare_bytes(int64_t s, int32_t d);
+sky_status gres_prepare(const float* x_soa, int64_t n, int32_t d, int64_t ld,
+                        const int64_t* cand_idx, int64_t s, void* prep, size_t prep_bytes,
+                        int32_t* dev_status, void* stream);
+
+/*
+ * gres_search -- Def. 2 via Alg. 1 for target tuples against a prepared candidate set (the
+ * same s and d as given to gres_prepare). targets: device int64[nt] row indices into x (any
+ * rows; their values are read from x, which must hold the same relation the candidates came
+ * from for the result to be gres in that relation). targets == NULL means "every candidate"
+ * (then nt must equal s and outputs are indexed like cand_idx, as in gres_compute); x may then
+ * be NULL. g_exit[q], gres[q] (either may be NULL) refer to targets[q]. ws: device memory of
+ * gres_search_bytes(nt, d) bytes. Requires s >= 1 when nt >= 1. Never synchronises; distinct
+ * searches on distinct streams may run concurrently on one prepared set.
+ */
+size_t gres_search_bytes(int64_t nt, int32_t d);
+sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_soa, int64_t n,
+                       int64_t ld, const int64_t* targets, int64_t nt, int32_t g_max,
+                       int32_t* g_exit, float* gres, void* ws, size_t ws_bytes,
+                       int32_t* dev_status, const sky_gres_opts* opts, void* stream);
 
 #ifdef __cplusplus
 }

@@ -36,7 +36,8 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "sky_build", "sky_local_skylines", "sky_merge", "sky_plan_partitions", "sky_plan_local",
            "sky_plan_set_events",
            "sky_plan_info", "sky_plan_destroy",
-           "gres_workspace_bytes", "gres_compute")
+           "gres_workspace_bytes", "gres_compute", "gres_prepare_bytes", "gres_prepare",
+           "gres_search_bytes", "gres_search")
 
 
 class SkyParams(C.Structure):
@@ -97,6 +98,11 @@ def load():
         "gres_workspace_bytes": (sz, [i64, i32, i32]),
         "gres_compute": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, vp, vp, sz, vp,
                                C.POINTER(GresOpts), vp]),
+        "gres_prepare_bytes": (sz, [i64, i32]),
+        "gres_prepare": (i32, [vp, i64, i32, i64, vp, i64, vp, sz, vp, vp]),
+        "gres_search_bytes": (sz, [i64, i32]),
+        "gres_search": (i32, [vp, i64, i32, vp, i64, i64, vp, i64, i32, vp, vp, vp, sz, vp,
+                              C.POINTER(GresOpts), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

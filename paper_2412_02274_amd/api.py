@@ -20,7 +20,8 @@ import torch
 from . import _lib
 from ._lib import SkyError
 
-__all__ = ["ingest", "build", "Plan", "Pipeline", "gres", "skyline", "gres_workspace_bytes",
+__all__ = ["ingest", "build", "Plan", "Pipeline", "PreparedCandidates", "gres", "skyline",
+           "gres_workspace_bytes",
            "build_workspace_bytes", "check_status", "SkyError"]
 
 
@@ -191,6 +192,50 @@ def gres(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, mapping="a
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         check_status(st, "gres_compute")
     return g_exit, gres_out
+
+
+class PreparedCandidates:
+    """A candidate set (normally a skyline) prepared once for many gres searches."""
+
+    def __init__(self, x_soa: torch.Tensor, cand_idx: torch.Tensor, status=None, stream=None):
+        lib = _lib.load()
+        self.x_soa = x_soa
+        self.d, self.n = x_soa.shape
+        self.s = int(cand_idx.numel())
+        self.cand_idx = cand_idx.contiguous()
+        nb = int(lib.gres_prepare_bytes(self.s, self.d))
+        if nb == 0:
+            raise SkyError(_lib.SKY_ERR_INVALID_ARG, "gres_prepare_bytes")
+        self.prep = torch.empty(nb, dtype=torch.uint8, device=x_soa.device)
+        self.status = status if status is not None else new_status(x_soa.device)
+        _lib.check(lib.gres_prepare(_ptr(x_soa), self.n, self.d, x_soa.stride(0),
+                                    _ptr(self.cand_idx), self.s, _ptr(self.prep), nb,
+                                    _ptr(self.status), _stream_ptr(stream)), "gres_prepare")
+
+    def search(self, targets: torch.Tensor | None = None, g_max: int = 25, mapping="auto",
+               stream=None, status=None, ws=None, g_exit=None, gres_out=None, check=True):
+        """(g_exit, gres) for `targets` (row indices of x), or for every candidate if None."""
+        lib = _lib.load()
+        nt = self.s if targets is None else int(targets.numel())
+        dev = self.x_soa.device
+        need = int(lib.gres_search_bytes(nt, self.d))
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        if g_exit is None:
+            g_exit = torch.empty(nt, dtype=torch.int32, device=dev)
+        if gres_out is None:
+            gres_out = torch.empty(nt, dtype=torch.float32, device=dev)
+        st = status if status is not None else self.status
+        opts = _lib.GresOpts(_lib.MAPPINGS[mapping] if isinstance(mapping, str) else int(mapping))
+        tptr = None if targets is None else _ptr(targets)
+        _lib.check(lib.gres_search(_ptr(self.prep), self.s, self.d, _ptr(self.x_soa), self.n,
+                                   self.x_soa.stride(0), tptr, nt, g_max, _ptr(g_exit),
+                                   _ptr(gres_out), _ptr(ws), need, _ptr(st), C.byref(opts),
+                                   _stream_ptr(stream)), "gres_search")
+        if check:
+            (stream or torch.cuda.current_stream()).synchronize()
+            check_status(st, "gres_search")
+        return g_exit, gres_out
 
 
 def skyline(x_rows: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0):

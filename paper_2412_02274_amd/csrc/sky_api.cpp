@@ -26,6 +26,7 @@ struct sky_plan {
     uint8_t* pruned = nullptr;
     double* tan2_dev = nullptr;
     int32_t *part_of_row = nullptr, *phist = nullptr, *scan_tmp = nullptr;
+    int64_t phist_cap = 0;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     int32_t* radix_tmp = nullptr;
     EngineBuffers eng{};
@@ -99,7 +100,7 @@ sky_status resolve_partitions(int64_t n, int32_t d, const sky_params* prm, int32
             if (prm->target_p < 1 || prm->slice_dim < 0 || prm->slice_dim >= d) return SKY_ERR_INVALID_ARG;
             *m = 0;
             *p = (int32_t)(prm->target_p < n ? prm->target_p : n);
-            return SKY_OK;
+            return *p <= SKY_MAX_CELLS ? SKY_OK : SKY_ERR_UNSUPPORTED;
         default:
             return SKY_ERR_INVALID_ARG;
     }
@@ -116,7 +117,9 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->part_off = c.take<int32_t>((size_t)p + 1);
     P->pruned = c.take<uint8_t>((size_t)p);
     P->tan2_dev = c.take<double>((size_t)(scheme == SKY_ANGULAR ? m + 1 : 1));
-    int64_t hist_elems = (scheme == SKY_GRID || scheme == SKY_ANGULAR) ? partition_hist_elems(n, p) : 64;
+    // the counting sort by partition runs for every scheme with p > 1 (Sliced included)
+    const int64_t hist_elems = p > 1 ? partition_hist_elems(n, p) : 64;
+    P->phist_cap = hist_elems;
     P->part_of_row = c.take<int32_t>((size_t)(scheme != SKY_NONE ? n : 1));
     P->phist = c.take<int32_t>((size_t)hist_elems);
     int64_t scan_n = hist_elems > n ? hist_elems : n;
@@ -154,23 +157,6 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->final_list = c.take<int32_t>((size_t)n);
     P->pos_tmp = c.take<int32_t>((size_t)n);
     P->count_tmp = c.take<int32_t>(64);
-}
-
-void carve_gres(Carver& c, GresWork& w, int64_t s, int32_t d) {
-    const int64_t s_pad = round_up(s > 0 ? s : 1, 64);
-    const int64_t ntile = ceil_div(s > 0 ? s : 1, 64);
-    const int64_t t_pad = round_up(ntile, 64);
-    w.s_pad = s_pad;
-    w.t_pad = t_pad;
-    w.cand = c.take<float>((size_t)(d * s_pad));
-    w.lo = c.take<float>((size_t)(d * t_pad));
-    w.hi = c.take<float>((size_t)(d * t_pad));
-    w.k0 = c.take<uint32_t>((size_t)s_pad);
-    w.v0 = c.take<uint32_t>((size_t)s_pad);
-    w.k1 = c.take<uint32_t>((size_t)s_pad);
-    w.v1 = c.take<uint32_t>((size_t)s_pad);
-    w.radix_tmp = c.take<int32_t>((size_t)radix_tmp_elems(s > 0 ? s : 1));
-    w.ge_sorted = c.take<int32_t>((size_t)s_pad);
 }
 
 }  // namespace
@@ -249,7 +235,8 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
     a.tan2 = P->tan2_dev;
     a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
     a.part_off = P->part_off; a.pruned = P->pruned;
-    a.part_of_row = P->part_of_row; a.hist = P->phist; a.scan_tmp = P->scan_tmp;
+    a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
+    a.scan_tmp = P->scan_tmp;
     a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
     a.dev_status = dev_status;
     sky_status s = launch_partition(a, st);
@@ -386,33 +373,109 @@ void sky_plan_destroy(sky_plan* P) {
 }
 
 size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max) {
-    if (s < 0 || s > kMaxRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return 0;
-    GresWork w{};
+    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return 0;
     Carver c(nullptr, 0);
-    carve_gres(c, w, s, d);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    GresTargets tg{};
+    carve_gres_store(c, store, s, d, 1);
+    carve_gres_prep_tmp(c, tmp, s);
+    carve_gres_targets(c, tg, s, d);
     return c.used;
+}
+
+static sky_status check_opts(const sky_gres_opts* opts, int32_t* mapping) {
+    *mapping = opts ? opts->mapping : SKY_GRES_AUTO;
+    if (*mapping < SKY_GRES_AUTO || *mapping > SKY_GRES_LEVELS) return SKY_ERR_INVALID_ARG;
+    if (opts && (opts->reserved != 0 || (!opts->ev_begin) != (!opts->ev_end))) return SKY_ERR_INVALID_ARG;
+    return SKY_OK;
 }
 
 sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
                         int64_t s, int32_t g_max, int32_t* g_exit, float* gres, void* ws,
                         size_t ws_bytes, int32_t* dev_status, const sky_gres_opts* opts,
                         void* stream) {
-    if (s < 0 || s > kMaxRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
+    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
     if (!dev_status) return SKY_ERR_INVALID_ARG;
-    int32_t mapping = opts ? opts->mapping : SKY_GRES_AUTO;
-    if (mapping < SKY_GRES_AUTO || mapping > SKY_GRES_LEVELS) return SKY_ERR_INVALID_ARG;
-    if (opts && (opts->reserved != 0 || (!opts->ev_begin) != (!opts->ev_end))) return SKY_ERR_INVALID_ARG;
+    int32_t mapping = 0;
+    SKY_TRY(check_opts(opts, &mapping));
     if (s == 0) return SKY_OK;
     if (!x_soa || !sky_idx || n < 1 || n > kMaxRows || ld < n || !ws) return SKY_ERR_INVALID_ARG;
-    size_t need = gres_workspace_bytes(s, d, g_max);
-    if (ws_bytes < need) return SKY_ERR_WORKSPACE;
-    GresWork w{};
+    if (ws_bytes < gres_workspace_bytes(s, d, g_max)) return SKY_ERR_WORKSPACE;
     Carver c(ws, ws_bytes);
-    carve_gres(c, w, s, d);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    GresTargets tg{};
+    carve_gres_store(c, store, s, d, 1);
+    carve_gres_prep_tmp(c, tmp, s);
+    carve_gres_targets(c, tg, s, d);
     if (c.overflow) return SKY_ERR_WORKSPACE;
-    return launch_gres(x_soa, n, d, ld, sky_idx, s, g_max, mapping, g_exit, gres, w, dev_status,
-                       opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
-                       (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
+    SKY_TRY(launch_gres_prepare(x_soa, n, d, ld, sky_idx, s, store, tmp, dev_status, st));
+    SKY_TRY(launch_gres_targets(x_soa, n, d, ld, nullptr, s, s, store, tg, dev_status, st));
+    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, 0, g_max, mapping, g_exit, gres,
+                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr, st);
+}
+
+size_t gres_prepare_bytes(int64_t s, int32_t d) {
+    if (s < 0 || s > kMaxBuildRows || !valid_d(d)) return 0;
+    Carver c(nullptr, 0);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    carve_gres_store(c, store, s, d, 1);
+    carve_gres_prep_tmp(c, tmp, s);
+    return c.used;
+}
+
+sky_status gres_prepare(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* cand_idx,
+                        int64_t s, void* prep, size_t prep_bytes, int32_t* dev_status, void* stream) {
+    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || !dev_status || !prep) return SKY_ERR_INVALID_ARG;
+    if (s > 0 && (!x_soa || !cand_idx || n < 1 || n > kMaxRows || ld < n)) return SKY_ERR_INVALID_ARG;
+    if (prep_bytes < gres_prepare_bytes(s, d)) return SKY_ERR_WORKSPACE;
+    Carver c(prep, prep_bytes);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    carve_gres_store(c, store, s, d, 1);
+    carve_gres_prep_tmp(c, tmp, s);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    return launch_gres_prepare(x_soa, n, d, ld, cand_idx, s, store, tmp, dev_status, (hipStream_t)stream);
+}
+
+size_t gres_search_bytes(int64_t nt, int32_t d) {
+    if (nt < 0 || nt > kMaxRows || !valid_d(d)) return 0;
+    Carver c(nullptr, 0);
+    GresTargets tg{};
+    carve_gres_targets(c, tg, nt, d);
+    return c.used;
+}
+
+sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_soa, int64_t n, int64_t ld,
+                       const int64_t* targets, int64_t nt, int32_t g_max, int32_t* g_exit, float* gres,
+                       void* ws, size_t ws_bytes, int32_t* dev_status, const sky_gres_opts* opts,
+                       void* stream) {
+    if (!prep || s < 0 || s > kMaxBuildRows || !valid_d(d) || nt < 0 || g_max < 2 || g_max > SKY_MAX_G ||
+        !dev_status)
+        return SKY_ERR_INVALID_ARG;
+    if (!targets && nt != s) return SKY_ERR_INVALID_ARG;
+    int32_t mapping = 0;
+    SKY_TRY(check_opts(opts, &mapping));
+    if (nt == 0) return SKY_OK;
+    if (targets && (!x_soa || n < 1 || n > kMaxRows || ld < n)) return SKY_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < gres_search_bytes(nt, d)) return SKY_ERR_WORKSPACE;
+    Carver cp(const_cast<void*>(prep), (size_t)-1);
+    GresStore store{};
+    carve_gres_store(cp, store, s, d, 1);
+    Carver c(ws, ws_bytes);
+    GresTargets tg{};
+    carve_gres_targets(c, tg, nt, d);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
+    if (s == 0) return SKY_ERR_INVALID_ARG;  // targets need candidates to be tested against
+    SKY_TRY(launch_gres_targets(x_soa, n, d, ld, targets, nt, s, store, tg, dev_status, st));
+    return launch_gres_search(store, d, (int32_t)s, tg, nt, nullptr, 0, g_max, mapping, g_exit, gres,
+                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr, st);
 }
 
 }  // extern "C"

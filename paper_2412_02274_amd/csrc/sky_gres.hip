@@ -1,55 +1,76 @@
-// Grid resistance (Def. 2) of the skyline tuples via Alg. 1 in per-tuple form.
+// Grid resistance (Def. 2) of skyline tuples via Alg. 1 in per-tuple form.
 //
-// For every skyline tuple t the result is g_exit(t) = the largest g in [2, g_max] at which
-// the projection of some other skyline tuple s dominates the projection of t (Alg. 1 scans g
-// downwards and records the first g at which t leaves the projected skyline), or 1. gres is
-// stable (dominated tuples never matter), so the candidates s are the skyline tuples
-// themselves. Projections are compared through integer keys K_g(v) = floor(fl32(v * g)).
+// For a tuple t the result is g_exit(t) = the largest g in [2, g_max] at which the projection
+// of some candidate s dominates the projection of t (Alg. 1 scans g downwards and records the
+// first g at which t leaves the projected skyline), or 1. gres is stable (dominated tuples
+// never matter), so the candidates are the skyline tuples. Projections are compared through
+// integer keys K_g(v) = floor(fl32(v * g)); in the kernels this is done on the products
+// themselves: K_g(v) <= K_g(t) <=> fl(v g) < K_g(t) + 1 and K_g(v) < K_g(t) <=> fl(v g) < K_g(t)
+// (K_g(t) and K_g(t) + 1 are small integers, exact in FP32).
 //
-// Exact pruning used by both mappings (no candidate that could dominate is ever skipped):
-//  * tile boxes -- candidates are sorted along a Hilbert curve and cut into tiles of 64; lo
-//    and hi are the tile's componentwise minimum and maximum. K_g is non-decreasing in v (an
-//    FP32 multiply by g > 0 rounded to nearest is monotone, floor too), so
-//    K_g(lo) <= K_g(s) <= K_g(hi) for every s of the tile. K_g(s) <= K_g(t) componentwise
-//    requires K_g(lo) <= K_g(t): tiles failing that hold no dominator at level g. If
-//    K_g(hi) <= K_g(t) everywhere and < somewhere, every s of the tile dominates t at level g
-//    (t itself in the tile would force K_g(hi) = K_g(t)), so the level is decided without
-//    looking at the candidates.
-//  * level bound -- if s_k > t_k, K_g(s_k) <= K_g(t_k) needs fl(s_k g) - fl(t_k g) < 1, and
-//    with FP32 relative rounding error at most u = 2^-24 on values below g this gives
-//    g (s_k - t_k - 2u) < 1. So with delta = max_k (s_k - t_k) (or the same from a tile's lo,
-//    which bounds every member from below), no level g with g (delta - 2^-23) >= 1 can see s
-//    dominate t. Evaluated in double with a 1e-9 margin.
+// Two phases:
+//  * prepare -- the candidate set is put in Hilbert-curve order inside each segment (one
+//    segment per dataset), stored 64-aligned per segment with padding candidates of value 2.0
+//    (their products are >= g, above every key of a value in [0, 1): they never dominate),
+//    and cut into tiles of 64 with the componentwise minimum (lo) and maximum (hi) of each.
+//  * search -- for each target tuple (all candidates, or any rows of the relation), one
+//    wavefront runs the level scan. Exact pruning (no candidate that could dominate is ever
+//    skipped, none that cannot is ever counted):
+//      - K_g is non-decreasing in v (an FP32 multiply by g > 0 rounded to nearest is monotone,
+//        floor too), so K_g(lo) <= K_g(s) <= K_g(hi) for every s of a tile. K_g(s) <= K_g(t)
+//        everywhere requires K_g(lo) <= K_g(t): tiles failing that hold no dominator at level
+//        g. If K_g(hi) <= K_g(t) everywhere and < somewhere, every s of the tile dominates t
+//        (t itself in the tile would force K_g(hi) = K_g(t)), and the level is decided at once.
+//      - the same test on the minimum over 64 consecutive tiles (a chunk) skips whole chunks.
+//      - LEVELS mapping only: if s_k > t_k, K_g(s_k) <= K_g(t_k) needs fl(s_k g) - fl(t_k g) < 1,
+//        and FP32 rounding (relative error <= 2^-24 below g) turns this into
+//        g (s_k - t_k - 2^-23) < 1; with delta = max_k (s_k - t_k), or the same from a tile's
+//        lo (a lower bound for every member), no level g with g (delta - 2^-23) >= 1 can see
+//        s dominate t. Evaluated in double with a 1e-9 margin.
 //
-// Mappings (both one wavefront per tuple t, which keeps the control flow wave-uniform and
-// lets the search stop at the first dominator):
-//  * TILES  -- levels in order g_max..2; per level the 64 lanes first test 64 tile boxes at
-//    once (ballot), then, tile by tile, the 64 lanes test the tile's 64 candidates (ballot);
-//    the first dominator ends the level and the search. Best when S is large and g_max
-//    small.
+// Mappings (both one wavefront per target, wave-uniform control flow, first dominator ends
+// the level):
+//  * TILES  -- levels g_max..2; per level the 64 lanes test 64 chunk boxes, then 64 tile
+//    boxes per chunk (cached in LDS when they fit), then up to 4 passing tiles of 64
+//    candidates per memory round trip, starting near the target's own place on the curve.
+//    Best when S is large and g_max small.
 //  * LEVELS -- lanes hold 64 consecutive levels; candidates are read as wave-uniform values
 //    and each lane tests its own level; the highest level with a dominator in the block of
 //    64 levels ends the search. Best when S is small and g_max large.
-// Bound: VALU compare/convert throughput and L2 latency (the candidate set of a dataset is
-// at most a few MB and stays in L2).
+// Bound: VALU compare/multiply throughput and L2 latency (a candidate set is at most a few MB
+// and stays in L2).
 #include "sky_internal.hpp"
 
 namespace sky {
 
 namespace {
 
-constexpr int kTileC = 64;  // candidates per tile
-constexpr int kGresBlock = 512;         // threads per workgroup of the TILES mapping
-constexpr int kBatch = 4;               // candidate tiles fetched per round trip
+constexpr int kTileC = 64;               // candidates per tile
+constexpr int kGresBlock = 512;          // threads per workgroup of the search kernels
+constexpr int kWaves = kGresBlock / kWave;
+constexpr int kBatch = 4;                // candidate tiles fetched per round trip
 constexpr int kGresLdsBytes = 64 * 1024; // tile boxes cached in LDS when they fit
+constexpr float kPadValue = 2.0f;
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
 
+// f32 load base[idx] with a 32-bit byte offset from a wave-uniform base
+__device__ __forceinline__ float ldf(const float* base, uint32_t idx) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (idx << 2));
+}
+
+// Iterate the set bits of a 64-bit mask starting at bit r (wrapping around).
+__device__ __forceinline__ uint64_t rotr64(uint64_t m, int r) {
+    return r ? ((m >> r) | (m << (64 - r))) : m;
+}
+
+// ---------------------------------------------------------------------------------- prepare
+
 // Hilbert key of every candidate (and checks of the row index and the domain)
 __global__ void __launch_bounds__(kBlock) curve_kernel(const float* __restrict__ x, int64_t n,
                                                         int32_t d, int64_t ld,
-                                                        const int64_t* __restrict__ sky_idx,
+                                                        const int64_t* __restrict__ rows,
                                                         int32_t s, int bits,
                                                         uint32_t* __restrict__ keys,
                                                         uint32_t* __restrict__ vals,
@@ -57,7 +78,7 @@ __global__ void __launch_bounds__(kBlock) curve_kernel(const float* __restrict__
     int32_t j = blockIdx.x * kBlock + threadIdx.x;
     bool bad_idx = false, bad_val = false;
     if (j < s) {
-        int64_t row = sky_idx[j];
+        int64_t row = rows[j];
         float v[SKY_MAX_D];
         if (row < 0 || row >= n) {
             bad_idx = true;
@@ -76,116 +97,210 @@ __global__ void __launch_bounds__(kBlock) curve_kernel(const float* __restrict__
     if (__ballot(bad_val) && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
 }
 
-__global__ void __launch_bounds__(kBlock) gather_sorted_kernel(const float* __restrict__ x, int64_t n,
-                                                                int32_t d, int64_t ld,
-                                                                const int64_t* __restrict__ sky_idx,
-                                                                int32_t s,
-                                                                const uint32_t* __restrict__ order,
-                                                                float* __restrict__ cand,
-                                                                int64_t s_pad) {
-    int32_t q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= s) return;
-    int64_t row = sky_idx[order[q]];
-    bool ok = row >= 0 && row < n;
-    for (int k = 0; k < d; ++k) {
-        float v = ok ? canon(x[(int64_t)k * ld + row]) : 0.0f;
-        cand[(int64_t)k * s_pad + q] = v;
-    }
+// every slot of the store: candidate values, curve key and caller index (padding: 2.0, ~0, -1)
+__global__ void __launch_bounds__(kBlock) store_kernel(const float* __restrict__ x, int64_t n,
+                                                        int32_t d, int64_t ld,
+                                                        const int64_t* __restrict__ rows, int32_t s,
+                                                        const uint32_t* __restrict__ skeys,
+                                                        const uint32_t* __restrict__ order,
+                                                        float* __restrict__ cand, int64_t ccap,
+                                                        uint32_t* __restrict__ ckey,
+                                                        int32_t* __restrict__ perm) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= ccap) return;
+    const bool real = q < s;
+    const int32_t j = real ? (int32_t)order[q] : -1;
+    const int64_t row = real ? rows[j] : -1;
+    const bool ok = real && row >= 0 && row < n;
+    for (int k = 0; k < d; ++k)
+        cand[(int64_t)k * ccap + q] = ok ? canon(x[(int64_t)k * ld + row]) : (real ? 0.0f : kPadValue);
+    ckey[q] = real ? skeys[q] : 0xFFFFFFFFu;
+    perm[q] = j;
 }
 
-// one wave per tile: componentwise minimum (lo) and maximum (hi) of its (up to 64) candidates
-__global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restrict__ cand,
-                                                           int64_t s_pad, int32_t s, int32_t d,
-                                                           int32_t ntile, float* __restrict__ lo,
-                                                           float* __restrict__ hi, int64_t t_pad) {
-    int32_t tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+// one wave per tile: componentwise minimum (lo) and maximum (hi) of its real candidates
+__global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restrict__ cand, int64_t ccap,
+                                                           int32_t s, int32_t d, int32_t ntile,
+                                                           float* __restrict__ lo,
+                                                           float* __restrict__ hi, int64_t tcap) {
+    const int32_t tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (tile >= ntile) return;
     const int lane = (int)lane_id();
-    int32_t j = tile * kTileC + lane;
+    const int32_t j = tile * kTileC + lane;
     for (int k = 0; k < d; ++k) {
-        float v = j < s ? cand[(int64_t)k * s_pad + j] : 1.0f;
+        float v = j < s ? cand[(int64_t)k * ccap + j] : 1.0f;
         float h = j < s ? v : 0.0f;
         for (int off = kWave / 2; off > 0; off >>= 1) {
             v = fminf(v, __shfl_xor(v, off, kWave));
             h = fmaxf(h, __shfl_xor(h, off, kWave));
         }
         if (lane == 0) {
-            lo[(int64_t)k * t_pad + tile] = v;
-            hi[(int64_t)k * t_pad + tile] = h;
+            lo[(int64_t)k * tcap + tile] = v;
+            hi[(int64_t)k * tcap + tile] = h;
         }
     }
 }
 
-// Iterate the set bits of a 64-bit mask starting at bit r (wrapping around).
-__device__ __forceinline__ uint64_t rotr64(uint64_t m, int r) {
-    return r ? ((m >> r) | (m << (64 - r))) : m;
+__global__ void single_segment_kernel(int32_t* __restrict__ seg_coff, int32_t* __restrict__ seg_cnt,
+                                      int32_t s) {
+    if (threadIdx.x == 0) {
+        seg_coff[0] = 0;
+        seg_cnt[0] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------------- targets
+
+// targets = every candidate of the store (slot order): values, hint tile, output index
+__global__ void __launch_bounds__(kBlock) targets_all_kernel(const float* __restrict__ cand, int64_t ccap,
+                                                              int32_t s, int32_t d,
+                                                              const int32_t* __restrict__ perm,
+                                                              float* __restrict__ tval, int64_t tvcap,
+                                                              int32_t* __restrict__ thint,
+                                                              int32_t* __restrict__ tout) {
+    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= s) return;
+    for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + q];
+    thint[q] = q / kTileC;
+    tout[q] = perm[q];
+}
+
+// targets = given rows of the relation: values, hint tile (where the row's curve key falls
+// among the sorted candidate keys), output index = position in the target list
+__global__ void __launch_bounds__(kBlock) targets_rows_kernel(const float* __restrict__ x, int64_t n,
+                                                               int32_t d, int64_t ld,
+                                                               const int64_t* __restrict__ rows,
+                                                               int32_t nt, int bits,
+                                                               const uint32_t* __restrict__ ckey,
+                                                               int32_t s,
+                                                               float* __restrict__ tval, int64_t tvcap,
+                                                               int32_t* __restrict__ thint,
+                                                               int32_t* __restrict__ tout,
+                                                               int32_t* dev_status) {
+    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+    bool bad_idx = false, bad_val = false;
+    if (q < nt) {
+        const int64_t row = rows[q];
+        float v[SKY_MAX_D];
+        if (row < 0 || row >= n) {
+            bad_idx = true;
+            for (int k = 0; k < d; ++k) v[k] = kPadValue;  // never dominated (keys >= g)
+        } else {
+            for (int k = 0; k < d; ++k) {
+                float t = x[(int64_t)k * ld + row];
+                bad_val |= !in_domain(t);
+                v[k] = canon(t);
+            }
+        }
+        for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = v[k];
+        const uint32_t key = bad_idx ? 0u : hilbert_key(v, d, bits);
+        int32_t lo = 0, hi = s;  // first slot with key >= the target's key
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (ckey[mid] < key) lo = mid + 1; else hi = mid;
+        }
+        const int32_t slot = lo < s ? lo : (s > 0 ? s - 1 : 0);
+        thint[q] = slot / kTileC;
+        tout[q] = q;
+    }
+    if (__ballot(bad_idx) && lane_id() == 0) raise_status(dev_status, SKY_ERR_INVALID_ARG);
+    if (__ballot(bad_val) && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
+}
+
+// ----------------------------------------------------------------------------------- search
+
+// Work of one workgroup: a segment and a contiguous range of its targets. Without a table,
+// one segment (0) and targets [blockIdx * per_wg, ...).
+struct WgWork { int32_t seg, t0, t1; };
+
+__device__ __forceinline__ WgWork wg_work(const int32_t* wg_table, int32_t per_wg, int32_t nt) {
+    WgWork w;
+    if (wg_table) {
+        w.seg = wg_table[3 * blockIdx.x];
+        w.t0 = wg_table[3 * blockIdx.x + 1];
+        w.t1 = wg_table[3 * blockIdx.x + 2];
+    } else {
+        w.seg = 0;
+        w.t0 = blockIdx.x * per_wg;
+        w.t1 = w.t0 + per_wg < nt ? w.t0 + per_wg : nt;
+    }
+    return w;
 }
 
 template <int D>
-__global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(const float* __restrict__ cand,
-                                                                 int64_t s_pad, int32_t s, int32_t d_rt,
-                                                                 const float* __restrict__ lo,
-                                                                 const float* __restrict__ hi,
-                                                                 int64_t t_pad, int32_t ntile,
-                                                                 int32_t g_max, int use_lds,
-                                                                 int32_t* __restrict__ ge_sorted) {
+__global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
+    const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
+    const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
+    const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
+    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
+    const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
+    int32_t* __restrict__ ge_out) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
-    extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo, hi
+    extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
-    constexpr int kWaves = kGresBlock / kWave;
+    const WgWork w = wg_work(wg_table, per_wg, nt);
+    if (w.t0 >= w.t1) return;  // uniform
+    const uint32_t coff = (uint32_t)seg_coff[w.seg];
+    const int32_t cnt = seg_cnt[w.seg];
+    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
     const int32_t nchunk = (ntile + kWave - 1) / kWave;
+    const uint32_t t0 = coff / kTileC;  // first tile of the segment
+    const uint32_t padslot = (uint32_t)(ccap - kTileC);
+    const bool use_lds = nchunk <= kWave && d * (2 * ntile + nchunk) <= lds_floats;  // uniform
     float* blo = sbox;
-    float* bhi = sbox + (int64_t)d * ntile;
-    float* clo = sbox + 2 * (int64_t)d * ntile;
-    float* chi = clo + (int64_t)d * nchunk;
+    float* bhi = sbox + d * ntile;
+    float* clo = sbox + 2 * d * ntile;
     if (use_lds) {
-        // tile boxes, then the boxes of chunks of 64 tiles
         for (int32_t e = threadIdx.x; e < d * ntile; e += kGresBlock) {
             const int32_t k = e / ntile, tl = e - k * ntile;
-            blo[e] = lo[(int64_t)k * t_pad + tl];
-            bhi[e] = hi[(int64_t)k * t_pad + tl];
+            blo[e] = lo[(int64_t)k * tcap + t0 + tl];
+            bhi[e] = hi[(int64_t)k * tcap + t0 + tl];
         }
         __syncthreads();
         for (int32_t e = threadIdx.x; e < d * nchunk; e += kGresBlock) {
             const int32_t k = e / nchunk, c = e - k * nchunk;
-            float mn = 1.0f, mx = 0.0f;
-            for (int32_t tl = c * kWave; tl < ntile && tl < (c + 1) * kWave; ++tl) {
+            float mn = 1.0f;
+            for (int32_t tl = c * kWave; tl < ntile && tl < (c + 1) * kWave; ++tl)
                 mn = fminf(mn, blo[k * ntile + tl]);
-                mx = fmaxf(mx, bhi[k * ntile + tl]);
-            }
             clo[e] = mn;
-            chi[e] = mx;
         }
         __syncthreads();
     }
-    for (int32_t q = blockIdx.x * kWaves + wave; q < s; q += gridDim.x * kWaves) {
+    for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) {
         float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
-            if (k < d) tv[k] = cand[(int64_t)k * s_pad + q];
-        const int32_t my_tile = q / kTileC;
+            if (k < d) tv[k] = ldf(tval + k * tvcap, (uint32_t)q);
+        int32_t my_tile = thint[q];
+        my_tile = my_tile < 0 ? 0 : (my_tile >= ntile ? ntile - 1 : my_tile);
         const int32_t my_chunk = my_tile / kWave;
         int32_t result = 1;
-        for (int32_t g = g_max; g >= 2; --g) {
+        for (int32_t g = g_max; g >= 2 && ntile > 0; --g) {
             const float fg = (float)g;
-            int32_t kt[DM];
+            // key(v) <= key(t) <=> fl(v g) < key(t) + 1;  key(v) < key(t) <=> fl(v g) < key(t)
+            float tle[DM], tlt[DM];
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d) kt[k] = qkey(tv[k], fg);
+                if (k < d) {
+                    const float kt = floorf(__fmul_rn(tv[k], fg));
+                    tlt[k] = kt;
+                    tle[k] = kt + 1.0f;
+                }
             bool found = false;
-            // chunks that may hold a dominator (one ballot over chunk boxes when cached)
             uint64_t cmask;
             if (use_lds) {
-                bool cp = lane < nchunk;
+                const bool inr = lane < nchunk;
+                const int32_t ci = inr ? lane : 0;
+                bool cp = inr;
 #pragma unroll
                 for (int k = 0; k < DM; ++k)
-                    if (k < d) cp &= cp && qkey(clo[k * nchunk + lane], fg) <= kt[k];
+                    if (k < d) cp &= __fmul_rn(clo[k * nchunk + ci], fg) < tle[k];
                 cmask = rotr64(__ballot(cp), my_chunk);
             } else {
                 cmask = nchunk >= 64 ? ~0ull : ((1ull << nchunk) - 1ull);
-                cmask = rotr64(cmask, my_chunk % 64);
+                cmask = rotr64(cmask, my_chunk % kWave);
             }
             for (int32_t cbase = 0; cbase < nchunk && !found; cbase += kWave) {
                 uint64_t cm = use_lds ? cmask : (cbase == 0 ? cmask : ~0ull);
@@ -197,54 +312,53 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(const float* __r
                                               : (cbase == 0 ? (cb + my_chunk % kWave) % kWave : cbase + cb);
                     if (c >= nchunk) continue;
                     const int32_t tile = c * kWave + lane;
-                    bool pass = tile < ntile, hle = true, hlt = false;
-                    if (pass) {
+                    const bool inr = tile < ntile;
+                    const uint32_t ti = inr ? (uint32_t)tile : 0u;
+                    bool pass = inr, hle = true, hlt = false;
 #pragma unroll
-                        for (int k = 0; k < DM; ++k)
-                            if (k < d) {
-                                const float l = use_lds ? blo[k * ntile + tile] : lo[(int64_t)k * t_pad + tile];
-                                const float h = use_lds ? bhi[k * ntile + tile] : hi[(int64_t)k * t_pad + tile];
-                                pass &= qkey(l, fg) <= kt[k];
-                                const int32_t kh = qkey(h, fg);
-                                hle &= kh <= kt[k];
-                                hlt |= kh < kt[k];
-                            }
-                    }
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) {
+                            const float l = use_lds ? blo[k * ntile + ti] : ldf(lo + k * tcap, t0 + ti);
+                            const float h = use_lds ? bhi[k * ntile + ti] : ldf(hi + k * tcap, t0 + ti);
+                            pass &= __fmul_rn(l, fg) < tle[k];
+                            const float ph = __fmul_rn(h, fg);
+                            hle &= ph < tle[k];
+                            hlt |= ph < tlt[k];
+                        }
                     // every candidate of a tile whose upper corner's keys dominate t's keys
-                    // dominates t (t itself in the tile would force equal keys)
+                    // dominates t
                     if (__ballot(pass && hle && hlt)) { found = true; break; }
                     const int r = c == my_chunk ? my_tile % kWave : 0;
                     uint64_t mask = rotr64(__ballot(pass), r);
                     while (mask) {
-                        // up to kBatch passing tiles per round trip: all loads issued together
-                        int32_t jb[kBatch];
+                        // up to kBatch passing tiles per round trip, branch-free loads
+                        uint32_t jb[kBatch];
 #pragma unroll
                         for (int b = 0; b < kBatch; ++b) {
-                            jb[b] = -1;
+                            jb[b] = padslot + (uint32_t)lane;
                             if (mask) {
                                 const int tb = ((__ffsll((unsigned long long)mask) - 1) + r) % kWave;
                                 mask &= mask - 1;
-                                jb[b] = (c * kWave + tb) * kTileC + lane;
+                                jb[b] = coff + (uint32_t)((c * kWave + tb) * kTileC + lane);
                             }
                         }
                         float sv[kBatch][DM];
 #pragma unroll
-                        for (int b = 0; b < kBatch; ++b) {
-                            const bool ok = jb[b] >= 0 && jb[b] < s && jb[b] != q;
+                        for (int b = 0; b < kBatch; ++b)
 #pragma unroll
                             for (int k = 0; k < DM; ++k)
-                                if (k < d) sv[b][k] = ok ? cand[(int64_t)k * s_pad + jb[b]] : 2.0f;
-                        }
+                                if (k < d) sv[b][k] = ldf(cand + k * ccap, jb[b]);
                         bool dom = false;
 #pragma unroll
                         for (int b = 0; b < kBatch; ++b) {
+                            // padding candidates hold 2.0: never below t's keys
                             bool le = true, lt = false;
 #pragma unroll
                             for (int k = 0; k < DM; ++k)
                                 if (k < d) {
-                                    const int32_t ks = qkey(sv[b][k], fg);
-                                    le &= ks <= kt[k];
-                                    lt |= ks < kt[k];
+                                    const float p = __fmul_rn(sv[b][k], fg);
+                                    le &= p < tle[k];
+                                    lt |= p < tlt[k];
                                 }
                             dom |= le && lt;
                         }
@@ -255,122 +369,133 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(const float* __r
             }
             if (found) { result = g; break; }
         }
-        if (lane == 0) ge_sorted[q] = result;
+        if (lane == 0) ge_out[q] = result;
     }
 }
 
 // no level g >= g_low can see a candidate whose (lower-bounding) excess over t is delta
 __device__ __forceinline__ bool beyond_levels(double delta, int32_t g_low) {
-    const double w = delta - 0x1p-23;
-    return w > 0.0 && (double)g_low * w >= 1.0 + 1e-9;
+    const double wv = delta - 0x1p-23;
+    return wv > 0.0 && (double)g_low * wv >= 1.0 + 1e-9;
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) gres_levels_kernel(const float* __restrict__ cand,
-                                                              int64_t s_pad, int32_t s, int32_t d_rt,
-                                                              const float* __restrict__ lo,
-                                                              const float* __restrict__ hi,
-                                                              int64_t t_pad, int32_t ntile,
-                                                              int32_t g_max,
-                                                              int32_t* __restrict__ ge_sorted) {
+__global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
+    const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
+    const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
+    const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
+    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
+    const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
+    int32_t* __restrict__ ge_out) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    (void)thint;
+    (void)lds_floats;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
-    const int32_t q = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (q >= s) return;  // whole wave
-    float tv[DM];
-#pragma unroll
-    for (int k = 0; k < DM; ++k)
-        if (k < d) tv[k] = cand[(int64_t)k * s_pad + q];
-    int32_t result = 1;
-    for (int32_t gh = g_max; gh >= 2; gh -= kWave) {
-        const int32_t g = gh - lane;
-        const bool lv = g >= 2;
-        const int32_t g_low = (gh - (kWave - 1)) > 2 ? (gh - (kWave - 1)) : 2;
-        const float fg = (float)(lv ? g : 2);
-        int32_t kt[DM];
+    const int wave = threadIdx.x / kWave;
+    const WgWork w = wg_work(wg_table, per_wg, nt);
+    if (w.t0 >= w.t1) return;
+    const int64_t coff = seg_coff[w.seg];
+    const int32_t cnt = seg_cnt[w.seg];
+    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
+    const int64_t t0 = coff / kTileC;
+    for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) {
+        float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
-            if (k < d) kt[k] = qkey(tv[k], fg);
-        const uint64_t lvmask = __ballot(lv);
-        uint64_t hit = 0;
-        for (int32_t tile = 0; tile < ntile; ++tile) {
-            const uint64_t need =
-                (hit ? ((1ull << (__ffsll((unsigned long long)hit) - 1)) - 1ull) : ~0ull) & lvmask;
-            if (!need) break;
-            // uniform bound on the whole tile
-            double dt = -1.0;
+            if (k < d) tv[k] = tval[(int64_t)k * tvcap + q];
+        int32_t result = 1;
+        for (int32_t gh = g_max; gh >= 2; gh -= kWave) {
+            const int32_t g = gh - lane;
+            const bool lv = g >= 2;
+            const int32_t g_low = (gh - (kWave - 1)) > 2 ? (gh - (kWave - 1)) : 2;
+            const float fg = (float)(lv ? g : 2);
+            float tle[DM], tlt[DM];
 #pragma unroll
             for (int k = 0; k < DM; ++k)
                 if (k < d) {
-                    double e = (double)lo[(int64_t)k * t_pad + tile] - (double)tv[k];
-                    dt = e > dt ? e : dt;
+                    const float kt = floorf(__fmul_rn(tv[k], fg));
+                    tlt[k] = kt;
+                    tle[k] = kt + 1.0f;
                 }
-            if (beyond_levels(dt, g_low)) continue;
-            bool pass = (need >> lane) & 1ull, hle = true, hlt = false;
-#pragma unroll
-            for (int k = 0; k < DM; ++k)
-                if (k < d) {
-                    pass &= qkey(lo[(int64_t)k * t_pad + tile], fg) <= kt[k];
-                    const int32_t kh = qkey(hi[(int64_t)k * t_pad + tile], fg);
-                    hle &= kh <= kt[k];
-                    hlt |= kh < kt[k];
-                }
-            // the whole tile dominates t at this lane's level
-            hit |= __ballot(pass && hle && hlt);
-            if (hit & 1ull) break;
-            if (!__ballot(pass)) continue;
-            const int32_t base = tile * kTileC;
-            const int32_t cnt = (s - base) < kTileC ? (s - base) : kTileC;
-            for (int32_t i = 0; i < cnt; ++i) {
-                const int32_t j = base + i;
-                if (j == q) continue;
-                float sv[DM];
-                double ds = -1.0;
+            const uint64_t lvmask = __ballot(lv);
+            uint64_t hit = 0;
+            for (int32_t tile = 0; tile < ntile; ++tile) {
+                const uint64_t need =
+                    (hit ? ((1ull << (__ffsll((unsigned long long)hit) - 1)) - 1ull) : ~0ull) & lvmask;
+                if (!need) break;
+                // uniform bound on the whole tile
+                double dt = -1.0;
 #pragma unroll
                 for (int k = 0; k < DM; ++k)
                     if (k < d) {
-                        sv[k] = cand[(int64_t)k * s_pad + j];
-                        double e = (double)sv[k] - (double)tv[k];
-                        ds = e > ds ? e : ds;
+                        double e = (double)lo[(int64_t)k * tcap + t0 + tile] - (double)tv[k];
+                        dt = e > dt ? e : dt;
                     }
-                if (beyond_levels(ds, g_low)) continue;
-                bool le = true, lt = false;
+                if (beyond_levels(dt, g_low)) continue;
+                bool pass = (need >> lane) & 1ull, hle = true, hlt = false;
 #pragma unroll
                 for (int k = 0; k < DM; ++k)
                     if (k < d) {
-                        int32_t ks = qkey(sv[k], fg);
-                        le &= ks <= kt[k];
-                        lt |= ks < kt[k];
+                        pass &= __fmul_rn(lo[(int64_t)k * tcap + t0 + tile], fg) < tle[k];
+                        const float ph = __fmul_rn(hi[(int64_t)k * tcap + t0 + tile], fg);
+                        hle &= ph < tle[k];
+                        hlt |= ph < tlt[k];
                     }
-                hit |= __ballot(pass && le && lt);
+                // the whole tile dominates t at this lane's level
+                hit |= __ballot(pass && hle && hlt);
+                if (hit & 1ull) break;
+                if (!__ballot(pass)) continue;
+                const int32_t base = tile * kTileC;
+                const int32_t cnt_t = (cnt - base) < kTileC ? (cnt - base) : kTileC;
+                for (int32_t i = 0; i < cnt_t; ++i) {
+                    const int64_t j = coff + base + i;
+                    float sv[DM];
+                    double ds = -1.0;
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) {
+                            sv[k] = cand[(int64_t)k * ccap + j];
+                            double e = (double)sv[k] - (double)tv[k];
+                            ds = e > ds ? e : ds;
+                        }
+                    if (beyond_levels(ds, g_low)) continue;
+                    bool le = true, lt = false;
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) {
+                            const float p = __fmul_rn(sv[k], fg);
+                            le &= p < tle[k];
+                            lt |= p < tlt[k];
+                        }
+                    hit |= __ballot(pass && le && lt);
+                    if (hit & 1ull) break;
+                }
                 if (hit & 1ull) break;
             }
-            if (hit & 1ull) break;
+            if (hit) {
+                result = gh - (__ffsll((unsigned long long)hit) - 1);
+                break;
+            }
         }
-        if (hit) {
-            result = gh - (__ffsll((unsigned long long)hit) - 1);
-            break;
-        }
+        if (lane == 0) ge_out[q] = result;
     }
-    if (lane == 0) ge_sorted[q] = result;
 }
 
-__global__ void __launch_bounds__(kBlock) gres_output_kernel(const int32_t* __restrict__ ge_sorted,
-                                                              const uint32_t* __restrict__ order,
-                                                              int32_t s, int32_t* __restrict__ g_exit,
+__global__ void __launch_bounds__(kBlock) gres_output_kernel(const int32_t* __restrict__ ge_t,
+                                                              const int32_t* __restrict__ tout,
+                                                              int32_t nt, int32_t* __restrict__ g_exit,
                                                               float* __restrict__ gres) {
-    int32_t q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= s) return;
-    int32_t j = (int32_t)order[q];
-    int32_t g = ge_sorted[q];
+    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nt) return;
+    const int32_t j = tout[q];
+    if (j < 0) return;
+    const int32_t g = ge_t[q];
     if (g_exit) g_exit[j] = g;
     if (gres) gres[j] = __fdiv_rn(1.0f, (float)g);
 }
 
 }  // namespace
-
-int64_t gres_pad(int64_t s) { return round_up(s > 0 ? s : 1, kWave * kTileC); }
 
 #define SKY_DISPATCH_D(d, KERNEL, ...)                                            \
     switch (d) {                                                                  \
@@ -385,45 +510,123 @@ int64_t gres_pad(int64_t s) { return round_up(s > 0 ? s : 1, kWave * kTileC); }
         default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;               \
     }
 
-sky_status launch_gres(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
-                       int64_t s64, int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres,
-                       const GresWork& w, int32_t* dev_status, void* ev_begin, void* ev_end,
-                       hipStream_t st) {
-    if (s64 <= 0) return SKY_OK;
+void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg) {
+    // every segment 64-aligned, plus one padding tile at the end
+    st.ccap = round_up(s > 0 ? s : 1, kTileC) + (int64_t)kTileC * (nseg + 1);
+    st.tcap = round_up(ceil_div(st.ccap, kTileC), 64);
+    st.cand = c.take<float>((size_t)(d * st.ccap));
+    st.lo = c.take<float>((size_t)(d * st.tcap));
+    st.hi = c.take<float>((size_t)(d * st.tcap));
+    st.ckey = c.take<uint32_t>((size_t)st.ccap);
+    st.perm = c.take<int32_t>((size_t)st.ccap);
+    st.seg_coff = c.take<int32_t>((size_t)nseg);
+    st.seg_cnt = c.take<int32_t>((size_t)nseg);
+}
+
+void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s) {
+    const int64_t sp = round_up(s > 0 ? s : 1, 64);
+    t.k0 = c.take<uint32_t>((size_t)sp);
+    t.v0 = c.take<uint32_t>((size_t)sp);
+    t.k1 = c.take<uint32_t>((size_t)sp);
+    t.v1 = c.take<uint32_t>((size_t)sp);
+    t.radix_tmp = c.take<int32_t>((size_t)radix_tmp_elems(s > 0 ? s : 1));
+}
+
+void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d) {
+    t.tvcap = round_up(nt > 0 ? nt : 1, 64);
+    t.tval = c.take<float>((size_t)(d * t.tvcap));
+    t.thint = c.take<int32_t>((size_t)t.tvcap);
+    t.tout = c.take<int32_t>((size_t)t.tvcap);
+    t.ge = c.take<int32_t>((size_t)t.tvcap);
+}
+
+sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                               int64_t s64, const GresStore& store, const GresPrepTmp& tmp,
+                               int32_t* dev_status, hipStream_t st) {
     const int32_t s = (int32_t)s64;
-    const int32_t ntile = (int32_t)ceil_div(s, kTileC);
-    const uint32_t sblocks = (uint32_t)ceil_div(s, kBlock);
     const int bits = curve_bits(d);
-    hipLaunchKernelGGL(curve_kernel, dim3(sblocks), dim3(kBlock), 0, st, x, n, d, ld, sky_idx, s,
-                       bits, w.k0, w.v0, dev_status);
+    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, s);
+    if (s > 0) {
+        hipLaunchKernelGGL(curve_kernel, dim3((uint32_t)ceil_div(s, kBlock)), dim3(kBlock), 0, st, x, n,
+                           d, ld, rows, s, bits, tmp.k0, tmp.v0, dev_status);
+        SKY_HIP(hipGetLastError());
+        SKY_TRY(launch_radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, s, bits * d, tmp.radix_tmp, st));
+    }
+    hipLaunchKernelGGL(store_kernel, dim3((uint32_t)ceil_div(store.ccap, kBlock)), dim3(kBlock), 0, st,
+                       x, n, d, ld, rows, s, (const uint32_t*)tmp.k0, (const uint32_t*)tmp.v0,
+                       store.cand, store.ccap, store.ckey, store.perm);
+    const int32_t ntile = (int32_t)ceil_div(s, kTileC);
+    if (ntile > 0)
+        hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
+                           st, (const float*)store.cand, store.ccap, s, d, ntile, store.lo, store.hi,
+                           store.tcap);
     SKY_HIP(hipGetLastError());
-    SKY_TRY(launch_radix_sort(w.k0, w.v0, w.k1, w.v1, s, bits * d, w.radix_tmp, st));
-    hipLaunchKernelGGL(gather_sorted_kernel, dim3(sblocks), dim3(kBlock), 0, st, x, n, d, ld, sky_idx,
-                       s, (const uint32_t*)w.v0, w.cand, w.s_pad);
-    hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock),
-                       0, st, (const float*)w.cand, w.s_pad, s, d, ntile, w.lo, w.hi, w.t_pad);
+    return SKY_OK;
+}
+
+sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld,
+                               const int64_t* rows /* null: all candidates */, int64_t nt64,
+                               int64_t s64, const GresStore& store, const GresTargets& tg,
+                               int32_t* dev_status, hipStream_t st) {
+    const int32_t nt = (int32_t)nt64;
+    if (nt <= 0) return SKY_OK;
+    if (!rows) {
+        hipLaunchKernelGGL(targets_all_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st,
+                           (const float*)store.cand, store.ccap, nt, d, (const int32_t*)store.perm,
+                           tg.tval, tg.tvcap, tg.thint, tg.tout);
+    } else {
+        hipLaunchKernelGGL(targets_rows_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st,
+                           x, n, d, ld, rows, nt, curve_bits(d), (const uint32_t*)store.ckey,
+                           (int32_t)s64, tg.tval, tg.tvcap, tg.thint, tg.tout, dev_status);
+    }
     SKY_HIP(hipGetLastError());
-    if (mapping == SKY_GRES_AUTO) mapping = (g_max > 64 && s <= 8192) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
-    const uint32_t wblocks = (uint32_t)ceil_div(s, kBlock / kWave);
+    return SKY_OK;
+}
+
+int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
+    return (g_max > 64 && s <= 8192) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
+}
+
+sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
+                              const GresTargets& tg, int64_t nt64, const int32_t* wg_table,
+                              int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
+                              float* gres, void* ev_begin, void* ev_end, hipStream_t st) {
+    const int32_t nt = (int32_t)nt64;
+    if (nt <= 0) return SKY_OK;
+    // LDS for the tile boxes of the largest segment, when they fit
+    const int32_t ntile = (int32_t)ceil_div(max_cnt, kTileC);
+    const int32_t nchunk = (int32_t)ceil_div(ntile, kWave);
+    int64_t floats = (int64_t)d * (2 * ntile + nchunk);
+    if (floats * 4 > kGresLdsBytes || nchunk > kWave) floats = 0;
+    const size_t lds = (size_t)floats * sizeof(float);
+    int32_t per_wg = 0;
+    uint32_t blocks = (uint32_t)n_wg;
+    if (!wg_table) {
+        // single segment: ~4 targets per wave when there are plenty, fewer otherwise
+        int64_t want = ceil_div(nt, kWaves * 4);
+        if (want < 256) want = ceil_div(nt, kWaves);
+        blocks = (uint32_t)(want < 1 ? 1 : want);
+        per_wg = (int32_t)ceil_div(nt, blocks);
+        blocks = (uint32_t)ceil_div(nt, per_wg);
+    }
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (mapping == SKY_GRES_LEVELS) {
-        SKY_DISPATCH_D(d, gres_levels_kernel, dim3(wblocks), dim3(kBlock), 0, st,
-                       (const float*)w.cand, w.s_pad, s, d, (const float*)w.lo, (const float*)w.hi,
-                       w.t_pad, ntile, g_max, w.ge_sorted);
+        SKY_DISPATCH_D(d, gres_levels_kernel, dim3(blocks), dim3(kGresBlock), 0, st,
+                       (const float*)store.cand, store.ccap, (const float*)store.lo,
+                       (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
+                       (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
+                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge);
     } else {
-        const int32_t nchunk = (int32_t)ceil_div(ntile, kWave);
-        const size_t lds = sizeof(float) * 2 * (size_t)d * (size_t)(ntile + nchunk);
-        const int use_lds = (lds <= (size_t)kGresLdsBytes && nchunk <= kWave) ? 1 : 0;
-        const int64_t want = ceil_div(s, kGresBlock / kWave);
-        const uint32_t blocks = (uint32_t)(want < 1024 ? want : 1024);
-        SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(blocks), dim3(kGresBlock), use_lds ? lds : 0, st,
-                       (const float*)w.cand, w.s_pad, s, d, (const float*)w.lo, (const float*)w.hi,
-                       w.t_pad, ntile, g_max, use_lds, w.ge_sorted);
+        SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(blocks), dim3(kGresBlock), lds, st,
+                       (const float*)store.cand, store.ccap, (const float*)store.lo,
+                       (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
+                       (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
+                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge);
     }
     SKY_HIP(hipGetLastError());
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));
-    hipLaunchKernelGGL(gres_output_kernel, dim3(sblocks), dim3(kBlock), 0, st,
-                       (const int32_t*)w.ge_sorted, (const uint32_t*)w.v0, s, g_exit, gres);
+    hipLaunchKernelGGL(gres_output_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st,
+                       (const int32_t*)tg.ge, (const int32_t*)tg.tout, nt, g_exit, gres);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

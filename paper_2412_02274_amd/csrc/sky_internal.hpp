@@ -165,6 +165,7 @@ struct PartitionArgs {
     uint8_t* pruned;           // [p] Grid: pruned by grid dominance
     int32_t* part_of_row;      // [n] scratch
     int32_t* hist;             // [p * ntiles] scratch
+    int64_t hist_cap;          // entries available in hist
     int32_t* scan_tmp;         // scan scratch
     uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp; // Sliced sort scratch
     int32_t* dev_status;
@@ -225,18 +226,35 @@ sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t
                                hipStream_t st);
 
 // sky_gres.hip
-struct GresWork {
-    float* cand;          // [d * s_pad] canonical candidates in spatial order
-    float* lo;            // [d * t_pad] per-tile lower corner
-    float* hi;            // [d * t_pad] per-tile upper corner
-    uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp;
-    int32_t* ge_sorted;   // [s]
-    int64_t s_pad, t_pad;
+// Prepared candidate store: segments 64-aligned in Hilbert order, padding value 2.0.
+struct GresStore {
+    float* cand; int64_t ccap;     // [d][ccap]
+    float* lo; float* hi; int64_t tcap;  // [d][tcap] per-tile boxes (global tile index)
+    uint32_t* ckey;                // [ccap] curve keys (sorted within a segment)
+    int32_t* perm;                 // [ccap] caller index of each slot (-1 for padding)
+    int32_t* seg_coff;             // [nseg] first slot of each segment (multiple of 64)
+    int32_t* seg_cnt;              // [nseg] candidates of each segment
 };
-int64_t gres_pad(int64_t s);
-sky_status launch_gres(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
-                       int64_t s, int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres,
-                       const GresWork& w, int32_t* dev_status, void* ev_begin, void* ev_end,
-                       hipStream_t st);
+struct GresPrepTmp { uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp; };
+struct GresTargets {
+    float* tval; int64_t tvcap;    // [d][tvcap] target values
+    int32_t* thint;                // [tvcap] starting tile of each target (local to its segment)
+    int32_t* tout;                 // [tvcap] output index of each target (-1: none)
+    int32_t* ge;                   // [tvcap] result per target
+};
+void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg);
+void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);
+void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d);
+sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                               int64_t s, const GresStore& store, const GresPrepTmp& tmp,
+                               int32_t* dev_status, hipStream_t st);
+sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                               int64_t nt, int64_t s, const GresStore& store, const GresTargets& tg,
+                               int32_t* dev_status, hipStream_t st);
+int32_t gres_auto_mapping(int64_t s, int32_t g_max);
+sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
+                              const GresTargets& tg, int64_t nt, const int32_t* wg_table,
+                              int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
+                              float* gres, void* ev_begin, void* ev_end, hipStream_t st);
 
 }  // namespace sky

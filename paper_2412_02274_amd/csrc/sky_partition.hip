@@ -398,6 +398,7 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     // 3. stable counting sort by partition over the curve order
     const int chunks = part_chunks(n, a.p);
     const int64_t ntiles = ceil_div(n, (int64_t)chunks * kWave);
+    if ((int64_t)a.p * ntiles > a.hist_cap) return SKY_ERR_WORKSPACE;  // never with the API's sizes
     const uint32_t tblocks = (uint32_t)ceil_div(ntiles, kWavesPerBlock);
     const size_t lds = sizeof(int32_t) * (size_t)kWavesPerBlock * (size_t)a.p;
     hipLaunchKernelGGL(part_hist_kernel, dim3(tblocks), dim3(kBlock), lds, st,

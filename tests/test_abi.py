@@ -104,3 +104,16 @@ def test_argument_errors_return_synchronously(lib):
                             C.byref(bad), None) == E
     assert lib.gres_compute(None, 0, 2, 0, None, 0, 25, None, None, None, 0, fake, None,
                             None) == _lib.SKY_OK  # s = 0: nothing to do
+
+
+def test_sliced_workspace_holds_partition_histogram(lib):
+    # Sliced partitions go through the same stable counting sort by partition as Grid/Angular,
+    # so for equal p its workspace must hold the same histogram table (regression: it used to
+    # reserve 64 entries and the table overran into the scan scratch).
+    for n in (5003, 1_000_000, 10_000_000):
+        ang = _lib.SkyParams(_lib.SKY_ANGULAR, 64, 0, 0)   # d = 4 -> m = 4, p = 64
+        sli = _lib.SkyParams(_lib.SKY_SLICED, 64, 0, 0)
+        assert lib.sky_build_workspace_bytes(n, 4, C.byref(sli)) >= \
+            lib.sky_build_workspace_bytes(n, 4, C.byref(ang))
+    too_many = _lib.SkyParams(_lib.SKY_SLICED, 5000, 0, 0)
+    assert lib.sky_build_workspace_bytes(100000, 4, C.byref(too_many)) == 0

@@ -260,3 +260,79 @@ def test_config_ant_1m_d6(dev):
     want_ge = oracle.gres_rows(x, want_sky, want_sky[pick], 25)
     assert (ge[pick] == want_ge).all()
     assert ((ge == 1) | ((ge >= 2) & (ge <= 25))).all()
+
+
+@pytest.mark.parametrize("scheme", ["grid", "angular", "sliced"])
+def test_config_uni_10m_d4_partitioned(dev, scheme):
+    """Partitioned plain method: UNI 10,000,000 x 4, target 64 partitions per scheme. Partition
+    ids, local skylines (per partition, by definition) and the final skyline in full; gres of
+    every skyline tuple at g_max = 25."""
+    x = _cached_uni_10m()
+    want_sky = _cached_uni_10m_sky()
+    _say("10m", scheme)
+    xs, idx, part, loc, info = run_skyline(dev, x, scheme, 64, slice_dim=0)
+    assert len(idx) == len(want_sky) and (idx == want_sky).all()
+    check_partitioned(x, scheme, 64, part, loc, info, slice_dim=0)
+    ge, _ = api.gres(xs, torch.from_numpy(idx).to(dev), 25)
+    want_ge, _ = oracle.gres(x, want_sky, 25)
+    assert (ge.cpu().numpy() == want_ge).all()
+
+
+_C10M = {}
+
+
+def _cached_uni_10m():
+    if "x" not in _C10M:
+        _C10M["x"] = G.uni(10_000_000, 4, 0)
+    return _C10M["x"]
+
+
+def _cached_uni_10m_sky():
+    if "sky" not in _C10M:
+        _C10M["sky"] = np.flatnonzero(oracle.skyline_sfs(_cached_uni_10m())[0])
+    return _C10M["sky"]
+
+
+@pytest.mark.parametrize("mapping", ["tiles", "levels"])
+@pytest.mark.parametrize("kind,d,g_max", [("ant", 4, 25), ("uni", 3, 300), ("ties", 5, 25)])
+def test_gres_prepare_search_targets(dev, mapping, kind, d, g_max):
+    """Prepared candidates (the skyline) searched for arbitrary target rows: skyline subsets in
+    any order with repeats, and dominated rows."""
+    x = _rows(kind, 20000, d, 5 * d)
+    sky = np.flatnonzero(oracle.skyline(x)) if len(x) <= 5000 else \
+        np.flatnonzero(oracle.skyline_sfs(x)[0])
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    prep = api.PreparedCandidates(xs, torch.from_numpy(sky).to(dev))
+    rng = np.random.default_rng(d)
+    targets = np.concatenate([rng.choice(sky, min(len(sky), 300)), sky[:5], rng.integers(0, 20000, 100)])
+    ge, gr = prep.search(torch.from_numpy(targets).to(dev), g_max, mapping)
+    want = oracle.gres_rows(x, sky, targets, g_max)
+    assert (ge.cpu().numpy() == want).all()
+    assert (gr.cpu().numpy().view(np.uint32) == oracle.gres_values(want).view(np.uint32)).all()
+    # every candidate, twice on one prepared set (the set is not consumed)
+    for _ in range(2):
+        ge_all, _ = prep.search(None, g_max, mapping)
+        want_all, _ = oracle.gres(x, sky, g_max)
+        assert (ge_all.cpu().numpy() == want_all).all()
+
+
+def test_gres_search_concurrent_streams(dev):
+    """Searches of one prepared set on several streams at once give the results they give alone."""
+    x = G.ant(50000, 5, 2)
+    sky = np.flatnonzero(oracle.skyline_sfs(x)[0])
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    prep = api.PreparedCandidates(xs, torch.from_numpy(sky).to(dev))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    reqs = [np.sort(rng.choice(sky, int(rng.integers(1, len(sky))), replace=False)) for _ in range(6)]
+    alone = [prep.search(torch.from_numpy(r).to(dev), 25)[0].cpu().numpy() for r in reqs]
+    streams = [torch.cuda.Stream() for _ in reqs]
+    outs = []
+    for r, st in zip(reqs, streams):
+        with torch.cuda.stream(st):
+            t = torch.from_numpy(r).to(dev, non_blocking=False)
+            outs.append(prep.search(t, 25, stream=st, status=api.new_status(dev), check=False))
+    torch.cuda.synchronize()
+    for a, (ge, _), r in zip(alone, outs, reqs):
+        assert (ge.cpu().numpy() == a).all()
+        assert (a == oracle.gres_rows(x, sky, r, 25)).all()
