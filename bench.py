@@ -158,20 +158,32 @@ def main():
     info = pipe.last_info
     tests = counts["sfs_tests"] + counts["gres_tests"]
     executed = info["tests_local"] + info["tests_merge"]
-    ops_per_test = 2 * d  # one <= and one < comparison per attribute (Def. 1)
+    ops_per_test = 2 * d  # the kernel's one <= and one < comparison per attribute (Def. 1)
     test_tops = executed * ops_per_test / (test_ms * 1e-3) / 1e12
+    # roofline of the dominant kernel: algorithmic work is the oracle-order SFS test count x d
+    # element compares per test, over the kernel's own event time (the average launch is the
+    # same ratio: per-step work / per-step time over `launches` launches)
+    alg_ops = counts["sfs_tests"] * d
+    alg_tops = alg_ops / (test_ms * 1e-3) / 1e12
+    traffic_step = stored_traffic(args.workload, os.path.join(
+        ROOT, "paper_2412_02274_amd", "csrc", "sky_skyline.hip"))
     kernels = {
         "dominance_test": {"ms_per_step": test_ms, "launches_per_step": launches,
-                           "tests_per_step": executed, "ops_per_test": ops_per_test,
-                           "achieved_TOPs": test_tops},
-        "gres_search": {"ms_per_step": gres_ms, "launches_per_step": 1},
+                           "executed_tests_per_step": executed, "ops_per_executed_test": ops_per_test,
+                           "executed_TOPs": test_tops},
+        "gres_search": {"ms_per_step": gres_ms, "launches_per_step": 1,
+                        "alg_tests_per_step": counts["gres_tests"],
+                        "alg_TOPs": counts["gres_tests"] * d / (gres_ms * 1e-3) / 1e12},
     }
-    roofline = {"kernel": "dominance_test", "bound": "alu", "achieved": test_tops,
-                "peak": PEAK_ALU_TOPS, "unit": "TOP/s", "frac": test_tops / PEAK_ALU_TOPS,
-                "traffic": stored_traffic(args.workload, os.path.join(
-                    ROOT, "paper_2412_02274_amd", "csrc", "sky_skyline.hip")),
-                "note": "achieved = dominance tests the test kernel evaluated (device counter) x 2d "
-                        "32-bit compares / its HIP-event time per step"}
+    roofline = {"kernel": "dominance_test", "bound": "alu", "achieved": alg_tops,
+                "peak": PEAK_ALU_TOPS, "unit": "TOP/s", "frac": alg_tops / PEAK_ALU_TOPS,
+                "traffic": None if traffic_step is None else traffic_step / launches,
+                "launches_per_step": launches, "avg_launch_us": test_ms * 1e3 / launches,
+                "alg_ops_per_launch": alg_ops / launches,
+                "note": "achieved = oracle-order SFS dominance tests x d element compares per "
+                        "launch / the kernel's average HIP-event launch time; peak = 256 CUs x 64 "
+                        "lanes x 2.4 GHz 32-bit VALU lane-ops; traffic = PMC FETCH_SIZE+WRITE_SIZE "
+                        "bytes per launch (calibrated), null when the kernel changed since"}
     line = {
         "metric": METRIC,
         "value": tests / dt,
