@@ -254,33 +254,6 @@ __global__ void __launch_bounds__(kBlock) slice_parts_kernel(const uint32_t* __r
     if (q < n) part[order[q]] = (int32_t)((q * (int64_t)p) / n);
 }
 
-// ---- None: identity copy ------------------------------------------------------------------------
-template <int D>
-__global__ void __launch_bounds__(kBlock) copy_identity_kernel(
-    const float* __restrict__ x, int64_t n, int32_t d_rt, int64_t ld, float* __restrict__ xp,
-    int64_t ldp, int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum,
-    int32_t* dev_status) {
-    const int d = dget<D>(d_rt);
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool bad = false;
-    if (i < n) {
-        float f = 0.0f;
-#pragma unroll
-        for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
-            if (k < d) {
-                float v = x[(int64_t)k * ld + i];
-                bad |= !in_domain(v);
-                v = canon(v);
-                xp[(int64_t)k * ldp + i] = v;
-                f = __fadd_rn(f, v);
-            }
-        rowid[i] = (int32_t)i;
-        seg[i] = 0;
-        fsum[i] = f;
-    }
-    if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
-}
-
 // ---- Sliced: sort keys, gather ----------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) slice_keys_kernel(const float* __restrict__ x, int64_t n,
                                                              int32_t d, int64_t ld, int32_t dim,

@@ -29,7 +29,8 @@
 //
 // Test kernels take one item at a time per wavefront: the 64 lanes test 64 candidates (or
 // 64 tile boxes) at once and a ballot ends the item at its first dominator, so no lane waits
-// behind another item. No LDS, no workgroup barriers.
+// behind another item. A workgroup caches the tile boxes of its current segment in LDS when
+// they fit (a barrier only when the segment changes).
 // Bound: VALU compares and L2 latency (candidate values are a few hundred KB per segment).
 #include "sky_internal.hpp"
 
