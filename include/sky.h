@@ -30,9 +30,12 @@
  *     to the device word *dev_status (first error wins; the caller zeroes it beforehand and
  *     reads it after synchronising the stream). Outputs are defined only when both are SKY_OK.
  *   - Work is queued on `stream` (a hipStream_t passed as void*; NULL = the null stream).
- *     sky_local_skylines and sky_merge read small counters back to the host between rounds
- *     (they synchronise `stream`); sky_ingest, sky_build and gres_compute never synchronise.
- *   - Thread safety: plans are independent; a plan must not be used by two threads at once.
+ *     sky_local_skylines, sky_merge, sky_batch_create, sky_batch_skylines and sky_batch_tune
+ *     read small counters back or copy small host tables (they synchronise `stream`);
+ *     sky_ingest, sky_build, gres_compute, gres_prepare, gres_search and sky_batch_gres never
+ *     synchronise.
+ *   - Thread safety: plans and batches are independent; one must not be used by two threads
+ *     at once.
  *     No global mutable state.
  */
 #ifndef SKY_H
@@ -247,6 +250,89 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
                        int64_t ld, const int64_t* targets, int64_t nt, int32_t g_max,
                        int32_t* g_exit, float* gres, void* ws, size_t ws_bytes,
                        int32_t* dev_status, const sky_gres_opts* opts, void* stream);
+
+/*
+ * ------------------------------------------------------------------ batched relations
+ * Many independent relations with the same number of attributes d, one after the other in one
+ * SoA buffer: relation j is rows [offsets[j], offsets[j+1]) of x_soa. Each relation gets its own
+ * skyline (Def. 1) and the gres (Def. 2 via Alg. 1) of each of its skyline tuples with its own
+ * skyline as the candidate set -- exactly what the plain calls give for that relation alone;
+ * rows of different relations never meet. All relations advance together: each skyline round
+ * serves all of them, and the gres search of all of them is one launch over a device table of
+ * work items (relation, range of its skyline tuples).
+ *
+ * Sequence: sky_batch_workspace_bytes -> sky_batch_create -> sky_batch_skylines ->
+ * sky_batch_tune -> sky_batch_gres (repeatable) -> sky_batch_destroy.
+ */
+typedef struct sky_batch sky_batch; /* opaque, host-side; refers to caller memory */
+
+typedef struct sky_tune {
+    int32_t mapping;        /* SKY_GRES_AUTO / SKY_GRES_TILES / SKY_GRES_LEVELS */
+    int32_t targets_per_wg; /* skyline tuples per work item (one workgroup of 8 wavefronts);
+                               0 = default (32); else 1..4096 */
+    int32_t near_first;     /* 1 = each tuple scans the candidate tiles next to its own place on
+                               the curve first (default), 0 = tiles in curve order */
+    int32_t lpt;            /* 1 = work items ordered by estimated cost, heaviest first
+                               (default), 0 = relation order */
+} sky_tune;
+
+/*
+ * Workspace for a batch: offsets is a HOST array of nbatch + 1 row offsets, non-decreasing,
+ * offsets[0] = 0; the total offsets[nbatch] in [1, 2^30 - 2^20]; nbatch in [1, SKY_MAX_CELLS].
+ * Relations may be empty. Returns 0 for invalid arguments.
+ */
+size_t sky_batch_workspace_bytes(const int64_t* offsets, int32_t nbatch, int32_t d);
+
+/*
+ * sky_batch_create -- validates the arguments, copies the offsets to the workspace (waiting
+ * for that copy, so the host array may be released on return) and queues the partition step:
+ * every relation's rows, canonical and along a Hilbert curve, as one segment of a
+ * segment-contiguous copy. x_soa: device float[d*ld], ld >= offsets[nbatch]. Values outside
+ * the domain raise SKY_ERR_DOMAIN in *dev_status.
+ */
+sky_status sky_batch_create(const float* x_soa, int32_t d, int64_t ld, const int64_t* offsets,
+                            int32_t nbatch, void* ws, size_t ws_bytes, int32_t* dev_status,
+                            void* stream, sky_batch** out);
+
+/*
+ * sky_batch_skylines -- the skyline of every relation (synchronises `stream`: rounds read
+ * counters back). Writes sky_idx (device int64[cap]): the skyline rows of all relations,
+ * ascending (so grouped by relation), as rows of x_soa; and sky_off (device int64[nbatch+1]):
+ * relation j's skyline is sky_idx[sky_off[j] .. sky_off[j+1]). Then prepares the candidate
+ * store of every relation for the gres search. Returns SKY_ERR_CAPACITY (synchronously, the
+ * batch stays usable for sky_batch_info only) when cap is below the total skyline size, which
+ * sky_batch_info reports in sky_count; cap = offsets[nbatch] always suffices.
+ */
+sky_status sky_batch_skylines(sky_batch* batch, int64_t* sky_idx, int64_t cap, int64_t* sky_off,
+                              void* stream);
+
+/*
+ * sky_batch_tune -- builds the work table of the gres search from the tuning choices (tune may
+ * be NULL: defaults) and copies it to the workspace (synchronises `stream`). Call after
+ * sky_batch_skylines; call again to change the choices. Results never depend on them.
+ */
+sky_status sky_batch_tune(sky_batch* batch, const sky_tune* tune, void* stream);
+
+/*
+ * sky_batch_gres -- gres of every skyline tuple of every relation: g_exit[j] and gres[j]
+ * (device arrays of at least sky_count entries; either may be NULL) refer to sky_idx[j], with
+ * the same meaning as in gres_compute and relation j's skyline as the candidate set.
+ * g_max in [2, SKY_MAX_G]. Only queues kernels on `stream` (no host synchronisation, no
+ * copies), so it can be captured in a graph and replayed; ev_begin / ev_end (hipEvent_t,
+ * optional, both or neither) are recorded around the search kernel.
+ */
+sky_status sky_batch_gres(sky_batch* batch, int32_t g_max, int32_t* g_exit, float* gres,
+                          void* ev_begin, void* ev_end, void* stream);
+
+/*
+ * sky_batch_info -- n = total rows, d, scheme = SKY_NONE, p = nbatch, rounds_local /
+ * tests_local of the skyline rounds, local_count = sky_count = total skyline size,
+ * max_partition = rows of the largest relation, state (1 created, 2 skylines done, 3 tuned).
+ */
+sky_status sky_batch_info(const sky_batch* batch, sky_info* out);
+
+/* Releases a batch (host memory only). Null is accepted. */
+void sky_batch_destroy(sky_batch* batch);
 
 #ifdef __cplusplus
 }

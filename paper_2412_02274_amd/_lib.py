@@ -37,7 +37,9 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "sky_plan_set_events",
            "sky_plan_info", "sky_plan_destroy",
            "gres_workspace_bytes", "gres_compute", "gres_prepare_bytes", "gres_prepare",
-           "gres_search_bytes", "gres_search")
+           "gres_search_bytes", "gres_search",
+           "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
+           "sky_batch_gres", "sky_batch_info", "sky_batch_destroy")
 
 
 class SkyParams(C.Structure):
@@ -60,6 +62,14 @@ class SkyInfo(C.Structure):
 class GresOpts(C.Structure):
     _fields_ = [("mapping", C.c_int32), ("reserved", C.c_int32), ("ev_begin", C.c_void_p),
                 ("ev_end", C.c_void_p)]
+
+
+class SkyTune(C.Structure):
+    _fields_ = [("mapping", C.c_int32), ("targets_per_wg", C.c_int32), ("near_first", C.c_int32),
+                ("lpt", C.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class SkyError(RuntimeError):
@@ -103,6 +113,13 @@ def load():
         "gres_search_bytes": (sz, [i64, i32]),
         "gres_search": (i32, [vp, i64, i32, vp, i64, i64, vp, i64, i32, vp, vp, vp, sz, vp,
                               C.POINTER(GresOpts), vp]),
+        "sky_batch_workspace_bytes": (sz, [C.POINTER(i64), i32, i32]),
+        "sky_batch_create": (i32, [vp, i32, i64, C.POINTER(i64), i32, vp, sz, vp, vp, C.POINTER(vp)]),
+        "sky_batch_skylines": (i32, [vp, vp, i64, vp, vp]),
+        "sky_batch_tune": (i32, [vp, C.POINTER(SkyTune), vp]),
+        "sky_batch_gres": (i32, [vp, i32, vp, vp, vp, vp, vp]),
+        "sky_batch_info": (i32, [vp, C.POINTER(SkyInfo)]),
+        "sky_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

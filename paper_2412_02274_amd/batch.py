@@ -1,0 +1,351 @@
+"""Many independent relations at once, over the batched C ABI (``sky_batch_*`` in
+include/sky.h); argument marshalling, packing and scheduling only.
+
+    runner = BatchRunner(datasets, g_max=25)   # host [n_i, d_i] float32 arrays
+    runner.run()                               # skyline + gres of every relation
+    rows, g_exit, gres = runner.result(i)      # relation i: its skyline rows (local indices)
+
+Relations are grouped by d. Each group is one ``sky_batch``: its rows packed one relation after
+the other in one device buffer, every relation's skyline computed by the same rounds of the
+segmented engine, then the gres of every skyline tuple (Def. 2 via Alg. 1, with the relation's
+own skyline as candidates) in one search launch per group over a device work table. The gres
+launches of all groups are captured once in a graph and replayed. ``GresTuner`` picks each
+group's work-table shape (mapping, tuples per workgroup, tile order) by timing the candidates
+on the group itself; results never depend on the choice.
+
+``PlainRunner`` is the one-relation-at-a-time path over the plain entry points (ingest, build,
+local skylines, merge, gres_compute), the reference for the batched path's throughput.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import SkyError
+from .api import _ptr, check_status
+
+__all__ = ["BatchGroup", "BatchRunner", "GresTuner", "PlainRunner", "pack_by_d"]
+
+
+def pack_by_d(datasets):
+    """Group relation indices by d: {d: [i, ...]} in ascending d, indices ascending."""
+    groups = {}
+    for i, x in enumerate(datasets):
+        groups.setdefault(int(x.shape[1]), []).append(i)
+    return dict(sorted(groups.items()))
+
+
+class BatchGroup:
+    """One sky_batch: relations of equal d packed into one row-major device buffer."""
+
+    def __init__(self, datasets, members, device, g_max):
+        lib = _lib.load()
+        self.members = list(members)
+        self.d = int(datasets[self.members[0]].shape[1])
+        sizes = [int(datasets[i].shape[0]) for i in self.members]
+        self.offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+        self.offsets[1:] = np.cumsum(sizes)
+        self.n = int(self.offsets[-1])
+        self.nb = len(self.members)
+        self.g_max = int(g_max)
+        host = np.concatenate([np.ascontiguousarray(datasets[i], dtype=np.float32)
+                               for i in self.members]) if self.n else np.zeros((0, self.d), np.float32)
+        self.x_rows = torch.from_numpy(host).to(device)
+        self.x_soa = torch.empty((self.d, self.n), dtype=torch.float32, device=device)
+        self._off_c = (C.c_int64 * (self.nb + 1))(*self.offsets.tolist())
+        self.ws_bytes = 0
+        if self.n > 0:  # a group of empty relations only has nothing to compute
+            self.ws_bytes = int(lib.sky_batch_workspace_bytes(self._off_c, self.nb, self.d))
+            if self.ws_bytes == 0:
+                raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_batch_workspace_bytes")
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.sky_idx = torch.empty(max(self.n, 1), dtype=torch.int64, device=device)
+        self.sky_off = torch.zeros(self.nb + 1, dtype=torch.int64, device=device)
+        self.g_exit = torch.empty(max(self.n, 1), dtype=torch.int32, device=device)
+        self.gres = torch.empty(max(self.n, 1), dtype=torch.float32, device=device)
+        self.h = None
+        self.sky_count = 0
+        self.info = None
+        self.tune = _lib.SkyTune(_lib.SKY_GRES_AUTO, 0, 1, 1)
+        self.n_wg_key = None
+
+    def skylines(self, stream):
+        """ingest -> create -> skylines (synchronises the stream)."""
+        lib = _lib.load()
+        sp = C.c_void_p(stream.cuda_stream)
+        self.close()
+        self.status.zero_()
+        if self.n == 0:
+            self.sky_count = 0
+            self.info = {"n": 0, "d": self.d, "p": self.nb, "sky_count": 0}
+            return
+        _lib.check(lib.sky_ingest(_ptr(self.x_rows), self.n, self.d, _ptr(self.x_soa), self.n,
+                                  _ptr(self.status), sp), "sky_ingest")
+        h = C.c_void_p()
+        _lib.check(lib.sky_batch_create(_ptr(self.x_soa), self.d, self.n, self._off_c, self.nb,
+                                        _ptr(self.ws), self.ws_bytes, _ptr(self.status), sp,
+                                        C.byref(h)), "sky_batch_create")
+        self.h = h
+        _lib.check(lib.sky_batch_skylines(self.h, _ptr(self.sky_idx), self.n, _ptr(self.sky_off),
+                                          sp), "sky_batch_skylines")
+        inf = _lib.SkyInfo()
+        _lib.check(lib.sky_batch_info(self.h, C.byref(inf)), "sky_batch_info")
+        self.info = inf.as_dict()
+        self.sky_count = int(inf.sky_count)
+
+    def set_tune(self, tune, stream):
+        self.tune = tune
+        if self.h is None:
+            return
+        _lib.check(_lib.load().sky_batch_tune(self.h, C.byref(tune), C.c_void_p(stream.cuda_stream)),
+                   "sky_batch_tune")
+
+    def launch_gres(self, stream, ev_begin=None, ev_end=None):
+        if self.h is None:
+            return
+        _lib.check(_lib.load().sky_batch_gres(self.h, self.g_max, _ptr(self.g_exit), _ptr(self.gres),
+                                              ev_begin, ev_end, C.c_void_p(stream.cuda_stream)),
+                   "sky_batch_gres")
+
+    def close(self):
+        if self.h is not None:
+            _lib.load().sky_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class GresTuner:
+    """Per-group choice of the gres work table by measurement: coordinate descent over
+    tuples-per-workgroup, mapping and tile order, each candidate timed on the group's own
+    prepared candidates (torch events on the launch stream). Choices are cached per
+    (d, skyline size, largest relation's skyline, g_max) in memory and, if `path` is given, in
+    a JSON file."""
+
+    PER_WG = (8, 16, 32, 64, 128)
+
+    def __init__(self, path=None, repeats=2):
+        self.path = path
+        self.repeats = repeats
+        self.cache = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.cache = json.load(f)
+        self.trials = []
+
+    @staticmethod
+    def key(group):
+        cnt = np.diff(group.sky_off.cpu().numpy())
+        return f"d{group.d}_s{group.sky_count}_m{int(cnt.max()) if cnt.size else 0}_g{group.g_max}"
+
+    def _time(self, group, tune, stream):
+        group.set_tune(tune, stream)
+        best = None
+        for _ in range(self.repeats):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            group.launch_gres(stream)
+            b.record(stream)
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+        self.trials.append((group.d, tune.as_dict(), best))
+        return best
+
+    def choose(self, group, stream):
+        if group.sky_count == 0:
+            return _lib.SkyTune(_lib.SKY_GRES_AUTO, 0, 1, 1)
+        k = self.key(group)
+        if k in self.cache:
+            return _lib.SkyTune(**self.cache[k])
+        cur = dict(mapping=_lib.SKY_GRES_TILES, targets_per_wg=32, near_first=1, lpt=1)
+        best_ms = None
+        for field, values in (("targets_per_wg", self.PER_WG),
+                              ("mapping", (_lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS)),
+                              ("near_first", (1, 0)), ("lpt", (1, 0))):
+            best_v = cur[field]
+            for v in values:
+                trial = dict(cur, **{field: v})
+                ms = self._time(group, _lib.SkyTune(**trial), stream)
+                if best_ms is None or ms < best_ms:
+                    best_ms, best_v = ms, v
+            cur[field] = best_v
+        self.cache[k] = cur
+        if self.path:
+            with open(self.path, "w") as f:
+                json.dump(self.cache, f, indent=1, sort_keys=True)
+        return _lib.SkyTune(**cur)
+
+
+class BatchRunner:
+    """Skyline and gres of many relations of mixed d (see the module docstring)."""
+
+    def __init__(self, datasets, g_max=25, device="cuda", tuner=None, use_graph=True):
+        self.device = torch.device(device)
+        self.g_max = int(g_max)
+        self.sizes = [(int(x.shape[0]), int(x.shape[1])) for x in datasets]
+        self.groups = [BatchGroup(datasets, mem, self.device, g_max)
+                       for mem in pack_by_d(datasets).values()]
+        self.where = {}
+        for gi, g in enumerate(self.groups):
+            for j, i in enumerate(g.members):
+                self.where[i] = (gi, j)
+        self.tuner = tuner
+        self.use_graph = use_graph
+        self.graph = None
+        self.graph_key = None
+        self.stream = torch.cuda.Stream(self.device)
+        self.phase = {}
+
+    def _graph_key(self):
+        return tuple((g.sky_count, tuple(g.tune.as_dict().values())) for g in self.groups)
+
+    def run(self, check=True, tune=True):
+        st = self.stream
+        cur = torch.cuda.current_stream(self.device)
+        st.wait_stream(cur)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(st):
+            e0.record(st)
+            for g in self.groups:
+                g.skylines(st)
+            for g in self.groups:
+                if tune and self.tuner is not None and g.sky_count:
+                    g.set_tune(self.tuner.choose(g, st), st)
+                else:
+                    g.set_tune(g.tune, st)
+            e1.record(st)
+            if self.use_graph:
+                key = self._graph_key()
+                if self.graph is None or key != self.graph_key:
+                    self._capture()
+                    self.graph_key = key
+                self.graph.replay()
+            else:
+                for g in self.groups:
+                    g.launch_gres(st)
+            e2.record(st)
+        cur.wait_stream(st)
+        if check:
+            st.synchronize()
+            for g in self.groups:
+                check_status(g.status, "batch")
+        self._ev = (e0, e1, e2)
+        return self
+
+    def _capture(self):
+        # one eager pass first (the graph then replays identical launches)
+        st = self.stream
+        for g in self.groups:
+            g.launch_gres(st)
+        st.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=st):
+            for g in self.groups:
+                g.launch_gres(torch.cuda.current_stream())
+
+    def phase_ms(self):
+        e0, e1, e2 = self._ev
+        e2.synchronize()
+        return {"skylines": e0.elapsed_time(e1), "gres": e1.elapsed_time(e2)}
+
+    def sky_total(self):
+        return sum(g.sky_count for g in self.groups)
+
+    def result(self, i):
+        """(skyline rows of relation i as local row indices, g_exit, gres) on the host."""
+        gi, j = self.where[i]
+        g = self.groups[gi]
+        off = g.sky_off.cpu().numpy()
+        a, b = int(off[j]), int(off[j + 1])
+        rows = g.sky_idx[a:b].cpu().numpy() - int(g.offsets[j])
+        return rows, g.g_exit[a:b].cpu().numpy(), g.gres[a:b].cpu().numpy()
+
+    def info(self):
+        return [dict(g.info, tune=g.tune.as_dict()) for g in self.groups]
+
+    def close(self):
+        for g in self.groups:
+            g.close()
+
+
+class PlainRunner:
+    """One relation at a time through the plain entry points (ingest -> build -> local
+    skylines -> merge -> gres_compute), buffers sized once for the largest relation of each d."""
+
+    def __init__(self, datasets, g_max=25, device="cuda"):
+        lib = _lib.load()
+        self.device = torch.device(device)
+        self.g_max = int(g_max)
+        self.x = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(self.device)
+                  for x in datasets]
+        self.bufs = {}
+        for x in datasets:
+            n, d = int(x.shape[0]), int(x.shape[1])
+            nmax = max(n, self.bufs.get(d, 0))
+            self.bufs[d] = nmax
+        prm = _lib.SkyParams(_lib.SKY_NONE, 1, 0, 0)
+        for d, nmax in list(self.bufs.items()):
+            bb = int(lib.sky_build_workspace_bytes(nmax, d, C.byref(prm)))
+            gb = int(lib.gres_workspace_bytes(nmax, d, self.g_max))
+            self.bufs[d] = dict(
+                nmax=nmax, bb=bb, gb=gb,
+                bws=torch.empty(bb, dtype=torch.uint8, device=self.device),
+                gws=torch.empty(gb, dtype=torch.uint8, device=self.device),
+                soa=torch.empty(d * nmax, dtype=torch.float32, device=self.device),
+                sky=torch.empty(nmax, dtype=torch.int64, device=self.device),
+                cnt=torch.zeros(1, dtype=torch.int64, device=self.device),
+                ge=torch.empty(nmax, dtype=torch.int32, device=self.device),
+                gr=torch.empty(nmax, dtype=torch.float32, device=self.device))
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.counts = [0] * len(datasets)
+        self.keep = None
+
+    def run_one(self, i, keep=False):
+        lib = _lib.load()
+        st = torch.cuda.current_stream(self.device)
+        sp = C.c_void_p(st.cuda_stream)
+        x = self.x[i]
+        n, d = int(x.shape[0]), int(x.shape[1])
+        b = self.bufs[d]
+        _lib.check(lib.sky_ingest(_ptr(x), n, d, _ptr(b["soa"]), n, _ptr(self.status), sp), "sky_ingest")
+        prm = _lib.SkyParams(_lib.SKY_NONE, 1, 0, 0)
+        h = C.c_void_p()
+        _lib.check(lib.sky_build(_ptr(b["soa"]), n, d, n, C.byref(prm), _ptr(b["bws"]), b["bb"],
+                                 _ptr(self.status), sp, C.byref(h)), "sky_build")
+        try:
+            _lib.check(lib.sky_local_skylines(h, sp), "sky_local_skylines")
+            _lib.check(lib.sky_merge(h, _ptr(b["sky"]), n, _ptr(b["cnt"]), None, sp), "sky_merge")
+            s = int(b["cnt"].item())
+        finally:
+            lib.sky_plan_destroy(h)
+        opts = _lib.GresOpts(_lib.SKY_GRES_AUTO)
+        _lib.check(lib.gres_compute(_ptr(b["soa"]), n, d, n, _ptr(b["sky"]), s, self.g_max,
+                                    _ptr(b["ge"]), _ptr(b["gr"]), _ptr(b["gws"]), b["gb"],
+                                    _ptr(self.status), C.byref(opts), sp), "gres_compute")
+        self.counts[i] = s
+        if keep:
+            return (b["sky"][:s].cpu().numpy(), b["ge"][:s].cpu().numpy(), b["gr"][:s].cpu().numpy())
+        return None
+
+    def run(self, check=True):
+        self.status.zero_()
+        for i in range(len(self.x)):
+            self.run_one(i)
+        if check:
+            torch.cuda.current_stream(self.device).synchronize()
+            check_status(self.status, "plain")
+        return self

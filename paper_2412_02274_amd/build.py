@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsky.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["sky_api.cpp", "sky_ingest.hip", "sky_scan.hip", "sky_radix.hip", "sky_partition.hip",
+SOURCES = ["sky_api.cpp", "sky_batch.cpp", "sky_ingest.hip", "sky_scan.hip", "sky_radix.hip", "sky_partition.hip",
            "sky_skyline.hip", "sky_gres.hip"]
 
 ARCH = os.environ.get("SKY_OFFLOAD_ARCH", "gfx950")

@@ -6,45 +6,11 @@
 
 #include <new>
 
-#include "sky_internal.hpp"
+#include "sky_plan.hpp"
 
 using namespace sky;
 
-struct sky_plan {
-    // input
-    const float* x = nullptr;
-    int64_t n = 0, ld = 0;
-    int32_t d = 0;
-    int32_t scheme = 0, p = 1, m = 0, slice_dim = 0;
-    int32_t* dev_status = nullptr;
-    int32_t state = 0;
-    // workspace regions
-    float* xp = nullptr; int64_t ldp = 0;
-    int32_t *rowid = nullptr, *seg = nullptr;
-    float* fsum = nullptr;
-    int32_t* part_off = nullptr;
-    uint8_t* pruned = nullptr;
-    double* tan2_dev = nullptr;
-    int32_t *part_of_row = nullptr, *phist = nullptr, *scan_tmp = nullptr;
-    int64_t phist_cap = 0;
-    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
-    int32_t* radix_tmp = nullptr;
-    EngineBuffers eng{};
-    uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;
-    int32_t *local_list = nullptr, *final_list = nullptr, *pos_tmp = nullptr, *count_tmp = nullptr;
-    // host copies
-    double* tan2_host = nullptr;
-    void* const* ev_begin = nullptr;
-    void* const* ev_end = nullptr;
-    int32_t ev_cap = 0;
-    int32_t ev_used = 0;
-    sky_info info{};
-};
-
 namespace {
-
-constexpr int32_t kMaxRows = 0x7FFFFFFF;
-constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset within 32 bits
 
 bool valid_d(int32_t d) { return d >= 1 && d <= SKY_MAX_D; }
 
@@ -117,6 +83,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->part_off = c.take<int32_t>((size_t)p + 1);
     P->pruned = c.take<uint8_t>((size_t)p);
     P->tan2_dev = c.take<double>((size_t)(scheme == SKY_ANGULAR ? m + 1 : 1));
+    P->seg_off_dev = c.take<int64_t>((size_t)(scheme == kSchemeSegments ? p + 1 : 1));
     // the counting sort by partition runs for every scheme with p > 1 (Sliced included)
     const int64_t hist_elems = p > 1 ? partition_hist_elems(n, p) : 64;
     P->phist_cap = hist_elems;
@@ -161,6 +128,74 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
 
 }  // namespace
 
+namespace sky {
+
+size_t plan_bytes(int64_t n, int32_t d, int32_t scheme, int32_t p, int32_t m) {
+    if (n < 1 || n > kMaxBuildRows || !valid_d(d) || p < 1) return 0;
+    sky_plan tmp;
+    Carver c(nullptr, 0);
+    carve_plan(c, &tmp, n, d, scheme, p, m);
+    return c.used;
+}
+
+sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int32_t scheme, int32_t p,
+                      int32_t m, int32_t slice_dim, const int64_t* seg_off_host, void* ws,
+                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out) {
+    *out = nullptr;
+    size_t need = plan_bytes(n, d, scheme, p, m);
+    if (need == 0) return SKY_ERR_INVALID_ARG;
+    if (ws_bytes < need) return SKY_ERR_WORKSPACE;
+    if (scheme == kSchemeSegments && !seg_off_host) return SKY_ERR_INVALID_ARG;
+    sky_plan* P = new (std::nothrow) sky_plan();
+    if (!P) return SKY_ERR_INVALID_ARG;
+    Carver c(ws, ws_bytes);
+    carve_plan(c, P, n, d, scheme, p, m);
+    if (c.overflow) { delete P; return SKY_ERR_WORKSPACE; }
+    P->x = x_soa; P->n = n; P->ld = ld; P->d = d;
+    P->scheme = scheme; P->p = p; P->m = m; P->slice_dim = slice_dim;
+    P->dev_status = dev_status;
+    if (P->scheme == SKY_ANGULAR) {
+        P->tan2_host = (double*)malloc(sizeof(double) * (size_t)(m + 1));
+        if (!P->tan2_host) { delete P; return SKY_ERR_INVALID_ARG; }
+        const double pi = 3.14159265358979323846;
+        for (int32_t k = 0; k <= m; ++k) {
+            double t = tan((double)k * pi / (2.0 * (double)m));
+            P->tan2_host[k] = t * t;
+        }
+        P->tan2_host[0] = 0.0;
+        hipError_t e = hipMemcpyAsync(P->tan2_dev, P->tan2_host, sizeof(double) * (size_t)(m + 1),
+                                      hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) { free(P->tan2_host); delete P; return SKY_ERR_HIP; }
+    }
+    if (P->scheme == kSchemeSegments) {
+        // the caller's host array may go away on return: wait for the copy
+        hipError_t e1 = hipMemcpyAsync(P->seg_off_dev, seg_off_host, sizeof(int64_t) * (size_t)(p + 1),
+                                       hipMemcpyHostToDevice, st);
+        hipError_t e2 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess) { delete P; return SKY_ERR_HIP; }
+    }
+    PartitionArgs a{};
+    a.x = x_soa; a.n = n; a.d = d; a.ld = ld;
+    a.scheme = P->scheme; a.p = p; a.m = m; a.slice_dim = P->slice_dim;
+    a.seg_off = P->seg_off_dev;
+    a.tan2 = P->tan2_dev;
+    a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
+    a.part_off = P->part_off; a.pruned = P->pruned;
+    a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
+    a.scan_tmp = P->scan_tmp;
+    a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
+    a.dev_status = dev_status;
+    sky_status s = launch_partition(a, st);
+    if (s != SKY_OK) { free(P->tan2_host); delete P; return s; }
+    P->state = 1;
+    P->info.n = n; P->info.d = d; P->info.scheme = P->scheme; P->info.p = p; P->info.m = m;
+    P->info.state = 1;
+    *out = P;
+    return SKY_OK;
+}
+
+}  // namespace sky
+
 extern "C" {
 
 const char* sky_status_string(sky_status s) {
@@ -190,10 +225,7 @@ size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params)
     if (!params || n < 1 || n > kMaxBuildRows || !valid_d(d) || params->flags != 0) return 0;
     int32_t p = 1, m = 0;
     if (resolve_partitions(n, d, params, &p, &m) != SKY_OK) return 0;
-    sky_plan tmp;
-    Carver c(nullptr, 0);
-    carve_plan(c, &tmp, n, d, params->scheme, p, m);
-    return c.used;
+    return plan_bytes(n, d, params->scheme, p, m);
 }
 
 sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const sky_params* params,
@@ -204,48 +236,8 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
     if (n < 1 || n > kMaxBuildRows || !valid_d(d) || ld < n || params->flags != 0) return SKY_ERR_INVALID_ARG;
     int32_t p = 1, m = 0;
     SKY_TRY(resolve_partitions(n, d, params, &p, &m));
-    size_t need = sky_build_workspace_bytes(n, d, params);
-    if (need == 0) return SKY_ERR_INVALID_ARG;
-    if (ws_bytes < need) return SKY_ERR_WORKSPACE;
-    sky_plan* P = new (std::nothrow) sky_plan();
-    if (!P) return SKY_ERR_INVALID_ARG;
-    Carver c(ws, ws_bytes);
-    carve_plan(c, P, n, d, params->scheme, p, m);
-    if (c.overflow) { delete P; return SKY_ERR_WORKSPACE; }
-    P->x = x_soa; P->n = n; P->ld = ld; P->d = d;
-    P->scheme = params->scheme; P->p = p; P->m = m; P->slice_dim = params->slice_dim;
-    P->dev_status = dev_status;
-    hipStream_t st = (hipStream_t)stream;
-    if (P->scheme == SKY_ANGULAR) {
-        P->tan2_host = (double*)malloc(sizeof(double) * (size_t)(m + 1));
-        if (!P->tan2_host) { delete P; return SKY_ERR_INVALID_ARG; }
-        const double pi = 3.14159265358979323846;
-        for (int32_t k = 0; k <= m; ++k) {
-            double t = tan((double)k * pi / (2.0 * (double)m));
-            P->tan2_host[k] = t * t;
-        }
-        P->tan2_host[0] = 0.0;
-        hipError_t e = hipMemcpyAsync(P->tan2_dev, P->tan2_host, sizeof(double) * (size_t)(m + 1),
-                                      hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) { free(P->tan2_host); delete P; return SKY_ERR_HIP; }
-    }
-    PartitionArgs a{};
-    a.x = x_soa; a.n = n; a.d = d; a.ld = ld;
-    a.scheme = P->scheme; a.p = p; a.m = m; a.slice_dim = P->slice_dim;
-    a.tan2 = P->tan2_dev;
-    a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
-    a.part_off = P->part_off; a.pruned = P->pruned;
-    a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
-    a.scan_tmp = P->scan_tmp;
-    a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
-    a.dev_status = dev_status;
-    sky_status s = launch_partition(a, st);
-    if (s != SKY_OK) { free(P->tan2_host); delete P; return s; }
-    P->state = 1;
-    P->info.n = n; P->info.d = d; P->info.scheme = P->scheme; P->info.p = p; P->info.m = m;
-    P->info.state = 1;
-    *out = P;
-    return SKY_OK;
+    return plan_build(x_soa, n, d, ld, params->scheme, p, m, params->slice_dim, nullptr, ws, ws_bytes,
+                      dev_status, (hipStream_t)stream, out);
 }
 
 sky_status sky_local_skylines(sky_plan* P, void* stream) {

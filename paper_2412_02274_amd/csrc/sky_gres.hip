@@ -118,18 +118,22 @@ __global__ void __launch_bounds__(kBlock) store_kernel(const float* __restrict__
     perm[q] = j;
 }
 
-// one wave per tile: componentwise minimum (lo) and maximum (hi) of its real candidates
+// one wave per tile: componentwise minimum (lo) and maximum (hi) of its real candidates (padding
+// slots hold kPadValue in every attribute; a tile of padding only gets lo = 1, which no key test
+// passes: fl(1 g) = g is above every key of a value in [0, 1))
 __global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restrict__ cand, int64_t ccap,
-                                                           int32_t s, int32_t d, int32_t ntile,
+                                                           int32_t d, int32_t ntile,
                                                            float* __restrict__ lo,
                                                            float* __restrict__ hi, int64_t tcap) {
     const int32_t tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (tile >= ntile) return;
     const int lane = (int)lane_id();
-    const int32_t j = tile * kTileC + lane;
+    const int64_t j = (int64_t)tile * kTileC + lane;
+    const bool real = cand[j] < kPadValue;
     for (int k = 0; k < d; ++k) {
-        float v = j < s ? cand[(int64_t)k * ccap + j] : 1.0f;
-        float h = j < s ? v : 0.0f;
+        const float c = cand[(int64_t)k * ccap + j];
+        float v = real ? c : 1.0f;
+        float h = real ? c : 0.0f;
         for (int off = kWave / 2; off > 0; off >>= 1) {
             v = fminf(v, __shfl_xor(v, off, kWave));
             h = fmaxf(h, __shfl_xor(h, off, kWave));
@@ -139,6 +143,49 @@ __global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restric
             hi[(int64_t)k * tcap + tile] = h;
         }
     }
+}
+
+// largest j in [0, cnt) with off[j] <= q (off non-decreasing; empty segments share their offset
+// with the next one, so the search lands on the segment that holds q)
+__device__ __forceinline__ int32_t find_seg(const int32_t* __restrict__ off, int32_t cnt, int64_t q) {
+    int32_t lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// segment of every element in the curve order (key of the stable second sort)
+__global__ void __launch_bounds__(kBlock) seg_key_kernel(const uint32_t* __restrict__ order, int32_t s,
+                                                          const int32_t* __restrict__ cand_off,
+                                                          int32_t nseg, uint32_t* __restrict__ keys) {
+    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q < s) keys[q] = (uint32_t)find_seg(cand_off, nseg, (int64_t)order[q]);
+}
+
+// every slot of a segmented store: slot q of segment sg holds the (q - coff)-th element of the
+// segment in curve order, or padding past the segment's count
+__global__ void __launch_bounds__(kBlock) store_seg_kernel(
+    const float* __restrict__ x, int64_t n, int32_t d, int64_t ld, const int64_t* __restrict__ rows,
+    const uint32_t* __restrict__ order, const int32_t* __restrict__ cand_off,
+    const int32_t* __restrict__ seg_coff, const int32_t* __restrict__ seg_cnt, int32_t nseg, int bits,
+    float* __restrict__ cand, int64_t ccap, uint32_t* __restrict__ ckey, int32_t* __restrict__ perm) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= ccap) return;
+    const int32_t sg = find_seg(seg_coff, nseg, q);
+    const int64_t r = q - seg_coff[sg];
+    const bool real = r >= 0 && r < seg_cnt[sg];
+    const int32_t j = real ? (int32_t)order[cand_off[sg] + r] : -1;
+    const int64_t row = real ? rows[j] : -1;
+    const bool ok = real && row >= 0 && row < n;
+    float v[SKY_MAX_D];
+    for (int k = 0; k < d; ++k) {
+        v[k] = ok ? canon(x[(int64_t)k * ld + row]) : (real ? 0.0f : kPadValue);
+        cand[(int64_t)k * ccap + q] = v[k];
+    }
+    ckey[q] = real ? hilbert_key(v, d, bits) : 0xFFFFFFFFu;
+    perm[q] = j;
 }
 
 __global__ void single_segment_kernel(int32_t* __restrict__ seg_coff, int32_t* __restrict__ seg_cnt,
@@ -163,6 +210,46 @@ __global__ void __launch_bounds__(kBlock) targets_all_kernel(const float* __rest
     for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + q];
     thint[q] = q / kTileC;
     tout[q] = perm[q];
+}
+
+// targets = every candidate of a segmented store in element order: element q of segment sg
+// sits at slot seg_coff[sg] + (q - cand_off[sg])
+__global__ void __launch_bounds__(kBlock) targets_seg_kernel(
+    const float* __restrict__ cand, int64_t ccap, int32_t s, int32_t d,
+    const int32_t* __restrict__ cand_off, const int32_t* __restrict__ seg_coff, int32_t nseg,
+    const int32_t* __restrict__ perm, int32_t near_first, float* __restrict__ tval, int64_t tvcap,
+    int32_t* __restrict__ thint, int32_t* __restrict__ tout) {
+    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= s) return;
+    const int32_t sg = find_seg(cand_off, nseg, q);
+    const int32_t r = q - cand_off[sg];
+    const int64_t slot = (int64_t)seg_coff[sg] + r;
+    for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + slot];
+    thint[q] = near_first ? r / kTileC : 0;
+    tout[q] = perm[slot];
+}
+
+// first position of every relation's rows in the ascending skyline list (lower bound of its
+// first row), as int64 offsets for the caller and int32 element offsets for the store
+__global__ void __launch_bounds__(kBlock) batch_offsets_kernel(const int64_t* __restrict__ sky_idx,
+                                                                int32_t count,
+                                                                const int64_t* __restrict__ row_off,
+                                                                int32_t nseg, int64_t* __restrict__ sky_off,
+                                                                int32_t* __restrict__ cand_off) {
+    const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j > nseg) return;
+    int32_t lo = 0, hi = count;
+    if (j == nseg) {
+        lo = count;
+    } else {
+        const int64_t key = row_off[j];
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (sky_idx[mid] < key) lo = mid + 1; else hi = mid;
+        }
+    }
+    sky_off[j] = lo;
+    cand_off[j] = lo;
 }
 
 // targets = given rows of the relation: values, hint tile (where the row's curve key falls
@@ -558,7 +645,7 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
     const int32_t ntile = (int32_t)ceil_div(s, kTileC);
     if (ntile > 0)
         hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
-                           st, (const float*)store.cand, store.ccap, s, d, ntile, store.lo, store.hi,
+                           st, (const float*)store.cand, store.ccap, d, ntile, store.lo, store.hi,
                            store.tcap);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
@@ -579,6 +666,62 @@ sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld,
                            x, n, d, ld, rows, nt, curve_bits(d), (const uint32_t*)store.ckey,
                            (int32_t)s64, tg.tval, tg.tvcap, tg.thint, tg.tout, dev_status);
     }
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_gres_prepare_segments(const float* x, int64_t n, int32_t d, int64_t ld,
+                                        const int64_t* rows, int64_t s64, const int32_t* cand_off,
+                                        int32_t nseg, int32_t ntile, const GresStore& store,
+                                        const GresPrepTmp& tmp, int32_t* dev_status, hipStream_t st) {
+    const int32_t s = (int32_t)s64;
+    const int bits = curve_bits(d);
+    if (s > 0) {
+        const uint32_t blocks = (uint32_t)ceil_div(s, kBlock);
+        hipLaunchKernelGGL(curve_kernel, dim3(blocks), dim3(kBlock), 0, st, x, n, d, ld, rows, s, bits,
+                           tmp.k0, tmp.v0, dev_status);
+        SKY_HIP(hipGetLastError());
+        SKY_TRY(launch_radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, s, bits * d, tmp.radix_tmp, st));
+        if (nseg > 1) {
+            // stable sort by segment over the curve order: (segment, curve) order
+            hipLaunchKernelGGL(seg_key_kernel, dim3(blocks), dim3(kBlock), 0, st, (const uint32_t*)tmp.v0,
+                               s, cand_off, nseg, tmp.k0);
+            SKY_HIP(hipGetLastError());
+            int sbits = 0;
+            while ((1 << sbits) < nseg) ++sbits;
+            SKY_TRY(launch_radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, s, sbits, tmp.radix_tmp, st));
+        }
+    }
+    hipLaunchKernelGGL(store_seg_kernel, dim3((uint32_t)ceil_div(store.ccap, kBlock)), dim3(kBlock), 0, st,
+                       x, n, d, ld, rows, (const uint32_t*)tmp.v0, cand_off, (const int32_t*)store.seg_coff,
+                       (const int32_t*)store.seg_cnt, nseg, bits, store.cand, store.ccap, store.ckey,
+                       store.perm);
+    SKY_HIP(hipGetLastError());
+    if (ntile > 0)
+        hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
+                           st, (const float*)store.cand, store.ccap, d, ntile, store.lo, store.hi,
+                           store.tcap);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_gres_targets_segments(const GresStore& store, int32_t d, int64_t s64,
+                                        const int32_t* cand_off, int32_t nseg, bool near_first,
+                                        const GresTargets& tg, hipStream_t st) {
+    const int32_t s = (int32_t)s64;
+    if (s <= 0) return SKY_OK;
+    hipLaunchKernelGGL(targets_seg_kernel, dim3((uint32_t)ceil_div(s, kBlock)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, s, d, cand_off,
+                       (const int32_t*)store.seg_coff, nseg, (const int32_t*)store.perm,
+                       near_first ? 1 : 0, tg.tval, tg.tvcap, tg.thint, tg.tout);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int64_t* row_off,
+                                int32_t nseg, int64_t* sky_off, int32_t* cand_off, hipStream_t st) {
+    hipLaunchKernelGGL(batch_offsets_kernel, dim3((uint32_t)ceil_div(nseg + 1, kBlock)), dim3(kBlock), 0,
+                       st, sky_idx, (int32_t)count, row_off, nseg, sky_off, cand_off);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

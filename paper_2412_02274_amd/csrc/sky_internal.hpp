@@ -153,9 +153,14 @@ sky_status launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
                              int key_bits, int32_t* tmp, hipStream_t st);
 
 // sky_partition.hip
+// Internal partition scheme of the batched path: partition j = the rows [seg_off[j],
+// seg_off[j+1]) of one dataset (datasets are contiguous row ranges of one SoA buffer).
+constexpr int32_t kSchemeSegments = 64;
+
 struct PartitionArgs {
     const float* x; int64_t n; int32_t d; int64_t ld;
     int32_t scheme; int32_t p; int32_t m; int32_t slice_dim;
+    const int64_t* seg_off;    // kSchemeSegments: [p+1] row offsets of the datasets (device)
     const double* tan2;   // Angular thresholds tan^2(k*pi/(2m)), k = 0..m (device)
     float* xp; int64_t ldp;    // partition-contiguous canonical SoA copy
     int32_t* rowid;            // partitioned position -> original row
@@ -251,6 +256,24 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
 sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t nt, int64_t s, const GresStore& store, const GresTargets& tg,
                                int32_t* dev_status, hipStream_t st);
+// Segmented store: candidates rows[0, s) grouped by segment, segment j = elements
+// [cand_off[j], cand_off[j+1]) (device int32, nseg + 1); store.seg_coff / seg_cnt must already
+// hold each segment's 64-aligned first slot and count; ntile = tiles up to the last segment.
+sky_status launch_gres_prepare_segments(const float* x, int64_t n, int32_t d, int64_t ld,
+                                        const int64_t* rows, int64_t s, const int32_t* cand_off,
+                                        int32_t nseg, int32_t ntile, const GresStore& store,
+                                        const GresPrepTmp& tmp, int32_t* dev_status, hipStream_t st);
+// Targets = every candidate of a segmented store, in element order (segment-major); start tile
+// = the target's own tile (near_first) or the segment's first tile.
+sky_status launch_gres_targets_segments(const GresStore& store, int32_t d, int64_t s,
+                                        const int32_t* cand_off, int32_t nseg, bool near_first,
+                                        const GresTargets& tg, hipStream_t st);
+// sky_off[j] = cand_off[j] = first position of relation j's rows (row_off[j] on) in the
+// ascending list sky_idx[0, count); index nseg gets count.
+sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int64_t* row_off,
+                                int32_t nseg, int64_t* sky_off, int32_t* cand_off, hipStream_t st);
+// Work table of the segmented search: per workgroup (segment, first target, end target).
+constexpr int kGresWgEntry = 3;
 int32_t gres_auto_mapping(int64_t s, int32_t g_max);
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
                               const GresTargets& tg, int64_t nt, const int32_t* wg_table,

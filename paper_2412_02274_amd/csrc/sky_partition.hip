@@ -101,6 +101,22 @@ __global__ void __launch_bounds__(kBlock) part_id_kernel(const float* __restrict
     if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
 }
 
+// ---- per-row partition id (batched datasets): the dataset holding the row ---------------------
+// largest j in [0, p) with seg_off[j] <= i; empty datasets share their offset with the next one,
+// so the search lands on the non-empty dataset that holds row i
+__global__ void __launch_bounds__(kBlock) seg_part_kernel(const int64_t* __restrict__ seg_off,
+                                                           int32_t p, int64_t n,
+                                                           int32_t* __restrict__ part) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int32_t lo = 0, hi = p - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (seg_off[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    part[i] = lo;
+}
+
 // ---- wave-tile histogram of partition ids ----------------------------------------------------
 __global__ void __launch_bounds__(kBlock) part_hist_kernel(const int32_t* __restrict__ part,
                                                             const uint32_t* __restrict__ order,
@@ -351,6 +367,10 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
         SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, 32, a.radix_tmp, st));
         hipLaunchKernelGGL(slice_parts_kernel, dim3(rblocks), dim3(kBlock), 0, st,
                            (const uint32_t*)a.v0, n, a.p, a.part_of_row);
+        SKY_HIP(hipGetLastError());
+    } else if (a.scheme == kSchemeSegments) {
+        hipLaunchKernelGGL(seg_part_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.seg_off, a.p, n,
+                           a.part_of_row);
         SKY_HIP(hipGetLastError());
     }
     // 2. every row in Hilbert order (stable): the order rows take inside their partition

@@ -1,0 +1,52 @@
+// Private to the library: the host-side plan of the two-phase skyline and the internal calls
+// that the batched path shares with the plain one.
+#pragma once
+
+#include "sky_internal.hpp"
+
+struct sky_plan {
+    // input
+    const float* x = nullptr;
+    int64_t n = 0, ld = 0;
+    int32_t d = 0;
+    int32_t scheme = 0, p = 1, m = 0, slice_dim = 0;
+    int32_t* dev_status = nullptr;
+    int32_t state = 0;
+    // workspace regions
+    float* xp = nullptr; int64_t ldp = 0;
+    int32_t *rowid = nullptr, *seg = nullptr;
+    float* fsum = nullptr;
+    int32_t* part_off = nullptr;
+    uint8_t* pruned = nullptr;
+    double* tan2_dev = nullptr;
+    int64_t* seg_off_dev = nullptr;  // kSchemeSegments: dataset row offsets [p+1]
+    int32_t *part_of_row = nullptr, *phist = nullptr, *scan_tmp = nullptr;
+    int64_t phist_cap = 0;
+    uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    int32_t* radix_tmp = nullptr;
+    sky::EngineBuffers eng{};
+    uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;
+    int32_t *local_list = nullptr, *final_list = nullptr, *pos_tmp = nullptr, *count_tmp = nullptr;
+    // host copies
+    double* tan2_host = nullptr;
+    void* const* ev_begin = nullptr;
+    void* const* ev_end = nullptr;
+    int32_t ev_cap = 0;
+    int32_t ev_used = 0;
+    sky_info info{};
+};
+
+namespace sky {
+
+constexpr int32_t kMaxRows = 0x7FFFFFFF;
+constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset within 32 bits
+
+// Workspace bytes of a plan (0 if the sizes are invalid).
+size_t plan_bytes(int64_t n, int32_t d, int32_t scheme, int32_t p, int32_t m);
+// Carve a plan from ws and launch its partition step. scheme may be kSchemeSegments, with
+// seg_off_host = the p + 1 dataset row offsets (copied to the device before returning).
+sky_status plan_build(const float* x, int64_t n, int32_t d, int64_t ld, int32_t scheme, int32_t p,
+                      int32_t m, int32_t slice_dim, const int64_t* seg_off_host, void* ws,
+                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out);
+
+}  // namespace sky

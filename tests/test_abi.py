@@ -117,3 +117,35 @@ def test_sliced_workspace_holds_partition_histogram(lib):
             lib.sky_build_workspace_bytes(n, 4, C.byref(ang))
     too_many = _lib.SkyParams(_lib.SKY_SLICED, 5000, 0, 0)
     assert lib.sky_build_workspace_bytes(100000, 4, C.byref(too_many)) == 0
+
+
+def test_batch_arguments(lib):
+    I64 = C.c_int64
+    off = (I64 * 4)(0, 10, 10, 25)
+    assert lib.sky_batch_workspace_bytes(off, 3, 4) > 25 * 4 * 4
+    assert lib.sky_batch_workspace_bytes(off, 3, 0) == 0
+    assert lib.sky_batch_workspace_bytes(off, 3, 17) == 0
+    assert lib.sky_batch_workspace_bytes(None, 3, 4) == 0
+    assert lib.sky_batch_workspace_bytes(off, 0, 4) == 0
+    bad = (I64 * 4)(0, 10, 9, 25)      # decreasing
+    assert lib.sky_batch_workspace_bytes(bad, 3, 4) == 0
+    bad0 = (I64 * 4)(1, 10, 10, 25)    # must start at 0
+    assert lib.sky_batch_workspace_bytes(bad0, 3, 4) == 0
+    empty = (I64 * 3)(0, 0, 0)         # no rows at all
+    assert lib.sky_batch_workspace_bytes(empty, 2, 4) == 0
+    many = (I64 * 4098)(*range(4098))  # more relations than SKY_MAX_CELLS
+    assert lib.sky_batch_workspace_bytes(many, 4097, 2) == 0
+    fake = C.c_void_p(0x1000)
+    h = C.c_void_p()
+    E = _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_batch_create(fake, 4, 25, off, 3, fake, 1 << 30, fake, None, None) == E
+    assert lib.sky_batch_create(fake, 4, 24, off, 3, fake, 1 << 30, fake, None, C.byref(h)) == E
+    assert lib.sky_batch_create(fake, 4, 25, bad, 3, fake, 1 << 30, fake, None, C.byref(h)) == E
+    assert lib.sky_batch_create(fake, 4, 25, off, 3, fake, 16, fake, None,
+                                C.byref(h)) == _lib.SKY_ERR_WORKSPACE
+    assert h.value is None
+    assert lib.sky_batch_skylines(None, fake, 1, fake, None) == E
+    assert lib.sky_batch_tune(None, None, None) == E
+    assert lib.sky_batch_gres(None, 25, None, None, None, None, None) == E
+    assert lib.sky_batch_info(None, None) == E
+    lib.sky_batch_destroy(None)
