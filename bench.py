@@ -106,11 +106,20 @@ def main():
     ap.add_argument("--mapping", default="auto", choices=["auto", "tiles", "levels"])
     ap.add_argument("--cpu-rows", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rate", type=float, default=500.0, help="serve_ties: queries per second")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="serve_ties: trace length")
+    ap.add_argument("--budget-mb", type=int, default=256, help="serve_ties: HBM budget of queries")
+    ap.add_argument("--slots", type=int, default=4, help="serve_ties: concurrent query streams")
+    ap.add_argument("--no-plain", action="store_true", help="batch/serve: skip the plain path")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch_4096":
+        return bench_batch(args)
+    if args.workload == "serve_ties":
+        return bench_serve(args)
 
     import numpy as np
     import torch
@@ -213,6 +222,147 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, g_max, min(args.cpu_rows, n))
     pool.close()
+    print(json.dumps(line), flush=True)
+
+
+def _base_line(args, value, unit, ms, dtype, config, higher=True):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": higher,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def bench_batch(args):
+    """Many-dataset workload: 4096 relations (log-normal N in [1k, 200k], d in 2..8, uniform and
+    anticorrelated alternating, seed 0); one step = skyline and gres of every relation through
+    the batched path (groups by d, tuned work tables, graph-replayed gres launches)."""
+    import numpy as np
+    import torch
+    from paper_2412_02274_amd import datagen as G
+    from paper_2412_02274_amd.batch import BatchRunner, GresTuner, PlainRunner
+    from tests.golden import workloads as W
+
+    specs = G.batch_specs()
+    data = [G.batch_dataset(sp) for sp in specs]
+    dev = torch.device("cuda:0")
+    tuner = GresTuner()
+    run = BatchRunner(data, g_max=25, device=dev, tuner=tuner)
+    for _ in range(max(args.warmup, 1)):
+        run.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run.run(check=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for g in run.groups:
+        from paper_2412_02274_amd.api import check_status
+        check_status(g.status, "batch")
+    phases = run.phase_ms()
+    s_total = run.sky_total()
+    rows = sum(x.shape[0] for x in data)
+    counts = None
+    if os.path.exists(W.BATCH_COUNTS):
+        with open(W.BATCH_COUNTS) as f:
+            counts = json.load(f)
+        if counts["sky_total"] != s_total:
+            raise SystemExit(f"skyline total {s_total} differs from the oracle's {counts['sky_total']}")
+    line = _base_line(args, s_total / dt, "skyline tuples/s", dt * 1e3, "f32",
+                      {"workload": "batch_4096", "relations": len(data), "rows": rows,
+                       "d": "2..8", "kinds": "uni/ant alternating", "seed": 0, "g_max": 25})
+    line["rows_per_s"] = rows / dt
+    line["sky_total"] = s_total
+    line["phase_ms"] = phases
+    line["groups"] = [{"d": g.d, "relations": g.nb, "rows": g.n, "sky": g.sky_count,
+                       "rounds": (g.info or {}).get("rounds_local"), "tune": g.tune.as_dict()}
+                      for g in run.groups]
+    if counts is not None:
+        alg = sum(t * sp[1] for t, sp in zip(counts["sfs_tests"], specs))
+        ach = alg / (phases["skylines"] * 1e-3) / 1e12
+        line["algorithmic_sfs_tests"] = counts["sfs_total"]
+        line["roofline"] = {"kernel": "skyline phase (all kernels and syncs)", "bound": "alu",
+                            "achieved": ach, "peak": PEAK_ALU_TOPS, "unit": "TOP/s",
+                            "frac": ach / PEAK_ALU_TOPS, "traffic": None,
+                            "note": "oracle SFS tests x d element compares per relation, over the "
+                                    "whole skyline phase time of a step"}
+    if not args.no_plain:
+        plain = PlainRunner(data, g_max=25, device=dev)
+        for i in range(64):
+            plain.run_one(i)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plain.run()
+        pt = time.perf_counter() - t1
+        if sum(plain.counts) != s_total:
+            raise SystemExit("plain path skyline total differs")
+        line["plain"] = {"s_per_pass": pt, "tuples_per_s": s_total / pt,
+                         "note": "one launch sequence per relation, serialized (ingest, build, "
+                                 "local skylines, merge, gres_compute)"}
+        line["speedup_vs_plain"] = pt / dt
+    if not args.no_cpu_baseline:
+        import oracle
+        t2 = time.perf_counter()
+        tup, k = 0, 0
+        while time.perf_counter() - t2 < 15.0 and k < len(data):
+            mem, _ = oracle.skyline_sfs(data[k])
+            sky = np.flatnonzero(mem)
+            oracle.gres(data[k], sky, 25)
+            tup += len(sky)
+            k += 1
+        ct = time.perf_counter() - t2
+        line["cpu_baseline"] = {"value": tup / ct, "unit": "skyline tuples/s",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"the first {k} relations (SFS 1 thread + Alg. 1 gres "
+                                          f"OpenMP), {ct:.1f} s"}
+    run.close()
+    print(json.dumps(line), flush=True)
+
+
+SERVE_RELATIONS = [(n, d) for n in (20_000, 130_000, 2_000_000) for d in (5, 6, 7)]
+
+
+def bench_serve(args):
+    """Serving workload: 9 resident tie-heavy relations (N in {20k, 130k, 2M} x d in {5, 6, 7},
+    seeds 0..8); Poisson arrivals of gres queries (a relation, a random subset of its skyline,
+    g_max 25); continuous batching under an HBM budget against the plain one-at-a-time path on
+    the same arrivals."""
+    import torch
+    from paper_2412_02274_amd import datagen as G
+    from paper_2412_02274_amd.serve import (PlainServer, Resident, Server, latency_stats,
+                                            poisson_trace)
+
+    dev = torch.device("cuda:0")
+    residents = [Resident(G.ties(n, d, i), dev) for i, (n, d) in enumerate(SERVE_RELATIONS)]
+    srv = Server(residents, budget_bytes=args.budget_mb << 20, slots=args.slots, device=dev)
+    warm = poisson_trace(residents, rate=args.rate, duration=2.0, seed=1, start=10_000_000)
+    srv.run_trace(warm)
+    trace = poisson_trace(residents, rate=args.rate, duration=args.serve_seconds, seed=0)
+    done = srv.run_trace(trace)
+    st = latency_stats(done)
+    burst = poisson_trace(residents, rate=1e9, duration=1e-9 * 2000, seed=2)  # all at once
+    sat = latency_stats(Server(residents, budget_bytes=args.budget_mb << 20, slots=args.slots,
+                               device=dev).run_trace(burst))
+    line = _base_line(args, st["tuples_per_s"], "skyline tuples' gres/s", st["mean_ms"], "f32",
+                      {"workload": "serve_ties", "relations": [f"{n}x{d}" for n, d in SERVE_RELATIONS],
+                       "rate_per_s": args.rate, "seconds": args.serve_seconds, "g_max": 25,
+                       "budget_mb": args.budget_mb, "slots": args.slots})
+    line["steps"] = st["requests"]
+    line["latency"] = st
+    line["saturation"] = sat
+    line["resident_mb"] = sum(r.resident_bytes() for r in residents) / 2**20
+    line["sky_sizes"] = [r.s for r in residents]
+    line["max_in_flight"] = srv.max_in_flight
+    if not args.no_plain:
+        plain = PlainServer(residents, device=dev)
+        plain.run_trace(poisson_trace(residents, rate=args.rate, duration=1.0, seed=1))
+        pdone = plain.run_trace(poisson_trace(residents, rate=args.rate, duration=args.serve_seconds,
+                                              seed=0))
+        line["plain_latency"] = latency_stats(pdone)
+        line["plain_saturation"] = latency_stats(PlainServer(residents, device=dev).run_trace(
+            poisson_trace(residents, rate=1e9, duration=1e-9 * 2000, seed=2)))
+        mix = {q.qid: q.g_exit for q in done}
+        line["same_results_as_plain"] = all(
+            (q.g_exit == mix[q.qid]).all() for q in pdone)
     print(json.dumps(line), flush=True)
 
 

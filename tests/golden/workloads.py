@@ -8,6 +8,8 @@ in ascending row order, each search stopping at the first dominator. They depend
 order, so they are reported as the algorithmic work of a workload, never compared.
 
 Run:  python tests/golden/workloads.py [name ...]
+      python tests/golden/workloads.py batch      (the many-dataset workload: skyline sizes and
+                                                   SFS counts per relation, batch_counts.json)
 """
 from __future__ import annotations
 
@@ -65,5 +67,41 @@ def record(names):
             json.dump(out, f, indent=1, sort_keys=True)
 
 
+BATCH_COUNTS = os.path.join(HERE, "batch_counts.json")
+
+
+def _batch_one(spec):
+    import oracle
+    from paper_2412_02274_amd import datagen
+    x = datagen.batch_dataset(spec)
+    mem, tests = oracle.skyline_sfs(x)
+    return int(mem.sum()), int(tests)
+
+
+def record_batch(seed=0, workers=8):
+    """Skyline size and oracle SFS test count of every relation of the many-dataset workload
+    (relations in parallel processes, each single-threaded)."""
+    from multiprocessing import Pool
+    from paper_2412_02274_amd import datagen
+    specs = datagen.batch_specs(seed=seed)
+    order = sorted(range(len(specs)), key=lambda i: -specs[i][0] * specs[i][1])
+    t0 = time.time()
+    with Pool(workers) as pool:
+        res = pool.map(_batch_one, [specs[i] for i in order], chunksize=1)
+    sky = [0] * len(specs)
+    sfs = [0] * len(specs)
+    for i, (s, t) in zip(order, res):
+        sky[i], sfs[i] = s, t
+    out = {"seed": seed, "count": len(specs), "sky_size": sky, "sfs_tests": sfs,
+           "sky_total": int(sum(sky)), "sfs_total": int(sum(sfs)),
+           "oracle_seconds": round(time.time() - t0, 1), "processes": workers}
+    with open(BATCH_COUNTS, "w") as f:
+        json.dump(out, f)
+    print("batch", {k: v for k, v in out.items() if k not in ("sky_size", "sfs_tests")}, flush=True)
+
+
 if __name__ == "__main__":
-    record(sys.argv[1:] or list(WORKLOADS))
+    if sys.argv[1:] == ["batch"]:
+        record_batch()
+    else:
+        record(sys.argv[1:] or list(WORKLOADS))

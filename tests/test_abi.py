@@ -149,3 +149,19 @@ def test_batch_arguments(lib):
     assert lib.sky_batch_gres(None, 25, None, None, None, None, None) == E
     assert lib.sky_batch_info(None, None) == E
     lib.sky_batch_destroy(None)
+
+
+def test_serving_arena_first_fit():
+    from paper_2412_02274_amd.serve import Arena
+    a = Arena(4096, "cpu")
+    r1 = a.alloc(100)      # 256
+    r2 = a.alloc(1000)     # 1024
+    r3 = a.alloc(2000)     # 2048
+    assert r1 == (0, 256) and r2 == (256, 1024) and r3 == (1280, 2048)
+    assert a.alloc(1024) is None          # 768 left
+    a.release(r2)
+    assert a.alloc(1024) == (256, 1024)   # the freed range is reused
+    a.release(r1)
+    a.release((256, 1024))
+    a.release(r3)
+    assert a.free == [(0, 4096)] and a.used == 0  # neighbours merge back

@@ -215,6 +215,15 @@ def test_batch_full_workload_sampled(dev):
         pick = np.arange(len(want)) if len(want) <= 200 else rng.choice(len(want), 200, False)
         wge = oracle.gres_rows(x, want, want[pick], 25)
         assert np.array_equal(ge[pick], wge), i
+    # every relation's skyline size against the oracle's (recorded by tests/golden/workloads.py)
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batch_counts.json")
+    with open(path) as f:
+        want_sizes = json.load(f)["sky_size"]
+    for g in run.groups:
+        got = np.diff(g.sky_off.cpu().numpy())
+        assert np.array_equal(got, [want_sizes[i] for i in g.members]), g.d
     for g in run.groups:
         s = g.sky_count
         ge = g.g_exit[:s].cpu().numpy()
