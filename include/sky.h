@@ -97,7 +97,8 @@ typedef struct sky_info {
     int64_t pruned_rows;      /* Grid: rows inside pruned cells */
     int64_t local_count;      /* size of the union of the local skylines */
     int64_t sky_count;        /* size of the final skyline */
-    int64_t tests_local;      /* dominance tests evaluated in the local phase (counted on device) */
+    int64_t tests_local;      /* row-against-row dominance tests evaluated in the local phase
+                                 (counted on device; tile-box tests are not counted) */
     int64_t tests_merge;      /* dominance tests evaluated in the final phase */
     int64_t max_partition;    /* rows in the largest partition */
     int32_t events_used;      /* timing-hook event pairs recorded (sky_plan_set_events) */

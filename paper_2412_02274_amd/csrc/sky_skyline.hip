@@ -23,15 +23,17 @@
 // sequence; it is stored 64-aligned (values and positions) and cut into tiles of 64 with the
 // componentwise minimum `lo` and maximum `hi` of each tile. A tile can hold a dominator of t
 // only if lo <= t in every attribute; if moreover hi <= t everywhere and hi < t somewhere,
-// every row of the (non-empty) tile dominates t. So each test first checks 64 tile boxes per
-// ballot, decides at once when a box dominates, and otherwise tests only the candidates of
-// the surviving tiles (exact: no dominator is ever skipped, none is ever invented).
+// every row of the (non-empty) tile dominates t. So an item is tested against the candidates
+// of a tile only when the box allows a dominator there and does not already decide (exact: no
+// dominator is ever skipped, none is ever invented).
 //
-// Test kernels take one item at a time per wavefront: the 64 lanes test 64 candidates (or
-// 64 tile boxes) at once and a ballot ends the item at its first dominator, so no lane waits
-// behind another item. A workgroup caches the tile boxes of its current segment in LDS when
-// they fit (a barrier only when the segment changes).
-// Bound: VALU compares and L2 latency (candidate values are a few hundred KB per segment).
+// The test kernel is register-tiled like an n-body step: a wavefront holds 64 items (one per
+// lane) and walks the head tiles of their segment; each tile's box is tested against all items
+// at once, and each tile's 64 candidates are loaded once and tested against every item that
+// passed the box, with the item's values broadcast from its lane. One candidate load serves 64
+// items, so the loop is bound by compares, not by cache bandwidth. A workgroup caches the tile
+// boxes of its current segment in LDS when they fit (a barrier only when the segment changes).
+// Bound: VALU compares (candidate values are a few hundred KB per segment and stay in cache).
 #include "sky_internal.hpp"
 
 namespace sky {
@@ -41,13 +43,13 @@ namespace {
 constexpr int kHead = 8192;   // head rows per segment and round (target)
 constexpr int kTargetWaves = 8192;  // waves per test launch the item split aims at
 constexpr int kTile = 64;     // candidates per tile box
-constexpr int kBatch = 4;     // candidate tiles fetched per round trip
-constexpr uint32_t kPad = 0xFFFFFFFFu;  // value of padding candidates: never <= a real value
+constexpr uint32_t kPad = 0x7FFFFFFFu;  // padding candidates: above every real value, also as int32
 constexpr int kBoxLds = 4096;           // uint32 tile-box values cached in LDS per workgroup
 constexpr uint32_t kMaxGrid = 8192;     // workgroups of the grid-stride kernels
+constexpr int kDense = 32;              // items passing a tile's box from which the candidates are broadcast
 
 // seg_info layout per segment (int32 x kInfo)
-enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, kInfo = 8 };
+enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, SI_HEADPRE, kInfo = 8 };
 // global counters
 enum { C_NEXT = 0, C_OUT, C_HTILES, C_RTILES, C_MAXH, C_HTOT, C_RTOT, kCounters = 16 };
 
@@ -258,12 +260,12 @@ __global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32
 // Per segment: list offset (scan of live counts), 64-aligned head offset (scan of head counts
 // rounded up to 64), rest offset, and the item-tile offsets of both groups; round totals.
 // Single workgroup, sequential over blocks of 256 segments.
-__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32_t hitems,
-                                                              int32_t ritems,
+__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32_t tpu_h,
+                                                              int32_t tpu_r,
                                                               int32_t* __restrict__ info,
                                                               int32_t* __restrict__ tile_off,
                                                               int32_t* __restrict__ counters) {
-    constexpr int Q = 5;
+    constexpr int Q = 6;
     __shared__ int32_t carry[Q];
     __shared__ int32_t wsum[Q][kBlock / kWave];
     __shared__ int32_t wmax[kBlock / kWave];
@@ -277,16 +279,18 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
     const int wave = threadIdx.x / kWave;
     for (int base = 0; base < nseg; base += kBlock) {
         int32_t s = base + threadIdx.x;
-        int32_t v[Q] = {0, 0, 0, 0, 0};
+        int32_t v[Q] = {0, 0, 0, 0, 0, 0};
         int32_t hn = 0;
         if (s < nseg) {
             hn = info[s * kInfo + SI_HEADN];
             int32_t rn = info[s * kInfo + SI_RESTN];
             v[0] = (hn + kTile - 1) / kTile * kTile;    // aligned head slots
             v[1] = rn;                                   // rest items
-            v[2] = (hn + hitems - 1) / hitems;          // head item tiles
-            v[3] = (rn + ritems - 1) / ritems;          // rest item tiles
+            const int32_t ntile = (hn + kTile - 1) / kTile;
+            v[2] = (hn + kBlock - 1) / kBlock * ((ntile + tpu_h - 1) / tpu_h);  // head units
+            v[3] = (rn + kBlock - 1) / kBlock * ((ntile + tpu_r - 1) / tpu_r);  // rest units
             v[4] = info[s * kInfo + SI_LIVE];            // list items
+            v[5] = hn;                                   // head items (unaligned)
         }
         int32_t inc[Q];
         for (int q = 0; q < Q; ++q) {
@@ -314,6 +318,7 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
             info[s * kInfo + SI_HEADOFF] = excl[0];
             info[s * kInfo + SI_RESTOFF] = excl[1];
             info[s * kInfo + SI_LISTOFF] = excl[4];
+            info[s * kInfo + SI_HEADPRE] = excl[5];
             tile_off[s] = excl[2];
             tile_off[(nseg + 1) + s] = excl[3];
         }
@@ -336,41 +341,177 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
 }
 
 // is_head flag per list item (for the stable split)
-__global__ void __launch_bounds__(kBlock) head_flag_kernel(const int32_t* __restrict__ items, int32_t n,
-                                                            const float* __restrict__ fsum,
-                                                            const int32_t* __restrict__ seg_of_pos,
-                                                            const uint32_t* __restrict__ smin,
-                                                            const uint32_t* __restrict__ smax,
-                                                            const int32_t* __restrict__ info,
-                                                            int32_t* __restrict__ flag) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int32_t pos = items[i];
-    int32_t s = seg_of(seg_of_pos, pos);
-    flag[i] = item_bin(fsum, smin, smax, s, pos) <= info[s * kInfo + SI_BSTAR] ? 1 : 0;
+// ---- two-kernel stable compactions ---------------------------------------------------------
+// Blocks of kCItems consecutive list entries; kernel 1 counts the kept entries of every block,
+// kernel 2 gets its block's prefix by summing the counts of the blocks before it (no waiting on
+// other blocks), ranks entries inside the block with wave ballots over 64-entry chunks in
+// order, and scatters. The result is in list order (stable).
+constexpr int kCItems = 4096;
+constexpr int kCChunks = kCItems / kWave;  // 64 chunks of 64 entries
+
+// sum of cnt[0, b) by the whole block (every thread gets it)
+__device__ __forceinline__ int32_t block_prefix(const int32_t* __restrict__ cnt, int32_t b) {
+    __shared__ int32_t part[kBlock / kWave];
+    int32_t v = 0;
+    for (int32_t j = threadIdx.x; j < b; j += kBlock) v += cnt[j];
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    if (lane_id() == 0) part[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int32_t t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    __syncthreads();
+    return t;
 }
 
-// Stable split: the list is in position order, hence grouped by segment; hscan is the
-// exclusive scan of the head flags over the list.
-__global__ void __launch_bounds__(kBlock) split_kernel(const int32_t* __restrict__ items, int32_t n,
-                                                        const int32_t* __restrict__ seg_of_pos,
-                                                        const int32_t* __restrict__ info,
-                                                        const int32_t* __restrict__ flag,
-                                                        const int32_t* __restrict__ hscan,
-                                                        int32_t* __restrict__ head,
-                                                        int32_t* __restrict__ rest,
-                                                        uint8_t* __restrict__ dom) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int32_t pos = items[i];
-    const int32_t s = seg_of(seg_of_pos, pos);
-    const int32_t* si = info + s * kInfo;
-    const int32_t lo = si[SI_LISTOFF];
-    const int32_t hr = hscan[i] - hscan[lo];
-    if (flag[i]) head[si[SI_HEADOFF] + hr] = pos;
-    else rest[si[SI_RESTOFF] + (i - lo) - hr] = pos;
-    dom[pos] = 0;
+// in-order exclusive prefix of the kCChunks chunk counts of a block; chunk c of the block is
+// handled by wave c % 4 (entries b*kCItems + c*64 + lane)
+__device__ __forceinline__ void chunk_prefix(int32_t* chunk_cnt) {
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        const int lane = (int)lane_id();
+        int32_t v = chunk_cnt[lane];
+        int32_t inc = v;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        chunk_cnt[lane] = inc - v;
+    }
+    __syncthreads();
 }
+
+__device__ __forceinline__ bool is_head(const int32_t* items, int32_t i, const float* fsum,
+                                        const int32_t* seg_of_pos, const uint32_t* smin,
+                                        const uint32_t* smax, const int32_t* info, int32_t& pos,
+                                        int32_t& s) {
+    pos = items[i];
+    s = seg_of(seg_of_pos, pos);
+    return item_bin(fsum, smin, smax, s, pos) <= info[s * kInfo + SI_BSTAR];
+}
+
+__global__ void __launch_bounds__(kBlock) split_count_kernel(
+    const int32_t* __restrict__ items, int32_t n, const float* __restrict__ fsum,
+    const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
+    const uint32_t* __restrict__ smax, const int32_t* __restrict__ info, int32_t* __restrict__ bcnt) {
+    __shared__ int32_t part[kBlock / kWave];
+    const int wave = threadIdx.x / kWave;
+    const int lane = (int)lane_id();
+    int32_t c = 0;
+    for (int ch = wave; ch < kCChunks; ch += kBlock / kWave) {
+        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
+        int32_t pos, s;
+        const bool h = i < n && is_head(items, i, fsum, seg_of_pos, smin, smax, info, pos, s);
+        c += __popcll(__builtin_amdgcn_ballot_w64(h));
+    }
+    if (lane == 0) part[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+        bcnt[blockIdx.x] = t;
+    }
+}
+
+// head entries -> their segment's head group, the others -> its rest group, both in list order;
+// every item's dominated flag is cleared
+__global__ void __launch_bounds__(kBlock) split_scatter_kernel(
+    const int32_t* __restrict__ items, int32_t n, const float* __restrict__ fsum,
+    const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
+    const uint32_t* __restrict__ smax, const int32_t* __restrict__ info,
+    const int32_t* __restrict__ bcnt, int32_t* __restrict__ head, int32_t* __restrict__ rest,
+    uint8_t* __restrict__ dom) {
+    __shared__ int32_t chunk_cnt[kCChunks];
+    const int wave = threadIdx.x / kWave;
+    const int lane = (int)lane_id();
+    const int32_t pre = block_prefix(bcnt, blockIdx.x);
+    constexpr int kPer = kCChunks / (kBlock / kWave);
+    int32_t mpos[kPer], mseg[kPer];
+    uint64_t mball[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int ch = wave + q * (kBlock / kWave);
+        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
+        int32_t pos = 0, sg = 0;
+        const bool h = i < n && is_head(items, i, fsum, seg_of_pos, smin, smax, info, pos, sg);
+        mpos[q] = i < n ? pos : -1;
+        mseg[q] = sg;
+        mball[q] = __builtin_amdgcn_ballot_w64(h);
+        if (lane == 0) chunk_cnt[ch] = __popcll(mball[q]);
+    }
+    chunk_prefix(chunk_cnt);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int ch = wave + q * (kBlock / kWave);
+        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
+        if (mpos[q] < 0) continue;
+        const bool h = (mball[q] >> lane) & 1ull;
+        // head items before i in the whole list, minus those of earlier segments
+        const int32_t hscan = pre + chunk_cnt[ch] + __popcll(mball[q] & __lanemask_lt());
+        const int32_t* si = info + mseg[q] * kInfo;
+        const int32_t hr = hscan - si[SI_HEADPRE];
+        if (h) head[si[SI_HEADOFF] + hr] = mpos[q];
+        else rest[si[SI_RESTOFF] + (i - si[SI_LISTOFF]) - hr] = mpos[q];
+        dom[mpos[q]] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) rest_count_kernel(const int32_t* __restrict__ rest,
+                                                             const int32_t* __restrict__ counters,
+                                                             const uint8_t* __restrict__ dom,
+                                                             int32_t* __restrict__ bcnt) {
+    __shared__ int32_t part[kBlock / kWave];
+    const int32_t n = counters[C_RTOT];
+    const int wave = threadIdx.x / kWave;
+    const int lane = (int)lane_id();
+    int32_t c = 0;
+    for (int ch = wave; ch < kCChunks; ch += kBlock / kWave) {
+        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
+        c += __popcll(__builtin_amdgcn_ballot_w64(i < n && dom[rest[i]] == 0));
+    }
+    if (lane == 0) part[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+        bcnt[blockIdx.x] = t;
+    }
+}
+
+// survivors of the rest groups, in order, into the next work list; the last block writes the
+// total into counters[C_NEXT]
+__global__ void __launch_bounds__(kBlock) rest_scatter_kernel(const int32_t* __restrict__ rest,
+                                                               int32_t* __restrict__ counters,
+                                                               const uint8_t* __restrict__ dom,
+                                                               const int32_t* __restrict__ bcnt,
+                                                               int32_t* __restrict__ next) {
+    __shared__ int32_t chunk_cnt[kCChunks];
+    const int32_t n = counters[C_RTOT];
+    const int wave = threadIdx.x / kWave;
+    const int lane = (int)lane_id();
+    const int32_t pre = block_prefix(bcnt, blockIdx.x);
+    constexpr int kPer = kCChunks / (kBlock / kWave);
+    int32_t mpos[kPer];
+    uint64_t mball[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int ch = wave + q * (kBlock / kWave);
+        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
+        const int32_t pos = i < n ? rest[i] : -1;
+        mpos[q] = pos;
+        mball[q] = __builtin_amdgcn_ballot_w64(pos >= 0 && dom[pos] == 0);
+        if (lane == 0) chunk_cnt[ch] = __popcll(mball[q]);
+    }
+    chunk_prefix(chunk_cnt);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int ch = wave + q * (kBlock / kWave);
+        if ((mball[q] >> lane) & 1ull)
+            next[pre + chunk_cnt[ch] + __popcll(mball[q] & __lanemask_lt())] = mpos[q];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) counters[C_NEXT] = pre + bcnt[blockIdx.x];
+}
+
+
 
 // largest s with info[s].field <= v (the field ascending in s)
 __device__ __forceinline__ int32_t find_segment(const int32_t* info, int32_t nseg, int field,
@@ -433,97 +574,49 @@ __device__ __forceinline__ int32_t tile_segment(const int32_t* tile_off, int32_t
 }
 
 // One item t (values tv, uniform across the wave) against the head group of its segment:
-// returns true when some head row dominates t. Lanes test 64 tile boxes per step (from LDS
-// when cached, else from global memory), then up to kBatch passing tiles per round trip.
-// All loads are unconditional: lanes past the end read the padding slot (all ones, never a
-// dominator), so the loop has no divergent branches. Addresses are a wave-uniform base per
-// attribute plus an unsigned 32-bit lane offset.
-template <int DM, bool kLds>
-__device__ __forceinline__ bool dominated_in_head(const uint32_t* tv, int d, const uint32_t* box,
-                                                  const uint32_t* __restrict__ hlo,
-                                                  const uint32_t* __restrict__ hhi, int64_t tcap,
-                                                  uint32_t t0, const uint32_t* __restrict__ hval,
-                                                  int64_t hcap, uint32_t hoff, int32_t ntile,
-                                                  uint32_t padslot, unsigned long long& ntests) {
-    const int lane = (int)lane_id();
-    const int32_t nb = ntile * d;
-    for (int32_t c = 0; c < ntile; c += kWave) {
-        const int32_t tl = c + lane;
-        const bool inr = tl < ntile;
-        const uint32_t ti = inr ? (uint32_t)tl : 0u;
-        bool pass = inr, hle = true, hlt = false;
-#pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k < d) {
-                const uint32_t lo = kLds ? box[k * ntile + ti] : ld32(hlo + k * tcap, t0 + ti);
-                const uint32_t hi = kLds ? box[nb + k * ntile + ti] : ld32(hhi + k * tcap, t0 + ti);
-                pass &= lo <= tv[k];
-                hle &= hi <= tv[k];
-                hlt |= hi < tv[k];
-            }
-        ntests += kWave;  // 64 box tests
-        // a non-empty tile whose upper corner dominates t: every row of it dominates t
-        if (__ballot(pass && hle && hlt)) return true;
-        uint64_t mask = __ballot(pass);
-        while (mask) {
-            uint32_t jb[kBatch];
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                jb[b] = padslot + (uint32_t)lane;
-                if (mask) {
-                    const int tb = __ffsll((unsigned long long)mask) - 1;
-                    mask &= mask - 1;
-                    jb[b] = hoff + (uint32_t)(c + tb) * kTile + (uint32_t)lane;
-                    ntests += kTile;  // 64 candidate tests
-                }
-            }
-            uint32_t cv[kBatch][DM];
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) cv[b][k] = ld32(hval + k * hcap, jb[b]);
-            bool dm = false;
-#pragma unroll
-            for (int b = 0; b < kBatch; ++b) {
-                bool le = true, lt = false;
-#pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) {
-                        le &= cv[b][k] <= tv[k];
-                        lt |= cv[b][k] < tv[k];
-                    }
-                dm |= le && lt;
-            }
-            if (__ballot(dm)) return true;
-        }
-    }
-    return false;
-}
-
-// Items of one segment tile (ipw items per wave, 4 waves) against the head group of the
-// segment; ipw <= 64 shrinks with the item count so that small rounds still fill the chip.
+// Dominance tests of items against the head group of their segment, register-tiled.
+// A work unit is (segment, a group of 256 items -- 64 per wave, one per lane --, a range of
+// the segment's head tiles). For every tile of the range a wave
+//   1. tests the tile's box against all its live items at once (lane = item): a tile can hold a
+//      dominator of t only if lo <= t everywhere, and if hi <= t everywhere with hi < t
+//      somewhere every row of the (non-empty) tile dominates t;
+//   2. loads the tile's 64 candidates once (lane = candidate) and tests every item that passed
+//      the box against all of them: the item's values are broadcast from its lane, and
+//      s dominates t iff max_k(s_k - t_k) <= 0 and min_k(s_k - t_k) < 0 on the bit patterns as
+//      signed integers (canonical values of [0, 1) are below 2^30, so the differences are
+//      exact; padding slots hold 0x7FFFFFFF, whose differences are positive).
+// One candidate load serves 64 items, so the loop is compute-bound. When a group's tiles are
+// split over several units, waves share deaths through dom[] every few tiles.
 // mode 0: items = the head group itself; mode 1: items = the rest group. A dominated item
 // gets dom[pos] = 1.
 template <int D>
 __global__ void __launch_bounds__(kBlock) test_kernel(
-    int mode, const float* __restrict__ xp, int64_t ldp, int32_t d_rt, int32_t nseg,
-    const int32_t* __restrict__ tile_off, const int32_t* __restrict__ info,
-    const int32_t* __restrict__ items_all, const uint32_t* __restrict__ hval, int64_t hcap,
-    const uint32_t* __restrict__ hlo, const uint32_t* __restrict__ hhi, int64_t tcap, int32_t ipw,
+    const float* __restrict__ xp, int64_t ldp, int32_t d_rt, int32_t nseg,
+    const int32_t* __restrict__ unit_off_all, const int32_t* __restrict__ info,
+    const int32_t* __restrict__ head, const int32_t* __restrict__ rest,
+    const uint32_t* __restrict__ hval, int64_t hcap, const uint32_t* __restrict__ hlo,
+    const uint32_t* __restrict__ hhi, int64_t tcap, int32_t tpu_h, int32_t tpu_r,
     uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     __shared__ uint32_t box[kBoxLds];  // [2][k][ntile] tile boxes (lo, hi) of the current segment
+    __shared__ int32_t itemv[kBlock / kWave][kWave][DM];  // each wave's items, for broadcasts
+    __shared__ int32_t candv[kBlock / kWave][kWave][DM];  // each wave's current tile (dense case)
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
-    const int32_t* toff = tile_off + (mode == 0 ? 0 : (nseg + 1));
-    const int32_t ntiles_items = toff[nseg];
-    const uint32_t padslot = (uint32_t)(hcap - kTile);
+    const int32_t nunits_h = unit_off_all[nseg];
+    const int32_t nunits = nunits_h + unit_off_all[(nseg + 1) + nseg];
     int32_t cached = -1;  // segment whose boxes are in LDS (uniform per workgroup)
-    unsigned long long ntests = 0;
-    for (int32_t t = blockIdx.x; t < ntiles_items; t += gridDim.x) {
-        const int32_t s = tile_segment(toff, nseg, t);
+    unsigned long long ntests_h = 0, ntests_r = 0;
+    for (int32_t ug = blockIdx.x; ug < nunits; ug += gridDim.x) {
+        // head units first (few items, latency-bound), then rest units
+        const int mode = ug < nunits_h ? 0 : 1;
+        const int32_t u = mode == 0 ? ug : ug - nunits_h;
+        const int32_t* uoff = unit_off_all + (mode == 0 ? 0 : (nseg + 1));
+        const int32_t tpu = mode == 0 ? tpu_h : tpu_r;
+        const int32_t* items_all = mode == 0 ? head : rest;
+        unsigned long long ntests = 0;
+        const int32_t s = tile_segment(uoff, nseg, u);
         const int32_t* si = info + s * kInfo;
         const int32_t hoff = si[SI_HEADOFF];
         const int32_t hn = si[SI_HEADN];
@@ -541,38 +634,127 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
             __syncthreads();
             cached = s;
         }
+        const int32_t nr = (ntile + tpu - 1) / tpu;  // tile ranges per item group
+        const int32_t lu = u - uoff[s];
+        const int32_t grp = lu / nr;
+        const int32_t c0 = (lu - grp * nr) * tpu;
+        const int32_t span = ntile - c0 < tpu ? ntile - c0 : tpu;
         const int32_t ioff = mode == 0 ? hoff : si[SI_RESTOFF];
         const int32_t icnt = mode == 0 ? hn : si[SI_RESTN];
-        const int32_t ibase = (t - toff[s]) * (ipw * (kBlock / kWave)) + wave * ipw;
-        const int32_t nmine = icnt - ibase < ipw ? (icnt - ibase > 0 ? icnt - ibase : 0) : ipw;
-        // lane i holds item i of this wave
-        const bool have = lane < nmine;
+        const int32_t ibase = grp * kBlock + wave * kWave;
+        const bool have = ibase + lane < icnt;
         const uint32_t myidx = (uint32_t)(ioff + ibase + (have ? lane : 0));
-        const uint32_t mypos = have ? (uint32_t)items_all[myidx] : 0u;
-        uint32_t mv[DM];
+        const int32_t mypos = have ? items_all[myidx] : 0;
+        int32_t tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
-            if (k < d)
-                mv[k] = !have ? 0u
-                              : (mode == 0 ? ld32(hval + k * hcap, myidx)
-                                           : ld32(reinterpret_cast<const uint32_t*>(xp) + k * ldp, mypos));
-        uint64_t todo = __ballot(have && dom[mypos] == 0);
-        while (todo) {
-            const int i = __ffsll((unsigned long long)todo) - 1;
-            todo &= todo - 1;
-            uint32_t tv[DM];
+            if (k < d) {
+                tv[k] = !have ? 0
+                              : (int32_t)(mode == 0 ? ld32(hval + k * hcap, myidx)
+                                                    : ld32(reinterpret_cast<const uint32_t*>(xp) + k * ldp,
+                                                           (uint32_t)mypos));
+                itemv[wave][lane][k] = tv[k];
+            }
+        __builtin_amdgcn_wave_barrier();  // the broadcasts below read other lanes' items
+        const uint64_t born = __builtin_amdgcn_ballot_w64(have && dom[mypos] == 0);
+        uint64_t live = born, written = 0;
+        // the head group's own tile first (its rows' nearest neighbours on the curve)
+        int32_t start = 0;
+        if (mode == 0 && nr == 1) start = (ibase / kTile) % ntile;
+        for (int32_t step = 0; step < span && live; ++step) {
+            int32_t c = start + step;
+            c = c < span ? c : c - span;
+            c += c0;
+            // 1. box of tile c against every live item (lane = item)
+            bool pass = (live >> lane) & 1ull, hle = true, hlt = false;
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d) tv[k] = __shfl(mv[k], i, kWave);
-            const bool found =
-                in_lds ? dominated_in_head<DM, true>(tv, d, box, hlo, hhi, tcap, (uint32_t)t0, hval, hcap,
-                                                     (uint32_t)hoff, ntile, padslot, ntests)
-                       : dominated_in_head<DM, false>(tv, d, box, hlo, hhi, tcap, (uint32_t)t0, hval,
-                                                      hcap, (uint32_t)hoff, ntile, padslot, ntests);
-            if (found && lane == i) dom[mypos] = 1;
+                if (k < d) {
+                    const int32_t lo = (int32_t)(in_lds ? box[k * ntile + c] : hlo[(int64_t)k * tcap + t0 + c]);
+                    const int32_t hi = (int32_t)(in_lds ? box[nb + k * ntile + c] : hhi[(int64_t)k * tcap + t0 + c]);
+                    pass &= lo <= tv[k];
+                    hle &= hi <= tv[k];
+                    hlt |= hi < tv[k];
+                }
+            live &= ~__builtin_amdgcn_ballot_w64(pass && hle && hlt);
+            uint64_t todo = __builtin_amdgcn_ballot_w64(pass) & live;
+            if (todo) {
+                // 2. the tile's candidates (lane = candidate) against every item that passed
+                const uint32_t slot = (uint32_t)((t0 + c) * kTile + lane);
+                int32_t cv[DM];
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) cv[k] = (int32_t)ld32(hval + k * hcap, slot);
+                const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
+                ntests += (unsigned long long)__popcll(todo) * (unsigned long long)creal;
+                if (__popcll(todo) >= kDense) {
+                    // dense: lanes keep their items and the candidates are broadcast one by
+                    // one from LDS; no per-item scalar work (padding candidates never dominate)
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) candv[wave][lane][k] = cv[k];
+                    __builtin_amdgcn_wave_barrier();
+                    int32_t acc = 0;
+#pragma unroll 4
+                    for (int j = 0; j < creal; ++j) {
+                        int32_t mx = INT32_MIN, mn = INT32_MAX;
+#pragma unroll
+                        for (int k = 0; k < DM; ++k)
+                            if (k < d) {
+                                const int32_t e = candv[wave][j][k] - tv[k];
+                                mx = e > mx ? e : mx;
+                                mn = e < mn ? e : mn;
+                            }
+                        acc |= (mx - 1) & mn;  // sign bit: candidate j dominates this lane's item
+                    }
+                    __builtin_amdgcn_wave_barrier();  // candv is rewritten by the next tile
+                    live &= ~(__builtin_amdgcn_ballot_w64(acc < 0) & todo);
+                    todo = 0;
+                }
+                // item values come from LDS as broadcasts; the next item's are fetched while the
+                // current one is tested
+                int i = todo ? __ffsll((unsigned long long)todo) - 1 : 0;
+                int32_t ts[DM];
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) ts[k] = itemv[wave][i][k];
+                while (todo) {
+                    todo &= todo - 1;
+                    const int inext = todo ? __ffsll((unsigned long long)todo) - 1 : i;
+                    int32_t tn[DM];
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) tn[k] = itemv[wave][inext][k];
+                    int32_t mx = INT32_MIN, mn = INT32_MAX;
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) {
+                            const int32_t e = cv[k] - ts[k];
+                            mx = e > mx ? e : mx;
+                            mn = e < mn ? e : mn;
+                        }
+                    // mx <= 0 and mn < 0  <=>  the sign bit of (mx - 1) & mn is set
+                    if (__builtin_amdgcn_ballot_w64(((mx - 1) & mn) < 0)) live &= ~(1ull << i);
+                    if (!todo) break;
+                    i = inext;
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) ts[k] = tn[k];
+                }
+            }
+            if (nr > 1 && (step & 7) == 7) {
+                // share deaths with the units testing the same items on other tiles
+                const uint64_t newly = born & ~live & ~written;
+                if ((newly >> lane) & 1ull) dom[mypos] = 1;
+                written |= newly;
+                live &= ~__builtin_amdgcn_ballot_w64(have && dom[mypos] != 0);
+            }
         }
+        if ((((born & ~live & ~written) >> lane) & 1ull) != 0) dom[mypos] = 1;
+        if (mode == 0) ntests_h += ntests; else ntests_r += ntests;
     }
-    if (lane == 0 && ntests) atomicAdd(&tests[mode], ntests);
+    if (lane == 0 && ntests_h) atomicAdd(&tests[0], ntests_h);
+    if (lane == 0 && ntests_r) atomicAdd(&tests[1], ntests_r);
 }
 
 // Head survivors -> output flags and output list (order irrelevant).
@@ -597,27 +779,7 @@ __global__ void __launch_bounds__(kBlock) compact_head_kernel(
     }
 }
 
-// keep flags of the rest items for i < n_bound (0 beyond the rest count)
-__global__ void __launch_bounds__(kBlock) rest_flag_kernel(const int32_t* __restrict__ rest,
-                                                            const int32_t* __restrict__ counters,
-                                                            const uint8_t* __restrict__ dom,
-                                                            int32_t n_bound, int32_t* __restrict__ flag) {
-    const int32_t rtot = counters[C_RTOT];
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n_bound; i += gridDim.x * kBlock)
-        flag[i] = (i < rtot && dom[rest[i]] == 0) ? 1 : 0;
-}
 
-__global__ void __launch_bounds__(kBlock) rest_compact_kernel(const int32_t* __restrict__ rest,
-                                                               int32_t* __restrict__ counters,
-                                                               const int32_t* __restrict__ flag,
-                                                               const int32_t* __restrict__ scan,
-                                                               int32_t* __restrict__ next) {
-    const int32_t n = counters[C_RTOT];
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        if (flag[i]) next[scan[i]] = rest[i];
-        if (i == n - 1) counters[C_NEXT] = scan[i] + flag[i];
-    }
-}
 
 // the padding slots at the end of the head buffer: all ones in every attribute
 __global__ void pad_slots_kernel(uint32_t* __restrict__ hval, int64_t hcap, int32_t d) {
@@ -785,24 +947,30 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         }
         hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)nseg), dim3(kWave), 0, st, nseg,
                            (const int32_t*)b.hist, b.seg_info);
-        // items per wave: enough waves to fill the chip (kTargetWaves), at most 64
-        auto ipw_for = [](int64_t items) -> int32_t {
-            int64_t v = ceil_div(items, kTargetWaves);
-            return (int32_t)(v < 1 ? 1 : (v > kWave ? kWave : v));
-        };
+        // tiles per unit: split the head tiles of an item group over several units when there
+        // are too few item groups to fill the chip (kTargetWaves waves)
         const int64_t head_est = (int64_t)nseg * kHead < live ? (int64_t)nseg * kHead : live;
-        const int32_t ipw_h = ipw_for(head_est), ipw_r = ipw_for(live);
-        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg,
-                           ipw_h * (kBlock / kWave), ipw_r * (kBlock / kWave), b.seg_info,
-                           b.tile_off, b.counters);
-        hipLaunchKernelGGL(head_flag_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+        int64_t ntile_est = ceil_div(live, (int64_t)kTile * nseg) + 1;
+        if (ntile_est > kHead / kTile + 2) ntile_est = kHead / kTile + 2;
+        auto tpu_for = [&](int64_t items) -> int32_t {
+            const int64_t groups = ceil_div(items, kBlock) + nseg;
+            const int64_t want = kTargetWaves / (kBlock / kWave);
+            int64_t t = ceil_div(groups * ntile_est, want);
+            return (int32_t)(t < 1 ? 1 : (t > (1 << 20) ? (1 << 20) : t));
+        };
+        const int32_t tpu_h = tpu_for(head_est), tpu_r = tpu_for(live);
+        auto units_est = [&](int64_t items, int32_t tpu) -> int64_t {
+            return (ceil_div(items, kBlock) + nseg) * ceil_div(ntile_est, tpu);
+        };
+        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg, tpu_h, tpu_r,
+                           b.seg_info, b.tile_off, b.counters);
+        const uint32_t cblocks = (uint32_t)ceil_div(live, kCItems);
+        hipLaunchKernelGGL(split_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
                            pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                           (const int32_t*)b.seg_info, b.flag);
-        SKY_HIP(hipGetLastError());
-        SKY_TRY(launch_exclusive_scan(b.flag, b.scan, live, b.scan_tmp, st));
-        hipLaunchKernelGGL(split_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.seg_of_pos,
-                           (const int32_t*)b.seg_info, (const int32_t*)b.flag, (const int32_t*)b.scan,
-                           b.head, b.rest, b.dom);
+                           (const int32_t*)b.seg_info, b.scan);
+        hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+                           pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
+                           (const int32_t*)b.seg_info, (const int32_t*)b.scan, b.head, b.rest, b.dom);
         SKY_HIP(hipGetLastError());
         // grid sizes from host-side bounds; the kernels read the exact counts on the device
         auto grid = [](int64_t want) -> uint32_t {
@@ -813,34 +981,24 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                        dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.seg_info,
                        (const int32_t*)b.counters, b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
         SKY_HIP(hipGetLastError());
-        // head skyline: every head row against the head rows of its segment
+        // one launch: the head skyline (every head row against the head rows of its segment)
+        // and the filter of the rest against the same head rows -- independent tests
         SKY_HIP(ev_rec(true));
-        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(ceil_div(head_est, ipw_h * (kBlock / kWave)) + nseg)),
-                       dim3(kBlock), 0, st, 0, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
-                       (const int32_t*)b.seg_info, (const int32_t*)b.head, (const uint32_t*)b.hval,
-                       b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi, b.tcap, ipw_h, b.dom,
-                       b.tests);
+        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(units_est(head_est, tpu_h) + units_est(live, tpu_r))),
+                       dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
+                       (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.rest,
+                       (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi,
+                       b.tcap, tpu_h, tpu_r, b.dom, b.tests);
         SKY_HIP(ev_rec(false));
         hipLaunchKernelGGL(compact_head_kernel, dim3(grid(ceil_div(slot_bound, kBlock))), dim3(kBlock), 0,
                            st, (const int32_t*)b.head, (const int32_t*)b.counters,
                            (const uint8_t*)b.dom, pb.flag_out, out_list, b.counters + C_OUT);
         SKY_HIP(hipGetLastError());
-        // filter the rest against the head rows of its segment
-        SKY_HIP(ev_rec(true));
-        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(ceil_div(live, ipw_r * (kBlock / kWave)) + nseg)),
-                       dim3(kBlock), 0, st, 1, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
-                       (const int32_t*)b.seg_info, (const int32_t*)b.rest, (const uint32_t*)b.hval,
-                       b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi, b.tcap, ipw_r, b.dom,
-                       b.tests);
-        SKY_HIP(ev_rec(false));
-        hipLaunchKernelGGL(rest_flag_kernel, dim3(grid(ceil_div(live, kBlock))), dim3(kBlock), 0, st,
-                           (const int32_t*)b.rest, (const int32_t*)b.counters, (const uint8_t*)b.dom,
-                           live, b.flag);
-        SKY_HIP(hipGetLastError());
-        SKY_TRY(launch_exclusive_scan(b.flag, b.scan, live, b.scan_tmp, st));
-        hipLaunchKernelGGL(rest_compact_kernel, dim3(grid(ceil_div(live, kBlock))), dim3(kBlock), 0, st,
-                           (const int32_t*)b.rest, b.counters, (const int32_t*)b.flag,
-                           (const int32_t*)b.scan, next);
+        // the survivors of the rest groups, in order, are the next round's work list
+        hipLaunchKernelGGL(rest_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, (const int32_t*)b.rest,
+                           (const int32_t*)b.counters, (const uint8_t*)b.dom, b.scan);
+        hipLaunchKernelGGL(rest_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, (const int32_t*)b.rest,
+                           b.counters, (const uint8_t*)b.dom, (const int32_t*)b.scan, next);
         SKY_HIP(hipGetLastError());
         int32_t cnt[kCounters];
         SKY_HIP(hipMemcpyAsync(cnt, b.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
