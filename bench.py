@@ -60,22 +60,27 @@ class HipEvents:
         self.ev = []
 
 
-def stored_traffic(workload, kernel_src):
-    """HBM bytes per step of the dominance-test kernel from the committed PMC summary
-    (profiles/traffic_<workload>.txt), or None when the kernel source changed since."""
+def stored_traffic(workload):
+    """HBM bytes per step of the dominance-test kernel and per launch of the gres search kernel
+    from the committed PMC summary (profiles/traffic_<workload>.txt); each is None when its
+    kernel source changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    out = {"dominance_test": None, "gres_search": None}
     if not os.path.exists(path):
-        return None
+        return out
     kv = {}
     for line in open(path):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
-    if kv.get("src_sha256_16") != sha:
-        return None
-    return int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])
+    csrc = os.path.join(ROOT, "paper_2412_02274_amd", "csrc")
+    sha = lambda f: hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+    if kv.get("src_sha256_16") == sha("sky_skyline.hip"):
+        out["dominance_test"] = int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])
+    if "gres_search_fetch_bytes" in kv and kv.get("gres_search_src_sha256_16") == sha("sky_gres.hip"):
+        out["gres_search"] = int(kv["gres_search_fetch_bytes"]) + int(kv["gres_search_write_bytes"])
+    return out
 
 
 def cpu_baseline(x, g_max, rows):
@@ -162,37 +167,56 @@ def main():
     if s != counts["sky_size"]:
         raise SystemExit(f"skyline size {s} differs from the oracle's {counts['sky_size']}")
     # per-phase breakdown (one more, separately timed run)
-    pipe.run(xr, timing=True)
+    gres_counter = torch.zeros(1, dtype=torch.int64, device=dev)
+    pipe.run(xr, timing=True, gres_counter=gres_counter)
     phases = pipe.phase_ms()
+    gres_executed = int(gres_counter.item())
     info = pipe.last_info
     tests = counts["sfs_tests"] + counts["gres_tests"]
     executed = info["tests_local"] + info["tests_merge"]
     ops_per_test = 2 * d  # the kernel's one <= and one < comparison per attribute (Def. 1)
     test_tops = executed * ops_per_test / (test_ms * 1e-3) / 1e12
-    # roofline of the dominant kernel: algorithmic work is the oracle-order SFS test count x d
-    # element compares per test, over the kernel's own event time (the average launch is the
-    # same ratio: per-step work / per-step time over `launches` launches)
-    alg_ops = counts["sfs_tests"] * d
-    alg_tops = alg_ops / (test_ms * 1e-3) / 1e12
-    traffic_step = stored_traffic(args.workload, os.path.join(
-        ROOT, "paper_2412_02274_amd", "csrc", "sky_skyline.hip"))
+    # rooflines: algorithmic work per launch over the kernel's average HIP-event launch time.
+    # Dominance tests: oracle-order SFS test count x d element compares; gres search: Alg. 1's
+    # per-tuple descending-scan test count x d key compares. Reported for both kernels; the
+    # `roofline` field is the one of the kernel that takes the most time per step.
+    traffic = stored_traffic(args.workload)
     kernels = {
         "dominance_test": {"ms_per_step": test_ms, "launches_per_step": launches,
                            "executed_tests_per_step": executed, "ops_per_executed_test": ops_per_test,
                            "executed_TOPs": test_tops},
         "gres_search": {"ms_per_step": gres_ms, "launches_per_step": 1,
-                        "alg_tests_per_step": counts["gres_tests"],
-                        "alg_TOPs": counts["gres_tests"] * d / (gres_ms * 1e-3) / 1e12},
+                        "executed_tests_per_step": gres_executed,
+                        "ops_per_executed_test": 3 * d},
     }
-    roofline = {"kernel": "dominance_test", "bound": "alu", "achieved": alg_tops,
-                "peak": PEAK_ALU_TOPS, "unit": "TOP/s", "frac": alg_tops / PEAK_ALU_TOPS,
-                "traffic": None if traffic_step is None else traffic_step / launches,
-                "launches_per_step": launches, "avg_launch_us": test_ms * 1e3 / launches,
-                "alg_ops_per_launch": alg_ops / launches,
-                "note": "achieved = oracle-order SFS dominance tests x d element compares per "
-                        "launch / the kernel's average HIP-event launch time; peak = 256 CUs x 64 "
-                        "lanes x 2.4 GHz 32-bit VALU lane-ops; traffic = PMC FETCH_SIZE+WRITE_SIZE "
-                        "bytes per launch (calibrated), null when the kernel changed since"}
+
+    def roof(name, alg_tests, ms, nl, traffic_step, executed_ops):
+        alg_ops = alg_tests * d
+        ach = alg_ops / (ms * 1e-3) / 1e12
+        exe = executed_ops / (ms * 1e-3) / 1e12
+        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": PEAK_ALU_TOPS,
+                "unit": "TOP/s", "frac": ach / PEAK_ALU_TOPS,
+                "traffic": None if traffic_step is None else traffic_step / nl,
+                "launches_per_step": nl, "avg_launch_us": ms * 1e3 / nl,
+                "alg_ops_per_launch": alg_ops / nl,
+                "executed_TOPs": exe, "executed_frac": exe / PEAK_ALU_TOPS}
+
+    # executed ops: a dominance test compares 2d values (<= and <); a gres candidate test
+    # multiplies d values by g and compares each product with two thresholds
+    roofs = {"dominance_test": roof("dominance_test", counts["sfs_tests"], test_ms, launches,
+                                    traffic["dominance_test"], executed * ops_per_test),
+             "gres_search": roof("gres_search", counts["gres_tests"], gres_ms, 1,
+                                 traffic["gres_search"], gres_executed * 3 * d)}
+    dominant = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    roofline = dict(roofs[dominant])
+    roofline["note"] = ("achieved = algorithmic tests (oracle's plain sequential method: SFS for the "
+                        "dominance tests, Alg. 1's descending scan for gres) x d element compares per "
+                        "launch / the kernel's average HIP-event launch time (above 1 when box "
+                        "pruning skips more of the plain method's tests than the hardware loses); "
+                        "executed_frac counts the element ops the kernel really evaluates (device "
+                        "counters); peak = 256 CUs x 64 lanes x 2.4 GHz 32-bit VALU lane-ops; "
+                        "traffic = PMC FETCH_SIZE+WRITE_SIZE bytes per launch (calibrated), null "
+                        "when the kernel changed since")
     line = {
         "metric": METRIC,
         "value": tests / dt,
@@ -215,6 +239,7 @@ def main():
         "executed_skyline_tests": executed,
         "phase_ms": phases,
         "roofline": roofline,
+        "roofline_kernels": roofs,
         "kernels": kernels,
         "plan": {k: info[k] for k in ("p", "m", "rounds_local", "rounds_merge", "local_count",
                                       "pruned_cells", "pruned_rows", "max_partition")},

@@ -110,6 +110,9 @@ typedef struct sky_gres_opts {
     int32_t reserved;  /* must be 0 */
     void* ev_begin;    /* optional hipEvent_t recorded on the stream just before the search kernel */
     void* ev_end;      /* optional hipEvent_t recorded just after it (both or neither) */
+    unsigned long long* dev_tests; /* optional device counter: the candidate tests the search
+                                      evaluates (one candidate against one tuple at one level;
+                                      tile-box tests not counted) are added to it */
 } sky_gres_opts;
 
 typedef struct sky_plan sky_plan; /* opaque, host-side; refers to caller memory */
@@ -270,7 +273,7 @@ typedef struct sky_batch sky_batch; /* opaque, host-side; refers to caller memor
 typedef struct sky_tune {
     int32_t mapping;        /* SKY_GRES_AUTO / SKY_GRES_TILES / SKY_GRES_LEVELS */
     int32_t targets_per_wg; /* skyline tuples per work item (one workgroup of 8 wavefronts);
-                               0 = default (32); else 1..4096 */
+                               0 = default (16); else 1..4096 */
     int32_t near_first;     /* 1 = each tuple scans the candidate tiles next to its own place on
                                the curve first (default), 0 = tiles in curve order */
     int32_t lpt;            /* 1 = work items ordered by estimated cost, heaviest first

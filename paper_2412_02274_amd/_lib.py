@@ -61,7 +61,7 @@ class SkyInfo(C.Structure):
 
 class GresOpts(C.Structure):
     _fields_ = [("mapping", C.c_int32), ("reserved", C.c_int32), ("ev_begin", C.c_void_p),
-                ("ev_end", C.c_void_p)]
+                ("ev_end", C.c_void_p), ("dev_tests", C.c_void_p)]
 
 
 class SkyTune(C.Structure):

@@ -282,9 +282,11 @@ class Pipeline:
         self.events = None
 
     def run(self, x_rows: torch.Tensor, check: bool = True, timing: bool = False,
-            test_events=None, gres_events=None):
+            test_events=None, gres_events=None, gres_counter: torch.Tensor | None = None):
         """test_events: optional (begin[], end[]) lists of hipEvent_t handles recorded around the
-        dominance-test launches; gres_events: optional (begin, end) around the gres search."""
+        dominance-test launches; gres_events: optional (begin, end) around the gres search;
+        gres_counter: optional int64 device tensor to which the gres search adds the candidate
+        tests it evaluates."""
         lib = _lib.load()
         st = torch.cuda.current_stream()
         sp = C.c_void_p(st.cuda_stream)
@@ -315,18 +317,21 @@ class Pipeline:
                 ev[3].record(st)
             _lib.check(lib.sky_merge(h, _ptr(self.sky_buf), self.n, _ptr(self.count), None, sp),
                        "sky_merge")
-            s = int(self.count.item())
             if ev:
                 ev[4].record(st)
+            # the skyline size is known on the host once the engine's last round has finished
             inf = _lib.SkyInfo()
             lib.sky_plan_info(h, C.byref(inf))
             self.last_info = inf.as_dict()
+            s = int(inf.sky_count)
         finally:
             lib.sky_plan_destroy(h)
         opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
                              else int(self.mapping))
         if gres_events is not None:
             opts.ev_begin, opts.ev_end = gres_events
+        if gres_counter is not None:
+            opts.dev_tests = gres_counter.data_ptr()
         _lib.check(lib.gres_compute(_ptr(self.x_soa), self.n, self.d, self.n, _ptr(self.sky_buf), s,
                                     self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
                                     _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),

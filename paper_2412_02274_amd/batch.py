@@ -132,7 +132,7 @@ class GresTuner:
     (d, skyline size, largest relation's skyline, g_max) in memory and, if `path` is given, in
     a JSON file."""
 
-    PER_WG = (8, 16, 32, 64, 128)
+    PER_WG = (8, 16, 32, 64, 128)  # 8 waves per workgroup: 1 to 16 tuples per wave
 
     def __init__(self, path=None, repeats=2):
         self.path = path
@@ -169,7 +169,7 @@ class GresTuner:
         k = self.key(group)
         if k in self.cache:
             return _lib.SkyTune(**self.cache[k])
-        cur = dict(mapping=_lib.SKY_GRES_TILES, targets_per_wg=32, near_first=1, lpt=1)
+        cur = dict(mapping=_lib.SKY_GRES_TILES, targets_per_wg=16, near_first=1, lpt=1)
         best_ms = None
         for field, values in (("targets_per_wg", self.PER_WG),
                               ("mapping", (_lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS)),

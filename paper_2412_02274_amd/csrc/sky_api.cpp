@@ -245,8 +245,12 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     if (P->state != 1) return SKY_ERR_STATE;
     hipStream_t st = (hipStream_t)stream;
     const int32_t n = (int32_t)P->n;
-    // partition statistics (sizes, pruned Grid cells)
-    {
+    // partition statistics (sizes, pruned Grid cells); one partition: known on the host
+    if (P->p == 1) {
+        P->info.pruned_cells = 0;
+        P->info.pruned_rows = 0;
+        P->info.max_partition = P->n;
+    } else {
         int32_t* off = (int32_t*)malloc(sizeof(int32_t) * (size_t)(P->p + 1));
         uint8_t* pr = (uint8_t*)malloc((size_t)P->p);
         if (!off || !pr) { free(off); free(pr); return SKY_ERR_INVALID_ARG; }
@@ -271,9 +275,8 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
     SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID ? P->pruned : nullptr, P->seg, n, P->eng.w1,
                                  P->count_tmp, P->eng.flag, P->eng.scan, P->eng.scan_tmp, st));
-    int32_t live = 0;
-    SKY_HIP(hipMemcpyAsync(&live, P->count_tmp, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SKY_HIP(hipStreamSynchronize(st));
+    // live rows: every row outside the pruned Grid cells (exactly what the list holds)
+    const int32_t live = n - (int32_t)P->info.pruned_rows;
     EngineProblem pb{};
     pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
     pb.seg_of_pos = P->p > 1 ? P->seg : nullptr;
@@ -407,7 +410,8 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
     SKY_TRY(launch_gres_prepare(x_soa, n, d, ld, sky_idx, s, store, tmp, dev_status, st));
     SKY_TRY(launch_gres_targets(x_soa, n, d, ld, nullptr, s, s, store, tg, dev_status, st));
     return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, 0, g_max, mapping, g_exit, gres,
-                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr, st);
+                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
+                              opts ? opts->dev_tests : nullptr, st);
 }
 
 size_t gres_prepare_bytes(int64_t s, int32_t d) {
@@ -467,7 +471,8 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
     if (s == 0) return SKY_ERR_INVALID_ARG;  // targets need candidates to be tested against
     SKY_TRY(launch_gres_targets(x_soa, n, d, ld, targets, nt, s, store, tg, dev_status, st));
     return launch_gres_search(store, d, (int32_t)s, tg, nt, nullptr, 0, g_max, mapping, g_exit, gres,
-                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr, st);
+                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
+                              opts ? opts->dev_tests : nullptr, st);
 }
 
 }  // extern "C"

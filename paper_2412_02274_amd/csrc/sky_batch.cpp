@@ -175,7 +175,7 @@ sky_status sky_batch_tune(sky_batch* B, const sky_tune* tune, void* stream) {
         t.targets_per_wg > 4096 || (t.near_first != 0 && t.near_first != 1) || (t.lpt != 0 && t.lpt != 1))
         return SKY_ERR_INVALID_ARG;
     if (B->state < 2) return SKY_ERR_STATE;
-    const int32_t per = t.targets_per_wg > 0 ? t.targets_per_wg : 32;
+    const int32_t per = t.targets_per_wg > 0 ? t.targets_per_wg : 16;
     struct Item { int32_t seg, t0, t1; double cost; };
     std::vector<Item> items;
     for (int32_t j = 0; j < B->nbatch; ++j) {
@@ -221,7 +221,7 @@ sky_status sky_batch_gres(sky_batch* B, int32_t g_max, int32_t* g_exit, float* g
     SKY_TRY(launch_gres_targets_segments(B->store, B->d, B->sky_count, B->cand_off, B->nbatch,
                                          B->near_first != 0, B->tg, st));
     return launch_gres_search(B->store, B->d, B->max_cnt, B->tg, B->sky_count, B->wg_table, B->n_wg,
-                              g_max, mapping, g_exit, gres, ev_begin, ev_end, st);
+                              g_max, mapping, g_exit, gres, ev_begin, ev_end, nullptr, st);
 }
 
 sky_status sky_batch_info(const sky_batch* B, sky_info* out) {

@@ -51,6 +51,8 @@ constexpr int kWaves = kGresBlock / kWave;
 constexpr int kBatch = 4;                // candidate tiles fetched per round trip
 constexpr int kGresLdsBytes = 64 * 1024; // tile boxes cached in LDS when they fit
 constexpr float kPadValue = 2.0f;
+constexpr int kBandLevels = 6;           // levels per band of the TILES search
+constexpr int kMaxBands = 8;
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -229,6 +231,11 @@ __global__ void __launch_bounds__(kBlock) targets_seg_kernel(
     tout[q] = perm[slot];
 }
 
+__global__ void __launch_bounds__(kBlock) fill_i32_kernel(int32_t* __restrict__ p, int32_t n, int32_t v) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // first position of every relation's rows in the ascending skyline list (lower bound of its
 // first row), as int64 offsets for the caller and int32 element offsets for the store
 __global__ void __launch_bounds__(kBlock) batch_offsets_kernel(const int64_t* __restrict__ sky_idx,
@@ -300,15 +307,16 @@ __global__ void __launch_bounds__(kBlock) targets_rows_kernel(const float* __res
 // one segment (0) and targets [blockIdx * per_wg, ...).
 struct WgWork { int32_t seg, t0, t1; };
 
-__device__ __forceinline__ WgWork wg_work(const int32_t* wg_table, int32_t per_wg, int32_t nt) {
+__device__ __forceinline__ WgWork wg_work(const int32_t* wg_table, int32_t per_wg, int32_t nt,
+                                          int32_t blk) {
     WgWork w;
     if (wg_table) {
-        w.seg = wg_table[3 * blockIdx.x];
-        w.t0 = wg_table[3 * blockIdx.x + 1];
-        w.t1 = wg_table[3 * blockIdx.x + 2];
+        w.seg = wg_table[3 * blk];
+        w.t0 = wg_table[3 * blk + 1];
+        w.t1 = wg_table[3 * blk + 2];
     } else {
         w.seg = 0;
-        w.t0 = blockIdx.x * per_wg;
+        w.t0 = blk * per_wg;
         w.t1 = w.t0 + per_wg < nt ? w.t0 + per_wg : nt;
     }
     return w;
@@ -321,13 +329,19 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
     const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
     int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
     const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
-    int32_t* __restrict__ ge_out) {
+    int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests, int32_t nblk,
+    int32_t band_len) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
+    unsigned long long ntests = 0;   // candidate tests (target against candidate at one level)
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
-    const WgWork w = wg_work(wg_table, per_wg, nt);
+    // blocks are band-major: every target's highest band first
+    const int32_t band = blockIdx.x / nblk;
+    const int32_t g_hi = g_max - band * band_len;
+    const int32_t g_lo = g_hi - band_len + 1 > 2 ? g_hi - band_len + 1 : 2;
+    const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x - band * nblk);
     if (w.t0 >= w.t1) return;  // uniform
     const uint32_t coff = (uint32_t)seg_coff[w.seg];
     const int32_t cnt = seg_cnt[w.seg];
@@ -364,7 +378,12 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
         my_tile = my_tile < 0 ? 0 : (my_tile >= ntile ? ntile - 1 : my_tile);
         const int32_t my_chunk = my_tile / kWave;
         int32_t result = 1;
-        for (int32_t g = g_max; g >= 2 && ntile > 0; --g) {
+        // a higher band may already have found the exit of q at or above this band's levels
+        int32_t seen = __hip_atomic_load(&ge_out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int32_t g = g_hi; g >= g_lo && ntile > 0; --g) {
+            if (seen >= g) break;
+            const int32_t seen_next =
+                __hip_atomic_load(&ge_out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const float fg = (float)g;
             // key(v) <= key(t) <=> fl(v g) < key(t) + 1;  key(v) < key(t) <=> fl(v g) < key(t)
             float tle[DM], tlt[DM];
@@ -427,6 +446,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
                                 const int tb = ((__ffsll((unsigned long long)mask) - 1) + r) % kWave;
                                 mask &= mask - 1;
                                 jb[b] = coff + (uint32_t)((c * kWave + tb) * kTileC + lane);
+                                ntests += kTileC;
                             }
                         }
                         float sv[kBatch][DM];
@@ -455,9 +475,12 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
                 if (use_lds) break;  // all chunks were covered by the chunk mask
             }
             if (found) { result = g; break; }
+            seen = seen_next;
         }
-        if (lane == 0) ge_out[q] = result;
+        // ge_out starts at 1 (no exit); each band raises it to its highest exit level
+        if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
     }
+    if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
 }
 
 // no level g >= g_low can see a candidate whose (lower-bounding) excess over t is delta
@@ -473,14 +496,15 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
     const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
     int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
     const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
-    int32_t* __restrict__ ge_out) {
+    int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    unsigned long long ntests = 0;  // candidate tests (target against candidate at one level)
     (void)thint;
     (void)lds_floats;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
-    const WgWork w = wg_work(wg_table, per_wg, nt);
+    const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x);
     if (w.t0 >= w.t1) return;
     const int64_t coff = seg_coff[w.seg];
     const int32_t cnt = seg_cnt[w.seg];
@@ -532,9 +556,11 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
                 // the whole tile dominates t at this lane's level
                 hit |= __ballot(pass && hle && hlt);
                 if (hit & 1ull) break;
-                if (!__ballot(pass)) continue;
+                const uint64_t pmask = __ballot(pass);
+                if (!pmask) continue;
                 const int32_t base = tile * kTileC;
                 const int32_t cnt_t = (cnt - base) < kTileC ? (cnt - base) : kTileC;
+                ntests += (unsigned long long)cnt_t * (unsigned long long)__popcll(pmask);
                 for (int32_t i = 0; i < cnt_t; ++i) {
                     const int64_t j = coff + base + i;
                     float sv[DM];
@@ -567,6 +593,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
         }
         if (lane == 0) ge_out[q] = result;
     }
+    if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
 }
 
 __global__ void __launch_bounds__(kBlock) gres_output_kernel(const int32_t* __restrict__ ge_t,
@@ -733,7 +760,8 @@ int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
                               const GresTargets& tg, int64_t nt64, const int32_t* wg_table,
                               int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
-                              float* gres, void* ev_begin, void* ev_end, hipStream_t st) {
+                              float* gres, void* ev_begin, void* ev_end,
+                              unsigned long long* dev_tests, hipStream_t st) {
     const int32_t nt = (int32_t)nt64;
     if (nt <= 0) return SKY_OK;
     // LDS for the tile boxes of the largest segment, when they fit
@@ -745,26 +773,41 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     int32_t per_wg = 0;
     uint32_t blocks = (uint32_t)n_wg;
     if (!wg_table) {
-        // single segment: ~4 targets per wave when there are plenty, fewer otherwise
-        int64_t want = ceil_div(nt, kWaves * 4);
+        // single segment: ~2 targets per wave when there are plenty (measured best on large
+        // skylines: fewer leaves waves idle on the longest searches), fewer otherwise
+        int64_t want = ceil_div(nt, kWaves * 2);
         if (want < 256) want = ceil_div(nt, kWaves);
         blocks = (uint32_t)(want < 1 ? 1 : want);
         per_wg = (int32_t)ceil_div(nt, blocks);
         blocks = (uint32_t)ceil_div(nt, per_wg);
     }
+    // TILES: the levels are split into bands searched by separate workgroups (band-major
+    // order), so a tuple that scans many levels is not one long sequential chain
+    int32_t nbands = 1, band_len = g_max - 1;
+    if (mapping != SKY_GRES_LEVELS) {
+        nbands = (int32_t)ceil_div(g_max - 1, kBandLevels);
+        nbands = nbands < 1 ? 1 : (nbands > kMaxBands ? kMaxBands : nbands);
+        band_len = (int32_t)ceil_div(g_max - 1, nbands);
+    }
+    // no exit (1) until a band finds one
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, tg.ge,
+                       nt, 1);
+    SKY_HIP(hipGetLastError());
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (mapping == SKY_GRES_LEVELS) {
         SKY_DISPATCH_D(d, gres_levels_kernel, dim3(blocks), dim3(kGresBlock), 0, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
-                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge);
+                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
+                       dev_tests);
     } else {
-        SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(blocks), dim3(kGresBlock), lds, st,
+        SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(blocks * (uint32_t)nbands), dim3(kGresBlock), lds, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
-                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge);
+                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
+                       dev_tests, (int32_t)blocks, band_len);
     }
     SKY_HIP(hipGetLastError());
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

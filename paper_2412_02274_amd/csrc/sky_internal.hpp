@@ -92,9 +92,10 @@ __device__ __forceinline__ uint32_t hilbert_key(const float* v, int d, int bits)
     return code;
 }
 
-// bits per attribute of the curve keys (bits * d <= 32)
+// bits per attribute of the curve keys: at most 24 bits in all (three 8-bit radix passes);
+// 2^24 cells are far finer than the 64-row tiles the order serves
 __host__ __device__ __forceinline__ int curve_bits(int d) {
-    int b = 32 / d;
+    int b = 24 / d;
     return b > 16 ? 16 : (b < 1 ? 1 : b);
 }
 
@@ -278,6 +279,7 @@ int32_t gres_auto_mapping(int64_t s, int32_t g_max);
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
                               const GresTargets& tg, int64_t nt, const int32_t* wg_table,
                               int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
-                              float* gres, void* ev_begin, void* ev_end, hipStream_t st);
+                              float* gres, void* ev_begin, void* ev_end,
+                              unsigned long long* dev_tests, hipStream_t st);
 
 }  // namespace sky
