@@ -89,12 +89,15 @@ __device__ __forceinline__ int32_t wave_slot(int32_t* ctr, int32_t stride, int32
 
 __global__ void init_segments_kernel(int32_t nseg, uint32_t* __restrict__ smin,
                                      uint32_t* __restrict__ smax, int32_t* __restrict__ hist,
-                                     int32_t* __restrict__ info, int32_t* __restrict__ counters) {
+                                     int32_t* __restrict__ info, int32_t* __restrict__ counters,
+                                     int32_t reset_range) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < (int64_t)nseg * kBins) hist[i] = 0;
     if (i < nseg) {
-        smin[i] = 0xFFFFFFFFu;
-        smax[i] = 0u;
+        if (reset_range) {
+            smin[i] = 0xFFFFFFFFu;
+            smax[i] = 0u;
+        }
         for (int j = 0; j < kInfo; ++j) info[i * kInfo + j] = 0;
     }
     if (i == 0) counters[C_NEXT] = 0;
@@ -211,8 +214,16 @@ __global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict
                                                         const float* __restrict__ fsum,
                                                         const uint32_t* __restrict__ smin,
                                                         const uint32_t* __restrict__ smax,
-                                                        int32_t* __restrict__ hist) {
+                                                        int32_t* __restrict__ hist,
+                                                        int32_t* __restrict__ info, int32_t count_live) {
     __shared__ int32_t h[kBins];
+    if (count_live && threadIdx.x == 0) {
+        // items this block visits (grid-stride), added once per block
+        int32_t c = 0;
+        for (int32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock)
+            c += n - base < kBlock ? n - base : kBlock;
+        if (c) atomicAdd(&info[SI_LIVE], c);
+    }
     for (int b = threadIdx.x; b < kBins; b += kBlock) h[b] = 0;
     __syncthreads();
     const float lo = __uint_as_float(smin[0]);
@@ -225,10 +236,8 @@ __global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict
 }
 
 // One wave per segment: smallest bin b* whose cumulative count reaches kHead.
-__global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32_t* __restrict__ hist,
-                                                        int32_t* __restrict__ info) {
-    int32_t s = blockIdx.x;
-    if (s >= nseg) return;
+// head threshold of segment s, by one wavefront: the lowest bins holding at least kHead rows
+__device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int32_t* __restrict__ info) {
     const int lane = (int)lane_id();
     const int32_t* h = hist + (int64_t)s * kBins;
     int32_t live = info[s * kInfo + SI_LIVE];
@@ -257,6 +266,11 @@ __global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32
     }
 }
 
+__global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32_t* __restrict__ hist,
+                                                        int32_t* __restrict__ info) {
+    if ((int32_t)blockIdx.x < nseg) thresh_segment(blockIdx.x, hist, info);
+}
+
 // Per segment: list offset (scan of live counts), 64-aligned head offset (scan of head counts
 // rounded up to 64), rest offset, and the item-tile offsets of both groups; round totals.
 // Single workgroup, sequential over blocks of 256 segments.
@@ -264,7 +278,13 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
                                                               int32_t tpu_r,
                                                               int32_t* __restrict__ info,
                                                               int32_t* __restrict__ tile_off,
-                                                              int32_t* __restrict__ counters) {
+                                                              int32_t* __restrict__ counters,
+                                                              const int32_t* __restrict__ hist,
+                                                              int32_t fused_thresh) {
+    if (fused_thresh) {  // few segments: their thresholds first, one wave each
+        for (int32_t s = threadIdx.x / kWave; s < nseg; s += kBlock / kWave) thresh_segment(s, hist, info);
+        __syncthreads();
+    }
     constexpr int Q = 6;
     __shared__ int32_t carry[Q];
     __shared__ int32_t wsum[Q][kBlock / kWave];
@@ -346,7 +366,7 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
 // kernel 2 gets its block's prefix by summing the counts of the blocks before it (no waiting on
 // other blocks), ranks entries inside the block with wave ballots over 64-entry chunks in
 // order, and scatters. The result is in list order (stable).
-constexpr int kCItems = 4096;
+constexpr int kCItems = 1024;
 constexpr int kCChunks = kCItems / kWave;  // 64 chunks of 64 entries
 
 // sum of cnt[0, b) by the whole block (every thread gets it)
@@ -455,10 +475,34 @@ __global__ void __launch_bounds__(kBlock) split_scatter_kernel(
     }
 }
 
+// Blocks [0, cblocks): survivors per block of the rest list (as split_count_kernel). Blocks from
+// cblocks on: the head survivors -> output flags and output list (order irrelevant).
 __global__ void __launch_bounds__(kBlock) rest_count_kernel(const int32_t* __restrict__ rest,
-                                                             const int32_t* __restrict__ counters,
+                                                             int32_t* __restrict__ counters,
                                                              const uint8_t* __restrict__ dom,
-                                                             int32_t* __restrict__ bcnt) {
+                                                             int32_t* __restrict__ bcnt, int32_t cblocks,
+                                                             const int32_t* __restrict__ head,
+                                                             uint8_t* __restrict__ flag_out,
+                                                             int32_t* __restrict__ out_list) {
+    if ((int32_t)blockIdx.x >= cblocks) {
+        const int32_t htot = counters[C_HTOT];
+        const int32_t nb = (int32_t)gridDim.x - cblocks;
+        for (int32_t base = ((int32_t)blockIdx.x - cblocks) * kBlock; base < htot; base += nb * kBlock) {
+            const int32_t i = base + threadIdx.x;
+            bool keep = false;
+            int32_t pos = -1;
+            if (i < htot) {
+                pos = head[i];
+                keep = pos >= 0 && dom[pos] == 0;
+            }
+            const int32_t os = wave_slot(counters + C_OUT, 0, 0, keep);
+            if (keep) {
+                flag_out[pos] = 1;
+                out_list[os] = pos;
+            }
+        }
+        return;
+    }
     __shared__ int32_t part[kBlock / kWave];
     const int32_t n = counters[C_RTOT];
     const int wave = threadIdx.x / kWave;
@@ -757,27 +801,6 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     if (lane == 0 && ntests_r) atomicAdd(&tests[1], ntests_r);
 }
 
-// Head survivors -> output flags and output list (order irrelevant).
-__global__ void __launch_bounds__(kBlock) compact_head_kernel(
-    const int32_t* __restrict__ head, const int32_t* __restrict__ counters,
-    const uint8_t* __restrict__ dom, uint8_t* __restrict__ flag_out,
-    int32_t* __restrict__ out_list, int32_t* __restrict__ out_counter) {
-    const int32_t htot = counters[C_HTOT];
-    for (int32_t base = blockIdx.x * kBlock; base < htot; base += gridDim.x * kBlock) {
-        const int32_t i = base + threadIdx.x;
-        bool keep = false;
-        int32_t pos = -1;
-        if (i < htot) {
-            pos = head[i];
-            keep = pos >= 0 && dom[pos] == 0;
-        }
-        const int32_t os = wave_slot(out_counter, 0, 0, keep);
-        if (keep) {
-            flag_out[pos] = 1;
-            out_list[os] = pos;
-        }
-    }
-}
 
 
 
@@ -929,15 +952,20 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         res->rounds++;
         const uint32_t iblocks = (uint32_t)ceil_div(live, kBlock);
         const int64_t hn = (int64_t)nseg * kBins;
+        // one segment: the score range of the first round serves every round (the live rows
+        // only ever shrink), so later rounds skip the min/max pass and count rows in hist1
+        const bool first = res->rounds == 1;
         hipLaunchKernelGGL(init_segments_kernel, dim3((uint32_t)ceil_div(hn > nseg ? hn : nseg, 256)),
                            dim3(256), 0, st, nseg, b.seg_min, b.seg_max, b.hist, b.seg_info,
-                           b.counters);
+                           b.counters, (int32_t)(nseg > 1 || first));
         if (nseg == 1) {
             const uint32_t sblocks = iblocks < 256 ? iblocks : 256;
-            hipLaunchKernelGGL(minmax1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                               b.seg_min, b.seg_max, b.seg_info);
+            if (first)
+                hipLaunchKernelGGL(minmax1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
+                                   b.seg_min, b.seg_max, b.seg_info);
             hipLaunchKernelGGL(hist1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                               (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist);
+                               (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist,
+                               b.seg_info, (int32_t)!first);
         } else {
             hipLaunchKernelGGL(minmax_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
                                pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
@@ -945,8 +973,10 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                                pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
                                b.hist);
         }
-        hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)nseg), dim3(kWave), 0, st, nseg,
-                           (const int32_t*)b.hist, b.seg_info);
+        const bool fused_thresh = nseg <= kBlock / kWave;
+        if (!fused_thresh)
+            hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)nseg), dim3(kWave), 0, st, nseg,
+                               (const int32_t*)b.hist, b.seg_info);
         // tiles per unit: split the head tiles of an item group over several units when there
         // are too few item groups to fill the chip (kTargetWaves waves)
         const int64_t head_est = (int64_t)nseg * kHead < live ? (int64_t)nseg * kHead : live;
@@ -963,7 +993,8 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
             return (ceil_div(items, kBlock) + nseg) * ceil_div(ntile_est, tpu);
         };
         hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg, tpu_h, tpu_r,
-                           b.seg_info, b.tile_off, b.counters);
+                           b.seg_info, b.tile_off, b.counters, (const int32_t*)b.hist,
+                           (int32_t)fused_thresh);
         const uint32_t cblocks = (uint32_t)ceil_div(live, kCItems);
         hipLaunchKernelGGL(split_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
                            pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
@@ -990,13 +1021,12 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                        (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi,
                        b.tcap, tpu_h, tpu_r, b.dom, b.tests);
         SKY_HIP(ev_rec(false));
-        hipLaunchKernelGGL(compact_head_kernel, dim3(grid(ceil_div(slot_bound, kBlock))), dim3(kBlock), 0,
-                           st, (const int32_t*)b.head, (const int32_t*)b.counters,
-                           (const uint8_t*)b.dom, pb.flag_out, out_list, b.counters + C_OUT);
-        SKY_HIP(hipGetLastError());
         // the survivors of the rest groups, in order, are the next round's work list
-        hipLaunchKernelGGL(rest_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, (const int32_t*)b.rest,
-                           (const int32_t*)b.counters, (const uint8_t*)b.dom, b.scan);
+        // (and the head survivors into the output, in extra blocks of the same launch)
+        const uint32_t hblocks = grid(ceil_div(slot_bound, kBlock));
+        hipLaunchKernelGGL(rest_count_kernel, dim3(cblocks + hblocks), dim3(kBlock), 0, st,
+                           (const int32_t*)b.rest, b.counters, (const uint8_t*)b.dom, b.scan,
+                           (int32_t)cblocks, (const int32_t*)b.head, pb.flag_out, out_list);
         hipLaunchKernelGGL(rest_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, (const int32_t*)b.rest,
                            b.counters, (const uint8_t*)b.dom, (const int32_t*)b.scan, next);
         SKY_HIP(hipGetLastError());
