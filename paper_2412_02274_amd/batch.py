@@ -133,6 +133,7 @@ class GresTuner:
     a JSON file."""
 
     PER_WG = (8, 16, 32, 64, 128)  # 8 waves per workgroup: 1 to 16 tuples per wave
+    LEVELS_MAX_CANDIDATES = 8192
 
     def __init__(self, path=None, repeats=2):
         self.path = path
@@ -171,8 +172,11 @@ class GresTuner:
             return _lib.SkyTune(**self.cache[k])
         cur = dict(mapping=_lib.SKY_GRES_TILES, targets_per_wg=16, near_first=1, lpt=1)
         best_ms = None
-        for field, values in (("targets_per_wg", self.PER_WG),
-                              ("mapping", (_lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS)),
+        # lanes over levels only pays off for small candidate sets (every lane walks all of them)
+        cnt = np.diff(group.sky_off.cpu().numpy())
+        mappings = (_lib.SKY_GRES_TILES,) if cnt.max() > self.LEVELS_MAX_CANDIDATES else (
+            _lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS)
+        for field, values in (("targets_per_wg", self.PER_WG), ("mapping", mappings),
                               ("near_first", (1, 0)), ("lpt", (1, 0))):
             best_v = cur[field]
             for v in values:
