@@ -204,6 +204,21 @@ sky_status sky_plan_info(const sky_plan* plan, sky_info* out);
 void sky_plan_destroy(sky_plan* plan);
 
 /*
+ * sky_project -- the grid projection of Def. 2 as a relation of its own, for running the
+ * skyline machinery on projected tuples (Alg. 1 as written recomputes Sky(gproj(s, g)) at every
+ * level; gres_compute gives the same answer per tuple without it). For j < s and every attribute
+ * k: out_soa[k*ld_out + j] = floor(fl32(x[k][rows[j]] * g)) * 2^-b, where 2^b is the smallest
+ * power of two >= g. That is the key of the quantisation contract scaled by a power of two:
+ * exact in FP32, in [0, 1), and ordered exactly like floor(t g) / g, so dominance between
+ * projections is unchanged. rows: device int64[s] in [0, n) (SKY_ERR_INVALID_ARG in
+ * *dev_status otherwise); values outside the domain raise SKY_ERR_DOMAIN. g in [1, SKY_MAX_G].
+ * Never synchronises.
+ */
+sky_status sky_project(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                       int64_t s, int32_t g, float* out_soa, int64_t ld_out, int32_t* dev_status,
+                       void* stream);
+
+/*
  * Workspace for gres_compute, in bytes. Returns 0 for invalid arguments.
  */
 size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max);

@@ -39,7 +39,7 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "gres_workspace_bytes", "gres_compute", "gres_prepare_bytes", "gres_prepare",
            "gres_search_bytes", "gres_search",
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
-           "sky_batch_gres", "sky_batch_info", "sky_batch_destroy")
+           "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project")
 
 
 class SkyParams(C.Structure):
@@ -120,6 +120,7 @@ def load():
         "sky_batch_gres": (i32, [vp, i32, vp, vp, vp, vp, vp]),
         "sky_batch_info": (i32, [vp, C.POINTER(SkyInfo)]),
         "sky_batch_destroy": (None, [vp]),
+        "sky_project": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, i64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

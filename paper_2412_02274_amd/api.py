@@ -21,6 +21,7 @@ from . import _lib
 from ._lib import SkyError
 
 __all__ = ["ingest", "build", "Plan", "Pipeline", "PreparedCandidates", "gres", "skyline",
+           "project", "gres_literal",
            "gres_workspace_bytes",
            "build_workspace_bytes", "check_status", "SkyError"]
 
@@ -236,6 +237,61 @@ class PreparedCandidates:
             (stream or torch.cuda.current_stream()).synchronize()
             check_status(st, "gres_search")
         return g_exit, gres_out
+
+
+def project(x_soa: torch.Tensor, rows: torch.Tensor, g: int, out: torch.Tensor | None = None,
+            status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Grid projection (Def. 2) of rows of x at level g as an SoA relation [d, s] of scaled keys
+    (``sky_project``)."""
+    lib = _lib.load()
+    d, n = x_soa.shape
+    s = int(rows.numel())
+    if out is None:
+        out = torch.empty((d, max(s, 1)), dtype=torch.float32, device=x_soa.device)
+    st = status if status is not None else new_status(x_soa.device)
+    _lib.check(lib.sky_project(_ptr(x_soa), n, d, x_soa.stride(0), _ptr(rows), s, int(g), _ptr(out),
+                               out.stride(0), _ptr(st), _stream_ptr(stream)), "sky_project")
+    if status is None:
+        check_status(st, "sky_project")
+    return out
+
+
+def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, scheme="none",
+                 target_p: int = 16, slice_dim: int = 0):
+    """Alg. 1 as written: for g = g_max .. 2, the skyline of the grid projection of the candidate
+    set (Sky(r)) is computed through the two-phase partitioned scheme (build, local skylines,
+    merge on the projected relation); every candidate not in it that has no value yet gets
+    g_exit = g. Returns (g_exit int32[s] on the host, per-level statistics). Equal to
+    ``gres()`` for every input (gres is stable and dominance between projections is the per-tuple
+    test); kept to run the paper's own formulation and count its work."""
+    import numpy as np
+    s = int(sky_idx.numel())
+    d = x_soa.shape[0]
+    ge = np.ones(s, dtype=np.int32)
+    if s == 0:
+        return ge, []
+    remaining = np.ones(s, dtype=bool)
+    proj = torch.empty((d, s), dtype=torch.float32, device=x_soa.device)
+    status = new_status(x_soa.device)
+    levels = []
+    for g in range(int(g_max), 1, -1):
+        project(x_soa, sky_idx, g, out=proj, status=status)
+        plan = build(proj, scheme, target_p, slice_dim, status=status)
+        plan.local_skylines()
+        _, member = plan.merge(member=True)
+        inf = plan.info()
+        plan.close()
+        check_status(status, "gres_literal")
+        inside = member.cpu().numpy().astype(bool)
+        exits = remaining & ~inside
+        ge[exits] = g
+        remaining &= inside
+        levels.append({"g": g, "sky": int(inf["sky_count"]), "exits": int(exits.sum()),
+                       "p": int(inf["p"]), "tests_local": int(inf["tests_local"]),
+                       "tests_merge": int(inf["tests_merge"])})
+        if not remaining.any():
+            break
+    return ge, levels
 
 
 def skyline(x_rows: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0):

@@ -221,6 +221,15 @@ sky_status sky_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, i
     return launch_ingest(x_rows, n, d, x_soa, ld, dev_status, (hipStream_t)stream);
 }
 
+sky_status sky_project(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                       int64_t s, int32_t g, float* out_soa, int64_t ld_out, int32_t* dev_status,
+                       void* stream) {
+    if (s < 0 || s > kMaxRows || !valid_d(d) || g < 1 || g > SKY_MAX_G || ld_out < s) return SKY_ERR_INVALID_ARG;
+    if (s == 0) return SKY_OK;
+    if (!x_soa || !rows || !out_soa || !dev_status || n < 1 || n > kMaxRows || ld < n) return SKY_ERR_INVALID_ARG;
+    return launch_project(x_soa, n, d, ld, rows, s, g, out_soa, ld_out, dev_status, (hipStream_t)stream);
+}
+
 size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params) {
     if (!params || n < 1 || n > kMaxBuildRows || !valid_d(d) || params->flags != 0) return 0;
     int32_t p = 1, m = 0;

@@ -37,7 +37,44 @@ __global__ void __launch_bounds__(kBlock) ingest_kernel(const float* __restrict_
     if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
 }
 
+// Grid projection (Def. 2) of the rows rows[0, s) at level g, as a relation of its own:
+// out[k*ld_out + j] = floor(fl32(x[k][rows[j]] * g)) * 2^-b with 2^b >= g. The scale keeps the
+// values in [0, 1) and exact in FP32 (keys < 2^20), and orders them like floor(t g) / g.
+__global__ void __launch_bounds__(kBlock) project_kernel(const float* __restrict__ x, int64_t n, int32_t d,
+                                                          int64_t ld, const int64_t* __restrict__ rows,
+                                                          int64_t s, int32_t g, float scale,
+                                                          float* __restrict__ out, int64_t ld_out,
+                                                          int32_t* dev_status) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool bad_idx = false, bad_val = false;
+    if (j < s) {
+        const int64_t row = rows[j];
+        bad_idx = row < 0 || row >= n;
+        const float fg = (float)g;
+        for (int k = 0; k < d; ++k) {
+            const float v = bad_idx ? 0.0f : x[(int64_t)k * ld + row];
+            bad_val |= !in_domain(v);
+            out[(int64_t)k * ld_out + j] = __fmul_rn((float)qkey(canon(v), fg), scale);
+        }
+    }
+    if (__ballot(bad_idx) && lane_id() == 0) raise_status(dev_status, SKY_ERR_INVALID_ARG);
+    if (__ballot(bad_val) && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
+}
+
 }  // namespace
+
+sky_status launch_project(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                          int64_t s, int32_t g, float* out, int64_t ld_out, int32_t* dev_status,
+                          hipStream_t st) {
+    if (s <= 0) return SKY_OK;
+    int b = 0;
+    while ((int64_t(1) << b) < g) ++b;
+    const float scale = ldexpf(1.0f, -b);
+    hipLaunchKernelGGL(project_kernel, dim3((uint32_t)ceil_div(s, kBlock)), dim3(kBlock), 0, st, x, n, d,
+                       ld, rows, s, g, scale, out, ld_out, dev_status);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
 
 sky_status launch_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, int64_t ld,
                          int32_t* dev_status, hipStream_t st) {

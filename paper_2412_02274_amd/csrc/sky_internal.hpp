@@ -139,6 +139,9 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // ----------------------------------------------------------------------------------------
 
 // sky_ingest.hip
+sky_status launch_project(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
+                          int64_t s, int32_t g, float* out, int64_t ld_out, int32_t* dev_status,
+                          hipStream_t st);
 sky_status launch_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, int64_t ld,
                          int32_t* dev_status, hipStream_t st);
 

@@ -165,3 +165,14 @@ def test_serving_arena_first_fit():
     a.release((256, 1024))
     a.release(r3)
     assert a.free == [(0, 4096)] and a.used == 0  # neighbours merge back
+
+
+def test_project_arguments(lib):
+    fake = C.c_void_p(0x1000)
+    E = _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_project(fake, 10, 2, 10, fake, 5, 0, fake, 5, fake, None) == E   # g < 1
+    assert lib.sky_project(fake, 10, 2, 10, fake, 5, (1 << 20) + 1, fake, 5, fake, None) == E
+    assert lib.sky_project(fake, 10, 2, 10, fake, 5, 25, fake, 4, fake, None) == E  # ld_out < s
+    assert lib.sky_project(None, 10, 2, 10, fake, 5, 25, fake, 5, fake, None) == E
+    assert lib.sky_project(fake, 10, 0, 10, fake, 5, 25, fake, 5, fake, None) == E
+    assert lib.sky_project(None, 0, 2, 0, None, 0, 25, None, 0, None, None) == _lib.SKY_OK
