@@ -70,6 +70,7 @@ typedef enum sky_scheme {
 #define SKY_MAX_D 16           /* attributes per tuple */
 #define SKY_MAX_CELLS 4096     /* partitions of any scheme (Grid m^d, Angular m^(d-1), Sliced p) */
 #define SKY_MAX_G 1048576      /* largest g_max accepted by gres_compute */
+#define SKY_HOST_SCRATCH_BYTES 256 /* size of the optional pinned host scratch of a plan */
 
 /* gres_compute mapping choice (sky_gres_opts.mapping). */
 #define SKY_GRES_AUTO 0         /* pick by shape */
@@ -200,7 +201,18 @@ sky_status sky_plan_set_events(sky_plan* plan, void* const* ev_begin, void* cons
 /* Plan inspection (host-side copy of the counters listed in sky_info). */
 sky_status sky_plan_info(const sky_plan* plan, sky_info* out);
 
-/* Releases a plan (host memory only). Null is accepted. */
+/*
+ * sky_plan_set_host_scratch -- optional: pinned host memory (hipHostMalloc, or a torch tensor
+ * with pin_memory=True) of at least SKY_HOST_SCRATCH_BYTES bytes, owned by the caller and kept
+ * alive until the plan is destroyed or the scratch is replaced (NULL removes it). With it,
+ * sky_local_skylines and sky_merge launch each skyline round before waiting for the previous
+ * round's counters (copied into this memory asynchronously), so the device does not idle while
+ * the host decides; without it they synchronise after every round. Results are the same either
+ * way. Creates two HIP events owned by the plan.
+ */
+sky_status sky_plan_set_host_scratch(sky_plan* plan, void* host_pinned, size_t bytes);
+
+/* Releases a plan (host memory and its events). Null is accepted. */
 void sky_plan_destroy(sky_plan* plan);
 
 /*

@@ -30,6 +30,7 @@ MAPPINGS = {"auto": SKY_GRES_AUTO, "tiles": SKY_GRES_TILES, "levels": SKY_GRES_L
 SKY_MAX_D = 16
 SKY_MAX_CELLS = 4096
 SKY_MAX_G = 1048576
+SKY_HOST_SCRATCH_BYTES = 256
 
 # every function the header declares (checked against the header by the tests)
 EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspace_bytes",
@@ -39,7 +40,8 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "gres_workspace_bytes", "gres_compute", "gres_prepare_bytes", "gres_prepare",
            "gres_search_bytes", "gres_search",
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
-           "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project")
+           "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
+           "sky_plan_set_host_scratch")
 
 
 class SkyParams(C.Structure):
@@ -121,6 +123,7 @@ def load():
         "sky_batch_info": (i32, [vp, C.POINTER(SkyInfo)]),
         "sky_batch_destroy": (None, [vp]),
         "sky_project": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, i64, vp, vp]),
+        "sky_plan_set_host_scratch": (i32, [vp, vp, sz]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -138,8 +138,11 @@ class Plan:
 
 
 def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0,
-          status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None) -> Plan:
-    """Partition assignment + partition-contiguous copy (sky_build)."""
+          status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
+          host_scratch: torch.Tensor | None = None) -> Plan:
+    """Partition assignment + partition-contiguous copy (sky_build). host_scratch: optional
+    pinned host tensor (>= SKY_HOST_SCRATCH_BYTES) that lets the skyline rounds run one ahead of
+    their readback (sky_plan_set_host_scratch)."""
     lib = _lib.load()
     if x_soa.dtype != torch.float32 or x_soa.dim() != 2 or not x_soa.is_cuda:
         raise ValueError("x_soa must be a float32 [d, N] CUDA tensor")
@@ -157,7 +160,16 @@ def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int
     h = C.c_void_p()
     _lib.check(lib.sky_build(_ptr(x_soa), n, d, ld, C.byref(prm), _ptr(ws), need, _ptr(st),
                              _stream_ptr(stream), C.byref(h)), "sky_build")
-    return Plan(h, ws, st, x_soa, stream)
+    plan = Plan(h, ws, st, x_soa, stream)
+    if host_scratch is not None:
+        if not host_scratch.is_pinned() or host_scratch.numel() * host_scratch.element_size() < \
+                _lib.SKY_HOST_SCRATCH_BYTES:
+            raise ValueError("host_scratch must be pinned and hold SKY_HOST_SCRATCH_BYTES bytes")
+        plan._scratch = host_scratch
+        _lib.check(lib.sky_plan_set_host_scratch(h, host_scratch.data_ptr(),
+                                                 _lib.SKY_HOST_SCRATCH_BYTES),
+                   "sky_plan_set_host_scratch")
+    return plan
 
 
 def gres_workspace_bytes(s: int, d: int, g_max: int) -> int:
@@ -336,6 +348,9 @@ class Pipeline:
         self.gres_v = torch.empty(n, dtype=torch.float32, device=dev)
         self.last_info = None
         self.events = None
+        # pinned host memory for reading skyline-round counters back without stalling the device
+        self.host_scratch = torch.zeros(_lib.SKY_HOST_SCRATCH_BYTES // 4, dtype=torch.int32,
+                                        pin_memory=True)
 
     def run(self, x_rows: torch.Tensor, check: bool = True, timing: bool = False,
             test_events=None, gres_events=None, gres_counter: torch.Tensor | None = None):
@@ -360,6 +375,9 @@ class Pipeline:
                                  _ptr(self.build_ws), self.build_bytes, _ptr(self.status), sp,
                                  C.byref(h)), "sky_build")
         try:
+            _lib.check(lib.sky_plan_set_host_scratch(h, self.host_scratch.data_ptr(),
+                                                     _lib.SKY_HOST_SCRATCH_BYTES),
+                       "sky_plan_set_host_scratch")
             if test_events is not None:
                 nb = len(test_events[0])
                 arr_b = (C.c_void_p * nb)(*test_events[0])

@@ -112,7 +112,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.seg_info = c.take<int32_t>((size_t)p * 8);
     e.dom = c.take<uint8_t>((size_t)n);
     e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
-    e.counters = c.take<int32_t>(16);
+    e.counters = c.take<int32_t>(48);
     e.tests = c.take<unsigned long long>(2);
     e.flag = c.take<int32_t>((size_t)n);
     e.scan = c.take<int32_t>((size_t)n);
@@ -293,6 +293,8 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     pb.items = P->eng.w1; pb.n_items = live;
     pb.flag_out = P->local_flag;
     pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
+    pb.host_scratch = P->host_scratch;
+    pb.round_events[0] = P->round_ev[0]; pb.round_events[1] = P->round_ev[1];
     EngineResult r{};
     SKY_TRY(run_engine(pb, P->eng, P->local_list, &r, st));
     P->info.events_used = P->ev_used;
@@ -324,6 +326,8 @@ sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_co
         pb.items = P->eng.w1; pb.n_items = count;
         pb.flag_out = P->final_flag;
         pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
+        pb.host_scratch = P->host_scratch;
+        pb.round_events[0] = P->round_ev[0]; pb.round_events[1] = P->round_ev[1];
         EngineResult r{};
         SKY_TRY(run_engine(pb, P->eng, P->final_list, &r, st));
         final_list = P->final_list;
@@ -364,6 +368,19 @@ sky_status sky_plan_set_events(sky_plan* P, void* const* ev_begin, void* const* 
     return SKY_OK;
 }
 
+sky_status sky_plan_set_host_scratch(sky_plan* P, void* host_pinned, size_t bytes) {
+    if (!P || (host_pinned && bytes < SKY_HOST_SCRATCH_BYTES)) return SKY_ERR_INVALID_ARG;
+    if (host_pinned && !P->round_ev[0]) {
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SKY_ERR_HIP;
+            P->round_ev[i] = e;
+        }
+    }
+    P->host_scratch = (int32_t*)host_pinned;
+    return SKY_OK;
+}
+
 sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
     if (!P || !out) return SKY_ERR_INVALID_ARG;
     *out = P->info;
@@ -372,6 +389,8 @@ sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
 
 void sky_plan_destroy(sky_plan* P) {
     if (!P) return;
+    for (int i = 0; i < 2; ++i)
+        if (P->round_ev[i]) (void)hipEventDestroy((hipEvent_t)P->round_ev[i]);
     free(P->tan2_host);
     delete P;
 }

@@ -196,7 +196,7 @@ struct EngineBuffers {
     int32_t* seg_info;             // [nseg * 8] per-segment counters / offsets
     uint8_t* dom;                  // [n] dominated flags
     int32_t* tile_off;             // [2 * (nseg + 1)] item-tile offsets for head / rest
-    int32_t* counters;             // [16] global counters
+    int32_t* counters;             // [3 * 16]: the output count, then two per-round sets
     unsigned long long* tests;     // [2] dominance-test counters
     int32_t* flag; int32_t* scan;  // [n] stable-compaction scratch
     int32_t* scan_tmp;             // scan scratch for n values
@@ -214,6 +214,8 @@ struct EngineProblem {
     void* const* ev_end;
     int32_t ev_cap;
     int32_t* ev_used;              // host counter, advanced per recorded pair
+    int32_t* host_scratch;         // optional pinned host memory (2 x 16 int32): with it and the
+    void* round_events[2];         // two events, rounds are launched one ahead of the readback
 };
 struct EngineResult { int32_t count; int32_t rounds; int64_t tests; };
 sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,

@@ -33,6 +33,8 @@ struct sky_plan {
     void* const* ev_end = nullptr;
     int32_t ev_cap = 0;
     int32_t ev_used = 0;
+    int32_t* host_scratch = nullptr;     // caller's pinned host memory (sky_plan_set_host_scratch)
+    void* round_ev[2] = {nullptr, nullptr};
     sky_info info{};
 };
 

@@ -51,7 +51,7 @@ constexpr int kDense = 32;              // items passing a tile's box from which
 // seg_info layout per segment (int32 x kInfo)
 enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, SI_HEADPRE, kInfo = 8 };
 // global counters
-enum { C_NEXT = 0, C_OUT, C_HTILES, C_RTILES, C_MAXH, C_HTOT, C_RTOT, kCounters = 16 };
+enum { C_NEXT = 0, C_OUT, C_HTILES, C_RTILES, C_MAXH, C_HTOT, C_RTOT, C_TPUH, C_TPUR, kCounters = 16 };
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -103,12 +103,14 @@ __global__ void init_segments_kernel(int32_t nseg, uint32_t* __restrict__ smin,
     if (i == 0) counters[C_NEXT] = 0;
 }
 
-__global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restrict__ items, int32_t n,
+__global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restrict__ items,
+                                                         int32_t n_host, const int32_t* __restrict__ n_dev,
                                                          const float* __restrict__ fsum,
                                                          const int32_t* __restrict__ seg_of_pos,
                                                          uint32_t* __restrict__ smin,
                                                          uint32_t* __restrict__ smax,
                                                          int32_t* __restrict__ info) {
+    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     const bool valid = i < n;
     int32_t s = 0;
@@ -157,12 +159,14 @@ __device__ __forceinline__ int32_t item_bin(const float* fsum, const uint32_t* s
     return bin_of(fsum[pos], __uint_as_float(smin[s]), seg_scale(smin[s], smax[s]));
 }
 
-__global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict__ items, int32_t n,
+__global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict__ items,
+                                                       int32_t n_host, const int32_t* __restrict__ n_dev,
                                                        const float* __restrict__ fsum,
                                                        const int32_t* __restrict__ seg_of_pos,
                                                        const uint32_t* __restrict__ smin,
                                                        const uint32_t* __restrict__ smax,
                                                        int32_t* __restrict__ hist) {
+    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int32_t pos = items[i];
@@ -172,11 +176,13 @@ __global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict_
 
 // Single-segment variants (the merge phase and unpartitioned data): grid-stride loops with
 // block-private LDS bins / block reductions, so that global atomics stay few.
-__global__ void __launch_bounds__(kBlock) minmax1_kernel(const int32_t* __restrict__ items, int32_t n,
+__global__ void __launch_bounds__(kBlock) minmax1_kernel(const int32_t* __restrict__ items,
+                                                          int32_t n_host, const int32_t* __restrict__ n_dev,
                                                           const float* __restrict__ fsum,
                                                           uint32_t* __restrict__ smin,
                                                           uint32_t* __restrict__ smax,
                                                           int32_t* __restrict__ info) {
+    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     __shared__ uint32_t rmin[kBlock / kWave], rmax[kBlock / kWave];
     __shared__ int32_t rcnt[kBlock / kWave];
     uint32_t vmin = 0xFFFFFFFFu, vmax = 0u;
@@ -210,12 +216,14 @@ __global__ void __launch_bounds__(kBlock) minmax1_kernel(const int32_t* __restri
     }
 }
 
-__global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict__ items, int32_t n,
+__global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict__ items,
+                                                        int32_t n_host, const int32_t* __restrict__ n_dev,
                                                         const float* __restrict__ fsum,
                                                         const uint32_t* __restrict__ smin,
                                                         const uint32_t* __restrict__ smax,
                                                         int32_t* __restrict__ hist,
                                                         int32_t* __restrict__ info, int32_t count_live) {
+    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     __shared__ int32_t h[kBins];
     if (count_live && threadIdx.x == 0) {
         // items this block visits (grid-stride), added once per block
@@ -274,8 +282,7 @@ __global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32
 // Per segment: list offset (scan of live counts), 64-aligned head offset (scan of head counts
 // rounded up to 64), rest offset, and the item-tile offsets of both groups; round totals.
 // Single workgroup, sequential over blocks of 256 segments.
-__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32_t tpu_h,
-                                                              int32_t tpu_r,
+__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg,
                                                               int32_t* __restrict__ info,
                                                               int32_t* __restrict__ tile_off,
                                                               int32_t* __restrict__ counters,
@@ -285,6 +292,43 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
         for (int32_t s = threadIdx.x / kWave; s < nseg; s += kBlock / kWave) thresh_segment(s, hist, info);
         __syncthreads();
     }
+    // tiles per unit of the test launch, from the exact counts: split the head tiles of an item
+    // group over several units when there are too few groups to fill the chip (kTargetWaves)
+    __shared__ int64_t red[3][kBlock / kWave];
+    {
+        int64_t gh = 0, gr = 0, mt = 0;
+        for (int32_t s = threadIdx.x; s < nseg; s += kBlock) {
+            const int32_t hn = info[s * kInfo + SI_HEADN], rn = info[s * kInfo + SI_RESTN];
+            gh += (hn + kBlock - 1) / kBlock;
+            gr += (rn + kBlock - 1) / kBlock;
+            const int64_t nt = (hn + kTile - 1) / kTile;
+            mt = nt > mt ? nt : mt;
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            gh += __shfl_xor(gh, off, kWave);
+            gr += __shfl_xor(gr, off, kWave);
+            const int64_t o = __shfl_xor(mt, off, kWave);
+            mt = o > mt ? o : mt;
+        }
+        if (lane_id() == 0) {
+            red[0][threadIdx.x / kWave] = gh;
+            red[1][threadIdx.x / kWave] = gr;
+            red[2][threadIdx.x / kWave] = mt;
+        }
+    }
+    __syncthreads();
+    int64_t gh = 0, gr = 0, mt = 1;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        gh += red[0][w];
+        gr += red[1][w];
+        mt = red[2][w] > mt ? red[2][w] : mt;
+    }
+    constexpr int64_t kWantUnits = kTargetWaves / (kBlock / kWave);
+    auto tpu_of = [&](int64_t groups) -> int32_t {
+        const int64_t t = (groups * mt + kWantUnits - 1) / kWantUnits;
+        return (int32_t)(t < 1 ? 1 : (t > mt ? mt : t));
+    };
+    const int32_t tpu_h = tpu_of(gh), tpu_r = tpu_of(gr);
     constexpr int Q = 6;
     __shared__ int32_t carry[Q];
     __shared__ int32_t wsum[Q][kBlock / kWave];
@@ -357,6 +401,8 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg, int32
         counters[C_MAXH] = maxh;
         counters[C_HTOT] = carry[0];
         counters[C_RTOT] = carry[1];
+        counters[C_TPUH] = tpu_h;
+        counters[C_TPUR] = tpu_r;
     }
 }
 
@@ -410,9 +456,11 @@ __device__ __forceinline__ bool is_head(const int32_t* items, int32_t i, const f
 }
 
 __global__ void __launch_bounds__(kBlock) split_count_kernel(
-    const int32_t* __restrict__ items, int32_t n, const float* __restrict__ fsum,
+    const int32_t* __restrict__ items,
+    int32_t n_host, const int32_t* __restrict__ n_dev, const float* __restrict__ fsum,
     const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
     const uint32_t* __restrict__ smax, const int32_t* __restrict__ info, int32_t* __restrict__ bcnt) {
+    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     __shared__ int32_t part[kBlock / kWave];
     const int wave = threadIdx.x / kWave;
     const int lane = (int)lane_id();
@@ -435,11 +483,13 @@ __global__ void __launch_bounds__(kBlock) split_count_kernel(
 // head entries -> their segment's head group, the others -> its rest group, both in list order;
 // every item's dominated flag is cleared
 __global__ void __launch_bounds__(kBlock) split_scatter_kernel(
-    const int32_t* __restrict__ items, int32_t n, const float* __restrict__ fsum,
+    const int32_t* __restrict__ items,
+    int32_t n_host, const int32_t* __restrict__ n_dev, const float* __restrict__ fsum,
     const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
     const uint32_t* __restrict__ smax, const int32_t* __restrict__ info,
     const int32_t* __restrict__ bcnt, int32_t* __restrict__ head, int32_t* __restrict__ rest,
     uint8_t* __restrict__ dom) {
+    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     __shared__ int32_t chunk_cnt[kCChunks];
     const int wave = threadIdx.x / kWave;
     const int lane = (int)lane_id();
@@ -483,7 +533,8 @@ __global__ void __launch_bounds__(kBlock) rest_count_kernel(const int32_t* __res
                                                              int32_t* __restrict__ bcnt, int32_t cblocks,
                                                              const int32_t* __restrict__ head,
                                                              uint8_t* __restrict__ flag_out,
-                                                             int32_t* __restrict__ out_list) {
+                                                             int32_t* __restrict__ out_list,
+                                                             int32_t* __restrict__ out_count) {
     if ((int32_t)blockIdx.x >= cblocks) {
         const int32_t htot = counters[C_HTOT];
         const int32_t nb = (int32_t)gridDim.x - cblocks;
@@ -495,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) rest_count_kernel(const int32_t* __res
                 pos = head[i];
                 keep = pos >= 0 && dom[pos] == 0;
             }
-            const int32_t os = wave_slot(counters + C_OUT, 0, 0, keep);
+            const int32_t os = wave_slot(out_count, 0, 0, keep);
             if (keep) {
                 flag_out[pos] = 1;
                 out_list[os] = pos;
@@ -639,7 +690,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     const int32_t* __restrict__ unit_off_all, const int32_t* __restrict__ info,
     const int32_t* __restrict__ head, const int32_t* __restrict__ rest,
     const uint32_t* __restrict__ hval, int64_t hcap, const uint32_t* __restrict__ hlo,
-    const uint32_t* __restrict__ hhi, int64_t tcap, int32_t tpu_h, int32_t tpu_r,
+    const uint32_t* __restrict__ hhi, int64_t tcap, const int32_t* __restrict__ round_counters,
     uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     __shared__ uint32_t box[kBoxLds];  // [2][k][ntile] tile boxes (lo, hi) of the current segment
@@ -648,6 +699,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
+    const int32_t tpu_h = round_counters[C_TPUH], tpu_r = round_counters[C_TPUR];
     const int32_t nunits_h = unit_off_all[nseg];
     const int32_t nunits = nunits_h + unit_off_all[(nseg + 1) + nseg];
     int32_t cached = -1;  // segment whose boxes are in LDS (uniform per workgroup)
@@ -929,11 +981,11 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
     res->rounds = 0;
     res->tests = 0;
     const int32_t nseg = pb.nseg;
-    int32_t live = pb.n_items;
-    const int32_t* cur = pb.items;
-    int32_t* next = b.w0;
-    int32_t* other = b.w1;
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, b.counters, (int32_t)kCounters);
+    // counters: [0, kCounters) hold the output count; two per-round sets alternate after it, so
+    // a round launched ahead never overwrites the counters of the round being read back
+    int32_t* const out_count = b.counters + C_OUT;
+    auto round_counters = [&](int32_t r) { return b.counters + kCounters * (1 + (r & 1)); };
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, b.counters, (int32_t)(3 * kCounters));
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, b.tests, 2);
     hipLaunchKernelGGL(pad_slots_kernel, dim3((uint32_t)ceil_div(pb.d * kTile, 256)), dim3(256), 0, st,
                        b.hval, b.hcap, pb.d);
@@ -946,104 +998,154 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         if (!begin) ++*pb.ev_used;
         return r;
     };
-    int guard = 0;
-    while (live > 0) {
-        if (++guard > 1000000) return SKY_ERR_HIP;
-        res->rounds++;
-        const uint32_t iblocks = (uint32_t)ceil_div(live, kBlock);
+    auto grid = [](int64_t want) -> uint32_t {
+        return (uint32_t)(want < 1 ? 1 : (want > kMaxGrid ? kMaxGrid : want));
+    };
+    const int32_t* lists[2] = {b.w0, b.w1};
+    // Round r (1-based) reads list `cur` and writes the next one. Its item count is n_host for
+    // the first round, else the previous round's C_NEXT on the device (n_dev); ub bounds it
+    // from above and only sizes grids and work splits.
+    auto launch_round = [&](int32_t r, const int32_t* cur, int32_t* next, int32_t n_host,
+                            const int32_t* n_dev, int64_t ub) -> sky_status {
+        int32_t* cnt = round_counters(r);
+        const uint32_t iblocks = (uint32_t)ceil_div(ub, kBlock);
         const int64_t hn = (int64_t)nseg * kBins;
         // one segment: the score range of the first round serves every round (the live rows
         // only ever shrink), so later rounds skip the min/max pass and count rows in hist1
-        const bool first = res->rounds == 1;
+        const bool first = r == 1;
         hipLaunchKernelGGL(init_segments_kernel, dim3((uint32_t)ceil_div(hn > nseg ? hn : nseg, 256)),
-                           dim3(256), 0, st, nseg, b.seg_min, b.seg_max, b.hist, b.seg_info,
-                           b.counters, (int32_t)(nseg > 1 || first));
+                           dim3(256), 0, st, nseg, b.seg_min, b.seg_max, b.hist, b.seg_info, cnt,
+                           (int32_t)(nseg > 1 || first));
         if (nseg == 1) {
             const uint32_t sblocks = iblocks < 256 ? iblocks : 256;
             if (first)
-                hipLaunchKernelGGL(minmax1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                                   b.seg_min, b.seg_max, b.seg_info);
-            hipLaunchKernelGGL(hist1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                               (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist,
+                hipLaunchKernelGGL(minmax1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+                                   pb.fsum, b.seg_min, b.seg_max, b.seg_info);
+            hipLaunchKernelGGL(hist1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+                               pb.fsum, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist,
                                b.seg_info, (int32_t)!first);
         } else {
-            hipLaunchKernelGGL(minmax_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                               pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
-            hipLaunchKernelGGL(hist_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                               pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                               b.hist);
+            hipLaunchKernelGGL(minmax_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+                               pb.fsum, pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
+            hipLaunchKernelGGL(hist_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+                               pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min,
+                               (const uint32_t*)b.seg_max, b.hist);
         }
         const bool fused_thresh = nseg <= kBlock / kWave;
         if (!fused_thresh)
             hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)nseg), dim3(kWave), 0, st, nseg,
                                (const int32_t*)b.hist, b.seg_info);
-        // tiles per unit: split the head tiles of an item group over several units when there
-        // are too few item groups to fill the chip (kTargetWaves waves)
-        const int64_t head_est = (int64_t)nseg * kHead < live ? (int64_t)nseg * kHead : live;
-        int64_t ntile_est = ceil_div(live, (int64_t)kTile * nseg) + 1;
-        if (ntile_est > kHead / kTile + 2) ntile_est = kHead / kTile + 2;
-        auto tpu_for = [&](int64_t items) -> int32_t {
-            const int64_t groups = ceil_div(items, kBlock) + nseg;
-            const int64_t want = kTargetWaves / (kBlock / kWave);
-            int64_t t = ceil_div(groups * ntile_est, want);
-            return (int32_t)(t < 1 ? 1 : (t > (1 << 20) ? (1 << 20) : t));
-        };
-        const int32_t tpu_h = tpu_for(head_est), tpu_r = tpu_for(live);
-        auto units_est = [&](int64_t items, int32_t tpu) -> int64_t {
-            return (ceil_div(items, kBlock) + nseg) * ceil_div(ntile_est, tpu);
-        };
-        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg, tpu_h, tpu_r,
-                           b.seg_info, b.tile_off, b.counters, (const int32_t*)b.hist,
-                           (int32_t)fused_thresh);
-        const uint32_t cblocks = (uint32_t)ceil_div(live, kCItems);
-        hipLaunchKernelGGL(split_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                           pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
+        // (the offsets kernel also picks the test launch's work split from the exact counts)
+        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg, b.seg_info, b.tile_off,
+                           cnt, (const int32_t*)b.hist, (int32_t)fused_thresh);
+        const uint32_t cblocks = (uint32_t)ceil_div(ub, kCItems);
+        hipLaunchKernelGGL(split_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+                           pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
                            (const int32_t*)b.seg_info, b.scan);
-        hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, live, pb.fsum,
-                           pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
+        hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+                           pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
                            (const int32_t*)b.seg_info, (const int32_t*)b.scan, b.head, b.rest, b.dom);
         SKY_HIP(hipGetLastError());
-        // grid sizes from host-side bounds; the kernels read the exact counts on the device
-        auto grid = [](int64_t want) -> uint32_t {
-            return (uint32_t)(want < 1 ? 1 : (want > kMaxGrid ? kMaxGrid : want));
-        };
-        const int64_t slot_bound = live + (int64_t)kTile * nseg;
+        const int64_t slot_bound = ub + (int64_t)kTile * nseg;
         SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
                        dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.seg_info,
-                       (const int32_t*)b.counters, b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
+                       (const int32_t*)cnt, b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
         SKY_HIP(hipGetLastError());
         // one launch: the head skyline (every head row against the head rows of its segment)
         // and the filter of the rest against the same head rows -- independent tests
         SKY_HIP(ev_rec(true));
-        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(units_est(head_est, tpu_h) + units_est(live, tpu_r))),
+        // grid-stride: enough workgroups for the split the device picks (about kTargetWaves
+        // waves), or one per item group when there are more
+        const int64_t want_wg = kTargetWaves / (kBlock / kWave);
+        const int64_t groups_ub = ceil_div(ub, kBlock) + 2 * (int64_t)nseg;
+        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(groups_ub + 2 * want_wg)),
                        dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
                        (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.rest,
                        (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi,
-                       b.tcap, tpu_h, tpu_r, b.dom, b.tests);
+                       b.tcap, (const int32_t*)cnt, b.dom, b.tests);
         SKY_HIP(ev_rec(false));
         // the survivors of the rest groups, in order, are the next round's work list
         // (and the head survivors into the output, in extra blocks of the same launch)
         const uint32_t hblocks = grid(ceil_div(slot_bound, kBlock));
         hipLaunchKernelGGL(rest_count_kernel, dim3(cblocks + hblocks), dim3(kBlock), 0, st,
-                           (const int32_t*)b.rest, b.counters, (const uint8_t*)b.dom, b.scan,
-                           (int32_t)cblocks, (const int32_t*)b.head, pb.flag_out, out_list);
+                           (const int32_t*)b.rest, cnt, (const uint8_t*)b.dom, b.scan, (int32_t)cblocks,
+                           (const int32_t*)b.head, pb.flag_out, out_list, out_count);
         hipLaunchKernelGGL(rest_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, (const int32_t*)b.rest,
-                           b.counters, (const uint8_t*)b.dom, (const int32_t*)b.scan, next);
+                           cnt, (const uint8_t*)b.dom, (const int32_t*)b.scan, next);
         SKY_HIP(hipGetLastError());
-        int32_t cnt[kCounters];
-        SKY_HIP(hipMemcpyAsync(cnt, b.counters, sizeof(cnt), hipMemcpyDeviceToHost, st));
-        SKY_HIP(hipStreamSynchronize(st));
-        const int32_t htot = cnt[C_HTOT], rtot = cnt[C_RTOT], nl = cnt[C_NEXT];
-        if (htot <= 0 || htot > b.hcap || rtot < 0 || rtot >= live) return SKY_ERR_HIP;
+        return SKY_OK;
+    };
+    // after round r: check its counters (exact input count in_r) and return its output count
+    auto check_round = [&](const int32_t* c, int64_t in_r, int32_t* nl_out) -> sky_status {
+        const int32_t htot = c[C_HTOT], rtot = c[C_RTOT], nl = c[C_NEXT];
+        if (htot <= 0 || htot > b.hcap || rtot < 0 || rtot >= in_r) return SKY_ERR_HIP;
         // every round removes the head rows from the live set
-        if (nl < 0 || nl >= live || nl > rtot) return SKY_ERR_HIP;
-        live = nl;
-        cur = next;
-        int32_t* t = next; next = other; other = t;
+        if (nl < 0 || nl >= in_r || nl > rtot) return SKY_ERR_HIP;
+        *nl_out = nl;
+        return SKY_OK;
+    };
+    int32_t live = pb.n_items;
+    if (live > 0) {
+        // round r reads lists[(r + 1) & 1] (the caller's list for r = 1) and writes lists[r & 1]
+        auto list_in = [&](int32_t r) { return r == 1 ? pb.items : lists[(r + 1) & 1]; };
+        auto list_out = [&](int32_t r) { return const_cast<int32_t*>(lists[r & 1]); };
+        const bool ahead = pb.host_scratch && pb.round_events[0] && pb.round_events[1];
+        int64_t ub_next = 0;  // bound on the input of the round after the last one launched
+        auto bound_after = [&](int64_t in) -> int64_t {
+            // a round takes at least min(kHead, live) rows of a lone segment into its head
+            if (nseg == 1) return in > kHead ? in - kHead : 0;
+            return in > 0 ? in - 1 : 0;
+        };
+        SKY_TRY(launch_round(1, list_in(1), list_out(1), live, nullptr, live));
+        int32_t launched = 1;
+        int64_t in_r = live;  // exact input count of the oldest round not yet checked
+        for (int32_t r = 1;; ++r) {
+            if (r > 1000000) return SKY_ERR_HIP;
+            int32_t* hs = ahead ? pb.host_scratch + kCounters * (r & 1) : nullptr;
+            if (ahead) {
+                SKY_HIP(hipMemcpyAsync(hs, round_counters(r), sizeof(int32_t) * kCounters,
+                                       hipMemcpyDeviceToHost, st));
+                SKY_HIP(hipEventRecord((hipEvent_t)pb.round_events[r & 1], st));
+                // launch the next round before waiting for this one: its kernels read their
+                // item count on the device and are sized by an upper bound
+                ub_next = bound_after(launched == r ? in_r : ub_next);
+                if (ub_next > 0) {
+                    SKY_TRY(launch_round(r + 1, list_in(r + 1), list_out(r + 1), 0,
+                                         round_counters(r) + C_NEXT, ub_next));
+                    launched = r + 1;
+                }
+                SKY_HIP(hipEventSynchronize((hipEvent_t)pb.round_events[r & 1]));
+            } else {
+                int32_t c[kCounters];
+                SKY_HIP(hipMemcpyAsync(c, round_counters(r), sizeof(c), hipMemcpyDeviceToHost, st));
+                SKY_HIP(hipStreamSynchronize(st));
+                hs = c;
+                int32_t nl = 0;
+                SKY_TRY(check_round(hs, in_r, &nl));
+                res->rounds = r;
+                if (nl == 0) break;
+                SKY_TRY(launch_round(r + 1, list_in(r + 1), list_out(r + 1), nl, nullptr, nl));
+                launched = r + 1;
+                in_r = nl;
+                continue;
+            }
+            int32_t nl = 0;
+            SKY_TRY(check_round(hs, in_r, &nl));
+            res->rounds = r;
+            if (nl == 0) break;  // a round launched ahead found nothing to do
+            if (launched == r) {
+                SKY_TRY(launch_round(r + 1, list_in(r + 1), list_out(r + 1), nl, nullptr, nl));
+                launched = r + 1;
+            } else if (nl > ub_next) {
+                return SKY_ERR_HIP;  // the bound the launched round was sized with was wrong
+            }
+            in_r = nl;
+            ub_next = nl;
+        }
     }
     int32_t outc = 0;
     unsigned long long tests[2] = {0, 0};
-    SKY_HIP(hipMemcpyAsync(&outc, b.counters + C_OUT, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SKY_HIP(hipMemcpyAsync(&outc, out_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SKY_HIP(hipMemcpyAsync(tests, b.tests, sizeof(tests), hipMemcpyDeviceToHost, st));
     SKY_HIP(hipStreamSynchronize(st));
     res->count = outc;
