@@ -8,12 +8,14 @@ their tile boxes, from which every level's keys are one FP32 multiply away).
 
 Scheduling (``Server``):
   * arrivals wait in a FIFO queue;
-  * a query is admitted when a slot (one HIP stream with its own pinned staging buffers) is
-    free AND its device memory -- target indices, search workspace, outputs -- fits in what is
-    left of the HBM budget (an arena of ``budget_bytes`` carved first-fit); queries that do not
-    fit wait, and later queries never overtake them (no starvation);
-  * an admitted query's upload, search and download are queued on its slot's stream, so up to
-    ``slots`` queries run on the device at once, overlapping each other;
+  * when a slot (one HIP stream with its own pinned staging buffers) is free, the oldest
+    queued query is admitted together with the later queued queries for the same relation (one
+    search launch over their concatenated tuples), if the batch's device memory -- target
+    indices, search workspace, outputs -- fits in what is left of the HBM budget (an arena of
+    ``budget_bytes`` carved first-fit); the batch shrinks to fit, and if even the oldest query
+    does not fit, everything waits (the oldest query is never overtaken: no starvation);
+  * a batch's upload, search and download are queued on its slot's stream, so up to ``slots``
+    batches run on the device at once, overlapping each other;
   * completions are detected by polling events, which frees the slot and the arena range and
     admits more work at once.
 Latency is arrival -> completion as the host observes it.
@@ -145,43 +147,57 @@ def _query_bytes(nt, d):
 
 
 class _Slot:
-    def __init__(self, device, max_nt):
+    def __init__(self, device, cap):
         self.stream = torch.cuda.Stream(device)
-        self.h_targets = torch.empty(max_nt, dtype=torch.int64, pin_memory=True)
-        self.h_out = torch.empty(max_nt + 1, dtype=torch.int32, pin_memory=True)
+        self.h_targets = torch.empty(cap, dtype=torch.int64, pin_memory=True)
+        self.h_out = torch.empty(cap + 1, dtype=torch.int32, pin_memory=True)
         self.event = torch.cuda.Event()
-        self.query = None
+        self.batch = None
         self.rng = None
 
 
 class Server:
-    """Continuous batching of gres queries under an HBM budget (see the module docstring)."""
+    """Continuous batching of gres queries under an HBM budget (see the module docstring).
 
-    def __init__(self, residents, budget_bytes=64 << 20, slots=4, device="cuda"):
+    When a slot frees, the oldest queued query is admitted together with the later queued
+    queries for the same relation and g_max (up to ``max_batch`` queries and ``max_targets``
+    tuples), as ONE search launch over their concatenated tuples; each query's answer is its
+    slice of the result. The oldest queued query is always in the next batch admitted."""
+
+    def __init__(self, residents, budget_bytes=64 << 20, slots=4, device="cuda", max_batch=64,
+                 max_targets=1 << 16):
         self.res = residents
         self.device = torch.device(device)
         max_nt = max(r.s for r in residents)
+        self.cap = max(max_nt, int(max_targets))
+        self.max_batch = int(max_batch)
         self.arena = Arena(budget_bytes, self.device)
-        self.slots = [_Slot(self.device, max_nt) for _ in range(slots)]
+        self.slots = [_Slot(self.device, self.cap) for _ in range(slots)]
         self.queue = []
         self.completed = []
         self.peak_used = 0
         self.max_in_flight = 0
         self.admit_order = []
+        self.batch_log = []   # (oldest queued qid at admission, qids of the batch)
         for r in residents:  # the largest query of any relation must fit the budget alone
-            _, parts = _query_bytes(r.s, r.d)
-            if sum(-(-p // Arena.ALIGN) * Arena.ALIGN for p in parts) > budget_bytes:
+            if self._footprint(r.s, r.d) > budget_bytes:
                 raise ValueError("budget_bytes below the largest query's footprint")
 
-    def _launch(self, slot, q, rng, now):
+    @staticmethod
+    def _footprint(nt, d):
+        _, parts = _query_bytes(nt, d)
+        return sum(-(-p // Arena.ALIGN) * Arena.ALIGN for p in parts)
+
+    def _launch(self, slot, batch, rng, now):
         lib = _lib.load()
-        r = self.res[q.rel]
-        nt = len(q.targets)
+        q0 = batch[0]
+        r = self.res[q0.rel]
+        nt = sum(len(q.targets) for q in batch)
         ws_bytes, parts = _query_bytes(nt, r.d)
         offs = np.cumsum([0] + [-(-p // Arena.ALIGN) * Arena.ALIGN for p in parts])
         st = slot.stream
         with torch.cuda.stream(st):
-            slot.h_targets[:nt].copy_(torch.from_numpy(q.targets))
+            slot.h_targets[:nt].copy_(torch.from_numpy(np.concatenate([q.targets for q in batch])))
             d_targets = self.arena.view(rng, torch.int64, nt, int(offs[0]))
             d_ge = self.arena.view(rng, torch.int32, nt, int(offs[1]))
             d_status = self.arena.view(rng, torch.int32, 1, int(offs[2]))
@@ -190,50 +206,73 @@ class Server:
             d_status.zero_()
             opts = _lib.GresOpts(_lib.SKY_GRES_AUTO)
             _lib.check(lib.gres_search(_ptr(r.prep.prep), r.s, r.d, _ptr(r.x_soa), r.n,
-                                       r.x_soa.stride(0), _ptr(d_targets), nt, q.g_max,
+                                       r.x_soa.stride(0), _ptr(d_targets), nt, q0.g_max,
                                        _ptr(d_ge), None, _ptr(d_ws), ws_bytes, _ptr(d_status),
                                        C.byref(opts), C.c_void_p(st.cuda_stream)), "gres_search")
             slot.h_out[:nt].copy_(d_ge, non_blocking=True)
             slot.h_out[nt:nt + 1].copy_(d_status, non_blocking=True)
             slot.event.record(st)
-        slot.query, slot.rng = q, rng
-        q.admitted = now
+        slot.batch, slot.rng = batch, rng
+        for q in batch:
+            q.admitted = now
 
     def _retire(self, slot, now):
-        q = slot.query
-        nt = len(q.targets)
+        batch = slot.batch
+        nt = sum(len(q.targets) for q in batch)
         code = int(slot.h_out[nt])
         if code != _lib.SKY_OK:
-            raise _lib.SkyError(code, f"query {q.qid}")
-        q.g_exit = slot.h_out[:nt].numpy().copy()
-        q.done = now
+            raise _lib.SkyError(code, f"queries {[q.qid for q in batch]}")
+        out = slot.h_out[:nt].numpy()
+        o = 0
+        for q in batch:
+            q.g_exit = out[o:o + len(q.targets)].copy()
+            o += len(q.targets)
+            q.done = now
+            self.completed.append(q)
         self.arena.release(slot.rng)
-        slot.query, slot.rng = None, None
-        self.completed.append(q)
+        slot.batch, slot.rng = None, None
+
+    def _gather(self):
+        """The next batch: the oldest queued query and later ones for the same relation and
+        g_max, within the batch limits."""
+        head = self.queue[0]
+        batch, nt = [head], len(head.targets)
+        for q in self.queue[1:]:
+            if len(batch) >= self.max_batch:
+                break
+            if q.rel == head.rel and q.g_max == head.g_max and nt + len(q.targets) <= self.cap:
+                batch.append(q)
+                nt += len(q.targets)
+        return batch, nt
 
     def poll(self, now):
-        """Retire finished queries, then admit queued ones while a slot and memory are free."""
+        """Retire finished batches, then admit queued queries while a slot and memory are free."""
         for slot in self.slots:
-            if slot.query is not None and slot.event.query():
+            if slot.batch is not None and slot.event.query():
                 self._retire(slot, now)
         while self.queue:
-            slot = next((s for s in self.slots if s.query is None), None)
+            slot = next((s for s in self.slots if s.batch is None), None)
             if slot is None:
                 break
-            q = self.queue[0]
-            r = self.res[q.rel]
-            _, parts = _query_bytes(len(q.targets), r.d)
-            rng = self.arena.alloc(sum(-(-p // Arena.ALIGN) * Arena.ALIGN for p in parts))
+            batch, nt = self._gather()
+            d = self.res[batch[0].rel].d
+            rng = self.arena.alloc(self._footprint(nt, d))
+            while rng is None and len(batch) > 1:  # shrink the batch, never skip its head
+                nt -= len(batch[-1].targets)
+                batch.pop()
+                rng = self.arena.alloc(self._footprint(nt, d))
             if rng is None:
-                break  # FIFO: wait for memory rather than let later queries overtake
-            self.queue.pop(0)
-            self._launch(slot, q, rng, now)
-            self.admit_order.append(q.qid)
+                break  # wait for memory rather than let later queries overtake the oldest
+            self.batch_log.append((self.queue[0].qid, [q.qid for q in batch]))
+            taken = {id(q) for q in batch}
+            self.queue = [q for q in self.queue if id(q) not in taken]
+            self._launch(slot, batch, rng, now)
+            self.admit_order.extend(q.qid for q in batch)
             self.peak_used = max(self.peak_used, self.arena.used)
-        self.max_in_flight = max(self.max_in_flight, sum(s.query is not None for s in self.slots))
+        self.max_in_flight = max(self.max_in_flight, sum(s.batch is not None for s in self.slots))
 
     def busy(self):
-        return bool(self.queue) or any(s.query is not None for s in self.slots)
+        return bool(self.queue) or any(s.batch is not None for s in self.slots)
 
     def run_trace(self, queries, clock=time.perf_counter):
         """Replay arrivals in real time (queries sorted by arrival); returns completed queries."""

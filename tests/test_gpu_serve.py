@@ -55,6 +55,7 @@ def test_mix_equals_alone_equals_oracle(dev, residents, relations):
     assert len(done) == len(trace)
     _say("mix:", latency_stats(done), "max in flight", srv.max_in_flight, "peak bytes", srv.peak_used)
     assert srv.max_in_flight >= 2          # work really overlapped
+    assert max(len(b) for _, b in srv.batch_log) >= 2  # queries really shared launches
     assert srv.peak_used <= 2 * largest    # the budget held
     mix = {q.qid: q.g_exit for q in done}
     alone = PlainServer(residents, device=dev)
@@ -74,7 +75,8 @@ def test_budget_below_largest_query_rejected(dev, residents):
 
 
 def test_fifo_admission_under_budget(dev, residents):
-    # budget for exactly one of the largest queries: big queries run one at a time, in order
+    # budget for exactly one of the largest queries: batches shrink to fit, the oldest query
+    # is never overtaken
     big = max(range(len(residents)), key=lambda i: residents[i].s)
     r = residents[big]
     largest = sum(-(-p // 256) * 256 for p in _query_bytes(r.s, r.d)[1])
@@ -82,5 +84,13 @@ def test_fifo_admission_under_budget(dev, residents):
     srv = Server(residents, budget_bytes=largest, slots=4, device=dev)
     done = srv.run_trace(trace)
     assert len(done) == len(trace)
-    assert srv.admit_order == [q.qid for q in trace]
+    assert sorted(srv.admit_order) == [q.qid for q in trace]
+    # every batch starts with the oldest query still queued, and holds one relation
+    admitted = set()
+    rel = {q.qid: q.rel for q in trace}
+    for oldest, qids in srv.batch_log:
+        assert qids[0] == oldest
+        assert oldest == min(q.qid for q in trace if q.qid not in admitted)
+        assert len({rel[x] for x in qids}) == 1
+        admitted.update(qids)
     assert srv.peak_used <= largest
