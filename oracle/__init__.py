@@ -52,6 +52,9 @@ def _load():
                                  C.c_int64, C.c_int32, _i32p]),
         "orc_skyline_rows": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, _i64p, C.c_int64, _u8p]),
         "orc_key": (C.c_int32, [C.c_float, C.c_int32]),
+        "orc_ell": (C.c_double, [_f32p, C.c_int64, C.c_int32, C.c_int64]),
+        "orc_ell_sorted": (C.c_double, [_f32p, C.c_int64, C.c_int32, C.c_int64]),
+        "orc_gbar": (C.c_double, [C.c_double]),
         "orc_num_threads": (C.c_int32, []),
     }
     for name, (res, args) in sig.items():
@@ -177,6 +180,20 @@ def gres_rows(x, cand, targets, g_max: int) -> np.ndarray:
     _load().orc_gres_rows(_p(xs, _f32p), n, d, n, _p(cand, _i64p), len(cand), _p(targets, _i64p),
                           len(targets), g_max, _p(ge, _i32p))
     return ge
+
+
+def ell(x, sorted_: bool = False) -> float:
+    """Sec. 3.2's ell: the smallest non-zero difference between two values of one attribute
+    (FP64 differences), +inf when there is none. ``sorted_`` uses the sort-based form."""
+    xs, n, d = _soa(x)
+    fn = _load().orc_ell_sorted if sorted_ else _load().orc_ell
+    return float(fn(_p(xs, _f32p), n, d, n))
+
+
+def gbar(x, sorted_: bool = True):
+    """(ell, g_bar) with g_bar = floor(1/ell) as a Python int (1 when ell is +inf)."""
+    e = ell(x, sorted_)
+    return e, int(_load().orc_gbar(e))
 
 
 def gres_values(g_exit) -> np.ndarray:

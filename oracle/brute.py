@@ -60,3 +60,25 @@ def gres_g_exit(x, g_max: int, mode: str = "fp32") -> dict:
             if proj[i] not in proj_sky[g]:
                 out[i] = max(out.get(i, 1), g)  # min 1/g over exit levels = 1/(max g)
     return {int(i): out.get(int(i), 1) for i in np.flatnonzero(member)}
+
+
+def ell_exact(x):
+    """Sec. 3.2's ell in exact rationals, over every pair of rows and every attribute: the
+    smallest non-zero |a - b| between two values of one attribute, or None if there is none."""
+    x = np.asarray(x, dtype=np.float32)
+    best = None
+    n = len(x)
+    for k in range(x.shape[1] if x.ndim == 2 else 0):
+        col = [Fraction(float(v)) for v in x[:, k]]
+        for i in range(n):
+            for j in range(i + 1, n):
+                e = abs(col[i] - col[j])
+                if e != 0 and (best is None or e < best):
+                    best = e
+    return best
+
+
+def gbar_exact(x) -> int:
+    """g_bar = floor(1/ell) in exact rationals (1 when ell does not exist)."""
+    e = ell_exact(x)
+    return 1 if e is None else (1 / e).__floor__()

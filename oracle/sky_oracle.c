@@ -26,6 +26,10 @@
  *                              and exact rationals; the worked counterexample; invariants).
  *   orc_gres_rows           -- pinned (equals orc_gres on the sampled rows).
  *   orc_skyline_rows        -- pinned (equals orc_skyline on the sampled rows).
+ *   orc_ell, orc_ell_sorted -- pinned (exact-rational brute force over pairs on tiny inputs, a
+ *                              hand-worked lattice example, degenerate inputs; the two agree).
+ *   orc_gbar                -- pinned (floor(1/ell) in exact rationals; on lattice data no exit
+ *                              appears beyond g_bar, checked by the exact brute force).
  *   test counts (orc_skyline_sfs return value, orc_gres *tests) -- "parity unpinned": they
  *                              depend on the scan order; reported, never compared.
  */
@@ -360,6 +364,57 @@ void orc_skyline_rows(const float* x, int64_t n, int32_t d, int64_t ld, const in
             if (s != rows[j] && dominates(x, ld, d, s, rows[j])) { in = 0; break; }
         member[j] = in;
     }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* The upper end of Alg. 1's level range (Sec. 3.2): ell is the smallest non-zero absolute      */
+/* difference between two values of the same attribute, over every pair of rows and every      */
+/* attribute, and g_bar = floor(1/ell); beyond g_bar no new dominance between grid projections  */
+/* can appear. Each difference is taken in FP64 (the difference of two FP32 values, rounded to  */
+/* nearest; exact whenever the two exponents are within 29 of each other). +inf when no        */
+/* attribute holds two different values.                                                       */
+/* orc_ell is the definition as nested loops over pairs.                                       */
+/* ------------------------------------------------------------------------------------------ */
+double orc_ell(const float* x, int64_t n, int32_t d, int64_t ld) {
+    double best = INFINITY;
+    for (int32_t k = 0; k < d; ++k) {
+#pragma omp parallel for schedule(dynamic, 64) reduction(min : best)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double e = fabs((double)X(x, ld, k, i) - (double)X(x, ld, k, j));
+                if (e > 0.0 && e < best) best = e;
+            }
+    }
+    return best;
+}
+
+static int dbl_cmp(const void* pa, const void* pb) {
+    double a = *(const double*)pa, b = *(const double*)pb;
+    return (a > b) - (a < b);
+}
+
+/* The same minimum through a sort of each attribute (for sizes where pairs are too many): in   */
+/* sorted order, the smallest non-zero difference is between neighbours.                       */
+double orc_ell_sorted(const float* x, int64_t n, int32_t d, int64_t ld) {
+    double best = INFINITY;
+    double* v = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int32_t k = 0; k < d; ++k) {
+        for (int64_t i = 0; i < n; ++i) v[i] = (double)X(x, ld, k, i);
+        qsort(v, (size_t)n, sizeof(double), dbl_cmp);
+        for (int64_t i = 1; i < n; ++i) {
+            double e = v[i] - v[i - 1];
+            if (e > 0.0 && e < best) best = e;
+        }
+    }
+    free(v);
+    return best;
+}
+
+/* g_bar = floor(1/ell), the quotient rounded to nearest in FP64; 1 when ell is +inf (no level  */
+/* above 1 to search).                                                                         */
+double orc_gbar(double ell) {
+    if (!(ell < INFINITY)) return 1.0;
+    return floor(1.0 / ell);
 }
 
 /* Projected key of one value, exposed so that the quantisation rule itself can be pinned. */

@@ -383,3 +383,61 @@ def test_count_invalid(orc):
     x = np.array([[0.0, 0.5], [-0.0, 0.999], [1.0, 0.2], [np.nan, 0.1], [0.3, -1e-30],
                   [np.inf, 0.0]], dtype=np.float32)
     assert orc.count_invalid(x) == 4
+
+
+# ----------------------------------------------------------------------------- ell and g_bar
+
+def test_ell_worked_lattice_example(orc):
+    # attribute 0 holds 1/4, 1/2, 3/4 (gaps 1/4); attribute 1 holds 1/8, 1/8, 5/16 (gaps 0 and
+    # 3/16): ell = 3/16 comes from the second attribute and g_bar = floor(16/3) = 5
+    x = np.array([[0.25, 0.125], [0.5, 0.125], [0.75, 0.3125]], np.float32)
+    assert brute.ell_exact(x) == Fraction(3, 16)
+    assert orc.ell(x) == 0.1875 and orc.ell(x, sorted_=True) == 0.1875
+    assert orc.gbar(x) == (0.1875, 5)
+
+
+def test_ell_degenerate(orc):
+    # no attribute holds two different values (-0 and +0 are one value): no ell, g_bar = 1
+    for x in (np.zeros((0, 3), np.float32), np.full((1, 2), 0.3, np.float32),
+              np.full((5, 2), 0.3, np.float32), np.array([[0.0], [-0.0]], np.float32)):
+        assert orc.ell(x) == math.inf and orc.ell(x, sorted_=True) == math.inf
+        assert orc.gbar(x)[1] == 1
+        assert brute.ell_exact(x) is None and brute.gbar_exact(x) == 1
+    # a constant attribute beside one with gaps 1/8 and 1/2
+    x = np.array([[0.5, 0.25], [0.5, 0.375], [0.5, 0.875]], np.float32)
+    assert orc.gbar(x) == (0.125, 8)
+    # the smallest step above 0 is a subnormal: ell is that value, g_bar far beyond 2^62
+    tiny = np.float32(1e-40)
+    x = np.array([[0.0], [tiny], [0.5]], np.float32)
+    assert orc.ell(x) == float(tiny) and orc.ell(x, sorted_=True) == float(tiny)
+    assert orc.gbar(x)[1] > 2 ** 62
+
+
+@pytest.mark.parametrize("kind", ["uni", "ties", "dyadic", "ant"])
+def test_ell_vs_exact_pairs(orc, kind):
+    for seed in range(6):
+        d = 1 + seed % 4
+        x = _rows(kind, 24, d, seed)
+        x = np.concatenate([x, x[:3]])       # whole-row duplicates
+        x[1, 0] = -0.0 if seed % 2 else x[1, 0]
+        e = brute.ell_exact(x)
+        assert e is not None
+        assert orc.ell(x) == float(e)        # every difference here is exact in FP64
+        assert orc.ell(x, sorted_=True) == orc.ell(x)
+        assert orc.gbar(x)[1] == brute.gbar_exact(x)
+
+
+def test_no_exit_beyond_gbar(orc):
+    # Sec. 3.2: at g > g_bar every difference within an attribute spans more than one grid
+    # interval, so projections keep every order and no new dominance appears. On dyadic data
+    # (exact in FP32) the exact brute force over levels up to 3 g_bar + 2 finds no exit above
+    # g_bar, and the oracle's search up to g_bar gives the same answer.
+    for seed in range(5):
+        x = G.dyadic(10, 2 + seed % 2, seed, bits=4)
+        gb = brute.gbar_exact(x)
+        assert orc.gbar(x)[1] == gb and 2 <= gb <= 16
+        far = brute.gres_g_exit(x, 3 * gb + 2, "exact")
+        assert far == brute.gres_g_exit(x, gb, "exact")
+        cand = np.flatnonzero(orc.skyline(x))
+        ge, _ = orc.gres(x, cand, gb)
+        assert [far[int(c)] for c in cand] == ge.tolist()
