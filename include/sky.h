@@ -69,7 +69,8 @@ typedef enum sky_scheme {
 /* Limits of this implementation. */
 #define SKY_MAX_D 16           /* attributes per tuple */
 #define SKY_MAX_CELLS 4096     /* partitions of any scheme (Grid m^d, Angular m^(d-1), Sliced p) */
-#define SKY_MAX_G 1048576      /* largest g_max accepted by gres_compute */
+#define SKY_MAX_G 16777216     /* largest g_max accepted by gres_compute: 2^24, the largest level
+                                  at which (float)g is exact, as the key contract needs */
 #define SKY_HOST_SCRATCH_BYTES 256 /* size of the optional pinned host scratch of a plan */
 
 /* gres_compute mapping choice (sky_gres_opts.mapping). */
@@ -250,6 +251,33 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld,
                         const int64_t* sky_idx, int64_t s, int32_t g_max, int32_t* g_exit,
                         float* gres, void* ws, size_t ws_bytes, int32_t* dev_status,
                         const sky_gres_opts* opts, void* stream);
+
+/*
+ * Workspace for gres_gbar, in bytes (independent of d). Returns 0 for invalid arguments.
+ */
+size_t gres_gbar_workspace_bytes(int64_t n);
+
+/*
+ * gres_gbar -- the upper end of Alg. 1's level range (Sec. 3.2): ell is the smallest non-zero
+ * absolute difference between two values of the same attribute, over every pair of rows of x
+ * and every attribute; g_bar = floor(1 / ell). Beyond g_bar, every difference within an
+ * attribute spans more than one grid interval, so no new dominance between projections can
+ * appear (exact arithmetic), and gres_compute with g_max = g_bar gives Def. 2's value.
+ * Outputs (device, either may be null, not both):
+ *   ell[0]   -- a double: each difference is taken in FP64 from the two FP32 values (rounded
+ *               to nearest; exact unless the two exponents differ by more than 29); +inf when no
+ *               attribute holds two different values (n < 2 included). -0.0 equals 0.0.
+ *   g_bar[0] -- an int64: floor of the FP64 quotient 1/ell, saturated at 2^62; 1 when ell is +inf
+ *               (no level above 1 to search). To search up to it, pass min(g_bar, SKY_MAX_G) as
+ *               g_max; a g_bar above SKY_MAX_G means levels past 2^24 are not searched.
+ * x_soa: [d][ld] device FP32, n in [0, 2^30 - 2^20), ld >= n. Values outside [0, 1) or NaN set
+ * SKY_ERR_DOMAIN in *dev_status (outputs then undefined). ws: device, at least
+ * gres_gbar_workspace_bytes(n) bytes, caller-owned, free again when the stream reaches the end
+ * of this call's work. Never synchronises.
+ */
+sky_status gres_gbar(const float* x_soa, int64_t n, int32_t d, int64_t ld, double* ell,
+                     int64_t* g_bar, void* ws, size_t ws_bytes, int32_t* dev_status,
+                     void* stream);
 
 /*
  * Two-phase form of gres_compute, for candidate sets that are queried many times (a resident

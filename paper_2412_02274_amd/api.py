@@ -207,6 +207,41 @@ def gres(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, mapping="a
     return g_exit, gres_out
 
 
+def gbar(x_soa: torch.Tensor, status: torch.Tensor | None = None, stream=None):
+    """gres_gbar: (ell, g_bar) of Alg. 1's level range (Sec. 3.2) for the relation x_soa, read
+    back to the host: ell as a float (+inf when no attribute holds two different values), g_bar
+    = floor(1/ell) as an int (saturated at 2^62; 1 when ell is +inf)."""
+    lib = _lib.load()
+    d, n = x_soa.shape
+    dev = x_soa.device
+    need = int(lib.gres_gbar_workspace_bytes(n))
+    if need == 0:
+        raise SkyError(_lib.SKY_ERR_INVALID_ARG, "gres_gbar_workspace_bytes")
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    ell = torch.empty(1, dtype=torch.float64, device=dev)
+    gb = torch.empty(1, dtype=torch.int64, device=dev)
+    st = status if status is not None else new_status(dev)
+    _lib.check(lib.gres_gbar(_ptr(x_soa), n, d, x_soa.stride(0), _ptr(ell), _ptr(gb), _ptr(ws), need,
+                             _ptr(st), _stream_ptr(stream)), "gres_gbar")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    check_status(st, "gres_gbar")
+    return float(ell.item()), int(gb.item())
+
+
+def gres_exact(x_soa: torch.Tensor, sky_idx: torch.Tensor, mapping="auto", status=None, stream=None):
+    """Def. 2 over Alg. 1's whole level range: g_max = g_bar = floor(1/ell) from gres_gbar, capped
+    at SKY_MAX_G (the largest level at which the key contract's (float)g is exact). Returns
+    (g_exit, gres, info) with info = {"ell", "g_bar", "g_max", "capped"}; when capped is True,
+    levels above SKY_MAX_G were not searched."""
+    ell, gb = gbar(x_soa, status=status, stream=stream)
+    # g_bar = 1 leaves no level to search; level 2 is then above g_bar and cannot hold an exit
+    # (and gres_compute needs g_max >= 2), so searching it gives the same all-ones answer
+    g_max = max(2, min(gb, _lib.SKY_MAX_G))
+    info = {"ell": ell, "g_bar": gb, "g_max": g_max, "capped": gb > _lib.SKY_MAX_G}
+    ge, gr = gres(x_soa, sky_idx, g_max, mapping=mapping, status=status, stream=stream)
+    return ge, gr, info
+
+
 class PreparedCandidates:
     """A candidate set (normally a skyline) prepared once for many gres searches."""
 

@@ -442,6 +442,26 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
                               opts ? opts->dev_tests : nullptr, st);
 }
 
+size_t gres_gbar_workspace_bytes(int64_t n) {
+    if (n < 0 || n > kMaxRows) return 0;
+    Carver c(nullptr, 0);
+    GbarBuffers b{};
+    carve_gbar(c, b, n);
+    return c.used;
+}
+
+sky_status gres_gbar(const float* x_soa, int64_t n, int32_t d, int64_t ld, double* ell, int64_t* g_bar,
+                     void* ws, size_t ws_bytes, int32_t* dev_status, void* stream) {
+    if (n < 0 || n > kMaxRows || !valid_d(d) || !dev_status || (!ell && !g_bar)) return SKY_ERR_INVALID_ARG;
+    if (n > 0 && (!x_soa || ld < n)) return SKY_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < gres_gbar_workspace_bytes(n)) return SKY_ERR_WORKSPACE;
+    Carver c(ws, ws_bytes);
+    GbarBuffers b{};
+    carve_gbar(c, b, n);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    return launch_gbar(x_soa, n, d, ld, b, ell, g_bar, dev_status, (hipStream_t)stream);
+}
+
 size_t gres_prepare_bytes(int64_t s, int32_t d) {
     if (s < 0 || s > kMaxBuildRows || !valid_d(d)) return 0;
     Carver c(nullptr, 0);

@@ -53,6 +53,9 @@ constexpr int kGresLdsBytes = 64 * 1024; // tile boxes cached in LDS when they f
 constexpr float kPadValue = 2.0f;
 constexpr int kBandLevels = 6;           // levels per band of the TILES search
 constexpr int kMaxBands = 8;
+constexpr int kStartLevels = 64;         // above this g_max, searches start at per-target bounds
+constexpr int kLevelWaves = 4096;        // LEVELS: waves wanted in flight (targets x bands)
+constexpr int kMaxLevelBands = 16;
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -330,7 +333,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
     int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
     const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
     int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests, int32_t nblk,
-    int32_t band_len) {
+    int32_t band_len, const int32_t* __restrict__ gstart) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     unsigned long long ntests = 0;   // candidate tests (target against candidate at one level)
@@ -339,8 +342,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
     const int wave = threadIdx.x / kWave;
     // blocks are band-major: every target's highest band first
     const int32_t band = blockIdx.x / nblk;
-    const int32_t g_hi = g_max - band * band_len;
-    const int32_t g_lo = g_hi - band_len + 1 > 2 ? g_hi - band_len + 1 : 2;
+    const int32_t nbands = (int32_t)(gridDim.x / (uint32_t)nblk);
     const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x - band * nblk);
     if (w.t0 >= w.t1) return;  // uniform
     const uint32_t coff = (uint32_t)seg_coff[w.seg];
@@ -380,6 +382,15 @@ __global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
         int32_t result = 1;
         // a higher band may already have found the exit of q at or above this band's levels
         int32_t seen = __hip_atomic_load(&ge_out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the bands split [2, g_max], or [2, start level] when the target has one (no exit lies
+        // above it, gres_start_kernel), into nbands ranges, highest first
+        int32_t gtop = g_max, blen = band_len;
+        if (gstart) {
+            gtop = gstart[q] < g_max ? gstart[q] : g_max;
+            blen = gtop > 2 ? (gtop - 2 + nbands) / nbands : 1;
+        }
+        const int32_t g_hi = gtop - band * blen;
+        const int32_t g_lo = g_hi - blen + 1 > 2 ? g_hi - blen + 1 : 2;
         for (int32_t g = g_hi; g >= g_lo && ntile > 0; --g) {
             if (seen >= g) break;
             const int32_t seen_next =
@@ -489,18 +500,30 @@ __device__ __forceinline__ bool beyond_levels(double delta, int32_t g_low) {
     return wv > 0.0 && (double)g_low * wv >= 1.0 + 1e-9;
 }
 
+// A level bound B for a candidate whose excess over t is delta: beyond_levels(delta, g) holds
+// for every g > B (with one level to spare against the rounding of the quotient); g_max when
+// the excess excludes no level.
+__device__ __forceinline__ int32_t collapse_bound(double delta, int32_t g_max) {
+    const double wv = delta - 0x1p-23;
+    if (!(wv > 0.0)) return g_max;
+    const double r = (1.0 + 1e-9) / wv;
+    return r >= (double)g_max ? g_max : (int32_t)r + 1;
+}
+
+// Highest level worth searching for each target. A candidate s can dominate the projection of
+// t at level g only if s is below t in some attribute (keys are monotone, so s >= t everywhere
+// gives keys >= t's keys), and only while every attribute where s is above t can still collapse
+// onto t's key (collapse_bound). The start level of t is the largest bound over the candidates
+// that qualify (1 when none does), so no level above it holds an exit. A tile's lower corner
+// bounds all of its candidates at once: a tile with no attribute below t is skipped, and so is
+// one whose bound does not exceed the start level found so far.
 template <int D>
-__global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
-    const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
-    const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
-    const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
-    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
-    const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
-    int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests) {
+__global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
+    const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo, int64_t tcap,
+    const int32_t* __restrict__ seg_coff, const int32_t* __restrict__ seg_cnt, int32_t d_rt,
+    const float* __restrict__ tval, int64_t tvcap, int32_t nt, const int32_t* __restrict__ wg_table,
+    int32_t per_wg, int32_t g_max, int32_t* __restrict__ gstart) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
-    unsigned long long ntests = 0;  // candidate tests (target against candidate at one level)
-    (void)thint;
-    (void)lds_floats;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
@@ -515,11 +538,98 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
 #pragma unroll
         for (int k = 0; k < DM; ++k)
             if (k < d) tv[k] = tval[(int64_t)k * tvcap + q];
+        int32_t best = 1;  // wave-uniform
+        for (int32_t tb = 0; tb < ntile && best < g_max; tb += kWave) {
+            // lanes over tiles
+            const int32_t tile = tb + lane;
+            int32_t tbound = 1;
+            if (tile < ntile) {
+                bool below = false;
+                double dt = -1.0;
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) {
+                        const float l = lo[(int64_t)k * tcap + t0 + tile];
+                        below |= l < tv[k];
+                        const double e = (double)l - (double)tv[k];
+                        dt = e > dt ? e : dt;
+                    }
+                if (below) tbound = collapse_bound(dt, g_max);
+            }
+            uint64_t todo = __ballot(tbound > best);
+            while (todo && best < g_max) {
+                const int i = __ffsll((unsigned long long)todo) - 1;
+                todo &= todo - 1;
+                if (__shfl(tbound, i) <= best) continue;
+                // lanes over the tile's candidates (padding slots hold 2.0: never below t)
+                const int64_t j = coff + (int64_t)(tb + i) * kTileC + lane;
+                bool below = false;
+                double ds = -1.0;
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) {
+                        const float v = cand[(int64_t)k * ccap + j];
+                        below |= v < tv[k];
+                        const double e = (double)v - (double)tv[k];
+                        ds = e > ds ? e : ds;
+                    }
+                int32_t b = below ? collapse_bound(ds, g_max) : 1;
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    const int32_t o = __shfl_xor(b, off);
+                    b = o > b ? o : b;
+                }
+                best = b > best ? b : best;
+            }
+        }
+        if (lane == 0) gstart[q] = best;
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
+    const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
+    const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
+    const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
+    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
+    const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
+    int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests,
+    const int32_t* __restrict__ gstart, int32_t nblk) {
+    constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    unsigned long long ntests = 0;  // candidate tests (target against candidate at one level)
+    (void)thint;
+    (void)lds_floats;
+    const int d = dget<D>(d_rt);
+    const int lane = (int)lane_id();
+    const int wave = threadIdx.x / kWave;
+    // blocks are band-major: every target's highest band first
+    const int32_t band = blockIdx.x / nblk;
+    const int32_t nbands = (int32_t)(gridDim.x / (uint32_t)nblk);
+    const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x - band * nblk);
+    if (w.t0 >= w.t1) return;
+    const int64_t coff = seg_coff[w.seg];
+    const int32_t cnt = seg_cnt[w.seg];
+    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
+    const int64_t t0 = coff / kTileC;
+    for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) {
+        float tv[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) tv[k] = tval[(int64_t)k * tvcap + q];
         int32_t result = 1;
-        for (int32_t gh = g_max; gh >= 2; gh -= kWave) {
+        // the bands split [2, g_max], or [2, start level] when the target has one (no exit lies
+        // above it, gres_start_kernel), into nbands ranges, highest first
+        const int32_t gtop = gstart ? (gstart[q] < g_max ? gstart[q] : g_max) : g_max;
+        const int32_t blen = gtop > 2 ? (gtop - 2 + nbands) / nbands : 1;
+        const int32_t g_hi = gtop - band * blen;
+        const int32_t g_lo = g_hi - blen + 1 > 2 ? g_hi - blen + 1 : 2;
+        for (int32_t gh = g_hi; gh >= g_lo; gh -= kWave) {
+            // a higher band has already found an exit at or above every level left here
+            if (nbands > 1 &&
+                __hip_atomic_load(&ge_out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= gh)
+                break;
             const int32_t g = gh - lane;
-            const bool lv = g >= 2;
-            const int32_t g_low = (gh - (kWave - 1)) > 2 ? (gh - (kWave - 1)) : 2;
+            const bool lv = g >= g_lo;
+            const int32_t g_low = (gh - (kWave - 1)) > g_lo ? (gh - (kWave - 1)) : g_lo;
             const float fg = (float)(lv ? g : 2);
             float tle[DM], tlt[DM];
 #pragma unroll
@@ -591,7 +701,8 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
                 break;
             }
         }
-        if (lane == 0) ge_out[q] = result;
+        // ge_out starts at 1 (no exit); each band raises it to its highest exit level
+        if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
     }
     if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
 }
@@ -652,6 +763,7 @@ void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d) {
     t.thint = c.take<int32_t>((size_t)t.tvcap);
     t.tout = c.take<int32_t>((size_t)t.tvcap);
     t.ge = c.take<int32_t>((size_t)t.tvcap);
+    t.gstart = c.take<int32_t>((size_t)t.tvcap);
 }
 
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -754,7 +866,11 @@ sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int
 }
 
 int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
-    return (g_max > 64 && s <= 8192) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
+    // measured (both mappings with per-target start levels): lanes over 64 levels pay off when
+    // many levels lie below the start levels (g_max >= 2^17) or on small skylines with
+    // g_max > 1000; otherwise the banded tile walk is faster
+    if (s > 8192) return SKY_GRES_TILES;
+    return (g_max >= (1 << 17) || (g_max > 1000 && s <= 1024)) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
 }
 
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
@@ -789,25 +905,40 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
         nbands = nbands < 1 ? 1 : (nbands > kMaxBands ? kMaxBands : nbands);
         band_len = (int32_t)ceil_div(g_max - 1, nbands);
     }
+    // many levels: each target's highest level worth searching, from the candidates' bounds
+    const int32_t* gstart = nullptr;
+    if (g_max > kStartLevels) {
+        SKY_DISPATCH_D(d, gres_start_kernel, dim3(blocks), dim3(kGresBlock), 0, st,
+                       (const float*)store.cand, store.ccap, (const float*)store.lo, store.tcap,
+                       (const int32_t*)store.seg_coff, (const int32_t*)store.seg_cnt, d,
+                       (const float*)tg.tval, tg.tvcap, nt, wg_table, per_wg, g_max, tg.gstart);
+        SKY_HIP(hipGetLastError());
+        gstart = tg.gstart;
+    }
     // no exit (1) until a band finds one
     hipLaunchKernelGGL(fill_i32_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, tg.ge,
                        nt, 1);
     SKY_HIP(hipGetLastError());
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (mapping == SKY_GRES_LEVELS) {
-        SKY_DISPATCH_D(d, gres_levels_kernel, dim3(blocks), dim3(kGresBlock), 0, st,
+        // few targets: split each target's levels over several waves so the chip fills
+        int64_t lb = nt < kLevelWaves ? ceil_div(kLevelWaves, nt) : 1;
+        const int64_t lmax = ceil_div(g_max - 1, kWave);  // at least 64 levels per band at g_max
+        lb = lb > lmax ? lmax : lb;
+        lb = lb > kMaxLevelBands ? kMaxLevelBands : (lb < 1 ? 1 : lb);
+        SKY_DISPATCH_D(d, gres_levels_kernel, dim3(blocks * (uint32_t)lb), dim3(kGresBlock), 0, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests);
+                       dev_tests, gstart, (int32_t)blocks);
     } else {
         SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(blocks * (uint32_t)nbands), dim3(kGresBlock), lds, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests, (int32_t)blocks, band_len);
+                       dev_tests, (int32_t)blocks, band_len, gstart);
     }
     SKY_HIP(hipGetLastError());
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(kBlock) ingest_kernel(const float* __restrict_
 
 // Grid projection (Def. 2) of the rows rows[0, s) at level g, as a relation of its own:
 // out[k*ld_out + j] = floor(fl32(x[k][rows[j]] * g)) * 2^-b with 2^b >= g. The scale keeps the
-// values in [0, 1) and exact in FP32 (keys < 2^20), and orders them like floor(t g) / g.
+// values in [0, 1) and exact in FP32 (keys < 2^24), and orders them like floor(t g) / g.
 __global__ void __launch_bounds__(kBlock) project_kernel(const float* __restrict__ x, int64_t n, int32_t d,
                                                           int64_t ld, const int64_t* __restrict__ rows,
                                                           int64_t s, int32_t g, float scale,

@@ -138,6 +138,12 @@ inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 // launchers implemented in the .hip files
 // ----------------------------------------------------------------------------------------
 
+// sky_gbar.hip: ell and g_bar of Alg. 1's level range (Sec. 3.2), device outputs
+struct GbarBuffers { uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp; unsigned long long* minbits; };
+void carve_gbar(Carver& c, GbarBuffers& b, int64_t n);
+sky_status launch_gbar(const float* x, int64_t n, int32_t d, int64_t ld, const GbarBuffers& b,
+                       double* ell, int64_t* g_bar, int32_t* dev_status, hipStream_t st);
+
 // sky_ingest.hip
 sky_status launch_project(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                           int64_t s, int32_t g, float* out, int64_t ld_out, int32_t* dev_status,
@@ -252,6 +258,7 @@ struct GresTargets {
     int32_t* thint;                // [tvcap] starting tile of each target (local to its segment)
     int32_t* tout;                 // [tvcap] output index of each target (-1: none)
     int32_t* ge;                   // [tvcap] result per target
+    int32_t* gstart;               // [tvcap] highest level worth searching per target
 };
 void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg);
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);

@@ -97,6 +97,8 @@ def test_argument_errors_return_synchronously(lib):
                             C.byref(o), None) == E  # g_max < 2
     assert lib.gres_compute(fake, 10, 2, 10, fake, 5, 25, fake, fake, fake, 1 << 20, None,
                             C.byref(o), None) == E  # no status word
+    assert lib.gres_compute(fake, 10, 2, 10, fake, 5, _lib.SKY_MAX_G + 1, fake, fake, fake, 1 << 20,
+                            fake, C.byref(o), None) == E  # g_max above the limit
     assert lib.gres_compute(fake, 10, 2, 10, fake, 5, 25, fake, fake, fake, 16, fake,
                             C.byref(o), None) == _lib.SKY_ERR_WORKSPACE
     bad = _lib.GresOpts(9)
@@ -171,8 +173,26 @@ def test_project_arguments(lib):
     fake = C.c_void_p(0x1000)
     E = _lib.SKY_ERR_INVALID_ARG
     assert lib.sky_project(fake, 10, 2, 10, fake, 5, 0, fake, 5, fake, None) == E   # g < 1
-    assert lib.sky_project(fake, 10, 2, 10, fake, 5, (1 << 20) + 1, fake, 5, fake, None) == E
+    assert lib.sky_project(fake, 10, 2, 10, fake, 5, _lib.SKY_MAX_G + 1, fake, 5, fake, None) == E
     assert lib.sky_project(fake, 10, 2, 10, fake, 5, 25, fake, 4, fake, None) == E  # ld_out < s
     assert lib.sky_project(None, 10, 2, 10, fake, 5, 25, fake, 5, fake, None) == E
     assert lib.sky_project(fake, 10, 0, 10, fake, 5, 25, fake, 5, fake, None) == E
     assert lib.sky_project(None, 0, 2, 0, None, 0, 25, None, 0, None, None) == _lib.SKY_OK
+
+
+def test_gbar_arguments(lib):
+    fake = C.c_void_p(0x1000)
+    E = _lib.SKY_ERR_INVALID_ARG
+    ws = lib.gres_gbar_workspace_bytes(1000)
+    assert ws > 4 * 4 * 1000 and lib.gres_gbar_workspace_bytes(-1) == 0
+    assert lib.gres_gbar_workspace_bytes(0) > 0
+    assert lib.gres_gbar(fake, 10, 2, 10, fake, fake, fake, ws, None, None) == E   # no status word
+    assert lib.gres_gbar(fake, 10, 2, 10, None, None, fake, ws, fake, None) == E   # no output
+    assert lib.gres_gbar(fake, 10, 0, 10, fake, fake, fake, ws, fake, None) == E   # d < 1
+    assert lib.gres_gbar(fake, 10, 2, 9, fake, fake, fake, ws, fake, None) == E    # ld < n
+    assert lib.gres_gbar(None, 10, 2, 10, fake, fake, fake, ws, fake, None) == E
+    assert lib.gres_gbar(fake, -1, 2, 10, fake, fake, fake, ws, fake, None) == E
+    assert lib.gres_gbar(fake, 1000, 2, 1000, fake, fake, fake, 16, fake,
+                         None) == _lib.SKY_ERR_WORKSPACE
+    assert lib.gres_gbar(fake, 1000, 2, 1000, fake, fake, None, ws, fake,
+                         None) == _lib.SKY_ERR_WORKSPACE

@@ -32,7 +32,7 @@ def _data(kind, n, d, seed):
     return G.make(kind, n, d, seed)
 
 
-@pytest.mark.parametrize("g", [1, 2, 7, 25, 1000, 1 << 20])
+@pytest.mark.parametrize("g", [1, 2, 7, 25, 1000, 1 << 20, (1 << 20) + 3, 1 << 24])
 def test_project_is_the_scaled_key(dev, g):
     x = G.uni(3001, 5, 11)
     xs = api.ingest(torch.from_numpy(x).to(dev))
