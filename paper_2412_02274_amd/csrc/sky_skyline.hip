@@ -68,6 +68,16 @@ __device__ __forceinline__ int32_t seg_of(const int32_t* seg_of_pos, int32_t pos
 
 // Wave-aggregated "slot = atomicAdd(&ctr[key*stride], 1)": one atomic per distinct key in the
 // wave; every active lane gets a unique slot.
+// Maximum of v over the 64 lanes (every lane receives it).
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const int32_t o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
 __device__ __forceinline__ int32_t wave_slot(int32_t* ctr, int32_t stride, int32_t key, bool active) {
     const int lane = (int)lane_id();
     const uint64_t lt = __lanemask_lt();
@@ -757,93 +767,117 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
         // the head group's own tile first (its rows' nearest neighbours on the curve)
         int32_t start = 0;
         if (mode == 0 && nr == 1) start = (ibase / kTile) % ntile;
-        for (int32_t step = 0; step < span && live; ++step) {
-            int32_t c = start + step;
-            c = c < span ? c : c - span;
-            c += c0;
-            // 1. box of tile c against every live item (lane = item)
-            bool pass = (live >> lane) & 1ull, hle = true, hlt = false;
+        int32_t done_steps = 0;
+        // the unit's tiles in visiting order c(step) = c0 + (start + step) mod span, 64 at a time
+        for (int32_t b0 = 0; b0 < span && live; b0 += kWave) {
+            // a tile can pass a live item only if its lower corner is <= the componentwise
+            // maximum of the live items: one test per tile, lanes over the next 64 tiles
+            const bool lv = (live >> lane) & 1ull;
+            int32_t mxk[DM];
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d) {
-                    const int32_t lo = (int32_t)(in_lds ? box[k * ntile + c] : hlo[(int64_t)k * tcap + t0 + c]);
-                    const int32_t hi = (int32_t)(in_lds ? box[nb + k * ntile + c] : hhi[(int64_t)k * tcap + t0 + c]);
-                    pass &= lo <= tv[k];
-                    hle &= hi <= tv[k];
-                    hlt |= hi < tv[k];
-                }
-            live &= ~__builtin_amdgcn_ballot_w64(pass && hle && hlt);
-            uint64_t todo = __builtin_amdgcn_ballot_w64(pass) & live;
-            if (todo) {
-                // 2. the tile's candidates (lane = candidate) against every item that passed
-                const uint32_t slot = (uint32_t)((t0 + c) * kTile + lane);
-                int32_t cv[DM];
+                if (k < d) mxk[k] = wave_max_i32(lv ? tv[k] : INT32_MIN);
+            const int32_t sl = b0 + lane;
+            bool maybe = sl < span;
+            if (maybe) {
+                int32_t cl = start + sl;
+                cl = (cl < span ? cl : cl - span) + c0;
 #pragma unroll
                 for (int k = 0; k < DM; ++k)
-                    if (k < d) cv[k] = (int32_t)ld32(hval + k * hcap, slot);
-                const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
-                ntests += (unsigned long long)__popcll(todo) * (unsigned long long)creal;
-                if (__popcll(todo) >= kDense) {
-                    // dense: lanes keep their items and the candidates are broadcast one by
-                    // one from LDS; no per-item scalar work (padding candidates never dominate)
+                    if (k < d)
+                        maybe &= (int32_t)(in_lds ? box[k * ntile + cl] : hlo[(int64_t)k * tcap + t0 + cl]) <= mxk[k];
+            }
+            uint64_t tmask = __builtin_amdgcn_ballot_w64(maybe);
+            while (tmask && live) {
+                const int32_t step = b0 + (__ffsll((unsigned long long)tmask) - 1);
+                tmask &= tmask - 1;
+                int32_t c = start + step;
+                c = c < span ? c : c - span;
+                c += c0;
+                // 1. box of tile c against every live item (lane = item)
+                bool pass = (live >> lane) & 1ull, hle = true, hlt = false;
+#pragma unroll
+                for (int k = 0; k < DM; ++k)
+                    if (k < d) {
+                        const int32_t lo = (int32_t)(in_lds ? box[k * ntile + c] : hlo[(int64_t)k * tcap + t0 + c]);
+                        const int32_t hi = (int32_t)(in_lds ? box[nb + k * ntile + c] : hhi[(int64_t)k * tcap + t0 + c]);
+                        pass &= lo <= tv[k];
+                        hle &= hi <= tv[k];
+                        hlt |= hi < tv[k];
+                    }
+                live &= ~__builtin_amdgcn_ballot_w64(pass && hle && hlt);
+                uint64_t todo = __builtin_amdgcn_ballot_w64(pass) & live;
+                if (todo) {
+                    // 2. the tile's candidates (lane = candidate) against every item that passed
+                    const uint32_t slot = (uint32_t)((t0 + c) * kTile + lane);
+                    int32_t cv[DM];
 #pragma unroll
                     for (int k = 0; k < DM; ++k)
-                        if (k < d) candv[wave][lane][k] = cv[k];
-                    __builtin_amdgcn_wave_barrier();
-                    int32_t acc = 0;
+                        if (k < d) cv[k] = (int32_t)ld32(hval + k * hcap, slot);
+                    const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
+                    ntests += (unsigned long long)__popcll(todo) * (unsigned long long)creal;
+                    if (__popcll(todo) >= kDense) {
+                        // dense: lanes keep their items and the candidates are broadcast one by
+                        // one from LDS; no per-item scalar work (padding candidates never dominate)
+#pragma unroll
+                        for (int k = 0; k < DM; ++k)
+                            if (k < d) candv[wave][lane][k] = cv[k];
+                        __builtin_amdgcn_wave_barrier();
+                        int32_t acc = 0;
 #pragma unroll 4
-                    for (int j = 0; j < creal; ++j) {
+                        for (int j = 0; j < creal; ++j) {
+                            int32_t mx = INT32_MIN, mn = INT32_MAX;
+#pragma unroll
+                            for (int k = 0; k < DM; ++k)
+                                if (k < d) {
+                                    const int32_t e = candv[wave][j][k] - tv[k];
+                                    mx = e > mx ? e : mx;
+                                    mn = e < mn ? e : mn;
+                                }
+                            acc |= (mx - 1) & mn;  // sign bit: candidate j dominates this lane's item
+                        }
+                        __builtin_amdgcn_wave_barrier();  // candv is rewritten by the next tile
+                        live &= ~(__builtin_amdgcn_ballot_w64(acc < 0) & todo);
+                        todo = 0;
+                    }
+                    // item values come from LDS as broadcasts; the next item's are fetched while the
+                    // current one is tested
+                    int i = todo ? __ffsll((unsigned long long)todo) - 1 : 0;
+                    int32_t ts[DM];
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) ts[k] = itemv[wave][i][k];
+                    while (todo) {
+                        todo &= todo - 1;
+                        const int inext = todo ? __ffsll((unsigned long long)todo) - 1 : i;
+                        int32_t tn[DM];
+#pragma unroll
+                        for (int k = 0; k < DM; ++k)
+                            if (k < d) tn[k] = itemv[wave][inext][k];
                         int32_t mx = INT32_MIN, mn = INT32_MAX;
 #pragma unroll
                         for (int k = 0; k < DM; ++k)
                             if (k < d) {
-                                const int32_t e = candv[wave][j][k] - tv[k];
+                                const int32_t e = cv[k] - ts[k];
                                 mx = e > mx ? e : mx;
                                 mn = e < mn ? e : mn;
                             }
-                        acc |= (mx - 1) & mn;  // sign bit: candidate j dominates this lane's item
+                        // mx <= 0 and mn < 0  <=>  the sign bit of (mx - 1) & mn is set
+                        if (__builtin_amdgcn_ballot_w64(((mx - 1) & mn) < 0)) live &= ~(1ull << i);
+                        if (!todo) break;
+                        i = inext;
+#pragma unroll
+                        for (int k = 0; k < DM; ++k)
+                            if (k < d) ts[k] = tn[k];
                     }
-                    __builtin_amdgcn_wave_barrier();  // candv is rewritten by the next tile
-                    live &= ~(__builtin_amdgcn_ballot_w64(acc < 0) & todo);
-                    todo = 0;
                 }
-                // item values come from LDS as broadcasts; the next item's are fetched while the
-                // current one is tested
-                int i = todo ? __ffsll((unsigned long long)todo) - 1 : 0;
-                int32_t ts[DM];
-#pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) ts[k] = itemv[wave][i][k];
-                while (todo) {
-                    todo &= todo - 1;
-                    const int inext = todo ? __ffsll((unsigned long long)todo) - 1 : i;
-                    int32_t tn[DM];
-#pragma unroll
-                    for (int k = 0; k < DM; ++k)
-                        if (k < d) tn[k] = itemv[wave][inext][k];
-                    int32_t mx = INT32_MIN, mn = INT32_MAX;
-#pragma unroll
-                    for (int k = 0; k < DM; ++k)
-                        if (k < d) {
-                            const int32_t e = cv[k] - ts[k];
-                            mx = e > mx ? e : mx;
-                            mn = e < mn ? e : mn;
-                        }
-                    // mx <= 0 and mn < 0  <=>  the sign bit of (mx - 1) & mn is set
-                    if (__builtin_amdgcn_ballot_w64(((mx - 1) & mn) < 0)) live &= ~(1ull << i);
-                    if (!todo) break;
-                    i = inext;
-#pragma unroll
-                    for (int k = 0; k < DM; ++k)
-                        if (k < d) ts[k] = tn[k];
+                if (nr > 1 && (++done_steps & 7) == 0) {
+                    // share deaths with the units testing the same items on other tiles
+                    const uint64_t newly = born & ~live & ~written;
+                    if ((newly >> lane) & 1ull) dom[mypos] = 1;
+                    written |= newly;
+                    live &= ~__builtin_amdgcn_ballot_w64(have && dom[mypos] != 0);
                 }
-            }
-            if (nr > 1 && (step & 7) == 7) {
-                // share deaths with the units testing the same items on other tiles
-                const uint64_t newly = born & ~live & ~written;
-                if ((newly >> lane) & 1ull) dom[mypos] = 1;
-                written |= newly;
-                live &= ~__builtin_amdgcn_ballot_w64(have && dom[mypos] != 0);
             }
         }
         if ((((born & ~live & ~written) >> lane) & 1ull) != 0) dom[mypos] = 1;
