@@ -28,11 +28,13 @@
 // dominator is ever skipped, none is ever invented).
 //
 // The test kernel is register-tiled like an n-body step: a wavefront holds 64 items (one per
-// lane) and walks the head tiles of their segment; each tile's box is tested against all items
-// at once, and each tile's 64 candidates are loaded once and tested against every item that
-// passed the box, with the item's values broadcast from its lane. One candidate load serves 64
-// items, so the loop is bound by compares, not by cache bandwidth. A workgroup caches the tile
-// boxes of its current segment in LDS when they fit (a barrier only when the segment changes).
+// lane) and walks the head tiles of their segment. Every 64 tiles it keeps only those whose
+// lower corner is <= the componentwise maximum of its live items (no other tile can pass any
+// of them); each kept tile's box is tested against all items at once, and the tile's 64
+// candidates are loaded once and tested against every item that passed the box. The passing
+// items are compacted in LDS and broadcast one by one against the 64 candidate lanes, so each
+// of the k steps keeps every lane busy. One candidate load serves all the items. A workgroup caches the tile boxes of its
+// current segment in LDS when they fit (a barrier only when the segment changes).
 // Bound: VALU compares (candidate values are a few hundred KB per segment and stay in cache).
 #include "sky_internal.hpp"
 
@@ -46,7 +48,6 @@ constexpr int kTile = 64;     // candidates per tile box
 constexpr uint32_t kPad = 0x7FFFFFFFu;  // padding candidates: above every real value, also as int32
 constexpr int kBoxLds = 4096;           // uint32 tile-box values cached in LDS per workgroup
 constexpr uint32_t kMaxGrid = 8192;     // workgroups of the grid-stride kernels
-constexpr int kDense = 32;              // items passing a tile's box from which the candidates are broadcast
 
 // seg_info layout per segment (int32 x kInfo)
 enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, SI_HEADPRE, kInfo = 8 };
@@ -68,6 +69,13 @@ __device__ __forceinline__ int32_t seg_of(const int32_t* seg_of_pos, int32_t pos
 
 // Wave-aggregated "slot = atomicAdd(&ctr[key*stride], 1)": one atomic per distinct key in the
 // wave; every active lane gets a unique slot.
+// Bitwise OR of v over the 64 lanes (every lane receives it).
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v |= (uint32_t)__shfl_xor((int32_t)v, off);
+    return v;
+}
+
 // Maximum of v over the 64 lanes (every lane receives it).
 __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
 #pragma unroll
@@ -704,8 +712,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     __shared__ uint32_t box[kBoxLds];  // [2][k][ntile] tile boxes (lo, hi) of the current segment
-    __shared__ int32_t itemv[kBlock / kWave][kWave][DM];  // each wave's items, for broadcasts
-    __shared__ int32_t candv[kBlock / kWave][kWave][DM];  // each wave's current tile (dense case)
+    __shared__ int32_t itemc[kBlock / kWave][kWave][DM];  // each wave's passing items, compacted
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = threadIdx.x / kWave;
@@ -759,9 +766,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
                               : (int32_t)(mode == 0 ? ld32(hval + k * hcap, myidx)
                                                     : ld32(reinterpret_cast<const uint32_t*>(xp) + k * ldp,
                                                            (uint32_t)mypos));
-                itemv[wave][lane][k] = tv[k];
             }
-        __builtin_amdgcn_wave_barrier();  // the broadcasts below read other lanes' items
         const uint64_t born = __builtin_amdgcn_ballot_w64(have && dom[mypos] == 0);
         uint64_t live = born, written = 0;
         // the head group's own tile first (its rows' nearest neighbours on the curve)
@@ -808,68 +813,61 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
                 live &= ~__builtin_amdgcn_ballot_w64(pass && hle && hlt);
                 uint64_t todo = __builtin_amdgcn_ballot_w64(pass) & live;
                 if (todo) {
-                    // 2. the tile's candidates (lane = candidate) against every item that passed
+                    // 2. the tile's candidates (lane = candidate, in registers) against every
+                    // item that passed: the passing items are compacted in rank order in LDS
+                    // and broadcast one by one, so every step keeps all 64 lanes busy (slots
+                    // past the real candidates hold padding, which never dominates)
                     const uint32_t slot = (uint32_t)((t0 + c) * kTile + lane);
                     int32_t cv[DM];
 #pragma unroll
                     for (int k = 0; k < DM; ++k)
                         if (k < d) cv[k] = (int32_t)ld32(hval + k * hcap, slot);
                     const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
-                    ntests += (unsigned long long)__popcll(todo) * (unsigned long long)creal;
-                    if (__popcll(todo) >= kDense) {
-                        // dense: lanes keep their items and the candidates are broadcast one by
-                        // one from LDS; no per-item scalar work (padding candidates never dominate)
+                    const int32_t kk = __popcll(todo);
+                    ntests += (unsigned long long)kk * (unsigned long long)creal;
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(todo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
+                    const bool mine = (todo >> lane) & 1ull;
+                    if (mine) {
 #pragma unroll
                         for (int k = 0; k < DM; ++k)
-                            if (k < d) candv[wave][lane][k] = cv[k];
-                        __builtin_amdgcn_wave_barrier();
-                        int32_t acc = 0;
-#pragma unroll 4
-                        for (int j = 0; j < creal; ++j) {
-                            int32_t mx = INT32_MIN, mn = INT32_MAX;
-#pragma unroll
-                            for (int k = 0; k < DM; ++k)
-                                if (k < d) {
-                                    const int32_t e = candv[wave][j][k] - tv[k];
-                                    mx = e > mx ? e : mx;
-                                    mn = e < mn ? e : mn;
-                                }
-                            acc |= (mx - 1) & mn;  // sign bit: candidate j dominates this lane's item
-                        }
-                        __builtin_amdgcn_wave_barrier();  // candv is rewritten by the next tile
-                        live &= ~(__builtin_amdgcn_ballot_w64(acc < 0) & todo);
-                        todo = 0;
+                            if (k < d) itemc[wave][rank][k] = tv[k];
                     }
-                    // item values come from LDS as broadcasts; the next item's are fetched while the
-                    // current one is tested
-                    int i = todo ? __ffsll((unsigned long long)todo) - 1 : 0;
-                    int32_t ts[DM];
-#pragma unroll
-                    for (int k = 0; k < DM; ++k)
-                        if (k < d) ts[k] = itemv[wave][i][k];
-                    while (todo) {
-                        todo &= todo - 1;
-                        const int inext = todo ? __ffsll((unsigned long long)todo) - 1 : i;
-                        int32_t tn[DM];
-#pragma unroll
-                        for (int k = 0; k < DM; ++k)
-                            if (k < d) tn[k] = itemv[wave][inext][k];
+                    __builtin_amdgcn_wave_barrier();
+                    // each lane marks, by rank, the items its candidate dominates (no
+                    // cross-lane step inside the loop); one OR over the lanes gives the dead
+                    uint32_t mlo = 0, mhi = 0;
+                    const int32_t k1 = kk < 32 ? kk : 32;
+#pragma unroll 4
+                    for (int32_t r = 0; r < k1; ++r) {
                         int32_t mx = INT32_MIN, mn = INT32_MAX;
 #pragma unroll
                         for (int k = 0; k < DM; ++k)
                             if (k < d) {
-                                const int32_t e = cv[k] - ts[k];
+                                const int32_t e = cv[k] - itemc[wave][r][k];
                                 mx = e > mx ? e : mx;
                                 mn = e < mn ? e : mn;
                             }
                         // mx <= 0 and mn < 0  <=>  the sign bit of (mx - 1) & mn is set
-                        if (__builtin_amdgcn_ballot_w64(((mx - 1) & mn) < 0)) live &= ~(1ull << i);
-                        if (!todo) break;
-                        i = inext;
+                        mlo |= ((uint32_t)((mx - 1) & mn) >> 31) << r;
+                    }
+#pragma unroll 4
+                    for (int32_t r = 32; r < kk; ++r) {
+                        int32_t mx = INT32_MIN, mn = INT32_MAX;
 #pragma unroll
                         for (int k = 0; k < DM; ++k)
-                            if (k < d) ts[k] = tn[k];
+                            if (k < d) {
+                                const int32_t e = cv[k] - itemc[wave][r][k];
+                                mx = e > mx ? e : mx;
+                                mn = e < mn ? e : mn;
+                            }
+                        mhi |= ((uint32_t)((mx - 1) & mn) >> 31) << (r - 32);
                     }
+                    mlo = wave_or_u32(mlo);
+                    if (kk > 32) mhi = wave_or_u32(mhi);
+                    const uint64_t dead = ((uint64_t)mhi << 32) | mlo;
+                    __builtin_amdgcn_wave_barrier();  // itemc is rewritten by the next tile
+                    live &= ~__builtin_amdgcn_ballot_w64(mine && ((dead >> (rank & 63u)) & 1ull));
                 }
                 if (nr > 1 && (++done_steps & 7) == 0) {
                     // share deaths with the units testing the same items on other tiles
