@@ -91,6 +91,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->phist = c.take<int32_t>((size_t)hist_elems);
     int64_t scan_n = hist_elems > n ? hist_elems : n;
     P->scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(scan_n));
+    P->xa = c.take<float>((size_t)n * (size_t)partition_row_stride(d));
     P->k0 = c.take<uint32_t>((size_t)n);
     P->v0 = c.take<uint32_t>((size_t)n);
     P->k1 = c.take<uint32_t>((size_t)n);
@@ -103,6 +104,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.w1 = c.take<int32_t>((size_t)n);
     e.head = c.take<int32_t>((size_t)e.hcap);
     e.rest = c.take<int32_t>((size_t)n);
+    e.rhb = c.take<int32_t>((size_t)n);
     e.hval = c.take<uint32_t>((size_t)(d * e.hcap));
     e.hlo = c.take<uint32_t>((size_t)(d * e.tcap));
     e.hhi = c.take<uint32_t>((size_t)(d * e.tcap));
@@ -184,6 +186,7 @@ sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int3
     a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
     a.scan_tmp = P->scan_tmp;
     a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
+    a.xa = P->xa;
     a.dev_status = dev_status;
     sky_status s = launch_partition(a, st);
     if (s != SKY_OK) { free(P->tan2_host); delete P; return s; }

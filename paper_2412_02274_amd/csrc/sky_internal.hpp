@@ -183,9 +183,11 @@ struct PartitionArgs {
     int64_t hist_cap;          // entries available in hist
     int32_t* scan_tmp;         // scan scratch
     uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp; // Sliced sort scratch
+    float* xa;                 // [n][partition_row_stride(d)] row-major canonical staging copy
     int32_t* dev_status;
 };
 int64_t partition_hist_elems(int64_t n, int32_t p);
+inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st);
 
 // sky_skyline.hip: segmented skyline engine (see the file header)
@@ -193,6 +195,8 @@ struct EngineBuffers {
     int32_t* w0; int32_t* w1;      // work lists (capacity n)
     int32_t* head;                 // head groups, 64-aligned per segment (capacity hcap)
     int32_t* rest;                 // rest groups (capacity n)
+    int32_t* rhb;                  // [n] at the first rest item of each 64-item group: the
+                                   // segment's head rows before it in position order
     uint32_t* hval;                // [d][hcap] head candidate bit patterns (pads = all ones)
     uint32_t* hlo;                 // [d][tcap] per-tile lower corners
     uint32_t* hhi;                 // [d][tcap] per-tile upper corners

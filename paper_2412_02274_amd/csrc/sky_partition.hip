@@ -29,6 +29,22 @@ namespace sky {
 
 namespace {
 
+// Row stride (floats) of the row-major staging copy: the smallest of 4, 8, 16 that holds d.
+template <int D>
+constexpr int row_stride() { return D == 0 ? 16 : (D <= 4 ? 4 : (D <= 8 ? 8 : 16)); }
+
+// The canonical values of row i from the staging copy.
+template <int D>
+__device__ __forceinline__ void load_row(const float* __restrict__ xa, int64_t i, float* v) {
+    constexpr int RS = row_stride<D>();
+    const float4* row = reinterpret_cast<const float4*>(xa + i * RS);
+#pragma unroll
+    for (int c = 0; c < RS / 4; ++c) {
+        const float4 q = row[c];
+        v[4 * c] = q.x; v[4 * c + 1] = q.y; v[4 * c + 2] = q.z; v[4 * c + 3] = q.w;
+    }
+}
+
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int64_t kHistCap = int64_t(1) << 22;  // max entries of the histogram table
 
@@ -145,7 +161,7 @@ __global__ void __launch_bounds__(kBlock) part_hist_kernel(const int32_t* __rest
 // ---- stable scatter into partition-contiguous order ---------------------------------------------
 template <int D>
 __global__ void __launch_bounds__(kBlock) part_scatter_kernel(
-    const float* __restrict__ x, int64_t n, int32_t d_rt, int64_t ld,
+    const float* __restrict__ xa, int64_t n, int32_t d_rt,
     const int32_t* __restrict__ part, const uint32_t* __restrict__ order, int32_t p, int pbits,
     int chunks, const int32_t* __restrict__ offs, int64_t ntiles, float* __restrict__ xp, int64_t ldp,
     int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
@@ -173,13 +189,14 @@ __global__ void __launch_bounds__(kBlock) part_scatter_kernel(
         __builtin_amdgcn_wave_barrier();
         if (valid) {
             int32_t pos = b + (int32_t)__popcll(peers & lt);
+            float v[row_stride<D>()];
+            load_row<D>(xa, i, v);
             float f = 0.0f;
 #pragma unroll
             for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
                 if (k < d) {
-                    float v = canon(x[(int64_t)k * ld + i]);
-                    xp[(int64_t)k * ldp + pos] = v;
-                    f = __fadd_rn(f, v);
+                    xp[(int64_t)k * ldp + pos] = v[k];
+                    f = __fadd_rn(f, v[k]);
                 }
             rowid[pos] = (int32_t)i;
             seg[pos] = id;
@@ -242,25 +259,37 @@ __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restr
 // ---- Hilbert key of every row (canonical values), with validation ----------------------------
 // Used to order the rows of each partition along a space-filling curve, so that consecutive
 // rows are close in space (tight tile boxes for the dominance tests).
+// Curve key of every row, and the row's canonical values copied row-major (stride
+// row_stride<D>(), zero padded): the gathers into curve order then read one contiguous row
+// per item instead of d scattered values.
+template <int D>
 __global__ void __launch_bounds__(kBlock) curve_rows_kernel(const float* __restrict__ x, int64_t n,
-                                                             int32_t d, int64_t ld, int bits,
+                                                             int32_t d_rt, int64_t ld, int bits,
                                                              uint32_t* __restrict__ keys,
                                                              uint32_t* __restrict__ vals,
+                                                             float* __restrict__ xa,
                                                              int32_t* dev_status) {
+    constexpr int RS = row_stride<D>();
+    const int d = dget<D>(d_rt);
     int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool bad = false;
     if (i < n) {
-        float v[SKY_MAX_D];
-        for (int k = 0; k < d; ++k) {
-            float t = x[(int64_t)k * ld + i];
+        float v[RS];
+#pragma unroll
+        for (int k = 0; k < RS; ++k) {
+            float t = k < d ? x[(int64_t)k * ld + i] : 0.0f;
             bad |= !in_domain(t);
             v[k] = canon(t);
         }
         keys[i] = hilbert_key(v, d, bits);
         vals[i] = (uint32_t)i;
+        float4* row = reinterpret_cast<float4*>(xa + i * RS);
+#pragma unroll
+        for (int c = 0; c < RS / 4; ++c) row[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
     }
     if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
 }
+
 
 // Sliced: the row at rank q of the (value, row) order goes to partition floor(q p / n)
 __global__ void __launch_bounds__(kBlock) slice_parts_kernel(const uint32_t* __restrict__ order,
@@ -289,20 +318,21 @@ __global__ void __launch_bounds__(kBlock) slice_keys_kernel(const float* __restr
 
 template <int D>
 __global__ void __launch_bounds__(kBlock) slice_gather_kernel(
-    const float* __restrict__ x, int64_t n, int32_t d_rt, int64_t ld, int32_t p,
+    const float* __restrict__ xa, int64_t n, int32_t d_rt, int32_t p,
     const uint32_t* __restrict__ order, float* __restrict__ xp, int64_t ldp,
     int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
     const int d = dget<D>(d_rt);
     int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (q >= n) return;
     int64_t i = order[q];
+    float v[row_stride<D>()];
+    load_row<D>(xa, i, v);
     float f = 0.0f;
 #pragma unroll
     for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
         if (k < d) {
-            float v = canon(x[(int64_t)k * ld + i]);
-            xp[(int64_t)k * ldp + q] = v;
-            f = __fadd_rn(f, v);
+            xp[(int64_t)k * ldp + q] = v[k];
+            f = __fadd_rn(f, v[k]);
         }
     rowid[q] = (int32_t)i;
     seg[q] = (int32_t)((q * (int64_t)p) / n);
@@ -375,14 +405,14 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     }
     // 2. every row in Hilbert order (stable): the order rows take inside their partition
     const int bits = curve_bits(a.d);
-    hipLaunchKernelGGL(curve_rows_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld, bits,
-                       a.k0, a.v0, a.dev_status);
+    SKY_DISPATCH_D(a.d, curve_rows_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld, bits,
+                   a.k0, a.v0, a.xa, a.dev_status);
     SKY_HIP(hipGetLastError());
     SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, bits * a.d, a.radix_tmp, st));
     const uint32_t* order = a.v0;
     if (a.p == 1) {
-        SKY_DISPATCH_D(a.d, slice_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d,
-                       a.ld, 1, order, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
+        SKY_DISPATCH_D(a.d, slice_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st,
+                       (const float*)a.xa, n, a.d, 1, order, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
         SKY_HIP(hipGetLastError());
         hipLaunchKernelGGL(slice_offsets_kernel, dim3(1), dim3(64), 0, st, n, 1, a.part_off, a.pruned);
         SKY_HIP(hipGetLastError());
@@ -399,8 +429,8 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     SKY_HIP(hipGetLastError());
     SKY_TRY(launch_exclusive_scan(a.hist, a.hist, (int64_t)a.p * ntiles, a.scan_tmp, st));
     const int pbits = bits_for(a.p);
-    SKY_DISPATCH_D(a.d, part_scatter_kernel, dim3(tblocks), dim3(kBlock), lds, st, a.x, n, a.d,
-                   a.ld, (const int32_t*)a.part_of_row, order, a.p, pbits, chunks,
+    SKY_DISPATCH_D(a.d, part_scatter_kernel, dim3(tblocks), dim3(kBlock), lds, st,
+                   (const float*)a.xa, n, a.d, (const int32_t*)a.part_of_row, order, a.p, pbits, chunks,
                    (const int32_t*)a.hist, ntiles, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
     SKY_HIP(hipGetLastError());
     hipLaunchKernelGGL(part_offsets_kernel, dim3((uint32_t)ceil_div(a.p + 1, 256)), dim3(256), 0,

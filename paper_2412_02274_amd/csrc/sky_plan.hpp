@@ -23,6 +23,7 @@ struct sky_plan {
     int32_t *part_of_row = nullptr, *phist = nullptr, *scan_tmp = nullptr;
     int64_t phist_cap = 0;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
+    float* xa = nullptr;  // row-major staging copy for the gathers into curve order
     int32_t* radix_tmp = nullptr;
     sky::EngineBuffers eng{};
     uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;

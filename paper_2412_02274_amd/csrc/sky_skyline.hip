@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(kBlock) split_scatter_kernel(
     const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
     const uint32_t* __restrict__ smax, const int32_t* __restrict__ info,
     const int32_t* __restrict__ bcnt, int32_t* __restrict__ head, int32_t* __restrict__ rest,
-    uint8_t* __restrict__ dom) {
+    int32_t* __restrict__ rhb, uint8_t* __restrict__ dom) {
     const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
     __shared__ int32_t chunk_cnt[kCChunks];
     const int wave = threadIdx.x / kWave;
@@ -537,8 +537,14 @@ __global__ void __launch_bounds__(kBlock) split_scatter_kernel(
         const int32_t hscan = pre + chunk_cnt[ch] + __popcll(mball[q] & __lanemask_lt());
         const int32_t* si = info + mseg[q] * kInfo;
         const int32_t hr = hscan - si[SI_HEADPRE];
-        if (h) head[si[SI_HEADOFF] + hr] = mpos[q];
-        else rest[si[SI_RESTOFF] + (i - si[SI_LISTOFF]) - hr] = mpos[q];
+        if (h) {
+            head[si[SI_HEADOFF] + hr] = mpos[q];
+        } else {
+            const int32_t ri = (i - si[SI_LISTOFF]) - hr;  // rest index in the segment
+            rest[si[SI_RESTOFF] + ri] = mpos[q];
+            // where the test kernel's wave of items [ri, ri + 64) starts in the head tiles
+            if ((ri & (kWave - 1)) == 0) rhb[si[SI_RESTOFF] + ri] = hr;
+        }
         dom[mpos[q]] = 0;
     }
 }
@@ -707,7 +713,8 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     const float* __restrict__ xp, int64_t ldp, int32_t d_rt, int32_t nseg,
     const int32_t* __restrict__ unit_off_all, const int32_t* __restrict__ info,
     const int32_t* __restrict__ head, const int32_t* __restrict__ rest,
-    const uint32_t* __restrict__ hval, int64_t hcap, const uint32_t* __restrict__ hlo,
+    const int32_t* __restrict__ rhb, const uint32_t* __restrict__ hval, int64_t hcap,
+    const uint32_t* __restrict__ hlo,
     const uint32_t* __restrict__ hhi, int64_t tcap, const int32_t* __restrict__ round_counters,
     uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
@@ -769,9 +776,15 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
             }
         const uint64_t born = __builtin_amdgcn_ballot_w64(have && dom[mypos] == 0);
         uint64_t live = born, written = 0;
-        // the head group's own tile first (its rows' nearest neighbours on the curve)
-        int32_t start = 0;
-        if (mode == 0 && nr == 1) start = (ibase / kTile) % ntile;
+        // start at the head tile nearest the wave's items on the curve (the likeliest place of
+        // their dominators) and go forward: a head group's own tile, or for rest items the tile
+        // of the head rows that precede the wave's first item; a unit whose tile range does not
+        // hold that tile starts at the beginning of its range
+        int32_t own = 0;
+        if (mode == 0) own = ibase / kTile;
+        else if (ibase < icnt) own = rhb[ioff + ibase] / kTile;
+        own = own < ntile ? own : ntile - 1;
+        const int32_t start = (own >= c0 && own < c0 + span) ? own - c0 : 0;
         int32_t done_steps = 0;
         // the unit's tiles in visiting order c(step) = c0 + (start + step) mod span, 64 at a time
         for (int32_t b0 = 0; b0 < span && live; b0 += kWave) {
@@ -1076,7 +1089,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                            (const int32_t*)b.seg_info, b.scan);
         hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
                            pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                           (const int32_t*)b.seg_info, (const int32_t*)b.scan, b.head, b.rest, b.dom);
+                           (const int32_t*)b.seg_info, (const int32_t*)b.scan, b.head, b.rest, b.rhb, b.dom);
         SKY_HIP(hipGetLastError());
         const int64_t slot_bound = ub + (int64_t)kTile * nseg;
         SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
@@ -1093,8 +1106,8 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(groups_ub + 2 * want_wg)),
                        dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
                        (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.rest,
-                       (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo, (const uint32_t*)b.hhi,
-                       b.tcap, (const int32_t*)cnt, b.dom, b.tests);
+                       (const int32_t*)b.rhb, (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo,
+                       (const uint32_t*)b.hhi, b.tcap, (const int32_t*)cnt, b.dom, b.tests);
         SKY_HIP(ev_rec(false));
         // the survivors of the rest groups, in order, are the next round's work list
         // (and the head survivors into the output, in extra blocks of the same launch)
