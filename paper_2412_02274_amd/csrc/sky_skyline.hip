@@ -6,7 +6,8 @@
 // score; Sec. 2 scoring functions, Sec. 4 SFS):
 //   1. per segment, the FP32 attribute sum f of the live rows is binned between the
 //      segment's min and max; the head is the set of rows in the lowest bins holding at
-//      least kHead rows. f is monotone: a row dominating another has f <= the other's f
+//      least kHead rows (all the live rows once there are at most kAllHead of them, which
+//      ends the segment in one all-pairs round instead of several small ones). f is monotone: a row dominating another has f <= the other's f
 //      (FP32 additions are monotone), so every dominator of a head row is itself in the head.
 //   2. head skyline: every head row is tested against the other head rows of its segment.
 //      The survivors are exactly the segment's skyline rows inside the head (their
@@ -43,6 +44,7 @@ namespace sky {
 namespace {
 
 constexpr int kHead = 8192;   // head rows per segment and round (target)
+constexpr int kAllHead = 65536;  // a segment with at most this many live rows takes them all
 constexpr int kTargetWaves = 8192;  // waves per test launch the item split aims at
 constexpr int kTile = 64;     // candidates per tile box
 constexpr uint32_t kPad = 0x7FFFFFFFu;  // padding candidates: above every real value, also as int32
@@ -261,12 +263,14 @@ __global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict
         if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-// One wave per segment: smallest bin b* whose cumulative count reaches kHead.
 // head threshold of segment s, by one wavefront: the lowest bins holding at least kHead rows
+// (or all the live rows, at most kAllHead)
 __device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int32_t* __restrict__ info) {
     const int lane = (int)lane_id();
     const int32_t* h = hist + (int64_t)s * kBins;
     int32_t live = info[s * kInfo + SI_LIVE];
+    // few rows left: all of them form the head, and the segment finishes in this round
+    const int32_t want = live <= kAllHead ? live : kHead;
     int32_t run = 0, bstar = kBins - 1, headn = live;
     bool done = false;
     for (int base = 0; base < kBins && !done; base += kWave) {
@@ -276,7 +280,7 @@ __device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int3
             int32_t o = __shfl_up(inc, off, kWave);
             if (lane >= off) inc += o;
         }
-        uint64_t hit = __ballot(run + inc >= kHead);
+        uint64_t hit = __ballot(run + inc >= want);
         if (hit) {
             int l = __ffsll((unsigned long long)hit) - 1;
             bstar = base + l;
