@@ -48,7 +48,7 @@ namespace {
 constexpr int kTileC = 64;               // candidates per tile
 constexpr int kGresBlock = 512;          // threads per workgroup of the search kernels
 constexpr int kWaves = kGresBlock / kWave;
-constexpr int kBatch = 4;                // candidate tiles fetched per round trip
+constexpr int kBatch = 2;                // candidate tiles fetched per round trip (measured best)
 constexpr int kGresLdsBytes = 64 * 1024; // tile boxes cached in LDS when they fit
 constexpr float kPadValue = 2.0f;
 constexpr int kBandLevels = 6;           // levels per band of the TILES search
@@ -326,7 +326,8 @@ __device__ __forceinline__ WgWork wg_work(const int32_t* wg_table, int32_t per_w
 }
 
 template <int D>
-__global__ void __launch_bounds__(kGresBlock) gres_tiles_kernel(
+// 8 waves per SIMD: the search waits on cache round trips, so more waves in flight pay
+__global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu(8))) gres_tiles_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
     const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
     const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
