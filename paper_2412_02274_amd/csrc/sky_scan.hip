@@ -1,7 +1,6 @@
 // Exclusive prefix sum of int32 values (totals must fit in int32), used for partition and
 // histogram offsets. Three phases per level: block sums, scan of the block sums (recursive),
-// block-local scan plus the block's offset; inputs of a few chunks take one single-workgroup
-// launch instead. Each block covers kChunk consecutive values,
+// block-local scan plus the block's offset. Each block covers kChunk consecutive values,
 // staged through LDS so that global reads and writes are coalesced. in == out is allowed.
 #include "sky_internal.hpp"
 
@@ -77,42 +76,6 @@ __global__ void __launch_bounds__(kBlock) block_scan_kernel(const int32_t* in, i
     }
 }
 
-// Small inputs (a few chunks): one workgroup walks the chunks in order, carrying the running
-// total, instead of three launches.
-__global__ void __launch_bounds__(kBlock) scan_small_kernel(const int32_t* in, int64_t n, int32_t* out) {
-    __shared__ int32_t buf[kChunk];
-    int32_t carry = 0;
-    for (int64_t base = 0; base < n; base += kChunk) {
-        for (int i = threadIdx.x; i < kChunk; i += kBlock) {
-            const int64_t g = base + i;
-            buf[i] = g < n ? in[g] : 0;
-        }
-        __syncthreads();
-        int32_t local[kPer];
-        int32_t acc = 0;
-        for (int j = 0; j < kPer; ++j) {
-            local[j] = buf[threadIdx.x * kPer + j];
-            acc += local[j];
-        }
-        int32_t excl;
-        const int32_t total = block_exclusive_scan(acc, &excl);  // ends with a barrier
-        int32_t run = carry + excl;
-        for (int j = 0; j < kPer; ++j) {
-            buf[threadIdx.x * kPer + j] = run;
-            run += local[j];
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < kChunk; i += kBlock) {
-            const int64_t g = base + i;
-            if (g < n) out[g] = buf[i];
-        }
-        carry += total;
-        __syncthreads();  // buf is reloaded by the next chunk
-    }
-}
-
-constexpr int64_t kSmallScanChunks = 4;
-
 }  // namespace
 
 int64_t scan_tmp_elems(int64_t n) {
@@ -132,11 +95,6 @@ sky_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int
     if (blocks == 1) {
         hipLaunchKernelGGL(block_scan_kernel, dim3(1), dim3(kBlock), 0, st, in, n,
                            (const int32_t*)nullptr, out);
-        SKY_HIP(hipGetLastError());
-        return SKY_OK;
-    }
-    if (blocks <= kSmallScanChunks) {
-        hipLaunchKernelGGL(scan_small_kernel, dim3(1), dim3(kBlock), 0, st, in, n, out);
         SKY_HIP(hipGetLastError());
         return SKY_OK;
     }
