@@ -253,6 +253,19 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld,
                         const sky_gres_opts* opts, void* stream);
 
 /*
+ * sky_gres -- gres_compute for the plan's own skyline, after sky_merge: the candidates and the
+ * tuples are Sky(r) as sky_merge returned it, and g_exit[j] / gres[j] (device arrays of
+ * info.sky_count entries, either may be null) refer to sky_idx[j] of that call. The result is
+ * the one gres_compute gives for (x, sky_idx, info.sky_count, g_max), but the candidates are
+ * read from the plan's partition-contiguous copy in its curve order, so no sort is needed.
+ * ws: at least gres_workspace_bytes(info.sky_count, d, g_max) bytes (device, caller-owned).
+ * g_max in [2, SKY_MAX_G]; opts as for gres_compute. SKY_ERR_STATE before sky_merge. The
+ * plan's skyline state is read, not changed (calls may repeat). Never synchronises.
+ */
+sky_status sky_gres(sky_plan* plan, int32_t g_max, int32_t* g_exit, float* gres, void* ws,
+                    size_t ws_bytes, int32_t* dev_status, const sky_gres_opts* opts, void* stream);
+
+/*
  * Workspace for gres_gbar, in bytes (independent of d). Returns 0 for invalid arguments.
  */
 size_t gres_gbar_workspace_bytes(int64_t n);

@@ -41,7 +41,7 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "gres_search_bytes", "gres_search",
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
            "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
-           "sky_plan_set_host_scratch", "gres_gbar_workspace_bytes", "gres_gbar")
+           "sky_plan_set_host_scratch", "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres")
 
 
 class SkyParams(C.Structure):
@@ -126,6 +126,7 @@ def load():
         "sky_plan_set_host_scratch": (i32, [vp, vp, sz]),
         "gres_gbar_workspace_bytes": (sz, [i64]),
         "gres_gbar": (i32, [vp, i64, i32, i64, vp, vp, vp, sz, vp, vp]),
+        "sky_gres": (i32, [vp, i32, vp, vp, vp, sz, vp, C.POINTER(GresOpts), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

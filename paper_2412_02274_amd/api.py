@@ -106,6 +106,26 @@ class Plan:
         out = self.sky_idx[:s]
         return (out, mem) if member else out
 
+    def gres(self, g_max: int = 25, mapping="auto"):
+        """sky_gres after merge(): (g_exit int32[s], gres float32[s]) aligned with the skyline
+        merge() returned (the plan's own skyline as candidates and tuples)."""
+        lib = _lib.load()
+        inf = self.info()
+        s, d = int(inf["sky_count"]), self.x_soa.shape[0]
+        dev = self.x_soa.device
+        need = int(lib.gres_workspace_bytes(s, d, g_max))
+        if need == 0:
+            raise SkyError(_lib.SKY_ERR_INVALID_ARG, "gres_workspace_bytes")
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        ge = torch.empty(max(s, 1), dtype=torch.int32, device=dev)
+        gr = torch.empty(max(s, 1), dtype=torch.float32, device=dev)
+        opts = _lib.GresOpts(_lib.MAPPINGS[mapping] if isinstance(mapping, str) else int(mapping))
+        _lib.check(lib.sky_gres(self._h, g_max, _ptr(ge), _ptr(gr), _ptr(ws), need, _ptr(self.status),
+                                C.byref(opts), _stream_ptr(self.stream)), "sky_gres")
+        torch.cuda.current_stream().synchronize() if self.stream is None else self.stream.synchronize()
+        check_status(self.status, "sky_gres")
+        return ge[:s], gr[:s]
+
     def partitions(self) -> torch.Tensor:
         """Partition of every original row (int32[n])."""
         part = torch.empty(self.x_soa.shape[1], dtype=torch.int32, device=self.x_soa.device)
@@ -433,18 +453,18 @@ class Pipeline:
             lib.sky_plan_info(h, C.byref(inf))
             self.last_info = inf.as_dict()
             s = int(inf.sky_count)
+            opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
+                                 else int(self.mapping))
+            if gres_events is not None:
+                opts.ev_begin, opts.ev_end = gres_events
+            if gres_counter is not None:
+                opts.dev_tests = gres_counter.data_ptr()
+            # gres of the plan's own skyline: candidates straight from the curve-ordered copy
+            _lib.check(lib.sky_gres(h, self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
+                                    _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),
+                                    C.byref(opts), sp), "sky_gres")
         finally:
             lib.sky_plan_destroy(h)
-        opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
-                             else int(self.mapping))
-        if gres_events is not None:
-            opts.ev_begin, opts.ev_end = gres_events
-        if gres_counter is not None:
-            opts.dev_tests = gres_counter.data_ptr()
-        _lib.check(lib.gres_compute(_ptr(self.x_soa), self.n, self.d, self.n, _ptr(self.sky_buf), s,
-                                    self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
-                                    _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),
-                                    C.byref(opts), sp), "gres_compute")
         if ev:
             ev[5].record(st)
             self.events = ev

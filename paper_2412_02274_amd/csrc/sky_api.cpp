@@ -445,6 +445,39 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
                               opts ? opts->dev_tests : nullptr, st);
 }
 
+sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, void* ws, size_t ws_bytes,
+                    int32_t* dev_status, const sky_gres_opts* opts, void* stream) {
+    if (!P || !dev_status || g_max < 2 || g_max > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
+    if (P->state != 3) return SKY_ERR_STATE;
+    int32_t mapping = 0;
+    SKY_TRY(check_opts(opts, &mapping));
+    const int64_t s = P->info.sky_count;
+    if (s == 0) return SKY_OK;
+    if (!ws || ws_bytes < gres_workspace_bytes(s, P->d, g_max)) return SKY_ERR_WORKSPACE;
+    Carver c(ws, ws_bytes);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    GresTargets tg{};
+    carve_gres_store(c, store, s, P->d, 1);
+    carve_gres_prep_tmp(c, tmp, s);
+    carve_gres_targets(c, tg, s, P->d);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
+    // the skyline's positions in ascending order (curve order inside each partition, and
+    // partitions are contiguous: with p > 1 the store is ordered by partition, then curve)
+    const uint8_t* flags = P->p > 1 ? P->final_flag : P->local_flag;
+    int32_t* pos = (int32_t*)tmp.k0;  // s entries, free until the search
+    SKY_TRY(launch_compact_flags(flags, (int32_t)P->n, pos, P->count_tmp, P->eng.flag, P->eng.scan,
+                                 P->eng.scan_tmp, st));
+    // the row -> index-in-sky_idx map is left in pos_tmp by sky_merge
+    SKY_TRY(launch_gres_prepare_positions(P->xp, P->ldp, P->d, pos, s, P->rowid, P->pos_tmp, store, st));
+    SKY_TRY(launch_gres_targets(nullptr, 0, P->d, 0, nullptr, s, s, store, tg, dev_status, st));
+    return launch_gres_search(store, P->d, (int32_t)s, tg, s, nullptr, 0, g_max, mapping, g_exit, gres,
+                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
+                              opts ? opts->dev_tests : nullptr, st);
+}
+
 size_t gres_gbar_workspace_bytes(int64_t n) {
     if (n < 0 || n > kMaxRows) return 0;
     Carver c(nullptr, 0);

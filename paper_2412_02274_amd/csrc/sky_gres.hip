@@ -123,6 +123,29 @@ __global__ void __launch_bounds__(kBlock) store_kernel(const float* __restrict__
     perm[q] = j;
 }
 
+// every slot of the store from a plan's partition-contiguous copy: the candidates are the rows at
+// positions pos[0, s), already in curve order (the copy is), so no sort is needed; the caller
+// index of a slot is idx_of_row[row] (padding: 2.0, ~0, -1)
+__global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restrict__ xp, int64_t ldp,
+                                                            int32_t d, const int32_t* __restrict__ pos,
+                                                            int32_t s, const int32_t* __restrict__ rowid,
+                                                            const int32_t* __restrict__ idx_of_row,
+                                                            float* __restrict__ cand, int64_t ccap,
+                                                            uint32_t* __restrict__ ckey,
+                                                            int32_t* __restrict__ perm) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= ccap) return;
+    const bool real = q < s;
+    const int32_t p = real ? pos[q] : 0;
+    float v[SKY_MAX_D];
+    for (int k = 0; k < d; ++k) {
+        v[k] = real ? xp[(int64_t)k * ldp + p] : kPadValue;
+        cand[(int64_t)k * ccap + q] = v[k];
+    }
+    ckey[q] = real ? hilbert_key(v, d, curve_bits(d)) : 0xFFFFFFFFu;
+    perm[q] = real ? idx_of_row[rowid[p]] : -1;
+}
+
 // one wave per tile: componentwise minimum (lo) and maximum (hi) of its real candidates (padding
 // slots hold kPadValue in every attribute; a tile of padding only gets lo = 1, which no key test
 // passes: fl(1 g) = g is above every key of a value in [0, 1))
@@ -782,6 +805,22 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
     hipLaunchKernelGGL(store_kernel, dim3((uint32_t)ceil_div(store.ccap, kBlock)), dim3(kBlock), 0, st,
                        x, n, d, ld, rows, s, (const uint32_t*)tmp.k0, (const uint32_t*)tmp.v0,
                        store.cand, store.ccap, store.ckey, store.perm);
+    const int32_t ntile = (int32_t)ceil_div(s, kTileC);
+    if (ntile > 0)
+        hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
+                           st, (const float*)store.cand, store.ccap, d, ntile, store.lo, store.hi,
+                           store.tcap);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
+                                         int64_t s64, const int32_t* rowid, const int32_t* idx_of_row,
+                                         const GresStore& store, hipStream_t st) {
+    const int32_t s = (int32_t)s64;
+    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, s);
+    hipLaunchKernelGGL(store_pos_kernel, dim3((uint32_t)ceil_div(store.ccap, kBlock)), dim3(kBlock), 0, st,
+                       xp, ldp, d, pos, s, rowid, idx_of_row, store.cand, store.ccap, store.ckey, store.perm);
     const int32_t ntile = (int32_t)ceil_div(s, kTileC);
     if (ntile > 0)
         hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,

@@ -270,6 +270,11 @@ void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d);
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t s, const GresStore& store, const GresPrepTmp& tmp,
                                int32_t* dev_status, hipStream_t st);
+// Store from a plan's partition-contiguous copy xp: the candidates are the rows at positions
+// pos[0, s) (ascending, hence curve order); perm[slot] = idx_of_row[rowid[pos]].
+sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
+                                         int64_t s, const int32_t* rowid, const int32_t* idx_of_row,
+                                         const GresStore& store, hipStream_t st);
 sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t nt, int64_t s, const GresStore& store, const GresTargets& tg,
                                int32_t* dev_status, hipStream_t st);

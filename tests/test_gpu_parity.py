@@ -171,6 +171,9 @@ def test_plan_state_errors(dev):
     with pytest.raises(api.SkyError) as e:
         plan.local_skylines()
     assert e.value.code == 6
+    with pytest.raises(api.SkyError) as e:
+        plan.gres(25)  # sky_gres needs the merged skyline
+    assert e.value.code == 6
     plan.merge()
     plan.close()
 
@@ -276,6 +279,51 @@ def test_config_uni_10m_d4_partitioned(dev, scheme):
     ge, _ = api.gres(xs, torch.from_numpy(idx).to(dev), 25)
     want_ge, _ = oracle.gres(x, want_sky, 25)
     assert (ge.cpu().numpy() == want_ge).all()
+
+
+@pytest.mark.parametrize("scheme,p", [("none", 1), ("grid", 16), ("angular", 16), ("sliced", 64)])
+@pytest.mark.parametrize("kind,n,d", [("uni", 3001, 3), ("ant", 4000, 5), ("ties", 5000, 4),
+                                      ("dyadic", 2000, 6), ("uni", 1, 2), ("ant", 70, 1)])
+@pytest.mark.parametrize("g_max", [25, 300])
+def test_plan_gres(dev, scheme, p, kind, n, d, g_max):
+    """sky_gres (the plan's own skyline, candidates read from its curve-ordered copy) against
+    gres_compute on the skyline merge() returned, and against the oracle."""
+    if d == 1 and scheme != "none":
+        pytest.skip("partitioned schemes need d >= 2")
+    x = _rows(kind, n, d, 4)
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    plan = api.build(xs, scheme, p)
+    plan.local_skylines()
+    sky = plan.merge().clone()
+    ge, gr = plan.gres(g_max)
+    ge2, _ = plan.gres(g_max, mapping="levels")  # the plan's skyline state is only read
+    plan.close()
+    ref, ref_gr = api.gres(xs, sky, g_max)
+    want, _ = oracle.gres(x, sky.cpu().numpy(), g_max)
+    assert np.array_equal(ge.cpu().numpy(), want)
+    assert np.array_equal(ge2.cpu().numpy(), want)
+    assert np.array_equal(ref.cpu().numpy(), want)
+    assert np.array_equal(gr.cpu().numpy(), ref_gr.cpu().numpy())
+
+
+def test_plan_gres_all_equal_and_full_size(dev):
+    # every row equal: the skyline is all of them, and nobody exits
+    x = np.full((500, 3), 0.375, np.float32)
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    plan = api.build(xs)
+    plan.local_skylines()
+    sky = plan.merge()
+    ge, _ = plan.gres(25)
+    plan.close()
+    assert len(sky) == 500 and (ge.cpu().numpy() == 1).all()
+    # the anticorrelated 1,000,000 x 6 workload through the pipeline (which uses sky_gres):
+    # every tuple equal to gres_compute on the same skyline
+    x = G.ant(1_000_000, 6, 0)
+    pipe = api.Pipeline(1_000_000, 6, g_max=25, device=dev)
+    sky, ge, _ = pipe.run(torch.from_numpy(x).to(dev))
+    ref, _ = api.gres(pipe.x_soa, sky.clone(), 25)
+    assert len(sky) == 44336
+    assert np.array_equal(ge.cpu().numpy(), ref.cpu().numpy())
 
 
 _C10M = {}
