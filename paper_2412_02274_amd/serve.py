@@ -25,7 +25,9 @@ waited for before the next starts.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
+import gc
 import time
 from dataclasses import dataclass, field
 
@@ -277,14 +279,15 @@ class Server:
     def run_trace(self, queries, clock=time.perf_counter):
         """Replay arrivals in real time (queries sorted by arrival); returns completed queries."""
         self.completed = []
-        t0 = clock()
-        i = 0
-        while i < len(queries) or self.busy():
-            now = clock() - t0
-            while i < len(queries) and queries[i].arrival <= now:
-                self.queue.append(queries[i])
-                i += 1
-            self.poll(now)
+        with _no_gc_pauses():
+            t0 = clock()
+            i = 0
+            while i < len(queries) or self.busy():
+                now = clock() - t0
+                while i < len(queries) and queries[i].arrival <= now:
+                    self.queue.append(queries[i])
+                    i += 1
+                self.poll(now)
         return self.completed
 
 
@@ -324,15 +327,31 @@ class PlainServer:
 
     def run_trace(self, queries, clock=time.perf_counter):
         done = []
-        t0 = clock()
-        for q in queries:
-            while clock() - t0 < q.arrival:
-                pass
-            q.admitted = clock() - t0
-            self.run_one(q)
-            q.done = clock() - t0
-            done.append(q)
+        with _no_gc_pauses():
+            t0 = clock()
+            for q in queries:
+                while clock() - t0 < q.arrival:
+                    pass
+                q.admitted = clock() - t0
+                self.run_one(q)
+                q.done = clock() - t0
+                done.append(q)
         return done
+
+
+@contextlib.contextmanager
+def _no_gc_pauses():
+    """The dispatch loop runs with Python's cyclic garbage collector off: a full collection over
+    thousands of live query objects stalls every query in flight for tens of milliseconds. It
+    is switched back on (and run once) when the loop ends."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+            gc.collect()
 
 
 def latency_stats(done):
