@@ -285,7 +285,9 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
         free(pr);
     }
     SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
-    SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID ? P->pruned : nullptr, P->seg, n, P->eng.w1,
+    // the rows outside the pruned Grid cells (every row when none is pruned)
+    SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID && P->info.pruned_rows > 0 ? P->pruned : nullptr,
+                                 P->seg, n, P->eng.w1,
                                  P->count_tmp, P->eng.flag, P->eng.scan, P->eng.scan_tmp, st));
     // live rows: every row outside the pruned Grid cells (exactly what the list holds)
     const int32_t live = n - (int32_t)P->info.pruned_rows;

@@ -985,6 +985,13 @@ __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
 }
 
 // stable compaction helpers: flags, then out[scan[i]] = i
+__global__ void __launch_bounds__(kBlock) iota_kernel(int32_t n, int32_t* __restrict__ out,
+                                                       int32_t* __restrict__ count) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = i;
+    if (i == 0) *count = n;
+}
+
 __global__ void __launch_bounds__(kBlock) keep_flag_kernel(const uint8_t* __restrict__ skip_seg,
                                                             const int32_t* __restrict__ seg,
                                                             const uint8_t* __restrict__ flags_u8,
@@ -1206,9 +1213,14 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
                                 int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
                                 int32_t* scan_tmp, hipStream_t st) {
+    const uint32_t nb = (uint32_t)ceil_div(n > 0 ? n : 1, kBlock);
+    if (!skip_seg) {  // nothing skipped: the list is every position
+        hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(kBlock), 0, st, n, out, count);
+        SKY_HIP(hipGetLastError());
+        return SKY_OK;
+    }
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, count, 1);
     if (n <= 0) { SKY_HIP(hipGetLastError()); return SKY_OK; }
-    const uint32_t nb = (uint32_t)ceil_div(n, kBlock);
     hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, skip_seg, seg_of_pos,
                        (const uint8_t*)nullptr, n, flag);
     SKY_HIP(hipGetLastError());
