@@ -326,6 +326,22 @@ def test_plan_gres_all_equal_and_full_size(dev):
     assert np.array_equal(ge.cpu().numpy(), ref.cpu().numpy())
 
 
+@pytest.mark.parametrize("kind,n,d,p", [("uni", 600000, 3, 4), ("ant", 300000, 4, 2),
+                                        ("ties", 400000, 5, 3)])
+def test_multi_round_segments(dev, kind, n, d, p):
+    """Sliced partitions of more than 65,536 rows each: every segment runs several
+    head-and-filter rounds (the all-pairs shortcut only ends them), side by side in the same
+    launches. Local skylines and the final skyline against the oracle."""
+    x = _rows(kind, n, d, 33)
+    xs, idx, part, loc, info = run_skyline(dev, x, "sliced", p)
+    _say(f"multi-round {kind} {n}x{d} p={p}: rounds {info['rounds_local']}+{info['rounds_merge']}")
+    if kind != "ties":  # tied scores can put a whole segment into the first head
+        assert info["rounds_local"] >= 2
+    check_partitioned(x, "sliced", p, part, loc, info)
+    mem, _ = oracle.skyline_sfs(x)
+    assert np.array_equal(idx, np.flatnonzero(mem))
+
+
 _C10M = {}
 
 
@@ -388,7 +404,7 @@ def test_gres_search_concurrent_streams(dev):
 
 @pytest.mark.parametrize("scheme,p", [("none", 1), ("grid", 16), ("angular", 16), ("sliced", 64)])
 @pytest.mark.parametrize("kind,n,d", [("ant", 60000, 5), ("uni", 200000, 3), ("ties", 120000, 6),
-                                      ("ant", 9000, 8)])
+                                      ("ant", 9000, 8), ("ant", 150000, 5)])
 def test_rounds_launched_ahead(dev, scheme, p, kind, n, d):
     # with pinned host scratch the engine launches every round before reading the previous
     # round's counters; results must equal the synchronous engine and the oracle
