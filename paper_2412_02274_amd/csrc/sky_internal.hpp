@@ -157,10 +157,12 @@ sky_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int
                                  hipStream_t st);
 
 // sky_radix.hip: stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
-// over the low 'key_bits' bits. Results end in (k0, v0) (the buffers are ping-ponged).
+// over the low 'key_bits' bits. Results end in (k0, v0) (the buffers are ping-ponged), or, when
+// out_k and out_v are given, wherever the last pass left them (no final copy).
 int64_t radix_tmp_elems(int64_t n);
 sky_status launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                             int key_bits, int32_t* tmp, hipStream_t st);
+                             int key_bits, int32_t* tmp, hipStream_t st,
+                             const uint32_t** out_k = nullptr, const uint32_t** out_v = nullptr);
 
 // sky_partition.hip
 // Internal partition scheme of the batched path: partition j = the rows [seg_off[j],

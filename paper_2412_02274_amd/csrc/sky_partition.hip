@@ -408,8 +408,9 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     SKY_DISPATCH_D(a.d, curve_rows_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld, bits,
                    a.k0, a.v0, a.xa, a.dev_status);
     SKY_HIP(hipGetLastError());
-    SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, bits * a.d, a.radix_tmp, st));
-    const uint32_t* order = a.v0;
+    const uint32_t* sorted_keys = nullptr;
+    const uint32_t* order = nullptr;
+    SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, bits * a.d, a.radix_tmp, st, &sorted_keys, &order));
     if (a.p == 1) {
         SKY_DISPATCH_D(a.d, slice_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st,
                        (const float*)a.xa, n, a.d, 1, order, a.xp, a.ldp, a.rowid, a.seg, a.fsum);

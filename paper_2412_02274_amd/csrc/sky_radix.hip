@@ -87,7 +87,10 @@ int64_t radix_tmp_elems(int64_t n) {
 }
 
 sky_status launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
-                             int key_bits, int32_t* tmp, hipStream_t st) {
+                             int key_bits, int32_t* tmp, hipStream_t st, const uint32_t** out_k,
+                             const uint32_t** out_v) {
+    if (out_k) *out_k = k0;
+    if (out_v) *out_v = v0;
     if (n <= 1) return SKY_OK;
     const int64_t ntiles = ceil_div(n, kTile);
     const int64_t blocks = ceil_div(ntiles, kWavesPerBlock);
@@ -107,6 +110,11 @@ sky_status launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t*
         uint32_t* t;
         t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
+    }
+    if (out_k && out_v) {  // the caller reads the result where the last pass left it
+        *out_k = ka;
+        *out_v = va;
+        return SKY_OK;
     }
     if (ka != k0) {
         hipLaunchKernelGGL(copy_pairs_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0,
