@@ -55,6 +55,9 @@ def _load():
         "orc_ell": (C.c_double, [_f32p, C.c_int64, C.c_int32, C.c_int64]),
         "orc_ell_sorted": (C.c_double, [_f32p, C.c_int64, C.c_int32, C.c_int64]),
         "orc_gbar": (C.c_double, [C.c_double]),
+        "orc_representatives": (C.c_int64, [_f32p, C.c_int64, C.c_int32, C.c_int64, C.c_int64, _i64p,
+                                            _u8p]),
+        "orc_dominated_by": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, _i64p, C.c_int64, _u8p]),
         "orc_num_threads": (C.c_int32, []),
     }
     for name, (res, args) in sig.items():
@@ -194,6 +197,33 @@ def gbar(x, sorted_: bool = True):
     """(ell, g_bar) with g_bar = floor(1/ell) as a Python int (1 when ell is +inf)."""
     e = ell(x, sorted_)
     return e, int(_load().orc_gbar(e))
+
+
+def representatives(x, k: int):
+    """Representative Filtering (Sec. 3.1): (rows of the k smallest FP32 attribute sums, ties in
+    row order; kept flags = not dominated by another representative)."""
+    xs, n, d = _soa(x)
+    k = min(int(k), n)
+    rows = np.zeros(max(k, 1), dtype=np.int64)
+    kept = np.zeros(max(k, 1), dtype=np.uint8)
+    _load().orc_representatives(_p(xs, _f32p), n, d, n, k, _p(rows, _i64p), _p(kept, _u8p))
+    return rows[:k], kept[:k].astype(bool)
+
+
+def dominated_by(x, by) -> np.ndarray:
+    """Rows of x dominated by some row listed in ``by`` (Def. 1)."""
+    xs, n, d = _soa(x)
+    by = np.ascontiguousarray(by, dtype=np.int64)
+    out = np.zeros(n, dtype=np.uint8)
+    _load().orc_dominated_by(_p(xs, _f32p), n, d, n, _p(by, _i64p), len(by), _p(out, _u8p))
+    return out.astype(bool)
+
+
+def local_skylines_reps(x, part, skip, k: int):
+    """Local skylines with Representative Filtering: rows of each partition's skyline that no
+    kept representative dominates."""
+    rows, kept = representatives(x, k)
+    return local_skylines(x, part, skip) & ~dominated_by(x, rows[kept])
 
 
 def gres_values(g_exit) -> np.ndarray:

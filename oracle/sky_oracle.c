@@ -26,6 +26,9 @@
  *                              and exact rationals; the worked counterexample; invariants).
  *   orc_gres_rows           -- pinned (equals orc_gres on the sampled rows).
  *   orc_skyline_rows        -- pinned (equals orc_skyline on the sampled rows).
+ *   orc_representatives     -- pinned (numpy lexsort of the FP32 scores for the selection, the
+ *                              Python brute force of Def. 1 for the kept set).
+ *   orc_dominated_by        -- pinned (brute force of Def. 1 on tiny inputs).
  *   orc_ell, orc_ell_sorted -- pinned (exact-rational brute force over pairs on tiny inputs, a
  *                              hand-worked lattice example, degenerate inputs; the two agree).
  *   orc_gbar                -- pinned (floor(1/ell) in exact rationals; on lattice data no exit
@@ -415,6 +418,55 @@ double orc_ell_sorted(const float* x, int64_t n, int32_t d, int64_t ld) {
 double orc_gbar(double ell) {
     if (!(ell < INFINITY)) return 1.0;
     return floor(1.0 / ell);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Representative Filtering (Sec. 3.1): the representatives are the k tuples with the smallest  */
+/* value of a monotone scoring function, here f = the FP32 sum of the attributes in ascending   */
+/* attribute order (the SFS score); equal scores are taken in row order. Representatives       */
+/* dominated by another representative add no pruning power and are dropped: kept[j] = 1 for    */
+/* the ones no other representative dominates (Def. 1).                                         */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct { float f; int64_t row; } rep_key;
+
+static int rep_cmp(const void* pa, const void* pb) {
+    const rep_key *a = (const rep_key*)pa, *b = (const rep_key*)pb;
+    if (a->f < b->f) return -1;
+    if (a->f > b->f) return 1;
+    return (a->row > b->row) - (a->row < b->row);
+}
+
+int64_t orc_representatives(const float* x, int64_t n, int32_t d, int64_t ld, int64_t k,
+                            int64_t* rows, uint8_t* kept) {
+    if (k > n) k = n;
+    rep_key* v = (rep_key*)malloc(sizeof(rep_key) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        float f = 0.0f;
+        for (int32_t a = 0; a < d; ++a) f = f + X(x, ld, a, i);
+        v[i].f = f;
+        v[i].row = i;
+    }
+    qsort(v, (size_t)n, sizeof(rep_key), rep_cmp);
+    for (int64_t j = 0; j < k; ++j) rows[j] = v[j].row;
+    free(v);
+    for (int64_t j = 0; j < k; ++j) {
+        kept[j] = 1;
+        for (int64_t q = 0; q < k && kept[j]; ++q)
+            if (q != j && dominates(x, ld, d, rows[q], rows[j])) kept[j] = 0;
+    }
+    return k;
+}
+
+/* flags[i] = 1 when some row of by[0..nb) dominates row i (Def. 1). */
+void orc_dominated_by(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* by,
+                      int64_t nb, uint8_t* flags) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        uint8_t f = 0;
+        for (int64_t q = 0; q < nb && !f; ++q)
+            if (dominates(x, ld, d, by[q], i)) f = 1;
+        flags[i] = f;
+    }
 }
 
 /* Projected key of one value, exposed so that the quantisation rule itself can be pinned. */

@@ -441,3 +441,57 @@ def test_no_exit_beyond_gbar(orc):
         cand = np.flatnonzero(orc.skyline(x))
         ge, _ = orc.gres(x, cand, gb)
         assert [far[int(c)] for c in cand] == ge.tolist()
+
+
+# ------------------------------------------------------------------ Representative Filtering
+
+def _fp32_scores(x):
+    f = np.zeros(len(x), np.float32)
+    for k in range(x.shape[1]):
+        f = (f + x[:, k]).astype(np.float32)  # one IEEE FP32 addition per attribute, in order
+    return f
+
+
+@pytest.mark.parametrize("kind", ["uni", "ant", "ties"])
+def test_representatives_selection(orc, kind):
+    # Sec. 3.1: the k tuples with the smallest monotone score (FP32 attribute sum), equal scores
+    # in row order; the kept ones are those no other representative dominates (Def. 1)
+    for seed, k in ((0, 1), (1, 10), (2, 60)):
+        x = _rows(kind, 400, 3 + seed % 3, seed)
+        rows, kept = orc.representatives(x, k)
+        f = _fp32_scores(x)
+        assert rows.tolist() == np.lexsort((np.arange(len(x)), f))[:k].tolist()
+        pts = [tuple(float(v) for v in x[r]) for r in rows]
+        want = [not any(brute.dominates(pts[q], pts[j]) for q in range(k) if q != j)
+                for j in range(k)]
+        assert kept.tolist() == want
+        assert kept[0]  # the smallest score is never dominated (f is monotone)
+
+
+def test_dominated_by_brute(orc):
+    for seed in range(3):
+        x = _rows("ties", 60, 3, seed)
+        by = np.array([0, 7, 19, 33])
+        got = orc.dominated_by(x, by)
+        pts = [tuple(float(v) for v in r) for r in x]
+        want = [any(brute.dominates(pts[b], pts[i]) for b in by) for i in range(len(x))]
+        assert got.tolist() == want
+
+
+@pytest.mark.parametrize("kind", ["uni", "ant", "ties"])
+def test_representatives_keep_the_skyline(orc, kind):
+    # representatives are tuples of r, so removing what they dominate never touches Sky(r):
+    # the final skyline of the reduced union is Sky(r), and each local skyline only shrinks
+    x = _rows(kind, 3000, 4, 5)
+    sky = orc.skyline(x)
+    part = orc.sliced_part(x, 8, 0)
+    plain = orc.local_skylines(x, part)
+    for k in (1, 10, 100):
+        loc = orc.local_skylines_reps(x, part, None, k)
+        assert not (loc & ~plain).any()
+        rows, kept = orc.representatives(x, k)
+        assert (plain & ~loc == plain & orc.dominated_by(x, rows[kept])).all()
+        u = np.flatnonzero(loc)
+        final = np.zeros(len(x), bool)
+        final[u[orc.skyline(x[u])]] = True
+        assert (final == sky).all()
