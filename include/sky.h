@@ -72,6 +72,7 @@ typedef enum sky_scheme {
 #define SKY_MAX_G 16777216     /* largest g_max accepted by gres_compute: 2^24, the largest level
                                   at which (float)g is exact, as the key contract needs */
 #define SKY_HOST_SCRATCH_BYTES 256 /* size of the optional pinned host scratch of a plan */
+#define SKY_MAX_REPS 1024      /* largest sky_params.reps */
 
 /* gres_compute mapping choice (sky_gres_opts.mapping). */
 #define SKY_GRES_AUTO 0         /* pick by shape */
@@ -83,7 +84,12 @@ typedef struct sky_params {
     int32_t target_p;  /* requested partitions; Grid/Angular take the closest m^e > 1 (Sec. 4),
                           Sliced takes exactly min(target_p, n); ignored for SKY_NONE */
     int32_t slice_dim; /* Sliced: attribute to sort on (0-based) */
-    int32_t flags;     /* reserved, must be 0 */
+    int32_t reps;      /* Representative Filtering (Sec. 3.1), 0 = off, at most SKY_MAX_REPS: the
+                          reps rows with the smallest FP32 attribute sum (summed in attribute
+                          order; equal sums in row order) are the representatives; those no
+                          other representative dominates are shared with every partition, and
+                          the rows they dominate leave the local skylines. The final skyline is
+                          unchanged. */
 } sky_params;
 
 typedef struct sky_info {
@@ -104,7 +110,8 @@ typedef struct sky_info {
     int64_t tests_merge;      /* dominance tests evaluated in the final phase */
     int64_t max_partition;    /* rows in the largest partition */
     int32_t events_used;      /* timing-hook event pairs recorded (sky_plan_set_events) */
-    int32_t reserved0;
+    int32_t reps_kept;        /* representatives no other representative dominates (0 when off);
+                                 their tests against the rows are counted in tests_local */
 } sky_info;
 
 typedef struct sky_gres_opts {

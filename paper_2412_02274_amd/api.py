@@ -63,14 +63,14 @@ def ingest(x_rows: torch.Tensor, status: torch.Tensor | None = None, stream=None
     return out
 
 
-def _params(scheme, target_p, slice_dim):
+def _params(scheme, target_p, slice_dim, reps=0):
     code = _lib.SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-    return _lib.SkyParams(code, int(target_p), int(slice_dim), 0)
+    return _lib.SkyParams(code, int(target_p), int(slice_dim), int(reps))
 
 
 def build_workspace_bytes(n: int, d: int, scheme="none", target_p: int = 16,
-                          slice_dim: int = 0) -> int:
-    prm = _params(scheme, target_p, slice_dim)
+                          slice_dim: int = 0, reps: int = 0) -> int:
+    prm = _params(scheme, target_p, slice_dim, reps)
     return int(_lib.load().sky_build_workspace_bytes(n, d, C.byref(prm)))
 
 
@@ -159,10 +159,11 @@ class Plan:
 
 def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0,
           status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
-          host_scratch: torch.Tensor | None = None) -> Plan:
+          host_scratch: torch.Tensor | None = None, reps: int = 0) -> Plan:
     """Partition assignment + partition-contiguous copy (sky_build). host_scratch: optional
     pinned host tensor (>= SKY_HOST_SCRATCH_BYTES) that lets the skyline rounds run one ahead of
-    their readback (sky_plan_set_host_scratch)."""
+    their readback (sky_plan_set_host_scratch). reps: Representative Filtering (Sec. 3.1), the
+    number of representatives (0 = off)."""
     lib = _lib.load()
     if x_soa.dtype != torch.float32 or x_soa.dim() != 2 or not x_soa.is_cuda:
         raise ValueError("x_soa must be a float32 [d, N] CUDA tensor")
@@ -170,7 +171,7 @@ def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int
     ld = x_soa.stride(0)
     if x_soa.stride(1) != 1:
         raise ValueError("x_soa rows must be contiguous")
-    prm = _params(scheme, target_p, slice_dim)
+    prm = _params(scheme, target_p, slice_dim, reps)
     need = int(lib.sky_build_workspace_bytes(n, d, C.byref(prm)))
     if need == 0:
         raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_build_workspace_bytes")
@@ -382,15 +383,16 @@ class Pipeline:
     run (host-side struct only)."""
 
     def __init__(self, n: int, d: int, scheme="none", target_p: int = 16, slice_dim: int = 0,
-                 g_max: int = 25, mapping="auto", device="cuda"):
+                 g_max: int = 25, mapping="auto", device="cuda", reps: int = 0):
         lib = _lib.load()
         self.n, self.d, self.g_max = int(n), int(d), int(g_max)
         self.scheme, self.target_p, self.slice_dim, self.mapping = scheme, target_p, slice_dim, mapping
+        self.reps = int(reps)
         dev = torch.device(device)
         self.device = dev
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.x_soa = torch.empty((d, n), dtype=torch.float32, device=dev)
-        prm = _params(scheme, target_p, slice_dim)
+        prm = _params(scheme, target_p, slice_dim, reps)
         self.build_bytes = int(lib.sky_build_workspace_bytes(n, d, C.byref(prm)))
         if self.build_bytes == 0:
             raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_build_workspace_bytes")
@@ -424,7 +426,7 @@ class Pipeline:
                                   _ptr(self.status), sp), "sky_ingest")
         if ev:
             ev[1].record(st)
-        prm = _params(self.scheme, self.target_p, self.slice_dim)
+        prm = _params(self.scheme, self.target_p, self.slice_dim, self.reps)
         h = C.c_void_p()
         _lib.check(lib.sky_build(_ptr(self.x_soa), self.n, self.d, self.n, C.byref(prm),
                                  _ptr(self.build_ws), self.build_bytes, _ptr(self.status), sp,

@@ -92,6 +92,8 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     int64_t scan_n = hist_elems > n ? hist_elems : n;
     P->scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(scan_n));
     P->xa = c.take<float>((size_t)n * (size_t)partition_row_stride(d));
+    P->rep_kept = c.take<int32_t>((size_t)SKY_MAX_REPS + 1);
+    P->rep_tests = c.take<unsigned long long>(1);
     P->k0 = c.take<uint32_t>((size_t)n);
     P->v0 = c.take<uint32_t>((size_t)n);
     P->k1 = c.take<uint32_t>((size_t)n);
@@ -234,7 +236,8 @@ sky_status sky_project(const float* x_soa, int64_t n, int32_t d, int64_t ld, con
 }
 
 size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params) {
-    if (!params || n < 1 || n > kMaxBuildRows || !valid_d(d) || params->flags != 0) return 0;
+    if (!params || n < 1 || n > kMaxBuildRows || !valid_d(d) || params->reps < 0 || params->reps > SKY_MAX_REPS)
+        return 0;
     int32_t p = 1, m = 0;
     if (resolve_partitions(n, d, params, &p, &m) != SKY_OK) return 0;
     return plan_bytes(n, d, params->scheme, p, m);
@@ -245,11 +248,14 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
     if (!out) return SKY_ERR_INVALID_ARG;
     *out = nullptr;
     if (!x_soa || !params || !ws || !dev_status) return SKY_ERR_INVALID_ARG;
-    if (n < 1 || n > kMaxBuildRows || !valid_d(d) || ld < n || params->flags != 0) return SKY_ERR_INVALID_ARG;
+    if (n < 1 || n > kMaxBuildRows || !valid_d(d) || ld < n || params->reps < 0 || params->reps > SKY_MAX_REPS)
+        return SKY_ERR_INVALID_ARG;
     int32_t p = 1, m = 0;
     SKY_TRY(resolve_partitions(n, d, params, &p, &m));
-    return plan_build(x_soa, n, d, ld, params->scheme, p, m, params->slice_dim, nullptr, ws, ws_bytes,
-                      dev_status, (hipStream_t)stream, out);
+    SKY_TRY(plan_build(x_soa, n, d, ld, params->scheme, p, m, params->slice_dim, nullptr, ws, ws_bytes,
+                       dev_status, (hipStream_t)stream, out));
+    (*out)->reps = params->reps;
+    return SKY_OK;
 }
 
 sky_status sky_local_skylines(sky_plan* P, void* stream) {
@@ -285,12 +291,40 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
         free(pr);
     }
     SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
+    // Representative Filtering (Sec. 3.1): the rows the kept representatives dominate leave
+    const uint8_t* keep = nullptr;
+    if (P->reps > 0) {
+        RepArgs ra{};
+        ra.fsum = P->fsum; ra.rowid = P->rowid; ra.n = n; ra.d = P->d;
+        ra.xp = P->xp; ra.ldp = P->ldp; ra.xa = P->xa; ra.rs = partition_row_stride(P->d);
+        ra.k = P->reps;
+        ra.k0 = P->k0; ra.v0 = P->v0; ra.k1 = P->k1; ra.v1 = P->v1; ra.radix_tmp = P->radix_tmp;
+        ra.kept = P->rep_kept; ra.nkept = P->rep_kept + SKY_MAX_REPS; ra.tests = P->rep_tests;
+        ra.keep = P->member_tmp;  // free until sky_merge
+        SKY_TRY(launch_representatives(ra, st));
+        keep = P->member_tmp;
+    }
     // the rows outside the pruned Grid cells (every row when none is pruned)
     SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID && P->info.pruned_rows > 0 ? P->pruned : nullptr,
                                  P->seg, n, P->eng.w1,
-                                 P->count_tmp, P->eng.flag, P->eng.scan, P->eng.scan_tmp, st));
-    // live rows: every row outside the pruned Grid cells (exactly what the list holds)
-    const int32_t live = n - (int32_t)P->info.pruned_rows;
+                                 P->count_tmp, P->eng.flag, P->eng.scan, P->eng.scan_tmp, st, keep));
+    // live rows: every row outside the pruned Grid cells (exactly what the list holds), minus the
+    // rows the representatives removed (read back)
+    int32_t live = n - (int32_t)P->info.pruned_rows;
+    int64_t rep_tests = 0;
+    P->info.reps_kept = 0;
+    if (keep) {
+        int32_t cnt = 0, nk = 0;
+        unsigned long long rt = 0;
+        hipError_t e1 = hipMemcpyAsync(&cnt, P->count_tmp, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(&nk, P->rep_kept + SKY_MAX_REPS, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipMemcpyAsync(&rt, P->rep_tests, sizeof(rt), hipMemcpyDeviceToHost, st);
+        hipError_t e4 = hipStreamSynchronize(st);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return SKY_ERR_HIP;
+        live = cnt;
+        P->info.reps_kept = nk;
+        rep_tests = (int64_t)rt;
+    }
     EngineProblem pb{};
     pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
     pb.seg_of_pos = P->p > 1 ? P->seg : nullptr;
@@ -305,7 +339,7 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     P->info.events_used = P->ev_used;
     P->info.local_count = r.count;
     P->info.rounds_local = r.rounds;
-    P->info.tests_local = r.tests;
+    P->info.tests_local = r.tests + rep_tests;
     P->state = 2;
     P->info.state = 2;
     return SKY_OK;

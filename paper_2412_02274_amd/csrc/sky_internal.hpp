@@ -192,6 +192,20 @@ int64_t partition_hist_elems(int64_t n, int32_t p);
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st);
 
+// sky_reps.hip: Representative Filtering (Sec. 3.1)
+struct RepArgs {
+    const float* fsum; const int32_t* rowid; int32_t n; int32_t d;  // the plan's score per position
+    const float* xp; int64_t ldp;       // partition-contiguous copy
+    const float* xa; int32_t rs;        // row-major staging copy (stride rs)
+    int32_t k;                          // representatives wanted
+    uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp;  // sort scratch (n)
+    int32_t* kept;                      // [SKY_MAX_REPS] out: 1 if kept
+    int32_t* nkept;                     // out: kept count (device)
+    unsigned long long* tests;          // out: row-against-representative tests (device)
+    uint8_t* keep;                      // [n] out: 1 for positions no kept representative dominates
+};
+sky_status launch_representatives(const RepArgs& a, hipStream_t st);
+
 // sky_skyline.hip: segmented skyline engine (see the file header)
 struct EngineBuffers {
     int32_t* w0; int32_t* w1;      // work lists (capacity n)
@@ -235,7 +249,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
 // helpers used by the API layer
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
                                 int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
-                                int32_t* scan_tmp, hipStream_t st);
+                                int32_t* scan_tmp, hipStream_t st, const uint8_t* keep = nullptr);
 sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 // dst[rowid[q]] = src[q] for q < n (int32 and/or uint8 arrays)
 sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,

@@ -24,6 +24,9 @@ struct sky_plan {
     int64_t phist_cap = 0;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     float* xa = nullptr;  // row-major staging copy for the gathers into curve order
+    int32_t reps = 0;     // Representative Filtering: representatives wanted (0 = off)
+    int32_t* rep_kept = nullptr;  // [SKY_MAX_REPS] kept flags, then the kept count
+    unsigned long long* rep_tests = nullptr;  // row-against-representative tests
     int32_t* radix_tmp = nullptr;
     sky::EngineBuffers eng{};
     uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;

@@ -1212,17 +1212,17 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
 // Positions [0, n) in order, without those whose segment is skipped (stable).
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
                                 int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
-                                int32_t* scan_tmp, hipStream_t st) {
+                                int32_t* scan_tmp, hipStream_t st, const uint8_t* keep) {
     const uint32_t nb = (uint32_t)ceil_div(n > 0 ? n : 1, kBlock);
-    if (!skip_seg) {  // nothing skipped: the list is every position
+    if (!skip_seg && !keep) {  // nothing skipped: the list is every position
         hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(kBlock), 0, st, n, out, count);
         SKY_HIP(hipGetLastError());
         return SKY_OK;
     }
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, count, 1);
     if (n <= 0) { SKY_HIP(hipGetLastError()); return SKY_OK; }
-    hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, skip_seg, seg_of_pos,
-                       (const uint8_t*)nullptr, n, flag);
+    hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, skip_seg, seg_of_pos, keep, n,
+                       flag);
     SKY_HIP(hipGetLastError());
     SKY_TRY(launch_exclusive_scan(flag, scan, n, scan_tmp, st));
     hipLaunchKernelGGL(index_compact_kernel, dim3(nb), dim3(kBlock), 0, st, (const int32_t*)flag,

@@ -56,8 +56,11 @@ def test_workspace_sizes(lib):
     assert lib.sky_build_workspace_bytes(100, 17, C.byref(prm)) == 0
     bad = _lib.SkyParams(9, 64, 0, 0)
     assert lib.sky_build_workspace_bytes(100, 4, C.byref(bad)) == 0
-    flags = _lib.SkyParams(_lib.SKY_NONE, 1, 0, 7)
-    assert lib.sky_build_workspace_bytes(100, 4, C.byref(flags)) == 0
+    for reps in (-1, _lib.SKY_MAX_REPS + 1):  # Representative Filtering: 0..SKY_MAX_REPS
+        bad_reps = _lib.SkyParams(_lib.SKY_NONE, 1, 0, reps)
+        assert lib.sky_build_workspace_bytes(100, 4, C.byref(bad_reps)) == 0
+    ok_reps = _lib.SkyParams(_lib.SKY_NONE, 1, 0, _lib.SKY_MAX_REPS)
+    assert lib.sky_build_workspace_bytes(100, 4, C.byref(ok_reps)) > 0
     ang1 = _lib.SkyParams(_lib.SKY_ANGULAR, 16, 0, 0)
     assert lib.sky_build_workspace_bytes(100, 1, C.byref(ang1)) == 0  # Angular needs d >= 2
     big = _lib.SkyParams(_lib.SKY_GRID, 1 << 20, 0, 0)

@@ -342,6 +342,45 @@ def test_multi_round_segments(dev, kind, n, d, p):
     assert np.array_equal(idx, np.flatnonzero(mem))
 
 
+def _check_reps(dev, x, scheme, p, reps):
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    plan = api.build(xs, scheme, p, reps=reps)
+    plan.local_skylines()
+    part = plan.partitions().cpu().numpy()
+    loc = plan.local_members().cpu().numpy().astype(bool)
+    idx = plan.merge().cpu().numpy()
+    info = plan.info()
+    plan.close()
+    opart, near, _, skip = oracle_partition(x, scheme, p)
+    if near is not None:
+        opart = np.where(near, part, opart)  # boundary rows: the GPU's (valid) bucket
+    want = oracle.local_skylines_reps(x, opart, skip, reps)
+    _, kept = oracle.representatives(x, reps)
+    assert info["reps_kept"] == int(kept.sum())
+    assert np.array_equal(loc, want), np.flatnonzero(loc != want)[:10]
+    assert np.array_equal(idx, np.flatnonzero(oracle.skyline_sfs(x)[0]))
+    return info
+
+
+@pytest.mark.parametrize("scheme,p", [("none", 1), ("grid", 16), ("angular", 16), ("sliced", 16)])
+@pytest.mark.parametrize("kind,n,d", [("uni", 5000, 3), ("ant", 8000, 4), ("ties", 6000, 5),
+                                      ("dyadic", 3000, 2)])
+@pytest.mark.parametrize("reps", [1, 10, 100, 1000])
+def test_representative_filtering(dev, scheme, p, kind, n, d, reps):
+    """Sec. 3.1: the kept representatives' dominated rows leave every local skyline; the local
+    skylines equal the oracle's (the same representatives: smallest FP32 sums, ties in row
+    order), and the final skyline is unchanged."""
+    _check_reps(dev, _rows(kind, n, d, 8), scheme, p, reps)
+
+
+def test_representative_filtering_large(dev):
+    # more rows than one all-pairs round takes, and more representatives than one LDS chunk
+    x = _rows("ant", 200_000, 5, 9)
+    for scheme, p in (("none", 1), ("sliced", 16)):
+        info = _check_reps(dev, x, scheme, p, 1000)
+        _say("reps", scheme, info["reps_kept"], info["local_count"], info["rounds_local"])
+
+
 _C10M = {}
 
 
