@@ -237,6 +237,9 @@ def main():
         "gres_tuples_per_s": s / dt,
         "algorithmic_tests": {"skyline_sfs": counts["sfs_tests"], "gres_alg1": counts["gres_tests"]},
         "executed_skyline_tests": executed,
+        # the paper's own count of the partitioned method (Sec. 4): the heaviest partition's
+        # local-phase tests plus the final phase's
+        "paper_skyline_tests": info["tests_local_max"] + info["tests_merge"],
         "phase_ms": phases,
         "roofline": roofline,
         "roofline_kernels": roofs,

@@ -112,6 +112,10 @@ typedef struct sky_info {
     int32_t events_used;      /* timing-hook event pairs recorded (sky_plan_set_events) */
     int32_t reps_kept;        /* representatives no other representative dominates (0 when off);
                                  their tests against the rows are counted in tests_local */
+    int64_t tests_local_max;  /* the largest local-phase test count of one partition: the cost
+                                 of the parallel phase as Sec. 4 counts it (its tests plus the
+                                 final phase's, tests_merge, are the method's count);
+                                 equals tests_local when p = 1 */
 } sky_info;
 
 typedef struct sky_gres_opts {
@@ -195,6 +199,16 @@ sky_status sky_plan_partitions(const sky_plan* plan, int32_t* part, void* stream
  * sky_local_skylines.
  */
 sky_status sky_plan_local(const sky_plan* plan, uint8_t* local, void* stream);
+
+/*
+ * sky_plan_partition_tests -- inspection: tests[j] = the dominance tests sky_local_skylines
+ * evaluated for the rows of partition j (device int64[p], p as sky_plan_info reports; rows
+ * against head rows of their own partition, plus rows against the representatives when
+ * Representative Filtering is on). They sum to sky_info.tests_local and their maximum is
+ * sky_info.tests_local_max; pruned Grid cells hold 0. Sec. 4 measures the parallel phase by
+ * this maximum. SKY_ERR_STATE before sky_local_skylines.
+ */
+sky_status sky_plan_partition_tests(const sky_plan* plan, int64_t* tests, void* stream);
 
 /*
  * sky_plan_set_events -- optional timing hooks, to measure the dominance-test kernels alone.

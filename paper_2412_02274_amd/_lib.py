@@ -36,7 +36,7 @@ SKY_MAX_REPS = 1024
 # every function the header declares (checked against the header by the tests)
 EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspace_bytes",
            "sky_build", "sky_local_skylines", "sky_merge", "sky_plan_partitions", "sky_plan_local",
-           "sky_plan_set_events",
+           "sky_plan_partition_tests", "sky_plan_set_events",
            "sky_plan_info", "sky_plan_destroy",
            "gres_workspace_bytes", "gres_compute", "gres_prepare_bytes", "gres_prepare",
            "gres_search_bytes", "gres_search",
@@ -56,7 +56,8 @@ class SkyInfo(C.Structure):
                 ("rounds_merge", C.c_int32), ("state", C.c_int32), ("pruned_rows", C.c_int64),
                 ("local_count", C.c_int64), ("sky_count", C.c_int64), ("tests_local", C.c_int64),
                 ("tests_merge", C.c_int64), ("max_partition", C.c_int64),
-                ("events_used", C.c_int32), ("reps_kept", C.c_int32)]
+                ("events_used", C.c_int32), ("reps_kept", C.c_int32),
+                ("tests_local_max", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -105,6 +106,7 @@ def load():
         "sky_merge": (i32, [vp, vp, i64, vp, vp, vp]),
         "sky_plan_partitions": (i32, [vp, vp, vp]),
         "sky_plan_local": (i32, [vp, vp, vp]),
+        "sky_plan_partition_tests": (i32, [vp, vp, vp]),
         "sky_plan_set_events": (i32, [vp, vp, vp, i32]),
         "sky_plan_info": (i32, [vp, C.POINTER(SkyInfo)]),
         "sky_plan_destroy": (None, [vp]),

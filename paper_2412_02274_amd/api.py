@@ -140,6 +140,17 @@ class Plan:
                    "sky_plan_local")
         return loc
 
+    def partition_tests(self) -> torch.Tensor:
+        """Local-phase dominance tests per partition (int64[p]); their maximum is the parallel
+        phase's cost as Sec. 4 counts it."""
+        p = int(self.info()["p"])
+        out = torch.zeros(p, dtype=torch.int64, device=self.x_soa.device)
+        if p == 0:  # Sliced over no rows
+            return out
+        _lib.check(_lib.load().sky_plan_partition_tests(self._h, _ptr(out), _stream_ptr(self.stream)),
+                   "sky_plan_partition_tests")
+        return out
+
     def info(self) -> dict:
         inf = _lib.SkyInfo()
         _lib.check(_lib.load().sky_plan_info(self._h, C.byref(inf)), "sky_plan_info")
@@ -356,7 +367,10 @@ def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, sc
         remaining &= inside
         levels.append({"g": g, "sky": int(inf["sky_count"]), "exits": int(exits.sum()),
                        "p": int(inf["p"]), "tests_local": int(inf["tests_local"]),
-                       "tests_merge": int(inf["tests_merge"])})
+                       "tests_local_max": int(inf["tests_local_max"]),
+                       "tests_merge": int(inf["tests_merge"]),
+                       # Sec. 4's count: the heaviest partition plus the final phase
+                       "tests_paper": int(inf["tests_local_max"]) + int(inf["tests_merge"])})
         if not remaining.any():
             break
     return ge, levels

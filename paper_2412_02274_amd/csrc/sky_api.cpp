@@ -94,6 +94,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->xa = c.take<float>((size_t)n * (size_t)partition_row_stride(d));
     P->rep_kept = c.take<int32_t>((size_t)SKY_MAX_REPS + 1);
     P->rep_tests = c.take<unsigned long long>(1);
+    P->seg_tests = c.take<unsigned long long>((size_t)p);
     P->k0 = c.take<uint32_t>((size_t)n);
     P->v0 = c.take<uint32_t>((size_t)n);
     P->k1 = c.take<uint32_t>((size_t)n);
@@ -117,7 +118,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.dom = c.take<uint8_t>((size_t)n);
     e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
     e.counters = c.take<int32_t>(48);
-    e.tests = c.take<unsigned long long>(2);
+    e.tests = c.take<unsigned long long>(3);
     e.flag = c.take<int32_t>((size_t)n);
     e.scan = c.take<int32_t>((size_t)n);
     e.scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(n));
@@ -291,6 +292,9 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
         free(pr);
     }
     SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
+    // the local phase's tests per partition (Sec. 4 counts its cost as the largest of them)
+    SKY_TRY(launch_fill_u8(reinterpret_cast<uint8_t*>(P->seg_tests),
+                           (int64_t)P->p * (int64_t)sizeof(unsigned long long), 0, st));
     // Representative Filtering (Sec. 3.1): the rows the kept representatives dominate leave
     const uint8_t* keep = nullptr;
     if (P->reps > 0) {
@@ -300,6 +304,8 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
         ra.k = P->reps;
         ra.k0 = P->k0; ra.v0 = P->v0; ra.k1 = P->k1; ra.v1 = P->v1; ra.radix_tmp = P->radix_tmp;
         ra.kept = P->rep_kept; ra.nkept = P->rep_kept + SKY_MAX_REPS; ra.tests = P->rep_tests;
+        ra.seg_of_pos = P->p > 1 ? P->seg : nullptr; ra.seg_tests = P->seg_tests;
+        ra.skip_seg = P->scheme == SKY_GRID && P->info.pruned_rows > 0 ? P->pruned : nullptr;
         ra.keep = P->member_tmp;  // free until sky_merge
         SKY_TRY(launch_representatives(ra, st));
         keep = P->member_tmp;
@@ -329,6 +335,7 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
     pb.seg_of_pos = P->p > 1 ? P->seg : nullptr;
     pb.nseg = P->p;
+    pb.seg_tests = P->seg_tests;
     pb.items = P->eng.w1; pb.n_items = live;
     pb.flag_out = P->local_flag;
     pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
@@ -340,6 +347,7 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     P->info.local_count = r.count;
     P->info.rounds_local = r.rounds;
     P->info.tests_local = r.tests + rep_tests;
+    P->info.tests_local_max = r.tests_max;
     P->state = 2;
     P->info.state = 2;
     return SKY_OK;
@@ -394,6 +402,14 @@ sky_status sky_plan_local(const sky_plan* P, uint8_t* local, void* stream) {
     if (P->state < 2) return SKY_ERR_STATE;
     return launch_scatter_rows(nullptr, P->local_flag, P->rowid, P->n, nullptr, local,
                                (hipStream_t)stream);
+}
+
+sky_status sky_plan_partition_tests(const sky_plan* P, int64_t* tests, void* stream) {
+    if (!P || !tests) return SKY_ERR_INVALID_ARG;
+    if (P->state < 2) return SKY_ERR_STATE;
+    SKY_HIP(hipMemcpyAsync(tests, P->seg_tests, (size_t)P->p * sizeof(unsigned long long),
+                           hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return SKY_OK;
 }
 
 sky_status sky_plan_set_events(sky_plan* P, void* const* ev_begin, void* const* ev_end, int32_t cap) {

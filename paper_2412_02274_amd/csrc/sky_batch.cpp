@@ -123,6 +123,7 @@ sky_status sky_batch_skylines(sky_batch* B, int64_t* sky_idx, int64_t cap, int64
     const int64_t S = P->info.local_count;
     B->info.rounds_local = P->info.rounds_local;
     B->info.tests_local = P->info.tests_local;
+    B->info.tests_local_max = P->info.tests_local_max;  // the costliest relation
     B->info.local_count = S;
     B->info.sky_count = S;
     if (S > cap) return SKY_ERR_CAPACITY;

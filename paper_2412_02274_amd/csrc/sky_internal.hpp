@@ -202,6 +202,9 @@ struct RepArgs {
     int32_t* kept;                      // [SKY_MAX_REPS] out: 1 if kept
     int32_t* nkept;                     // out: kept count (device)
     unsigned long long* tests;          // out: row-against-representative tests (device)
+    const int32_t* seg_of_pos;          // segment of a position (nullptr = one segment)
+    unsigned long long* seg_tests;      // optional [nseg]: the same tests added per segment
+    const uint8_t* skip_seg;            // optional [nseg]: segments whose rows are not tested
     uint8_t* keep;                      // [n] out: 1 for positions no kept representative dominates
 };
 sky_status launch_representatives(const RepArgs& a, hipStream_t st);
@@ -223,7 +226,7 @@ struct EngineBuffers {
     uint8_t* dom;                  // [n] dominated flags
     int32_t* tile_off;             // [2 * (nseg + 1)] item-tile offsets for head / rest
     int32_t* counters;             // [3 * 16]: the output count, then two per-round sets
-    unsigned long long* tests;     // [2] dominance-test counters
+    unsigned long long* tests;     // [3] dominance-test counters (head, rest, per-segment max)
     int32_t* flag; int32_t* scan;  // [n] stable-compaction scratch
     int32_t* scan_tmp;             // scan scratch for n values
 };
@@ -234,6 +237,7 @@ struct EngineProblem {
     const float* fsum;             // score per position
     const int32_t* seg_of_pos;     // segment of a position (nullptr = single segment)
     int32_t nseg;
+    unsigned long long* seg_tests; // optional [nseg]: tests added per segment (the caller zeroes)
     const int32_t* items; int32_t n_items;  // initial work list (positions)
     uint8_t* flag_out;             // [n_pos] set to 1 for skyline items (must be zeroed)
     void* const* ev_begin;         // optional timing events around the test launches
@@ -243,7 +247,8 @@ struct EngineProblem {
     int32_t* host_scratch;         // optional pinned host memory (2 x 16 int32): with it and the
     void* round_events[2];         // two events, rounds are launched one ahead of the readback
 };
-struct EngineResult { int32_t count; int32_t rounds; int64_t tests; };
+// tests_max: the largest per-segment count in seg_tests after the run (tests when there is none)
+struct EngineResult { int32_t count; int32_t rounds; int64_t tests; int64_t tests_max; };
 sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,
                       EngineResult* res, hipStream_t st);
 // helpers used by the API layer

@@ -27,6 +27,7 @@ struct sky_plan {
     int32_t reps = 0;     // Representative Filtering: representatives wanted (0 = off)
     int32_t* rep_kept = nullptr;  // [SKY_MAX_REPS] kept flags, then the kept count
     unsigned long long* rep_tests = nullptr;  // row-against-representative tests
+    unsigned long long* seg_tests = nullptr;  // [p] local-phase tests per partition
     int32_t* radix_tmp = nullptr;
     sky::EngineBuffers eng{};
     uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;

@@ -78,19 +78,26 @@ __global__ void __launch_bounds__(kBlock) rep_skyline_kernel(const float* __rest
 }
 
 // keep[p] = 1 for positions no kept representative dominates (0 for the others); tests holds
-// the row-against-representative tests made (each row stops at its first dominator)
+// the row-against-representative tests made (each row stops at its first dominator), and
+// seg_tests (when given) the same tests per segment of the rows. Rows of skipped segments
+// (pruned Grid cells, which the local phase disregards) are not tested.
 __global__ void __launch_bounds__(kBlock) rep_filter_kernel(const float* __restrict__ xp, int64_t ldp,
                                                             int32_t d, int32_t n,
                                                             const float* __restrict__ xa, int32_t rs,
                                                             const uint32_t* __restrict__ rows,
                                                             const int32_t* __restrict__ kept, int32_t k,
                                                             uint8_t* __restrict__ keep,
-                                                            unsigned long long* __restrict__ tests) {
+                                                            unsigned long long* __restrict__ tests,
+                                                            const int32_t* __restrict__ seg_of_pos,
+                                                            unsigned long long* __restrict__ seg_tests,
+                                                            const uint8_t* __restrict__ skip_seg) {
     __shared__ float cv[kRepChunk * SKY_MAX_D];
     __shared__ int32_t cok[kRepChunk];
     const int32_t p = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t sg = (seg_of_pos && p < n) ? seg_of_pos[p] : 0;
+    const bool act = p < n && !(skip_seg && skip_seg[sg]);
     float t[SKY_MAX_D];
-    if (p < n)
+    if (act)
         for (int a = 0; a < d; ++a) t[a] = xp[(int64_t)a * ldp + p];
     bool dom = false;
     unsigned long long nt = 0;
@@ -103,7 +110,7 @@ __global__ void __launch_bounds__(kBlock) rep_filter_kernel(const float* __restr
         }
         for (int32_t q = threadIdx.x; q < cn; q += kBlock) cok[q] = kept[c0 + q];
         __syncthreads();
-        if (p < n && !dom)
+        if (act && !dom)
             for (int32_t q = 0; q < cn && !dom; ++q)
                 if (cok[q]) {
                     ++nt;
@@ -111,8 +118,16 @@ __global__ void __launch_bounds__(kBlock) rep_filter_kernel(const float* __restr
                 }
     }
     if (p < n) keep[p] = dom ? 0 : 1;
+    // per segment: one add per wave when its rows share a segment (segments are runs of
+    // positions, so nearly every wave does), else one per lane
+    const int32_t s0 = __shfl(sg, 0);
+    const bool mixed = __builtin_amdgcn_ballot_w64(p < n && sg != s0) != 0;
+    if (seg_tests && mixed && nt) atomicAdd(&seg_tests[sg], nt);
     for (int off = kWave / 2; off > 0; off >>= 1) nt += __shfl_xor(nt, off);
-    if (lane_id() == 0 && nt) atomicAdd(tests, nt);
+    if (lane_id() == 0 && nt) {
+        atomicAdd(tests, nt);
+        if (seg_tests && !mixed) atomicAdd(&seg_tests[s0], nt);
+    }
 }
 
 }  // namespace
@@ -129,7 +144,8 @@ sky_status launch_representatives(const RepArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(rep_skyline_kernel, dim3((uint32_t)ceil_div(k, kBlock)), dim3(kBlock), 0, st, a.xa,
                        a.rs, a.d, sorted_rows, k, a.kept, a.nkept);
     hipLaunchKernelGGL(rep_filter_kernel, dim3(nb), dim3(kBlock), 0, st, a.xp, a.ldp, a.d, a.n, a.xa, a.rs,
-                       sorted_rows, (const int32_t*)a.kept, k, a.keep, a.tests);
+                       sorted_rows, (const int32_t*)a.kept, k, a.keep, a.tests,
+                       a.seg_of_pos, a.seg_tests, a.skip_seg);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

@@ -720,7 +720,8 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     const int32_t* __restrict__ rhb, const uint32_t* __restrict__ hval, int64_t hcap,
     const uint32_t* __restrict__ hlo,
     const uint32_t* __restrict__ hhi, int64_t tcap, const int32_t* __restrict__ round_counters,
-    uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests) {
+    uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests,
+    unsigned long long* __restrict__ seg_tests) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     __shared__ uint32_t box[kBoxLds];  // [2][k][ntile] tile boxes (lo, hi) of the current segment
     __shared__ int32_t itemc[kBlock / kWave][kWave][DM];  // each wave's passing items, compacted
@@ -732,6 +733,9 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     const int32_t nunits = nunits_h + unit_off_all[(nseg + 1) + nseg];
     int32_t cached = -1;  // segment whose boxes are in LDS (uniform per workgroup)
     unsigned long long ntests_h = 0, ntests_r = 0;
+    // the wave's tests of the segment it worked on last, added to seg_tests when it moves on
+    int32_t acc_seg = -1;
+    unsigned long long acc = 0;
     for (int32_t ug = blockIdx.x; ug < nunits; ug += gridDim.x) {
         // head units first (few items, latency-bound), then rest units
         const int mode = ug < nunits_h ? 0 : 1;
@@ -897,9 +901,18 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
         }
         if ((((born & ~live & ~written) >> lane) & 1ull) != 0) dom[mypos] = 1;
         if (mode == 0) ntests_h += ntests; else ntests_r += ntests;
+        if (seg_tests) {
+            if (s != acc_seg) {
+                if (lane == 0 && acc) atomicAdd(&seg_tests[acc_seg], acc);
+                acc_seg = s;
+                acc = 0;
+            }
+            acc += ntests;
+        }
     }
     if (lane == 0 && ntests_h) atomicAdd(&tests[0], ntests_h);
     if (lane == 0 && ntests_r) atomicAdd(&tests[1], ntests_r);
+    if (seg_tests && lane == 0 && acc) atomicAdd(&seg_tests[acc_seg], acc);
 }
 
 
@@ -922,6 +935,24 @@ __global__ void zero_i32_kernel(int32_t* __restrict__ p, int32_t n) {
 __global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int32_t n) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
+}
+
+// *out = max(v[0 .. n)), 0 when n == 0 (one workgroup)
+__global__ void __launch_bounds__(kBlock) max_u64_kernel(const unsigned long long* __restrict__ v,
+                                                          int32_t n, unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long part[kBlock / kWave];
+    unsigned long long m = 0;
+    for (int32_t i = threadIdx.x; i < n; i += kBlock) m = v[i] > m ? v[i] : m;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(m, off);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0) part[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) m = part[w] > m ? part[w] : m;
+        *out = m;
+    }
 }
 
 // positions [0, n) whose segment is not skipped
@@ -1036,13 +1067,14 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
     res->count = 0;
     res->rounds = 0;
     res->tests = 0;
+    res->tests_max = 0;
     const int32_t nseg = pb.nseg;
     // counters: [0, kCounters) hold the output count; two per-round sets alternate after it, so
     // a round launched ahead never overwrites the counters of the round being read back
     int32_t* const out_count = b.counters + C_OUT;
     auto round_counters = [&](int32_t r) { return b.counters + kCounters * (1 + (r & 1)); };
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, b.counters, (int32_t)(3 * kCounters));
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, b.tests, 2);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, b.tests, 3);
     hipLaunchKernelGGL(pad_slots_kernel, dim3((uint32_t)ceil_div(pb.d * kTile, 256)), dim3(256), 0, st,
                        b.hval, b.hcap, pb.d);
     SKY_HIP(hipGetLastError());
@@ -1118,7 +1150,8 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                        dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
                        (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.rest,
                        (const int32_t*)b.rhb, (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo,
-                       (const uint32_t*)b.hhi, b.tcap, (const int32_t*)cnt, b.dom, b.tests);
+                       (const uint32_t*)b.hhi, b.tcap, (const int32_t*)cnt, b.dom, b.tests,
+                       pb.seg_tests);
         SKY_HIP(ev_rec(false));
         // the survivors of the rest groups, in order, are the next round's work list
         // (and the head survivors into the output, in extra blocks of the same launch)
@@ -1199,13 +1232,19 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
             ub_next = nl;
         }
     }
+    if (pb.seg_tests) {
+        hipLaunchKernelGGL(max_u64_kernel, dim3(1), dim3(kBlock), 0, st,
+                           (const unsigned long long*)pb.seg_tests, nseg, b.tests + 2);
+        SKY_HIP(hipGetLastError());
+    }
     int32_t outc = 0;
-    unsigned long long tests[2] = {0, 0};
+    unsigned long long tests[3] = {0, 0, 0};
     SKY_HIP(hipMemcpyAsync(&outc, out_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SKY_HIP(hipMemcpyAsync(tests, b.tests, sizeof(tests), hipMemcpyDeviceToHost, st));
     SKY_HIP(hipStreamSynchronize(st));
     res->count = outc;
     res->tests = (int64_t)(tests[0] + tests[1]);
+    res->tests_max = pb.seg_tests ? (int64_t)tests[2] : res->tests;
     return SKY_OK;
 }
 

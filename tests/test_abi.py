@@ -41,6 +41,32 @@ def test_header_declarations_exported(lib):
         assert hasattr(lib, name)
 
 
+def test_struct_layouts_match_header(tmp_path):
+    # the ctypes mirrors of the header's structs: size and every field's offset, as a C
+    # compiler lays them out from include/sky.h
+    structs = {"sky_params": _lib.SkyParams, "sky_info": _lib.SkyInfo,
+               "sky_gres_opts": _lib.GresOpts, "sky_tune": _lib.SkyTune}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "sky.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
 def test_status_strings(lib):
     for code in range(8):
         s = lib.sky_status_string(code).decode()
@@ -90,6 +116,7 @@ def test_argument_errors_return_synchronously(lib):
     assert lib.sky_plan_info(None, None) == E
     assert lib.sky_plan_partitions(None, fake, None) == E
     assert lib.sky_plan_local(None, fake, None) == E
+    assert lib.sky_plan_partition_tests(None, fake, None) == E
     lib.sky_plan_destroy(None)
     assert lib.sky_ingest(fake, -1, 2, fake, 10, fake, None) == E
     assert lib.sky_ingest(fake, 10, 2, fake, 9, fake, None) == E

@@ -63,6 +63,12 @@ def test_literal_equals_per_tuple(dev, scheme, kind, n, d, g_max):
     assert np.array_equal(ge_lit, want)
     # every candidate exits at most once, and the counts add up
     assert sum(lv["exits"] for lv in levels) == int((ge_lit > 1).sum())
+    # the paper's count per level: the heaviest partition plus the final phase
+    for lv in levels:
+        assert lv["tests_local_max"] <= lv["tests_local"]
+        assert lv["tests_paper"] == lv["tests_local_max"] + lv["tests_merge"]
+        if scheme == "none":
+            assert lv["tests_local_max"] == lv["tests_local"]
 
 
 def test_literal_anticorrelated_partitioned(dev):
@@ -77,3 +83,5 @@ def test_literal_anticorrelated_partitioned(dev):
         ge_lit, levels = api.gres_literal(xs, sky, 25, scheme=scheme, target_p=64)
         assert np.array_equal(ge_lit, ge.cpu().numpy()), scheme
         assert all(lv["p"] > 1 for lv in levels)
+        # partitioning spreads the local phase: its heaviest partition holds a part of it
+        assert all(lv["tests_local_max"] < lv["tests_local"] for lv in levels), scheme

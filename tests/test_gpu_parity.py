@@ -46,8 +46,10 @@ def run_skyline(dev, x, scheme="none", p=16, slice_dim=0):
     plan.local_skylines()
     part = plan.partitions().cpu().numpy()
     loc = plan.local_members().cpu().numpy().astype(bool)
-    idx = plan.merge().cpu().numpy()
     info = plan.info()
+    info["partition_tests"] = plan.partition_tests().cpu().numpy()
+    idx = plan.merge().cpu().numpy()
+    info.update({k: v for k, v in plan.info().items() if k != "partition_tests"})
     plan.close()
     return xs, idx, part, loc, info
 
@@ -70,9 +72,29 @@ def oracle_partition(x, scheme, p, slice_dim=0):
     return oracle.sliced_part(x, pp, slice_dim), None, pp, None
 
 
+def check_partition_tests(info, part, pp, skip, reps_kept=0):
+    """The local phase's per-partition test counts (Sec. 4 counts the parallel phase by their
+    maximum): they add up to tests_local, their maximum is tests_local_max, a partition without
+    live rows has none, one with two or more has some, and no partition exceeds one test per
+    (row, row of the partition) pair plus one per (row, kept representative) pair. Counts
+    depend on the order of the work, so they are checked by these properties only."""
+    pt = np.asarray(info["partition_tests"], np.int64)
+    assert len(pt) == pp
+    assert int(pt.sum()) == info["tests_local"]
+    assert int(pt.max(initial=0)) == info["tests_local_max"]
+    live = np.bincount(part, minlength=pp).astype(np.int64)
+    if skip is not None:
+        live[skip.astype(bool)] = 0
+    assert (pt[live == 0] == 0).all()
+    if reps_kept == 0:
+        assert (pt[live >= 2] > 0).all()
+    assert (pt <= live * live + live * reps_kept).all(), np.flatnonzero(pt > live * live + live * reps_kept)
+
+
 def check_partitioned(x, scheme, p, part, loc, info, slice_dim=0):
     opart, near, pp, skip = oracle_partition(x, scheme, p, slice_dim)
     assert info["p"] == pp
+    check_partition_tests(info, part, pp, skip)
     if near is None:
         assert (part == opart).all()
     else:
@@ -113,9 +135,11 @@ def test_skyline_none(dev, kind, d, n):
     _say("skyline none", kind, d, n)
     x = _rows(kind, n, d, 3 * d + n)
     want = np.flatnonzero(oracle.skyline(x))
-    _, idx, _, loc, info = run_skyline(dev, x, "none")
+    _, idx, part, loc, info = run_skyline(dev, x, "none")
     assert (idx == want).all() and len(idx) == len(want)
     assert info["sky_count"] == len(want)
+    check_partition_tests(info, part, 1, None)
+    assert info["tests_local_max"] == info["tests_local"]
 
 
 @pytest.mark.parametrize("scheme,p", [("grid", 16), ("grid", 64), ("angular", 16),
@@ -348,10 +372,13 @@ def _check_reps(dev, x, scheme, p, reps):
     plan.local_skylines()
     part = plan.partitions().cpu().numpy()
     loc = plan.local_members().cpu().numpy().astype(bool)
+    ptests = plan.partition_tests().cpu().numpy()
     idx = plan.merge().cpu().numpy()
     info = plan.info()
+    info["partition_tests"] = ptests
     plan.close()
-    opart, near, _, skip = oracle_partition(x, scheme, p)
+    opart, near, pp, skip = oracle_partition(x, scheme, p)
+    check_partition_tests(info, part, pp, skip, info["reps_kept"])
     if near is not None:
         opart = np.where(near, part, opart)  # boundary rows: the GPU's (valid) bucket
     want = oracle.local_skylines_reps(x, opart, skip, reps)
