@@ -336,13 +336,14 @@ def project(x_soa: torch.Tensor, rows: torch.Tensor, g: int, out: torch.Tensor |
 
 
 def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, scheme="none",
-                 target_p: int = 16, slice_dim: int = 0):
+                 target_p: int = 16, slice_dim: int = 0, reps: int = 0):
     """Alg. 1 as written: for g = g_max .. 2, the skyline of the grid projection of the candidate
     set (Sky(r)) is computed through the two-phase partitioned scheme (build, local skylines,
     merge on the projected relation); every candidate not in it that has no value yet gets
     g_exit = g. Returns (g_exit int32[s] on the host, per-level statistics). Equal to
     ``gres()`` for every input (gres is stable and dominance between projections is the per-tuple
-    test); kept to run the paper's own formulation and count its work."""
+    test); kept to run the paper's own formulation and count its work. reps > 0 applies
+    Representative Filtering (Sec. 3.1) inside every level's skyline."""
     import numpy as np
     s = int(sky_idx.numel())
     d = x_soa.shape[0]
@@ -355,7 +356,7 @@ def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, sc
     levels = []
     for g in range(int(g_max), 1, -1):
         project(x_soa, sky_idx, g, out=proj, status=status)
-        plan = build(proj, scheme, target_p, slice_dim, status=status)
+        plan = build(proj, scheme, target_p, slice_dim, status=status, reps=reps)
         plan.local_skylines()
         _, member = plan.merge(member=True)
         inf = plan.info()

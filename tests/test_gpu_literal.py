@@ -85,3 +85,21 @@ def test_literal_anticorrelated_partitioned(dev):
         assert all(lv["p"] > 1 for lv in levels)
         # partitioning spreads the local phase: its heaviest partition holds a part of it
         assert all(lv["tests_local_max"] < lv["tests_local"] for lv in levels), scheme
+
+
+def test_experiment_point_counts(dev):
+    # one point of the Sec. 4 sweeps: the same skyline and exits under every scheme, and the
+    # paper's counts (heaviest partition + final phase) add up from the per-level records
+    from paper_2412_02274_amd import experiments
+    x = G.ant(30000, 3, 4)
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    rows = {s: experiments.point(xs, 16, 0, s) for s in experiments.SCHEMES}
+    base = rows["none"]
+    assert base["p"] == 1 and base["gres_levels"] >= 1 and base["gres_local_max"] > 0
+    for s, r in rows.items():
+        assert r["sky"] == base["sky"] and r["exits"] == base["exits"], s
+        if s != "none":
+            assert r["p"] > 1
+            assert r["sky_local_max"] < base["sky_local_max"], s
+    r = experiments.point(xs, 16, 10, "sliced")  # with representatives
+    assert r["sky"] == base["sky"] and r["exits"] == base["exits"]
