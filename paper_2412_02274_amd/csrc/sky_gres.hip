@@ -41,6 +41,8 @@
 // and stays in L2).
 #include "sky_internal.hpp"
 
+#include <atomic>
+
 namespace sky {
 
 namespace {
@@ -56,6 +58,8 @@ constexpr int kMaxBands = 8;
 constexpr int kStartLevels = 64;         // above this g_max, searches start at per-target bounds
 constexpr int kLevelWaves = 4096;        // LEVELS: waves wanted in flight (targets x bands)
 constexpr int kMaxLevelBands = 16;
+constexpr int kWorkCounters = 32;        // TILES work counters (measured: 8 and 128 were slower)
+constexpr int kCounterStride = 32;       // int32 per counter: one 128-byte line each
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -349,7 +353,14 @@ __device__ __forceinline__ WgWork wg_work(const int32_t* wg_table, int32_t per_w
 }
 
 template <int D>
-// 8 waves per SIMD: the search waits on cache round trips, so more waves in flight pay
+// 8 waves per SIMD: the search waits on cache round trips, so more waves in flight pay.
+// Two ways to hand out the work, (target, band) pairs in band-major order (every target's
+// highest band first):
+//  * work == nullptr: workgroup b searches band b / nblk of the targets of wg_table entry
+//    b % nblk (or of the contiguous range b % nblk * per_wg ...), one target per wave at a time;
+//  * work != nullptr (one segment): the grid is what the device holds at once, and every wave
+//    takes the next pair from the counter *work (zero at launch) until none is left, so a
+//    workgroup's tile boxes are loaded once and no wave waits for a slow one to free its slot.
 __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu(8))) gres_tiles_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
     const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
@@ -357,18 +368,21 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
     const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
     int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests, int32_t nblk,
-    int32_t band_len, const int32_t* __restrict__ gstart) {
+    int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
+    int32_t* __restrict__ work) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     unsigned long long ntests = 0;   // candidate tests (target against candidate at one level)
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
-    const int wave = threadIdx.x / kWave;
-    // blocks are band-major: every target's highest band first
-    const int32_t band = blockIdx.x / nblk;
-    const int32_t nbands = (int32_t)(gridDim.x / (uint32_t)nblk);
-    const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x - band * nblk);
-    if (w.t0 >= w.t1) return;  // uniform
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+    int32_t band0 = 0;
+    WgWork w{0, 0, nt};
+    if (!work) {
+        band0 = blockIdx.x / nblk;
+        w = wg_work(wg_table, per_wg, nt, blockIdx.x - band0 * nblk);
+        if (w.t0 >= w.t1) return;  // uniform
+    }
     const uint32_t coff = (uint32_t)seg_coff[w.seg];
     const int32_t cnt = seg_cnt[w.seg];
     const int32_t ntile = (cnt + kTileC - 1) / kTileC;
@@ -395,7 +409,8 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         }
         __syncthreads();
     }
-    for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) {
+    // the level scan of target q over the levels of band `band`
+    auto search = [&](const int32_t q, const int32_t band) {
         float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
@@ -514,6 +529,26 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         }
         // ge_out starts at 1 (no exit); each band raises it to its highest exit level
         if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
+    };
+    if (work) {
+        const int32_t total = nt * nbands;  // below 2^30 (checked at launch): no counter overflow
+        // kWorkCounters counters, 128 bytes apart, so that no single address takes every
+        // atomic: workgroup b draws from counter b % nctr, which hands out the pairs
+        // x, x + nctr, x + 2 nctr, ... (every pair belongs to exactly one counter, and every
+        // counter has workgroups when the grid holds at least nctr of them)
+        const int32_t nctr = gridDim.x >= (uint32_t)kWorkCounters ? kWorkCounters : 1;
+        const int32_t x = (int32_t)(blockIdx.x % (uint32_t)nctr);
+        for (;;) {
+            int32_t k = 0;
+            if (lane == 0) k = atomicAdd(work + kCounterStride * x, 1);
+            k = __builtin_amdgcn_readfirstlane(k);
+            const int32_t item = x + nctr * k;
+            if (item >= total) break;  // every wave ends here once its counter passes the total
+            const int32_t b = item / nt;
+            search(item - b * nt, b);
+        }
+    } else {
+        for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) search(q, band0);
     }
     if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
 }
@@ -550,7 +585,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x);
     if (w.t0 >= w.t1) return;
     const int64_t coff = seg_coff[w.seg];
@@ -624,7 +659,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
     (void)lds_floats;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
-    const int wave = threadIdx.x / kWave;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     // blocks are band-major: every target's highest band first
     const int32_t band = blockIdx.x / nblk;
     const int32_t nbands = (int32_t)(gridDim.x / (uint32_t)nblk);
@@ -788,6 +823,7 @@ void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d) {
     t.tout = c.take<int32_t>((size_t)t.tvcap);
     t.ge = c.take<int32_t>((size_t)t.tvcap);
     t.gstart = c.take<int32_t>((size_t)t.tvcap);
+    t.work = c.take<int32_t>((size_t)kWorkCounters * kCounterStride);
 }
 
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -905,6 +941,26 @@ sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int
     return SKY_OK;
 }
 
+// Workgroups of the search kernels the current device holds at once: 32 waves per compute unit
+// (8 per SIMD), and the LDS of a compute unit shared by the workgroups' tile boxes.
+sky_status resident_workgroups(size_t lds, int32_t* out) {
+    static std::atomic<int32_t> cache[64][2] = {};  // per device: compute units, LDS bytes per CU
+    int dev = 0;
+    SKY_HIP(hipGetDevice(&dev));
+    int32_t cus = dev >= 0 && dev < 64 ? cache[dev][0].load() : 0;
+    int32_t lds_cu = dev >= 0 && dev < 64 ? cache[dev][1].load() : 0;
+    if (cus <= 0 || lds_cu <= 0) {
+        SKY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        SKY_HIP(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+        if (dev >= 0 && dev < 64) { cache[dev][0].store(cus); cache[dev][1].store(lds_cu); }
+    }
+    int32_t per_cu = 32 / kWaves;
+    if (lds > 0 && (int64_t)lds_cu / (int64_t)lds < per_cu) per_cu = (int32_t)((int64_t)lds_cu / (int64_t)lds);
+    if (per_cu < 1) per_cu = 1;
+    *out = (cus > 0 ? cus : 1) * per_cu;
+    return SKY_OK;
+}
+
 int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
     // measured (both mappings with per-target start levels): lanes over 64 levels pay off when
     // many levels lie below the start levels (g_max >= 2^17) or on small skylines with
@@ -959,6 +1015,20 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     hipLaunchKernelGGL(fill_i32_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, tg.ge,
                        nt, 1);
     SKY_HIP(hipGetLastError());
+    // TILES on one segment: as many workgroups as the device holds at once, fed from a counter
+    uint32_t grid = blocks * (uint32_t)nbands;
+    int32_t* work = nullptr;
+    if (mapping != SKY_GRES_LEVELS && !wg_table && (int64_t)nt * nbands < ((int64_t)1 << 30)) {
+        int32_t resident = 0;
+        SKY_TRY(resident_workgroups(lds, &resident));
+        if ((int64_t)grid > resident) {
+            grid = (uint32_t)resident;
+            work = tg.work;
+            hipLaunchKernelGGL(fill_i32_kernel, dim3(kWorkCounters * kCounterStride / kBlock), dim3(kBlock), 0,
+                               st, work, kWorkCounters * kCounterStride, 0);
+            SKY_HIP(hipGetLastError());
+        }
+    }
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (mapping == SKY_GRES_LEVELS) {
         // few targets: split each target's levels over several waves so the chip fills
@@ -973,12 +1043,12 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                        (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
                        dev_tests, gstart, (int32_t)blocks);
     } else {
-        SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(blocks * (uint32_t)nbands), dim3(kGresBlock), lds, st,
+        SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(grid), dim3(kGresBlock), lds, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests, (int32_t)blocks, band_len, gstart);
+                       dev_tests, (int32_t)blocks, band_len, gstart, nbands, work);
     }
     SKY_HIP(hipGetLastError());
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

@@ -284,6 +284,7 @@ struct GresTargets {
     int32_t* tout;                 // [tvcap] output index of each target (-1: none)
     int32_t* ge;                   // [tvcap] result per target
     int32_t* gstart;               // [tvcap] highest level worth searching per target
+    int32_t* work;                 // work counters of the search (zeroed before each launch)
 };
 void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg);
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);
