@@ -119,6 +119,7 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
     e.counters = c.take<int32_t>(48);
     e.tests = c.take<unsigned long long>(3);
+    e.work = c.take<int32_t>((size_t)kWorkCounters * kCounterStride);
     e.flag = c.take<int32_t>((size_t)n);
     e.scan = c.take<int32_t>((size_t)n);
     e.scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(n));

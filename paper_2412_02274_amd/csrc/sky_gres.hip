@@ -41,8 +41,6 @@
 // and stays in L2).
 #include "sky_internal.hpp"
 
-#include <atomic>
-
 namespace sky {
 
 namespace {
@@ -58,8 +56,6 @@ constexpr int kMaxBands = 8;
 constexpr int kStartLevels = 64;         // above this g_max, searches start at per-target bounds
 constexpr int kLevelWaves = 4096;        // LEVELS: waves wanted in flight (targets x bands)
 constexpr int kMaxLevelBands = 16;
-constexpr int kWorkCounters = 32;        // TILES work counters (measured: 8 and 128 were slower)
-constexpr int kCounterStride = 32;       // int32 per counter: one 128-byte line each
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -941,23 +937,12 @@ sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int
     return SKY_OK;
 }
 
-// Workgroups of the search kernels the current device holds at once: 32 waves per compute unit
-// (8 per SIMD), and the LDS of a compute unit shared by the workgroups' tile boxes.
-sky_status resident_workgroups(size_t lds, int32_t* out) {
-    static std::atomic<int32_t> cache[64][2] = {};  // per device: compute units, LDS bytes per CU
-    int dev = 0;
+sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds, int32_t* out) {
+    int dev = 0, cus = 0, per_cu = 0;
     SKY_HIP(hipGetDevice(&dev));
-    int32_t cus = dev >= 0 && dev < 64 ? cache[dev][0].load() : 0;
-    int32_t lds_cu = dev >= 0 && dev < 64 ? cache[dev][1].load() : 0;
-    if (cus <= 0 || lds_cu <= 0) {
-        SKY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        SKY_HIP(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
-        if (dev >= 0 && dev < 64) { cache[dev][0].store(cus); cache[dev][1].store(lds_cu); }
-    }
-    int32_t per_cu = 32 / kWaves;
-    if (lds > 0 && (int64_t)lds_cu / (int64_t)lds < per_cu) per_cu = (int32_t)((int64_t)lds_cu / (int64_t)lds);
-    if (per_cu < 1) per_cu = 1;
-    *out = (cus > 0 ? cus : 1) * per_cu;
+    SKY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    SKY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, dyn_lds));
+    *out = (cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
     return SKY_OK;
 }
 
@@ -1019,8 +1004,10 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     uint32_t grid = blocks * (uint32_t)nbands;
     int32_t* work = nullptr;
     if (mapping != SKY_GRES_LEVELS && !wg_table && (int64_t)nt * nbands < ((int64_t)1 << 30)) {
+        const void* fn = nullptr;
+        SKY_KERNEL_PTR_D(d, gres_tiles_kernel, fn);
         int32_t resident = 0;
-        SKY_TRY(resident_workgroups(lds, &resident));
+        SKY_TRY(resident_workgroups(fn, kGresBlock, lds, &resident));
         if ((int64_t)grid > resident) {
             grid = (uint32_t)resident;
             work = tg.work;

@@ -209,6 +209,28 @@ struct RepArgs {
 };
 sky_status launch_representatives(const RepArgs& a, hipStream_t st);
 
+// Persistent launches: workgroups draw work from kWorkCounters counters kCounterStride int32
+// apart (one 128-byte line each), so that no single address takes every atomic (measured on
+// the gres search: 8 and 128 counters were slower than 32).
+constexpr int kWorkCounters = 32;
+constexpr int kCounterStride = 32;
+// Workgroups of `kernel` (block threads, dyn_lds bytes of dynamic LDS) that the current device
+// holds at once, from the runtime's occupancy calculation.
+sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds, int32_t* out);
+// fn = the instantiation of a kernel template over the attribute count d (0: any d)
+#define SKY_KERNEL_PTR_D(d, KERNEL, fn)                                   \
+    switch (d) {                                                          \
+        case 1: fn = reinterpret_cast<const void*>(&KERNEL<1>); break;    \
+        case 2: fn = reinterpret_cast<const void*>(&KERNEL<2>); break;    \
+        case 3: fn = reinterpret_cast<const void*>(&KERNEL<3>); break;    \
+        case 4: fn = reinterpret_cast<const void*>(&KERNEL<4>); break;    \
+        case 5: fn = reinterpret_cast<const void*>(&KERNEL<5>); break;    \
+        case 6: fn = reinterpret_cast<const void*>(&KERNEL<6>); break;    \
+        case 7: fn = reinterpret_cast<const void*>(&KERNEL<7>); break;    \
+        case 8: fn = reinterpret_cast<const void*>(&KERNEL<8>); break;    \
+        default: fn = reinterpret_cast<const void*>(&KERNEL<0>); break;   \
+    }
+
 // sky_skyline.hip: segmented skyline engine (see the file header)
 struct EngineBuffers {
     int32_t* w0; int32_t* w1;      // work lists (capacity n)
@@ -227,6 +249,7 @@ struct EngineBuffers {
     int32_t* tile_off;             // [2 * (nseg + 1)] item-tile offsets for head / rest
     int32_t* counters;             // [3 * 16]: the output count, then two per-round sets
     unsigned long long* tests;     // [3] dominance-test counters (head, rest, per-segment max)
+    int32_t* work;                 // [kWorkCounters * kCounterStride] work counters of the test launch
     int32_t* flag; int32_t* scan;  // [n] stable-compaction scratch
     int32_t* scan_tmp;             // scan scratch for n values
 };

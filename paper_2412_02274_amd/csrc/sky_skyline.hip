@@ -721,12 +721,13 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     const uint32_t* __restrict__ hlo,
     const uint32_t* __restrict__ hhi, int64_t tcap, const int32_t* __restrict__ round_counters,
     uint8_t* __restrict__ dom, unsigned long long* __restrict__ tests,
-    unsigned long long* __restrict__ seg_tests) {
+    unsigned long long* __restrict__ seg_tests, int32_t* __restrict__ work) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     __shared__ uint32_t box[kBoxLds];  // [2][k][ntile] tile boxes (lo, hi) of the current segment
     __shared__ int32_t itemc[kBlock / kWave][kWave][DM];  // each wave's passing items, compacted
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
+    // (left as a vector value: marking it uniform made the partitioned launches slower)
     const int wave = threadIdx.x / kWave;
     const int32_t tpu_h = round_counters[C_TPUH], tpu_r = round_counters[C_TPUR];
     const int32_t nunits_h = unit_off_all[nseg];
@@ -736,7 +737,8 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
     // the wave's tests of the segment it worked on last, added to seg_tests when it moves on
     int32_t acc_seg = -1;
     unsigned long long acc = 0;
-    for (int32_t ug = blockIdx.x; ug < nunits; ug += gridDim.x) {
+    // one wave's share of unit ug: its items part * 64 .. part * 64 + 63 of the unit's group
+    auto unit = [&](const int32_t ug, const int32_t part) {
         // head units first (few items, latency-bound), then rest units
         const int mode = ug < nunits_h ? 0 : 1;
         const int32_t u = mode == 0 ? ug : ug - nunits_h;
@@ -752,7 +754,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
         const int32_t t0 = hoff / kTile;
         const int32_t nb = ntile * d;
         const bool in_lds = 2 * nb <= kBoxLds;
-        if (in_lds && s != cached) {
+        if (!work && in_lds && s != cached) {  // (with work, the one segment's boxes are loaded)
             __syncthreads();  // every wave is done with the previous boxes
             for (int32_t e = threadIdx.x; e < nb; e += kBlock) {
                 const int32_t k = e / ntile, tl = e - k * ntile;
@@ -769,7 +771,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
         const int32_t span = ntile - c0 < tpu ? ntile - c0 : tpu;
         const int32_t ioff = mode == 0 ? hoff : si[SI_RESTOFF];
         const int32_t icnt = mode == 0 ? hn : si[SI_RESTN];
-        const int32_t ibase = grp * kBlock + wave * kWave;
+        const int32_t ibase = grp * kBlock + part * kWave;
         const bool have = ibase + lane < icnt;
         const uint32_t myidx = (uint32_t)(ioff + ibase + (have ? lane : 0));
         const int32_t mypos = have ? items_all[myidx] : 0;
@@ -909,6 +911,37 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
             }
             acc += ntests;
         }
+    };
+    if (work) {
+        // one segment, persistent workgroups: its tile boxes are loaded once, then every wave
+        // takes (unit, part) pairs from the striped counters until its counter passes the total
+        // (no barrier after the load, so waves that run out of work simply end)
+        const int32_t* si = info;
+        const int32_t ntile = (si[SI_HEADN] + kTile - 1) / kTile;
+        const int32_t t0 = si[SI_HEADOFF] / kTile;
+        const int32_t nb = ntile * d;
+        if (2 * nb <= kBoxLds) {
+            for (int32_t e = threadIdx.x; e < nb; e += kBlock) {
+                const int32_t k = e / ntile, tl = e - k * ntile;
+                box[e] = hlo[(int64_t)k * tcap + t0 + tl];
+                box[nb + e] = hhi[(int64_t)k * tcap + t0 + tl];
+            }
+        }
+        __syncthreads();
+        cached = 0;
+        const int32_t total = nunits * (kBlock / kWave);
+        const int32_t nctr = gridDim.x >= (uint32_t)kWorkCounters ? kWorkCounters : 1;
+        const int32_t x = (int32_t)(blockIdx.x % (uint32_t)nctr);
+        for (;;) {
+            int32_t k = 0;
+            if (lane == 0) k = atomicAdd(work + kCounterStride * x, 1);
+            k = __builtin_amdgcn_readfirstlane(k);
+            const int32_t item = x + nctr * k;
+            if (item >= total) break;
+            unit(item / (kBlock / kWave), item % (kBlock / kWave));
+        }
+    } else {
+        for (int32_t ug = blockIdx.x; ug < nunits; ug += gridDim.x) unit(ug, wave);
     }
     if (lane == 0 && ntests_h) atomicAdd(&tests[0], ntests_h);
     if (lane == 0 && ntests_r) atomicAdd(&tests[1], ntests_r);
@@ -1146,12 +1179,29 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         // waves), or one per item group when there are more
         const int64_t want_wg = kTargetWaves / (kBlock / kWave);
         const int64_t groups_ub = ceil_div(ub, kBlock) + 2 * (int64_t)nseg;
-        SKY_DISPATCH_D(pb.d, test_kernel, dim3(grid(groups_ub + 2 * want_wg)),
+        uint32_t tgrid = grid(groups_ub + 2 * want_wg);
+        // one segment: persistent workgroups fed from the work counters, as many as fit at once
+        // (a workgroup holds its LDS until its slowest wave is done, so one workgroup per unit
+        // left most of the chip idle behind a few long units)
+        int32_t* work = nullptr;
+        if (nseg == 1) {
+            const void* fn = nullptr;
+            SKY_KERNEL_PTR_D(pb.d, test_kernel, fn);
+            int32_t resident = 0;
+            SKY_TRY(resident_workgroups(fn, kBlock, 0, &resident));
+            if ((int64_t)tgrid > resident) {
+                tgrid = (uint32_t)resident;
+                work = b.work;
+                hipLaunchKernelGGL(zero_i32_kernel, dim3(kWorkCounters * kCounterStride / 64), dim3(64), 0, st,
+                                   work, (int32_t)(kWorkCounters * kCounterStride));
+            }
+        }
+        SKY_DISPATCH_D(pb.d, test_kernel, dim3(tgrid),
                        dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
                        (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.rest,
                        (const int32_t*)b.rhb, (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo,
                        (const uint32_t*)b.hhi, b.tcap, (const int32_t*)cnt, b.dom, b.tests,
-                       pb.seg_tests);
+                       pb.seg_tests, work);
         SKY_HIP(ev_rec(false));
         // the survivors of the rest groups, in order, are the next round's work list
         // (and the head survivors into the output, in extra blocks of the same launch)
