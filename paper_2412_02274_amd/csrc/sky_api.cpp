@@ -120,7 +120,6 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.counters = c.take<int32_t>(48);
     e.tests = c.take<unsigned long long>(3);
     e.work = c.take<int32_t>((size_t)kWorkCounters * kCounterStride);
-    e.flag = c.take<int32_t>((size_t)n);
     e.scan = c.take<int32_t>((size_t)n);
     e.scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(n));
     P->local_flag = c.take<uint8_t>((size_t)n);
@@ -314,7 +313,7 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     // the rows outside the pruned Grid cells (every row when none is pruned)
     SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID && P->info.pruned_rows > 0 ? P->pruned : nullptr,
                                  P->seg, n, P->eng.w1,
-                                 P->count_tmp, P->eng.flag, P->eng.scan, P->eng.scan_tmp, st, keep));
+                                 P->count_tmp, P->eng.scan_tmp, st, keep));
     // live rows: every row outside the pruned Grid cells (exactly what the list holds), minus the
     // rows the representatives removed (read back)
     int32_t live = n - (int32_t)P->info.pruned_rows;
@@ -364,8 +363,7 @@ sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_co
     int32_t count = (int32_t)P->info.local_count;
     if (P->p > 1) {
         // the union of the local skylines, in position order (spatially coherent)
-        SKY_TRY(launch_compact_flags(P->local_flag, n, P->eng.w1, P->count_tmp, P->eng.flag,
-                                     P->eng.scan, P->eng.scan_tmp, st));
+        SKY_TRY(launch_compact_flags(P->local_flag, n, P->eng.w1, P->count_tmp, P->eng.scan_tmp, st));
         SKY_TRY(launch_fill_u8(P->final_flag, n, 0, st));
         EngineProblem pb{};
         pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
@@ -521,8 +519,7 @@ sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, vo
     // partitions are contiguous: with p > 1 the store is ordered by partition, then curve)
     const uint8_t* flags = P->p > 1 ? P->final_flag : P->local_flag;
     int32_t* pos = (int32_t*)tmp.k0;  // s entries, free until the search
-    SKY_TRY(launch_compact_flags(flags, (int32_t)P->n, pos, P->count_tmp, P->eng.flag, P->eng.scan,
-                                 P->eng.scan_tmp, st));
+    SKY_TRY(launch_compact_flags(flags, (int32_t)P->n, pos, P->count_tmp, P->eng.scan_tmp, st));
     // the row -> index-in-sky_idx map is left in pos_tmp by sky_merge
     SKY_TRY(launch_gres_prepare_positions(P->xp, P->ldp, P->d, pos, s, P->rowid, P->pos_tmp, store, st));
     SKY_TRY(launch_gres_targets(nullptr, 0, P->d, 0, nullptr, s, s, store, tg, dev_status, st));

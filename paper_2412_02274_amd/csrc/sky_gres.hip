@@ -373,7 +373,6 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     unsigned long long ntests = 0;   // candidate tests (target against candidate at one level)
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     int32_t band0 = 0;
     WgWork w{0, 0, nt};
     if (!work) {

@@ -250,7 +250,7 @@ struct EngineBuffers {
     int32_t* counters;             // [3 * 16]: the output count, then two per-round sets
     unsigned long long* tests;     // [3] dominance-test counters (head, rest, per-segment max)
     int32_t* work;                 // [kWorkCounters * kCounterStride] work counters of the test launch
-    int32_t* flag; int32_t* scan;  // [n] stable-compaction scratch
+    int32_t* scan;                 // [n] rest-compaction scratch
     int32_t* scan_tmp;             // scan scratch for n values
 };
 int64_t engine_head_capacity(int64_t n, int32_t nseg);
@@ -275,15 +275,16 @@ struct EngineResult { int32_t count; int32_t rounds; int64_t tests; int64_t test
 sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,
                       EngineResult* res, hipStream_t st);
 // helpers used by the API layer
+// (scan_tmp: scan_tmp_elems(n) int32 of scratch, for these two and launch_final_output)
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
-                                int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
-                                int32_t* scan_tmp, hipStream_t st, const uint8_t* keep = nullptr);
+                                int32_t* out, int32_t* count, int32_t* scan_tmp, hipStream_t st,
+                                const uint8_t* keep = nullptr);
 sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 // dst[rowid[q]] = src[q] for q < n (int32 and/or uint8 arrays)
 sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
                                int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st);
 sky_status launch_compact_flags(const uint8_t* flags, int32_t n, int32_t* out, int32_t* count,
-                                int32_t* flag, int32_t* scan, int32_t* scan_tmp, hipStream_t st);
+                                int32_t* scan_tmp, hipStream_t st);
 sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t* rowid,
                                int64_t n, uint8_t* member_tmp, uint8_t* member_out,
                                int64_t* sky_idx, int64_t cap, int64_t* dev_count,

@@ -1000,35 +1000,6 @@ __global__ void __launch_bounds__(kBlock) mark_rows_kernel(const int32_t* __rest
     if (i < count) member[rowid[list[i]]] = 1;
 }
 
-__global__ void __launch_bounds__(kBlock) u8_to_i32_kernel(const uint8_t* __restrict__ m, int64_t n,
-                                                            int32_t* __restrict__ out) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) out[i] = m[i];
-}
-
-__global__ void __launch_bounds__(kBlock) write_idx_kernel(const uint8_t* __restrict__ m, int64_t n,
-                                                            const int32_t* __restrict__ pos,
-                                                            int64_t* __restrict__ sky_idx,
-                                                            int64_t cap,
-                                                            uint8_t* __restrict__ member_out) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    uint8_t v = m[i];
-    if (member_out) member_out[i] = v;
-    if (v) {
-        int64_t p = pos[i];
-        if (p < cap) sky_idx[p] = i;
-    }
-}
-
-__global__ void finish_count_kernel(const int32_t* __restrict__ pos, const uint8_t* __restrict__ m,
-                                    int64_t n, int64_t cap, int64_t* __restrict__ dev_count,
-                                    int32_t* dev_status) {
-    int64_t c = (int64_t)pos[n - 1] + (int64_t)m[n - 1];
-    *dev_count = c;
-    if (c > cap) raise_status(dev_status, SKY_ERR_CAPACITY);
-}
-
 __global__ void __launch_bounds__(kBlock) scatter_rows_i32_kernel(const int32_t* __restrict__ src,
                                                                    const int32_t* __restrict__ rowid,
                                                                    int64_t n, int32_t* __restrict__ dst) {
@@ -1048,7 +1019,7 @@ __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
     if (i < n) p[i] = v;
 }
 
-// stable compaction helpers: flags, then out[scan[i]] = i
+// every position in order
 __global__ void __launch_bounds__(kBlock) iota_kernel(int32_t n, int32_t* __restrict__ out,
                                                        int32_t* __restrict__ count) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -1056,25 +1027,101 @@ __global__ void __launch_bounds__(kBlock) iota_kernel(int32_t n, int32_t* __rest
     if (i == 0) *count = n;
 }
 
-__global__ void __launch_bounds__(kBlock) keep_flag_kernel(const uint8_t* __restrict__ skip_seg,
-                                                            const int32_t* __restrict__ seg,
-                                                            const uint8_t* __restrict__ flags_u8,
-                                                            int32_t n, int32_t* __restrict__ flag) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    bool keep = flags_u8 ? flags_u8[i] != 0 : true;
-    if (skip_seg && skip_seg[seg[i]]) keep = false;
-    flag[i] = keep ? 1 : 0;
+// ---- stable selection in three launches: per-block counts, their scan, then each block
+// re-derives its positions' predicate bits and writes the selected ones at its offset ---------
+constexpr int kSelPer = 16;                  // consecutive positions per thread
+constexpr int kSelChunk = kBlock * kSelPer;  // positions per block
+
+// position i is selected iff flags[i] != 0 (no flags: every position), keep[i] != 0 (if given)
+// and its segment is not skipped (if skip_seg is given)
+struct SelPred {
+    const uint8_t* flags;
+    const uint8_t* keep;
+    const uint8_t* skip_seg;
+    const int32_t* seg;
+};
+
+__device__ __forceinline__ uint32_t sel_bits(const SelPred& p, int64_t base, int64_t n) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j) {
+        const int64_t i = base + j;
+        if (i < n) {
+            bool v = p.flags ? p.flags[i] != 0 : true;
+            if (p.keep) v = v && p.keep[i] != 0;
+            if (p.skip_seg) v = v && !p.skip_seg[p.seg[i]];
+            m |= (v ? 1u : 0u) << j;
+        }
+    }
+    return m;
 }
 
-__global__ void __launch_bounds__(kBlock) index_compact_kernel(const int32_t* __restrict__ flag,
-                                                                const int32_t* __restrict__ scan,
-                                                                int32_t n, int32_t* __restrict__ out,
-                                                                int32_t* __restrict__ count) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    if (flag[i]) out[scan[i]] = i;
-    if (i == n - 1) *count = scan[i] + flag[i];
+// block-wide exclusive scan of one value per thread; *total gets the block's sum
+__device__ __forceinline__ int32_t sel_block_scan(int32_t v, int32_t* total) {
+    __shared__ int32_t wsum[kBlock / kWave];
+    const int lane = (int)lane_id();
+    const int wave = threadIdx.x / kWave;
+    int32_t inc = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t o = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += o;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    int32_t before = 0, t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        before += w < wave ? wsum[w] : 0;
+        t += wsum[w];
+    }
+    *total = t;
+    return before + inc - v;
+}
+
+__global__ void __launch_bounds__(kBlock) sel_count_kernel(SelPred p, int64_t n, int32_t* __restrict__ blk) {
+    const int64_t base = (int64_t)blockIdx.x * kSelChunk + (int64_t)threadIdx.x * kSelPer;
+    int32_t total = 0;
+    sel_block_scan(__popc(sel_bits(p, base, n)), &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+// out32[k] = the k-th selected position (int32 output), or out64[k] for k < cap (int64 output);
+// all_idx[i] (if given) = number of selected positions before i, for every i; flags_copy (if
+// given) = the selection as bytes; the last block stores the total in *count32 / *count64 and
+// raises SKY_ERR_CAPACITY when it exceeds cap (int64 output)
+__global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
+                                                            const int32_t* __restrict__ blk_off,
+                                                            int32_t* __restrict__ out32,
+                                                            int64_t* __restrict__ out64, int64_t cap,
+                                                            int32_t* __restrict__ all_idx,
+                                                            uint8_t* __restrict__ flags_copy,
+                                                            int32_t* __restrict__ count32,
+                                                            int64_t* __restrict__ count64,
+                                                            int32_t* dev_status) {
+    const int64_t base = (int64_t)blockIdx.x * kSelChunk + (int64_t)threadIdx.x * kSelPer;
+    const uint32_t m = sel_bits(p, base, n);
+    int32_t total = 0;
+    int32_t k = blk_off[blockIdx.x] + sel_block_scan(__popc(m), &total);
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j) {
+        const int64_t i = base + j;
+        if (i >= n) break;
+        const bool v = (m >> j) & 1u;
+        if (all_idx) all_idx[i] = k;
+        if (flags_copy) flags_copy[i] = v ? 1 : 0;
+        if (v) {
+            if (out32) out32[k] = (int32_t)i;
+            if (out64 && k < cap) out64[k] = i;
+            ++k;
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        const int64_t c = (int64_t)blk_off[blockIdx.x] + total;
+        if (count32) *count32 = (int32_t)c;
+        if (count64) {
+            *count64 = c;
+            if (c > cap) raise_status(dev_status, SKY_ERR_CAPACITY);
+        }
+    }
 }
 
 
@@ -1231,6 +1278,10 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         const bool ahead = pb.host_scratch && pb.round_events[0] && pb.round_events[1];
         int64_t ub_next = 0;  // bound on the input of the round after the last one launched
         auto bound_after = [&](int64_t in) -> int64_t {
+            // a segment with at most kAllHead live rows takes them all into its head, so a
+            // round whose whole input is that small leaves nothing for the next one (no empty
+            // round is launched ahead)
+            if (in <= kAllHead) return 0;
             // a round takes at least min(kHead, live) rows of a lone segment into its head
             if (nseg == 1) return in > kHead ? in - kHead : 0;
             return in > 0 ? in - 1 : 0;
@@ -1298,42 +1349,42 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
     return SKY_OK;
 }
 
+// Stable selection of the positions [0, n) that satisfy p (see sel_write_kernel for the
+// outputs). tmp: scan_tmp_elems(n) int32 of scratch.
+static sky_status launch_select(const SelPred& p, int64_t n, int32_t* out32, int64_t* out64, int64_t cap,
+                                int32_t* all_idx, uint8_t* flags_copy, int32_t* count32, int64_t* count64,
+                                int32_t* dev_status, int32_t* tmp, hipStream_t st) {
+    const int64_t nblk = ceil_div(n > 0 ? n : 1, kSelChunk);
+    int32_t* blk = tmp;  // block counts, then their exclusive scan (the layout of scan_tmp_elems)
+    hipLaunchKernelGGL(sel_count_kernel, dim3((uint32_t)nblk), dim3(kBlock), 0, st, p, n, blk);
+    SKY_HIP(hipGetLastError());
+    SKY_TRY(launch_exclusive_scan(blk, blk, nblk, tmp + round_up(nblk, 64), st));
+    hipLaunchKernelGGL(sel_write_kernel, dim3((uint32_t)nblk), dim3(kBlock), 0, st, p, n,
+                       (const int32_t*)blk, out32, out64, cap, all_idx, flags_copy, count32, count64,
+                       dev_status);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
 // Positions [0, n) in order, without those whose segment is skipped (stable).
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
-                                int32_t* out, int32_t* count, int32_t* flag, int32_t* scan,
-                                int32_t* scan_tmp, hipStream_t st, const uint8_t* keep) {
+                                int32_t* out, int32_t* count, int32_t* scan_tmp, hipStream_t st,
+                                const uint8_t* keep) {
     const uint32_t nb = (uint32_t)ceil_div(n > 0 ? n : 1, kBlock);
     if (!skip_seg && !keep) {  // nothing skipped: the list is every position
         hipLaunchKernelGGL(iota_kernel, dim3(nb), dim3(kBlock), 0, st, n, out, count);
         SKY_HIP(hipGetLastError());
         return SKY_OK;
     }
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, count, 1);
-    if (n <= 0) { SKY_HIP(hipGetLastError()); return SKY_OK; }
-    hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, skip_seg, seg_of_pos, keep, n,
-                       flag);
-    SKY_HIP(hipGetLastError());
-    SKY_TRY(launch_exclusive_scan(flag, scan, n, scan_tmp, st));
-    hipLaunchKernelGGL(index_compact_kernel, dim3(nb), dim3(kBlock), 0, st, (const int32_t*)flag,
-                       (const int32_t*)scan, n, out, count);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
+    const SelPred p{nullptr, keep, skip_seg, skip_seg ? seg_of_pos : nullptr};
+    return launch_select(p, n, out, nullptr, 0, nullptr, nullptr, count, nullptr, nullptr, scan_tmp, st);
 }
 
 // Positions i with flags[i] != 0, in order (stable).
 sky_status launch_compact_flags(const uint8_t* flags, int32_t n, int32_t* out, int32_t* count,
-                                int32_t* flag, int32_t* scan, int32_t* scan_tmp, hipStream_t st) {
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, count, 1);
-    if (n <= 0) { SKY_HIP(hipGetLastError()); return SKY_OK; }
-    const uint32_t nb = (uint32_t)ceil_div(n, kBlock);
-    hipLaunchKernelGGL(keep_flag_kernel, dim3(nb), dim3(kBlock), 0, st, (const uint8_t*)nullptr,
-                       (const int32_t*)nullptr, flags, n, flag);
-    SKY_HIP(hipGetLastError());
-    SKY_TRY(launch_exclusive_scan(flag, scan, n, scan_tmp, st));
-    hipLaunchKernelGGL(index_compact_kernel, dim3(nb), dim3(kBlock), 0, st, (const int32_t*)flag,
-                       (const int32_t*)scan, n, out, count);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
+                                int32_t* scan_tmp, hipStream_t st) {
+    const SelPred p{flags, nullptr, nullptr, nullptr};
+    return launch_select(p, n, out, nullptr, 0, nullptr, nullptr, count, nullptr, nullptr, scan_tmp, st);
 }
 
 
@@ -1367,17 +1418,10 @@ sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t
     if (count > 0)
         hipLaunchKernelGGL(mark_rows_kernel, dim3((uint32_t)ceil_div(count, kBlock)), dim3(kBlock), 0,
                            st, list, count, rowid, member_tmp);
-    const uint32_t nb = (uint32_t)ceil_div(n, kBlock);
-    hipLaunchKernelGGL(u8_to_i32_kernel, dim3(nb), dim3(kBlock), 0, st, (const uint8_t*)member_tmp, n,
-                       pos_tmp);
-    SKY_HIP(hipGetLastError());
-    SKY_TRY(launch_exclusive_scan(pos_tmp, pos_tmp, n, scan_tmp, st));
-    hipLaunchKernelGGL(write_idx_kernel, dim3(nb), dim3(kBlock), 0, st, (const uint8_t*)member_tmp, n,
-                       (const int32_t*)pos_tmp, sky_idx, cap, member_out);
-    hipLaunchKernelGGL(finish_count_kernel, dim3(1), dim3(1), 0, st, (const int32_t*)pos_tmp,
-                       (const uint8_t*)member_tmp, n, cap, dev_count, dev_status);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
+    // ascending rows: pos_tmp[row] = the row's index in sky_idx (kept for the gres store)
+    const SelPred p{member_tmp, nullptr, nullptr, nullptr};
+    return launch_select(p, n, nullptr, sky_idx, cap, pos_tmp, member_out, nullptr, dev_count, dev_status,
+                         scan_tmp, st);
 }
 
 }  // namespace sky
