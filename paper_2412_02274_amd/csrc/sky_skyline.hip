@@ -123,6 +123,17 @@ __global__ void init_segments_kernel(int32_t nseg, uint32_t* __restrict__ smin,
     if (i == 0) counters[C_NEXT] = 0;
 }
 
+// Multi-segment passes over a round's list. The list is in position order and segments are
+// runs of positions, so a wavefront's kSegPer * 64 consecutive items (lane l takes items
+// l, l + 64, ...) fall into one or a few segments: each lane folds its items into runs of one
+// segment, a lane flushes a run only when its segment changes, and the lanes' last runs are
+// combined per segment across the wavefront, so the global atomics are a few per wavefront
+// instead of one per item (they all land on a few lines per segment).
+constexpr int kSegPer = 16;
+__host__ __device__ constexpr int64_t seg_pass_blocks(int64_t n) {
+    return (n + (int64_t)kBlock * kSegPer - 1) / ((int64_t)kBlock * kSegPer);
+}
+
 __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restrict__ items,
                                                          int32_t n_host, const int32_t* __restrict__ n_dev,
                                                          const float* __restrict__ fsum,
@@ -131,32 +142,52 @@ __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restric
                                                          uint32_t* __restrict__ smax,
                                                          int32_t* __restrict__ info) {
     const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = i < n;
-    int32_t s = 0;
-    uint32_t fb = 0;
-    if (valid) {
-        int32_t pos = items[i];
-        s = seg_of(seg_of_pos, pos);
-        fb = fbits(fsum[pos]);  // f >= 0: bit order == value order
-    }
     const int lane = (int)lane_id();
+    const int64_t wbase = ((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (kWave * kSegPer);
+    int32_t cs = -1;  // segment of the lane's current run
+    uint32_t cmin = 0xFFFFFFFFu, cmax = 0u;
+    int32_t ccnt = 0;
+    for (int j = 0; j < kSegPer; ++j) {
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        if (i >= n) break;
+        const int32_t pos = items[i];
+        const int32_t sg = seg_of(seg_of_pos, pos);
+        const uint32_t fb = fbits(fsum[pos]);  // f >= 0: bit order == value order
+        if (sg != cs) {
+            if (cs >= 0) {
+                atomicMin(&smin[cs], cmin);
+                atomicMax(&smax[cs], cmax);
+                atomicAdd(&info[cs * kInfo + SI_LIVE], ccnt);
+            }
+            cs = sg;
+            cmin = fb;
+            cmax = fb;
+            ccnt = 1;
+        } else {
+            cmin = fb < cmin ? fb : cmin;
+            cmax = fb > cmax ? fb : cmax;
+            ++ccnt;
+        }
+    }
+    const bool valid = cs >= 0;
     uint64_t act = __ballot(valid);
     while (act) {
         const int leader = __ffsll((unsigned long long)act) - 1;
-        const int32_t sl = __shfl(s, leader, kWave);
-        const bool mine = valid && s == sl;
+        const int32_t sl = __shfl(cs, leader, kWave);
+        const bool mine = valid && cs == sl;
         const uint64_t peers = __ballot(mine);
-        uint32_t vmin = mine ? fb : 0xFFFFFFFFu, vmax = mine ? fb : 0u;
+        uint32_t vmin = mine ? cmin : 0xFFFFFFFFu, vmax = mine ? cmax : 0u;
+        int32_t vcnt = mine ? ccnt : 0;
         for (int off = kWave / 2; off > 0; off >>= 1) {
-            uint32_t a = __shfl_xor(vmin, off, kWave), b = __shfl_xor(vmax, off, kWave);
+            const uint32_t a = __shfl_xor(vmin, off, kWave), b = __shfl_xor(vmax, off, kWave);
             vmin = a < vmin ? a : vmin;
             vmax = b > vmax ? b : vmax;
+            vcnt += __shfl_xor(vcnt, off, kWave);
         }
         if (lane == leader) {
             atomicMin(&smin[sl], vmin);
             atomicMax(&smax[sl], vmax);
-            atomicAdd(&info[sl * kInfo + SI_LIVE], (int32_t)__popcll(peers));
+            atomicAdd(&info[sl * kInfo + SI_LIVE], vcnt);
         }
         act &= ~peers;
     }
@@ -179,6 +210,9 @@ __device__ __forceinline__ int32_t item_bin(const float* fsum, const uint32_t* s
     return bin_of(fsum[pos], __uint_as_float(smin[s]), seg_scale(smin[s], smax[s]));
 }
 
+// Score histogram per segment. The block's items (consecutive, kSegPer * kBlock of them) go
+// into an LDS histogram of the segment of its first item, flushed once at the end; items of
+// any other segment (the block straddles a boundary) are counted with global atomics.
 __global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict__ items,
                                                        int32_t n_host, const int32_t* __restrict__ n_dev,
                                                        const float* __restrict__ fsum,
@@ -186,12 +220,30 @@ __global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict_
                                                        const uint32_t* __restrict__ smin,
                                                        const uint32_t* __restrict__ smax,
                                                        int32_t* __restrict__ hist) {
+    __shared__ int32_t lh[kBins];
     const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    int32_t pos = items[i];
-    int32_t s = seg_of(seg_of_pos, pos);
-    atomicAdd(&hist[(int64_t)s * kBins + item_bin(fsum, smin, smax, s, pos)], 1);
+    const int64_t bbase = (int64_t)blockIdx.x * kBlock * kSegPer;
+    for (int b = threadIdx.x; b < kBins; b += kBlock) lh[b] = 0;
+    const int32_t s0 = bbase < n ? seg_of(seg_of_pos, items[bbase]) : -1;  // block-uniform
+    __syncthreads();
+    if (s0 >= 0) {
+        const float lo0 = __uint_as_float(smin[s0]);
+        const float sc0 = seg_scale(smin[s0], smax[s0]);
+        const int lane = (int)lane_id();
+        const int64_t wbase = bbase + (int64_t)(threadIdx.x / kWave) * (kWave * kSegPer);
+        for (int j = 0; j < kSegPer; ++j) {
+            const int64_t i = wbase + (int64_t)j * kWave + lane;
+            if (i >= n) break;
+            const int32_t pos = items[i];
+            const int32_t sg = seg_of(seg_of_pos, pos);
+            if (sg == s0) atomicAdd(&lh[bin_of(fsum[pos], lo0, sc0)], 1);
+            else atomicAdd(&hist[(int64_t)sg * kBins + item_bin(fsum, smin, smax, sg, pos)], 1);
+        }
+    }
+    __syncthreads();
+    if (s0 >= 0)
+        for (int b = threadIdx.x; b < kBins; b += kBlock)
+            if (lh[b]) atomicAdd(&hist[(int64_t)s0 * kBins + b], lh[b]);
 }
 
 // Single-segment variants (the merge phase and unpartitioned data): grid-stride loops with
@@ -1193,9 +1245,10 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
                                pb.fsum, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist,
                                b.seg_info, (int32_t)!first);
         } else {
-            hipLaunchKernelGGL(minmax_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+            const uint32_t pblocks = (uint32_t)(seg_pass_blocks(ub) > 0 ? seg_pass_blocks(ub) : 1);
+            hipLaunchKernelGGL(minmax_kernel, dim3(pblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
                                pb.fsum, pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
-            hipLaunchKernelGGL(hist_kernel, dim3(iblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
+            hipLaunchKernelGGL(hist_kernel, dim3(pblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
                                pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min,
                                (const uint32_t*)b.seg_max, b.hist);
         }
