@@ -207,6 +207,14 @@ def main():
                                     traffic["dominance_test"], executed * ops_per_test),
              "gres_search": roof("gres_search", counts["gres_tests"], gres_ms, 1,
                                  traffic["gres_search"], gres_executed * 3 * d)}
+    # the HBM-bound ingest (validate + transpose): 4 N d bytes read and 4 N d bytes written, over
+    # the event-timed ingest phase of the separately timed pass (one kernel)
+    ingest_bytes = 8 * n * d
+    ingest_gbs = ingest_bytes / (phases["ingest"] * 1e-3) / 1e9
+    roofs["ingest"] = {"kernel": "ingest", "bound": "hbm", "achieved": ingest_gbs, "peak": PEAK_HBM_GBS,
+                       "unit": "GB/s", "frac": ingest_gbs / PEAK_HBM_GBS, "traffic": None,
+                       "launches_per_step": 1, "avg_launch_us": phases["ingest"] * 1e3,
+                       "alg_bytes_per_launch": ingest_bytes}
     dominant = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     roofline = dict(roofs[dominant])
     roofline["note"] = ("achieved = algorithmic tests (oracle's plain sequential method: SFS for the "

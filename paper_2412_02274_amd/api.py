@@ -434,9 +434,9 @@ class Pipeline:
         st = torch.cuda.current_stream()
         sp = C.c_void_p(st.cuda_stream)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if timing else None
+        self.status.zero_()
         if ev:
             ev[0].record(st)
-        self.status.zero_()
         _lib.check(lib.sky_ingest(_ptr(x_rows), self.n, self.d, _ptr(self.x_soa), self.n,
                                   _ptr(self.status), sp), "sky_ingest")
         if ev:
