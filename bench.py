@@ -93,8 +93,15 @@ def cpu_baseline(x, g_max, rows):
     sky = np.flatnonzero(mem)
     _, t_gres = oracle.gres(sub, sky, g_max)
     dt = time.perf_counter() - t0
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": (t_sfs + t_gres) / dt, "unit": "dominance tests/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model,
+            "host_cpus": os.cpu_count(),
             "sample": f"first {rows} rows of the workload: SFS skyline ({t_sfs} tests, 1 thread) "
                       f"+ Alg. 1 gres of its {len(sky)} skyline tuples ({t_gres} tests, OpenMP); "
                       f"{dt:.1f} s"}
