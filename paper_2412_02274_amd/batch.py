@@ -132,7 +132,7 @@ class GresTuner:
     (d, skyline size, largest relation's skyline, g_max) in memory and, if `path` is given, in
     a JSON file."""
 
-    PER_WG = (8, 16, 32, 64, 128)  # 8 waves per workgroup: 1 to 16 tuples per wave
+    PER_WG = (8, 16, 32, 64, 128, 256, 512)  # 8 waves per workgroup: 1 to 64 tuples per wave
     LEVELS_MAX_CANDIDATES = 8192
 
     def __init__(self, path=None, repeats=2):
