@@ -172,6 +172,36 @@ def test_skyline_all_equal(dev):
     assert (idx == np.arange(4000)).all()
 
 
+@pytest.mark.parametrize("n", [4095, 4096, 4097, 12289])
+@pytest.mark.parametrize("scheme,p", [("none", 1), ("sliced", 3)])
+def test_selection_block_edges(dev, n, scheme, p):
+    # every row in the skyline (all equal) and every second row (a staircase) at sizes around
+    # the selection's 4096-position blocks: ascending ids, member bytes, per-row indices (the
+    # gres store reads them) and the count
+    for kind in ("equal", "stair"):
+        if kind == "equal":
+            x = np.full((n, 2), 0.25, np.float32)
+            want = np.arange(n)
+        else:
+            t = (np.arange(n) // 2).astype(np.float64) / n
+            x = np.stack([t, 1.0 - 1.0 / n - t], 1).astype(np.float32)
+            x[1::2] += np.float32(0.5 / n)  # odd rows: dominated by the row before
+            want = np.flatnonzero(oracle.skyline(x))
+        xs = api.ingest(torch.from_numpy(x).to(dev))
+        plan = api.build(xs, scheme, p)
+        plan.local_skylines()
+        idx, mem = plan.merge(member=True)
+        ge, _ = plan.gres(25)
+        plan.close()
+        assert np.array_equal(idx.cpu().numpy(), want), (kind, n)
+        assert np.array_equal(np.flatnonzero(mem.cpu().numpy()), want)
+        if kind == "equal":  # equal rows never dominate one another: no exit at any level
+            assert (ge.cpu().numpy() == 1).all()
+        else:
+            want_ge, _ = oracle.gres(x, want, 25)
+            assert np.array_equal(ge.cpu().numpy(), want_ge)
+
+
 def test_merge_capacity_error(dev):
     x = G.ant(2000, 4, 1)
     xs = api.ingest(torch.from_numpy(x).to(dev))
