@@ -357,9 +357,8 @@ template <int D>
 //    next target from a counter in LDS when it is free (measured: 9% faster than a fixed share
 //    per wave on the batched workload);
 //  * work != nullptr (one segment): the grid is what the device holds at once, and every wave
-//    takes the next pair from its workgroup's counter in `work` (striped counters, zero at
-//    launch) until none is left, so a workgroup's tile boxes are loaded once and no wave waits
-//    for a slow one to free its slot.
+//    takes the next pair from the counter *work (zero at launch) until none is left, so a
+//    workgroup's tile boxes are loaded once and no wave waits for a slow one to free its slot.
 __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu(8))) gres_tiles_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
     const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
