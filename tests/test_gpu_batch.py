@@ -160,6 +160,8 @@ def test_batch_capacity_and_state_errors(dev):
     assert lib.sky_batch_info(h, C.byref(inf)) == 0
     mem, _ = oracle.skyline_sfs(x)
     assert inf.sky_count == 2 * int(mem.sum())
+    # the costliest relation's local tests: at most all of them, at least their mean
+    assert 0 < inf.tests_local_max <= inf.tests_local <= 2 * inf.tests_local_max
     lib.sky_batch_destroy(h)
     run.close()
 
