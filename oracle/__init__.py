@@ -43,7 +43,7 @@ def _load():
         "orc_local_skylines": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, _i32p, _u8p, _u8p]),
         "orc_grid_part": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _i32p]),
         "orc_grid_pruned": (None, [_u8p, C.c_int32, C.c_int32, _u8p]),
-        "orc_angular_part": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _i32p, _u8p]),
+        "orc_angular_part": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, _i32p, _i32p]),
         "orc_sliced_part": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_int32, _i32p]),
         "orc_closest_m": (C.c_int32, [C.c_int64, C.c_int32]),
         "orc_gres": (None, [_f32p, C.c_int64, C.c_int32, C.c_int64, _i64p, C.c_int64, C.c_int32,
@@ -140,12 +140,14 @@ def grid_pruned(nonempty, m: int, d: int) -> np.ndarray:
 
 
 def angular_part(x, m: int):
-    """Eq. (1): (partition ids, near-boundary flags)."""
+    """Eq. (1): (partition ids, near-boundary masks). Bit a of mask[i] is set when angle a of
+    row i lies within 1e-9 of a bucket boundary (there an equally faithful evaluation may give
+    the neighbouring bucket of that angle); 0 for every other row."""
     xs, n, d = _soa(x)
     part = np.zeros(n, dtype=np.int32)
-    near = np.zeros(n, dtype=np.uint8)
-    _load().orc_angular_part(_p(xs, _f32p), n, d, n, m, _p(part, _i32p), _p(near, _u8p))
-    return part, near.astype(bool)
+    near = np.zeros(n, dtype=np.int32)
+    _load().orc_angular_part(_p(xs, _f32p), n, d, n, m, _p(part, _i32p), _p(near, _i32p))
+    return part, near
 
 
 def sliced_part(x, p: int, dim: int = 0) -> np.ndarray:
@@ -164,7 +166,8 @@ def key(v: float, g: int) -> int:
 
 
 def gres(x, cand, g_max: int):
-    """Alg. 1 over candidate rows ``cand`` (normally Sky(r)): (g_exit[len(cand)], tests).
+    """Def. 2 over candidate rows ``cand`` (normally Sky(r)), levels 2..g_max as in Alg. 1:
+    (g_exit[len(cand)], tests).
     gres = 1 / g_exit; g_exit == 1 means the tuple never left the skyline."""
     xs, n, d = _soa(x)
     cand = np.ascontiguousarray(cand, dtype=np.int64)

@@ -17,14 +17,18 @@
  *   orc_count_invalid       -- pinned (hand-made values).
  *   orc_skyline             -- pinned (brute force on tiny inputs, d=1 and d=2 closed forms).
  *   orc_skyline_sfs         -- pinned (equals orc_skyline on random inputs with ties).
- *   orc_local_skylines      -- pinned (union/final == orc_skyline for every scheme).
+ *   orc_local_skylines      -- pinned (each partition's local skyline equals the Python brute
+ *                              force of Def. 1 over that partition's rows alone, for Grid with
+ *                              a pruned cell, Angular and Sliced ids on data with duplicates;
+ *                              union/final == orc_skyline for every scheme).
  *   orc_grid_part           -- pinned (paper's 3x3 worked example, cell bounds).
  *   orc_grid_pruned         -- pinned (paper's worked example: cell 1 prunes exactly 5 and 8).
- *   orc_angular_part        -- pinned (angles recomputed in closed form on special directions).
+ *   orc_angular_part        -- pinned (angles recomputed in closed form on special directions
+ *                              and by arccos on random rows).
  *   orc_sliced_part         -- pinned (sizes floor/ceil(N/p), order on the slicing attribute).
- *   orc_gres                -- pinned (Python brute force of Def. 2 with set semantics, FP32
- *                              and exact rationals; the worked counterexample; invariants).
- *   orc_gres_rows           -- pinned (equals orc_gres on the sampled rows).
+ *   orc_gres, orc_gres_rows -- pinned (Python brute force of Def. 2 with set semantics, FP32
+ *                              and exact rationals; the worked counterexample; invariants;
+ *                              the two agree on sampled rows).
  *   orc_skyline_rows        -- pinned (equals orc_skyline on the sampled rows).
  *   orc_representatives     -- pinned (numpy lexsort of the FP32 scores for the selection, the
  *                              Python brute force of Def. 1 for the kept set).
@@ -218,15 +222,16 @@ void orc_grid_pruned(const uint8_t* nonempty, int32_t m, int32_t d, uint8_t* pru
 /* non-negative data), and partition sum_{i=1}^{d-1} floor(2*phi_i*m/pi) * m^(i-1).             */
 /* The bucket of phi_i = pi/2 exactly would be m; it is clamped to m-1. Computed in double.     */
 /* A zero sub-vector (t_i = 0 and all later attributes 0) has atan2(0, 0) = 0, bucket 0.         */
-/* near[i] = 1 when some angle lies within 1e-9 (relative) of a bucket boundary: there a        */
-/* different but equally faithful evaluation of the same formula may round to the other side.  */
+/* near[i] has bit i-1 set when angle phi_i lies within 1e-9 (relative) of a bucket boundary:  */
+/* there a different but equally faithful evaluation of the same formula may put the row in    */
+/* the bucket on the other side of that boundary (and only there).                              */
 /* ------------------------------------------------------------------------------------------ */
 void orc_angular_part(const float* x, int64_t n, int32_t d, int64_t ld, int32_t m, int32_t* part,
-                      uint8_t* near) {
+                      int32_t* near) {
     const double pi = 3.14159265358979323846;
     for (int64_t i = 0; i < n; ++i) {
         int64_t id = 0, w = 1;
-        uint8_t nb = 0;
+        int32_t nb = 0;
         for (int32_t a = 0; a + 1 < d; ++a) {
             double tail = 0.0;
             for (int32_t j = a + 1; j < d; ++j) {
@@ -240,7 +245,7 @@ void orc_angular_part(const float* x, int64_t n, int32_t d, int64_t ld, int32_t 
             if (b > m - 1) b = m - 1;
             if (b < 0) b = 0;
             double r = q - floor(q + 0.5);
-            if (fabs(r) < 1e-9 * (q > 1.0 ? q : 1.0) && q > 0.5 && q < (double)m - 0.5) nb = 1;
+            if (fabs(r) < 1e-9 * (q > 1.0 ? q : 1.0) && q > 0.5 && q < (double)m - 0.5) nb |= 1 << a;
             id += b * w;
             w *= m;
         }
@@ -307,53 +312,53 @@ static int proj_dominates(const float* x, int64_t ld, int32_t d, int64_t s, int6
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Grid resistance, Def. 2 (Sec. 2) via Alg. 1 (Sec. 3.2).                                      */
-/* Candidates cand[0..s) are the rows of the skyline s = Sky(r) (gres is stable: dominated rows */
-/* do not change it), and they are also the tuples t whose gres is computed.                    */
-/* Alg. 1 scans g = g_max, g_max-1, ..., 2; at each g the projection of t is in                 */
-/* Sky(gproj(r,g)) iff no projected candidate dominates it; the first (largest) g at which t is */
-/* not a member is recorded, and t never leaving the skyline is recorded as 1.                  */
-/* Output: g_exit[j] = that g for t = cand[j], or 1; gres = 1/g_exit.                           */
-/* tests (nullable) receives the number of projected dominance tests made, scanning candidates */
-/* in the given order and stopping at the first dominator (reported, not compared).            */
+/* Grid resistance, Def. 2 (Sec. 2): gres(t) = min { 1/g : gproj(t,g) is not in              */
+/* Sky(gproj(r,g)) }, 1 when there is no such g; the levels are g = 2..g_max, the range Alg. 1 */
+/* (Sec. 3.2) searches (g = 1 sends every value of [0, 1) to 0, so nothing leaves there).     */
+/* The projection of t is outside the projected skyline iff some projected candidate dominates */
+/* it, and the smallest 1/g is the largest such g, so each tuple scans g downwards from g_max   */
+/* and stops at the first level where a candidate's projection dominates its own.              */
+/* Candidates cand[0..s) are the skyline rows (gres is stable, Sec. 3.2: dominated rows never  */
+/* change it); they are also the tuples whose gres is computed.                                */
+/* g_exit_of returns that level, or 1; *tests counts the projected dominance tests made,       */
+/* scanning candidates in the given order and stopping at the first dominator. This is also   */
+/* the count of Alg. 1's level-by-level scan: both test the same (tuple, level) pairs against */
+/* the same candidates in the same order (reported, not compared).                            */
 /* ------------------------------------------------------------------------------------------ */
+static int32_t g_exit_of(const float* x, int64_t ld, int32_t d, const int64_t* cand, int64_t s,
+                         int64_t t, int32_t g_max, int64_t* tests) {
+    for (int32_t g = g_max; g >= 2; --g)
+        for (int64_t q = 0; q < s; ++q) {
+            if (cand[q] == t) continue;
+            ++*tests;
+            if (proj_dominates(x, ld, d, cand[q], t, g)) return g;
+        }
+    return 1; /* no level at which the projection of t is dominated: gres(t) = 1 */
+}
+
+/* Output: g_exit[j] for t = cand[j]; gres = 1/g_exit. */
 void orc_gres(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* cand, int64_t s,
               int32_t g_max, int32_t* g_exit, int64_t* tests) {
     (void)n;
     int64_t total = 0;
-    for (int64_t j = 0; j < s; ++j) g_exit[j] = 0; /* 0 = map(t) still nil */
-    for (int32_t g = g_max; g >= 2; --g) {
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : total)
-        for (int64_t j = 0; j < s; ++j) {
-            if (g_exit[j] != 0) continue;
-            for (int64_t q = 0; q < s; ++q) {
-                if (q == j) continue;
-                ++total;
-                if (proj_dominates(x, ld, d, cand[q], cand[j], g)) { g_exit[j] = g; break; }
-            }
-        }
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+    for (int64_t j = 0; j < s; ++j) {
+        int64_t c = 0;
+        g_exit[j] = g_exit_of(x, ld, d, cand, s, cand[j], g_max, &c);
+        total += c;
     }
-    for (int64_t j = 0; j < s; ++j)
-        if (g_exit[j] == 0) g_exit[j] = 1; /* t never exited the skyline */
     if (tests) *tests = total;
 }
 
-/* Per-tuple variant of the same search for a subset of the tuples: for targets[0..nt) (row
- * ids), the largest g in [2, g_max] at which some candidate's projection dominates the
- * target's projection, else 1. Lets full-size parity be checked on sampled tuples. */
+/* The same search for a subset of the tuples: targets[0..nt) (row ids) against the candidates
+ * (lets full-size parity be checked on sampled tuples). */
 void orc_gres_rows(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* cand,
                    int64_t s, const int64_t* targets, int64_t nt, int32_t g_max, int32_t* g_exit) {
     (void)n;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t j = 0; j < nt; ++j) {
-        int32_t found = 1;
-        for (int32_t g = g_max; g >= 2 && found == 1; --g)
-            for (int64_t q = 0; q < s; ++q)
-                if (cand[q] != targets[j] && proj_dominates(x, ld, d, cand[q], targets[j], g)) {
-                    found = g;
-                    break;
-                }
-        g_exit[j] = found;
+        int64_t c = 0;
+        g_exit[j] = g_exit_of(x, ld, d, cand, s, targets[j], g_max, &c);
     }
 }
 

@@ -379,6 +379,57 @@ def test_two_phase_equals_skyline(orc, kind, d):
         assert (final == want).all(), name
 
 
+def _partition_ids(orc, x, scheme, target):
+    """(ids, pruned-cell flags or None) of the oracle's Grid / Angular / Sliced partitioning."""
+    d = x.shape[1]
+    if scheme == "grid":
+        m, p = orc.grid_p(target, d)
+        part = orc.grid_part(x, m)
+        ne = np.zeros(p, np.uint8)
+        ne[np.unique(part)] = 1
+        return part, orc.grid_pruned(ne, m, d).astype(np.uint8)
+    if scheme == "angular":
+        return orc.angular_part(x, orc.angular_p(target, d)[0])[0], None
+    return orc.sliced_part(x, target, d - 1), None
+
+
+@pytest.mark.parametrize("scheme,target", [("grid", 9), ("grid", 16), ("angular", 4),
+                                           ("angular", 9), ("sliced", 5), ("sliced", 12)])
+@pytest.mark.parametrize("kind,d", [("ties", 2), ("ties", 3), ("dyadic", 2), ("dyadic", 3)])
+def test_local_skylines_per_partition_brute(orc, scheme, target, kind, d):
+    """Sec. 3, phase 1: a local skyline is Def. 1 over the rows of ONE partition. Each partition
+    is checked on its own against the Python brute force of Def. 1 over just its rows; rows of
+    pruned Grid cells (Def. 3) are in no local skyline. Duplicated rows are added. At least one
+    partition must hold a row that its partition keeps although another partition dominates it
+    (so reading the local skyline as Sky(r) restricted to the partition fails here)."""
+    x = _rows(kind, 240, d, 17 * d + target)
+    x = np.concatenate([x, x[::7]])  # exact duplicates, in other positions
+    part, skip = _partition_ids(orc, x, scheme, target)
+    local = orc.local_skylines(x, part, skip)
+    glob = orc.skyline(x)
+    if scheme == "grid":
+        assert skip[np.unique(part)].any(), "the data must put rows in a pruned cell"
+    differs = 0
+    for j in np.unique(part):
+        rows = np.flatnonzero(part == j)
+        if skip is not None and skip[j]:
+            assert not local[rows].any(), j
+            continue
+        want = brute.skyline_rows(x[rows])
+        assert np.array_equal(local[rows], want), (j, rows[local[rows] != want][:5])
+        differs += int((want & ~glob[rows]).any())
+    assert differs >= 1
+
+
+def test_local_skylines_ignore_other_partitions(orc):
+    """Hand-made: row 1 dominates row 0, but they lie in different partitions, so both are in
+    their local skylines; row 2 (same partition as row 0, dominated by it) is not."""
+    x = np.array([[0.5, 0.5], [0.25, 0.25], [0.75, 0.75]], np.float32)
+    part = np.array([0, 1, 0], np.int32)
+    assert orc.local_skylines(x, part).tolist() == [True, True, False]
+    assert orc.local_skylines(x, part, np.array([0, 1], np.uint8)).tolist() == [True, False, False]
+
+
 def test_count_invalid(orc):
     x = np.array([[0.0, 0.5], [-0.0, 0.999], [1.0, 0.2], [np.nan, 0.1], [0.3, -1e-30],
                   [np.inf, 0.0]], dtype=np.float32)
