@@ -335,7 +335,9 @@ sky_status gres_prepare(const float* x_soa, int64_t n, int32_t d, int64_t ld,
  * from for the result to be gres in that relation). targets == NULL means "every candidate"
  * (then nt must equal s and outputs are indexed like cand_idx, as in gres_compute); x may then
  * be NULL. g_exit[q], gres[q] (either may be NULL) refer to targets[q]. ws: device memory of
- * gres_search_bytes(nt, d) bytes. Requires s >= 1 when nt >= 1. Never synchronises; distinct
+ * gres_search_bytes(nt, d) bytes. Requires s >= 1 when nt >= 1; nt at most 2^30 - 2^20 (the row
+ * cap of a plan; gres_search_bytes returns 0 and gres_search SKY_ERR_INVALID_ARG above it; the
+ * targets may repeat rows, so nt is not bounded by n). Never synchronises; distinct
  * searches on distinct streams may run concurrently on one prepared set.
  */
 size_t gres_search_bytes(int64_t nt, int32_t d);

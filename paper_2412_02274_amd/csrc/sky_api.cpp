@@ -573,7 +573,9 @@ sky_status gres_prepare(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
 }
 
 size_t gres_search_bytes(int64_t nt, int32_t d) {
-    if (nt < 0 || nt > kMaxRows || !valid_d(d)) return 0;
+    // targets are indexed with 32-bit byte offsets inside each attribute column of the target
+    // copy, like the rows of a plan
+    if (nt < 0 || nt > kMaxBuildRows || !valid_d(d)) return 0;
     Carver c(nullptr, 0);
     GresTargets tg{};
     carve_gres_targets(c, tg, nt, d);
@@ -584,8 +586,8 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
                        const int64_t* targets, int64_t nt, int32_t g_max, int32_t* g_exit, float* gres,
                        void* ws, size_t ws_bytes, int32_t* dev_status, const sky_gres_opts* opts,
                        void* stream) {
-    if (!prep || s < 0 || s > kMaxBuildRows || !valid_d(d) || nt < 0 || g_max < 2 || g_max > SKY_MAX_G ||
-        !dev_status)
+    if (!prep || s < 0 || s > kMaxBuildRows || !valid_d(d) || nt < 0 || nt > kMaxBuildRows || g_max < 2 ||
+        g_max > SKY_MAX_G || !dev_status)
         return SKY_ERR_INVALID_ARG;
     if (!targets && nt != s) return SKY_ERR_INVALID_ARG;
     int32_t mapping = 0;

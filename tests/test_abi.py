@@ -138,6 +138,18 @@ def test_argument_errors_return_synchronously(lib):
                             None) == _lib.SKY_OK  # s = 0: nothing to do
 
 
+def test_gres_search_target_cap(lib):
+    # target values are addressed with 32-bit byte offsets per attribute column: the target
+    # count is capped like the rows of a plan (targets may repeat rows, so n does not bound it)
+    cap = (1 << 30) - (1 << 20)
+    assert lib.gres_search_bytes(cap, 6) > 0
+    assert lib.gres_search_bytes(cap + 1, 6) == 0
+    assert lib.gres_search_bytes(1 << 30, 1) == 0
+    fake = C.c_void_p(0x1000)  # never dereferenced: the size check comes first
+    assert lib.gres_search(fake, 10, 2, fake, 10, 10, fake, cap + 1, 25, fake, fake, fake, 1 << 40,
+                           fake, None, None) == _lib.SKY_ERR_INVALID_ARG
+
+
 def test_sliced_workspace_holds_partition_histogram(lib):
     # Sliced partitions go through the same stable counting sort by partition as Grid/Angular,
     # so for equal p its workspace must hold the same histogram table (regression: it used to
