@@ -361,9 +361,6 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-SERVE_RELATIONS = [(n, d) for n in (20_000, 130_000, 2_000_000) for d in (5, 6, 7)]
-
-
 def bench_serve(args):
     """Serving workload: 9 resident tie-heavy relations (N in {20k, 130k, 2M} x d in {5, 6, 7},
     seeds 0..8); Poisson arrivals of gres queries (a relation, a random subset of its skyline,
@@ -375,7 +372,7 @@ def bench_serve(args):
                                             poisson_trace)
 
     dev = torch.device("cuda:0")
-    residents = [Resident(G.ties(n, d, i), dev) for i, (n, d) in enumerate(SERVE_RELATIONS)]
+    residents = [Resident(x, dev) for x in G.serve_relations()]
     srv = Server(residents, budget_bytes=args.budget_mb << 20, slots=args.slots, device=dev)
     warm = poisson_trace(residents, rate=args.rate, duration=2.0, seed=1, start=10_000_000)
     srv.run_trace(warm)
@@ -386,7 +383,7 @@ def bench_serve(args):
     sat = latency_stats(Server(residents, budget_bytes=args.budget_mb << 20, slots=args.slots,
                                device=dev).run_trace(burst))
     line = _base_line(args, st["tuples_per_s"], "skyline tuples' gres/s", st["mean_ms"], "f32",
-                      {"workload": "serve_ties", "relations": [f"{n}x{d}" for n, d in SERVE_RELATIONS],
+                      {"workload": "serve_ties", "relations": [f"{n}x{d}" for n, d, _ in G.SERVE_SPECS],
                        "rate_per_s": args.rate, "seconds": args.serve_seconds, "g_max": 25,
                        "budget_mb": args.budget_mb, "slots": args.slots})
     line["steps"] = st["requests"]

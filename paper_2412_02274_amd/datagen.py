@@ -74,6 +74,18 @@ def ties(n: int, d: int, seed: int, levels: int = 100, zipf_s: float = 1.1,
     return out
 
 
+# The served relations: tie-heavy data of N in {20k, 130k, 2M} rows x d in {5, 6, 7}
+# attributes, seeds 0..8 in that order (stand-ins for the paper's real datasets of about 130k x 6
+# and 2M x 7 rows, which are not available).
+SERVE_SPECS = [(n, d, i) for i, (n, d) in
+               enumerate((n, d) for n in (20_000, 130_000, 2_000_000) for d in (5, 6, 7))]
+
+
+def serve_relations():
+    """The nine served relations, as row-major float32 arrays, in SERVE_SPECS order."""
+    return [ties(n, d, seed) for n, d, seed in SERVE_SPECS]
+
+
 def dyadic(n: int, d: int, seed: int, bits: int = 12) -> np.ndarray:
     """Values k * 2**-bits, k uniform in [0, 2**bits)."""
     rng = np.random.default_rng(seed)

@@ -320,21 +320,34 @@ def test_config_uni_10k_d4_gmax_1e4(dev):
 
 
 def test_config_ant_1m_d6(dev):
-    """Plain method, anticorrelated: ANT 1,000,000 x 6, g_max = 25. The skyline is compared in
-    full (oracle SFS); gres on 1,500 sampled skyline tuples (oracle per-tuple search)."""
+    """Plain method, anticorrelated: ANT 1,000,000 x 6, g_max = 25, everything compared: the
+    skyline (oracle SFS), then g_exit and the bits of gres of all 44,336 skyline tuples (oracle
+    Def. 2 search), through gres_compute and through the plan's own sky_gres. The oracle's
+    g_exit histogram must also be the one recorded in tests/golden/workload_counts.json."""
+    from tests.golden.workloads import load_counts
     x = G.ant(1_000_000, 6, 0)
     _say("oracle sfs ...")
     want_mem, _ = oracle.skyline_sfs(x)
     want_sky = np.flatnonzero(want_mem)
-    xs, idx, _, _, info = run_skyline(dev, x, "none")
+    xs = api.ingest(torch.from_numpy(x).to(dev))
+    plan = api.build(xs, "none")
+    plan.local_skylines()
+    idx = plan.merge().clone()
+    ge_plan, gr_plan = plan.gres(25)
+    ge, gr = api.gres(xs, idx, 25)
+    idx = idx.cpu().numpy()
+    plan.close()
     assert len(idx) == len(want_sky) and (idx == want_sky).all()
-    ge, gr = api.gres(xs, torch.from_numpy(idx).to(dev), 25)
-    ge = ge.cpu().numpy()
-    rng = np.random.default_rng(0)
-    pick = np.sort(rng.choice(len(idx), 1500, replace=False))
-    want_ge = oracle.gres_rows(x, want_sky, want_sky[pick], 25)
-    assert (ge[pick] == want_ge).all()
-    assert ((ge == 1) | ((ge >= 2) & (ge <= 25))).all()
+    _say("oracle gres of", len(want_sky), "tuples ...")
+    want_ge, _ = oracle.gres(x, want_sky, 25)
+    rec = load_counts()["ant_1m_d6"]["g_exit_hist"]
+    assert np.bincount(want_ge, minlength=26).tolist() == rec
+    want_bits = oracle.gres_values(want_ge).view(np.uint32)
+    for g_exit, g_val in ((ge, gr), (ge_plan, gr_plan)):
+        g_exit = g_exit.cpu().numpy()
+        bad = np.flatnonzero(g_exit != want_ge)
+        assert len(bad) == 0, (len(bad), bad[:10], g_exit[bad[:10]], want_ge[bad[:10]])
+        assert np.array_equal(g_val.cpu().numpy().view(np.uint32), want_bits)
 
 
 @pytest.mark.parametrize("scheme", ["grid", "angular", "sliced"])

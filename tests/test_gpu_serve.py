@@ -94,3 +94,60 @@ def test_fifo_admission_under_budget(dev, residents):
         assert len({rel[x] for x in qids}) == 1
         admitted.update(qids)
     assert srv.peak_used <= largest
+
+
+# ------------------------------------------- the served workload itself: its nine relations
+
+@pytest.fixture(scope="module")
+def spec_relations():
+    _say("generating the nine served relations ...")
+    return G.serve_relations()
+
+
+@pytest.fixture(scope="module")
+def spec_residents(dev, spec_relations):
+    return [Resident(x, dev) for x in spec_relations]
+
+
+@pytest.fixture(scope="module")
+def spec_oracle(spec_relations):
+    """Per relation: the oracle's skyline (SFS) and the g_exit of every skyline tuple (Def. 2
+    search, g_max 25)."""
+    out = []
+    for (n, d, seed), x in zip(G.SERVE_SPECS, spec_relations):
+        mem, _ = oracle.skyline_sfs(x)
+        sky = np.flatnonzero(mem)
+        ge, _ = oracle.gres(x, sky, 25)
+        _say(f"oracle ties {n}x{d} seed {seed}: |Sky| = {len(sky)}")
+        out.append((sky, ge))
+    return out
+
+
+def test_served_relations_skylines_and_gres_match_oracle(dev, spec_residents, spec_oracle):
+    """Each of the nine tie-heavy relations (N in {20k, 130k, 2M} x d in {5, 6, 7}): the resident
+    skyline and the gres of every skyline tuple of its prepared candidates equal the oracle's,
+    g_exit and gres bits."""
+    for (n, d, seed), r, (sky, want) in zip(G.SERVE_SPECS, spec_residents, spec_oracle):
+        assert np.array_equal(r.sky_host, sky), (n, d)
+        ge, gr = r.prep.search(None, 25)
+        assert np.array_equal(ge.cpu().numpy(), want), (n, d)
+        assert np.array_equal(gr.cpu().numpy().view(np.uint32),
+                              oracle.gres_values(want).view(np.uint32)), (n, d)
+
+
+def test_served_queries_match_oracle(dev, spec_residents, spec_oracle):
+    """Queries of the served workload (Poisson arrivals, a relation, a random subset of its
+    skyline) through continuous batching under a tight budget: every answer equals the oracle's
+    g_exit of those tuples in their relation (a tuple's gres does not depend on which other
+    tuples a query names)."""
+    largest = max(sum(-(-p // 256) * 256 for p in _query_bytes(r.s, r.d)[1]) for r in spec_residents)
+    trace = poisson_trace(spec_residents, rate=5000.0, duration=0.1, seed=3)
+    srv = Server(spec_residents, budget_bytes=2 * largest, slots=4, device=dev)
+    done = srv.run_trace(trace)
+    assert len(done) == len(trace) > 100
+    assert srv.max_in_flight >= 2
+    for q in done:
+        sky, want = spec_oracle[q.rel]
+        pos = np.searchsorted(sky, q.targets)
+        assert np.array_equal(sky[pos], q.targets)
+        assert np.array_equal(q.g_exit, want[pos]), q.qid
