@@ -73,6 +73,8 @@ typedef enum sky_scheme {
                                   at which (float)g is exact, as the key contract needs */
 #define SKY_HOST_SCRATCH_BYTES 256 /* size of the optional pinned host scratch of a plan */
 #define SKY_MAX_REPS 1024      /* largest sky_params.reps */
+#define SKY_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB: the fixed device workspace of
+                                              gres_compute_noalloc, per device */
 
 /* gres_compute mapping choice (sky_gres_opts.mapping). */
 #define SKY_GRES_AUTO 0         /* pick by shape */
@@ -272,6 +274,26 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld,
                         const int64_t* sky_idx, int64_t s, int32_t g_max, int32_t* g_exit,
                         float* gres, void* ws, size_t ws_bytes, int32_t* dev_status,
                         const sky_gres_opts* opts, void* stream);
+
+/*
+ * gres_compute_noalloc -- gres_compute without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops, harnesses that forbid
+ * allocation). Same arguments, results and errors as gres_compute, minus ws / ws_bytes: the
+ * workspace is a fixed array of SKY_NOALLOC_SCRATCH_BYTES bytes inside this library, one per
+ * device, held from the library's first use on that device until the process ends. Calls whose
+ * gres_workspace_bytes(s, d, g_max) exceeds it return SKY_ERR_UNSUPPORTED (with no work queued);
+ * at d = 6 that is about 700,000 tuples. The array of the CURRENT device is used, so `stream`
+ * must belong to the current device. Every call on one device shares its array and leaves its
+ * contents behind (the call itself depends on none of them): calls that overlap on one device,
+ * on different streams or from different threads, race and give undefined results -- queue
+ * them on one stream. The first call on a device looks up the array's address (a host-side
+ * runtime query, no device work); the calls never allocate or free memory and never
+ * synchronise.
+ */
+sky_status gres_compute_noalloc(const float* x_soa, int64_t n, int32_t d, int64_t ld,
+                                const int64_t* sky_idx, int64_t s, int32_t g_max, int32_t* g_exit,
+                                float* gres, int32_t* dev_status, const sky_gres_opts* opts,
+                                void* stream);
 
 /*
  * sky_gres -- gres_compute for the plan's own skyline, after sky_merge: the candidates and the

@@ -32,6 +32,7 @@ SKY_MAX_CELLS = 4096
 SKY_MAX_G = 16777216
 SKY_HOST_SCRATCH_BYTES = 256
 SKY_MAX_REPS = 1024
+SKY_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every function the header declares (checked against the header by the tests)
 EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspace_bytes",
@@ -42,7 +43,8 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "gres_search_bytes", "gres_search",
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
            "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
-           "sky_plan_set_host_scratch", "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres")
+           "sky_plan_set_host_scratch", "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres",
+           "gres_compute_noalloc")
 
 
 class SkyParams(C.Structure):
@@ -130,6 +132,8 @@ def load():
         "gres_gbar_workspace_bytes": (sz, [i64]),
         "gres_gbar": (i32, [vp, i64, i32, i64, vp, vp, vp, sz, vp, vp]),
         "sky_gres": (i32, [vp, i32, vp, vp, vp, sz, vp, C.POINTER(GresOpts), vp]),
+        "gres_compute_noalloc": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, vp, vp,
+                                       C.POINTER(GresOpts), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

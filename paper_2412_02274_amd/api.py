@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import SkyError
 
 __all__ = ["ingest", "build", "Plan", "Pipeline", "PreparedCandidates", "gres", "skyline",
-           "project", "gres_literal",
+           "project", "gres_literal", "gres_noalloc",
            "gres_workspace_bytes",
            "build_workspace_bytes", "check_status", "SkyError"]
 
@@ -236,6 +236,33 @@ def gres(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, mapping="a
     if status is None:
         torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
         check_status(st, "gres_compute")
+    return g_exit, gres_out
+
+
+def gres_noalloc(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, mapping="auto",
+                 status: torch.Tensor | None = None, stream=None,
+                 g_exit: torch.Tensor | None = None, gres_out: torch.Tensor | None = None):
+    """gres_compute_noalloc: gres_compute with the library's fixed per-device workspace (no
+    workspace tensor); (g_exit int32[s], gres float32[s]) for the rows sky_idx of x_soa."""
+    lib = _lib.load()
+    d, n = x_soa.shape
+    s = sky_idx.numel()
+    dev = x_soa.device
+    if sky_idx.dtype != torch.int64:
+        raise ValueError("sky_idx must be int64")
+    sky_idx = sky_idx.contiguous()
+    if g_exit is None:
+        g_exit = torch.empty(s, dtype=torch.int32, device=dev)
+    if gres_out is None:
+        gres_out = torch.empty(s, dtype=torch.float32, device=dev)
+    st = status if status is not None else new_status(dev)
+    opts = _lib.GresOpts(_lib.MAPPINGS[mapping] if isinstance(mapping, str) else int(mapping))
+    _lib.check(lib.gres_compute_noalloc(_ptr(x_soa), n, d, x_soa.stride(0), _ptr(sky_idx), s, g_max,
+                                        _ptr(g_exit), _ptr(gres_out), _ptr(st), C.byref(opts),
+                                        _stream_ptr(stream)), "gres_compute_noalloc")
+    if status is None:
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+        check_status(st, "gres_compute_noalloc")
     return g_exit, gres_out
 
 

@@ -150,6 +150,31 @@ def test_gres_search_target_cap(lib):
                            fake, None, None) == _lib.SKY_ERR_INVALID_ARG
 
 
+def test_gres_noalloc_limits(lib):
+    # the allocation-free gres_compute refuses work beyond its fixed workspace before any
+    # device call, and checks its arguments like gres_compute
+    fake = C.c_void_p(0x1000)  # never dereferenced: the checks come first
+    assert _lib.SKY_NOALLOC_SCRATCH_BYTES == 64 << 20
+    s_fit, s_over = 1, 1
+    while lib.gres_workspace_bytes(s_over, 6, 25) <= _lib.SKY_NOALLOC_SCRATCH_BYTES:
+        s_fit, s_over = s_over, s_over * 2
+    while s_over - s_fit > 1:
+        mid = (s_fit + s_over) // 2
+        if lib.gres_workspace_bytes(mid, 6, 25) <= _lib.SKY_NOALLOC_SCRATCH_BYTES:
+            s_fit = mid
+        else:
+            s_over = mid
+    assert s_fit > 500_000  # the documented order of magnitude at d = 6
+    assert lib.gres_compute_noalloc(fake, s_over, 6, s_over, fake, s_over, 25, fake, fake, fake,
+                                    None, None) == _lib.SKY_ERR_UNSUPPORTED
+    assert lib.gres_compute_noalloc(fake, 10, 6, 10, fake, 10, 1, fake, fake, fake, None,
+                                    None) == _lib.SKY_ERR_INVALID_ARG  # g_max < 2
+    assert lib.gres_compute_noalloc(fake, 10, 0, 10, fake, 10, 25, fake, fake, fake, None,
+                                    None) == _lib.SKY_ERR_INVALID_ARG  # d < 1
+    assert lib.gres_compute_noalloc(fake, 10, 6, 10, fake, 10, 25, fake, fake, None, None,
+                                    None) == _lib.SKY_ERR_INVALID_ARG  # no status word
+
+
 def test_sliced_workspace_holds_partition_histogram(lib):
     # Sliced partitions go through the same stable counting sort by partition as Grid/Angular,
     # so for equal p its workspace must hold the same histogram table (regression: it used to
