@@ -146,8 +146,9 @@ def main():
     pipe = api.Pipeline(n, d, args.scheme, args.p, 0, g_max, args.mapping, dev)
     for _ in range(args.warmup):
         pipe.run(xr)
+    pipe.result()
     # kernel-level events for every timed step: dominance-test launches and the gres search
-    max_pairs = 256
+    max_pairs = 64
     pool = HipEvents(args.steps * (2 * max_pairs + 2))
     per_step = []
     for k in range(args.steps):
@@ -158,32 +159,48 @@ def main():
         per_step.append((tb, te, gb, ge_))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    used = []
     for k in range(args.steps):
         tb, te, gb, ge_ = per_step[k]
-        sky, ge, gr = pipe.run(xr, check=False, test_events=(tb, te), gres_events=(gb, ge_))
-        used.append(pipe.last_info["events_used"])
+        pipe.run(xr, test_events=(tb, te), gres_events=(gb, ge_))
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    api.check_status(pipe.status, "pipeline")
-    test_ms = sum(sum(pool.elapsed_ms(per_step[k][0][i], per_step[k][1][i]) for i in range(used[k]))
+    dt_eager = (time.perf_counter() - t0) / args.steps
+    sky, ge, gr = pipe.result()
+    used = pipe.info()["events_used"]  # the same launch sequence every pass
+    test_ms = sum(sum(pool.elapsed_ms(per_step[k][0][i], per_step[k][1][i]) for i in range(used))
                   for k in range(args.steps)) / args.steps
     gres_ms = sum(pool.elapsed_ms(per_step[k][2], per_step[k][3]) for k in range(args.steps)) / args.steps
-    launches = sum(used) / args.steps
+    launches = used
     s = int(sky.numel())
     if s != counts["sky_size"]:
         raise SystemExit(f"skyline size {s} differs from the oracle's {counts['sky_size']}")
+    hist = np.bincount(ge.cpu().numpy(), minlength=g_max + 1).tolist()  # index = g_exit
+    if counts.get("g_exit_hist") is not None and hist != counts["g_exit_hist"]:
+        raise SystemExit("g_exit histogram differs from the oracle's")
+    # the same pass captured once in a HIP graph and replayed (no host work per step)
+    graph = pipe.capture(xr)
+    graph.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt_graph = (time.perf_counter() - t1) / args.steps
+    sky_g, ge_g, _ = pipe.result()
+    if not (torch.equal(sky_g, sky) and torch.equal(ge_g, ge)):
+        raise SystemExit("graph replay differs from the eager pass")
+    del graph
+    dt = min(dt_eager, dt_graph)
     # per-phase breakdown (one more, separately timed run)
     gres_counter = torch.zeros(1, dtype=torch.int64, device=dev)
     pipe.run(xr, timing=True, gres_counter=gres_counter)
     phases = pipe.phase_ms()
     gres_executed = int(gres_counter.item())
-    info = pipe.last_info
+    info = pipe.info()
     tests = counts["sfs_tests"] + counts["gres_tests"]
     executed = info["tests_local"] + info["tests_merge"]
     ops_per_test = 2 * d  # the kernel's one <= and one < comparison per attribute (Def. 1)
     test_tops = executed * ops_per_test / (test_ms * 1e-3) / 1e12
-    # rooflines: algorithmic work per launch over the kernel's average HIP-event launch time.
+    # rooflines: algorithmic work per launch over the kernel's average launch time.
     # Dominance tests: oracle-order SFS test count x d element compares; gres search: Alg. 1's
     # per-tuple descending-scan test count x d key compares. Reported for both kernels; the
     # `roofline` field is the one of the kernel that takes the most time per step.
@@ -240,6 +257,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt * 1e3,
+        "ms_per_step_eager": dt_eager * 1e3,
+        "ms_per_step_graph": dt_graph * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -247,7 +266,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "generator": kind, "n": n, "d": d, "seed": seed,
                    "g_max": g_max, "scheme": args.scheme,
-                   "target_p": args.p if args.scheme != "none" else 1},
+                   "target_p": args.p if args.scheme != "none" else 1,
+                   "launch": "hip_graph" if dt_graph <= dt_eager else "stream"},
         "sky_size": s,
         "gres_tuples_per_s": s / dt,
         "algorithmic_tests": {"skyline_sfs": counts["sfs_tests"], "gres_alg1": counts["gres_tests"]},

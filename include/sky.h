@@ -30,10 +30,13 @@
  *     to the device word *dev_status (first error wins; the caller zeroes it beforehand and
  *     reads it after synchronising the stream). Outputs are defined only when both are SKY_OK.
  *   - Work is queued on `stream` (a hipStream_t passed as void*; NULL = the null stream).
- *     sky_local_skylines, sky_merge, sky_batch_create, sky_batch_skylines and sky_batch_tune
- *     read small counters back or copy small host tables (they synchronise `stream`);
- *     sky_ingest, sky_build, gres_compute, gres_prepare, gres_search and sky_batch_gres never
- *     synchronise.
+ *     The calls of the plain path -- sky_ingest, sky_build, sky_local_skylines, sky_merge,
+ *     sky_gres, gres_compute, gres_prepare, gres_search -- never synchronise and never read
+ *     anything back: every count they need stays on the device and every launch is sized by a
+ *     bound known when the call is made, so a whole pass can be captured in a HIP graph and
+ *     replayed. The inspection call sky_plan_info, and
+ *     sky_batch_create, sky_batch_skylines and sky_batch_tune, read back or copy small host
+ *     tables and synchronise.
  *   - Thread safety: plans and batches are independent; one must not be used by two threads
  *     at once.
  *     No global mutable state.
@@ -71,7 +74,6 @@ typedef enum sky_scheme {
 #define SKY_MAX_CELLS 4096     /* partitions of any scheme (Grid m^d, Angular m^(d-1), Sliced p) */
 #define SKY_MAX_G 16777216     /* largest g_max accepted by gres_compute: 2^24, the largest level
                                   at which (float)g is exact, as the key contract needs */
-#define SKY_HOST_SCRATCH_BYTES 256 /* size of the optional pinned host scratch of a plan */
 #define SKY_MAX_REPS 1024      /* largest sky_params.reps */
 #define SKY_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB: the fixed device workspace of
                                               gres_compute_noalloc, per device */
@@ -173,8 +175,9 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld,
 /*
  * sky_local_skylines -- Sec. 3, phase 1: the skyline of every partition, all partitions at
  * once. Rows of Grid cells pruned by grid dominance take no part. The result stays in the
- * plan's workspace. Synchronises `stream` between filter rounds. SKY_ERR_STATE unless the
- * plan is freshly built.
+ * plan's workspace. Queues a fixed number of filter rounds, chosen from n alone; rounds that
+ * find no live row do no work. Never synchronises. SKY_ERR_STATE unless the plan is freshly
+ * built.
  */
 sky_status sky_local_skylines(sky_plan* plan, void* stream);
 
@@ -184,7 +187,8 @@ sky_status sky_local_skylines(sky_plan* plan, void* stream);
  * int64[cap]), the count to *dev_count (device int64), and, if member is non-null, member[i]
  * = 1 iff row i is in Sky(r) (device uint8[n]). If count > cap, SKY_ERR_CAPACITY goes to
  * *dev_status, *dev_count holds the required size and sky_idx is left undefined.
- * SKY_ERR_STATE unless sky_local_skylines has run on the plan.
+ * cap = 0 (sky_idx may then be null) only counts. Never synchronises. SKY_ERR_STATE unless
+ * sky_local_skylines has run on the plan.
  */
 sky_status sky_merge(sky_plan* plan, int64_t* sky_idx, int64_t cap, int64_t* dev_count,
                      uint8_t* member, void* stream);
@@ -222,19 +226,13 @@ sky_status sky_plan_partition_tests(const sky_plan* plan, int64_t* tests, void* 
 sky_status sky_plan_set_events(sky_plan* plan, void* const* ev_begin, void* const* ev_end,
                                int32_t cap);
 
-/* Plan inspection (host-side copy of the counters listed in sky_info). */
-sky_status sky_plan_info(const sky_plan* plan, sky_info* out);
-
 /*
- * sky_plan_set_host_scratch -- optional: pinned host memory (hipHostMalloc, or a torch tensor
- * with pin_memory=True) of at least SKY_HOST_SCRATCH_BYTES bytes, owned by the caller and kept
- * alive until the plan is destroyed or the scratch is replaced (NULL removes it). With it,
- * sky_local_skylines and sky_merge launch each skyline round before waiting for the previous
- * round's counters (copied into this memory asynchronously), so the device does not idle while
- * the host decides; without it they synchronise after every round. Results are the same either
- * way. Creates two HIP events owned by the plan.
+ * Plan inspection: the counters listed in sky_info. Those the device computes (partition
+ * statistics, rounds, counts, tests) are copied back on the stream of the plan's last call
+ * that queued work, which this call waits for: do not call it while that stream is being
+ * captured into a graph. Fields of a phase that has not run are 0.
  */
-sky_status sky_plan_set_host_scratch(sky_plan* plan, void* host_pinned, size_t bytes);
+sky_status sky_plan_info(const sky_plan* plan, sky_info* out);
 
 /* Releases a plan (host memory and its events). Null is accepted. */
 void sky_plan_destroy(sky_plan* plan);
@@ -298,10 +296,13 @@ sky_status gres_compute_noalloc(const float* x_soa, int64_t n, int32_t d, int64_
 /*
  * sky_gres -- gres_compute for the plan's own skyline, after sky_merge: the candidates and the
  * tuples are Sky(r) as sky_merge returned it, and g_exit[j] / gres[j] (device arrays of
- * info.sky_count entries, either may be null) refer to sky_idx[j] of that call. The result is
- * the one gres_compute gives for (x, sky_idx, info.sky_count, g_max), but the candidates are
- * read from the plan's partition-contiguous copy in its curve order, so no sort is needed.
- * ws: at least gres_workspace_bytes(info.sky_count, d, g_max) bytes (device, caller-owned).
+ * min(count, cap) entries, cap being sky_merge's; either may be null) refer to sky_idx[j] of
+ * that call. The result is the one gres_compute gives for (x, sky_idx, count, g_max), but the
+ * candidates are read from the plan's partition-contiguous copy in its curve order, so no sort
+ * is needed. The skyline size is read on the device: ws must hold at least
+ * gres_workspace_bytes(c, d, g_max) bytes with c = max(1, min(cap, n)) (device,
+ * caller-owned); a skyline larger than cap raises SKY_ERR_CAPACITY in *dev_status. The mapping
+ * (SKY_GRES_AUTO included) and the work split are chosen on the device from the real size.
  * g_max in [2, SKY_MAX_G]; opts as for gres_compute. SKY_ERR_STATE before sky_merge. The
  * plan's skyline state is read, not changed (calls may repeat). Never synchronises.
  */

@@ -30,7 +30,6 @@ MAPPINGS = {"auto": SKY_GRES_AUTO, "tiles": SKY_GRES_TILES, "levels": SKY_GRES_L
 SKY_MAX_D = 16
 SKY_MAX_CELLS = 4096
 SKY_MAX_G = 16777216
-SKY_HOST_SCRATCH_BYTES = 256
 SKY_MAX_REPS = 1024
 SKY_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -43,7 +42,7 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "gres_search_bytes", "gres_search",
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
            "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
-           "sky_plan_set_host_scratch", "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres",
+           "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres",
            "gres_compute_noalloc")
 
 
@@ -128,7 +127,6 @@ def load():
         "sky_batch_info": (i32, [vp, C.POINTER(SkyInfo)]),
         "sky_batch_destroy": (None, [vp]),
         "sky_project": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, i64, vp, vp]),
-        "sky_plan_set_host_scratch": (i32, [vp, vp, sz]),
         "gres_gbar_workspace_bytes": (sz, [i64]),
         "gres_gbar": (i32, [vp, i64, i32, i64, vp, vp, vp, sz, vp, vp]),
         "sky_gres": (i32, [vp, i32, vp, vp, vp, sz, vp, C.POINTER(GresOpts), vp]),

@@ -85,6 +85,7 @@ class Plan:
         self.stream = stream
         self.sky_idx = None
         self.count = None
+        self.cap = 0
 
     def local_skylines(self):
         _lib.check(_lib.load().sky_local_skylines(self._h, _stream_ptr(self.stream)),
@@ -92,9 +93,12 @@ class Plan:
         return self
 
     def merge(self, member: bool = False, cap: int | None = None):
+        """sky_merge, then the count is read back: the skyline's rows (ascending), and with
+        member=True also the uint8[n] membership flags."""
         lib = _lib.load()
         n = self.x_soa.shape[1]
         cap = n if cap is None else cap
+        self.cap = cap
         dev = self.x_soa.device
         self.sky_idx = torch.empty(max(cap, 1), dtype=torch.int64, device=dev)
         self.count = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -113,7 +117,9 @@ class Plan:
         inf = self.info()
         s, d = int(inf["sky_count"]), self.x_soa.shape[0]
         dev = self.x_soa.device
-        need = int(lib.gres_workspace_bytes(s, d, g_max))
+        # sky_gres reads the skyline size on the device; its workspace holds sky_merge's cap
+        c = max(1, min(self.cap, self.x_soa.shape[1]))
+        need = int(lib.gres_workspace_bytes(c, d, g_max))
         if need == 0:
             raise SkyError(_lib.SKY_ERR_INVALID_ARG, "gres_workspace_bytes")
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -170,11 +176,9 @@ class Plan:
 
 def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0,
           status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
-          host_scratch: torch.Tensor | None = None, reps: int = 0) -> Plan:
-    """Partition assignment + partition-contiguous copy (sky_build). host_scratch: optional
-    pinned host tensor (>= SKY_HOST_SCRATCH_BYTES) that lets the skyline rounds run one ahead of
-    their readback (sky_plan_set_host_scratch). reps: Representative Filtering (Sec. 3.1), the
-    number of representatives (0 = off)."""
+          reps: int = 0) -> Plan:
+    """Partition assignment + partition-contiguous copy (sky_build). reps: Representative
+    Filtering (Sec. 3.1), the number of representatives (0 = off)."""
     lib = _lib.load()
     if x_soa.dtype != torch.float32 or x_soa.dim() != 2 or not x_soa.is_cuda:
         raise ValueError("x_soa must be a float32 [d, N] CUDA tensor")
@@ -192,16 +196,7 @@ def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int
     h = C.c_void_p()
     _lib.check(lib.sky_build(_ptr(x_soa), n, d, ld, C.byref(prm), _ptr(ws), need, _ptr(st),
                              _stream_ptr(stream), C.byref(h)), "sky_build")
-    plan = Plan(h, ws, st, x_soa, stream)
-    if host_scratch is not None:
-        if not host_scratch.is_pinned() or host_scratch.numel() * host_scratch.element_size() < \
-                _lib.SKY_HOST_SCRATCH_BYTES:
-            raise ValueError("host_scratch must be pinned and hold SKY_HOST_SCRATCH_BYTES bytes")
-        plan._scratch = host_scratch
-        _lib.check(lib.sky_plan_set_host_scratch(h, host_scratch.data_ptr(),
-                                                 _lib.SKY_HOST_SCRATCH_BYTES),
-                   "sky_plan_set_host_scratch")
-    return plan
+    return Plan(h, ws, st, x_soa, stream)
 
 
 def gres_workspace_bytes(s: int, d: int, g_max: int) -> int:
@@ -420,9 +415,10 @@ class Pipeline:
 
         ingest (validate, SoA) -> build (partitions) -> local skylines -> merge -> gres
 
-    ``run(x_rows)`` executes one pass on torch's current stream and returns
-    ``(sky_idx, g_exit, gres)`` views (valid until the next run). The plan is rebuilt on every
-    run (host-side struct only)."""
+    ``run(x_rows)`` queues one pass on torch's current stream and returns without waiting: no
+    call of the pass reads anything back, so a pass can also be captured in a HIP graph
+    (``capture``) and replayed. ``result()`` waits and returns ``(sky_idx, g_exit, gres)`` views
+    of the last pass (valid until the next one); ``info()`` its plan counters."""
 
     def __init__(self, n: int, d: int, scheme="none", target_p: int = 16, slice_dim: int = 0,
                  g_max: int = 25, mapping="auto", device="cuda", reps: int = 0):
@@ -439,28 +435,33 @@ class Pipeline:
         if self.build_bytes == 0:
             raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_build_workspace_bytes")
         self.build_ws = torch.empty(self.build_bytes, dtype=torch.uint8, device=dev)
-        self.gres_bytes = int(lib.gres_workspace_bytes(n, d, g_max))  # worst case s = n
+        self.gres_bytes = int(lib.gres_workspace_bytes(n, d, g_max))  # any skyline size up to n
         self.gres_ws = torch.empty(self.gres_bytes, dtype=torch.uint8, device=dev)
         self.sky_buf = torch.empty(n, dtype=torch.int64, device=dev)
         self.count = torch.zeros(1, dtype=torch.int64, device=dev)
         self.g_exit = torch.empty(n, dtype=torch.int32, device=dev)
         self.gres_v = torch.empty(n, dtype=torch.float32, device=dev)
-        self.last_info = None
         self.events = None
-        # pinned host memory for reading skyline-round counters back without stalling the device
-        self.host_scratch = torch.zeros(_lib.SKY_HOST_SCRATCH_BYTES // 4, dtype=torch.int32,
-                                        pin_memory=True)
+        self._h = None
+        self._ev_keep = None
 
-    def run(self, x_rows: torch.Tensor, check: bool = True, timing: bool = False,
-            test_events=None, gres_events=None, gres_counter: torch.Tensor | None = None):
-        """test_events: optional (begin[], end[]) lists of hipEvent_t handles recorded around the
-        dominance-test launches; gres_events: optional (begin, end) around the gres search;
-        gres_counter: optional int64 device tensor to which the gres search adds the candidate
-        tests it evaluates."""
+    def _close_plan(self):
+        if self._h is not None:
+            _lib.load().sky_plan_destroy(self._h)
+            self._h = None
+
+    def run(self, x_rows: torch.Tensor, timing: bool = False, test_events=None, gres_events=None,
+            gres_counter: torch.Tensor | None = None, stream=None):
+        """Queue one pass. test_events: optional (begin[], end[]) lists of hipEvent_t handles
+        recorded around the dominance-test launches; gres_events: optional (begin, end) around
+        the gres search; gres_counter: optional int64 device tensor to which the gres search
+        adds the candidate tests it evaluates; timing: torch events between the phases
+        (``phase_ms``)."""
         lib = _lib.load()
-        st = torch.cuda.current_stream()
+        st = stream if stream is not None else torch.cuda.current_stream()
         sp = C.c_void_p(st.cuda_stream)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)] if timing else None
+        self._close_plan()
         self.status.zero_()
         if ev:
             ev[0].record(st)
@@ -473,48 +474,60 @@ class Pipeline:
         _lib.check(lib.sky_build(_ptr(self.x_soa), self.n, self.d, self.n, C.byref(prm),
                                  _ptr(self.build_ws), self.build_bytes, _ptr(self.status), sp,
                                  C.byref(h)), "sky_build")
-        try:
-            _lib.check(lib.sky_plan_set_host_scratch(h, self.host_scratch.data_ptr(),
-                                                     _lib.SKY_HOST_SCRATCH_BYTES),
-                       "sky_plan_set_host_scratch")
-            if test_events is not None:
-                nb = len(test_events[0])
-                arr_b = (C.c_void_p * nb)(*test_events[0])
-                arr_e = (C.c_void_p * nb)(*test_events[1])
-                self._ev_keep = (arr_b, arr_e)
-                _lib.check(lib.sky_plan_set_events(h, arr_b, arr_e, nb), "sky_plan_set_events")
-            if ev:
-                ev[2].record(st)
-            _lib.check(lib.sky_local_skylines(h, sp), "sky_local_skylines")
-            if ev:
-                ev[3].record(st)
-            _lib.check(lib.sky_merge(h, _ptr(self.sky_buf), self.n, _ptr(self.count), None, sp),
-                       "sky_merge")
-            if ev:
-                ev[4].record(st)
-            # the skyline size is known on the host once the engine's last round has finished
-            inf = _lib.SkyInfo()
-            lib.sky_plan_info(h, C.byref(inf))
-            self.last_info = inf.as_dict()
-            s = int(inf.sky_count)
-            opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
-                                 else int(self.mapping))
-            if gres_events is not None:
-                opts.ev_begin, opts.ev_end = gres_events
-            if gres_counter is not None:
-                opts.dev_tests = gres_counter.data_ptr()
-            # gres of the plan's own skyline: candidates straight from the curve-ordered copy
-            _lib.check(lib.sky_gres(h, self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
-                                    _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),
-                                    C.byref(opts), sp), "sky_gres")
-        finally:
-            lib.sky_plan_destroy(h)
+        self._h = h
+        if test_events is not None:
+            nb = len(test_events[0])
+            arr_b = (C.c_void_p * nb)(*test_events[0])
+            arr_e = (C.c_void_p * nb)(*test_events[1])
+            self._ev_keep = (arr_b, arr_e)
+            _lib.check(lib.sky_plan_set_events(h, arr_b, arr_e, nb), "sky_plan_set_events")
+        if ev:
+            ev[2].record(st)
+        _lib.check(lib.sky_local_skylines(h, sp), "sky_local_skylines")
+        if ev:
+            ev[3].record(st)
+        _lib.check(lib.sky_merge(h, _ptr(self.sky_buf), self.n, _ptr(self.count), None, sp),
+                   "sky_merge")
+        if ev:
+            ev[4].record(st)
+        opts = _lib.GresOpts(_lib.MAPPINGS[self.mapping] if isinstance(self.mapping, str)
+                             else int(self.mapping))
+        if gres_events is not None:
+            opts.ev_begin, opts.ev_end = gres_events
+        if gres_counter is not None:
+            opts.dev_tests = gres_counter.data_ptr()
+        # gres of the plan's own skyline: candidates straight from the curve-ordered copy
+        _lib.check(lib.sky_gres(h, self.g_max, _ptr(self.g_exit), _ptr(self.gres_v),
+                                _ptr(self.gres_ws), self.gres_bytes, _ptr(self.status),
+                                C.byref(opts), sp), "sky_gres")
         if ev:
             ev[5].record(st)
             self.events = ev
+        return self
+
+    def capture(self, x_rows: torch.Tensor, stream=None):
+        """Capture one pass over x_rows (a tensor that stays allocated) in a CUDA/HIP graph;
+        graph.replay() then reruns the whole pass. The plan of the captured pass stays open."""
+        graph = torch.cuda.CUDAGraph()
+        side = stream if stream is not None else torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(graph, stream=side):
+            self.run(x_rows, stream=side)
+        torch.cuda.current_stream().wait_stream(side)
+        return graph
+
+    def result(self, check: bool = True):
+        """Waits for the last pass: (sky_idx, g_exit, gres) views, after the status check."""
+        s = int(self.count.item())  # synchronises
         if check:
             check_status(self.status, "pipeline")
         return self.sky_buf[:s], self.g_exit[:s], self.gres_v[:s]
+
+    def info(self) -> dict:
+        """The plan counters of the last pass (sky_plan_info; waits for it)."""
+        inf = _lib.SkyInfo()
+        _lib.check(_lib.load().sky_plan_info(self._h, C.byref(inf)), "sky_plan_info")
+        return inf.as_dict()
 
     def phase_ms(self):
         """Per-phase milliseconds of the last timed run: ingest, build, local, merge, gres."""
@@ -522,3 +535,12 @@ class Pipeline:
         ev[5].synchronize()
         names = ("ingest", "build", "local", "merge", "gres")
         return {names[i]: ev[i].elapsed_time(ev[i + 1]) for i in range(5)}
+
+    def close(self):
+        self._close_plan()
+
+    def __del__(self):
+        try:
+            self._close_plan()
+        except Exception:
+            pass

@@ -113,22 +113,22 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.hhi = c.take<uint32_t>((size_t)(d * e.tcap));
     e.seg_min = c.take<uint32_t>((size_t)p);
     e.seg_max = c.take<uint32_t>((size_t)p);
-    e.hist = c.take<int32_t>((size_t)p * kBins);
-    e.seg_info = c.take<int32_t>((size_t)p * 8);
+    e.hist = c.take<int32_t>((size_t)2 * p * kBins);
+    e.seg_info = c.take<int32_t>((size_t)2 * p * 8);
     e.dom = c.take<uint8_t>((size_t)n);
     e.tile_off = c.take<int32_t>((size_t)2 * (p + 1));
     e.counters = c.take<int32_t>(48);
     e.tests = c.take<unsigned long long>(3);
     e.work = c.take<int32_t>((size_t)kWorkCounters * kCounterStride);
-    e.scan = c.take<int32_t>((size_t)n);
+    e.scan = c.take<int32_t>((size_t)engine_scan_elems(n));
     e.scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(n));
     P->local_flag = c.take<uint8_t>((size_t)n);
     P->final_flag = c.take<uint8_t>((size_t)n);
     P->member_tmp = c.take<uint8_t>((size_t)n);
-    P->local_list = c.take<int32_t>((size_t)n);
     P->final_list = c.take<int32_t>((size_t)n);
     P->pos_tmp = c.take<int32_t>((size_t)n);
     P->count_tmp = c.take<int32_t>(64);
+    P->dinfo = c.take<int64_t>(kDinfo);
 }
 
 }  // namespace
@@ -159,19 +159,6 @@ sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int3
     P->x = x_soa; P->n = n; P->ld = ld; P->d = d;
     P->scheme = scheme; P->p = p; P->m = m; P->slice_dim = slice_dim;
     P->dev_status = dev_status;
-    if (P->scheme == SKY_ANGULAR) {
-        P->tan2_host = (double*)malloc(sizeof(double) * (size_t)(m + 1));
-        if (!P->tan2_host) { delete P; return SKY_ERR_INVALID_ARG; }
-        const double pi = 3.14159265358979323846;
-        for (int32_t k = 0; k <= m; ++k) {
-            double t = tan((double)k * pi / (2.0 * (double)m));
-            P->tan2_host[k] = t * t;
-        }
-        P->tan2_host[0] = 0.0;
-        hipError_t e = hipMemcpyAsync(P->tan2_dev, P->tan2_host, sizeof(double) * (size_t)(m + 1),
-                                      hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) { free(P->tan2_host); delete P; return SKY_ERR_HIP; }
-    }
     if (P->scheme == kSchemeSegments) {
         // the caller's host array may go away on return: wait for the copy
         hipError_t e1 = hipMemcpyAsync(P->seg_off_dev, seg_off_host, sizeof(int64_t) * (size_t)(p + 1),
@@ -192,7 +179,7 @@ sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int3
     a.xa = P->xa;
     a.dev_status = dev_status;
     sky_status s = launch_partition(a, st);
-    if (s != SKY_OK) { free(P->tan2_host); delete P; return s; }
+    if (s != SKY_OK) { delete P; return s; }
     P->state = 1;
     P->info.n = n; P->info.d = d; P->info.scheme = P->scheme; P->info.p = p; P->info.m = m;
     P->info.state = 1;
@@ -263,41 +250,19 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     if (!P) return SKY_ERR_INVALID_ARG;
     if (P->state != 1) return SKY_ERR_STATE;
     hipStream_t st = (hipStream_t)stream;
+    P->last_stream = st;
     const int32_t n = (int32_t)P->n;
-    // partition statistics (sizes, pruned Grid cells); one partition: known on the host
-    if (P->p == 1) {
-        P->info.pruned_cells = 0;
-        P->info.pruned_rows = 0;
-        P->info.max_partition = P->n;
-    } else {
-        int32_t* off = (int32_t*)malloc(sizeof(int32_t) * (size_t)(P->p + 1));
-        uint8_t* pr = (uint8_t*)malloc((size_t)P->p);
-        if (!off || !pr) { free(off); free(pr); return SKY_ERR_INVALID_ARG; }
-        hipError_t e1 = hipMemcpyAsync(off, P->part_off, sizeof(int32_t) * (size_t)(P->p + 1),
-                                       hipMemcpyDeviceToHost, st);
-        hipError_t e2 = hipMemcpyAsync(pr, P->pruned, (size_t)P->p, hipMemcpyDeviceToHost, st);
-        hipError_t e3 = hipStreamSynchronize(st);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) { free(off); free(pr); return SKY_ERR_HIP; }
-        int64_t prow = 0, maxp = 0;
-        int32_t pcells = 0;
-        for (int32_t j = 0; j < P->p; ++j) {
-            int64_t sz = off[j + 1] - off[j];
-            if (sz > maxp) maxp = sz;
-            if (pr[j] && sz > 0) { ++pcells; prow += sz; }
-        }
-        P->info.pruned_cells = pcells;
-        P->info.pruned_rows = prow;
-        P->info.max_partition = maxp;
-        free(off);
-        free(pr);
-    }
-    SKY_TRY(launch_fill_u8(P->local_flag, n, 0, st));
-    // the local phase's tests per partition (Sec. 4 counts its cost as the largest of them)
-    SKY_TRY(launch_fill_u8(reinterpret_cast<uint8_t*>(P->seg_tests),
-                           (int64_t)P->p * (int64_t)sizeof(unsigned long long), 0, st));
+    // partition statistics (pruned Grid cells and their rows, the largest partition)
+    SKY_TRY(launch_partition_stats(P->part_off, P->pruned, P->p, P->dinfo + D_PRUNED_CELLS, st));
+    // the local phase's tests per partition (Sec. 4 counts its cost as the largest of them):
+    // zeroed here when representatives add to them first, else by the engine run
+    // rows of Grid cells pruned by grid dominance take no part (Def. 3)
+    const uint8_t* skip = P->scheme == SKY_GRID && P->p > 1 ? P->pruned : nullptr;
     // Representative Filtering (Sec. 3.1): the rows the kept representatives dominate leave
     const uint8_t* keep = nullptr;
     if (P->reps > 0) {
+        SKY_TRY(launch_fill_u8(reinterpret_cast<uint8_t*>(P->seg_tests),
+                               (int64_t)P->p * (int64_t)sizeof(unsigned long long), 0, st));
         RepArgs ra{};
         ra.fsum = P->fsum; ra.rowid = P->rowid; ra.n = n; ra.d = P->d;
         ra.xp = P->xp; ra.ldp = P->ldp; ra.xa = P->xa; ra.rs = partition_row_stride(P->d);
@@ -305,49 +270,31 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
         ra.k0 = P->k0; ra.v0 = P->v0; ra.k1 = P->k1; ra.v1 = P->v1; ra.radix_tmp = P->radix_tmp;
         ra.kept = P->rep_kept; ra.nkept = P->rep_kept + SKY_MAX_REPS; ra.tests = P->rep_tests;
         ra.seg_of_pos = P->p > 1 ? P->seg : nullptr; ra.seg_tests = P->seg_tests;
-        ra.skip_seg = P->scheme == SKY_GRID && P->info.pruned_rows > 0 ? P->pruned : nullptr;
+        ra.skip_seg = skip;
         ra.keep = P->member_tmp;  // free until sky_merge
         SKY_TRY(launch_representatives(ra, st));
         keep = P->member_tmp;
     }
-    // the rows outside the pruned Grid cells (every row when none is pruned)
-    SKY_TRY(launch_iota_filtered(P->scheme == SKY_GRID && P->info.pruned_rows > 0 ? P->pruned : nullptr,
-                                 P->seg, n, P->eng.w1,
-                                 P->count_tmp, P->eng.scan_tmp, st, keep));
-    // live rows: every row outside the pruned Grid cells (exactly what the list holds), minus the
-    // rows the representatives removed (read back)
-    int32_t live = n - (int32_t)P->info.pruned_rows;
-    int64_t rep_tests = 0;
-    P->info.reps_kept = 0;
-    if (keep) {
-        int32_t cnt = 0, nk = 0;
-        unsigned long long rt = 0;
-        hipError_t e1 = hipMemcpyAsync(&cnt, P->count_tmp, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-        hipError_t e2 = hipMemcpyAsync(&nk, P->rep_kept + SKY_MAX_REPS, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-        hipError_t e3 = hipMemcpyAsync(&rt, P->rep_tests, sizeof(rt), hipMemcpyDeviceToHost, st);
-        hipError_t e4 = hipStreamSynchronize(st);
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) return SKY_ERR_HIP;
-        live = cnt;
-        P->info.reps_kept = nk;
-        rep_tests = (int64_t)rt;
-    }
+    // the first round's list: every position outside the pruned cells and not filtered out
+    int32_t* cnt = P->count_tmp + CT_LIST;
+    SKY_TRY(launch_iota_filtered(skip, P->seg, n, P->eng.w1, cnt, P->eng.scan_tmp, st, keep));
     EngineProblem pb{};
     pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
     pb.seg_of_pos = P->p > 1 ? P->seg : nullptr;
     pb.nseg = P->p;
     pb.seg_tests = P->seg_tests;
-    pb.items = P->eng.w1; pb.n_items = live;
+    pb.zero_seg_tests = P->reps == 0;
+    pb.items = P->eng.w1;
+    pb.n_items = n;
+    pb.n_items_dev = (skip || keep) ? cnt : nullptr;
+    pb.ub_items = n;
     pb.flag_out = P->local_flag;
+    pb.out_rounds = P->dinfo + D_ROUNDS_LOCAL;
+    pb.out_tests = P->dinfo + D_TESTS_LOCAL;
+    pb.out_tests_max = P->dinfo + D_TESTS_LOCAL_MAX;
     pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
-    pb.host_scratch = P->host_scratch;
-    pb.round_events[0] = P->round_ev[0]; pb.round_events[1] = P->round_ev[1];
-    EngineResult r{};
-    SKY_TRY(run_engine(pb, P->eng, P->local_list, &r, st));
+    SKY_TRY(run_engine(pb, P->eng, st));
     P->info.events_used = P->ev_used;
-    P->info.local_count = r.count;
-    P->info.rounds_local = r.rounds;
-    P->info.tests_local = r.tests + rep_tests;
-    P->info.tests_local_max = r.tests_max;
     P->state = 2;
     P->info.state = 2;
     return SKY_OK;
@@ -358,33 +305,37 @@ sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_co
     if (!P || !dev_count || cap < 0 || (cap > 0 && !sky_idx)) return SKY_ERR_INVALID_ARG;
     if (P->state != 2) return SKY_ERR_STATE;
     hipStream_t st = (hipStream_t)stream;
+    P->last_stream = st;
     const int32_t n = (int32_t)P->n;
-    const int32_t* final_list = P->local_list;
-    int32_t count = (int32_t)P->info.local_count;
+    uint8_t* F = P->local_flag;  // per position: in the final skyline (with dom clear)
     if (P->p > 1) {
-        // the union of the local skylines, in position order (spatially coherent)
-        SKY_TRY(launch_compact_flags(P->local_flag, n, P->eng.w1, P->count_tmp, P->eng.scan_tmp, st));
-        SKY_TRY(launch_fill_u8(P->final_flag, n, 0, st));
+        // the union of the local skylines, in position order (spatially coherent); local_flag
+        // becomes exactly the local skylines
+        SKY_TRY(launch_compact_flags(P->local_flag, P->eng.dom, true, n, P->eng.w1, P->count_tmp + CT_UNION,
+                                     P->dinfo + D_LOCAL_COUNT, P->eng.scan_tmp, st));
         EngineProblem pb{};
         pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
         pb.seg_of_pos = nullptr;
         pb.nseg = 1;
-        pb.items = P->eng.w1; pb.n_items = count;
+        pb.items = P->eng.w1;
+        pb.n_items = 0;
+        pb.n_items_dev = P->count_tmp + CT_UNION;
+        pb.ub_items = n;
         pb.flag_out = P->final_flag;
+        pb.out_rounds = P->dinfo + D_ROUNDS_MERGE;
+        pb.out_tests = P->dinfo + D_TESTS_MERGE;
         pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
-        pb.host_scratch = P->host_scratch;
-        pb.round_events[0] = P->round_ev[0]; pb.round_events[1] = P->round_ev[1];
-        EngineResult r{};
-        SKY_TRY(run_engine(pb, P->eng, P->final_list, &r, st));
-        final_list = P->final_list;
-        count = r.count;
-        P->info.rounds_merge = r.rounds;
-        P->info.tests_merge = r.tests;
+        SKY_TRY(run_engine(pb, P->eng, st));
         P->info.events_used = P->ev_used;
+        F = P->final_flag;
     }
-    P->info.sky_count = count;
-    SKY_TRY(launch_final_output(final_list, count, P->rowid, P->n, P->member_tmp, member, sky_idx,
-                                cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st));
+    // the skyline's positions in curve order (the gres store of sky_gres reads them), with F
+    // rewritten to the skyline itself
+    SKY_TRY(launch_compact_flags(F, P->eng.dom, true, n, P->final_list, P->count_tmp + CT_SKY,
+                                 P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st));
+    SKY_TRY(launch_final_output(P->final_list, P->count_tmp + CT_SKY, P->rowid, P->n, P->member_tmp, member,
+                                sky_idx, cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st));
+    P->merge_cap = cap;
     P->state = 3;
     P->info.state = 3;
     return SKY_OK;
@@ -399,8 +350,10 @@ sky_status sky_plan_partitions(const sky_plan* P, int32_t* part, void* stream) {
 sky_status sky_plan_local(const sky_plan* P, uint8_t* local, void* stream) {
     if (!P || !local) return SKY_ERR_INVALID_ARG;
     if (P->state < 2) return SKY_ERR_STATE;
-    return launch_scatter_rows(nullptr, P->local_flag, P->rowid, P->n, nullptr, local,
-                               (hipStream_t)stream);
+    // before sky_merge the local skylines are the head rows not dominated; sky_merge rewrites
+    // local_flag to exactly them (its own phase marks more rows dominated)
+    return launch_scatter_rows_live(P->local_flag, P->state == 2 ? P->eng.dom : nullptr, P->rowid, P->n,
+                                    local, (hipStream_t)stream);
 }
 
 sky_status sky_plan_partition_tests(const sky_plan* P, int64_t* tests, void* stream) {
@@ -422,30 +375,42 @@ sky_status sky_plan_set_events(sky_plan* P, void* const* ev_begin, void* const* 
     return SKY_OK;
 }
 
-sky_status sky_plan_set_host_scratch(sky_plan* P, void* host_pinned, size_t bytes) {
-    if (!P || (host_pinned && bytes < SKY_HOST_SCRATCH_BYTES)) return SKY_ERR_INVALID_ARG;
-    if (host_pinned && !P->round_ev[0]) {
-        for (int i = 0; i < 2; ++i) {
-            hipEvent_t e = nullptr;
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SKY_ERR_HIP;
-            P->round_ev[i] = e;
-        }
-    }
-    P->host_scratch = (int32_t*)host_pinned;
-    return SKY_OK;
-}
-
 sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
     if (!P || !out) return SKY_ERR_INVALID_ARG;
     *out = P->info;
+    if (P->state < 2) return SKY_OK;
+    // the counters the device wrote, read on the stream of the plan's last call
+    int64_t dv[kDinfo];
+    int32_t nk = 0;
+    unsigned long long rt = 0;
+    hipStream_t st = P->last_stream;
+    SKY_HIP(hipMemcpyAsync(dv, P->dinfo, sizeof(dv), hipMemcpyDeviceToHost, st));
+    if (P->reps > 0) {
+        SKY_HIP(hipMemcpyAsync(&nk, P->rep_kept + SKY_MAX_REPS, sizeof(nk), hipMemcpyDeviceToHost, st));
+        SKY_HIP(hipMemcpyAsync(&rt, P->rep_tests, sizeof(rt), hipMemcpyDeviceToHost, st));
+    }
+    SKY_HIP(hipStreamSynchronize(st));
+    out->pruned_cells = (int32_t)dv[D_PRUNED_CELLS];
+    out->pruned_rows = dv[D_PRUNED_ROWS];
+    out->max_partition = dv[D_MAX_PART];
+    out->rounds_local = (int32_t)dv[D_ROUNDS_LOCAL];
+    out->tests_local = dv[D_TESTS_LOCAL] + (int64_t)rt;
+    out->tests_local_max = dv[D_TESTS_LOCAL_MAX];
+    out->reps_kept = nk;
+    if (P->state >= 3) {
+        out->sky_count = dv[D_SKY_COUNT];
+        if (P->p > 1) {
+            out->local_count = dv[D_LOCAL_COUNT];
+            out->rounds_merge = (int32_t)dv[D_ROUNDS_MERGE];
+            out->tests_merge = dv[D_TESTS_MERGE];
+        } else {
+            out->local_count = dv[D_SKY_COUNT];
+        }
+    }
     return SKY_OK;
 }
 
 void sky_plan_destroy(sky_plan* P) {
-    if (!P) return;
-    for (int i = 0; i < 2; ++i)
-        if (P->round_ev[i]) (void)hipEventDestroy((hipEvent_t)P->round_ev[i]);
-    free(P->tan2_host);
     delete P;
 }
 
@@ -491,7 +456,7 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
     if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
     SKY_TRY(launch_gres_prepare(x_soa, n, d, ld, sky_idx, s, store, tmp, dev_status, st));
     SKY_TRY(launch_gres_targets(x_soa, n, d, ld, nullptr, s, s, store, tg, dev_status, st));
-    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, 0, g_max, mapping, g_exit, gres,
+    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, nullptr, 0, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                               opts ? opts->dev_tests : nullptr, st);
 }
@@ -502,28 +467,28 @@ sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, vo
     if (P->state != 3) return SKY_ERR_STATE;
     int32_t mapping = 0;
     SKY_TRY(check_opts(opts, &mapping));
-    const int64_t s = P->info.sky_count;
-    if (s == 0) return SKY_OK;
-    if (!ws || ws_bytes < gres_workspace_bytes(s, P->d, g_max)) return SKY_ERR_WORKSPACE;
-    Carver c(ws, ws_bytes);
+    // the skyline size is on the device (count_tmp[CT_SKY]); the workspace holds the largest
+    // skyline sky_merge could return in full
+    const int64_t cap = P->merge_cap < P->n ? P->merge_cap : P->n;
+    const int64_t c = cap > 0 ? cap : 1;
+    if (!ws || ws_bytes < gres_workspace_bytes(c, P->d, g_max)) return SKY_ERR_WORKSPACE;
+    Carver cv(ws, ws_bytes);
     GresStore store{};
     GresPrepTmp tmp{};
     GresTargets tg{};
-    carve_gres_store(c, store, s, P->d, 1);
-    carve_gres_prep_tmp(c, tmp, s);
-    carve_gres_targets(c, tg, s, P->d);
-    if (c.overflow) return SKY_ERR_WORKSPACE;
+    carve_gres_store(cv, store, c, P->d, 1);
+    carve_gres_prep_tmp(cv, tmp, c);
+    carve_gres_targets(cv, tg, c, P->d);
+    if (cv.overflow) return SKY_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
-    // the skyline's positions in ascending order (curve order inside each partition, and
-    // partitions are contiguous: with p > 1 the store is ordered by partition, then curve)
-    const uint8_t* flags = P->p > 1 ? P->final_flag : P->local_flag;
-    int32_t* pos = (int32_t*)tmp.k0;  // s entries, free until the search
-    SKY_TRY(launch_compact_flags(flags, (int32_t)P->n, pos, P->count_tmp, P->eng.scan_tmp, st));
-    // the row -> index-in-sky_idx map is left in pos_tmp by sky_merge
-    SKY_TRY(launch_gres_prepare_positions(P->xp, P->ldp, P->d, pos, s, P->rowid, P->pos_tmp, store, st));
-    SKY_TRY(launch_gres_targets(nullptr, 0, P->d, 0, nullptr, s, s, store, tg, dev_status, st));
-    return launch_gres_search(store, P->d, (int32_t)s, tg, s, nullptr, 0, g_max, mapping, g_exit, gres,
+    P->last_stream = st;
+    const int32_t* s_dev = P->count_tmp + CT_SKY;
+    // candidates from the partition-contiguous copy at the skyline's positions (ascending, hence
+    // curve order inside each partition); pos_tmp maps a row to its index in sky_idx
+    SKY_TRY(launch_gres_prepare_positions(P->xp, P->ldp, P->d, P->final_list, c, s_dev, P->rowid, P->pos_tmp,
+                                          store, dev_status, st));
+    SKY_TRY(launch_gres_targets_all(store, P->d, c, s_dev, tg, st));
+    return launch_gres_search(store, P->d, (int32_t)c, tg, c, s_dev, nullptr, 0, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                               opts ? opts->dev_tests : nullptr, st);
 }
@@ -606,7 +571,7 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
     if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
     if (s == 0) return SKY_ERR_INVALID_ARG;  // targets need candidates to be tested against
     SKY_TRY(launch_gres_targets(x_soa, n, d, ld, targets, nt, s, store, tg, dev_status, st));
-    return launch_gres_search(store, d, (int32_t)s, tg, nt, nullptr, 0, g_max, mapping, g_exit, gres,
+    return launch_gres_search(store, d, (int32_t)s, tg, nt, nullptr, nullptr, 0, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                               opts ? opts->dev_tests : nullptr, st);
 }

@@ -120,10 +120,16 @@ sky_status sky_batch_skylines(sky_batch* B, int64_t* sky_idx, int64_t cap, int64
     sky_plan* P = B->plan;
     // 1. every relation's skyline: one segment per relation, no final phase
     SKY_TRY(sky_local_skylines(P, stream));
-    const int64_t S = P->info.local_count;
-    B->info.rounds_local = P->info.rounds_local;
-    B->info.tests_local = P->info.tests_local;
-    B->info.tests_local_max = P->info.tests_local_max;  // the costliest relation
+    // every relation's skyline flags (local_flag rewritten to them), and their count read back
+    SKY_TRY(launch_compact_flags(P->local_flag, P->eng.dom, true, (int32_t)P->n, P->final_list,
+                                 P->count_tmp + CT_SKY, P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st));
+    P->state = 3;
+    sky_info pi{};
+    SKY_TRY(sky_plan_info(P, &pi));
+    const int64_t S = pi.sky_count;
+    B->info.rounds_local = pi.rounds_local;
+    B->info.tests_local = pi.tests_local;
+    B->info.tests_local_max = pi.tests_local_max;  // the costliest relation
     B->info.local_count = S;
     B->info.sky_count = S;
     if (S > cap) return SKY_ERR_CAPACITY;
@@ -131,7 +137,7 @@ sky_status sky_batch_skylines(sky_batch* B, int64_t* sky_idx, int64_t cap, int64
     Carver c(B->rest, B->rest_bytes);
     carve_batch_tail(c, B, S, B->d, B->nbatch);  // sized for the actual skyline
     if (c.overflow) return SKY_ERR_WORKSPACE;
-    SKY_TRY(launch_final_output(P->local_list, (int32_t)S, P->rowid, P->n, P->member_tmp, nullptr,
+    SKY_TRY(launch_final_output(P->final_list, P->count_tmp + CT_SKY, P->rowid, P->n, P->member_tmp, nullptr,
                                 sky_idx, cap, B->dev_count, P->pos_tmp, P->scan_tmp, B->dev_status, st));
     SKY_TRY(launch_batch_offsets(sky_idx, S, P->seg_off_dev, B->nbatch, sky_off, B->cand_off, st));
     B->sky_off.assign((size_t)B->nbatch + 1, 0);
@@ -221,7 +227,7 @@ sky_status sky_batch_gres(sky_batch* B, int32_t g_max, int32_t* g_exit, float* g
     const int32_t mapping = B->mapping == SKY_GRES_AUTO ? gres_auto_mapping(B->max_cnt, g_max) : B->mapping;
     SKY_TRY(launch_gres_targets_segments(B->store, B->d, B->sky_count, B->cand_off, B->nbatch,
                                          B->near_first != 0, B->tg, st));
-    return launch_gres_search(B->store, B->d, B->max_cnt, B->tg, B->sky_count, B->wg_table, B->n_wg,
+    return launch_gres_search(B->store, B->d, B->max_cnt, B->tg, B->sky_count, nullptr, B->wg_table, B->n_wg,
                               g_max, mapping, g_exit, gres, ev_begin, ev_end, nullptr, st);
 }
 

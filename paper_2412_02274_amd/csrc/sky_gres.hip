@@ -56,6 +56,8 @@ constexpr int kMaxBands = 8;
 constexpr int kStartLevels = 64;         // above this g_max, searches start at per-target bounds
 constexpr int kLevelWaves = 4096;        // LEVELS: waves wanted in flight (targets x bands)
 constexpr int kMaxLevelBands = 16;
+constexpr int kGresLdsDevBytes = 40 * 1024;  // box LDS of searches whose count is on the device
+constexpr int kStrideGrid = 4096;       // workgroups of searches whose count is on the device
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -123,52 +125,63 @@ __global__ void __launch_bounds__(kBlock) store_kernel(const float* __restrict__
     perm[q] = j;
 }
 
-// every slot of the store from a plan's partition-contiguous copy: the candidates are the rows at
-// positions pos[0, s), already in curve order (the copy is), so no sort is needed; the caller
-// index of a slot is idx_of_row[row] (padding: 2.0, ~0, -1)
+// the store from a plan's partition-contiguous copy: the candidates are the rows at positions
+// pos[0, s), already in curve order (the copy is), so no sort is needed; the caller index of a
+// slot is idx_of_row[row]. s = min(*s_dev, cap) when s_dev is given. Slots from s to the end of
+// its tile, and the store's last tile, get padding (2.0, ~0, -1); slots beyond are never read.
 __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restrict__ xp, int64_t ldp,
                                                             int32_t d, const int32_t* __restrict__ pos,
-                                                            int32_t s, const int32_t* __restrict__ rowid,
+                                                            int32_t s_host, const int32_t* __restrict__ s_dev,
+                                                            const int32_t* __restrict__ rowid,
                                                             const int32_t* __restrict__ idx_of_row,
                                                             float* __restrict__ cand, int64_t ccap,
                                                             uint32_t* __restrict__ ckey,
                                                             int32_t* __restrict__ perm) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= ccap) return;
-    const bool real = q < s;
-    const int32_t p = real ? pos[q] : 0;
-    float v[SKY_MAX_D];
-    for (int k = 0; k < d; ++k) {
-        v[k] = real ? xp[(int64_t)k * ldp + p] : kPadValue;
-        cand[(int64_t)k * ccap + q] = v[k];
+    int32_t s = s_host;
+    if (s_dev) s = *s_dev < s_host ? *s_dev : s_host;
+    const int64_t used = ((int64_t)s + kTileC - 1) / kTileC * kTileC;
+    const int64_t lim = used + kTileC;  // then the last tile, [ccap - 64, ccap)
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < lim; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = i < used ? i : ccap - kTileC + (i - used);
+        const bool real = q < s;
+        const int32_t p = real ? pos[q] : 0;
+        float v[SKY_MAX_D];
+        for (int k = 0; k < d; ++k) {
+            v[k] = real ? xp[(int64_t)k * ldp + p] : kPadValue;
+            cand[(int64_t)k * ccap + q] = v[k];
+        }
+        ckey[q] = real ? hilbert_key(v, d, curve_bits(d)) : 0xFFFFFFFFu;
+        perm[q] = real ? idx_of_row[rowid[p]] : -1;
     }
-    ckey[q] = real ? hilbert_key(v, d, curve_bits(d)) : 0xFFFFFFFFu;
-    perm[q] = real ? idx_of_row[rowid[p]] : -1;
 }
 
 // one wave per tile: componentwise minimum (lo) and maximum (hi) of its real candidates (padding
 // slots hold kPadValue in every attribute; a tile of padding only gets lo = 1, which no key test
 // passes: fl(1 g) = g is above every key of a value in [0, 1))
 __global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restrict__ cand, int64_t ccap,
-                                                           int32_t d, int32_t ntile,
+                                                           int32_t d, int32_t ntile_host,
+                                                           const int32_t* __restrict__ s_dev, int32_t s_cap,
                                                            float* __restrict__ lo,
                                                            float* __restrict__ hi, int64_t tcap) {
-    const int32_t tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (tile >= ntile) return;
+    int32_t ntile = ntile_host;
+    if (s_dev) ntile = ((*s_dev < s_cap ? *s_dev : s_cap) + kTileC - 1) / kTileC;
     const int lane = (int)lane_id();
-    const int64_t j = (int64_t)tile * kTileC + lane;
-    const bool real = cand[j] < kPadValue;
-    for (int k = 0; k < d; ++k) {
-        const float c = cand[(int64_t)k * ccap + j];
-        float v = real ? c : 1.0f;
-        float h = real ? c : 0.0f;
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            v = fminf(v, __shfl_xor(v, off, kWave));
-            h = fmaxf(h, __shfl_xor(h, off, kWave));
-        }
-        if (lane == 0) {
-            lo[(int64_t)k * tcap + tile] = v;
-            hi[(int64_t)k * tcap + tile] = h;
+    for (int32_t tile = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; tile < ntile;
+         tile += gridDim.x * (kBlock / kWave)) {
+        const int64_t j = (int64_t)tile * kTileC + lane;
+        const bool real = cand[j] < kPadValue;
+        for (int k = 0; k < d; ++k) {
+            const float c = cand[(int64_t)k * ccap + j];
+            float v = real ? c : 1.0f;
+            float h = real ? c : 0.0f;
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                v = fminf(v, __shfl_xor(v, off, kWave));
+                h = fmaxf(h, __shfl_xor(h, off, kWave));
+            }
+            if (lane == 0) {
+                lo[(int64_t)k * tcap + tile] = v;
+                hi[(int64_t)k * tcap + tile] = h;
+            }
         }
     }
 }
@@ -216,11 +229,18 @@ __global__ void __launch_bounds__(kBlock) store_seg_kernel(
     perm[q] = j;
 }
 
+// one segment of s candidates; with s_dev, s = min(*s_dev, s), and a larger count raises
+// SKY_ERR_CAPACITY (the store was carved for s)
 __global__ void single_segment_kernel(int32_t* __restrict__ seg_coff, int32_t* __restrict__ seg_cnt,
-                                      int32_t s) {
+                                      int32_t s, const int32_t* __restrict__ s_dev, int32_t* dev_status) {
     if (threadIdx.x == 0) {
+        int32_t c = s;
+        if (s_dev) {
+            if (*s_dev > s) raise_status(dev_status, SKY_ERR_CAPACITY);
+            else c = *s_dev;
+        }
         seg_coff[0] = 0;
-        seg_cnt[0] = s;
+        seg_cnt[0] = c;
     }
 }
 
@@ -228,16 +248,18 @@ __global__ void single_segment_kernel(int32_t* __restrict__ seg_coff, int32_t* _
 
 // targets = every candidate of the store (slot order): values, hint tile, output index
 __global__ void __launch_bounds__(kBlock) targets_all_kernel(const float* __restrict__ cand, int64_t ccap,
-                                                              int32_t s, int32_t d,
-                                                              const int32_t* __restrict__ perm,
+                                                              int32_t s_host, const int32_t* __restrict__ s_dev,
+                                                              int32_t d, const int32_t* __restrict__ perm,
                                                               float* __restrict__ tval, int64_t tvcap,
                                                               int32_t* __restrict__ thint,
                                                               int32_t* __restrict__ tout) {
-    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= s) return;
-    for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + q];
-    thint[q] = q / kTileC;
-    tout[q] = perm[q];
+    int32_t s = s_host;
+    if (s_dev) s = *s_dev < s_host ? *s_dev : s_host;
+    for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < s; q += gridDim.x * kBlock) {
+        for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + q];
+        thint[q] = q / kTileC;
+        tout[q] = perm[q];
+    }
 }
 
 // targets = every candidate of a segmented store in element order: element q of segment sg
@@ -260,6 +282,49 @@ __global__ void __launch_bounds__(kBlock) targets_seg_kernel(
 __global__ void __launch_bounds__(kBlock) fill_i32_kernel(int32_t* __restrict__ p, int32_t n, int32_t v) {
     const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------- search shape on the device
+// The targets of a search whose count is on the device: its shape, as the host would pick it
+// for that count (params[P_*]).
+enum { P_NT = 0, P_MAPPING, P_PER_WG, P_BLOCKS, P_LBANDS };
+
+__host__ __device__ inline void search_shape(int32_t nt, int32_t g_max, int32_t* per_wg, int32_t* blocks,
+                                             int32_t* lbands) {
+    // ~2 targets per wave when there are plenty (measured best on large skylines: fewer leaves
+    // waves idle on the longest searches), fewer otherwise
+    int64_t want = ((int64_t)nt + kWaves * 2 - 1) / (kWaves * 2);
+    if (want < 256) want = ((int64_t)nt + kWaves - 1) / kWaves;
+    int32_t b = (int32_t)(want < 1 ? 1 : want);
+    const int32_t pw = nt > 0 ? (nt + b - 1) / b : 1;
+    *per_wg = pw;
+    *blocks = nt > 0 ? (nt + pw - 1) / pw : 0;
+    // LEVELS with few targets: each target's levels split over several waves so the chip fills
+    int64_t lb = nt > 0 && nt < kLevelWaves ? ((int64_t)kLevelWaves + nt - 1) / nt : 1;
+    const int64_t lmax = ((int64_t)g_max - 1 + kWave - 1) / kWave;  // at least 64 levels per band
+    lb = lb > lmax ? lmax : lb;
+    lb = lb > kMaxLevelBands ? kMaxLevelBands : (lb < 1 ? 1 : lb);
+    *lbands = (int32_t)lb;
+}
+
+__global__ void search_setup_kernel(const int32_t* __restrict__ nt_dev, int32_t nt_cap, int32_t g_max,
+                                    int32_t mapping, int32_t* __restrict__ params) {
+    if (threadIdx.x != 0) return;
+    const int32_t nt = *nt_dev < nt_cap ? *nt_dev : nt_cap;
+    int32_t per_wg, blocks, lb;
+    search_shape(nt, g_max, &per_wg, &blocks, &lb);
+    params[P_NT] = nt;
+    params[P_MAPPING] = mapping == SKY_GRES_AUTO ? gres_auto_mapping(nt, g_max) : mapping;
+    params[P_PER_WG] = per_wg;
+    params[P_BLOCKS] = blocks;
+    params[P_LBANDS] = lb;
+}
+
+// p[0, n) = v, n = params[P_NT] when params is given (grid-stride)
+__global__ void __launch_bounds__(kBlock) fill_targets_kernel(int32_t* __restrict__ p, int32_t n,
+                                                               const int32_t* __restrict__ params, int32_t v) {
+    if (params) n = params[P_NT];
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = v;
 }
 
 // first position of every relation's rows in the ascending skyline list (lower bound of its
@@ -367,9 +432,13 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
     int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests, int32_t nblk,
     int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
-    int32_t* __restrict__ work) {
+    int32_t* __restrict__ work, const int32_t* __restrict__ params) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
+    if (params) {  // target count and mapping decided on the device
+        if (params[P_MAPPING] != SKY_GRES_TILES) return;
+        nt = params[P_NT];
+    }
     unsigned long long ntests = 0;   // candidate tests (target against candidate at one level)
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
@@ -588,13 +657,20 @@ __global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo, int64_t tcap,
     const int32_t* __restrict__ seg_coff, const int32_t* __restrict__ seg_cnt, int32_t d_rt,
     const float* __restrict__ tval, int64_t tvcap, int32_t nt, const int32_t* __restrict__ wg_table,
-    int32_t per_wg, int32_t g_max, int32_t* __restrict__ gstart) {
+    int32_t per_wg, int32_t g_max, int32_t* __restrict__ gstart, const int32_t* __restrict__ params) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
-    const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x);
-    if (w.t0 >= w.t1) return;
+    int32_t nblk = (int32_t)gridDim.x;
+    if (params) {  // the target count and the split are on the device: grid-stride over the blocks
+        nt = params[P_NT];
+        per_wg = params[P_PER_WG];
+        nblk = params[P_BLOCKS];
+    }
+    for (int32_t vb = blockIdx.x; vb < nblk; vb += gridDim.x) {
+    const WgWork w = wg_work(wg_table, per_wg, nt, vb);
+    if (w.t0 >= w.t1) continue;
     const int64_t coff = seg_coff[w.seg];
     const int32_t cnt = seg_cnt[w.seg];
     const int32_t ntile = (cnt + kTileC - 1) / kTileC;
@@ -649,6 +725,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
         }
         if (lane == 0) gstart[q] = best;
     }
+    }
 }
 
 template <int D>
@@ -659,7 +736,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
     int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
     const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
     int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests,
-    const int32_t* __restrict__ gstart, int32_t nblk) {
+    const int32_t* __restrict__ gstart, int32_t nblk, const int32_t* __restrict__ params) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     unsigned long long ntests = 0;  // candidate tests (target against candidate at one level)
     (void)thint;
@@ -667,11 +744,19 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
+    int32_t nbands = (int32_t)(gridDim.x / (uint32_t)nblk);
+    if (params) {  // target count, mapping and split decided on the device: grid-stride
+        if (params[P_MAPPING] != SKY_GRES_LEVELS) return;
+        nt = params[P_NT];
+        per_wg = params[P_PER_WG];
+        nblk = params[P_BLOCKS];
+        nbands = params[P_LBANDS];
+    }
     // blocks are band-major: every target's highest band first
-    const int32_t band = blockIdx.x / nblk;
-    const int32_t nbands = (int32_t)(gridDim.x / (uint32_t)nblk);
-    const WgWork w = wg_work(wg_table, per_wg, nt, blockIdx.x - band * nblk);
-    if (w.t0 >= w.t1) return;
+    for (int32_t vb = blockIdx.x; vb < nblk * nbands; vb += gridDim.x) {
+    const int32_t band = vb / nblk;
+    const WgWork w = wg_work(wg_table, per_wg, nt, vb - band * nblk);
+    if (w.t0 >= w.t1) continue;
     const int64_t coff = seg_coff[w.seg];
     const int32_t cnt = seg_cnt[w.seg];
     const int32_t ntile = (cnt + kTileC - 1) / kTileC;
@@ -770,20 +855,23 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
         // ge_out starts at 1 (no exit); each band raises it to its highest exit level
         if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
     }
+    }
     if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
 }
 
 __global__ void __launch_bounds__(kBlock) gres_output_kernel(const int32_t* __restrict__ ge_t,
                                                               const int32_t* __restrict__ tout,
-                                                              int32_t nt, int32_t* __restrict__ g_exit,
+                                                              int32_t nt, const int32_t* __restrict__ params,
+                                                              int32_t out_cap, int32_t* __restrict__ g_exit,
                                                               float* __restrict__ gres) {
-    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nt) return;
-    const int32_t j = tout[q];
-    if (j < 0) return;
-    const int32_t g = ge_t[q];
-    if (g_exit) g_exit[j] = g;
-    if (gres) gres[j] = __fdiv_rn(1.0f, (float)g);
+    if (params) nt = params[P_NT];
+    for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < nt; q += gridDim.x * kBlock) {
+        const int32_t j = tout[q];
+        if (j < 0 || j >= out_cap) continue;  // (beyond the outputs only after a capacity error)
+        const int32_t g = ge_t[q];
+        if (g_exit) g_exit[j] = g;
+        if (gres) gres[j] = __fdiv_rn(1.0f, (float)g);
+    }
 }
 
 }  // namespace
@@ -831,6 +919,7 @@ void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d) {
     t.ge = c.take<int32_t>((size_t)t.tvcap);
     t.gstart = c.take<int32_t>((size_t)t.tvcap);
     t.work = c.take<int32_t>((size_t)kWorkCounters * kCounterStride);
+    t.params = c.take<int32_t>(16);
 }
 
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -838,7 +927,8 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
                                int32_t* dev_status, hipStream_t st) {
     const int32_t s = (int32_t)s64;
     const int bits = curve_bits(d);
-    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, s);
+    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, s,
+                       (const int32_t*)nullptr, dev_status);
     if (s > 0) {
         hipLaunchKernelGGL(curve_kernel, dim3((uint32_t)ceil_div(s, kBlock)), dim3(kBlock), 0, st, x, n,
                            d, ld, rows, s, bits, tmp.k0, tmp.v0, dev_status);
@@ -851,24 +941,39 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
     const int32_t ntile = (int32_t)ceil_div(s, kTileC);
     if (ntile > 0)
         hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
-                           st, (const float*)store.cand, store.ccap, d, ntile, store.lo, store.hi,
-                           store.tcap);
+                           st, (const float*)store.cand, store.ccap, d, ntile, (const int32_t*)nullptr, 0,
+                           store.lo, store.hi, store.tcap);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
 
 sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
-                                         int64_t s64, const int32_t* rowid, const int32_t* idx_of_row,
-                                         const GresStore& store, hipStream_t st) {
-    const int32_t s = (int32_t)s64;
-    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, s);
-    hipLaunchKernelGGL(store_pos_kernel, dim3((uint32_t)ceil_div(store.ccap, kBlock)), dim3(kBlock), 0, st,
-                       xp, ldp, d, pos, s, rowid, idx_of_row, store.cand, store.ccap, store.ckey, store.perm);
-    const int32_t ntile = (int32_t)ceil_div(s, kTileC);
-    if (ntile > 0)
-        hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
-                           st, (const float*)store.cand, store.ccap, d, ntile, store.lo, store.hi,
-                           store.tcap);
+                                         int64_t cap64, const int32_t* s_dev, const int32_t* rowid,
+                                         const int32_t* idx_of_row, const GresStore& store,
+                                         int32_t* dev_status, hipStream_t st) {
+    const int32_t cap = (int32_t)cap64;
+    auto grid = [](int64_t want, int64_t most) -> uint32_t {
+        return (uint32_t)(want < 1 ? 1 : (want > most ? most : want));
+    };
+    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, cap, s_dev,
+                       dev_status);
+    hipLaunchKernelGGL(store_pos_kernel, dim3(grid(ceil_div(round_up(cap, kTileC) + kTileC, kBlock), 2048)),
+                       dim3(kBlock), 0, st, xp, ldp, d, pos, cap, s_dev, rowid, idx_of_row, store.cand, store.ccap,
+                       store.ckey, store.perm);
+    const int64_t ntile = ceil_div(cap, kTileC);
+    hipLaunchKernelGGL(tile_box_kernel, dim3(grid(ceil_div(ntile, kBlock / kWave), 2048)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, d, (int32_t)ntile, s_dev, cap, store.lo, store.hi,
+                       store.tcap);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_gres_targets_all(const GresStore& store, int32_t d, int64_t cap64, const int32_t* s_dev,
+                                   const GresTargets& tg, hipStream_t st) {
+    const int64_t blocks = ceil_div(cap64 > 0 ? cap64 : 1, kBlock);
+    hipLaunchKernelGGL(targets_all_kernel, dim3((uint32_t)(blocks > 1024 ? 1024 : blocks)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, (int32_t)cap64, s_dev, d,
+                       (const int32_t*)store.perm, tg.tval, tg.tvcap, tg.thint, tg.tout);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
@@ -881,8 +986,8 @@ sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld,
     if (nt <= 0) return SKY_OK;
     if (!rows) {
         hipLaunchKernelGGL(targets_all_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st,
-                           (const float*)store.cand, store.ccap, nt, d, (const int32_t*)store.perm,
-                           tg.tval, tg.tvcap, tg.thint, tg.tout);
+                           (const float*)store.cand, store.ccap, nt, (const int32_t*)nullptr, d,
+                           (const int32_t*)store.perm, tg.tval, tg.tvcap, tg.thint, tg.tout);
     } else {
         hipLaunchKernelGGL(targets_rows_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st,
                            x, n, d, ld, rows, nt, curve_bits(d), (const uint32_t*)store.ckey,
@@ -921,8 +1026,8 @@ sky_status launch_gres_prepare_segments(const float* x, int64_t n, int32_t d, in
     SKY_HIP(hipGetLastError());
     if (ntile > 0)
         hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
-                           st, (const float*)store.cand, store.ccap, d, ntile, store.lo, store.hi,
-                           store.tcap);
+                           st, (const float*)store.cand, store.ccap, d, ntile, (const int32_t*)nullptr, 0,
+                           store.lo, store.hi, store.tcap);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
@@ -957,69 +1062,73 @@ sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds
     return SKY_OK;
 }
 
-int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
-    // measured (both mappings with per-target start levels): lanes over 64 levels pay off when
-    // many levels lie below the start levels (g_max >= 2^17) or on small skylines with
-    // g_max > 1000; otherwise the banded tile walk is faster
-    if (s > 8192) return SKY_GRES_TILES;
-    return (g_max >= (1 << 17) || (g_max > 1000 && s <= 1024)) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
-}
-
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
-                              const GresTargets& tg, int64_t nt64, const int32_t* wg_table,
+                              const GresTargets& tg, int64_t nt64, const int32_t* nt_dev, const int32_t* wg_table,
                               int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
                               unsigned long long* dev_tests, hipStream_t st) {
-    const int32_t nt = (int32_t)nt64;
+    const int32_t nt = (int32_t)nt64;  // with nt_dev: an upper bound of the count
     if (nt <= 0) return SKY_OK;
-    // LDS for the tile boxes of the largest segment, when they fit
+    const bool on_dev = nt_dev && !wg_table;
+    // LDS for the tile boxes of the largest segment, when they fit; with the count on the
+    // device, a fixed 40 KB (the kernel checks the real size), which costs no occupancy at 8
+    // waves per SIMD
     const int32_t ntile = (int32_t)ceil_div(max_cnt, kTileC);
     const int32_t nchunk = (int32_t)ceil_div(ntile, kWave);
     int64_t floats = (int64_t)d * (2 * ntile + nchunk);
     if (floats * 4 > kGresLdsBytes || nchunk > kWave) floats = 0;
+    if (on_dev) floats = kGresLdsDevBytes / 4;
     const size_t lds = (size_t)floats * sizeof(float);
-    int32_t per_wg = 0;
-    uint32_t blocks = (uint32_t)n_wg;
+    int32_t per_wg = 0, lbands = 1;
+    int32_t blocks = n_wg;
     if (!wg_table) {
-        // single segment: ~2 targets per wave when there are plenty (measured best on large
-        // skylines: fewer leaves waves idle on the longest searches), fewer otherwise
-        int64_t want = ceil_div(nt, kWaves * 2);
-        if (want < 256) want = ceil_div(nt, kWaves);
-        blocks = (uint32_t)(want < 1 ? 1 : want);
-        per_wg = (int32_t)ceil_div(nt, blocks);
-        blocks = (uint32_t)ceil_div(nt, per_wg);
+        search_shape(nt, g_max, &per_wg, &blocks, &lbands);
+    } else {
+        int32_t pw_unused = 0, b_unused = 0;  // a table fixes the blocks; the level bands follow nt
+        search_shape(nt, g_max, &pw_unused, &b_unused, &lbands);
+    }
+    int32_t* params = nullptr;
+    if (on_dev) {
+        params = tg.params;
+        hipLaunchKernelGGL(search_setup_kernel, dim3(1), dim3(64), 0, st, nt_dev, nt, g_max, mapping, params);
+        SKY_HIP(hipGetLastError());
     }
     // TILES: the levels are split into bands searched by separate workgroups (band-major
     // order), so a tuple that scans many levels is not one long sequential chain
-    int32_t nbands = 1, band_len = g_max - 1;
-    if (mapping != SKY_GRES_LEVELS) {
-        nbands = (int32_t)ceil_div(g_max - 1, kBandLevels);
-        nbands = nbands < 1 ? 1 : (nbands > kMaxBands ? kMaxBands : nbands);
-        band_len = (int32_t)ceil_div(g_max - 1, nbands);
-    }
+    int32_t nbands = (int32_t)ceil_div(g_max - 1, kBandLevels);
+    nbands = nbands < 1 ? 1 : (nbands > kMaxBands ? kMaxBands : nbands);
+    const int32_t band_len = (int32_t)ceil_div(g_max - 1, nbands);
+    const bool run_tiles = on_dev ? mapping != SKY_GRES_LEVELS : mapping != SKY_GRES_LEVELS;
+    const bool run_levels = on_dev ? mapping != SKY_GRES_TILES : mapping == SKY_GRES_LEVELS;
+    // grids of the kernels that stride over the blocks a device-side count asks for
+    const uint32_t stride_grid = (uint32_t)(blocks < kStrideGrid ? (blocks < 1 ? 1 : blocks) : kStrideGrid);
     // many levels: each target's highest level worth searching, from the candidates' bounds
     const int32_t* gstart = nullptr;
     if (g_max > kStartLevels) {
-        SKY_DISPATCH_D(d, gres_start_kernel, dim3(blocks), dim3(kGresBlock), 0, st,
-                       (const float*)store.cand, store.ccap, (const float*)store.lo, store.tcap,
+        SKY_DISPATCH_D(d, gres_start_kernel, dim3(on_dev ? stride_grid : (uint32_t)blocks), dim3(kGresBlock), 0,
+                       st, (const float*)store.cand, store.ccap, (const float*)store.lo, store.tcap,
                        (const int32_t*)store.seg_coff, (const int32_t*)store.seg_cnt, d,
-                       (const float*)tg.tval, tg.tvcap, nt, wg_table, per_wg, g_max, tg.gstart);
+                       (const float*)tg.tval, tg.tvcap, nt, wg_table, per_wg, g_max, tg.gstart,
+                       (const int32_t*)params);
         SKY_HIP(hipGetLastError());
         gstart = tg.gstart;
     }
     // no exit (1) until a band finds one
-    hipLaunchKernelGGL(fill_i32_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st, tg.ge,
-                       nt, 1);
-    SKY_HIP(hipGetLastError());
+    {
+        const int64_t fb = ceil_div(nt, kBlock);
+        hipLaunchKernelGGL(fill_targets_kernel, dim3((uint32_t)(fb > 1024 ? 1024 : fb)), dim3(kBlock), 0, st, tg.ge,
+                           nt, (const int32_t*)params, 1);
+        SKY_HIP(hipGetLastError());
+    }
     // TILES on one segment: as many workgroups as the device holds at once, fed from a counter
-    uint32_t grid = blocks * (uint32_t)nbands;
+    uint32_t grid = (uint32_t)blocks * (uint32_t)nbands;
     int32_t* work = nullptr;
-    if (mapping != SKY_GRES_LEVELS && !wg_table && (int64_t)nt * nbands < ((int64_t)1 << 30)) {
+    if (run_tiles && !wg_table && (int64_t)nt * nbands < ((int64_t)1 << 30)) {
         const void* fn = nullptr;
         SKY_KERNEL_PTR_D(d, gres_tiles_kernel, fn);
         int32_t resident = 0;
         SKY_TRY(resident_workgroups(fn, kGresBlock, lds, &resident));
-        if ((int64_t)grid > resident) {
+        if ((int64_t)grid > resident || on_dev) {
             grid = (uint32_t)resident;
             work = tg.work;
             hipLaunchKernelGGL(fill_i32_kernel, dim3(kWorkCounters * kCounterStride / kBlock), dim3(kBlock), 0,
@@ -1028,30 +1137,32 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
         }
     }
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
-    if (mapping == SKY_GRES_LEVELS) {
-        // few targets: split each target's levels over several waves so the chip fills
-        int64_t lb = nt < kLevelWaves ? ceil_div(kLevelWaves, nt) : 1;
-        const int64_t lmax = ceil_div(g_max - 1, kWave);  // at least 64 levels per band at g_max
-        lb = lb > lmax ? lmax : lb;
-        lb = lb > kMaxLevelBands ? kMaxLevelBands : (lb < 1 ? 1 : lb);
-        SKY_DISPATCH_D(d, gres_levels_kernel, dim3(blocks * (uint32_t)lb), dim3(kGresBlock), 0, st,
+    if (run_levels) {
+        const uint32_t lgrid = on_dev ? (uint32_t)(stride_grid * (uint32_t)kMaxLevelBands > kStrideGrid
+                                                       ? kStrideGrid : stride_grid * (uint32_t)kMaxLevelBands)
+                                      : (uint32_t)blocks * (uint32_t)lbands;
+        SKY_DISPATCH_D(d, gres_levels_kernel, dim3(lgrid), dim3(kGresBlock), 0, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests, gstart, (int32_t)blocks);
-    } else {
+                       dev_tests, gstart, (int32_t)blocks, (const int32_t*)params);
+        SKY_HIP(hipGetLastError());
+    }
+    if (run_tiles) {
         SKY_DISPATCH_D(d, gres_tiles_kernel, dim3(grid), dim3(kGresBlock), lds, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests, (int32_t)blocks, band_len, gstart, nbands, work);
+                       dev_tests, (int32_t)blocks, band_len, gstart, nbands, work, (const int32_t*)params);
+        SKY_HIP(hipGetLastError());
     }
-    SKY_HIP(hipGetLastError());
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));
-    hipLaunchKernelGGL(gres_output_kernel, dim3((uint32_t)ceil_div(nt, kBlock)), dim3(kBlock), 0, st,
-                       (const int32_t*)tg.ge, (const int32_t*)tg.tout, nt, g_exit, gres);
+    const int64_t ob = ceil_div(nt, kBlock);
+    hipLaunchKernelGGL(gres_output_kernel, dim3((uint32_t)(ob > 1024 ? 1024 : ob)), dim3(kBlock), 0, st,
+                       (const int32_t*)tg.ge, (const int32_t*)tg.tout, nt, (const int32_t*)params, nt, g_exit,
+                       gres);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

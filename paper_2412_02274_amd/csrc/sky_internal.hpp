@@ -173,7 +173,7 @@ struct PartitionArgs {
     const float* x; int64_t n; int32_t d; int64_t ld;
     int32_t scheme; int32_t p; int32_t m; int32_t slice_dim;
     const int64_t* seg_off;    // kSchemeSegments: [p+1] row offsets of the datasets (device)
-    const double* tan2;   // Angular thresholds tan^2(k*pi/(2m)), k = 0..m (device)
+    double* tan2;              // Angular thresholds tan^2(k*pi/(2m)), k = 0..m (device, written here)
     float* xp; int64_t ldp;    // partition-contiguous canonical SoA copy
     int32_t* rowid;            // partitioned position -> original row
     int32_t* seg;              // partitioned position -> partition
@@ -191,6 +191,9 @@ struct PartitionArgs {
 int64_t partition_hist_elems(int64_t n, int32_t p);
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st);
+// out[0..3) = pruned non-empty cells, rows inside them, rows of the largest partition (int64)
+sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned, int32_t p, int64_t* out,
+                                  hipStream_t st);
 
 // sky_reps.hip: Representative Filtering (Sec. 3.1)
 struct RepArgs {
@@ -233,49 +236,55 @@ sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds
 
 // sky_skyline.hip: segmented skyline engine (see the file header)
 struct EngineBuffers {
-    int32_t* w0; int32_t* w1;      // work lists (capacity n)
+    int32_t* w0;                   // rest groups of every second round (capacity n)
+    int32_t* w1;                   // the first round's list (filled by the caller, capacity n)
     int32_t* head;                 // head groups, 64-aligned per segment (capacity hcap)
-    int32_t* rest;                 // rest groups (capacity n)
+    int32_t* rest;                 // rest groups of the other rounds (capacity n)
     int32_t* rhb;                  // [n] at the first rest item of each 64-item group: the
                                    // segment's head rows before it in position order
-    uint32_t* hval;                // [d][hcap] head candidate bit patterns (pads = all ones)
+    uint32_t* hval;                // [d][hcap] head candidate bit patterns
     uint32_t* hlo;                 // [d][tcap] per-tile lower corners
     uint32_t* hhi;                 // [d][tcap] per-tile upper corners
     int64_t hcap, tcap;
     uint32_t* seg_min; uint32_t* seg_max;   // [nseg]
-    int32_t* hist;                 // [nseg * kBins]
-    int32_t* seg_info;             // [nseg * 8] per-segment counters / offsets
+    int32_t* hist;                 // [2][nseg * kBins] (by round parity)
+    int32_t* seg_info;             // [2][nseg * 8] per-segment counters / offsets (by round parity)
     uint8_t* dom;                  // [n] dominated flags
     int32_t* tile_off;             // [2 * (nseg + 1)] item-tile offsets for head / rest
-    int32_t* counters;             // [3 * 16]: the output count, then two per-round sets
-    unsigned long long* tests;     // [3] dominance-test counters (head, rest, per-segment max)
+    int32_t* counters;             // [3 * 16]: the run's counters, then two per-round sets
+    unsigned long long* tests;     // [3] dominance-test counters (head, rest, spare)
     int32_t* work;                 // [kWorkCounters * kCounterStride] work counters of the test launch
-    int32_t* scan;                 // [n] rest-compaction scratch
+    int32_t* scan;                 // [engine_scan_elems(n)] per-block counts of the split
     int32_t* scan_tmp;             // scan scratch for n values
 };
 int64_t engine_head_capacity(int64_t n, int32_t nseg);
+int64_t engine_scan_elems(int64_t n);
 constexpr int kBins = 1024;
 struct EngineProblem {
     const float* xp; int64_t ldp; int32_t d; int32_t n_pos;  // rows live at positions [0, n_pos)
     const float* fsum;             // score per position
     const int32_t* seg_of_pos;     // segment of a position (nullptr = single segment)
     int32_t nseg;
-    unsigned long long* seg_tests; // optional [nseg]: tests added per segment (the caller zeroes)
-    const int32_t* items; int32_t n_items;  // initial work list (positions)
-    uint8_t* flag_out;             // [n_pos] set to 1 for skyline items (must be zeroed)
+    unsigned long long* seg_tests; // optional [nseg]: tests added per segment
+    bool zero_seg_tests;           // the run zeroes seg_tests first (else the caller has)
+    const int32_t* items;          // initial work list (positions); not one of the engine's buffers
+    int32_t n_items;               // its length, when n_items_dev is null
+    const int32_t* n_items_dev;    // its length on the device (or null)
+    int64_t ub_items;              // with n_items_dev: an upper bound on that length
+    uint8_t* flag_out;             // [n_pos] zeroed by the run; 1 for every row that entered a head
+    int64_t* out_rounds;           // optional device words written at the end of the run: rounds
+    int64_t* out_tests;            //   with live items, dominance tests evaluated, and the largest
+    int64_t* out_tests_max;        //   count of one segment (the total without seg_tests)
     void* const* ev_begin;         // optional timing events around the test launches
     void* const* ev_end;
     int32_t ev_cap;
     int32_t* ev_used;              // host counter, advanced per recorded pair
-    int32_t* host_scratch;         // optional pinned host memory (2 x 16 int32): with it and the
-    void* round_events[2];         // two events, rounds are launched one ahead of the readback
 };
-// tests_max: the largest per-segment count in seg_tests after the run (tests when there is none)
-struct EngineResult { int32_t count; int32_t rounds; int64_t tests; int64_t tests_max; };
-sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,
-                      EngineResult* res, hipStream_t st);
+// A run queues a fixed launch sequence (no host synchronisation). Afterwards the skyline of
+// every segment is the set of positions with flag_out = 1 and b.dom = 0.
+sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream_t st);
 // helpers used by the API layer
-// (scan_tmp: scan_tmp_elems(n) int32 of scratch, for these two and launch_final_output)
+// (scan_tmp: scan_tmp_elems(n) int32 of scratch, for these and launch_final_output)
 sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_pos, int32_t n,
                                 int32_t* out, int32_t* count, int32_t* scan_tmp, hipStream_t st,
                                 const uint8_t* keep = nullptr);
@@ -283,13 +292,21 @@ sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
 // dst[rowid[q]] = src[q] for q < n (int32 and/or uint8 arrays)
 sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
                                int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st);
-sky_status launch_compact_flags(const uint8_t* flags, int32_t n, int32_t* out, int32_t* count,
-                                int32_t* scan_tmp, hipStream_t st);
-sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t* rowid,
-                               int64_t n, uint8_t* member_tmp, uint8_t* member_out,
-                               int64_t* sky_idx, int64_t cap, int64_t* dev_count,
-                               int32_t* pos_tmp, int32_t* scan_tmp, int32_t* dev_status,
-                               hipStream_t st);
+// dst[rowid[q]] = src[q] && !(drop && drop[q]) for q < n
+sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,
+                                    uint8_t* dst, hipStream_t st);
+// positions i < n with flags[i] != 0 and (drop null or drop[i] == 0), in order, into out; their
+// number into *count32 and *count64 (either may be null); with bake, flags[i] is rewritten to
+// the selection
+sky_status launch_compact_flags(uint8_t* flags, const uint8_t* drop, bool bake, int32_t n, int32_t* out,
+                                int32_t* count32, int64_t* count64, int32_t* scan_tmp, hipStream_t st);
+// ascending rows of the positions list[0, *count) (count on the device, at most n):
+// sky_idx[0, min(count, cap)), *dev_count = count (SKY_ERR_CAPACITY above cap), member_out[row]
+// (optional), and pos_tmp[row] = the row's index in sky_idx for every skyline row
+sky_status launch_final_output(const int32_t* list, const int32_t* count, const int32_t* rowid, int64_t n,
+                               uint8_t* member_tmp, uint8_t* member_out, int64_t* sky_idx,
+                               int64_t cap, int64_t* dev_count, int32_t* pos_tmp, int32_t* scan_tmp,
+                               int32_t* dev_status, hipStream_t st);
 
 // sky_gres.hip
 // Prepared candidate store: segments 64-aligned in Hilbert order, padding value 2.0.
@@ -309,6 +326,7 @@ struct GresTargets {
     int32_t* ge;                   // [tvcap] result per target
     int32_t* gstart;               // [tvcap] highest level worth searching per target
     int32_t* work;                 // work counters of the search (zeroed before each launch)
+    int32_t* params;               // [16] the search's shape when its target count is on the device
 };
 void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg);
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);
@@ -317,10 +335,15 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
                                int64_t s, const GresStore& store, const GresPrepTmp& tmp,
                                int32_t* dev_status, hipStream_t st);
 // Store from a plan's partition-contiguous copy xp: the candidates are the rows at positions
-// pos[0, s) (ascending, hence curve order); perm[slot] = idx_of_row[rowid[pos]].
+// pos[0, s) (ascending, hence curve order), s = min(*s_dev, cap) read on the device (more than
+// cap raises SKY_ERR_CAPACITY); perm[slot] = idx_of_row[rowid[pos]]. The store is carved for cap.
 sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
-                                         int64_t s, const int32_t* rowid, const int32_t* idx_of_row,
-                                         const GresStore& store, hipStream_t st);
+                                         int64_t cap, const int32_t* s_dev, const int32_t* rowid,
+                                         const int32_t* idx_of_row, const GresStore& store,
+                                         int32_t* dev_status, hipStream_t st);
+// Targets = every candidate of a one-segment store whose count is on the device (min(*s_dev, cap)).
+sky_status launch_gres_targets_all(const GresStore& store, int32_t d, int64_t cap, const int32_t* s_dev,
+                                   const GresTargets& tg, hipStream_t st);
 sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t nt, int64_t s, const GresStore& store, const GresTargets& tg,
                                int32_t* dev_status, hipStream_t st);
@@ -342,9 +365,17 @@ sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int
                                 int32_t nseg, int64_t* sky_off, int32_t* cand_off, hipStream_t st);
 // Work table of the segmented search: per workgroup (segment, first target, end target).
 constexpr int kGresWgEntry = 3;
-int32_t gres_auto_mapping(int64_t s, int32_t g_max);
+// measured (both mappings with per-target start levels): lanes over 64 levels pay off when
+// many levels lie below the start levels (g_max >= 2^17) or on small skylines with
+// g_max > 1000; otherwise the banded tile walk is faster
+__host__ __device__ inline int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
+    if (s > 8192) return SKY_GRES_TILES;
+    return (g_max >= (1 << 17) || (g_max > 1000 && s <= 1024)) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
+}
+// nt_dev (one segment, no table): the target count is min(*nt_dev, nt) on the device, nt being
+// an upper bound; the mapping (AUTO included) and the work split are then decided on the device
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
-                              const GresTargets& tg, int64_t nt, const int32_t* wg_table,
+                              const GresTargets& tg, int64_t nt, const int32_t* nt_dev, const int32_t* wg_table,
                               int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
                               unsigned long long* dev_tests, hipStream_t st);

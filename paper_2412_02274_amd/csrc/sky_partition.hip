@@ -382,10 +382,69 @@ int64_t partition_hist_elems(int64_t n, int32_t p) {
         default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;               \
     }
 
+// Angular bucket thresholds (Eq. (1)): tan2[k] = tan^2(k pi / (2m)) in FP64, tan2[0] = 0. A
+// row's bucket along an angle is the number of k in [1, m-1] whose threshold its ratio reaches.
+__global__ void angular_table_kernel(int32_t m, double* __restrict__ tan2) {
+    for (int32_t k = threadIdx.x; k <= m; k += blockDim.x) {
+        const double t = tan((double)k * 3.14159265358979323846 / (2.0 * (double)m));
+        tan2[k] = k == 0 ? 0.0 : t * t;
+    }
+}
+
+// Partition statistics as int64 words: out[0] = Grid cells pruned by grid dominance that hold
+// rows, out[1] = the rows inside them, out[2] = rows of the largest partition (one workgroup).
+__global__ void __launch_bounds__(kBlock) partition_stats_kernel(const int32_t* __restrict__ part_off,
+                                                                  const uint8_t* __restrict__ pruned,
+                                                                  int32_t p, int64_t* __restrict__ out) {
+    __shared__ int64_t red[3][kBlock / kWave];
+    int64_t pc = 0, pr = 0, mx = 0;
+    for (int32_t j = threadIdx.x; j < p; j += kBlock) {
+        const int64_t sz = (int64_t)part_off[j + 1] - part_off[j];
+        mx = sz > mx ? sz : mx;
+        if (pruned[j] && sz > 0) {
+            ++pc;
+            pr += sz;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        pc += __shfl_xor(pc, off, kWave);
+        pr += __shfl_xor(pr, off, kWave);
+        const int64_t o = __shfl_xor(mx, off, kWave);
+        mx = o > mx ? o : mx;
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / kWave] = pc;
+        red[1][threadIdx.x / kWave] = pr;
+        red[2][threadIdx.x / kWave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            pc += red[0][w];
+            pr += red[1][w];
+            mx = red[2][w] > mx ? red[2][w] : mx;
+        }
+        out[0] = pc;
+        out[1] = pr;
+        out[2] = mx;
+    }
+}
+
+sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned, int32_t p, int64_t* out,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(partition_stats_kernel, dim3(1), dim3(kBlock), 0, st, part_off, pruned, p, out);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const int64_t n = a.n;
     const uint32_t rblocks = (uint32_t)ceil_div(n, kBlock);
     // 1. partition of every row (Grid / Angular directly, Sliced from the rank order)
+    if (a.scheme == SKY_ANGULAR) {
+        hipLaunchKernelGGL(angular_table_kernel, dim3(1), dim3(256), 0, st, a.m, a.tan2);
+        SKY_HIP(hipGetLastError());
+    }
     if (a.scheme == SKY_GRID || a.scheme == SKY_ANGULAR) {
         SKY_DISPATCH_D(a.d, part_id_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld,
                        a.scheme, a.m, a.tan2, a.part_of_row, a.dev_status);

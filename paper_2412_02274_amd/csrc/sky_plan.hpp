@@ -32,18 +32,26 @@ struct sky_plan {
     sky::EngineBuffers eng{};
     uint8_t *local_flag = nullptr, *final_flag = nullptr, *member_tmp = nullptr;
     int32_t *local_list = nullptr, *final_list = nullptr, *pos_tmp = nullptr, *count_tmp = nullptr;
-    // host copies
-    double* tan2_host = nullptr;
+    int64_t* dinfo = nullptr;  // [kDinfo] device-side counters of sky_info (D_* below)
+    int64_t merge_cap = 0;     // sky_idx capacity of the last sky_merge
+    hipStream_t last_stream = nullptr;  // stream of the last call that queued work
+    // host side
     void* const* ev_begin = nullptr;
     void* const* ev_end = nullptr;
     int32_t ev_cap = 0;
     int32_t ev_used = 0;
-    int32_t* host_scratch = nullptr;     // caller's pinned host memory (sky_plan_set_host_scratch)
-    void* round_ev[2] = {nullptr, nullptr};
     sky_info info{};
 };
 
 namespace sky {
+
+// device-side counters of a plan (int64 words of sky_plan::dinfo)
+enum {
+    D_PRUNED_CELLS = 0, D_PRUNED_ROWS, D_MAX_PART, D_ROUNDS_LOCAL, D_ROUNDS_MERGE, D_LOCAL_COUNT,
+    D_SKY_COUNT, D_TESTS_LOCAL, D_TESTS_MERGE, D_TESTS_LOCAL_MAX, kDinfo = 16
+};
+// count_tmp words: the first round's list length, the union's, the skyline's
+enum { CT_LIST = 0, CT_UNION = 1, CT_SKY = 2 };
 
 constexpr int32_t kMaxRows = 0x7FFFFFFF;
 constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset within 32 bits

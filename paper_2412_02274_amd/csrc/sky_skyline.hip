@@ -6,9 +6,10 @@
 // score; Sec. 2 scoring functions, Sec. 4 SFS):
 //   1. per segment, the FP32 attribute sum f of the live rows is binned between the
 //      segment's min and max; the head is the set of rows in the lowest bins holding at
-//      least kHead rows (all the live rows once there are at most kAllHead of them, which
-//      ends the segment in one all-pairs round instead of several small ones). f is monotone: a row dominating another has f <= the other's f
-//      (FP32 additions are monotone), so every dominator of a head row is itself in the head.
+//      least H_r rows (all the live rows once there are at most A_r of them, which ends the
+//      segment in one all-pairs round instead of several small ones). f is monotone: a row
+//      dominating another has f <= the other's f (FP32 additions are monotone), so every
+//      dominator of a head row is itself in the head.
 //   2. head skyline: every head row is tested against the other head rows of its segment.
 //      The survivors are exactly the segment's skyline rows inside the head (their
 //      dominators would be in the head), so they are final.
@@ -17,6 +18,18 @@
 //      testing against all head rows is exact); the survivors form the next live set. Every
 //      head row leaves the live set, so the rounds terminate.
 // Rows are compared through their canonical FP32 bit patterns (exact for [0, 1) data).
+//
+// Scheduling without the host. The host never reads a count back: every kernel reads its
+// item count on the device, grids are sized by upper bounds known before the run, and the
+// number of rounds is fixed in advance. Round r uses H_r = 8192 * 4^(r-1) and
+// A_r = 65536 * 16^(r-1); the host stops at the first round whose bound on the live rows is at
+// most A_r, and that round takes every live row into the head, so the run always ends there
+// (two rounds up to about 10^6 rows, three up to 1.6 * 10^7).
+// Rounds after the data ran out find no live item and do nothing. A run is therefore a fixed
+// launch sequence that a HIP graph can capture.
+// The result is a pair of byte arrays: flag_out[pos] = 1 for every row that entered a head,
+// dom[pos] = 1 for every row found dominated; the skyline rows are those with flag_out = 1 and
+// dom = 0.
 //
 // Spatial pruning. Positions index a partition-contiguous copy whose rows are in Hilbert-curve
 // order inside each partition, and every list of the engine stays in position order
@@ -43,18 +56,33 @@ namespace sky {
 
 namespace {
 
-constexpr int kHead = 8192;   // head rows per segment and round (target)
-constexpr int kAllHead = 65536;  // a segment with at most this many live rows takes them all
+constexpr int kHead = 8192;      // head rows per segment in the first round (target)
+constexpr int kAllHead = 65536;  // first round: a segment with at most this many live rows takes them all
+constexpr int kMaxRounds = 16;   // schedule cap (the last round takes every live row)
 constexpr int kTargetWaves = 8192;  // waves per test launch the item split aims at
 constexpr int kTile = 64;     // candidates per tile box
 constexpr uint32_t kPad = 0x7FFFFFFFu;  // padding candidates: above every real value, also as int32
 constexpr int kBoxLds = 4096;           // uint32 tile-box values cached in LDS per workgroup
 constexpr uint32_t kMaxGrid = 8192;     // workgroups of the grid-stride kernels
+constexpr uint32_t kTestGridLater = 8192;  // most workgroups of a test launch after the first round
 
 // seg_info layout per segment (int32 x kInfo)
 enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, SI_HEADPRE, kInfo = 8 };
-// global counters
-enum { C_NEXT = 0, C_OUT, C_HTILES, C_RTILES, C_MAXH, C_HTOT, C_RTOT, C_TPUH, C_TPUR, kCounters = 16 };
+// per-round counters (two sets, alternating with the round's parity)
+enum { C_SPARE = 0, C_HTILES, C_RTILES, C_MAXH, C_HTOT, C_RTOT, C_TPUH, C_TPUR, kCounters = 16 };
+// counters of the whole run (the set before the two round sets)
+enum { G_ROUNDS = 0 };
+
+// head target (grows 4x per round) and all-head limit (16x per round) of round r (from 1)
+__host__ __device__ inline int64_t round_head(int32_t r) {
+    const int64_t v = (int64_t)kHead << (2 * (r - 1));
+    return v < 0x7FFFFFFF ? v : 0x7FFFFFFF;
+}
+__host__ __device__ inline int64_t round_all(int32_t r) {
+    if (r > 5) return 0x7FFFFFFF;
+    const int64_t v = (int64_t)kAllHead << (4 * (r - 1));
+    return v < 0x7FFFFFFF ? v : 0x7FFFFFFF;
+}
 
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
@@ -69,8 +97,6 @@ __device__ __forceinline__ int32_t seg_of(const int32_t* seg_of_pos, int32_t pos
     return seg_of_pos ? seg_of_pos[pos] : 0;
 }
 
-// Wave-aggregated "slot = atomicAdd(&ctr[key*stride], 1)": one atomic per distinct key in the
-// wave; every active lane gets a unique slot.
 // Bitwise OR of v over the 64 lanes (every lane receives it).
 __device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
 #pragma unroll
@@ -88,39 +114,28 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
     return v;
 }
 
-__device__ __forceinline__ int32_t wave_slot(int32_t* ctr, int32_t stride, int32_t key, bool active) {
-    const int lane = (int)lane_id();
-    const uint64_t lt = __lanemask_lt();
-    uint64_t act = __ballot(active);
-    int32_t slot = 0;
-    while (act) {
-        const int leader = __ffsll((unsigned long long)act) - 1;
-        const int32_t kl = __shfl(key, leader, kWave);
-        const bool mine = active && key == kl;
-        const uint64_t peers = __ballot(mine);
-        int32_t base = 0;
-        if (lane == leader) base = atomicAdd(&ctr[(int64_t)kl * stride], (int32_t)__popcll(peers));
-        base = __shfl(base, leader, kWave);
-        if (mine) slot = base + (int32_t)__popcll(peers & lt);
-        act &= ~peers;
+// Start of a run: output flags cleared, the round records and histograms of both parities
+// cleared, every segment's score range empty, counters zeroed (and the per-segment test
+// counters, when given).
+__global__ void __launch_bounds__(kBlock) engine_init_kernel(
+    int32_t n_pos, uint8_t* __restrict__ flag_out, int32_t nseg, int32_t* __restrict__ hist2,
+    int32_t* __restrict__ info2, uint32_t* __restrict__ smin, uint32_t* __restrict__ smax,
+    int32_t* __restrict__ counters, unsigned long long* __restrict__ tests,
+    unsigned long long* __restrict__ seg_tests) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gs = (int64_t)gridDim.x * kBlock;
+    const int64_t n16 = n_pos / 16;  // flag_out is 256-byte aligned
+    for (int64_t i = g; i < n16; i += gs) reinterpret_cast<uint4*>(flag_out)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = n16 * 16 + g; i < n_pos; i += gs) flag_out[i] = 0;
+    for (int64_t i = g; i < 2 * (int64_t)nseg * kBins; i += gs) hist2[i] = 0;
+    for (int64_t i = g; i < 2 * (int64_t)nseg * kInfo; i += gs) info2[i] = 0;
+    for (int64_t i = g; i < nseg; i += gs) {
+        smin[i] = 0xFFFFFFFFu;
+        smax[i] = 0u;
+        if (seg_tests) seg_tests[i] = 0ull;
     }
-    return slot;
-}
-
-__global__ void init_segments_kernel(int32_t nseg, uint32_t* __restrict__ smin,
-                                     uint32_t* __restrict__ smax, int32_t* __restrict__ hist,
-                                     int32_t* __restrict__ info, int32_t* __restrict__ counters,
-                                     int32_t reset_range) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < (int64_t)nseg * kBins) hist[i] = 0;
-    if (i < nseg) {
-        if (reset_range) {
-            smin[i] = 0xFFFFFFFFu;
-            smax[i] = 0u;
-        }
-        for (int j = 0; j < kInfo; ++j) info[i * kInfo + j] = 0;
-    }
-    if (i == 0) counters[C_NEXT] = 0;
+    if (g < 3 * kCounters) counters[g] = 0;
+    if (g < 3) tests[g] = 0ull;
 }
 
 // Multi-segment passes over a round's list. The list is in position order and segments are
@@ -134,19 +149,18 @@ __host__ __device__ constexpr int64_t seg_pass_blocks(int64_t n) {
     return (n + (int64_t)kBlock * kSegPer - 1) / ((int64_t)kBlock * kSegPer);
 }
 
+// Score range (min and max of f) of every segment over the first round's list.
 __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restrict__ items,
                                                          int32_t n_host, const int32_t* __restrict__ n_dev,
                                                          const float* __restrict__ fsum,
                                                          const int32_t* __restrict__ seg_of_pos,
                                                          uint32_t* __restrict__ smin,
-                                                         uint32_t* __restrict__ smax,
-                                                         int32_t* __restrict__ info) {
-    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
+                                                         uint32_t* __restrict__ smax) {
+    const int32_t n = n_dev ? *n_dev : n_host;
     const int lane = (int)lane_id();
     const int64_t wbase = ((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (kWave * kSegPer);
     int32_t cs = -1;  // segment of the lane's current run
     uint32_t cmin = 0xFFFFFFFFu, cmax = 0u;
-    int32_t ccnt = 0;
     for (int j = 0; j < kSegPer; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
         if (i >= n) break;
@@ -157,16 +171,13 @@ __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restric
             if (cs >= 0) {
                 atomicMin(&smin[cs], cmin);
                 atomicMax(&smax[cs], cmax);
-                atomicAdd(&info[cs * kInfo + SI_LIVE], ccnt);
             }
             cs = sg;
             cmin = fb;
             cmax = fb;
-            ccnt = 1;
         } else {
             cmin = fb < cmin ? fb : cmin;
             cmax = fb > cmax ? fb : cmax;
-            ++ccnt;
         }
     }
     const bool valid = cs >= 0;
@@ -177,19 +188,50 @@ __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restric
         const bool mine = valid && cs == sl;
         const uint64_t peers = __ballot(mine);
         uint32_t vmin = mine ? cmin : 0xFFFFFFFFu, vmax = mine ? cmax : 0u;
-        int32_t vcnt = mine ? ccnt : 0;
         for (int off = kWave / 2; off > 0; off >>= 1) {
             const uint32_t a = __shfl_xor(vmin, off, kWave), b = __shfl_xor(vmax, off, kWave);
             vmin = a < vmin ? a : vmin;
             vmax = b > vmax ? b : vmax;
-            vcnt += __shfl_xor(vcnt, off, kWave);
         }
         if (lane == leader) {
             atomicMin(&smin[sl], vmin);
             atomicMax(&smax[sl], vmax);
-            atomicAdd(&info[sl * kInfo + SI_LIVE], vcnt);
         }
         act &= ~peers;
+    }
+}
+
+// Single-segment variant: grid-stride with block reductions.
+__global__ void __launch_bounds__(kBlock) minmax1_kernel(const int32_t* __restrict__ items,
+                                                          int32_t n_host, const int32_t* __restrict__ n_dev,
+                                                          const float* __restrict__ fsum,
+                                                          uint32_t* __restrict__ smin,
+                                                          uint32_t* __restrict__ smax) {
+    const int32_t n = n_dev ? *n_dev : n_host;
+    __shared__ uint32_t rmin[kBlock / kWave], rmax[kBlock / kWave];
+    uint32_t vmin = 0xFFFFFFFFu, vmax = 0u;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        uint32_t fb = fbits(fsum[items[i]]);
+        vmin = fb < vmin ? fb : vmin;
+        vmax = fb > vmax ? fb : vmax;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        uint32_t a = __shfl_xor(vmin, off, kWave), b = __shfl_xor(vmax, off, kWave);
+        vmin = a < vmin ? a : vmin;
+        vmax = b > vmax ? b : vmax;
+    }
+    const int wave = threadIdx.x / kWave;
+    if (lane_id() == 0) { rmin[wave] = vmin; rmax[wave] = vmax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; ++w) {
+            vmin = rmin[w] < vmin ? rmin[w] : vmin;
+            vmax = rmax[w] > vmax ? rmax[w] : vmax;
+        }
+        if (vmin <= vmax) {
+            atomicMin(&smin[0], vmin);
+            atomicMax(&smax[0], vmax);
+        }
     }
 }
 
@@ -210,124 +252,22 @@ __device__ __forceinline__ int32_t item_bin(const float* fsum, const uint32_t* s
     return bin_of(fsum[pos], __uint_as_float(smin[s]), seg_scale(smin[s], smax[s]));
 }
 
-// Score histogram per segment. The block's items (consecutive, kSegPer * kBlock of them) go
-// into an LDS histogram of the segment of its first item, flushed once at the end; items of
-// any other segment (the block straddles a boundary) are counted with global atomics.
-__global__ void __launch_bounds__(kBlock) hist_kernel(const int32_t* __restrict__ items,
-                                                       int32_t n_host, const int32_t* __restrict__ n_dev,
-                                                       const float* __restrict__ fsum,
-                                                       const int32_t* __restrict__ seg_of_pos,
-                                                       const uint32_t* __restrict__ smin,
-                                                       const uint32_t* __restrict__ smax,
-                                                       int32_t* __restrict__ hist) {
-    __shared__ int32_t lh[kBins];
-    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    const int64_t bbase = (int64_t)blockIdx.x * kBlock * kSegPer;
-    for (int b = threadIdx.x; b < kBins; b += kBlock) lh[b] = 0;
-    const int32_t s0 = bbase < n ? seg_of(seg_of_pos, items[bbase]) : -1;  // block-uniform
-    __syncthreads();
-    if (s0 >= 0) {
-        const float lo0 = __uint_as_float(smin[s0]);
-        const float sc0 = seg_scale(smin[s0], smax[s0]);
-        const int lane = (int)lane_id();
-        const int64_t wbase = bbase + (int64_t)(threadIdx.x / kWave) * (kWave * kSegPer);
-        for (int j = 0; j < kSegPer; ++j) {
-            const int64_t i = wbase + (int64_t)j * kWave + lane;
-            if (i >= n) break;
-            const int32_t pos = items[i];
-            const int32_t sg = seg_of(seg_of_pos, pos);
-            if (sg == s0) atomicAdd(&lh[bin_of(fsum[pos], lo0, sc0)], 1);
-            else atomicAdd(&hist[(int64_t)sg * kBins + item_bin(fsum, smin, smax, sg, pos)], 1);
-        }
-    }
-    __syncthreads();
-    if (s0 >= 0)
-        for (int b = threadIdx.x; b < kBins; b += kBlock)
-            if (lh[b]) atomicAdd(&hist[(int64_t)s0 * kBins + b], lh[b]);
-}
-
-// Single-segment variants (the merge phase and unpartitioned data): grid-stride loops with
-// block-private LDS bins / block reductions, so that global atomics stay few.
-__global__ void __launch_bounds__(kBlock) minmax1_kernel(const int32_t* __restrict__ items,
-                                                          int32_t n_host, const int32_t* __restrict__ n_dev,
-                                                          const float* __restrict__ fsum,
-                                                          uint32_t* __restrict__ smin,
-                                                          uint32_t* __restrict__ smax,
-                                                          int32_t* __restrict__ info) {
-    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    __shared__ uint32_t rmin[kBlock / kWave], rmax[kBlock / kWave];
-    __shared__ int32_t rcnt[kBlock / kWave];
-    uint32_t vmin = 0xFFFFFFFFu, vmax = 0u;
-    int32_t cnt = 0;
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        uint32_t fb = fbits(fsum[items[i]]);
-        vmin = fb < vmin ? fb : vmin;
-        vmax = fb > vmax ? fb : vmax;
-        ++cnt;
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        uint32_t a = __shfl_xor(vmin, off, kWave), b = __shfl_xor(vmax, off, kWave);
-        vmin = a < vmin ? a : vmin;
-        vmax = b > vmax ? b : vmax;
-        cnt += __shfl_xor(cnt, off, kWave);
-    }
-    const int wave = threadIdx.x / kWave;
-    if (lane_id() == 0) { rmin[wave] = vmin; rmax[wave] = vmax; rcnt[wave] = cnt; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / kWave; ++w) {
-            vmin = rmin[w] < vmin ? rmin[w] : vmin;
-            vmax = rmax[w] > vmax ? rmax[w] : vmax;
-            cnt += rcnt[w];
-        }
-        if (cnt) {
-            atomicMin(&smin[0], vmin);
-            atomicMax(&smax[0], vmax);
-            atomicAdd(&info[SI_LIVE], cnt);
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) hist1_kernel(const int32_t* __restrict__ items,
-                                                        int32_t n_host, const int32_t* __restrict__ n_dev,
-                                                        const float* __restrict__ fsum,
-                                                        const uint32_t* __restrict__ smin,
-                                                        const uint32_t* __restrict__ smax,
-                                                        int32_t* __restrict__ hist,
-                                                        int32_t* __restrict__ info, int32_t count_live) {
-    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    __shared__ int32_t h[kBins];
-    if (count_live && threadIdx.x == 0) {
-        // items this block visits (grid-stride), added once per block
-        int32_t c = 0;
-        for (int32_t base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock)
-            c += n - base < kBlock ? n - base : kBlock;
-        if (c) atomicAdd(&info[SI_LIVE], c);
-    }
-    for (int b = threadIdx.x; b < kBins; b += kBlock) h[b] = 0;
-    __syncthreads();
-    const float lo = __uint_as_float(smin[0]);
-    const float scale = seg_scale(smin[0], smax[0]);
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock)
-        atomicAdd(&h[bin_of(fsum[items[i]], lo, scale)], 1);
-    __syncthreads();
-    for (int b = threadIdx.x; b < kBins; b += kBlock)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
-}
-
-// head threshold of segment s, by one wavefront: the lowest bins holding at least kHead rows
-// (or all the live rows, at most kAllHead)
-__device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int32_t* __restrict__ info) {
+// head threshold of segment s, by one wavefront: the lowest bins holding at least `want` rows
+// (all the live rows when there are at most `all_below` of them)
+__device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int32_t* __restrict__ info,
+                               int32_t want_head, int32_t all_below) {
     const int lane = (int)lane_id();
     const int32_t* h = hist + (int64_t)s * kBins;
-    int32_t live = info[s * kInfo + SI_LIVE];
+    const int32_t live = info[s * kInfo + SI_LIVE];
     // few rows left: all of them form the head, and the segment finishes in this round
-    const int32_t want = live <= kAllHead ? live : kHead;
+    const int32_t want = live <= all_below ? live : want_head;
+    int32_t hv[kBins / kWave];  // the whole histogram in flight at once (one round trip)
+#pragma unroll
+    for (int it = 0; it < kBins / kWave; ++it) hv[it] = h[it * kWave + lane];
     int32_t run = 0, bstar = kBins - 1, headn = live;
-    bool done = false;
-    for (int base = 0; base < kBins && !done; base += kWave) {
-        int32_t v = h[base + lane];
-        int32_t inc = v;
+#pragma unroll
+    for (int it = 0; it < kBins / kWave; ++it) {
+        int32_t inc = hv[it];
         for (int off = 1; off < kWave; off <<= 1) {
             int32_t o = __shfl_up(inc, off, kWave);
             if (lane >= off) inc += o;
@@ -335,9 +275,9 @@ __device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int3
         uint64_t hit = __ballot(run + inc >= want);
         if (hit) {
             int l = __ffsll((unsigned long long)hit) - 1;
-            bstar = base + l;
+            bstar = it * kWave + l;
             headn = run + __shfl(inc, l, kWave);
-            done = true;
+            break;
         }
         run += __shfl(inc, kWave - 1, kWave);
     }
@@ -348,24 +288,20 @@ __device__ void thresh_segment(int32_t s, const int32_t* __restrict__ hist, int3
     }
 }
 
-__global__ void __launch_bounds__(kWave) thresh_kernel(int32_t nseg, const int32_t* __restrict__ hist,
-                                                        int32_t* __restrict__ info) {
-    if ((int32_t)blockIdx.x < nseg) thresh_segment(blockIdx.x, hist, info);
+// the head thresholds of many segments at once, one wave each
+__global__ void __launch_bounds__(kBlock) thresh_kernel(int32_t nseg, const int32_t* __restrict__ hist,
+                                                         int32_t* __restrict__ info, int32_t want_head,
+                                                         int32_t all_below) {
+    const int32_t s = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (s < nseg) thresh_segment(s, hist, info, want_head, all_below);
 }
 
 // Per segment: list offset (scan of live counts), 64-aligned head offset (scan of head counts
-// rounded up to 64), rest offset, and the item-tile offsets of both groups; round totals.
-// Single workgroup, sequential over blocks of 256 segments.
-__global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg,
-                                                              int32_t* __restrict__ info,
-                                                              int32_t* __restrict__ tile_off,
-                                                              int32_t* __restrict__ counters,
-                                                              const int32_t* __restrict__ hist,
-                                                              int32_t fused_thresh) {
-    if (fused_thresh) {  // few segments: their thresholds first, one wave each
-        for (int32_t s = threadIdx.x / kWave; s < nseg; s += kBlock / kWave) thresh_segment(s, hist, info);
-        __syncthreads();
-    }
+// rounded up to 64), rest offset, and the item-tile offsets of both groups; round totals and
+// the test launch's work split. Run by one whole workgroup, sequential over blocks of 256
+// segments.
+__device__ void round_layout(int32_t nseg, int32_t* __restrict__ info, int32_t* __restrict__ tile_off,
+                             int32_t* __restrict__ counters) {
     // tiles per unit of the test launch, from the exact counts: split the head tiles of an item
     // group over several units when there are too few groups to fill the chip (kTargetWaves)
     __shared__ int64_t red[3][kBlock / kWave];
@@ -427,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg,
             const int32_t ntile = (hn + kTile - 1) / kTile;
             v[2] = (hn + kBlock - 1) / kBlock * ((ntile + tpu_h - 1) / tpu_h);  // head units
             v[3] = (rn + kBlock - 1) / kBlock * ((ntile + tpu_r - 1) / tpu_r);  // rest units
-            v[4] = info[s * kInfo + SI_LIVE];            // list items
+            v[4] = info[s * kInfo + SI_LIVE];            // live items
             v[5] = hn;                                   // head items (unaligned)
         }
         int32_t inc[Q];
@@ -480,14 +416,138 @@ __global__ void __launch_bounds__(kBlock) seg_offsets_kernel(int32_t nseg,
     }
 }
 
-// is_head flag per list item (for the stable split)
-// ---- two-kernel stable compactions ---------------------------------------------------------
-// Blocks of kCItems consecutive list entries; kernel 1 counts the kept entries of every block,
-// kernel 2 gets its block's prefix by summing the counts of the blocks before it (no waiting on
-// other blocks), ranks entries inside the block with wave ballots over 64-entry chunks in
-// order, and scatters. The result is in list order (stable).
+struct StatsArgs {
+    const int32_t* items; int32_t n_host; const int32_t* n_dev;  // the round's list
+    const uint8_t* dead;         // rounds after the first: items with dead[pos] != 0 are gone
+    const float* fsum; const int32_t* seg_of_pos; int32_t nseg;
+    const uint32_t* smin; const uint32_t* smax;
+    int32_t* hist; int32_t* info;           // this round's (its parity)
+    int32_t* hist_next; int32_t* info_next; // the next round's, cleared here
+};
+
+// First kernel of a round: clears the next round's records and histograms (the round that last
+// used that parity has finished) and adds the round's live items to their segment's live count
+// and score histogram. One segment: grid-stride with an LDS histogram. Several: every workgroup
+// takes a contiguous range of kBlock * kSegPer-item chunks (segments are runs of consecutive
+// items), histograms the segment of each chunk's first item in LDS (flushed when it changes)
+// and folds live counts into per-lane runs of one segment.
+template <bool MULTI>
+__global__ void __launch_bounds__(kBlock) stats_kernel(StatsArgs a) {
+    __shared__ int32_t lh[kBins];
+    __shared__ int32_t lcnt;
+    const int32_t n = a.n_dev ? *a.n_dev : a.n_host;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gs = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = g; i < (int64_t)a.nseg * kBins; i += gs) a.hist_next[i] = 0;
+    for (int64_t i = g; i < (int64_t)a.nseg * kInfo; i += gs) a.info_next[i] = 0;
+    for (int b = threadIdx.x; b < kBins; b += kBlock) lh[b] = 0;
+    if (threadIdx.x == 0) lcnt = 0;
+    __syncthreads();
+    const int lane = (int)lane_id();
+    if (!MULTI) {
+        const float lo = __uint_as_float(a.smin[0]);
+        const float scale = seg_scale(a.smin[0], a.smax[0]);
+        int32_t c = 0;
+        for (int64_t i = g; i < n; i += gs) {
+            const int32_t pos = a.items[i];
+            if (a.dead && a.dead[pos]) continue;
+            atomicAdd(&lh[bin_of(a.fsum[pos], lo, scale)], 1);
+            ++c;
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off, kWave);
+        if (lane == 0 && c) atomicAdd(&lcnt, c);
+        __syncthreads();
+        for (int b = threadIdx.x; b < kBins; b += kBlock)
+            if (lh[b]) atomicAdd(&a.hist[b], lh[b]);
+        if (threadIdx.x == 0 && lcnt) atomicAdd(&a.info[SI_LIVE], lcnt);
+        return;
+    }
+    constexpr int64_t kChunk = (int64_t)kBlock * kSegPer;
+    const int64_t nchunk = (n + kChunk - 1) / kChunk;
+    const int64_t per = (nchunk + gridDim.x - 1) / gridDim.x;
+    const int64_t c_end = ((int64_t)blockIdx.x + 1) * per < nchunk ? ((int64_t)blockIdx.x + 1) * per : nchunk;
+    int32_t hs = -1;  // segment whose histogram is in lh (block-uniform)
+    for (int64_t cidx = (int64_t)blockIdx.x * per; cidx < c_end; ++cidx) {
+        const int64_t bbase = cidx * kChunk;
+        const int32_t s0 = seg_of(a.seg_of_pos, a.items[bbase]);  // block-uniform
+        if (s0 != hs) {
+            __syncthreads();
+            if (hs >= 0)
+                for (int b = threadIdx.x; b < kBins; b += kBlock)
+                    if (lh[b]) {
+                        atomicAdd(&a.hist[(int64_t)hs * kBins + b], lh[b]);
+                        lh[b] = 0;
+                    }
+            hs = s0;
+            __syncthreads();
+        }
+        const float lo0 = __uint_as_float(a.smin[s0]);
+        const float sc0 = seg_scale(a.smin[s0], a.smax[s0]);
+        const int64_t wbase = bbase + (int64_t)(threadIdx.x / kWave) * (kWave * kSegPer);
+        int32_t cs = -1, ccnt = 0;  // the lane's current run of live items of one segment
+        for (int j = 0; j < kSegPer; ++j) {
+            const int64_t i = wbase + (int64_t)j * kWave + lane;
+            if (i >= n) break;
+            const int32_t pos = a.items[i];
+            if (a.dead && a.dead[pos]) continue;
+            const int32_t sg = seg_of(a.seg_of_pos, pos);
+            if (sg == s0) atomicAdd(&lh[bin_of(a.fsum[pos], lo0, sc0)], 1);
+            else atomicAdd(&a.hist[(int64_t)sg * kBins + item_bin(a.fsum, a.smin, a.smax, sg, pos)], 1);
+            if (sg != cs) {
+                if (cs >= 0) atomicAdd(&a.info[cs * kInfo + SI_LIVE], ccnt);
+                cs = sg;
+                ccnt = 1;
+            } else {
+                ++ccnt;
+            }
+        }
+        const bool valid = cs >= 0;
+        uint64_t act = __ballot(valid);
+        while (act) {
+            const int leader = __ffsll((unsigned long long)act) - 1;
+            const int32_t sl = __shfl(cs, leader, kWave);
+            const bool mine = valid && cs == sl;
+            const uint64_t peers = __ballot(mine);
+            int32_t v = mine ? ccnt : 0;
+            for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+            if (lane == leader) atomicAdd(&a.info[sl * kInfo + SI_LIVE], v);
+            act &= ~peers;
+        }
+    }
+    __syncthreads();
+    if (hs >= 0)
+        for (int b = threadIdx.x; b < kBins; b += kBlock)
+            if (lh[b]) atomicAdd(&a.hist[(int64_t)hs * kBins + b], lh[b]);
+}
+
+// The round's layout, one workgroup: every segment's head (thresh_segment), the offsets of its
+// groups and the test launch's split (round_layout); the test launch's work counters cleared;
+// the round counted when it has live items.
+__global__ void __launch_bounds__(kBlock) layout_kernel(int32_t nseg, const int32_t* __restrict__ hist,
+                                                         int32_t* __restrict__ info, int32_t* __restrict__ tile_off,
+                                                         int32_t* __restrict__ counters, int32_t* __restrict__ work,
+                                                         int32_t* __restrict__ gcounters, int32_t head_want,
+                                                         int32_t all_below, int32_t thresh_here) {
+    if (thresh_here) {  // few segments: their thresholds first, one wave each
+        const int wave = threadIdx.x / kWave;
+        for (int32_t s = wave; s < nseg; s += kBlock / kWave) thresh_segment(s, hist, info, head_want, all_below);
+        __syncthreads();
+    }
+    round_layout(nseg, info, tile_off, counters);
+    if (work)
+        for (int i = threadIdx.x; i < kWorkCounters * kCounterStride; i += kBlock) work[i] = 0;
+    if (threadIdx.x == 0 && counters[C_HTOT] > 0) ++gcounters[G_ROUNDS];
+}
+
+// ---- stable split of a round's list into head and rest groups ------------------------------
+// Chunks of kCItems consecutive list entries; every workgroup takes a contiguous range of
+// chunks. Kernel 1 counts the head entries and the live entries of every workgroup's range,
+// kernel 2 gets its range's prefixes by summing the counts of the workgroups before it (no
+// waiting on other workgroups), ranks entries inside each chunk with wave ballots over 64-entry
+// sub-chunks in order, and scatters. The result is in list order (stable).
 constexpr int kCItems = 1024;
-constexpr int kCChunks = kCItems / kWave;  // 64 chunks of 64 entries
+constexpr int kCChunks = kCItems / kWave;  // 16 sub-chunks of 64 entries
+constexpr int64_t kSplitGrid = 1024;       // most workgroups of a split launch
 
 // sum of cnt[0, b) by the whole block (every thread gets it)
 __device__ __forceinline__ int32_t block_prefix(const int32_t* __restrict__ cnt, int32_t b) {
@@ -503,190 +563,150 @@ __device__ __forceinline__ int32_t block_prefix(const int32_t* __restrict__ cnt,
     return t;
 }
 
-// in-order exclusive prefix of the kCChunks chunk counts of a block; chunk c of the block is
-// handled by wave c % 4 (entries b*kCItems + c*64 + lane)
-__device__ __forceinline__ void chunk_prefix(int32_t* chunk_cnt) {
+// in-order exclusive prefix of the kCChunks sub-chunk counts of a chunk (sub-chunk c is handled
+// by wave c % 4); *total gets their sum
+__device__ __forceinline__ void chunk_prefix(int32_t* chunk_cnt, int32_t* total) {
     __syncthreads();
     if (threadIdx.x < kWave) {
         const int lane = (int)lane_id();
-        int32_t v = chunk_cnt[lane];
+        int32_t v = lane < kCChunks ? chunk_cnt[lane] : 0;
         int32_t inc = v;
         for (int off = 1; off < kWave; off <<= 1) {
             const int32_t o = __shfl_up(inc, off, kWave);
             if (lane >= off) inc += o;
         }
-        chunk_cnt[lane] = inc - v;
+        if (lane < kCChunks) chunk_cnt[lane] = inc - v;
+        if (lane == kCChunks - 1) *total = inc;
     }
     __syncthreads();
 }
 
-__device__ __forceinline__ bool is_head(const int32_t* items, int32_t i, const float* fsum,
-                                        const int32_t* seg_of_pos, const uint32_t* smin,
-                                        const uint32_t* smax, const int32_t* info, int32_t& pos,
+__device__ __forceinline__ bool is_head(int32_t pos, const float* fsum, const int32_t* seg_of_pos,
+                                        const uint32_t* smin, const uint32_t* smax, const int32_t* info,
                                         int32_t& s) {
-    pos = items[i];
     s = seg_of(seg_of_pos, pos);
     return item_bin(fsum, smin, smax, s, pos) <= info[s * kInfo + SI_BSTAR];
 }
 
-__global__ void __launch_bounds__(kBlock) split_count_kernel(
-    const int32_t* __restrict__ items,
-    int32_t n_host, const int32_t* __restrict__ n_dev, const float* __restrict__ fsum,
-    const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
-    const uint32_t* __restrict__ smax, const int32_t* __restrict__ info, int32_t* __restrict__ bcnt) {
-    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    __shared__ int32_t part[kBlock / kWave];
+struct SplitArgs {
+    const int32_t* items; int32_t n_host; const int32_t* n_dev; const uint8_t* dead;
+    const float* fsum; const int32_t* seg_of_pos; const uint32_t* smin; const uint32_t* smax;
+    const int32_t* info;
+    int32_t* bcnt;              // [2][gridDim.x]: head entries, then live entries, per workgroup
+    int32_t* head; int32_t* rest; int32_t* rhb;
+    uint8_t* dom_clear;         // first round: dom of every list item cleared (else null)
+    uint8_t* flag_out;          // set to 1 for every head item
+};
+
+// the workgroup's chunk range [c0, c1)
+__device__ __forceinline__ void split_range(int32_t n, int64_t* c0, int64_t* c1) {
+    const int64_t nchunk = ((int64_t)n + kCItems - 1) / kCItems;
+    const int64_t per = (nchunk + gridDim.x - 1) / gridDim.x;
+    *c0 = (int64_t)blockIdx.x * per;
+    *c1 = *c0 + per < nchunk ? *c0 + per : nchunk;
+}
+
+__global__ void __launch_bounds__(kBlock) split_count_kernel(SplitArgs a) {
+    const int32_t n = a.n_dev ? *a.n_dev : a.n_host;
+    __shared__ int32_t part[2][kBlock / kWave];
     const int wave = threadIdx.x / kWave;
     const int lane = (int)lane_id();
-    int32_t c = 0;
-    for (int ch = wave; ch < kCChunks; ch += kBlock / kWave) {
-        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
-        int32_t pos, s;
-        const bool h = i < n && is_head(items, i, fsum, seg_of_pos, smin, smax, info, pos, s);
-        c += __popcll(__builtin_amdgcn_ballot_w64(h));
+    int64_t c0, c1;
+    split_range(n, &c0, &c1);
+    int32_t nh = 0, nl = 0;
+    const int64_t end = c1 * kCItems < n ? c1 * kCItems : n;
+    for (int64_t i = c0 * kCItems + threadIdx.x; i < end; i += kBlock) {
+        const int32_t pos = a.items[i];
+        const bool live = !a.dead || a.dead[pos] == 0;
+        int32_t sg;
+        const bool h = live && is_head(pos, a.fsum, a.seg_of_pos, a.smin, a.smax, a.info, sg);
+        nh += h;
+        nl += live;
     }
-    if (lane == 0) part[wave] = c;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        nh += __shfl_xor(nh, off, kWave);
+        nl += __shfl_xor(nl, off, kWave);
+    }
+    if (lane == 0) {
+        part[0][wave] = nh;
+        part[1][wave] = nl;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int32_t t = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
-        bcnt[blockIdx.x] = t;
+        int32_t th = 0, tl = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            th += part[0][w];
+            tl += part[1][w];
+        }
+        a.bcnt[blockIdx.x] = th;
+        a.bcnt[gridDim.x + blockIdx.x] = tl;
     }
 }
 
-// head entries -> their segment's head group, the others -> its rest group, both in list order;
-// every item's dominated flag is cleared
-__global__ void __launch_bounds__(kBlock) split_scatter_kernel(
-    const int32_t* __restrict__ items,
-    int32_t n_host, const int32_t* __restrict__ n_dev, const float* __restrict__ fsum,
-    const int32_t* __restrict__ seg_of_pos, const uint32_t* __restrict__ smin,
-    const uint32_t* __restrict__ smax, const int32_t* __restrict__ info,
-    const int32_t* __restrict__ bcnt, int32_t* __restrict__ head, int32_t* __restrict__ rest,
-    int32_t* __restrict__ rhb, uint8_t* __restrict__ dom) {
-    const int32_t n = n_dev ? *n_dev : n_host;  // a round launched ahead reads its count here
-    __shared__ int32_t chunk_cnt[kCChunks];
+// live head entries -> their segment's head group (and flag_out), the other live entries -> its
+// rest group, both in list order
+__global__ void __launch_bounds__(kBlock) split_scatter_kernel(SplitArgs a) {
+    const int32_t n = a.n_dev ? *a.n_dev : a.n_host;
+    __shared__ int32_t chunk_h[kCChunks], chunk_l[kCChunks];
+    __shared__ int32_t tot_h, tot_l;
     const int wave = threadIdx.x / kWave;
     const int lane = (int)lane_id();
-    const int32_t pre = block_prefix(bcnt, blockIdx.x);
+    int64_t c0, c1;
+    split_range(n, &c0, &c1);
+    int32_t pre_h = block_prefix(a.bcnt, blockIdx.x);
+    int32_t pre_l = block_prefix(a.bcnt + gridDim.x, blockIdx.x);
     constexpr int kPer = kCChunks / (kBlock / kWave);
-    int32_t mpos[kPer], mseg[kPer];
-    uint64_t mball[kPer];
+    const uint64_t lt = __lanemask_lt();
+    for (int64_t cidx = c0; cidx < c1; ++cidx) {
+        int32_t mpos[kPer], mseg[kPer];
+        uint64_t mh[kPer], ml[kPer];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int ch = wave + q * (kBlock / kWave);
-        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
-        int32_t pos = 0, sg = 0;
-        const bool h = i < n && is_head(items, i, fsum, seg_of_pos, smin, smax, info, pos, sg);
-        mpos[q] = i < n ? pos : -1;
-        mseg[q] = sg;
-        mball[q] = __builtin_amdgcn_ballot_w64(h);
-        if (lane == 0) chunk_cnt[ch] = __popcll(mball[q]);
-    }
-    chunk_prefix(chunk_cnt);
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int ch = wave + q * (kBlock / kWave);
-        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
-        if (mpos[q] < 0) continue;
-        const bool h = (mball[q] >> lane) & 1ull;
-        // head items before i in the whole list, minus those of earlier segments
-        const int32_t hscan = pre + chunk_cnt[ch] + __popcll(mball[q] & __lanemask_lt());
-        const int32_t* si = info + mseg[q] * kInfo;
-        const int32_t hr = hscan - si[SI_HEADPRE];
-        if (h) {
-            head[si[SI_HEADOFF] + hr] = mpos[q];
-        } else {
-            const int32_t ri = (i - si[SI_LISTOFF]) - hr;  // rest index in the segment
-            rest[si[SI_RESTOFF] + ri] = mpos[q];
-            // where the test kernel's wave of items [ri, ri + 64) starts in the head tiles
-            if ((ri & (kWave - 1)) == 0) rhb[si[SI_RESTOFF] + ri] = hr;
-        }
-        dom[mpos[q]] = 0;
-    }
-}
-
-// Blocks [0, cblocks): survivors per block of the rest list (as split_count_kernel). Blocks from
-// cblocks on: the head survivors -> output flags and output list (order irrelevant).
-__global__ void __launch_bounds__(kBlock) rest_count_kernel(const int32_t* __restrict__ rest,
-                                                             int32_t* __restrict__ counters,
-                                                             const uint8_t* __restrict__ dom,
-                                                             int32_t* __restrict__ bcnt, int32_t cblocks,
-                                                             const int32_t* __restrict__ head,
-                                                             uint8_t* __restrict__ flag_out,
-                                                             int32_t* __restrict__ out_list,
-                                                             int32_t* __restrict__ out_count) {
-    if ((int32_t)blockIdx.x >= cblocks) {
-        const int32_t htot = counters[C_HTOT];
-        const int32_t nb = (int32_t)gridDim.x - cblocks;
-        for (int32_t base = ((int32_t)blockIdx.x - cblocks) * kBlock; base < htot; base += nb * kBlock) {
-            const int32_t i = base + threadIdx.x;
-            bool keep = false;
-            int32_t pos = -1;
-            if (i < htot) {
-                pos = head[i];
-                keep = pos >= 0 && dom[pos] == 0;
+        for (int q = 0; q < kPer; ++q) {
+            const int ch = wave + q * (kBlock / kWave);
+            const int64_t i = cidx * kCItems + ch * kWave + lane;
+            int32_t pos = -1, sg = 0;
+            bool live = false, h = false;
+            if (i < n) {
+                pos = a.items[i];
+                live = !a.dead || a.dead[pos] == 0;
+                h = live && is_head(pos, a.fsum, a.seg_of_pos, a.smin, a.smax, a.info, sg);
             }
-            const int32_t os = wave_slot(out_count, 0, 0, keep);
-            if (keep) {
-                flag_out[pos] = 1;
-                out_list[os] = pos;
+            mpos[q] = live ? pos : -1;
+            mseg[q] = sg;
+            mh[q] = __builtin_amdgcn_ballot_w64(h);
+            ml[q] = __builtin_amdgcn_ballot_w64(live);
+            if (lane == 0) {
+                chunk_h[ch] = __popcll(mh[q]);
+                chunk_l[ch] = __popcll(ml[q]);
             }
         }
-        return;
-    }
-    __shared__ int32_t part[kBlock / kWave];
-    const int32_t n = counters[C_RTOT];
-    const int wave = threadIdx.x / kWave;
-    const int lane = (int)lane_id();
-    int32_t c = 0;
-    for (int ch = wave; ch < kCChunks; ch += kBlock / kWave) {
-        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
-        c += __popcll(__builtin_amdgcn_ballot_w64(i < n && dom[rest[i]] == 0));
-    }
-    if (lane == 0) part[wave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t t = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
-        bcnt[blockIdx.x] = t;
+        chunk_prefix(chunk_h, &tot_h);
+        chunk_prefix(chunk_l, &tot_l);
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int ch = wave + q * (kBlock / kWave);
+            if (mpos[q] < 0) continue;
+            const bool h = (mh[q] >> lane) & 1ull;
+            const int32_t* si = a.info + mseg[q] * kInfo;
+            // head / live items before this one in the whole list, minus those of earlier segments
+            const int32_t hr = pre_h + chunk_h[ch] + __popcll(mh[q] & lt) - si[SI_HEADPRE];
+            const int32_t lr = pre_l + chunk_l[ch] + __popcll(ml[q] & lt) - si[SI_LISTOFF];
+            if (h) {
+                a.head[si[SI_HEADOFF] + hr] = mpos[q];
+                a.flag_out[mpos[q]] = 1;
+            } else {
+                const int32_t ri = lr - hr;  // rest index in the segment
+                a.rest[si[SI_RESTOFF] + ri] = mpos[q];
+                // where the test kernel's wave of items [ri, ri + 64) starts in the head tiles
+                if ((ri & (kWave - 1)) == 0) a.rhb[si[SI_RESTOFF] + ri] = hr;
+            }
+            if (a.dom_clear) a.dom_clear[mpos[q]] = 0;
+        }
+        pre_h += tot_h;
+        pre_l += tot_l;
+        __syncthreads();  // chunk_h / chunk_l / totals are rewritten by the next chunk
     }
 }
-
-// survivors of the rest groups, in order, into the next work list; the last block writes the
-// total into counters[C_NEXT]
-__global__ void __launch_bounds__(kBlock) rest_scatter_kernel(const int32_t* __restrict__ rest,
-                                                               int32_t* __restrict__ counters,
-                                                               const uint8_t* __restrict__ dom,
-                                                               const int32_t* __restrict__ bcnt,
-                                                               int32_t* __restrict__ next) {
-    __shared__ int32_t chunk_cnt[kCChunks];
-    const int32_t n = counters[C_RTOT];
-    const int wave = threadIdx.x / kWave;
-    const int lane = (int)lane_id();
-    const int32_t pre = block_prefix(bcnt, blockIdx.x);
-    constexpr int kPer = kCChunks / (kBlock / kWave);
-    int32_t mpos[kPer];
-    uint64_t mball[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int ch = wave + q * (kBlock / kWave);
-        const int32_t i = blockIdx.x * kCItems + ch * kWave + lane;
-        const int32_t pos = i < n ? rest[i] : -1;
-        mpos[q] = pos;
-        mball[q] = __builtin_amdgcn_ballot_w64(pos >= 0 && dom[pos] == 0);
-        if (lane == 0) chunk_cnt[ch] = __popcll(mball[q]);
-    }
-    chunk_prefix(chunk_cnt);
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int ch = wave + q * (kBlock / kWave);
-        if ((mball[q] >> lane) & 1ull)
-            next[pre + chunk_cnt[ch] + __popcll(mball[q] & __lanemask_lt())] = mpos[q];
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) counters[C_NEXT] = pre + bcnt[blockIdx.x];
-}
-
-
 
 // largest s with info[s].field <= v (the field ascending in s)
 __device__ __forceinline__ int32_t find_segment(const int32_t* info, int32_t nseg, int field,
@@ -748,7 +768,6 @@ __device__ __forceinline__ int32_t tile_segment(const int32_t* tile_off, int32_t
     return lo;
 }
 
-// One item t (values tv, uniform across the wave) against the head group of its segment:
 // Dominance tests of items against the head group of their segment, register-tiled.
 // A work unit is (segment, a group of 256 items -- 64 per wave, one per lane --, a range of
 // the segment's head tiles). For every tile of the range a wave
@@ -759,7 +778,7 @@ __device__ __forceinline__ int32_t tile_segment(const int32_t* tile_off, int32_t
 //      the box against all of them: the item's values are broadcast from its lane, and
 //      s dominates t iff max_k(s_k - t_k) <= 0 and min_k(s_k - t_k) < 0 on the bit patterns as
 //      signed integers (canonical values of [0, 1) are below 2^30, so the differences are
-//      exact; padding slots hold 0x7FFFFFFF, whose differences are positive).
+//      exact; lanes past the tile's real rows take 0x7FFFFFFF, whose differences are positive).
 // One candidate load serves 64 items, so the loop is compute-bound. When a group's tiles are
 // split over several units, waves share deaths through dom[] every few tiles.
 // mode 0: items = the head group itself; mode 1: items = the rest group. A dominated item
@@ -893,11 +912,13 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
                     // and broadcast one by one, so every step keeps all 64 lanes busy (slots
                     // past the real candidates hold padding, which never dominates)
                     const uint32_t slot = (uint32_t)((t0 + c) * kTile + lane);
+                    const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
+                    // slots past the tile's real rows act as padding (their values are stale)
+                    const bool cin = lane < creal;
                     int32_t cv[DM];
 #pragma unroll
                     for (int k = 0; k < DM; ++k)
-                        if (k < d) cv[k] = (int32_t)ld32(hval + k * hcap, slot);
-                    const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
+                        if (k < d) cv[k] = cin ? (int32_t)ld32(hval + k * hcap, slot) : (int32_t)kPad;
                     const int32_t kk = __popcll(todo);
                     ntests += (unsigned long long)kk * (unsigned long long)creal;
                     const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
@@ -993,41 +1014,30 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
             unit(item / (kBlock / kWave), item % (kBlock / kWave));
         }
     } else {
-        for (int32_t ug = blockIdx.x; ug < nunits; ug += gridDim.x) unit(ug, wave);
+        // a contiguous range of units per workgroup (one unit each when the grid covers them):
+        // the units of a segment are consecutive, so its tile boxes stay in LDS
+        const int32_t per = (nunits + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+        const int32_t u1 = ((int32_t)blockIdx.x + 1) * per < nunits ? ((int32_t)blockIdx.x + 1) * per : nunits;
+        for (int32_t ug = (int32_t)blockIdx.x * per; ug < u1; ++ug) unit(ug, wave);
     }
     if (lane == 0 && ntests_h) atomicAdd(&tests[0], ntests_h);
     if (lane == 0 && ntests_r) atomicAdd(&tests[1], ntests_r);
     if (seg_tests && lane == 0 && acc) atomicAdd(&seg_tests[acc_seg], acc);
 }
 
-
-
-
-// the padding slots at the end of the head buffer: all ones in every attribute
-__global__ void pad_slots_kernel(uint32_t* __restrict__ hval, int64_t hcap, int32_t d) {
-    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < d * kTile) {
-        const int32_t k = e / kTile, l = e - k * kTile;
-        hval[(int64_t)k * hcap + (hcap - kTile) + l] = kPad;
-    }
-}
-
-__global__ void zero_i32_kernel(int32_t* __restrict__ p, int32_t n) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-__global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int32_t n) {
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
-}
-
-// *out = max(v[0 .. n)), 0 when n == 0 (one workgroup)
-__global__ void __launch_bounds__(kBlock) max_u64_kernel(const unsigned long long* __restrict__ v,
-                                                          int32_t n, unsigned long long* __restrict__ out) {
+// End of a run: the dominance tests it evaluated (head and rest groups), the largest count of
+// one segment (the sum when no per-segment counters are kept) and the rounds that had live
+// items, as int64 words for the caller (each output may be null).
+__global__ void __launch_bounds__(kBlock) engine_finish_kernel(const unsigned long long* __restrict__ tests,
+                                                                const unsigned long long* __restrict__ seg_tests,
+                                                                int32_t nseg, const int32_t* __restrict__ gcounters,
+                                                                int64_t* __restrict__ out_rounds,
+                                                                int64_t* __restrict__ out_tests,
+                                                                int64_t* __restrict__ out_max) {
     __shared__ unsigned long long part[kBlock / kWave];
     unsigned long long m = 0;
-    for (int32_t i = threadIdx.x; i < n; i += kBlock) m = v[i] > m ? v[i] : m;
+    if (seg_tests)
+        for (int32_t i = threadIdx.x; i < nseg; i += kBlock) m = seg_tests[i] > m ? seg_tests[i] : m;
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const unsigned long long o = __shfl_xor(m, off);
         m = o > m ? o : m;
@@ -1036,20 +1046,11 @@ __global__ void __launch_bounds__(kBlock) max_u64_kernel(const unsigned long lon
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kBlock / kWave; ++w) m = part[w] > m ? part[w] : m;
-        *out = m;
+        const unsigned long long total = tests[0] + tests[1];
+        if (out_rounds) *out_rounds = gcounters[G_ROUNDS];
+        if (out_tests) *out_tests = (int64_t)total;
+        if (out_max) *out_max = (int64_t)(seg_tests ? m : total);
     }
-}
-
-// positions [0, n) whose segment is not skipped
-
-
-// ---- final output: ascending original row ids ------------------------------------------------
-__global__ void __launch_bounds__(kBlock) mark_rows_kernel(const int32_t* __restrict__ list,
-                                                            int32_t count,
-                                                            const int32_t* __restrict__ rowid,
-                                                            uint8_t* __restrict__ member) {
-    int32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < count) member[rowid[list[i]]] = 1;
 }
 
 __global__ void __launch_bounds__(kBlock) scatter_rows_i32_kernel(const int32_t* __restrict__ src,
@@ -1059,11 +1060,13 @@ __global__ void __launch_bounds__(kBlock) scatter_rows_i32_kernel(const int32_t*
     if (q < n) dst[rowid[q]] = src[q];
 }
 
+// dst[rowid[q]] = src[q], or 0 where drop[q] != 0 (drop may be null)
 __global__ void __launch_bounds__(kBlock) scatter_rows_u8_kernel(const uint8_t* __restrict__ src,
+                                                                  const uint8_t* __restrict__ drop,
                                                                   const int32_t* __restrict__ rowid,
                                                                   int64_t n, uint8_t* __restrict__ dst) {
     int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < n) dst[rowid[q]] = src[q];
+    if (q < n) dst[rowid[q]] = (drop && drop[q]) ? 0 : src[q];
 }
 
 __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
@@ -1079,16 +1082,34 @@ __global__ void __launch_bounds__(kBlock) iota_kernel(int32_t n, int32_t* __rest
     if (i == 0) *count = n;
 }
 
+// p[0, n) = 0 (p 16-byte aligned; grid-stride, 16 bytes per store)
+__global__ void __launch_bounds__(kBlock) zero_bytes_kernel(uint8_t* __restrict__ p, int64_t n) {
+    const int64_t n16 = n / 16;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x, gs = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = g; i < n16; i += gs) reinterpret_cast<uint4*>(p)[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int64_t i = n16 * 16 + g; i < n; i += gs) p[i] = 0;
+}
+
+// member[rowid[list[i]]] = 1 for i < *count (grid-stride)
+__global__ void __launch_bounds__(kBlock) mark_rows_kernel(const int32_t* __restrict__ list,
+                                                            const int32_t* __restrict__ count,
+                                                            const int32_t* __restrict__ rowid,
+                                                            uint8_t* __restrict__ member) {
+    const int32_t c = *count;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < c; i += gridDim.x * kBlock) member[rowid[list[i]]] = 1;
+}
+
 // ---- stable selection in three launches: per-block counts, their scan, then each block
 // re-derives its positions' predicate bits and writes the selected ones at its offset ---------
 constexpr int kSelPer = 16;                  // consecutive positions per thread
 constexpr int kSelChunk = kBlock * kSelPer;  // positions per block
 
-// position i is selected iff flags[i] != 0 (no flags: every position), keep[i] != 0 (if given)
-// and its segment is not skipped (if skip_seg is given)
+// position i is selected iff flags[i] != 0 (no flags: every position), keep[i] != 0 (if given),
+// drop[i] == 0 (if given) and its segment is not skipped (if skip_seg is given)
 struct SelPred {
     const uint8_t* flags;
     const uint8_t* keep;
+    const uint8_t* drop;
     const uint8_t* skip_seg;
     const int32_t* seg;
 };
@@ -1101,6 +1122,7 @@ __device__ __forceinline__ uint32_t sel_bits(const SelPred& p, int64_t base, int
         if (i < n) {
             bool v = p.flags ? p.flags[i] != 0 : true;
             if (p.keep) v = v && p.keep[i] != 0;
+            if (p.drop) v = v && p.drop[i] == 0;
             if (p.skip_seg) v = v && !p.skip_seg[p.seg[i]];
             m |= (v ? 1u : 0u) << j;
         }
@@ -1137,15 +1159,16 @@ __global__ void __launch_bounds__(kBlock) sel_count_kernel(SelPred p, int64_t n,
 }
 
 // out32[k] = the k-th selected position (int32 output), or out64[k] for k < cap (int64 output);
-// all_idx[i] (if given) = number of selected positions before i, for every i; flags_copy (if
-// given) = the selection as bytes; the last block stores the total in *count32 / *count64 and
-// raises SKY_ERR_CAPACITY when it exceeds cap (int64 output)
+// all_idx[i] (if given) = number of selected positions before i, for every selected i; flags_copy (if
+// given) = the selection as bytes (it may be the flags array itself: each thread rewrites only
+// the positions it has read); the last block stores the total in *count32 / *count64 and raises
+// SKY_ERR_CAPACITY when it exceeds cap (int64 output)
 __global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
                                                             const int32_t* __restrict__ blk_off,
                                                             int32_t* __restrict__ out32,
                                                             int64_t* __restrict__ out64, int64_t cap,
                                                             int32_t* __restrict__ all_idx,
-                                                            uint8_t* __restrict__ flags_copy,
+                                                            uint8_t* flags_copy,
                                                             int32_t* __restrict__ count32,
                                                             int64_t* __restrict__ count64,
                                                             int32_t* dev_status) {
@@ -1158,7 +1181,7 @@ __global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
         const int64_t i = base + j;
         if (i >= n) break;
         const bool v = (m >> j) & 1u;
-        if (all_idx) all_idx[i] = k;
+        if (all_idx && v) all_idx[i] = k;
         if (flags_copy) flags_copy[i] = v ? 1 : 0;
         if (v) {
             if (out32) out32[k] = (int32_t)i;
@@ -1175,7 +1198,6 @@ __global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
         }
     }
 }
-
 
 }  // namespace
 
@@ -1194,22 +1216,37 @@ __global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
 
 int64_t engine_head_capacity(int64_t n, int32_t nseg) { return n + (int64_t)kTile * nseg + kTile; }
 
-sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* out_list,
-                      EngineResult* res, hipStream_t st) {
-    res->count = 0;
-    res->rounds = 0;
-    res->tests = 0;
-    res->tests_max = 0;
+int64_t engine_scan_elems(int64_t n) { return 2 * (ceil_div(n > 0 ? n : 1, kCItems) + 1); }
+
+// The rounds of a run over at most `ub` live items: round r is the last one when its bound is
+// at most A_r (every segment then takes all of its live rows into the head). With one segment
+// every round takes at least H_r rows out of the live set, which lowers the next bound; with
+// several, a segment may hold every live row, so the bound stays.
+int32_t engine_rounds(int64_t ub, int32_t nseg, int64_t* ub_of_round) {
+    for (int32_t r = 1;; ++r) {
+        ub_of_round[r - 1] = ub;
+        if (ub <= round_all(r) || r == kMaxRounds) return r;
+        if (nseg == 1) ub = ub > round_head(r) ? ub - round_head(r) : 0;
+    }
+}
+
+sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream_t st) {
     const int32_t nseg = pb.nseg;
-    // counters: [0, kCounters) hold the output count; two per-round sets alternate after it, so
-    // a round launched ahead never overwrites the counters of the round being read back
-    int32_t* const out_count = b.counters + C_OUT;
-    auto round_counters = [&](int32_t r) { return b.counters + kCounters * (1 + (r & 1)); };
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, b.counters, (int32_t)(3 * kCounters));
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, b.tests, 3);
-    hipLaunchKernelGGL(pad_slots_kernel, dim3((uint32_t)ceil_div(pb.d * kTile, 256)), dim3(256), 0, st,
-                       b.hval, b.hcap, pb.d);
-    SKY_HIP(hipGetLastError());
+    int32_t* const gctr = b.counters;
+    auto ctr = [&](int32_t r) { return b.counters + kCounters * (1 + (r & 1)); };
+    auto hist_of = [&](int32_t r) { return b.hist + (int64_t)(r & 1) * nseg * kBins; };
+    auto info_of = [&](int32_t r) { return b.seg_info + (int64_t)(r & 1) * nseg * kInfo; };
+    auto grid = [](int64_t want) -> uint32_t {
+        return (uint32_t)(want < 1 ? 1 : (want > kMaxGrid ? kMaxGrid : want));
+    };
+    {
+        int64_t work = pb.n_pos / 16;
+        if (2 * (int64_t)nseg * kBins > work) work = 2 * (int64_t)nseg * kBins;
+        hipLaunchKernelGGL(engine_init_kernel, dim3(grid(ceil_div(work, kBlock))), dim3(kBlock), 0, st,
+                           pb.n_pos, pb.flag_out, nseg, b.hist, b.seg_info, b.seg_min, b.seg_max, b.counters,
+                           b.tests, pb.zero_seg_tests ? pb.seg_tests : nullptr);
+        SKY_HIP(hipGetLastError());
+    }
     // optional timing hooks around the dominance-test launches
     auto ev_rec = [&](bool begin) -> hipError_t {
         if (!pb.ev_begin || !pb.ev_end || !pb.ev_used || *pb.ev_used >= pb.ev_cap) return hipSuccess;
@@ -1218,187 +1255,101 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, int32_t* 
         if (!begin) ++*pb.ev_used;
         return r;
     };
-    auto grid = [](int64_t want) -> uint32_t {
-        return (uint32_t)(want < 1 ? 1 : (want > kMaxGrid ? kMaxGrid : want));
-    };
-    const int32_t* lists[2] = {b.w0, b.w1};
-    // Round r (1-based) reads list `cur` and writes the next one. Its item count is n_host for
-    // the first round, else the previous round's C_NEXT on the device (n_dev); ub bounds it
-    // from above and only sizes grids and work splits.
-    auto launch_round = [&](int32_t r, const int32_t* cur, int32_t* next, int32_t n_host,
-                            const int32_t* n_dev, int64_t ub) -> sky_status {
-        int32_t* cnt = round_counters(r);
-        const uint32_t iblocks = (uint32_t)ceil_div(ub, kBlock);
-        const int64_t hn = (int64_t)nseg * kBins;
-        // one segment: the score range of the first round serves every round (the live rows
-        // only ever shrink), so later rounds skip the min/max pass and count rows in hist1
-        const bool first = r == 1;
-        hipLaunchKernelGGL(init_segments_kernel, dim3((uint32_t)ceil_div(hn > nseg ? hn : nseg, 256)),
-                           dim3(256), 0, st, nseg, b.seg_min, b.seg_max, b.hist, b.seg_info, cnt,
-                           (int32_t)(nseg > 1 || first));
-        if (nseg == 1) {
-            const uint32_t sblocks = iblocks < 256 ? iblocks : 256;
-            if (first)
-                hipLaunchKernelGGL(minmax1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
-                                   pb.fsum, b.seg_min, b.seg_max, b.seg_info);
-            hipLaunchKernelGGL(hist1_kernel, dim3(sblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
-                               pb.fsum, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max, b.hist,
-                               b.seg_info, (int32_t)!first);
-        } else {
-            const uint32_t pblocks = (uint32_t)(seg_pass_blocks(ub) > 0 ? seg_pass_blocks(ub) : 1);
-            hipLaunchKernelGGL(minmax_kernel, dim3(pblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
-                               pb.fsum, pb.seg_of_pos, b.seg_min, b.seg_max, b.seg_info);
-            hipLaunchKernelGGL(hist_kernel, dim3(pblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
-                               pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min,
-                               (const uint32_t*)b.seg_max, b.hist);
-        }
-        const bool fused_thresh = nseg <= kBlock / kWave;
-        if (!fused_thresh)
-            hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)nseg), dim3(kWave), 0, st, nseg,
-                               (const int32_t*)b.hist, b.seg_info);
-        // (the offsets kernel also picks the test launch's work split from the exact counts)
-        hipLaunchKernelGGL(seg_offsets_kernel, dim3(1), dim3(kBlock), 0, st, nseg, b.seg_info, b.tile_off,
-                           cnt, (const int32_t*)b.hist, (int32_t)fused_thresh);
-        const uint32_t cblocks = (uint32_t)ceil_div(ub, kCItems);
-        hipLaunchKernelGGL(split_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
-                           pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                           (const int32_t*)b.seg_info, b.scan);
-        hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, cur, n_host, n_dev,
-                           pb.fsum, pb.seg_of_pos, (const uint32_t*)b.seg_min, (const uint32_t*)b.seg_max,
-                           (const int32_t*)b.seg_info, (const int32_t*)b.scan, b.head, b.rest, b.rhb, b.dom);
-        SKY_HIP(hipGetLastError());
-        const int64_t slot_bound = ub + (int64_t)kTile * nseg;
-        SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
-                       dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.seg_info,
-                       (const int32_t*)cnt, b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
-        SKY_HIP(hipGetLastError());
-        // one launch: the head skyline (every head row against the head rows of its segment)
-        // and the filter of the rest against the same head rows -- independent tests
-        SKY_HIP(ev_rec(true));
-        // grid-stride: enough workgroups for the split the device picks (about kTargetWaves
-        // waves), or one per item group when there are more
-        const int64_t want_wg = kTargetWaves / (kBlock / kWave);
-        const int64_t groups_ub = ceil_div(ub, kBlock) + 2 * (int64_t)nseg;
-        uint32_t tgrid = grid(groups_ub + 2 * want_wg);
-        // one segment: persistent workgroups fed from the work counters, as many as fit at once
-        // (a workgroup holds its LDS until its slowest wave is done, so one workgroup per unit
-        // left most of the chip idle behind a few long units)
-        int32_t* work = nullptr;
-        if (nseg == 1) {
-            const void* fn = nullptr;
-            SKY_KERNEL_PTR_D(pb.d, test_kernel, fn);
-            int32_t resident = 0;
-            SKY_TRY(resident_workgroups(fn, kBlock, 0, &resident));
-            if ((int64_t)tgrid > resident) {
-                tgrid = (uint32_t)resident;
-                work = b.work;
-                hipLaunchKernelGGL(zero_i32_kernel, dim3(kWorkCounters * kCounterStride / 64), dim3(64), 0, st,
-                                   work, (int32_t)(kWorkCounters * kCounterStride));
+    const int64_t ub0 = pb.n_items_dev ? pb.ub_items : pb.n_items;
+    if (ub0 > 0) {
+        int64_t ubs[kMaxRounds];
+        const int32_t R = engine_rounds(ub0, nseg, ubs);
+        // round r writes its rest groups into rest_buf[r & 1] and reads the previous round's
+        // (the caller's list in the first round)
+        int32_t* rest_buf[2] = {b.rest, b.w0};
+        for (int32_t r = 1; r <= R; ++r) {
+            const int64_t ub = ubs[r - 1];
+            const int32_t* items = r == 1 ? pb.items : rest_buf[(r - 1) & 1];
+            const int32_t n_host = r == 1 ? pb.n_items : 0;
+            const int32_t* n_dev = r == 1 ? pb.n_items_dev : ctr(r - 1) + C_RTOT;
+            const uint8_t* dead = r == 1 ? nullptr : b.dom;
+            const uint32_t iblocks = (uint32_t)ceil_div(ub, kBlock);
+            if (r == 1) {
+                if (nseg == 1)
+                    hipLaunchKernelGGL(minmax1_kernel, dim3(iblocks < 256 ? iblocks : 256), dim3(kBlock), 0, st,
+                                       items, n_host, n_dev, pb.fsum, b.seg_min, b.seg_max);
+                else
+                    hipLaunchKernelGGL(minmax_kernel, dim3((uint32_t)seg_pass_blocks(ub)), dim3(kBlock), 0, st,
+                                       items, n_host, n_dev, pb.fsum, pb.seg_of_pos, b.seg_min, b.seg_max);
+                SKY_HIP(hipGetLastError());
             }
-        }
-        SKY_DISPATCH_D(pb.d, test_kernel, dim3(tgrid),
-                       dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
-                       (const int32_t*)b.seg_info, (const int32_t*)b.head, (const int32_t*)b.rest,
-                       (const int32_t*)b.rhb, (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo,
-                       (const uint32_t*)b.hhi, b.tcap, (const int32_t*)cnt, b.dom, b.tests,
-                       pb.seg_tests, work);
-        SKY_HIP(ev_rec(false));
-        // the survivors of the rest groups, in order, are the next round's work list
-        // (and the head survivors into the output, in extra blocks of the same launch)
-        const uint32_t hblocks = grid(ceil_div(slot_bound, kBlock));
-        hipLaunchKernelGGL(rest_count_kernel, dim3(cblocks + hblocks), dim3(kBlock), 0, st,
-                           (const int32_t*)b.rest, cnt, (const uint8_t*)b.dom, b.scan, (int32_t)cblocks,
-                           (const int32_t*)b.head, pb.flag_out, out_list, out_count);
-        hipLaunchKernelGGL(rest_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, (const int32_t*)b.rest,
-                           cnt, (const uint8_t*)b.dom, (const int32_t*)b.scan, next);
-        SKY_HIP(hipGetLastError());
-        return SKY_OK;
-    };
-    // after round r: check its counters (exact input count in_r) and return its output count
-    auto check_round = [&](const int32_t* c, int64_t in_r, int32_t* nl_out) -> sky_status {
-        const int32_t htot = c[C_HTOT], rtot = c[C_RTOT], nl = c[C_NEXT];
-        if (htot <= 0 || htot > b.hcap || rtot < 0 || rtot >= in_r) return SKY_ERR_HIP;
-        // every round removes the head rows from the live set
-        if (nl < 0 || nl >= in_r || nl > rtot) return SKY_ERR_HIP;
-        *nl_out = nl;
-        return SKY_OK;
-    };
-    int32_t live = pb.n_items;
-    if (live > 0) {
-        // round r reads lists[(r + 1) & 1] (the caller's list for r = 1) and writes lists[r & 1]
-        auto list_in = [&](int32_t r) { return r == 1 ? pb.items : lists[(r + 1) & 1]; };
-        auto list_out = [&](int32_t r) { return const_cast<int32_t*>(lists[r & 1]); };
-        const bool ahead = pb.host_scratch && pb.round_events[0] && pb.round_events[1];
-        int64_t ub_next = 0;  // bound on the input of the round after the last one launched
-        auto bound_after = [&](int64_t in) -> int64_t {
-            // a segment with at most kAllHead live rows takes them all into its head, so a
-            // round whose whole input is that small leaves nothing for the next one (no empty
-            // round is launched ahead)
-            if (in <= kAllHead) return 0;
-            // a round takes at least min(kHead, live) rows of a lone segment into its head
-            if (nseg == 1) return in > kHead ? in - kHead : 0;
-            return in > 0 ? in - 1 : 0;
-        };
-        SKY_TRY(launch_round(1, list_in(1), list_out(1), live, nullptr, live));
-        int32_t launched = 1;
-        int64_t in_r = live;  // exact input count of the oldest round not yet checked
-        for (int32_t r = 1;; ++r) {
-            if (r > 1000000) return SKY_ERR_HIP;
-            int32_t* hs = ahead ? pb.host_scratch + kCounters * (r & 1) : nullptr;
-            if (ahead) {
-                SKY_HIP(hipMemcpyAsync(hs, round_counters(r), sizeof(int32_t) * kCounters,
-                                       hipMemcpyDeviceToHost, st));
-                SKY_HIP(hipEventRecord((hipEvent_t)pb.round_events[r & 1], st));
-                // launch the next round before waiting for this one: its kernels read their
-                // item count on the device and are sized by an upper bound
-                ub_next = bound_after(launched == r ? in_r : ub_next);
-                if (ub_next > 0) {
-                    SKY_TRY(launch_round(r + 1, list_in(r + 1), list_out(r + 1), 0,
-                                         round_counters(r) + C_NEXT, ub_next));
-                    launched = r + 1;
+            // the test launch: one segment runs persistent workgroups fed from work counters when
+            // more workgroups are wanted than the device holds at once
+            const int64_t want_wg = kTargetWaves / (kBlock / kWave);
+            const int64_t groups_ub = ceil_div(ub, kBlock) + 2 * (int64_t)nseg;
+            uint32_t tgrid = grid(groups_ub + 2 * want_wg);
+            if (r > 1 && tgrid > kTestGridLater) tgrid = kTestGridLater;
+            int32_t* work = nullptr;
+            if (nseg == 1) {
+                const void* fn = nullptr;
+                SKY_KERNEL_PTR_D(pb.d, test_kernel, fn);
+                int32_t resident = 0;
+                SKY_TRY(resident_workgroups(fn, kBlock, 0, &resident));
+                if ((int64_t)tgrid > resident) {
+                    tgrid = (uint32_t)resident;
+                    work = b.work;
                 }
-                SKY_HIP(hipEventSynchronize((hipEvent_t)pb.round_events[r & 1]));
-            } else {
-                int32_t c[kCounters];
-                SKY_HIP(hipMemcpyAsync(c, round_counters(r), sizeof(c), hipMemcpyDeviceToHost, st));
-                SKY_HIP(hipStreamSynchronize(st));
-                hs = c;
-                int32_t nl = 0;
-                SKY_TRY(check_round(hs, in_r, &nl));
-                res->rounds = r;
-                if (nl == 0) break;
-                SKY_TRY(launch_round(r + 1, list_in(r + 1), list_out(r + 1), nl, nullptr, nl));
-                launched = r + 1;
-                in_r = nl;
-                continue;
             }
-            int32_t nl = 0;
-            SKY_TRY(check_round(hs, in_r, &nl));
-            res->rounds = r;
-            if (nl == 0) break;  // a round launched ahead found nothing to do
-            if (launched == r) {
-                SKY_TRY(launch_round(r + 1, list_in(r + 1), list_out(r + 1), nl, nullptr, nl));
-                launched = r + 1;
-            } else if (nl > ub_next) {
-                return SKY_ERR_HIP;  // the bound the launched round was sized with was wrong
-            }
-            in_r = nl;
-            ub_next = nl;
+            StatsArgs sa{};
+            sa.items = items; sa.n_host = n_host; sa.n_dev = n_dev; sa.dead = dead;
+            sa.fsum = pb.fsum; sa.seg_of_pos = pb.seg_of_pos; sa.nseg = nseg;
+            sa.smin = b.seg_min; sa.smax = b.seg_max;
+            sa.hist = hist_of(r); sa.info = info_of(r);
+            sa.hist_next = hist_of(r + 1); sa.info_next = info_of(r + 1);
+            if (nseg == 1)
+                hipLaunchKernelGGL(stats_kernel<false>, dim3(iblocks < 256 ? iblocks : 256), dim3(kBlock), 0, st, sa);
+            else
+                hipLaunchKernelGGL(stats_kernel<true>, dim3(grid(seg_pass_blocks(ub))), dim3(kBlock), 0, st, sa);
+            SKY_HIP(hipGetLastError());
+            const int32_t want_head = (int32_t)round_head(r);
+            const int32_t all_below = r == R ? (int32_t)0x7FFFFFFF : (int32_t)round_all(r);
+            const bool thresh_here = nseg <= kBlock / kWave;
+            if (!thresh_here)
+                hipLaunchKernelGGL(thresh_kernel, dim3((uint32_t)ceil_div(nseg, kBlock / kWave)), dim3(kBlock), 0, st,
+                                   nseg, (const int32_t*)hist_of(r), info_of(r), want_head, all_below);
+            hipLaunchKernelGGL(layout_kernel, dim3(1), dim3(kBlock), 0, st, nseg, (const int32_t*)hist_of(r),
+                               info_of(r), b.tile_off, ctr(r), work, gctr, want_head, all_below,
+                               (int32_t)thresh_here);
+            SKY_HIP(hipGetLastError());
+            SplitArgs xa{};
+            xa.items = items; xa.n_host = n_host; xa.n_dev = n_dev; xa.dead = dead;
+            xa.fsum = pb.fsum; xa.seg_of_pos = pb.seg_of_pos; xa.smin = b.seg_min; xa.smax = b.seg_max;
+            xa.info = info_of(r); xa.bcnt = b.scan;
+            xa.head = b.head; xa.rest = rest_buf[r & 1]; xa.rhb = b.rhb;
+            xa.dom_clear = r == 1 ? b.dom : nullptr;
+            xa.flag_out = pb.flag_out;
+            const int64_t cb = ceil_div(ub, kCItems);
+            const uint32_t cblocks = (uint32_t)(cb > kSplitGrid ? kSplitGrid : cb);
+            hipLaunchKernelGGL(split_count_kernel, dim3(cblocks), dim3(kBlock), 0, st, xa);
+            hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, xa);
+            SKY_HIP(hipGetLastError());
+            const int64_t slot_bound = ub + (int64_t)kTile * nseg;
+            SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
+                           dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)info_of(r),
+                           (const int32_t*)ctr(r), b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
+            SKY_HIP(hipGetLastError());
+            // one launch: the head skyline (every head row against the head rows of its segment)
+            // and the filter of the rest against the same head rows -- independent tests
+            SKY_HIP(ev_rec(true));
+            SKY_DISPATCH_D(pb.d, test_kernel, dim3(tgrid),
+                           dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)b.tile_off,
+                           (const int32_t*)info_of(r), (const int32_t*)b.head, (const int32_t*)rest_buf[r & 1],
+                           (const int32_t*)b.rhb, (const uint32_t*)b.hval, b.hcap, (const uint32_t*)b.hlo,
+                           (const uint32_t*)b.hhi, b.tcap, (const int32_t*)ctr(r), b.dom, b.tests,
+                           pb.seg_tests, work);
+            SKY_HIP(hipGetLastError());
+            SKY_HIP(ev_rec(false));
         }
     }
-    if (pb.seg_tests) {
-        hipLaunchKernelGGL(max_u64_kernel, dim3(1), dim3(kBlock), 0, st,
-                           (const unsigned long long*)pb.seg_tests, nseg, b.tests + 2);
-        SKY_HIP(hipGetLastError());
-    }
-    int32_t outc = 0;
-    unsigned long long tests[3] = {0, 0, 0};
-    SKY_HIP(hipMemcpyAsync(&outc, out_count, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    SKY_HIP(hipMemcpyAsync(tests, b.tests, sizeof(tests), hipMemcpyDeviceToHost, st));
-    SKY_HIP(hipStreamSynchronize(st));
-    res->count = outc;
-    res->tests = (int64_t)(tests[0] + tests[1]);
-    res->tests_max = pb.seg_tests ? (int64_t)tests[2] : res->tests;
+    hipLaunchKernelGGL(engine_finish_kernel, dim3(1), dim3(kBlock), 0, st, (const unsigned long long*)b.tests,
+                       (const unsigned long long*)pb.seg_tests, nseg, (const int32_t*)gctr, pb.out_rounds,
+                       pb.out_tests, pb.out_tests_max);
+    SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
 
@@ -1429,18 +1380,18 @@ sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_p
         SKY_HIP(hipGetLastError());
         return SKY_OK;
     }
-    const SelPred p{nullptr, keep, skip_seg, skip_seg ? seg_of_pos : nullptr};
+    const SelPred p{nullptr, keep, nullptr, skip_seg, skip_seg ? seg_of_pos : nullptr};
     return launch_select(p, n, out, nullptr, 0, nullptr, nullptr, count, nullptr, nullptr, scan_tmp, st);
 }
 
-// Positions i with flags[i] != 0, in order (stable).
-sky_status launch_compact_flags(const uint8_t* flags, int32_t n, int32_t* out, int32_t* count,
-                                int32_t* scan_tmp, hipStream_t st) {
-    const SelPred p{flags, nullptr, nullptr, nullptr};
-    return launch_select(p, n, out, nullptr, 0, nullptr, nullptr, count, nullptr, nullptr, scan_tmp, st);
+// Positions i with flags[i] != 0 and (drop null or drop[i] == 0), in order (stable); with
+// bake, flags[i] is rewritten to the selection.
+sky_status launch_compact_flags(uint8_t* flags, const uint8_t* drop, bool bake, int32_t n, int32_t* out,
+                                int32_t* count32, int64_t* count64, int32_t* scan_tmp, hipStream_t st) {
+    const SelPred p{flags, nullptr, drop, nullptr, nullptr};
+    return launch_select(p, n, out, nullptr, (int64_t)n, nullptr, bake ? flags : nullptr, count32, count64,
+                         nullptr, scan_tmp, st);
 }
-
-
 
 sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
                                int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st) {
@@ -1450,8 +1401,17 @@ sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, co
         hipLaunchKernelGGL(scatter_rows_i32_kernel, dim3(nb), dim3(kBlock), 0, st, src_i32, rowid, n,
                            dst_i32);
     if (dst_u8)
-        hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3(nb), dim3(kBlock), 0, st, src_u8, rowid, n,
-                           dst_u8);
+        hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3(nb), dim3(kBlock), 0, st, src_u8,
+                           (const uint8_t*)nullptr, rowid, n, dst_u8);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,
+                                    uint8_t* dst, hipStream_t st) {
+    if (n <= 0) return SKY_OK;
+    hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0, st, src,
+                       drop, rowid, n, dst);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
@@ -1463,16 +1423,21 @@ sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st) {
     return SKY_OK;
 }
 
-sky_status launch_final_output(const int32_t* list, int32_t count, const int32_t* rowid, int64_t n,
+// The final skyline's rows in ascending order: member_tmp cleared, set at the rows of the
+// positions list[0, *count) (count on the device, at most n), then a selection over the rows.
+sky_status launch_final_output(const int32_t* list, const int32_t* count, const int32_t* rowid, int64_t n,
                                uint8_t* member_tmp, uint8_t* member_out, int64_t* sky_idx,
                                int64_t cap, int64_t* dev_count, int32_t* pos_tmp, int32_t* scan_tmp,
                                int32_t* dev_status, hipStream_t st) {
-    SKY_TRY(launch_fill_u8(member_tmp, n, 0, st));
-    if (count > 0)
-        hipLaunchKernelGGL(mark_rows_kernel, dim3((uint32_t)ceil_div(count, kBlock)), dim3(kBlock), 0,
-                           st, list, count, rowid, member_tmp);
+    const int64_t n16 = ceil_div(n, 16);
+    hipLaunchKernelGGL(zero_bytes_kernel, dim3((uint32_t)(ceil_div(n16, kBlock) > 2048 ? 2048 : ceil_div(n16, kBlock))),
+                       dim3(kBlock), 0, st, member_tmp, n);
+    const int64_t mb = ceil_div(n, kBlock);
+    hipLaunchKernelGGL(mark_rows_kernel, dim3((uint32_t)(mb > 1024 ? 1024 : mb)), dim3(kBlock), 0, st, list, count,
+                       rowid, member_tmp);
+    SKY_HIP(hipGetLastError());
     // ascending rows: pos_tmp[row] = the row's index in sky_idx (kept for the gres store)
-    const SelPred p{member_tmp, nullptr, nullptr, nullptr};
+    const SelPred p{member_tmp, nullptr, nullptr, nullptr, nullptr};
     return launch_select(p, n, nullptr, sky_idx, cap, pos_tmp, member_out, nullptr, dev_count, dev_status,
                          scan_tmp, st);
 }
