@@ -253,6 +253,21 @@ sky_status sky_project(const float* x_soa, int64_t n, int32_t d, int64_t ld, con
                        void* stream);
 
 /*
+ * sky_literal_level -- the exit bookkeeping of Alg. 1 as written (Sec. 3.2), for one level g,
+ * after the skyline of the projected candidates at g has been computed (sky_project, then the
+ * skyline path on the projected relation, whose sky_merge gives member[j] = 1 iff projected
+ * candidate j is in it): for every j < s with g_exit[j] == 0 (no level yet) and member[j] == 0,
+ * g_exit[j] = g. Call it for g = g_max, g_max - 1, ..., 2 on g_exit zeroed beforehand, then once
+ * with g = 1 (member may be null): every tuple still at 0 gets 1, it never left the skyline.
+ * The result equals gres_compute's g_exit for the same candidates. nil_left (device int32,
+ * optional, zeroed by the caller) gets the number of tuples still without a level added to it,
+ * for stopping early. member: device uint8[s]; g_exit: device int32[s]; g in [1, SKY_MAX_G].
+ * Never synchronises.
+ */
+sky_status sky_literal_level(const uint8_t* member, int64_t s, int32_t g, int32_t* g_exit, int32_t* nil_left,
+                             void* stream);
+
+/*
  * Workspace for gres_compute, in bytes. Returns 0 for invalid arguments.
  */
 size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max);
@@ -376,22 +391,23 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
  * skyline (Def. 1) and the gres (Def. 2 via Alg. 1) of each of its skyline tuples with its own
  * skyline as the candidate set -- exactly what the plain calls give for that relation alone;
  * rows of different relations never meet. All relations advance together: each skyline round
- * serves all of them, and the gres search of all of them is one launch over a device table of
- * work items (relation, range of its skyline tuples).
+ * serves all of them (one segment per relation), and the gres search of all of their skyline
+ * tuples is ONE persistent launch whose waves take (tuple, level band) pairs of any relation.
  *
- * Sequence: sky_batch_workspace_bytes -> sky_batch_create -> sky_batch_skylines ->
- * sky_batch_tune -> sky_batch_gres (repeatable) -> sky_batch_destroy.
+ * Sequence: sky_batch_workspace_bytes -> sky_batch_create -> (sky_batch_tune) ->
+ * sky_batch_skylines -> sky_batch_gres -> ... -> sky_batch_destroy. After sky_batch_create no
+ * call synchronises or reads anything back (sky_batch_info aside): a step sky_batch_skylines +
+ * sky_batch_gres, repeated on new values in x_soa, can be captured in one HIP graph and replayed.
  */
 typedef struct sky_batch sky_batch; /* opaque, host-side; refers to caller memory */
 
 typedef struct sky_tune {
-    int32_t mapping;        /* SKY_GRES_AUTO / SKY_GRES_TILES / SKY_GRES_LEVELS */
-    int32_t targets_per_wg; /* skyline tuples per work item (one workgroup of 8 wavefronts);
-                               0 = default (16); else 1..4096 */
+    int32_t mapping;        /* SKY_GRES_AUTO (by the largest relation's skyline) / SKY_GRES_TILES /
+                               SKY_GRES_LEVELS */
     int32_t near_first;     /* 1 = each tuple scans the candidate tiles next to its own place on
                                the curve first (default), 0 = tiles in curve order */
-    int32_t lpt;            /* 1 = work items ordered by estimated cost, heaviest first
-                               (default), 0 = relation order */
+    int32_t lpt;            /* 1 = the tuples of the relations with the largest skylines are
+                               searched first (default), 0 = relation order */
 } sky_tune;
 
 /*
@@ -402,50 +418,52 @@ typedef struct sky_tune {
 size_t sky_batch_workspace_bytes(const int64_t* offsets, int32_t nbatch, int32_t d);
 
 /*
- * sky_batch_create -- validates the arguments, copies the offsets to the workspace (waiting
- * for that copy, so the host array may be released on return) and queues the partition step:
- * every relation's rows, canonical and along a Hilbert curve, as one segment of a
- * segment-contiguous copy. x_soa: device float[d*ld], ld >= offsets[nbatch]. Values outside
- * the domain raise SKY_ERR_DOMAIN in *dev_status.
+ * sky_batch_create -- validates the arguments and copies the offsets to the workspace (waiting
+ * for that copy, so the host array may be released on return). No other device work. The batch
+ * reads x_soa (device float[d*ld], ld >= offsets[nbatch]) at every sky_batch_skylines, which
+ * raises SKY_ERR_DOMAIN in *dev_status for values outside the domain.
  */
 sky_status sky_batch_create(const float* x_soa, int32_t d, int64_t ld, const int64_t* offsets,
                             int32_t nbatch, void* ws, size_t ws_bytes, int32_t* dev_status,
                             void* stream, sky_batch** out);
 
 /*
- * sky_batch_skylines -- the skyline of every relation (synchronises `stream`: rounds read
- * counters back). Writes sky_idx (device int64[cap]): the skyline rows of all relations,
- * ascending (so grouped by relation), as rows of x_soa; and sky_off (device int64[nbatch+1]):
- * relation j's skyline is sky_idx[sky_off[j] .. sky_off[j+1]). Then prepares the candidate
- * store of every relation for the gres search. Returns SKY_ERR_CAPACITY (synchronously, the
- * batch stays usable for sky_batch_info only) when cap is below the total skyline size, which
- * sky_batch_info reports in sky_count; cap = offsets[nbatch] always suffices.
+ * sky_batch_skylines -- the skyline of every relation from the current values of x_soa (every
+ * relation's rows ordered along a Hilbert curve as one segment, then the segmented skyline
+ * rounds). Writes sky_idx (device int64[cap]): the skyline rows of all relations, ascending (so
+ * grouped by relation), as rows of x_soa; and sky_off (device int64[nbatch+1]): relation j's
+ * skyline is sky_idx[sky_off[j] .. sky_off[j+1]). Then prepares the candidate store of every
+ * relation for the gres search. A total above cap raises SKY_ERR_CAPACITY in *dev_status (then
+ * only the first cap rows are written and searched); cap = offsets[nbatch] always suffices.
+ * Never synchronises; may be repeated (each call recomputes everything).
  */
 sky_status sky_batch_skylines(sky_batch* batch, int64_t* sky_idx, int64_t cap, int64_t* sky_off,
                               void* stream);
 
 /*
- * sky_batch_tune -- builds the work table of the gres search from the tuning choices (tune may
- * be NULL: defaults) and copies it to the workspace (synchronises `stream`). Call after
- * sky_batch_skylines; call again to change the choices. Results never depend on them.
+ * sky_batch_tune -- the search's choices for the next sky_batch_gres calls (tune may be NULL:
+ * defaults). Host-side only. Results never depend on them.
  */
 sky_status sky_batch_tune(sky_batch* batch, const sky_tune* tune, void* stream);
 
 /*
  * sky_batch_gres -- gres of every skyline tuple of every relation: g_exit[j] and gres[j]
- * (device arrays of at least sky_count entries; either may be NULL) refer to sky_idx[j], with
- * the same meaning as in gres_compute and relation j's skyline as the candidate set.
- * g_max in [2, SKY_MAX_G]. Only queues kernels on `stream` (no host synchronisation, no
- * copies), so it can be captured in a graph and replayed; ev_begin / ev_end (hipEvent_t,
- * optional, both or neither) are recorded around the search kernel.
+ * (device arrays of min(cap of sky_batch_skylines, offsets[nbatch]) entries; either may be
+ * NULL) refer to sky_idx[j], with the same meaning as in gres_compute and relation j's
+ * skyline as the candidate set. g_max in [2, SKY_MAX_G]. The counts, the mapping choice of AUTO
+ * and the order of the relations are worked out on the device; ev_begin / ev_end (hipEvent_t,
+ * optional, both or neither) are recorded around the search kernels. Never synchronises.
+ * SKY_ERR_STATE before sky_batch_skylines.
  */
 sky_status sky_batch_gres(sky_batch* batch, int32_t g_max, int32_t* g_exit, float* gres,
                           void* ev_begin, void* ev_end, void* stream);
 
 /*
- * sky_batch_info -- n = total rows, d, scheme = SKY_NONE, p = nbatch, rounds_local /
- * tests_local of the skyline rounds, local_count = sky_count = total skyline size,
- * max_partition = rows of the largest relation, state (1 created, 2 skylines done, 3 tuned).
+ * sky_batch_info -- n = total rows, d, scheme = SKY_NONE, p = nbatch, max_partition = rows of
+ * the largest relation, state (1 created, 2 skylines queued); after sky_batch_skylines also
+ * rounds_local / tests_local / tests_local_max of the skyline rounds and local_count =
+ * sky_count = the total skyline size, read back on the stream of the last sky_batch_skylines
+ * (this call waits for it).
  */
 sky_status sky_batch_info(const sky_batch* batch, sky_info* out);
 

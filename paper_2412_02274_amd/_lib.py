@@ -43,7 +43,7 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
            "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
            "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres",
-           "gres_compute_noalloc")
+           "gres_compute_noalloc", "sky_literal_level")
 
 
 class SkyParams(C.Structure):
@@ -70,8 +70,7 @@ class GresOpts(C.Structure):
 
 
 class SkyTune(C.Structure):
-    _fields_ = [("mapping", C.c_int32), ("targets_per_wg", C.c_int32), ("near_first", C.c_int32),
-                ("lpt", C.c_int32)]
+    _fields_ = [("mapping", C.c_int32), ("near_first", C.c_int32), ("lpt", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -130,6 +129,7 @@ def load():
         "gres_gbar_workspace_bytes": (sz, [i64]),
         "gres_gbar": (i32, [vp, i64, i32, i64, vp, vp, vp, sz, vp, vp]),
         "sky_gres": (i32, [vp, i32, vp, vp, vp, sz, vp, C.POINTER(GresOpts), vp]),
+        "sky_literal_level": (i32, [vp, i64, i32, vp, vp, vp]),
         "gres_compute_noalloc": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, vp, vp,
                                        C.POINTER(GresOpts), vp]),
     }

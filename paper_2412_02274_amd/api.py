@@ -362,41 +362,49 @@ def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, sc
     """Alg. 1 as written: for g = g_max .. 2, the skyline of the grid projection of the candidate
     set (Sky(r)) is computed through the two-phase partitioned scheme (build, local skylines,
     merge on the projected relation); every candidate not in it that has no value yet gets
-    g_exit = g. Returns (g_exit int32[s] on the host, per-level statistics). Equal to
+    g_exit = g, on the device (sky_literal_level); the host only reads how many are left, to stop
+    once none is. Returns (g_exit int32[s] on the host, per-level statistics). Equal to
     ``gres()`` for every input (gres is stable and dominance between projections is the per-tuple
     test); kept to run the paper's own formulation and count its work. reps > 0 applies
     Representative Filtering (Sec. 3.1) inside every level's skyline."""
-    import numpy as np
+    lib = _lib.load()
     s = int(sky_idx.numel())
     d = x_soa.shape[0]
-    ge = np.ones(s, dtype=np.int32)
+    dev = x_soa.device
     if s == 0:
-        return ge, []
-    remaining = np.ones(s, dtype=bool)
-    proj = torch.empty((d, s), dtype=torch.float32, device=x_soa.device)
-    status = new_status(x_soa.device)
+        return torch.ones(0, dtype=torch.int32).numpy(), []
+    ge = torch.zeros(s, dtype=torch.int32, device=dev)  # 0: no level yet (Alg. 1's empty map)
+    nil_left = torch.zeros(1, dtype=torch.int32, device=dev)
+    proj = torch.empty((d, s), dtype=torch.float32, device=dev)
+    status = new_status(dev)
     levels = []
+    sp = _stream_ptr()
     for g in range(int(g_max), 1, -1):
         project(x_soa, sky_idx, g, out=proj, status=status)
         plan = build(proj, scheme, target_p, slice_dim, status=status, reps=reps)
         plan.local_skylines()
-        _, member = plan.merge(member=True)
+        sky_g, member = plan.merge(member=True)
         inf = plan.info()
         plan.close()
         check_status(status, "gres_literal")
-        inside = member.cpu().numpy().astype(bool)
-        exits = remaining & ~inside
-        ge[exits] = g
-        remaining &= inside
-        levels.append({"g": g, "sky": int(inf["sky_count"]), "exits": int(exits.sum()),
+        # the level's exits, assigned on the device (sky_literal_level)
+        nil_left.zero_()
+        _lib.check(lib.sky_literal_level(_ptr(member), s, g, _ptr(ge), _ptr(nil_left), sp),
+                   "sky_literal_level")
+        left = int(nil_left.item())
+        levels.append({"g": g, "sky": int(inf["sky_count"]), "nil_left": left,
                        "p": int(inf["p"]), "tests_local": int(inf["tests_local"]),
                        "tests_local_max": int(inf["tests_local_max"]),
                        "tests_merge": int(inf["tests_merge"]),
                        # Sec. 4's count: the heaviest partition plus the final phase
                        "tests_paper": int(inf["tests_local_max"]) + int(inf["tests_merge"])})
-        if not remaining.any():
+        if left == 0:
             break
-    return ge, levels
+    _lib.check(lib.sky_literal_level(None, s, 1, _ptr(ge), None, sp), "sky_literal_level")
+    for i, lv in enumerate(levels):  # tuples that left at each level
+        before = s if i == 0 else levels[i - 1]["nil_left"]
+        lv["exits"] = before - lv["nil_left"]
+    return ge.cpu().numpy(), levels
 
 
 def skyline(x_rows: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0):

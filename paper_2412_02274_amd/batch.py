@@ -8,10 +8,10 @@ include/sky.h); argument marshalling, packing and scheduling only.
 Relations are grouped by d. Each group is one ``sky_batch``: its rows packed one relation after
 the other in one device buffer, every relation's skyline computed by the same rounds of the
 segmented engine, then the gres of every skyline tuple (Def. 2 via Alg. 1, with the relation's
-own skyline as candidates) in one search launch per group over a device work table. The gres
-launches of all groups are captured once in a graph and replayed. ``GresTuner`` picks each
-group's work-table shape (mapping, tuples per workgroup, tile order) by timing the candidates
-on the group itself; results never depend on the choice.
+own skyline as candidates) in one persistent search launch per group. A step -- ingest,
+skylines and gres of every group -- reads nothing back, so it is captured once in a HIP graph
+and replayed. ``GresTuner`` picks each group's search choices (mapping, tile order, relation
+order) by timing them on the group itself; results never depend on the choice.
 
 ``PlainRunner`` is the one-relation-at-a-time path over the plain entry points (ingest, build,
 local skylines, merge, gres_compute), the reference for the batched path's throughput.
@@ -70,41 +70,35 @@ class BatchGroup:
         self.g_exit = torch.empty(max(self.n, 1), dtype=torch.int32, device=device)
         self.gres = torch.empty(max(self.n, 1), dtype=torch.float32, device=device)
         self.h = None
-        self.sky_count = 0
-        self.info = None
-        self.tune = _lib.SkyTune(_lib.SKY_GRES_AUTO, 0, 1, 1)
-        self.n_wg_key = None
+        self.tune = _lib.SkyTune(_lib.SKY_GRES_AUTO, 1, 1)
+
+    def create(self, stream):
+        """sky_batch_create (once; waits for the copy of the offsets)."""
+        if self.h is not None or self.n == 0:
+            return
+        h = C.c_void_p()
+        _lib.check(_lib.load().sky_batch_create(_ptr(self.x_soa), self.d, self.n, self._off_c, self.nb,
+                                                _ptr(self.ws), self.ws_bytes, _ptr(self.status),
+                                                C.c_void_p(stream.cuda_stream), C.byref(h)),
+                   "sky_batch_create")
+        self.h = h
+        self.set_tune(self.tune)
 
     def skylines(self, stream):
-        """ingest -> create -> skylines (synchronises the stream)."""
-        lib = _lib.load()
-        sp = C.c_void_p(stream.cuda_stream)
-        self.close()
-        self.status.zero_()
-        if self.n == 0:
-            self.sky_count = 0
-            self.info = {"n": 0, "d": self.d, "p": self.nb, "sky_count": 0}
-            return
-        _lib.check(lib.sky_ingest(_ptr(self.x_rows), self.n, self.d, _ptr(self.x_soa), self.n,
-                                  _ptr(self.status), sp), "sky_ingest")
-        h = C.c_void_p()
-        _lib.check(lib.sky_batch_create(_ptr(self.x_soa), self.d, self.n, self._off_c, self.nb,
-                                        _ptr(self.ws), self.ws_bytes, _ptr(self.status), sp,
-                                        C.byref(h)), "sky_batch_create")
-        self.h = h
-        _lib.check(lib.sky_batch_skylines(self.h, _ptr(self.sky_idx), self.n, _ptr(self.sky_off),
-                                          sp), "sky_batch_skylines")
-        inf = _lib.SkyInfo()
-        _lib.check(lib.sky_batch_info(self.h, C.byref(inf)), "sky_batch_info")
-        self.info = inf.as_dict()
-        self.sky_count = int(inf.sky_count)
-
-    def set_tune(self, tune, stream):
-        self.tune = tune
+        """Queue ingest and sky_batch_skylines (no synchronisation)."""
         if self.h is None:
             return
-        _lib.check(_lib.load().sky_batch_tune(self.h, C.byref(tune), C.c_void_p(stream.cuda_stream)),
-                   "sky_batch_tune")
+        lib = _lib.load()
+        sp = C.c_void_p(stream.cuda_stream)
+        _lib.check(lib.sky_ingest(_ptr(self.x_rows), self.n, self.d, _ptr(self.x_soa), self.n,
+                                  _ptr(self.status), sp), "sky_ingest")
+        _lib.check(lib.sky_batch_skylines(self.h, _ptr(self.sky_idx), self.n, _ptr(self.sky_off),
+                                          sp), "sky_batch_skylines")
+
+    def set_tune(self, tune):
+        self.tune = tune
+        if self.h is not None:
+            _lib.check(_lib.load().sky_batch_tune(self.h, C.byref(tune), None), "sky_batch_tune")
 
     def launch_gres(self, stream, ev_begin=None, ev_end=None):
         if self.h is None:
@@ -112,6 +106,18 @@ class BatchGroup:
         _lib.check(_lib.load().sky_batch_gres(self.h, self.g_max, _ptr(self.g_exit), _ptr(self.gres),
                                               ev_begin, ev_end, C.c_void_p(stream.cuda_stream)),
                    "sky_batch_gres")
+
+    @property
+    def sky_count(self):
+        """Total skyline size of the last pass (reads the offsets back)."""
+        return int(self.sky_off[-1].item()) if self.nb else 0
+
+    def info(self):
+        if self.h is None:
+            return {"n": 0, "d": self.d, "p": self.nb, "sky_count": 0}
+        inf = _lib.SkyInfo()
+        _lib.check(_lib.load().sky_batch_info(self.h, C.byref(inf)), "sky_batch_info")
+        return inf.as_dict()
 
     def close(self):
         if self.h is not None:
@@ -126,13 +132,11 @@ class BatchGroup:
 
 
 class GresTuner:
-    """Per-group choice of the gres work table by measurement: coordinate descent over
-    tuples-per-workgroup, mapping and tile order, each candidate timed on the group's own
-    prepared candidates (torch events on the launch stream). Choices are cached per
-    (d, skyline size, largest relation's skyline, g_max) in memory and, if `path` is given, in
-    a JSON file."""
+    """Per-group choice of the gres search by measurement: coordinate descent over the mapping,
+    the tile order and the relation order, each candidate timed on the group's own prepared
+    candidates (torch events on the launch stream). Choices are cached per (d, skyline size,
+    largest relation's skyline, g_max) in memory and, if `path` is given, in a JSON file."""
 
-    PER_WG = (8, 16, 32, 64, 128, 256, 512)  # 8 waves per workgroup: 1 to 64 tuples per wave
     LEVELS_MAX_CANDIDATES = 8192
 
     def __init__(self, path=None, repeats=2):
@@ -147,10 +151,10 @@ class GresTuner:
     @staticmethod
     def key(group):
         cnt = np.diff(group.sky_off.cpu().numpy())
-        return f"d{group.d}_s{group.sky_count}_m{int(cnt.max()) if cnt.size else 0}_g{group.g_max}"
+        return f"d{group.d}_s{int(cnt.sum())}_m{int(cnt.max()) if cnt.size else 0}_g{group.g_max}"
 
     def _time(self, group, tune, stream):
-        group.set_tune(tune, stream)
+        group.set_tune(tune)
         best = None
         for _ in range(self.repeats):
             a = torch.cuda.Event(enable_timing=True)
@@ -166,18 +170,17 @@ class GresTuner:
 
     def choose(self, group, stream):
         if group.sky_count == 0:
-            return _lib.SkyTune(_lib.SKY_GRES_AUTO, 0, 1, 1)
+            return _lib.SkyTune(_lib.SKY_GRES_AUTO, 1, 1)
         k = self.key(group)
         if k in self.cache:
             return _lib.SkyTune(**self.cache[k])
-        cur = dict(mapping=_lib.SKY_GRES_TILES, targets_per_wg=16, near_first=1, lpt=1)
+        cur = dict(mapping=_lib.SKY_GRES_TILES, near_first=1, lpt=1)
         best_ms = None
         # lanes over levels only pays off for small candidate sets (every lane walks all of them)
         cnt = np.diff(group.sky_off.cpu().numpy())
         mappings = (_lib.SKY_GRES_TILES,) if cnt.max() > self.LEVELS_MAX_CANDIDATES else (
             _lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS)
-        for field, values in (("targets_per_wg", self.PER_WG), ("mapping", mappings),
-                              ("near_first", (1, 0)), ("lpt", (1, 0))):
+        for field, values in (("mapping", mappings), ("near_first", (1, 0)), ("lpt", (1, 0))):
             best_v = cur[field]
             for v in values:
                 trial = dict(cur, **{field: v})
@@ -193,7 +196,9 @@ class GresTuner:
 
 
 class BatchRunner:
-    """Skyline and gres of many relations of mixed d (see the module docstring)."""
+    """Skyline and gres of many relations of mixed d (see the module docstring). The first run
+    is eager (and tunes the groups when a tuner is given); with use_graph, that step is then
+    captured once and every later run replays it."""
 
     def __init__(self, datasets, g_max=25, device="cuda", tuner=None, use_graph=True):
         self.device = torch.device(device)
@@ -208,14 +213,22 @@ class BatchRunner:
         self.tuner = tuner
         self.use_graph = use_graph
         self.graph = None
-        self.graph_key = None
         self.stream = torch.cuda.Stream(self.device)
-        self.phase = {}
+        self._ev = None
+        for g in self.groups:
+            g.create(self.stream)
+        self.stream.synchronize()
 
-    def _graph_key(self):
-        return tuple((g.sky_count, tuple(g.tune.as_dict().values())) for g in self.groups)
+    def _step(self, st, ev=None):
+        for g in self.groups:
+            g.status.zero_()
+            g.skylines(st)
+        if ev is not None:
+            ev.record(st)
+        for g in self.groups:
+            g.launch_gres(st)
 
-    def run(self, check=True, tune=True):
+    def run(self, check=True, tune=True, timing=False):
         st = self.stream
         cur = torch.cuda.current_stream(self.device)
         st.wait_stream(cur)
@@ -224,24 +237,20 @@ class BatchRunner:
         e2 = torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(st):
             e0.record(st)
-            for g in self.groups:
-                g.skylines(st)
-            for g in self.groups:
-                if tune and self.tuner is not None and g.sky_count:
-                    g.set_tune(self.tuner.choose(g, st), st)
-                else:
-                    g.set_tune(g.tune, st)
-            e1.record(st)
-            if self.use_graph:
-                key = self._graph_key()
-                if self.graph is None or key != self.graph_key:
-                    self._capture()
-                    self.graph_key = key
+            if self.graph is not None and not timing:
                 self.graph.replay()
+                e1 = None
             else:
-                for g in self.groups:
-                    g.launch_gres(st)
+                self._step(st, e1)
             e2.record(st)
+            if self.graph is None and tune and self.tuner is not None:
+                for g in self.groups:
+                    if g.h is not None and g.sky_count:
+                        g.set_tune(self.tuner.choose(g, st))
+                for g in self.groups:  # the results of the tuned choices
+                    g.launch_gres(st)
+            if self.graph is None and self.use_graph:
+                self._capture()
         cur.wait_stream(st)
         if check:
             st.synchronize()
@@ -251,20 +260,22 @@ class BatchRunner:
         return self
 
     def _capture(self):
-        # one eager pass first (the graph then replays identical launches)
         st = self.stream
-        for g in self.groups:
-            g.launch_gres(st)
         st.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph, stream=st):
-            for g in self.groups:
-                g.launch_gres(torch.cuda.current_stream())
+            self._step(torch.cuda.current_stream())
 
     def phase_ms(self):
+        """Milliseconds of the last run: its total, and with timing=True (an eager step) the
+        skylines and gres phases."""
         e0, e1, e2 = self._ev
         e2.synchronize()
-        return {"skylines": e0.elapsed_time(e1), "gres": e1.elapsed_time(e2)}
+        out = {"step": e0.elapsed_time(e2)}
+        if e1 is not None:
+            out["skylines"] = e0.elapsed_time(e1)
+            out["gres"] = e1.elapsed_time(e2)
+        return out
 
     def sky_total(self):
         return sum(g.sky_count for g in self.groups)
@@ -279,9 +290,10 @@ class BatchRunner:
         return rows, g.g_exit[a:b].cpu().numpy(), g.gres[a:b].cpu().numpy()
 
     def info(self):
-        return [dict(g.info, tune=g.tune.as_dict()) for g in self.groups]
+        return [dict(g.info(), tune=g.tune.as_dict()) for g in self.groups]
 
     def close(self):
+        self.graph = None
         for g in self.groups:
             g.close()
 

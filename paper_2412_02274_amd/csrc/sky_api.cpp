@@ -143,9 +143,25 @@ size_t plan_bytes(int64_t n, int32_t d, int32_t scheme, int32_t p, int32_t m) {
     return c.used;
 }
 
+sky_status plan_partition(sky_plan* P, hipStream_t st) {
+    PartitionArgs a{};
+    a.x = P->x; a.n = P->n; a.d = P->d; a.ld = P->ld;
+    a.scheme = P->scheme; a.p = P->p; a.m = P->m; a.slice_dim = P->slice_dim;
+    a.seg_off = P->seg_off_dev;
+    a.tan2 = P->tan2_dev;
+    a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
+    a.part_off = P->part_off; a.pruned = P->pruned;
+    a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
+    a.scan_tmp = P->scan_tmp;
+    a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
+    a.xa = P->xa;
+    a.dev_status = P->dev_status;
+    return launch_partition(a, st);
+}
+
 sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int32_t scheme, int32_t p,
                       int32_t m, int32_t slice_dim, const int64_t* seg_off_host, void* ws,
-                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out) {
+                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out, bool launch) {
     *out = nullptr;
     size_t need = plan_bytes(n, d, scheme, p, m);
     if (need == 0) return SKY_ERR_INVALID_ARG;
@@ -166,20 +182,10 @@ sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int3
         hipError_t e2 = hipStreamSynchronize(st);
         if (e1 != hipSuccess || e2 != hipSuccess) { delete P; return SKY_ERR_HIP; }
     }
-    PartitionArgs a{};
-    a.x = x_soa; a.n = n; a.d = d; a.ld = ld;
-    a.scheme = P->scheme; a.p = p; a.m = m; a.slice_dim = P->slice_dim;
-    a.seg_off = P->seg_off_dev;
-    a.tan2 = P->tan2_dev;
-    a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
-    a.part_off = P->part_off; a.pruned = P->pruned;
-    a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
-    a.scan_tmp = P->scan_tmp;
-    a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
-    a.xa = P->xa;
-    a.dev_status = dev_status;
-    sky_status s = launch_partition(a, st);
-    if (s != SKY_OK) { delete P; return s; }
+    if (launch) {
+        sky_status s = plan_partition(P, st);
+        if (s != SKY_OK) { delete P; return s; }
+    }
     P->state = 1;
     P->info.n = n; P->info.d = d; P->info.scheme = P->scheme; P->info.p = p; P->info.m = m;
     P->info.state = 1;
@@ -223,6 +229,13 @@ sky_status sky_project(const float* x_soa, int64_t n, int32_t d, int64_t ld, con
     return launch_project(x_soa, n, d, ld, rows, s, g, out_soa, ld_out, dev_status, (hipStream_t)stream);
 }
 
+sky_status sky_literal_level(const uint8_t* member, int64_t s, int32_t g, int32_t* g_exit, int32_t* nil_left,
+                             void* stream) {
+    if (s < 0 || s > kMaxRows || g < 1 || g > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
+    if (s > 0 && (!g_exit || (g > 1 && !member))) return SKY_ERR_INVALID_ARG;
+    return launch_literal_level(member, s, g, g_exit, nil_left, (hipStream_t)stream);
+}
+
 size_t sky_build_workspace_bytes(int64_t n, int32_t d, const sky_params* params) {
     if (!params || n < 1 || n > kMaxBuildRows || !valid_d(d) || params->reps < 0 || params->reps > SKY_MAX_REPS)
         return 0;
@@ -241,7 +254,7 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
     int32_t p = 1, m = 0;
     SKY_TRY(resolve_partitions(n, d, params, &p, &m));
     SKY_TRY(plan_build(x_soa, n, d, ld, params->scheme, p, m, params->slice_dim, nullptr, ws, ws_bytes,
-                       dev_status, (hipStream_t)stream, out));
+                       dev_status, (hipStream_t)stream, out, true));
     (*out)->reps = params->reps;
     return SKY_OK;
 }
@@ -249,7 +262,28 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
 sky_status sky_local_skylines(sky_plan* P, void* stream) {
     if (!P) return SKY_ERR_INVALID_ARG;
     if (P->state != 1) return SKY_ERR_STATE;
-    hipStream_t st = (hipStream_t)stream;
+    SKY_TRY(plan_local_phase(P, (hipStream_t)stream));
+    P->state = 2;
+    P->info.state = 2;
+    return SKY_OK;
+}
+
+sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_count,
+                     uint8_t* member, void* stream) {
+    if (!P || !dev_count || cap < 0 || (cap > 0 && !sky_idx)) return SKY_ERR_INVALID_ARG;
+    if (P->state != 2) return SKY_ERR_STATE;
+    SKY_TRY(plan_final_phase(P, sky_idx, cap, dev_count, member, (hipStream_t)stream));
+    P->merge_cap = cap;
+    P->state = 3;
+    P->info.state = 3;
+    return SKY_OK;
+}
+
+}  // extern "C"
+
+namespace sky {
+
+sky_status plan_local_phase(sky_plan* P, hipStream_t st) {
     P->last_stream = st;
     const int32_t n = (int32_t)P->n;
     // partition statistics (pruned Grid cells and their rows, the largest partition)
@@ -295,16 +329,11 @@ sky_status sky_local_skylines(sky_plan* P, void* stream) {
     pb.ev_begin = P->ev_begin; pb.ev_end = P->ev_end; pb.ev_cap = P->ev_cap; pb.ev_used = &P->ev_used;
     SKY_TRY(run_engine(pb, P->eng, st));
     P->info.events_used = P->ev_used;
-    P->state = 2;
-    P->info.state = 2;
     return SKY_OK;
 }
 
-sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_count,
-                     uint8_t* member, void* stream) {
-    if (!P || !dev_count || cap < 0 || (cap > 0 && !sky_idx)) return SKY_ERR_INVALID_ARG;
-    if (P->state != 2) return SKY_ERR_STATE;
-    hipStream_t st = (hipStream_t)stream;
+sky_status plan_final_phase(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_count, uint8_t* member,
+                            hipStream_t st) {
     P->last_stream = st;
     const int32_t n = (int32_t)P->n;
     uint8_t* F = P->local_flag;  // per position: in the final skyline (with dom clear)
@@ -333,13 +362,13 @@ sky_status sky_merge(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_co
     // rewritten to the skyline itself
     SKY_TRY(launch_compact_flags(F, P->eng.dom, true, n, P->final_list, P->count_tmp + CT_SKY,
                                  P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st));
-    SKY_TRY(launch_final_output(P->final_list, P->count_tmp + CT_SKY, P->rowid, P->n, P->member_tmp, member,
-                                sky_idx, cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st));
-    P->merge_cap = cap;
-    P->state = 3;
-    P->info.state = 3;
-    return SKY_OK;
+    return launch_final_output(P->final_list, P->count_tmp + CT_SKY, P->rowid, P->n, P->member_tmp, member,
+                               sky_idx, cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st);
 }
+
+}  // namespace sky
+
+extern "C" {
 
 sky_status sky_plan_partitions(const sky_plan* P, int32_t* part, void* stream) {
     if (!P || !part) return SKY_ERR_INVALID_ARG;
@@ -456,7 +485,7 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, co
     if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
     SKY_TRY(launch_gres_prepare(x_soa, n, d, ld, sky_idx, s, store, tmp, dev_status, st));
     SKY_TRY(launch_gres_targets(x_soa, n, d, ld, nullptr, s, s, store, tg, dev_status, st));
-    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, nullptr, 0, g_max, mapping, g_exit, gres,
+    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, nullptr, nullptr, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                               opts ? opts->dev_tests : nullptr, st);
 }
@@ -488,7 +517,7 @@ sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, vo
     SKY_TRY(launch_gres_prepare_positions(P->xp, P->ldp, P->d, P->final_list, c, s_dev, P->rowid, P->pos_tmp,
                                           store, dev_status, st));
     SKY_TRY(launch_gres_targets_all(store, P->d, c, s_dev, tg, st));
-    return launch_gres_search(store, P->d, (int32_t)c, tg, c, s_dev, nullptr, 0, g_max, mapping, g_exit, gres,
+    return launch_gres_search(store, P->d, (int32_t)c, tg, c, s_dev, nullptr, nullptr, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                               opts ? opts->dev_tests : nullptr, st);
 }
@@ -571,7 +600,7 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
     if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
     if (s == 0) return SKY_ERR_INVALID_ARG;  // targets need candidates to be tested against
     SKY_TRY(launch_gres_targets(x_soa, n, d, ld, targets, nt, s, store, tg, dev_status, st));
-    return launch_gres_search(store, d, (int32_t)s, tg, nt, nullptr, nullptr, 0, g_max, mapping, g_exit, gres,
+    return launch_gres_search(store, d, (int32_t)s, tg, nt, nullptr, nullptr, nullptr, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
                               opts ? opts->dev_tests : nullptr, st);
 }

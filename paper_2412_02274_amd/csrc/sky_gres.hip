@@ -263,20 +263,22 @@ __global__ void __launch_bounds__(kBlock) targets_all_kernel(const float* __rest
 }
 
 // targets = every candidate of a segmented store in element order: element q of segment sg
-// sits at slot seg_coff[sg] + (q - cand_off[sg])
+// sits at slot seg_coff[sg] + (q - cand_off[sg]); tseg[q] = sg. The count is cand_off[nseg].
 __global__ void __launch_bounds__(kBlock) targets_seg_kernel(
-    const float* __restrict__ cand, int64_t ccap, int32_t s, int32_t d,
+    const float* __restrict__ cand, int64_t ccap, int32_t d,
     const int32_t* __restrict__ cand_off, const int32_t* __restrict__ seg_coff, int32_t nseg,
     const int32_t* __restrict__ perm, int32_t near_first, float* __restrict__ tval, int64_t tvcap,
-    int32_t* __restrict__ thint, int32_t* __restrict__ tout) {
-    const int32_t q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= s) return;
-    const int32_t sg = find_seg(cand_off, nseg, q);
-    const int32_t r = q - cand_off[sg];
-    const int64_t slot = (int64_t)seg_coff[sg] + r;
-    for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + slot];
-    thint[q] = near_first ? r / kTileC : 0;
-    tout[q] = perm[slot];
+    int32_t* __restrict__ thint, int32_t* __restrict__ tout, int32_t* __restrict__ tseg) {
+    const int32_t s = cand_off[nseg];
+    for (int32_t q = blockIdx.x * kBlock + threadIdx.x; q < s; q += gridDim.x * kBlock) {
+        const int32_t sg = find_seg(cand_off, nseg, q);
+        const int32_t r = q - cand_off[sg];
+        const int64_t slot = (int64_t)seg_coff[sg] + r;
+        for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = cand[(int64_t)k * ccap + slot];
+        thint[q] = near_first ? r / kTileC : 0;
+        tout[q] = perm[slot];
+        tseg[q] = sg;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) fill_i32_kernel(int32_t* __restrict__ p, int32_t n, int32_t v) {
@@ -327,15 +329,18 @@ __global__ void __launch_bounds__(kBlock) fill_targets_kernel(int32_t* __restric
     for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) p[i] = v;
 }
 
-// first position of every relation's rows in the ascending skyline list (lower bound of its
-// first row), as int64 offsets for the caller and int32 element offsets for the store
+// first position of every relation's rows in the ascending skyline list sky_idx[0, *count)
+// (lower bound of its first row), as int64 offsets for the caller and int32 element offsets
+// for the store
 __global__ void __launch_bounds__(kBlock) batch_offsets_kernel(const int64_t* __restrict__ sky_idx,
-                                                                int32_t count,
+                                                                const int32_t* __restrict__ count_dev,
+                                                                int32_t cap,
                                                                 const int64_t* __restrict__ row_off,
                                                                 int32_t nseg, int64_t* __restrict__ sky_off,
                                                                 int32_t* __restrict__ cand_off) {
     const int32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j > nseg) return;
+    const int32_t count = *count_dev < cap ? *count_dev : cap;
     int32_t lo = 0, hi = count;
     if (j == nseg) {
         lo = count;
@@ -348,6 +353,161 @@ __global__ void __launch_bounds__(kBlock) batch_offsets_kernel(const int64_t* __
     }
     sky_off[j] = lo;
     cand_off[j] = lo;
+}
+
+// ------------------------------------------------------------------ batched store and order
+// Layout of a batch's candidate store, one workgroup: relation j holds cnt_j = cand_off[j+1] -
+// cand_off[j] candidates from slot seg_coff[j] (64-aligned); used[0] = the slots in use,
+// used[1] = the largest cnt_j.
+__global__ void __launch_bounds__(1024) batch_layout_kernel(const int32_t* __restrict__ cand_off, int32_t nseg,
+                                                             int32_t* __restrict__ seg_coff,
+                                                             int32_t* __restrict__ seg_cnt,
+                                                             int32_t* __restrict__ used) {
+    __shared__ int32_t wsum[1024 / kWave], wmax[1024 / kWave];
+    __shared__ int32_t carry, mx_all;
+    const int lane = (int)lane_id(), wave = threadIdx.x / kWave;
+    if (threadIdx.x == 0) { carry = 0; mx_all = 0; }
+    __syncthreads();
+    for (int32_t base = 0; base < nseg; base += 1024) {
+        const int32_t j = base + threadIdx.x;
+        const int32_t c = j < nseg ? cand_off[j + 1] - cand_off[j] : 0;
+        const int32_t v = (c + kTileC - 1) / kTileC * kTileC;
+        int32_t inc = v, m = c;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const int32_t o = __shfl_xor(m, off, kWave);
+            m = o > m ? o : m;
+        }
+        if (lane == kWave - 1) wsum[wave] = inc;
+        if (lane == 0) wmax[wave] = m;
+        __syncthreads();
+        int32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (j < nseg) {
+            seg_coff[j] = before + inc - v;
+            seg_cnt[j] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 0; w < 1024 / kWave; ++w) {
+                carry += wsum[w];
+                mx_all = wmax[w] > mx_all ? wmax[w] : mx_all;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        used[0] = carry;
+        used[1] = mx_all;
+    }
+}
+
+// The search's shape for all S = cand_off[nseg] targets of a batch (as search_setup_kernel
+// gives it; AUTO judged by the largest relation's count, used[1]).
+__global__ void batch_params_kernel(const int32_t* __restrict__ cand_off, int32_t nseg,
+                                    const int32_t* __restrict__ used, int32_t g_max, int32_t mapping,
+                                    int32_t* __restrict__ params) {
+    if (threadIdx.x != 0) return;
+    const int32_t nt = cand_off[nseg];
+    int32_t per_wg, blocks, lb;
+    search_shape(nt, g_max, &per_wg, &blocks, &lb);
+    params[P_NT] = nt;
+    params[P_MAPPING] = mapping == SKY_GRES_AUTO ? gres_auto_mapping(used[1], g_max) : mapping;
+    params[P_PER_WG] = per_wg;
+    params[P_BLOCKS] = blocks;
+    params[P_LBANDS] = lb;
+}
+
+// Longest-first order of the relations: rank_of = the number of relations with more candidates
+// (equal counts in relation order); order[rank] = relation. Every workgroup holds all counts.
+__global__ void __launch_bounds__(kBlock) batch_rank_kernel(const int32_t* __restrict__ seg_cnt, int32_t nseg,
+                                                             int32_t* __restrict__ order) {
+    __shared__ int32_t c[SKY_MAX_CELLS];
+    for (int32_t i = threadIdx.x; i < nseg; i += kBlock) c[i] = seg_cnt[i];
+    __syncthreads();
+    const int32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nseg) return;
+    const int32_t cj = c[j];
+    int32_t rank = 0;
+    for (int32_t i = 0; i < nseg; ++i) rank += (c[i] > cj) || (c[i] == cj && i < j);
+    order[rank] = j;
+}
+
+// rank_off[i] = targets of the relations ranked before i (one workgroup)
+__global__ void __launch_bounds__(1024) batch_rank_scan_kernel(const int32_t* __restrict__ seg_cnt,
+                                                                const int32_t* __restrict__ order, int32_t nseg,
+                                                                int32_t* __restrict__ rank_off) {
+    __shared__ int32_t wsum[1024 / kWave];
+    __shared__ int32_t carry;
+    const int lane = (int)lane_id(), wave = threadIdx.x / kWave;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < nseg; base += 1024) {
+        const int32_t i = base + threadIdx.x;
+        const int32_t v = i < nseg ? seg_cnt[order[i]] : 0;
+        int32_t inc = v;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        if (lane == kWave - 1) wsum[wave] = inc;
+        __syncthreads();
+        int32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (i < nseg) rank_off[i] = before + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < 1024 / kWave; ++w) carry += wsum[w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rank_off[nseg] = carry;
+}
+
+// tord: the targets in longest-first relation order, one workgroup per relation rank
+__global__ void __launch_bounds__(kBlock) batch_tord_kernel(const int32_t* __restrict__ order,
+                                                             const int32_t* __restrict__ rank_off,
+                                                             const int32_t* __restrict__ cand_off,
+                                                             int32_t nseg, int32_t* __restrict__ tord) {
+    for (int32_t i = blockIdx.x; i < nseg; i += gridDim.x) {
+        const int32_t j = order[i];
+        const int32_t a = rank_off[i], c = rank_off[i + 1] - a, e = cand_off[j];
+        for (int32_t r = threadIdx.x; r < c; r += kBlock) tord[a + r] = e + r;
+    }
+}
+
+// The slots of a batch's store from the plan's partition-contiguous copy: slot r of relation j
+// holds element cand_off[j] + r of the skyline's positions list (relation-major, curve order
+// inside each relation, as the copy is); slots past a relation's count, and the store's last
+// tile, hold padding. perm = the row's index in the ascending skyline list (idx_of_row).
+__global__ void __launch_bounds__(kBlock) store_seg_pos_kernel(
+    const float* __restrict__ xp, int64_t ldp, int32_t d, const int32_t* __restrict__ pos,
+    const int32_t* __restrict__ cand_off, const int32_t* __restrict__ seg_coff,
+    const int32_t* __restrict__ seg_cnt, int32_t nseg, const int32_t* __restrict__ used,
+    const int32_t* __restrict__ rowid, const int32_t* __restrict__ idx_of_row, float* __restrict__ cand,
+    int64_t ccap, uint32_t* __restrict__ ckey, int32_t* __restrict__ perm) {
+    const int64_t u = used[0];
+    const int64_t lim = u + kTileC;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < lim; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t q = i < u ? i : ccap - kTileC + (i - u);
+        bool real = false;
+        int32_t p = 0;
+        if (i < u) {
+            const int32_t sg = find_seg(seg_coff, nseg, q);
+            const int64_t r = q - seg_coff[sg];
+            real = r < seg_cnt[sg];
+            if (real) p = pos[cand_off[sg] + r];
+        }
+        float v[SKY_MAX_D];
+        for (int k = 0; k < d; ++k) {
+            v[k] = real ? xp[(int64_t)k * ldp + p] : kPadValue;
+            cand[(int64_t)k * ccap + q] = v[k];
+        }
+        ckey[q] = real ? hilbert_key(v, d, curve_bits(d)) : 0xFFFFFFFFu;
+        perm[q] = real ? idx_of_row[rowid[p]] : -1;
+    }
 }
 
 // targets = given rows of the relation: values, hint tile (where the row's curve key falls
@@ -394,45 +554,40 @@ __global__ void __launch_bounds__(kBlock) targets_rows_kernel(const float* __res
 
 // ----------------------------------------------------------------------------------- search
 
-// Work of one workgroup: a segment and a contiguous range of its targets. Without a table,
-// one segment (0) and targets [blockIdx * per_wg, ...).
+// Work of one workgroup of a one-segment search: targets [blk * per_wg, ...) of segment 0.
 struct WgWork { int32_t seg, t0, t1; };
 
-__device__ __forceinline__ WgWork wg_work(const int32_t* wg_table, int32_t per_wg, int32_t nt,
-                                          int32_t blk) {
+__device__ __forceinline__ WgWork wg_work(int32_t per_wg, int32_t nt, int32_t blk) {
     WgWork w;
-    if (wg_table) {
-        w.seg = wg_table[3 * blk];
-        w.t0 = wg_table[3 * blk + 1];
-        w.t1 = wg_table[3 * blk + 2];
-    } else {
-        w.seg = 0;
-        w.t0 = blk * per_wg;
-        w.t1 = w.t0 + per_wg < nt ? w.t0 + per_wg : nt;
-    }
+    w.seg = 0;
+    w.t0 = blk * per_wg;
+    w.t1 = w.t0 + per_wg < nt ? w.t0 + per_wg : nt;
     return w;
 }
 
 template <int D>
 // 8 waves per SIMD: the search waits on cache round trips, so more waves in flight pay.
-// Two ways to hand out the work, (target, band) pairs in band-major order (every target's
+// Three ways to hand out the work, (target, band) pairs in band-major order (every target's
 // highest band first):
-//  * work == nullptr: workgroup b searches band b / nblk of the targets of wg_table entry
-//    b % nblk (or of the contiguous range b % nblk * per_wg ...), each wave taking the range's
-//    next target from a counter in LDS when it is free (measured: 9% faster than a fixed share
-//    per wave on the batched workload);
-//  * work != nullptr (one segment): the grid is what the device holds at once, and every wave
-//    takes the next pair from the counter *work (zero at launch) until none is left, so a
-//    workgroup's tile boxes are loaded once and no wave waits for a slow one to free its slot.
+//  * work == nullptr (one segment, few targets): workgroup b searches band b / nblk of the
+//    contiguous range of targets b % nblk * per_wg ..., each wave taking the range's next
+//    target from a counter in LDS when it is free;
+//  * work != nullptr, tseg == nullptr (one segment): the grid is what the device holds at once,
+//    and every wave takes the next pair from the counters until none is left, so a workgroup's
+//    tile boxes are loaded once and no wave waits for a slow one to free its slot;
+//  * tseg != nullptr (many segments, one per relation of a batch): the same persistent pairs
+//    over every target of every relation, tseg[q] naming the target's relation and tord (when
+//    given) the order of the targets (the heaviest relations first); a wave reads the tile boxes
+//    of its target's relation from L2.
 __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu(8))) gres_tiles_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
     const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
     const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
-    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
-    const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
-    int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests, int32_t nblk,
-    int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
-    int32_t* __restrict__ work, const int32_t* __restrict__ params) {
+    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint, int32_t per_wg, int32_t g_max,
+    int32_t lds_floats, int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests,
+    int32_t nblk, int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
+    int32_t* __restrict__ work, const int32_t* __restrict__ params, const int32_t* __restrict__ tseg,
+    const int32_t* __restrict__ tord) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     if (params) {  // target count and mapping decided on the device
@@ -442,28 +597,37 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     unsigned long long ntests = 0;   // candidate tests (target against candidate at one level)
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
+    const uint32_t padslot = (uint32_t)(ccap - kTileC);
+    // a segment's place in the store (and whether its boxes fit in LDS)
+    struct Seg { uint32_t coff; int32_t ntile, nchunk; uint32_t t0; bool use_lds; };
+    auto seg_at = [&](int32_t sg, bool lds_ok) -> Seg {
+        Seg v;
+        v.coff = (uint32_t)seg_coff[sg];
+        const int32_t cnt = seg_cnt[sg];
+        v.ntile = (cnt + kTileC - 1) / kTileC;
+        v.nchunk = (v.ntile + kWave - 1) / kWave;
+        v.t0 = v.coff / kTileC;  // first tile of the segment
+        v.use_lds = lds_ok && v.nchunk <= kWave && d * (2 * v.ntile + v.nchunk) <= lds_floats;
+        return v;
+    };
     int32_t band0 = 0;
     WgWork w{0, 0, nt};
     if (!work) {
         band0 = blockIdx.x / nblk;
-        w = wg_work(wg_table, per_wg, nt, blockIdx.x - band0 * nblk);
+        w = wg_work(per_wg, nt, blockIdx.x - band0 * nblk);
         if (w.t0 >= w.t1) return;  // uniform
     }
-    const uint32_t coff = (uint32_t)seg_coff[w.seg];
-    const int32_t cnt = seg_cnt[w.seg];
-    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
-    const int32_t nchunk = (ntile + kWave - 1) / kWave;
-    const uint32_t t0 = coff / kTileC;  // first tile of the segment
-    const uint32_t padslot = (uint32_t)(ccap - kTileC);
-    const bool use_lds = nchunk <= kWave && d * (2 * ntile + nchunk) <= lds_floats;  // uniform
+    // one segment: its boxes in LDS when they fit
+    const Seg sv0 = seg_at(0, tseg == nullptr);
     float* blo = sbox;
-    float* bhi = sbox + d * ntile;
-    float* clo = sbox + 2 * d * ntile;
-    if (use_lds) {
+    float* bhi = sbox + d * sv0.ntile;
+    float* clo = sbox + 2 * d * sv0.ntile;
+    if (sv0.use_lds) {
+        const int32_t ntile = sv0.ntile, nchunk = sv0.nchunk;
         for (int32_t e = threadIdx.x; e < d * ntile; e += kGresBlock) {
             const int32_t k = e / ntile, tl = e - k * ntile;
-            blo[e] = lo[(int64_t)k * tcap + t0 + tl];
-            bhi[e] = hi[(int64_t)k * tcap + t0 + tl];
+            blo[e] = lo[(int64_t)k * tcap + sv0.t0 + tl];
+            bhi[e] = hi[(int64_t)k * tcap + sv0.t0 + tl];
         }
         __syncthreads();
         for (int32_t e = threadIdx.x; e < d * nchunk; e += kGresBlock) {
@@ -475,8 +639,12 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         }
         __syncthreads();
     }
-    // the level scan of target q over the levels of band `band`
-    auto search = [&](const int32_t q, const int32_t band) {
+    // the level scan of target q over the levels of band `band`, in segment sv
+    auto search = [&](const int32_t q, const int32_t band, const Seg& sv) {
+        const uint32_t coff = sv.coff;
+        const int32_t ntile = sv.ntile, nchunk = sv.nchunk;
+        const uint32_t t0 = sv.t0;
+        const bool use_lds = sv.use_lds;
         float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
@@ -597,7 +765,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
     };
     if (work) {
-        const int32_t total = nt * nbands;  // below 2^30 (checked at launch): no counter overflow
+        const int64_t total = (int64_t)nt * nbands;
         // kWorkCounters counters, 128 bytes apart, so that no single address takes every
         // atomic: workgroup b draws from counter b % nctr, which hands out the pairs
         // x, x + nctr, x + 2 nctr, ... (every pair belongs to exactly one counter, and every
@@ -608,10 +776,16 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             int32_t k = 0;
             if (lane == 0) k = atomicAdd(work + kCounterStride * x, 1);
             k = __builtin_amdgcn_readfirstlane(k);
-            const int32_t item = x + nctr * k;
+            const int64_t item = x + (int64_t)nctr * k;
             if (item >= total) break;  // every wave ends here once its counter passes the total
-            const int32_t b = item / nt;
-            search(item - b * nt, b);
+            const int32_t b = (int32_t)(item / nt);
+            const int32_t r = (int32_t)(item - (int64_t)b * nt);
+            if (tseg) {
+                const int32_t q = tord ? tord[r] : r;
+                search(q, b, seg_at(tseg[q], false));
+            } else {
+                search(r, b, sv0);
+            }
         }
     } else {
         // the workgroup's range, one target at a time to whichever wave is free
@@ -623,7 +797,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             if (lane == 0) q = atomicAdd(&next_q, 1);
             q = __builtin_amdgcn_readfirstlane(q);
             if (q >= w.t1) break;
-            search(q, band0);
+            search(q, band0, sv0);
         }
     }
     if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
@@ -656,7 +830,7 @@ template <int D>
 __global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo, int64_t tcap,
     const int32_t* __restrict__ seg_coff, const int32_t* __restrict__ seg_cnt, int32_t d_rt,
-    const float* __restrict__ tval, int64_t tvcap, int32_t nt, const int32_t* __restrict__ wg_table,
+    const float* __restrict__ tval, int64_t tvcap, int32_t nt, const int32_t* __restrict__ tseg,
     int32_t per_wg, int32_t g_max, int32_t* __restrict__ gstart, const int32_t* __restrict__ params) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     const int d = dget<D>(d_rt);
@@ -669,13 +843,13 @@ __global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
         nblk = params[P_BLOCKS];
     }
     for (int32_t vb = blockIdx.x; vb < nblk; vb += gridDim.x) {
-    const WgWork w = wg_work(wg_table, per_wg, nt, vb);
-    if (w.t0 >= w.t1) continue;
-    const int64_t coff = seg_coff[w.seg];
-    const int32_t cnt = seg_cnt[w.seg];
-    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
-    const int64_t t0 = coff / kTileC;
+    const WgWork w = wg_work(per_wg, nt, vb);
     for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) {
+        const int32_t sg = tseg ? tseg[q] : 0;  // the target's segment (a relation of a batch)
+        const int64_t coff = seg_coff[sg];
+        const int32_t cnt = seg_cnt[sg];
+        const int32_t ntile = (cnt + kTileC - 1) / kTileC;
+        const int64_t t0 = coff / kTileC;
         float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
@@ -729,18 +903,20 @@ __global__ void __launch_bounds__(kGresBlock) gres_start_kernel(
 }
 
 template <int D>
+// Lanes over 64 consecutive levels, candidates wave-uniform. Work: the levels of each target
+// split into nbands bands, blocks band-major over contiguous target ranges (per_wg), or, with
+// tseg (the relations of a batch), persistent waves taking (target, band) pairs from the work
+// counters like the tile search.
 __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo,
     const float* __restrict__ hi, int64_t tcap, const int32_t* __restrict__ seg_coff,
     const int32_t* __restrict__ seg_cnt, int32_t d_rt, const float* __restrict__ tval,
-    int64_t tvcap, int32_t nt, const int32_t* __restrict__ thint,
-    const int32_t* __restrict__ wg_table, int32_t per_wg, int32_t g_max, int32_t lds_floats,
+    int64_t tvcap, int32_t nt, int32_t per_wg, int32_t g_max,
     int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests,
-    const int32_t* __restrict__ gstart, int32_t nblk, const int32_t* __restrict__ params) {
+    const int32_t* __restrict__ gstart, int32_t nblk, const int32_t* __restrict__ params,
+    int32_t* __restrict__ work, const int32_t* __restrict__ tseg, const int32_t* __restrict__ tord) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     unsigned long long ntests = 0;  // candidate tests (target against candidate at one level)
-    (void)thint;
-    (void)lds_floats;
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
@@ -752,16 +928,12 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
         nblk = params[P_BLOCKS];
         nbands = params[P_LBANDS];
     }
-    // blocks are band-major: every target's highest band first
-    for (int32_t vb = blockIdx.x; vb < nblk * nbands; vb += gridDim.x) {
-    const int32_t band = vb / nblk;
-    const WgWork w = wg_work(wg_table, per_wg, nt, vb - band * nblk);
-    if (w.t0 >= w.t1) continue;
-    const int64_t coff = seg_coff[w.seg];
-    const int32_t cnt = seg_cnt[w.seg];
-    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
-    const int64_t t0 = coff / kTileC;
-    for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) {
+    // the level scan of target q over the levels of band `band`, in segment sg
+    auto search = [&](const int32_t q, const int32_t band, const int32_t sg) {
+        const int64_t coff = seg_coff[sg];
+        const int32_t cnt = seg_cnt[sg];
+        const int32_t ntile = (cnt + kTileC - 1) / kTileC;
+        const int64_t t0 = coff / kTileC;
         float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
@@ -854,7 +1026,29 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
         }
         // ge_out starts at 1 (no exit); each band raises it to its highest exit level
         if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
-    }
+    };
+    if (tseg) {
+        const int64_t total = (int64_t)nt * nbands;
+        const int32_t nctr = gridDim.x >= (uint32_t)kWorkCounters ? kWorkCounters : 1;
+        const int32_t x = (int32_t)(blockIdx.x % (uint32_t)nctr);
+        for (;;) {
+            int32_t k = 0;
+            if (lane == 0) k = atomicAdd(work + kCounterStride * x, 1);
+            k = __builtin_amdgcn_readfirstlane(k);
+            const int64_t item = x + (int64_t)nctr * k;
+            if (item >= total) break;
+            const int32_t b = (int32_t)(item / nt);
+            const int32_t r = (int32_t)(item - (int64_t)b * nt);
+            const int32_t q = tord ? tord[r] : r;
+            search(q, b, tseg[q]);
+        }
+    } else {
+        // blocks are band-major: every target's highest band first
+        for (int32_t vb = blockIdx.x; vb < nblk * nbands; vb += gridDim.x) {
+            const int32_t band = vb / nblk;
+            const WgWork w = wg_work(per_wg, nt, vb - band * nblk);
+            for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) search(q, band, 0);
+        }
     }
     if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
 }
@@ -997,60 +1191,54 @@ sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld,
     return SKY_OK;
 }
 
-sky_status launch_gres_prepare_segments(const float* x, int64_t n, int32_t d, int64_t ld,
-                                        const int64_t* rows, int64_t s64, const int32_t* cand_off,
-                                        int32_t nseg, int32_t ntile, const GresStore& store,
-                                        const GresPrepTmp& tmp, int32_t* dev_status, hipStream_t st) {
-    const int32_t s = (int32_t)s64;
-    const int bits = curve_bits(d);
-    if (s > 0) {
-        const uint32_t blocks = (uint32_t)ceil_div(s, kBlock);
-        hipLaunchKernelGGL(curve_kernel, dim3(blocks), dim3(kBlock), 0, st, x, n, d, ld, rows, s, bits,
-                           tmp.k0, tmp.v0, dev_status);
+sky_status launch_batch_store(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
+                              const int32_t* rowid, const int32_t* idx_of_row, const int64_t* sky_idx,
+                              const int32_t* count_dev, int64_t cap, const int64_t* row_off, int32_t nseg,
+                              int64_t* sky_off, int32_t* cand_off, int32_t* used, const GresStore& store,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(batch_offsets_kernel, dim3((uint32_t)ceil_div(nseg + 1, kBlock)), dim3(kBlock), 0, st,
+                       sky_idx, count_dev, (int32_t)cap, row_off, nseg, sky_off, cand_off);
+    hipLaunchKernelGGL(batch_layout_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)cand_off, nseg,
+                       store.seg_coff, store.seg_cnt, used);
+    const int64_t slots = round_up(cap > 0 ? cap : 1, kTileC) + (int64_t)kTileC * (nseg + 1);
+    const int64_t sb = ceil_div(slots, kBlock);
+    hipLaunchKernelGGL(store_seg_pos_kernel, dim3((uint32_t)(sb > 2048 ? 2048 : sb)), dim3(kBlock), 0, st, xp, ldp,
+                       d, pos, (const int32_t*)cand_off, (const int32_t*)store.seg_coff,
+                       (const int32_t*)store.seg_cnt, nseg, (const int32_t*)used, rowid, idx_of_row, store.cand,
+                       store.ccap, store.ckey, store.perm);
+    const int64_t ntile = ceil_div(slots, kTileC);
+    const int64_t tb = ceil_div(ntile, kBlock / kWave);
+    hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)(tb > 2048 ? 2048 : tb)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, d, (int32_t)ntile, (const int32_t*)used,
+                       (int32_t)(ntile * kTileC), store.lo, store.hi, store.tcap);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
+sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, const int32_t* cand_off,
+                               int32_t nseg, const int32_t* used, bool near_first, bool lpt, int32_t* order,
+                               int32_t* rank_off, int32_t* tord, int32_t* tseg, const GresTargets& tg,
+                               int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres, void* ev_begin,
+                               void* ev_end, hipStream_t st) {
+    if (cap <= 0) return SKY_OK;
+    if (lpt) {  // the targets of the relations with the most candidates first
+        hipLaunchKernelGGL(batch_rank_kernel, dim3((uint32_t)ceil_div(nseg, kBlock)), dim3(kBlock), 0, st,
+                           (const int32_t*)store.seg_cnt, nseg, order);
+        hipLaunchKernelGGL(batch_rank_scan_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)store.seg_cnt,
+                           (const int32_t*)order, nseg, rank_off);
+        hipLaunchKernelGGL(batch_tord_kernel, dim3((uint32_t)(nseg < 4096 ? nseg : 4096)), dim3(kBlock), 0, st,
+                           (const int32_t*)order, (const int32_t*)rank_off, cand_off, nseg, tord);
         SKY_HIP(hipGetLastError());
-        SKY_TRY(launch_radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, s, bits * d, tmp.radix_tmp, st));
-        if (nseg > 1) {
-            // stable sort by segment over the curve order: (segment, curve) order
-            hipLaunchKernelGGL(seg_key_kernel, dim3(blocks), dim3(kBlock), 0, st, (const uint32_t*)tmp.v0,
-                               s, cand_off, nseg, tmp.k0);
-            SKY_HIP(hipGetLastError());
-            int sbits = 0;
-            while ((1 << sbits) < nseg) ++sbits;
-            SKY_TRY(launch_radix_sort(tmp.k0, tmp.v0, tmp.k1, tmp.v1, s, sbits, tmp.radix_tmp, st));
-        }
     }
-    hipLaunchKernelGGL(store_seg_kernel, dim3((uint32_t)ceil_div(store.ccap, kBlock)), dim3(kBlock), 0, st,
-                       x, n, d, ld, rows, (const uint32_t*)tmp.v0, cand_off, (const int32_t*)store.seg_coff,
-                       (const int32_t*)store.seg_cnt, nseg, bits, store.cand, store.ccap, store.ckey,
-                       store.perm);
+    hipLaunchKernelGGL(batch_params_kernel, dim3(1), dim3(64), 0, st, cand_off, nseg, used, g_max, mapping,
+                       tg.params);
+    const int64_t qb = ceil_div(cap, kBlock);
+    hipLaunchKernelGGL(targets_seg_kernel, dim3((uint32_t)(qb > 2048 ? 2048 : qb)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, d, cand_off, (const int32_t*)store.seg_coff, nseg,
+                       (const int32_t*)store.perm, near_first ? 1 : 0, tg.tval, tg.tvcap, tg.thint, tg.tout, tseg);
     SKY_HIP(hipGetLastError());
-    if (ntile > 0)
-        hipLaunchKernelGGL(tile_box_kernel, dim3((uint32_t)ceil_div(ntile, kBlock / kWave)), dim3(kBlock), 0,
-                           st, (const float*)store.cand, store.ccap, d, ntile, (const int32_t*)nullptr, 0,
-                           store.lo, store.hi, store.tcap);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
-}
-
-sky_status launch_gres_targets_segments(const GresStore& store, int32_t d, int64_t s64,
-                                        const int32_t* cand_off, int32_t nseg, bool near_first,
-                                        const GresTargets& tg, hipStream_t st) {
-    const int32_t s = (int32_t)s64;
-    if (s <= 0) return SKY_OK;
-    hipLaunchKernelGGL(targets_seg_kernel, dim3((uint32_t)ceil_div(s, kBlock)), dim3(kBlock), 0, st,
-                       (const float*)store.cand, store.ccap, s, d, cand_off,
-                       (const int32_t*)store.seg_coff, nseg, (const int32_t*)store.perm,
-                       near_first ? 1 : 0, tg.tval, tg.tvcap, tg.thint, tg.tout);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
-}
-
-sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int64_t* row_off,
-                                int32_t nseg, int64_t* sky_off, int32_t* cand_off, hipStream_t st) {
-    hipLaunchKernelGGL(batch_offsets_kernel, dim3((uint32_t)ceil_div(nseg + 1, kBlock)), dim3(kBlock), 0,
-                       st, sky_idx, (int32_t)count, row_off, nseg, sky_off, cand_off);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
+    return launch_gres_search(store, d, 0, tg, cap, nullptr, tseg, lpt ? tord : nullptr, g_max, mapping, g_exit,
+                              gres, ev_begin, ev_end, nullptr, st);
 }
 
 sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds, int32_t* out) {
@@ -1063,36 +1251,31 @@ sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds
 }
 
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
-                              const GresTargets& tg, int64_t nt64, const int32_t* nt_dev, const int32_t* wg_table,
-                              int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
+                              const GresTargets& tg, int64_t nt64, const int32_t* nt_dev, const int32_t* tseg,
+                              const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
                               unsigned long long* dev_tests, hipStream_t st) {
-    const int32_t nt = (int32_t)nt64;  // with nt_dev: an upper bound of the count
+    const int32_t nt = (int32_t)nt64;  // with a count on the device: an upper bound of it
     if (nt <= 0) return SKY_OK;
-    const bool on_dev = nt_dev && !wg_table;
-    // LDS for the tile boxes of the largest segment, when they fit; with the count on the
-    // device, a fixed 40 KB (the kernel checks the real size), which costs no occupancy at 8
-    // waves per SIMD
+    const bool batch = tseg != nullptr;
+    const bool on_dev = nt_dev || batch;
+    // LDS for the tile boxes of the one segment, when they fit; with the count on the device,
+    // a fixed 40 KB (the kernel checks the real size), which costs no occupancy at 8 waves per
+    // SIMD; a batch reads every relation's boxes from L2
     const int32_t ntile = (int32_t)ceil_div(max_cnt, kTileC);
     const int32_t nchunk = (int32_t)ceil_div(ntile, kWave);
     int64_t floats = (int64_t)d * (2 * ntile + nchunk);
     if (floats * 4 > kGresLdsBytes || nchunk > kWave) floats = 0;
-    if (on_dev) floats = kGresLdsDevBytes / 4;
+    if (nt_dev) floats = kGresLdsDevBytes / 4;
+    if (batch) floats = 0;
     const size_t lds = (size_t)floats * sizeof(float);
-    int32_t per_wg = 0, lbands = 1;
-    int32_t blocks = n_wg;
-    if (!wg_table) {
-        search_shape(nt, g_max, &per_wg, &blocks, &lbands);
-    } else {
-        int32_t pw_unused = 0, b_unused = 0;  // a table fixes the blocks; the level bands follow nt
-        search_shape(nt, g_max, &pw_unused, &b_unused, &lbands);
-    }
-    int32_t* params = nullptr;
-    if (on_dev) {
-        params = tg.params;
+    int32_t per_wg = 0, lbands = 1, blocks = 0;
+    search_shape(nt, g_max, &per_wg, &blocks, &lbands);
+    int32_t* params = on_dev ? tg.params : nullptr;
+    if (nt_dev) {
         hipLaunchKernelGGL(search_setup_kernel, dim3(1), dim3(64), 0, st, nt_dev, nt, g_max, mapping, params);
         SKY_HIP(hipGetLastError());
-    }
+    }  // (a batch's own setup has filled params)
     // TILES: the levels are split into bands searched by separate workgroups (band-major
     // order), so a tuple that scans many levels is not one long sequential chain
     int32_t nbands = (int32_t)ceil_div(g_max - 1, kBandLevels);
@@ -1108,7 +1291,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
         SKY_DISPATCH_D(d, gres_start_kernel, dim3(on_dev ? stride_grid : (uint32_t)blocks), dim3(kGresBlock), 0,
                        st, (const float*)store.cand, store.ccap, (const float*)store.lo, store.tcap,
                        (const int32_t*)store.seg_coff, (const int32_t*)store.seg_cnt, d,
-                       (const float*)tg.tval, tg.tvcap, nt, wg_table, per_wg, g_max, tg.gstart,
+                       (const float*)tg.tval, tg.tvcap, nt, tseg, per_wg, g_max, tg.gstart,
                        (const int32_t*)params);
         SKY_HIP(hipGetLastError());
         gstart = tg.gstart;
@@ -1120,33 +1303,49 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                            nt, (const int32_t*)params, 1);
         SKY_HIP(hipGetLastError());
     }
-    // TILES on one segment: as many workgroups as the device holds at once, fed from a counter
+    // persistent launches (one segment with many targets, a count on the device, a batch): as
+    // many workgroups as the device holds at once, fed from the work counters
     uint32_t grid = (uint32_t)blocks * (uint32_t)nbands;
     int32_t* work = nullptr;
-    if (run_tiles && !wg_table && (int64_t)nt * nbands < ((int64_t)1 << 30)) {
+    uint32_t resident_tiles = 0;
+    if (run_tiles) {
         const void* fn = nullptr;
         SKY_KERNEL_PTR_D(d, gres_tiles_kernel, fn);
         int32_t resident = 0;
         SKY_TRY(resident_workgroups(fn, kGresBlock, lds, &resident));
+        resident_tiles = (uint32_t)resident;
         if ((int64_t)grid > resident || on_dev) {
-            grid = (uint32_t)resident;
+            grid = resident_tiles;
             work = tg.work;
-            hipLaunchKernelGGL(fill_i32_kernel, dim3(kWorkCounters * kCounterStride / kBlock), dim3(kBlock), 0,
-                               st, work, kWorkCounters * kCounterStride, 0);
-            SKY_HIP(hipGetLastError());
         }
+    }
+    uint32_t lgrid = (uint32_t)blocks * (uint32_t)lbands;
+    if (run_levels && on_dev) {
+        if (batch) {
+            const void* fn = nullptr;
+            SKY_KERNEL_PTR_D(d, gres_levels_kernel, fn);
+            int32_t resident = 0;
+            SKY_TRY(resident_workgroups(fn, kGresBlock, 0, &resident));
+            lgrid = (uint32_t)resident;
+            work = tg.work;
+        } else {
+            lgrid = stride_grid * (uint32_t)kMaxLevelBands > (uint32_t)kStrideGrid
+                        ? (uint32_t)kStrideGrid : stride_grid * (uint32_t)kMaxLevelBands;
+        }
+    }
+    if (work) {
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(kWorkCounters * kCounterStride / kBlock), dim3(kBlock), 0,
+                           st, work, kWorkCounters * kCounterStride, 0);
+        SKY_HIP(hipGetLastError());
     }
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (run_levels) {
-        const uint32_t lgrid = on_dev ? (uint32_t)(stride_grid * (uint32_t)kMaxLevelBands > kStrideGrid
-                                                       ? kStrideGrid : stride_grid * (uint32_t)kMaxLevelBands)
-                                      : (uint32_t)blocks * (uint32_t)lbands;
         SKY_DISPATCH_D(d, gres_levels_kernel, dim3(lgrid), dim3(kGresBlock), 0, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
-                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests, gstart, (int32_t)blocks, (const int32_t*)params);
+                       per_wg, g_max, tg.ge, dev_tests, gstart, (int32_t)blocks, (const int32_t*)params,
+                       work, tseg, tord);
         SKY_HIP(hipGetLastError());
     }
     if (run_tiles) {
@@ -1154,8 +1353,9 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                        (const float*)store.cand, store.ccap, (const float*)store.lo,
                        (const float*)store.hi, store.tcap, (const int32_t*)store.seg_coff,
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
-                       (const int32_t*)tg.thint, wg_table, per_wg, g_max, (int32_t)floats, tg.ge,
-                       dev_tests, (int32_t)blocks, band_len, gstart, nbands, work, (const int32_t*)params);
+                       (const int32_t*)tg.thint, per_wg, g_max, (int32_t)floats, tg.ge,
+                       dev_tests, (int32_t)blocks, band_len, gstart, nbands, work, (const int32_t*)params,
+                       tseg, tord);
         SKY_HIP(hipGetLastError());
     }
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

@@ -63,6 +63,35 @@ __global__ void __launch_bounds__(kBlock) project_kernel(const float* __restrict
 
 }  // namespace
 
+// One level of Alg. 1 as written: a tuple whose projection is not in the skyline of the
+// projected candidates at level g, and that has no level yet (0), exits at g; *nil_left (if
+// given) gets the number of tuples still without a level added to it. Level 1 ends the scan:
+// every tuple without a level gets 1 (it never left the skyline).
+__global__ void __launch_bounds__(kBlock) literal_level_kernel(const uint8_t* __restrict__ member, int64_t s,
+                                                                int32_t g, int32_t* __restrict__ g_exit,
+                                                                int32_t* __restrict__ nil_left) {
+    int32_t left = 0;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < s; j += (int64_t)gridDim.x * kBlock) {
+        if (g_exit[j] != 0) continue;
+        if (g == 1 || !member[j]) g_exit[j] = g;
+        else ++left;
+    }
+    if (nil_left) {
+        for (int off = kWave / 2; off > 0; off >>= 1) left += __shfl_xor(left, off, kWave);
+        if (lane_id() == 0 && left) atomicAdd(nil_left, left);
+    }
+}
+
+sky_status launch_literal_level(const uint8_t* member, int64_t s, int32_t g, int32_t* g_exit, int32_t* nil_left,
+                                hipStream_t st) {
+    if (s <= 0) return SKY_OK;
+    const int64_t b = ceil_div(s, kBlock);
+    hipLaunchKernelGGL(literal_level_kernel, dim3((uint32_t)(b > 1024 ? 1024 : b)), dim3(kBlock), 0, st, member, s,
+                       g, g_exit, nil_left);
+    SKY_HIP(hipGetLastError());
+    return SKY_OK;
+}
+
 sky_status launch_project(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                           int64_t s, int32_t g, float* out, int64_t ld_out, int32_t* dev_status,
                           hipStream_t st) {

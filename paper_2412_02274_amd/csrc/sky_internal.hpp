@@ -150,6 +150,8 @@ sky_status launch_project(const float* x, int64_t n, int32_t d, int64_t ld, cons
                           hipStream_t st);
 sky_status launch_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa, int64_t ld,
                          int32_t* dev_status, hipStream_t st);
+sky_status launch_literal_level(const uint8_t* member, int64_t s, int32_t g, int32_t* g_exit, int32_t* nil_left,
+                                hipStream_t st);
 
 // sky_scan.hip: exclusive scan of n int32 values (n < 2^31); tmp needs scan_tmp_elems(n).
 int64_t scan_tmp_elems(int64_t n);
@@ -347,24 +349,24 @@ sky_status launch_gres_targets_all(const GresStore& store, int32_t d, int64_t ca
 sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t nt, int64_t s, const GresStore& store, const GresTargets& tg,
                                int32_t* dev_status, hipStream_t st);
-// Segmented store: candidates rows[0, s) grouped by segment, segment j = elements
-// [cand_off[j], cand_off[j+1]) (device int32, nseg + 1); store.seg_coff / seg_cnt must already
-// hold each segment's 64-aligned first slot and count; ntile = tiles up to the last segment.
-sky_status launch_gres_prepare_segments(const float* x, int64_t n, int32_t d, int64_t ld,
-                                        const int64_t* rows, int64_t s, const int32_t* cand_off,
-                                        int32_t nseg, int32_t ntile, const GresStore& store,
-                                        const GresPrepTmp& tmp, int32_t* dev_status, hipStream_t st);
-// Targets = every candidate of a segmented store, in element order (segment-major); start tile
-// = the target's own tile (near_first) or the segment's first tile.
-sky_status launch_gres_targets_segments(const GresStore& store, int32_t d, int64_t s,
-                                        const int32_t* cand_off, int32_t nseg, bool near_first,
-                                        const GresTargets& tg, hipStream_t st);
-// sky_off[j] = cand_off[j] = first position of relation j's rows (row_off[j] on) in the
-// ascending list sky_idx[0, count); index nseg gets count.
-sky_status launch_batch_offsets(const int64_t* sky_idx, int64_t count, const int64_t* row_off,
-                                int32_t nseg, int64_t* sky_off, int32_t* cand_off, hipStream_t st);
-// Work table of the segmented search: per workgroup (segment, first target, end target).
-constexpr int kGresWgEntry = 3;
+// Batched relations (segments of one plan): sky_off[j] / cand_off[j] = the first index of
+// relation j's rows in the ascending skyline list sky_idx[0, min(*count_dev, cap)) (row_off =
+// the relations' row offsets); the candidate store (relation j in curve order from a 64-aligned
+// slot, read from the plan's copy at the skyline's positions pos, relation-major) with its tile
+// boxes; used[0] = slots in use, used[1] = the largest relation's skyline.
+sky_status launch_batch_store(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
+                              const int32_t* rowid, const int32_t* idx_of_row, const int64_t* sky_idx,
+                              const int32_t* count_dev, int64_t cap, const int64_t* row_off, int32_t nseg,
+                              int64_t* sky_off, int32_t* cand_off, int32_t* used, const GresStore& store,
+                              hipStream_t st);
+// The gres of every skyline tuple of every relation: targets (tseg[q] = relation of target q),
+// with lpt the longest-first order tord (order / rank_off: nseg and nseg + 1 int32 of scratch),
+// then one persistent search over all of them; counts and shape read on the device.
+sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, const int32_t* cand_off,
+                               int32_t nseg, const int32_t* used, bool near_first, bool lpt, int32_t* order,
+                               int32_t* rank_off, int32_t* tord, int32_t* tseg, const GresTargets& tg,
+                               int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres, void* ev_begin,
+                               void* ev_end, hipStream_t st);
 // measured (both mappings with per-target start levels): lanes over 64 levels pay off when
 // many levels lie below the start levels (g_max >= 2^17) or on small skylines with
 // g_max > 1000; otherwise the banded tile walk is faster
@@ -372,11 +374,13 @@ __host__ __device__ inline int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
     if (s > 8192) return SKY_GRES_TILES;
     return (g_max >= (1 << 17) || (g_max > 1000 && s <= 1024)) ? SKY_GRES_LEVELS : SKY_GRES_TILES;
 }
-// nt_dev (one segment, no table): the target count is min(*nt_dev, nt) on the device, nt being
-// an upper bound; the mapping (AUTO included) and the work split are then decided on the device
+// One segment of max_cnt candidates, nt targets. nt_dev: the target count is min(*nt_dev, nt)
+// on the device, nt being an upper bound; the mapping (AUTO included) and the work split are then
+// decided on the device. tseg (a batch): every target q of segment tseg[q] (in the order tord,
+// when given) as persistent work, with tg.params already holding the count and shape.
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
-                              const GresTargets& tg, int64_t nt, const int32_t* nt_dev, const int32_t* wg_table,
-                              int32_t n_wg, int32_t g_max, int32_t mapping, int32_t* g_exit,
+                              const GresTargets& tg, int64_t nt, const int32_t* nt_dev, const int32_t* tseg,
+                              const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
                               unsigned long long* dev_tests, hipStream_t st);
 

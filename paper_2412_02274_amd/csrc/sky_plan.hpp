@@ -58,10 +58,17 @@ constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset
 
 // Workspace bytes of a plan (0 if the sizes are invalid).
 size_t plan_bytes(int64_t n, int32_t d, int32_t scheme, int32_t p, int32_t m);
-// Carve a plan from ws and launch its partition step. scheme may be kSchemeSegments, with
-// seg_off_host = the p + 1 dataset row offsets (copied to the device before returning).
+// Carve a plan from ws and (launch) queue its partition step. scheme may be kSchemeSegments,
+// with seg_off_host = the p + 1 dataset row offsets (copied to the device before returning).
 sky_status plan_build(const float* x, int64_t n, int32_t d, int64_t ld, int32_t scheme, int32_t p,
                       int32_t m, int32_t slice_dim, const int64_t* seg_off_host, void* ws,
-                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out);
+                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out, bool launch);
+// Queue the partition step of a plan (re-reads its relation).
+sky_status plan_partition(sky_plan* P, hipStream_t st);
+// Sec. 3 phase 1 (the local skylines) and phase 2 (the union's skyline, its positions list
+// and the ascending rows), never synchronising; no state checks.
+sky_status plan_local_phase(sky_plan* P, hipStream_t st);
+sky_status plan_final_phase(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_count, uint8_t* member,
+                            hipStream_t st);
 
 }  // namespace sky

@@ -175,6 +175,16 @@ def test_gres_noalloc_limits(lib):
                                     None) == _lib.SKY_ERR_INVALID_ARG  # no status word
 
 
+def test_literal_level_arguments(lib):
+    fake = C.c_void_p(0x1000)  # never dereferenced: the checks come first
+    assert lib.sky_literal_level(fake, -1, 5, fake, None, None) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_literal_level(fake, 10, 0, fake, None, None) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_literal_level(fake, 10, _lib.SKY_MAX_G + 1, fake, None, None) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_literal_level(None, 10, 5, fake, None, None) == _lib.SKY_ERR_INVALID_ARG  # member needed
+    assert lib.sky_literal_level(fake, 10, 5, None, None, None) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_literal_level(None, 0, 5, None, None, None) == _lib.SKY_OK  # nothing to do
+
+
 def test_sliced_workspace_holds_partition_histogram(lib):
     # Sliced partitions go through the same stable counting sort by partition as Grid/Angular,
     # so for equal p its workspace must hold the same histogram table (regression: it used to

@@ -87,22 +87,21 @@ def test_batch_tunes_agree(dev):
     g = run.groups[0]
     st = run.stream
     ref = None
-    for mapping in (_lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS):
-        for per in (1, 7, 32, 4096):
-            for near in (1, 0):
-                for lpt in (1, 0):
-                    with torch.cuda.stream(st):
-                        g.set_tune(_lib.SkyTune(mapping, per, near, lpt), st)
-                        g.g_exit.fill_(-7)
-                        g.launch_gres(st)
-                    st.synchronize()
-                    got = g.g_exit[:g.sky_count].cpu().numpy().copy()
-                    if ref is None:
-                        ref = got
-                        for i in range(len(data)):
-                            rows, ge, gr = run.result(i)
-                            _check_relation(data[i], rows, ge, gr, 25, f"relation {i}")
-                    assert np.array_equal(got, ref), (mapping, per, near, lpt)
+    for mapping in (_lib.SKY_GRES_AUTO, _lib.SKY_GRES_TILES, _lib.SKY_GRES_LEVELS):
+        for near in (1, 0):
+            for lpt in (1, 0):
+                with torch.cuda.stream(st):
+                    g.set_tune(_lib.SkyTune(mapping, near, lpt))
+                    g.g_exit.fill_(-7)
+                    g.launch_gres(st)
+                st.synchronize()
+                got = g.g_exit[:g.sky_count].cpu().numpy().copy()
+                if ref is None:
+                    ref = got
+                    for i in range(len(data)):
+                        rows, ge, gr = run.result(i)
+                        _check_relation(data[i], rows, ge, gr, 25, f"relation {i}")
+                assert np.array_equal(got, ref), (mapping, near, lpt)
     run.close()
 
 
@@ -152,16 +151,31 @@ def test_batch_capacity_and_state_errors(dev):
     assert lib.sky_batch_create(g.x_soa.data_ptr(), g.d, g.n, g._off_c, g.nb, g.ws.data_ptr(),
                                 g.ws_bytes, g.status.data_ptr(), sp, C.byref(h)) == 0
     assert lib.sky_batch_gres(h, 25, None, None, None, None, sp) == _lib.SKY_ERR_STATE
-    assert lib.sky_batch_tune(h, None, sp) == _lib.SKY_ERR_STATE
-    # capacity 1 is below the two relations' skylines
-    rc = lib.sky_batch_skylines(h, g.sky_idx.data_ptr(), 1, g.sky_off.data_ptr(), sp)
-    assert rc == _lib.SKY_ERR_CAPACITY
+    assert lib.sky_batch_tune(h, None, sp) == 0  # choices may be set any time
+    bad = _lib.SkyTune(7, 1, 1)
+    assert lib.sky_batch_tune(h, C.byref(bad), sp) == _lib.SKY_ERR_INVALID_ARG
+    # capacity 1 is below the two relations' skylines: reported on the device
+    assert lib.sky_batch_skylines(h, g.sky_idx.data_ptr(), 1, g.sky_off.data_ptr(), sp) == 0
+    torch.cuda.synchronize()
+    assert int(g.status.item()) == _lib.SKY_ERR_CAPACITY
     inf = _lib.SkyInfo()
     assert lib.sky_batch_info(h, C.byref(inf)) == 0
     mem, _ = oracle.skyline_sfs(x)
     assert inf.sky_count == 2 * int(mem.sum())
     # the costliest relation's local tests: at most all of them, at least their mean
     assert 0 < inf.tests_local_max <= inf.tests_local <= 2 * inf.tests_local_max
+    # with room for every row the same batch gives the oracle's skylines
+    g.status.zero_()
+    assert lib.sky_batch_skylines(h, g.sky_idx.data_ptr(), g.n, g.sky_off.data_ptr(), sp) == 0
+    assert lib.sky_batch_gres(h, 25, g.g_exit.data_ptr(), None, None, None, sp) == 0
+    torch.cuda.synchronize()
+    assert int(g.status.item()) == 0
+    off = g.sky_off.cpu().numpy()
+    want = np.flatnonzero(mem)
+    assert np.array_equal(g.sky_idx[off[0]:off[1]].cpu().numpy(), want)
+    assert np.array_equal(g.sky_idx[off[1]:off[2]].cpu().numpy() - 1000, want)
+    wge, _ = oracle.gres(x, want, 25)
+    assert np.array_equal(g.g_exit[:off[2]].cpu().numpy(), np.concatenate([wge, wge]))
     lib.sky_batch_destroy(h)
     run.close()
 
