@@ -83,28 +83,63 @@ def stored_traffic(workload):
     return out
 
 
+def stored_valu(workload):
+    """VALU figures of the dominance-test and gres-search kernels from the committed PMC summary
+    (profiles/valu_<workload>.txt): per kernel, the VALU instructions issued per launch and the
+    share of the chip's VALU issue slots they fill over the kernel's traced duration; None for a
+    kernel whose source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
+    out = {"dominance_test": None, "gres_search": None}
+    if not os.path.exists(path):
+        return out
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2412_02274_amd", "csrc")
+    sha = lambda f: hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+    for name, src in (("dominance_test", "sky_skyline.hip"), ("gres_search", "sky_gres.hip")):
+        if kv.get(f"{name}.src_sha256_16") == sha(src):
+            out[name] = {"valu_insts_per_launch": float(kv[f"{name}.valu_insts_per_launch"]),
+                         "valu_issue_frac": float(kv[f"{name}.valu_issue_frac"]),
+                         "valu_active_frac": float(kv[f"{name}.valu_active_frac"])}
+    return out
+
+
 def cpu_baseline(x, g_max, rows):
-    """The oracle as it stands on a bounded sample: the first `rows` rows of the workload."""
+    """The oracle as it stands on the first `rows` rows of the workload (all of them by
+    default): SFS on one thread, then Alg. 1's per-tuple search of every skyline tuple on every
+    host core (OpenMP); each leg timed and counted on its own."""
     import numpy as np
     import oracle
     sub = np.ascontiguousarray(x[:rows])
     t0 = time.perf_counter()
     mem, t_sfs = oracle.skyline_sfs(sub)
+    t1 = time.perf_counter()
     sky = np.flatnonzero(mem)
     _, t_gres = oracle.gres(sub, sky, g_max)
-    dt = time.perf_counter() - t0
+    t2 = time.perf_counter()
     cpu_model = None
     try:
         with open("/proc/cpuinfo") as f:
             cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
     except OSError:
         pass
+    dt = t2 - t0
+    part = "the whole workload" if rows >= x.shape[0] else f"the first {rows} rows of the workload"
     return {"value": (t_sfs + t_gres) / dt, "unit": "dominance tests/s",
             "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu_model,
             "host_cpus": os.cpu_count(),
-            "sample": f"first {rows} rows of the workload: SFS skyline ({t_sfs} tests, 1 thread) "
-                      f"+ Alg. 1 gres of its {len(sky)} skyline tuples ({t_gres} tests, OpenMP); "
-                      f"{dt:.1f} s"}
+            "legs": {"skyline_sfs": {"tests": int(t_sfs), "seconds": t1 - t0, "threads": 1,
+                                     "tests_per_s": t_sfs / (t1 - t0)},
+                     "gres_alg1": {"tests": int(t_gres), "seconds": t2 - t1,
+                                   "threads": oracle.num_threads(), "tuples": int(len(sky)),
+                                   "tests_per_s": t_gres / (t2 - t1)}},
+            "seconds_per_pass": dt,
+            "sample": f"{part}: SFS skyline ({t_sfs} tests, 1 thread) + Alg. 1 gres of its "
+                      f"{len(sky)} skyline tuples ({t_gres} tests, OpenMP); {dt:.1f} s"}
 
 
 def main():
@@ -116,10 +151,14 @@ def main():
     ap.add_argument("--scheme", default="none", choices=["none", "grid", "angular", "sliced"])
     ap.add_argument("--p", type=int, default=16)
     ap.add_argument("--mapping", default="auto", choices=["auto", "tiles", "levels"])
-    ap.add_argument("--cpu-rows", type=int, default=200_000)
+    ap.add_argument("--cpu-rows", type=int, default=0, help="oracle baseline rows (0: all)")
+    ap.add_argument("--no-sub", action="store_true", help="default line without the partitioned "
+                    "and serving sub-results")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rate", type=float, default=500.0, help="serve_ties: queries per second")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serve_ties: trace length")
+    ap.add_argument("--sub-serve-seconds", type=float, default=10.0,
+                    help="default line: trace length of the serving sub-result")
     ap.add_argument("--budget-mb", type=int, default=256, help="serve_ties: HBM budget of queries")
     ap.add_argument("--slots", type=int, default=4, help="serve_ties: concurrent query streams")
     ap.add_argument("--no-plain", action="store_true", help="batch/serve: skip the plain path")
@@ -214,23 +253,33 @@ def main():
                         "ops_per_executed_test": 3 * d},
     }
 
-    def roof(name, alg_tests, ms, nl, traffic_step, executed_ops):
-        alg_ops = alg_tests * d
-        ach = alg_ops / (ms * 1e-3) / 1e12
+    valu = stored_valu(args.workload)
+
+    def roof(name, alg_tests, ms, nl, traffic_step, executed_ops, valu_k):
+        # achieved: the element ops of the tests the kernel evaluates (device counters x ops per
+        # test) per launch over its average launch time; the plain method's test count (far more
+        # tests than the pruned kernel evaluates) only as an upper-bound credit
         exe = executed_ops / (ms * 1e-3) / 1e12
-        return {"kernel": name, "bound": "alu", "achieved": ach, "peak": PEAK_ALU_TOPS,
-                "unit": "TOP/s", "frac": ach / PEAK_ALU_TOPS,
-                "traffic": None if traffic_step is None else traffic_step / nl,
-                "launches_per_step": nl, "avg_launch_us": ms * 1e3 / nl,
-                "alg_ops_per_launch": alg_ops / nl,
-                "executed_TOPs": exe, "executed_frac": exe / PEAK_ALU_TOPS}
+        alg = alg_tests * d / (ms * 1e-3) / 1e12
+        r = {"kernel": name, "bound": "alu", "achieved": exe, "peak": PEAK_ALU_TOPS,
+             "unit": "TOP/s", "frac": exe / PEAK_ALU_TOPS,
+             "traffic": None if traffic_step is None else traffic_step / nl,
+             "launches_per_step": nl, "avg_launch_us": ms * 1e3 / nl,
+             "executed_ops_per_launch": executed_ops / nl,
+             "algorithmic_credit": {"ops_per_launch": alg_tests * d / nl, "TOPs": alg,
+                                    "frac_upper_bound": min(alg / PEAK_ALU_TOPS, 1.0),
+                                    "upper_bound": True}}
+        if valu_k is not None:
+            r["valu_pmc"] = valu_k
+        return r
 
     # executed ops: a dominance test compares 2d values (<= and <); a gres candidate test
     # multiplies d values by g and compares each product with two thresholds
     roofs = {"dominance_test": roof("dominance_test", counts["sfs_tests"], test_ms, launches,
-                                    traffic["dominance_test"], executed * ops_per_test),
+                                    traffic["dominance_test"], executed * ops_per_test,
+                                    valu["dominance_test"]),
              "gres_search": roof("gres_search", counts["gres_tests"], gres_ms, 1,
-                                 traffic["gres_search"], gres_executed * 3 * d)}
+                                 traffic["gres_search"], gres_executed * 3 * d, valu["gres_search"])}
     # the HBM-bound ingest (validate + transpose): 4 N d bytes read and 4 N d bytes written, over
     # the event-timed ingest phase of the separately timed pass (one kernel)
     ingest_bytes = 8 * n * d
@@ -241,14 +290,15 @@ def main():
                        "alg_bytes_per_launch": ingest_bytes}
     dominant = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     roofline = dict(roofs[dominant])
-    roofline["note"] = ("achieved = algorithmic tests (oracle's plain sequential method: SFS for the "
-                        "dominance tests, Alg. 1's descending scan for gres) x d element compares per "
-                        "launch / the kernel's average HIP-event launch time (above 1 when box "
-                        "pruning skips more of the plain method's tests than the hardware loses); "
-                        "executed_frac counts the element ops the kernel really evaluates (device "
-                        "counters); peak = 256 CUs x 64 lanes x 2.4 GHz 32-bit VALU lane-ops; "
-                        "traffic = PMC FETCH_SIZE+WRITE_SIZE bytes per launch (calibrated), null "
-                        "when the kernel changed since")
+    roofline["note"] = ("achieved = element ops of the tests the kernel evaluates (device counters: "
+                        "2d compares per dominance test, d multiplies + 2d compares per gres "
+                        "candidate test) per launch / the kernel's average HIP-event launch time; "
+                        "peak = 256 CUs x 64 lanes x 2.4 GHz 32-bit VALU lane-ops; valu_pmc = "
+                        "SQ_INSTS_VALU and SQ_ACTIVE_INST_VALU from rocprofv3 against the issue "
+                        "slots of the traced duration; algorithmic_credit = the plain method's "
+                        "test count (SFS, Alg. 1) x d, an upper bound the pruned kernel does not "
+                        "execute; traffic = PMC FETCH_SIZE+WRITE_SIZE bytes per launch "
+                        "(calibrated), null when the kernel changed since")
     line = {
         "metric": METRIC,
         "value": tests / dt,
@@ -272,6 +322,8 @@ def main():
         "gres_tuples_per_s": s / dt,
         "algorithmic_tests": {"skyline_sfs": counts["sfs_tests"], "gres_alg1": counts["gres_tests"]},
         "executed_skyline_tests": executed,
+        "executed_gres_tests": gres_executed,
+        "executed_tests_per_s": (executed + gres_executed) / dt,
         # the paper's own count of the partitioned method (Sec. 4): the heaviest partition's
         # local-phase tests plus the final phase's
         "paper_skyline_tests": info["tests_local_max"] + info["tests_merge"],
@@ -283,8 +335,18 @@ def main():
                                       "pruned_cells", "pruned_rows", "max_partition")},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(x, g_max, min(args.cpu_rows, n))
+        line["cpu_baseline"] = cpu_baseline(x, g_max, n if args.cpu_rows <= 0 else min(args.cpu_rows, n))
     pool.close()
+    if args.workload == "ant_1m_d6" and args.scheme == "none" and not args.no_sub:
+        # the other single-GPU workloads, compact: partitioned (three schemes) and serving
+        pipe.close()
+        del pipe, xr
+        torch.cuda.empty_cache()
+        line["sub_results"] = {"partitioned": sub_partitioned()}
+        m = serve_measure(dev, args.rate, args.sub_serve_seconds, args.budget_mb, args.slots)
+        line["sub_results"]["serving"] = {k: m[k] for k in (
+            "rate_per_s", "seconds", "latency", "plain_latency", "saturation", "plain_saturation",
+            "same_results_as_plain", "max_in_flight", "sky_sizes")}
     print(json.dumps(line), flush=True)
 
 
@@ -383,49 +445,105 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def bench_serve(args):
-    """Serving workload: 9 resident tie-heavy relations (N in {20k, 130k, 2M} x d in {5, 6, 7},
-    seeds 0..8); Poisson arrivals of gres queries (a relation, a random subset of its skyline,
-    g_max 25); continuous batching under an HBM budget against the plain one-at-a-time path on
-    the same arrivals."""
-    import torch
+def serve_measure(dev, rate, seconds, budget_mb, slots, plain=True):
+    """The served relations (9 resident tie-heavy relations, N in {20k, 130k, 2M} x d in
+    {5, 6, 7}, seeds 0..8) under Poisson arrivals of gres queries (a relation, a random subset
+    of its skyline, g_max 25): continuous batching under an HBM budget, then (plain) the
+    serialized one-query-at-a-time path on the same arrivals, and both at saturation."""
     from paper_2412_02274_amd import datagen as G
     from paper_2412_02274_amd.serve import (PlainServer, Resident, Server, latency_stats,
                                             poisson_trace)
-
-    dev = torch.device("cuda:0")
     residents = [Resident(x, dev) for x in G.serve_relations()]
-    srv = Server(residents, budget_bytes=args.budget_mb << 20, slots=args.slots, device=dev)
-    warm = poisson_trace(residents, rate=args.rate, duration=2.0, seed=1, start=10_000_000)
+    srv = Server(residents, budget_bytes=budget_mb << 20, slots=slots, device=dev)
+    warm = poisson_trace(residents, rate=rate, duration=2.0, seed=1, start=10_000_000)
     srv.run_trace(warm)
-    trace = poisson_trace(residents, rate=args.rate, duration=args.serve_seconds, seed=0)
+    trace = poisson_trace(residents, rate=rate, duration=seconds, seed=0)
     done = srv.run_trace(trace)
-    st = latency_stats(done)
+    out = {"relations": [f"{n}x{d}" for n, d, _ in G.SERVE_SPECS], "rate_per_s": rate,
+           "seconds": seconds, "g_max": 25, "budget_mb": budget_mb, "slots": slots,
+           "latency": latency_stats(done)}
     burst = poisson_trace(residents, rate=1e9, duration=1e-9 * 2000, seed=2)  # all at once
-    sat = latency_stats(Server(residents, budget_bytes=args.budget_mb << 20, slots=args.slots,
-                               device=dev).run_trace(burst))
-    line = _base_line(args, st["tuples_per_s"], "skyline tuples' gres/s", st["mean_ms"], "f32",
-                      {"workload": "serve_ties", "relations": [f"{n}x{d}" for n, d, _ in G.SERVE_SPECS],
-                       "rate_per_s": args.rate, "seconds": args.serve_seconds, "g_max": 25,
-                       "budget_mb": args.budget_mb, "slots": args.slots})
-    line["steps"] = st["requests"]
-    line["latency"] = st
-    line["saturation"] = sat
-    line["resident_mb"] = sum(r.resident_bytes() for r in residents) / 2**20
-    line["sky_sizes"] = [r.s for r in residents]
-    line["max_in_flight"] = srv.max_in_flight
-    if not args.no_plain:
-        plain = PlainServer(residents, device=dev)
-        plain.run_trace(poisson_trace(residents, rate=args.rate, duration=1.0, seed=1))
-        pdone = plain.run_trace(poisson_trace(residents, rate=args.rate, duration=args.serve_seconds,
-                                              seed=0))
-        line["plain_latency"] = latency_stats(pdone)
-        line["plain_saturation"] = latency_stats(PlainServer(residents, device=dev).run_trace(
+    out["saturation"] = latency_stats(Server(residents, budget_bytes=budget_mb << 20, slots=slots,
+                                             device=dev).run_trace(burst))
+    out["resident_mb"] = sum(r.resident_bytes() for r in residents) / 2**20
+    out["sky_sizes"] = [r.s for r in residents]
+    out["max_in_flight"] = srv.max_in_flight
+    if plain:
+        pl = PlainServer(residents, device=dev)
+        pl.run_trace(poisson_trace(residents, rate=rate, duration=1.0, seed=1))
+        pdone = pl.run_trace(poisson_trace(residents, rate=rate, duration=seconds, seed=0))
+        out["plain_latency"] = latency_stats(pdone)
+        out["plain_saturation"] = latency_stats(PlainServer(residents, device=dev).run_trace(
             poisson_trace(residents, rate=1e9, duration=1e-9 * 2000, seed=2)))
         mix = {q.qid: q.g_exit for q in done}
-        line["same_results_as_plain"] = all(
-            (q.g_exit == mix[q.qid]).all() for q in pdone)
+        out["same_results_as_plain"] = all((q.g_exit == mix[q.qid]).all() for q in pdone)
+    return out
+
+
+def bench_serve(args):
+    """Serving workload (serve_measure) as the line's own workload."""
+    import torch
+    dev = torch.device("cuda:0")
+    m = serve_measure(dev, args.rate, args.serve_seconds, args.budget_mb, args.slots, not args.no_plain)
+    st = m["latency"]
+    cfg = {"workload": "serve_ties"}
+    cfg.update({k: m[k] for k in ("relations", "rate_per_s", "seconds", "g_max", "budget_mb", "slots")})
+    line = _base_line(args, st["tuples_per_s"], "skyline tuples' gres/s", st["mean_ms"], "f32", cfg)
+    line["steps"] = st["requests"]
+    line.update({k: v for k, v in m.items() if k not in cfg})
     print(json.dumps(line), flush=True)
+
+
+def sub_partitioned(steps=10):
+    """The partitioned workload (uniform 10,000,000 x 4, seed 0, g_max 25) under Grid, Angular
+    and Sliced partitioning (target 64 partitions) through the captured pipeline: step time,
+    phases, and the HBM-bound phases against the 8 TB/s roof -- build (partition ids, curve
+    order and the partition-contiguous copy: 12d + 8 bytes per row algorithmically: read d
+    values, write d values plus row id and partition id, read and write the staged row) and the
+    local skylines (uniform data: the rows are read once, 4d bytes per row)."""
+    import numpy as np
+    import torch
+    from paper_2412_02274_amd import api
+    from tests.golden import workloads as W
+    counts = W.load_counts()["uni_10m_d4"]
+    kind, n, d, seed, g_max = W.WORKLOADS["uni_10m_d4"]
+    x = torch.from_numpy(W.make("uni_10m_d4")).to("cuda:0")
+    out = {"workload": "uni_10m_d4", "n": n, "d": d, "g_max": g_max, "target_p": 64}
+    for scheme in ("grid", "angular", "sliced"):
+        pipe = api.Pipeline(n, d, scheme, 64, 0, g_max, "auto", "cuda:0")
+        pipe.run(x)
+        sky, ge, _ = pipe.result()
+        if int(sky.numel()) != counts["sky_size"]:
+            raise SystemExit(f"{scheme}: skyline size {int(sky.numel())} differs from the oracle's")
+        hist = np.bincount(ge.cpu().numpy(), minlength=g_max + 1).tolist()
+        if counts.get("g_exit_hist") is not None and hist != counts["g_exit_hist"]:
+            raise SystemExit(f"{scheme}: g_exit histogram differs from the oracle's")
+        graph = pipe.capture(x)
+        graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        del graph
+        pipe.run(x, timing=True)
+        ph = pipe.phase_ms()
+        inf = pipe.info()
+        build_bytes = n * (12 * d + 8)
+        local_bytes = n * 4 * d
+        hbm = lambda b, ms: {"achieved": b / (ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "alg_bytes": b}
+        out[scheme] = {"ms_per_step": dt * 1e3, "phase_ms": ph, "sky_size": int(sky.numel()),
+                       "p": inf["p"], "pruned_rows": inf["pruned_rows"],
+                       "rounds": [inf["rounds_local"], inf["rounds_merge"]],
+                       "paper_skyline_tests": inf["tests_local_max"] + inf["tests_merge"],
+                       "build_hbm": hbm(build_bytes, ph["build"]),
+                       "local_hbm": hbm(local_bytes, ph["local"])}
+        pipe.close()
+        del pipe
+        torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":
