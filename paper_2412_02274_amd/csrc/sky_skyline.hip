@@ -61,6 +61,7 @@ constexpr int kAllHead = 65536;  // first round: a segment with at most this man
 constexpr int kMaxRounds = 16;   // schedule cap (the last round takes every live row)
 constexpr int kTargetWaves = 8192;  // waves per test launch the item split aims at
 constexpr int kTile = 64;     // candidates per tile box
+constexpr int kProbe = 8;     // best-score candidates of a tile tried first against all items
 constexpr uint32_t kPad = 0x7FFFFFFFu;  // padding candidates: above every real value, also as int32
 constexpr int kBoxLds = 4096;           // uint32 tile-box values cached in LDS per workgroup
 constexpr uint32_t kMaxGrid = 8192;     // workgroups of the grid-stride kernels
@@ -720,11 +721,14 @@ __device__ __forceinline__ int32_t find_segment(const int32_t* info, int32_t nse
 }
 
 // One wave per 64-slot tile of the aligned head buffer: candidate values (pads = kPad, pad
-// positions = -1) and the tile box: componentwise minimum lo and maximum hi of its rows.
+// positions = -1) and the tile box: componentwise minimum lo and maximum hi of its rows. Inside
+// the tile the rows are put in ascending score order (ties by slot), pads last: a row with a
+// smaller attribute sum dominates more of the space around the tile, so the test kernel's
+// early-exit probe meets the likeliest dominators first. The box does not depend on the order.
 template <int D>
 __global__ void __launch_bounds__(kBlock) head_values_kernel(
-    const float* __restrict__ xp, int64_t ldp, int32_t d_rt, int32_t nseg,
-    const int32_t* __restrict__ info, const int32_t* __restrict__ counters,
+    const float* __restrict__ xp, int64_t ldp, int32_t d_rt, const float* __restrict__ fsum,
+    int32_t nseg, const int32_t* __restrict__ info, const int32_t* __restrict__ counters,
     int32_t* __restrict__ head, uint32_t* __restrict__ hval, int64_t hcap,
     uint32_t* __restrict__ hlo, uint32_t* __restrict__ hhi, int64_t tcap) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
@@ -737,14 +741,30 @@ __global__ void __launch_bounds__(kBlock) head_values_kernel(
         const int32_t j = j0 + lane;
         const int32_t s = find_segment(info, nseg, SI_HEADOFF, j0);
         const bool valid = j < info[s * kInfo + SI_HEADOFF] + info[s * kInfo + SI_HEADN];
-        const int32_t pos = valid ? head[j] : -1;
-        if (!valid) head[j] = -1;
+        const int32_t pos0 = valid ? head[j] : -1;
+        // bitonic sort of (score bits, slot) over the 64 lanes; scores are >= 0, so their bit
+        // patterns order like the values, and pads (all ones) go last
+        uint64_t key = ((uint64_t)(valid ? fbits(fsum[pos0]) : 0xFFFFFFFFu) << 32) | (uint32_t)lane;
+#pragma unroll
+        for (int size = 2; size <= kWave; size <<= 1)
+#pragma unroll
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const uint32_t ohi = __shfl_xor((uint32_t)(key >> 32), stride, kWave);
+                const uint32_t olo = __shfl_xor((uint32_t)key, stride, kWave);
+                const uint64_t o = ((uint64_t)ohi << 32) | olo;
+                const bool asc = (lane & size) == 0;
+                const bool low = (lane & stride) == 0;
+                key = (low == asc) ? (o < key ? o : key) : (o > key ? o : key);
+            }
+        const int src = (int)(key & (kWave - 1));
+        const int32_t pos = __shfl(pos0, src, kWave);
+        head[j] = pos;  // -1 for the pads, which now fill the tile's last slots
 #pragma unroll
         for (int k = 0; k < DM; ++k)
             if (k < d) {
-                uint32_t v = valid ? fbits(xp[(int64_t)k * ldp + pos]) : kPad;
+                uint32_t v = __shfl(valid ? fbits(xp[(int64_t)k * ldp + pos0]) : kPad, src, kWave);
                 hval[(int64_t)k * hcap + j] = v;
-                uint32_t h = valid ? v : 0u;
+                uint32_t h = pos >= 0 ? v : 0u;
                 for (int off = kWave / 2; off > 0; off >>= 1) {
                     uint32_t o = __shfl_xor(v, off, kWave), q = __shfl_xor(h, off, kWave);
                     v = o < v ? o : v;
@@ -774,11 +794,14 @@ __device__ __forceinline__ int32_t tile_segment(const int32_t* tile_off, int32_t
 //   1. tests the tile's box against all its live items at once (lane = item): a tile can hold a
 //      dominator of t only if lo <= t everywhere, and if hi <= t everywhere with hi < t
 //      somewhere every row of the (non-empty) tile dominates t;
-//   2. loads the tile's 64 candidates once (lane = candidate) and tests every item that passed
-//      the box against all of them: the item's values are broadcast from its lane, and
-//      s dominates t iff max_k(s_k - t_k) <= 0 and min_k(s_k - t_k) < 0 on the bit patterns as
-//      signed integers (canonical values of [0, 1) are below 2^30, so the differences are
-//      exact; lanes past the tile's real rows take 0x7FFFFFFF, whose differences are positive).
+//   2. loads the tile's 64 candidates once (lane = candidate, ascending score order);
+//   3. while many items passed the box, broadcasts the candidates one at a time against all
+//      of them (lane = item), so items that fall to the tile's first rows leave early;
+//   4. tests the items still undecided against all candidates: each item's values are
+//      broadcast from LDS against the candidate lanes.
+// s dominates t iff max_k(s_k - t_k) <= 0 and min_k(s_k - t_k) < 0 on the bit patterns as
+// signed integers (canonical values of [0, 1) are below 2^30, so the differences are exact;
+// lanes past the tile's real rows take 0x7FFFFFFF, whose differences are positive).
 // One candidate load serves 64 items, so the loop is compute-bound. When a group's tiles are
 // split over several units, waves share deaths through dom[] every few tiles.
 // mode 0: items = the head group itself; mode 1: items = the rest group. A dominated item
@@ -867,6 +890,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
         own = own < ntile ? own : ntile - 1;
         const int32_t start = (own >= c0 && own < c0 + span) ? own - c0 : 0;
         int32_t done_steps = 0;
+        bool probe = true;  // uniform: whether the unit still probes its tiles' best rows first
         // the unit's tiles in visiting order c(step) = c0 + (start + step) mod span, 64 at a time
         for (int32_t b0 = 0; b0 < span && live; b0 += kWave) {
             // a tile can pass a live item only if its lower corner is <= the componentwise
@@ -907,10 +931,8 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
                 live &= ~__builtin_amdgcn_ballot_w64(pass && hle && hlt);
                 uint64_t todo = __builtin_amdgcn_ballot_w64(pass) & live;
                 if (todo) {
-                    // 2. the tile's candidates (lane = candidate, in registers) against every
-                    // item that passed: the passing items are compacted in rank order in LDS
-                    // and broadcast one by one, so every step keeps all 64 lanes busy (slots
-                    // past the real candidates hold padding, which never dominates)
+                    // 2. the tile's candidates (lane = candidate, in registers), in ascending
+                    // score order
                     const uint32_t slot = (uint32_t)((t0 + c) * kTile + lane);
                     const int32_t creal = hn - c * kTile < kTile ? hn - c * kTile : kTile;
                     // slots past the tile's real rows act as padding (their values are stale)
@@ -919,51 +941,87 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
 #pragma unroll
                     for (int k = 0; k < DM; ++k)
                         if (k < d) cv[k] = cin ? (int32_t)ld32(hval + k * hcap, slot) : (int32_t)kPad;
-                    const int32_t kk = __popcll(todo);
-                    ntests += (unsigned long long)kk * (unsigned long long)creal;
-                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(todo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
-                    const bool mine = (todo >> lane) & 1ull;
-                    if (mine) {
+                    // 3. probe (lane = item): the tile's kProbe best-score rows, read from the
+                    // candidate lanes, against every passing item at once. On data where most
+                    // rows fall to the first candidates they meet, this replaces a full tile
+                    // of tests per item; a unit stops probing after a probe that decided
+                    // fewer than a quarter of its items.
+                    int32_t q = 0;
+                    if (probe && 2 * __popcll(todo) >= creal) {
+                        q = creal < kProbe ? creal : kProbe;
+                        bool hit = false;
 #pragma unroll
-                        for (int k = 0; k < DM; ++k)
-                            if (k < d) itemc[wave][rank][k] = tv[k];
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                    // each lane marks, by rank, the items its candidate dominates (no
-                    // cross-lane step inside the loop); one OR over the lanes gives the dead
-                    uint32_t mlo = 0, mhi = 0;
-                    const int32_t k1 = kk < 32 ? kk : 32;
-#pragma unroll 4
-                    for (int32_t r = 0; r < k1; ++r) {
-                        int32_t mx = INT32_MIN, mn = INT32_MAX;
+                        for (int32_t j = 0; j < kProbe; ++j)
+                            if (j < q) {
+                                int32_t mx = INT32_MIN, mn = INT32_MAX;
 #pragma unroll
-                        for (int k = 0; k < DM; ++k)
-                            if (k < d) {
-                                const int32_t e = cv[k] - itemc[wave][r][k];
-                                mx = e > mx ? e : mx;
-                                mn = e < mn ? e : mn;
+                                for (int k = 0; k < DM; ++k)
+                                    if (k < d) {
+                                        const int32_t e = __builtin_amdgcn_readlane(cv[k], j) - tv[k];
+                                        mx = e > mx ? e : mx;
+                                        mn = e < mn ? e : mn;
+                                    }
+                                hit |= ((mx - 1) & mn) < 0;
                             }
-                        // mx <= 0 and mn < 0  <=>  the sign bit of (mx - 1) & mn is set
-                        mlo |= ((uint32_t)((mx - 1) & mn) >> 31) << r;
+                        const int32_t left = __popcll(todo);
+                        ntests += (unsigned long long)left * (unsigned long long)q;
+                        const uint64_t killed = __builtin_amdgcn_ballot_w64(((todo >> lane) & 1ull) && hit);
+                        todo &= ~killed;
+                        live &= ~killed;
+                        probe = 4 * __popcll(killed) >= left;
                     }
-#pragma unroll 4
-                    for (int32_t r = 32; r < kk; ++r) {
-                        int32_t mx = INT32_MIN, mn = INT32_MAX;
+                    if (todo) {
+                        // 4. every candidate against every item still undecided: the items are
+                        // compacted in rank order in LDS and broadcast one by one, so every step
+                        // keeps all 64 lanes busy (padding never dominates; the q candidates the
+                        // probe already tried are tried again, which changes nothing and is not
+                        // counted: the count stays one test per pair)
+                        const int32_t kk = __popcll(todo);
+                        ntests += (unsigned long long)kk * (unsigned long long)(creal - q);
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(todo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)todo, 0u));
+                        const bool mine = (todo >> lane) & 1ull;
+                        if (mine) {
 #pragma unroll
-                        for (int k = 0; k < DM; ++k)
-                            if (k < d) {
-                                const int32_t e = cv[k] - itemc[wave][r][k];
-                                mx = e > mx ? e : mx;
-                                mn = e < mn ? e : mn;
-                            }
-                        mhi |= ((uint32_t)((mx - 1) & mn) >> 31) << (r - 32);
+                            for (int k = 0; k < DM; ++k)
+                                if (k < d) itemc[wave][rank][k] = tv[k];
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        // each lane marks, by rank, the items its candidate dominates (no
+                        // cross-lane step inside the loop); one OR over the lanes gives the dead
+                        uint32_t mlo = 0, mhi = 0;
+                        const int32_t k1 = kk < 32 ? kk : 32;
+#pragma unroll 4
+                        for (int32_t r = 0; r < k1; ++r) {
+                            int32_t mx = INT32_MIN, mn = INT32_MAX;
+#pragma unroll
+                            for (int k = 0; k < DM; ++k)
+                                if (k < d) {
+                                    const int32_t e = cv[k] - itemc[wave][r][k];
+                                    mx = e > mx ? e : mx;
+                                    mn = e < mn ? e : mn;
+                                }
+                            // mx <= 0 and mn < 0  <=>  the sign bit of (mx - 1) & mn is set
+                            mlo |= ((uint32_t)((mx - 1) & mn) >> 31) << r;
+                        }
+#pragma unroll 4
+                        for (int32_t r = 32; r < kk; ++r) {
+                            int32_t mx = INT32_MIN, mn = INT32_MAX;
+#pragma unroll
+                            for (int k = 0; k < DM; ++k)
+                                if (k < d) {
+                                    const int32_t e = cv[k] - itemc[wave][r][k];
+                                    mx = e > mx ? e : mx;
+                                    mn = e < mn ? e : mn;
+                                }
+                            mhi |= ((uint32_t)((mx - 1) & mn) >> 31) << (r - 32);
+                        }
+                        mlo = wave_or_u32(mlo);
+                        if (kk > 32) mhi = wave_or_u32(mhi);
+                        const uint64_t dead = ((uint64_t)mhi << 32) | mlo;
+                        __builtin_amdgcn_wave_barrier();  // itemc is rewritten by the next tile
+                        live &= ~__builtin_amdgcn_ballot_w64(mine && ((dead >> (rank & 63u)) & 1ull));
                     }
-                    mlo = wave_or_u32(mlo);
-                    if (kk > 32) mhi = wave_or_u32(mhi);
-                    const uint64_t dead = ((uint64_t)mhi << 32) | mlo;
-                    __builtin_amdgcn_wave_barrier();  // itemc is rewritten by the next tile
-                    live &= ~__builtin_amdgcn_ballot_w64(mine && ((dead >> (rank & 63u)) & 1ull));
                 }
                 if (nr > 1 && (++done_steps & 7) == 0) {
                     // share deaths with the units testing the same items on other tiles
@@ -1330,7 +1388,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
             SKY_HIP(hipGetLastError());
             const int64_t slot_bound = ub + (int64_t)kTile * nseg;
             SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
-                           dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, nseg, (const int32_t*)info_of(r),
+                           dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, pb.fsum, nseg, (const int32_t*)info_of(r),
                            (const int32_t*)ctr(r), b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
             SKY_HIP(hipGetLastError());
             // one launch: the head skyline (every head row against the head rows of its segment)
