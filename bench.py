@@ -155,6 +155,8 @@ def main():
     ap.add_argument("--no-sub", action="store_true", help="default line without the partitioned "
                     "and serving sub-results")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prefilter", action="store_true",
+                    help="every row through the local phase (sky_params.prefilter_off)")
     ap.add_argument("--rate", type=float, default=500.0, help="serve_ties: queries per second")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serve_ties: trace length")
     ap.add_argument("--sub-serve-seconds", type=float, default=10.0,
@@ -182,7 +184,8 @@ def main():
     x = W.make(args.workload)
     dev = torch.device("cuda:0")
     xr = torch.from_numpy(x).to(dev)
-    pipe = api.Pipeline(n, d, args.scheme, args.p, 0, g_max, args.mapping, dev)
+    pipe = api.Pipeline(n, d, args.scheme, args.p, 0, g_max, args.mapping, dev,
+                        prefilter=not args.no_prefilter)
     for _ in range(args.warmup):
         pipe.run(xr)
     pipe.result()
@@ -332,7 +335,7 @@ def main():
         "roofline_kernels": roofs,
         "kernels": kernels,
         "plan": {k: info[k] for k in ("p", "m", "rounds_local", "rounds_merge", "local_count",
-                                      "pruned_cells", "pruned_rows", "max_partition")},
+                                      "pruned_cells", "pruned_rows", "max_partition", "rows_kept")},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(x, g_max, n if args.cpu_rows <= 0 else min(args.cpu_rows, n))

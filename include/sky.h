@@ -75,6 +75,8 @@ typedef enum sky_scheme {
 #define SKY_MAX_G 16777216     /* largest g_max accepted by gres_compute: 2^24, the largest level
                                   at which (float)g is exact, as the key contract needs */
 #define SKY_MAX_REPS 1024      /* largest sky_params.reps */
+#define SKY_KILLERS 8          /* rows per partition that sky_build's prefilter tests every row of
+                                  the partition against (see sky_params.prefilter_off) */
 #define SKY_NOALLOC_SCRATCH_BYTES 67108864 /* 64 MiB: the fixed device workspace of
                                               gres_compute_noalloc, per device */
 
@@ -94,6 +96,13 @@ typedef struct sky_params {
                           other representative dominates are shared with every partition, and
                           the rows they dominate leave the local skylines. The final skyline is
                           unchanged. */
+    int32_t prefilter_off; /* 0 (default): before sorting, sky_build drops every row that one of
+                          SKY_KILLERS rows of its own partition dominates (per partition, the
+                          rows of smallest attribute sum among fixed blocks of rows); such a
+                          row is in no skyline of its partition (Def. 1), so the local skylines,
+                          the final skyline and gres are unchanged, and its tests are counted in
+                          the local phase. 1: every row goes through the local phase. With
+                          reps > 0 every row is kept either way. */
 } sky_params;
 
 typedef struct sky_info {
@@ -109,8 +118,9 @@ typedef struct sky_info {
     int64_t pruned_rows;      /* Grid: rows inside pruned cells */
     int64_t local_count;      /* size of the union of the local skylines */
     int64_t sky_count;        /* size of the final skyline */
-    int64_t tests_local;      /* row-against-row dominance tests evaluated in the local phase
-                                 (counted on device; tile-box tests are not counted) */
+    int64_t tests_local;      /* row-against-row dominance tests evaluated in the local phase,
+                                 the prefilter's (sky_params.prefilter_off) included (counted on
+                                 device; tile-box tests are not counted) */
     int64_t tests_merge;      /* dominance tests evaluated in the final phase */
     int64_t max_partition;    /* rows in the largest partition */
     int32_t events_used;      /* timing-hook event pairs recorded (sky_plan_set_events) */
@@ -120,6 +130,9 @@ typedef struct sky_info {
                                  of the parallel phase as Sec. 4 counts it (its tests plus the
                                  final phase's, tests_merge, are the method's count);
                                  equals tests_local when p = 1 */
+    int64_t rows_kept;        /* rows the build kept for the local phase: n without the
+                                 prefilter (sky_params.prefilter_off), else the rows of unpruned
+                                 partitions that no killer row dominates */
 } sky_info;
 
 typedef struct sky_gres_opts {
@@ -209,8 +222,8 @@ sky_status sky_plan_local(const sky_plan* plan, uint8_t* local, void* stream);
 /*
  * sky_plan_partition_tests -- inspection: tests[j] = the dominance tests sky_local_skylines
  * evaluated for the rows of partition j (device int64[p], p as sky_plan_info reports; rows
- * against head rows of their own partition, plus rows against the representatives when
- * Representative Filtering is on). They sum to sky_info.tests_local and their maximum is
+ * against the prefilter's killer rows and the head rows of their own partition, plus rows
+ * against the representatives when Representative Filtering is on). They sum to sky_info.tests_local and their maximum is
  * sky_info.tests_local_max; pruned Grid cells hold 0. Sec. 4 measures the parallel phase by
  * this maximum. SKY_ERR_STATE before sky_local_skylines.
  */

@@ -31,6 +31,7 @@ SKY_MAX_D = 16
 SKY_MAX_CELLS = 4096
 SKY_MAX_G = 16777216
 SKY_MAX_REPS = 1024
+SKY_KILLERS = 8
 SKY_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # every function the header declares (checked against the header by the tests)
@@ -48,7 +49,7 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
 
 class SkyParams(C.Structure):
     _fields_ = [("scheme", C.c_int32), ("target_p", C.c_int32), ("slice_dim", C.c_int32),
-                ("reps", C.c_int32)]
+                ("reps", C.c_int32), ("prefilter_off", C.c_int32)]
 
 
 class SkyInfo(C.Structure):
@@ -58,7 +59,7 @@ class SkyInfo(C.Structure):
                 ("local_count", C.c_int64), ("sky_count", C.c_int64), ("tests_local", C.c_int64),
                 ("tests_merge", C.c_int64), ("max_partition", C.c_int64),
                 ("events_used", C.c_int32), ("reps_kept", C.c_int32),
-                ("tests_local_max", C.c_int64)]
+                ("tests_local_max", C.c_int64), ("rows_kept", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

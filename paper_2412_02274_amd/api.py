@@ -63,9 +63,9 @@ def ingest(x_rows: torch.Tensor, status: torch.Tensor | None = None, stream=None
     return out
 
 
-def _params(scheme, target_p, slice_dim, reps=0):
+def _params(scheme, target_p, slice_dim, reps=0, prefilter=True):
     code = _lib.SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
-    return _lib.SkyParams(code, int(target_p), int(slice_dim), int(reps))
+    return _lib.SkyParams(code, int(target_p), int(slice_dim), int(reps), 0 if prefilter else 1)
 
 
 def build_workspace_bytes(n: int, d: int, scheme="none", target_p: int = 16,
@@ -176,9 +176,11 @@ class Plan:
 
 def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int = 0,
           status: torch.Tensor | None = None, stream=None, ws: torch.Tensor | None = None,
-          reps: int = 0) -> Plan:
+          reps: int = 0, prefilter: bool = True) -> Plan:
     """Partition assignment + partition-contiguous copy (sky_build). reps: Representative
-    Filtering (Sec. 3.1), the number of representatives (0 = off)."""
+    Filtering (Sec. 3.1), the number of representatives (0 = off). prefilter: drop the rows
+    that a killer row of their own partition dominates before sorting (no effect on any
+    result; sky_params.prefilter_off)."""
     lib = _lib.load()
     if x_soa.dtype != torch.float32 or x_soa.dim() != 2 or not x_soa.is_cuda:
         raise ValueError("x_soa must be a float32 [d, N] CUDA tensor")
@@ -186,7 +188,7 @@ def build(x_soa: torch.Tensor, scheme="none", target_p: int = 16, slice_dim: int
     ld = x_soa.stride(0)
     if x_soa.stride(1) != 1:
         raise ValueError("x_soa rows must be contiguous")
-    prm = _params(scheme, target_p, slice_dim, reps)
+    prm = _params(scheme, target_p, slice_dim, reps, prefilter)
     need = int(lib.sky_build_workspace_bytes(n, d, C.byref(prm)))
     if need == 0:
         raise SkyError(_lib.SKY_ERR_INVALID_ARG, "sky_build_workspace_bytes")
@@ -429,11 +431,12 @@ class Pipeline:
     of the last pass (valid until the next one); ``info()`` its plan counters."""
 
     def __init__(self, n: int, d: int, scheme="none", target_p: int = 16, slice_dim: int = 0,
-                 g_max: int = 25, mapping="auto", device="cuda", reps: int = 0):
+                 g_max: int = 25, mapping="auto", device="cuda", reps: int = 0, prefilter: bool = True):
         lib = _lib.load()
         self.n, self.d, self.g_max = int(n), int(d), int(g_max)
         self.scheme, self.target_p, self.slice_dim, self.mapping = scheme, target_p, slice_dim, mapping
         self.reps = int(reps)
+        self.prefilter = bool(prefilter)
         dev = torch.device(device)
         self.device = dev
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -477,7 +480,7 @@ class Pipeline:
                                   _ptr(self.status), sp), "sky_ingest")
         if ev:
             ev[1].record(st)
-        prm = _params(self.scheme, self.target_p, self.slice_dim, self.reps)
+        prm = _params(self.scheme, self.target_p, self.slice_dim, self.reps, self.prefilter)
         h = C.c_void_p()
         _lib.check(lib.sky_build(_ptr(self.x_soa), self.n, self.d, self.n, C.byref(prm),
                                  _ptr(self.build_ws), self.build_bytes, _ptr(self.status), sp,

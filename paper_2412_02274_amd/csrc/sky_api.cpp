@@ -84,13 +84,14 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->pruned = c.take<uint8_t>((size_t)p);
     P->tan2_dev = c.take<double>((size_t)(scheme == SKY_ANGULAR ? m + 1 : 1));
     P->seg_off_dev = c.take<int64_t>((size_t)(scheme == kSchemeSegments ? p + 1 : 1));
-    // the counting sort by partition runs for every scheme with p > 1 (Sliced included)
-    const int64_t hist_elems = p > 1 ? partition_hist_elems(n, p) : 64;
-    P->phist_cap = hist_elems;
-    P->part_of_row = c.take<int32_t>((size_t)(scheme != SKY_NONE ? n : 1));
-    P->phist = c.take<int32_t>((size_t)hist_elems);
-    int64_t scan_n = hist_elems > n ? hist_elems : n;
-    P->scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(scan_n));
+    P->part_of_row = c.take<int32_t>((size_t)(p > 1 ? n : 1));
+    P->pcount = c.take<int32_t>((size_t)p);
+    P->kmin = c.take<unsigned long long>((size_t)p * SKY_KILLERS);
+    P->krow = c.take<int32_t>((size_t)p * SKY_KILLERS);
+    P->kval = c.take<float>((size_t)p * SKY_KILLERS * (size_t)partition_row_stride(d));
+    P->alive = c.take<uint8_t>((size_t)n);
+    P->blk = c.take<int32_t>((size_t)partition_blocks(n) + 64);
+    P->scan_tmp = c.take<int32_t>((size_t)scan_tmp_elems(n));
     P->xa = c.take<float>((size_t)n * (size_t)partition_row_stride(d));
     P->rep_kept = c.take<int32_t>((size_t)SKY_MAX_REPS + 1);
     P->rep_tests = c.take<unsigned long long>(1);
@@ -149,19 +150,26 @@ sky_status plan_partition(sky_plan* P, hipStream_t st) {
     a.scheme = P->scheme; a.p = P->p; a.m = P->m; a.slice_dim = P->slice_dim;
     a.seg_off = P->seg_off_dev;
     a.tan2 = P->tan2_dev;
+    a.prefilter = P->prefilter;
     a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
+    a.n_live = P->count_tmp + CT_ROWS;
     a.part_off = P->part_off; a.pruned = P->pruned;
-    a.part_of_row = P->part_of_row; a.hist = P->phist; a.hist_cap = P->phist_cap;
+    a.part_of_row = P->part_of_row;
+    a.pcount = P->pcount; a.kmin = P->kmin; a.krow = P->krow; a.kval = P->kval;
+    a.alive = P->alive; a.blk = P->blk;
     a.scan_tmp = P->scan_tmp;
     a.k0 = P->k0; a.v0 = P->v0; a.k1 = P->k1; a.v1 = P->v1; a.radix_tmp = P->radix_tmp;
     a.xa = P->xa;
+    a.seg_tests = P->seg_tests;
+    a.tests = reinterpret_cast<unsigned long long*>(P->dinfo + D_TESTS_FILTER);
     a.dev_status = P->dev_status;
     return launch_partition(a, st);
 }
 
 sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int32_t scheme, int32_t p,
-                      int32_t m, int32_t slice_dim, const int64_t* seg_off_host, void* ws,
-                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out, bool launch) {
+                      int32_t m, int32_t slice_dim, const int64_t* seg_off_host, int32_t reps, bool prefilter,
+                      void* ws, size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out,
+                      bool launch) {
     *out = nullptr;
     size_t need = plan_bytes(n, d, scheme, p, m);
     if (need == 0) return SKY_ERR_INVALID_ARG;
@@ -175,6 +183,8 @@ sky_status plan_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, int3
     P->x = x_soa; P->n = n; P->ld = ld; P->d = d;
     P->scheme = scheme; P->p = p; P->m = m; P->slice_dim = slice_dim;
     P->dev_status = dev_status;
+    P->reps = reps;
+    P->prefilter = prefilter && reps == 0;
     if (P->scheme == kSchemeSegments) {
         // the caller's host array may go away on return: wait for the copy
         hipError_t e1 = hipMemcpyAsync(P->seg_off_dev, seg_off_host, sizeof(int64_t) * (size_t)(p + 1),
@@ -249,14 +259,13 @@ sky_status sky_build(const float* x_soa, int64_t n, int32_t d, int64_t ld, const
     if (!out) return SKY_ERR_INVALID_ARG;
     *out = nullptr;
     if (!x_soa || !params || !ws || !dev_status) return SKY_ERR_INVALID_ARG;
-    if (n < 1 || n > kMaxBuildRows || !valid_d(d) || ld < n || params->reps < 0 || params->reps > SKY_MAX_REPS)
+    if (n < 1 || n > kMaxBuildRows || !valid_d(d) || ld < n || params->reps < 0 || params->reps > SKY_MAX_REPS ||
+        (params->prefilter_off != 0 && params->prefilter_off != 1))
         return SKY_ERR_INVALID_ARG;
     int32_t p = 1, m = 0;
     SKY_TRY(resolve_partitions(n, d, params, &p, &m));
-    SKY_TRY(plan_build(x_soa, n, d, ld, params->scheme, p, m, params->slice_dim, nullptr, ws, ws_bytes,
-                       dev_status, (hipStream_t)stream, out, true));
-    (*out)->reps = params->reps;
-    return SKY_OK;
+    return plan_build(x_soa, n, d, ld, params->scheme, p, m, params->slice_dim, nullptr, params->reps,
+                      params->prefilter_off == 0, ws, ws_bytes, dev_status, (hipStream_t)stream, out, true);
 }
 
 sky_status sky_local_skylines(sky_plan* P, void* stream) {
@@ -309,18 +318,29 @@ sky_status plan_local_phase(sky_plan* P, hipStream_t st) {
         SKY_TRY(launch_representatives(ra, st));
         keep = P->member_tmp;
     }
-    // the first round's list: every position outside the pruned cells and not filtered out
-    int32_t* cnt = P->count_tmp + CT_LIST;
-    SKY_TRY(launch_iota_filtered(skip, P->seg, n, P->eng.w1, cnt, P->eng.scan_tmp, st, keep));
+    // the first round's list: with the prefilter, every position of the copy (it holds only
+    // rows of unpruned partitions that no killer row dominates); else every position outside
+    // the pruned cells and not filtered out by the representatives
+    const int32_t* cnt = P->count_tmp + CT_LIST;
+    if (P->prefilter) {
+        cnt = P->count_tmp + CT_ROWS;
+        SKY_TRY(launch_iota_count(cnt, n, P->eng.w1, st));
+    } else {
+        SKY_TRY(launch_iota_filtered(skip, P->seg, n, P->eng.w1, P->count_tmp + CT_LIST, P->eng.scan_tmp, st,
+                                     keep));
+    }
     EngineProblem pb{};
     pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
     pb.seg_of_pos = P->p > 1 ? P->seg : nullptr;
     pb.nseg = P->p;
     pb.seg_tests = P->seg_tests;
-    pb.zero_seg_tests = P->reps == 0;
+    // the prefilter's tests are already in seg_tests (the build zeroed them); representatives
+    // add theirs above
+    pb.zero_seg_tests = P->reps == 0 && !P->prefilter;
+    pb.extra_tests = reinterpret_cast<const unsigned long long*>(P->dinfo + D_TESTS_FILTER);
     pb.items = P->eng.w1;
     pb.n_items = n;
-    pb.n_items_dev = (skip || keep) ? cnt : nullptr;
+    pb.n_items_dev = (skip || keep || P->prefilter) ? cnt : nullptr;
     pb.ub_items = n;
     pb.flag_out = P->local_flag;
     pb.out_rounds = P->dinfo + D_ROUNDS_LOCAL;
@@ -373,7 +393,12 @@ extern "C" {
 sky_status sky_plan_partitions(const sky_plan* P, int32_t* part, void* stream) {
     if (!P || !part) return SKY_ERR_INVALID_ARG;
     if (P->state < 1) return SKY_ERR_STATE;
-    return launch_scatter_rows(P->seg, nullptr, P->rowid, P->n, part, nullptr, (hipStream_t)stream);
+    if (P->p == 1)
+        return launch_fill_u8(reinterpret_cast<uint8_t*>(part), P->n * (int64_t)sizeof(int32_t), 0,
+                              (hipStream_t)stream);
+    SKY_HIP(hipMemcpyAsync(part, P->part_of_row, (size_t)P->n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return SKY_OK;
 }
 
 sky_status sky_plan_local(const sky_plan* P, uint8_t* local, void* stream) {
@@ -381,8 +406,10 @@ sky_status sky_plan_local(const sky_plan* P, uint8_t* local, void* stream) {
     if (P->state < 2) return SKY_ERR_STATE;
     // before sky_merge the local skylines are the head rows not dominated; sky_merge rewrites
     // local_flag to exactly them (its own phase marks more rows dominated)
+    // rows the build did not keep (the prefilter's) are in no local skyline
+    SKY_TRY(launch_fill_u8(local, P->n, 0, (hipStream_t)stream));
     return launch_scatter_rows_live(P->local_flag, P->state == 2 ? P->eng.dom : nullptr, P->rowid, P->n,
-                                    local, (hipStream_t)stream);
+                                    P->count_tmp + CT_ROWS, local, (hipStream_t)stream);
 }
 
 sky_status sky_plan_partition_tests(const sky_plan* P, int64_t* tests, void* stream) {
@@ -410,10 +437,11 @@ sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
     if (P->state < 2) return SKY_OK;
     // the counters the device wrote, read on the stream of the plan's last call
     int64_t dv[kDinfo];
-    int32_t nk = 0;
+    int32_t nk = 0, kept = 0;
     unsigned long long rt = 0;
     hipStream_t st = P->last_stream;
     SKY_HIP(hipMemcpyAsync(dv, P->dinfo, sizeof(dv), hipMemcpyDeviceToHost, st));
+    SKY_HIP(hipMemcpyAsync(&kept, P->count_tmp + CT_ROWS, sizeof(kept), hipMemcpyDeviceToHost, st));
     if (P->reps > 0) {
         SKY_HIP(hipMemcpyAsync(&nk, P->rep_kept + SKY_MAX_REPS, sizeof(nk), hipMemcpyDeviceToHost, st));
         SKY_HIP(hipMemcpyAsync(&rt, P->rep_tests, sizeof(rt), hipMemcpyDeviceToHost, st));
@@ -426,6 +454,7 @@ sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
     out->tests_local = dv[D_TESTS_LOCAL] + (int64_t)rt;
     out->tests_local_max = dv[D_TESTS_LOCAL_MAX];
     out->reps_kept = nk;
+    out->rows_kept = kept;
     if (P->state >= 3) {
         out->sky_count = dv[D_SKY_COUNT];
         if (P->p > 1) {

@@ -98,7 +98,7 @@ sky_status sky_batch_create(const float* x_soa, int32_t d, int64_t ld, const int
     if (!B) return SKY_ERR_INVALID_ARG;
     const size_t pb = (size_t)round_up((int64_t)plan_bytes(n, d, kSchemeSegments, nbatch, 0), 256);
     // the plan only: its partition step is queued by every sky_batch_skylines
-    sky_status s = plan_build(x_soa, n, d, ld, kSchemeSegments, nbatch, 0, 0, offsets, ws, pb,
+    sky_status s = plan_build(x_soa, n, d, ld, kSchemeSegments, nbatch, 0, 0, offsets, 0, true, ws, pb,
                               dev_status, (hipStream_t)stream, &B->plan, false);
     if (s != SKY_OK) { delete B; return s; }
     Carver c((char*)ws + pb, ws_bytes - pb);
@@ -176,6 +176,7 @@ sky_status sky_batch_info(const sky_batch* B, sky_info* out) {
     out->rounds_local = pi.rounds_local;
     out->tests_local = pi.tests_local;
     out->tests_local_max = pi.tests_local_max;  // the costliest relation
+    out->rows_kept = pi.rows_kept;
     out->local_count = pi.sky_count;
     out->sky_count = pi.sky_count;
     return SKY_OK;

@@ -53,6 +53,30 @@ __device__ __forceinline__ uint64_t match_any(uint32_t key, int bits, uint64_t a
     return m;
 }
 
+// Exclusive prefix over a workgroup of kBlock threads of one int32 per thread; *total = the
+// sum. ws: kBlock / kWave int32 of LDS. Every thread of the workgroup must call it.
+__device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* ws, int32_t* total) {
+    const int lane = (int)lane_id(), wave = threadIdx.x / kWave;
+    int32_t x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t t = __shfl_up(x, off, kWave);
+        if (lane >= off) x += t;
+    }
+    if (lane == kWave - 1) ws[wave] = x;
+    __syncthreads();
+    int32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        const int32_t s = ws[w];
+        pre += w < wave ? s : 0;
+        tot += s;
+    }
+    __syncthreads();  // ws may be reused at once
+    *total = tot;
+    return pre + x - v;
+}
+
 // Hilbert-curve key of a point of canonical values in [0, 1): `bits` bits per attribute,
 // bits * d <= 32. Coordinates are the top bits of the values (v * 2^bits, exact), mapped to
 // the curve with J. Skilling's transposition algorithm ("Programming the Hilbert curve",
@@ -160,11 +184,13 @@ sky_status launch_exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int
 
 // sky_radix.hip: stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
 // over the low 'key_bits' bits. Results end in (k0, v0) (the buffers are ping-ponged), or, when
-// out_k and out_v are given, wherever the last pass left them (no final copy).
+// out_k and out_v are given, wherever the last pass left them (no final copy). With n_dev the
+// pairs are the first min(*n_dev, n) (a count on the device; n bounds it and sizes the grids).
 int64_t radix_tmp_elems(int64_t n);
 sky_status launch_radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n,
                              int key_bits, int32_t* tmp, hipStream_t st,
-                             const uint32_t** out_k = nullptr, const uint32_t** out_v = nullptr);
+                             const uint32_t** out_k = nullptr, const uint32_t** out_v = nullptr,
+                             const int32_t* n_dev = nullptr);
 
 // sky_partition.hip
 // Internal partition scheme of the batched path: partition j = the rows [seg_off[j],
@@ -176,22 +202,31 @@ struct PartitionArgs {
     int32_t scheme; int32_t p; int32_t m; int32_t slice_dim;
     const int64_t* seg_off;    // kSchemeSegments: [p+1] row offsets of the datasets (device)
     double* tan2;              // Angular thresholds tan^2(k*pi/(2m)), k = 0..m (device, written here)
-    float* xp; int64_t ldp;    // partition-contiguous canonical SoA copy
-    int32_t* rowid;            // partitioned position -> original row
-    int32_t* seg;              // partitioned position -> partition
-    float* fsum;               // partitioned position -> FP32 attribute sum (SFS score)
-    int32_t* part_off;         // [p+1]
+    bool prefilter;            // drop the rows their partition's killer rows dominate (else keep all)
+    float* xp; int64_t ldp;    // partition-contiguous canonical SoA copy of the kept rows
+    int32_t* rowid;            // position -> original row
+    int32_t* seg;              // position -> partition
+    float* fsum;               // position -> FP32 attribute sum (SFS score)
+    int32_t* n_live;           // device: positions in the copy (rows kept)
+    int32_t* part_off;         // [p+1] partition offsets over all rows (partition sizes)
     uint8_t* pruned;           // [p] Grid: pruned by grid dominance
-    int32_t* part_of_row;      // [n] scratch
-    int32_t* hist;             // [p * ntiles] scratch
-    int64_t hist_cap;          // entries available in hist
-    int32_t* scan_tmp;         // scan scratch
-    uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp; // Sliced sort scratch
+    int32_t* part_of_row;      // [n] partition of every row (p > 1)
+    int32_t* pcount;           // [p] scratch: rows per partition
+    unsigned long long* kmin;  // [p * SKY_KILLERS] scratch: per-slot minima of (score, row)
+    int32_t* krow;             // [p * SKY_KILLERS] scratch: killer rows (-1: none)
+    float* kval;               // [p * SKY_KILLERS][row stride] scratch: killer values
+    uint8_t* alive;            // [n] scratch: rows kept
+    int32_t* blk;              // [partition_blocks(n)] scratch: rows kept per workgroup
+    int32_t* scan_tmp;         // scan scratch (scan_tmp_elems(partition_blocks(n)))
+    uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp;  // sort scratch (n)
     float* xa;                 // [n][partition_row_stride(d)] row-major canonical staging copy
+    unsigned long long* seg_tests;  // [p] out: the prefilter's tests per partition
+    unsigned long long* tests;      // out: the prefilter's tests in all
     int32_t* dev_status;
 };
-int64_t partition_hist_elems(int64_t n, int32_t p);
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
+// workgroups of the per-row passes of launch_partition (4096 rows each)
+int64_t partition_blocks(int64_t n);
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st);
 // out[0..3) = pruned non-empty cells, rows inside them, rows of the largest partition (int64)
 sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned, int32_t p, int64_t* out,
@@ -277,6 +312,8 @@ struct EngineProblem {
     int64_t* out_rounds;           // optional device words written at the end of the run: rounds
     int64_t* out_tests;            //   with live items, dominance tests evaluated, and the largest
     int64_t* out_tests_max;        //   count of one segment (the total without seg_tests)
+    const unsigned long long* extra_tests;  // optional device word added to out_tests (tests the
+                                            // caller evaluated before the run, already in seg_tests)
     void* const* ev_begin;         // optional timing events around the test launches
     void* const* ev_end;
     int32_t ev_cap;
@@ -291,12 +328,12 @@ sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_p
                                 int32_t* out, int32_t* count, int32_t* scan_tmp, hipStream_t st,
                                 const uint8_t* keep = nullptr);
 sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
-// dst[rowid[q]] = src[q] for q < n (int32 and/or uint8 arrays)
-sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
-                               int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st);
-// dst[rowid[q]] = src[q] && !(drop && drop[q]) for q < n
+// out[q] = q for q < *count (count on the device, at most n)
+sky_status launch_iota_count(const int32_t* count, int32_t n, int32_t* out, hipStream_t st);
+// dst[rowid[q]] = src[q] && !(drop && drop[q]) for q < n (q < min(n, *count) with count, a
+// device word)
 sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,
-                                    uint8_t* dst, hipStream_t st);
+                                    const int32_t* count, uint8_t* dst, hipStream_t st);
 // positions i < n with flags[i] != 0 and (drop null or drop[i] == 0), in order, into out; their
 // number into *count32 and *count64 (either may be null); with bake, flags[i] is rewritten to
 // the selection

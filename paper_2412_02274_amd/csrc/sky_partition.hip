@@ -13,16 +13,28 @@
 //  Sliced   rows ordered by (t[dim], row index); the i-th (0-based) goes to floor(i p / n).
 //  None     one partition.
 //
-// Every path validates the domain (SKY_ERR_DOMAIN) and writes a canonical SoA copy in partition
-// order, with the rows of each partition along a Hilbert curve (a stable radix sort of the
-// Hilbert keys followed by a stable counting sort by partition), the original row of every
-// position, its partition, and the FP32 attribute sum used as the monotone score that orders
-// the skyline filter (Sec. 2, scoring function). The spatial order inside partitions keeps
-// the tile boxes of the dominance tests tight.
-//
-// Grid/Angular use a counting sort: per wave-tile histograms of the partition ids, one
-// exclusive scan of the partition-major table, then a stable scatter where each wave ranks
-// equal ids among its 64 lanes with ballots. Bound: HBM.
+// The steps, for every scheme:
+//  1. classify (one pass over the relation): validate the domain (SKY_ERR_DOMAIN), take the
+//     canonical values, the partition and the FP32 attribute sum (the monotone score of the
+//     skyline filter, Sec. 2), write a row-major staging copy, count the rows of every
+//     partition, and keep, per partition, the row of smallest score of each workgroup's 4096
+//     rows, folded into SKY_KILLERS slots (slot = workgroup mod SKY_KILLERS, minimum per slot).
+//  2. partition offsets, then Grid pruning (Def. 3) from the partition sizes.
+//  3. prefilter: every row of an unpruned partition is tested against that partition's slot
+//     rows (the "killers"; a row is not tested against itself). A row one of them dominates
+//     belongs to no skyline of its partition (Def. 1 inside the partition), so it is dropped
+//     before any sorting. On uniform data a few rows of smallest score dominate almost every
+//     row of their partition (10M x 4 in 81 cells: about 3% of the rows remain); on
+//     anticorrelated data the prefilter keeps most rows and costs one streaming pass. With
+//     Representative Filtering, or when the caller turns it off, every row is kept (the
+//     representatives are drawn from all rows, pruned cells included).
+//  4. the kept rows, in row order, with sort keys (partition, Hilbert key of the values);
+//  5. a stable radix sort of those keys over the kept rows only (their count stays on the
+//     device);
+//  6. the partition-contiguous canonical SoA copy of the kept rows in key order: inside every
+//     partition the rows follow a Hilbert curve, which keeps the tile boxes of the dominance
+//     tests tight; with the original row, the partition and the score of every position.
+// Bound: HBM (steps 1 and 3 stream the relation; the sort and the copy touch the kept rows).
 #include "sky_internal.hpp"
 
 namespace sky {
@@ -33,11 +45,11 @@ namespace {
 template <int D>
 constexpr int row_stride() { return D == 0 ? 16 : (D <= 4 ? 4 : (D <= 8 ? 8 : 16)); }
 
-// The canonical values of row i from the staging copy.
+// The first row_stride<D>() floats at p (16-byte aligned).
 template <int D>
-__device__ __forceinline__ void load_row(const float* __restrict__ xa, int64_t i, float* v) {
+__device__ __forceinline__ void load_row(const float* __restrict__ p, float* v) {
     constexpr int RS = row_stride<D>();
-    const float4* row = reinterpret_cast<const float4*>(xa + i * RS);
+    const float4* row = reinterpret_cast<const float4*>(p);
 #pragma unroll
     for (int c = 0; c < RS / 4; ++c) {
         const float4 q = row[c];
@@ -45,8 +57,9 @@ __device__ __forceinline__ void load_row(const float* __restrict__ xa, int64_t i
     }
 }
 
-constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int64_t kHistCap = int64_t(1) << 22;  // max entries of the histogram table
+constexpr int kPRows = 4096;              // rows per workgroup of the classify/filter/compact passes
+constexpr int kPPer = kPRows / kBlock;    // 16 rows per thread
+constexpr int kKill = SKY_KILLERS;
 
 int bits_for(int32_t p) {
     int b = 0;
@@ -57,165 +70,193 @@ int bits_for(int32_t p) {
 template <int D>
 __device__ __forceinline__ int dget(int d) { return D > 0 ? D : d; }
 
-// ---- per-row partition id (Grid / Angular) + validation --------------------------------------
+// ---- the partition of a row from its canonical values (Grid / Angular) ------------------------
 template <int D>
-__global__ void __launch_bounds__(kBlock) part_id_kernel(const float* __restrict__ x, int64_t n,
-                                                          int32_t d_rt, int64_t ld, int32_t scheme,
-                                                          int32_t m, const double* __restrict__ tan2,
-                                                          int32_t* __restrict__ part,
-                                                          int32_t* dev_status) {
-    const int d = dget<D>(d_rt);
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool bad = false;
-    if (i < n) {
-        float v[SKY_MAX_D];
+__device__ __forceinline__ int32_t cell_of(const float* v, int d, int32_t scheme, int32_t m,
+                                           const double* __restrict__ tan2) {
+    int32_t id = 0;
+    if (scheme == SKY_GRID) {
+        const float fm = (float)m;
+        int32_t w = 1;
 #pragma unroll
         for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
             if (k < d) {
-                float t = x[(int64_t)k * ld + i];
-                bad |= !in_domain(t);
-                v[k] = canon(t);
+                int32_t c = qkey(v[k], fm);
+                c = c < 0 ? 0 : (c > m - 1 ? m - 1 : c);
+                id += c * w;
+                w *= m;
             }
-        int32_t id = 0;
-        if (scheme == SKY_GRID) {
-            const float fm = (float)m;
-            int32_t w = 1;
-#pragma unroll
-            for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
-                if (k < d) {
-                    int32_t c = qkey(v[k], fm);
-                    c = c < 0 ? 0 : (c > m - 1 ? m - 1 : c);
-                    id += c * w;
-                    w *= m;
-                }
-        } else {  // SKY_ANGULAR
-            // weights m^a for a = 0..d-2; suffix sums of squares from the last attribute down
-            int32_t w[SKY_MAX_D];
-            w[0] = 1;
-            for (int a = 1; a < d - 1; ++a) w[a] = w[a - 1] * m;
-            double r2 = 0.0;
-            for (int a = d - 2; a >= 0; --a) {
-                double nx = (double)v[a + 1];
-                r2 += nx * nx;
-                double xa = (double)v[a];
-                double xa2 = xa * xa;
-                int32_t b = 0;
-                if (r2 > 0.0) {
-                    // largest k in [0, m-1] with r2 >= xa2 * tan2[k] (tan2[0] = 0 always holds)
-                    int lo = 0, hi = m - 1;
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (r2 >= xa2 * tan2[mid]) lo = mid; else hi = mid - 1;
-                    }
-                    b = lo;
-                }
-                id += b * w[a];
-            }
-        }
-        part[i] = id;
+        return id;
     }
-    if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
+    // SKY_ANGULAR: weights m^a for a = 0..d-2; suffix sums of squares from the last attribute
+    int32_t w[SKY_MAX_D];
+    w[0] = 1;
+    for (int a = 1; a < d - 1; ++a) w[a] = w[a - 1] * m;
+    double r2 = 0.0;
+    for (int a = d - 2; a >= 0; --a) {
+        const double nx = (double)v[a + 1];
+        r2 += nx * nx;
+        const double xa = (double)v[a];
+        const double xa2 = xa * xa;
+        int32_t b = 0;
+        if (r2 > 0.0) {
+            // largest k in [0, m-1] with r2 >= xa2 * tan2[k] (tan2[0] = 0 always holds)
+            int lo = 0, hi = m - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (r2 >= xa2 * tan2[mid]) lo = mid; else hi = mid - 1;
+            }
+            b = lo;
+        }
+        id += b * w[a];
+    }
+    return id;
 }
 
-// ---- per-row partition id (batched datasets): the dataset holding the row ---------------------
-// largest j in [0, p) with seg_off[j] <= i; empty datasets share their offset with the next one,
-// so the search lands on the non-empty dataset that holds row i
-__global__ void __launch_bounds__(kBlock) seg_part_kernel(const int64_t* __restrict__ seg_off,
-                                                           int32_t p, int64_t n,
-                                                           int32_t* __restrict__ part) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
+// The dataset holding row i (batched path): largest j in [0, p) with seg_off[j] <= i; empty
+// datasets share their offset with the next one, so the search lands on the non-empty one.
+__device__ __forceinline__ int32_t dataset_of(const int64_t* __restrict__ seg_off, int32_t p, int64_t i) {
     int32_t lo = 0, hi = p - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
         if (seg_off[mid] <= i) lo = mid; else hi = mid - 1;
     }
-    part[i] = lo;
+    return lo;
 }
 
-// ---- wave-tile histogram of partition ids ----------------------------------------------------
-__global__ void __launch_bounds__(kBlock) part_hist_kernel(const int32_t* __restrict__ part,
-                                                            const uint32_t* __restrict__ order,
-                                                            int64_t n, int32_t p, int chunks,
-                                                            int32_t* __restrict__ hist,
-                                                            int64_t ntiles) {
-    extern __shared__ int32_t cnt[];  // [kWavesPerBlock][p]
-    const int wave = threadIdx.x / kWave;
-    const int lane = (int)lane_id();
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    int32_t* my = cnt + (int64_t)wave * p;
-    for (int i = lane; i < p; i += kWave) my[i] = 0;
-    __syncthreads();
-    if (tile < ntiles) {
-        const int64_t base = tile * (int64_t)chunks * kWave;
-        for (int c = 0; c < chunks; ++c) {
-            int64_t idx = base + (int64_t)c * kWave + lane;
-            if (idx < n) atomicAdd(&my[part[order ? (int64_t)order[idx] : idx]], 1);
-        }
+// ---- 0. per-build counters -----------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) partition_init_kernel(int32_t p, int32_t* __restrict__ pcount,
+                                                                unsigned long long* __restrict__ kmin,
+                                                                unsigned long long* __restrict__ seg_tests,
+                                                                unsigned long long* __restrict__ tests) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g < p) {
+        pcount[g] = 0;
+        seg_tests[g] = 0ull;
+    }
+    if (g < (int64_t)p * kKill) kmin[g] = ~0ull;
+    if (g == 0) *tests = 0ull;
+}
+
+// ---- 1. classify -----------------------------------------------------------------------------------
+struct ClassifyArgs {
+    const float* x; int64_t n; int32_t d; int64_t ld;
+    int32_t scheme; int32_t p; int32_t m;
+    const double* tan2;             // Angular thresholds
+    const int64_t* seg_off;         // batched datasets
+    int32_t* part_of_row;           // written (Grid/Angular/datasets), read (Sliced), null (None)
+    float* xa;                      // [n][row stride] staging copy
+    int32_t* pcount;                // [p] rows per partition (+=)
+    unsigned long long* kmin;       // [p][kKill] minima of (score bits << 32 | row)
+    int32_t* dev_status;
+};
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) classify_kernel(ClassifyArgs a) {
+    constexpr int RS = row_stride<D>();
+    extern __shared__ unsigned long long lmin[];  // [p], then int32 counts [p]
+    int32_t* lcnt = reinterpret_cast<int32_t*>(lmin + a.p);
+    const int d = dget<D>(a.d);
+    for (int32_t j = threadIdx.x; j < a.p; j += kBlock) {
+        lmin[j] = ~0ull;
+        lcnt[j] = 0;
     }
     __syncthreads();
-    if (tile < ntiles)
-        for (int i = lane; i < p; i += kWave) hist[(int64_t)i * ntiles + tile] = my[i];
-}
-
-// ---- stable scatter into partition-contiguous order ---------------------------------------------
-template <int D>
-__global__ void __launch_bounds__(kBlock) part_scatter_kernel(
-    const float* __restrict__ xa, int64_t n, int32_t d_rt,
-    const int32_t* __restrict__ part, const uint32_t* __restrict__ order, int32_t p, int pbits,
-    int chunks, const int32_t* __restrict__ offs, int64_t ntiles, float* __restrict__ xp, int64_t ldp,
-    int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
-    extern __shared__ int32_t base[];  // [kWavesPerBlock][p]
-    const int d = dget<D>(d_rt);
-    const int wave = threadIdx.x / kWave;
-    const int lane = (int)lane_id();
-    const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + wave;
-    if (tile >= ntiles) return;  // only wave-level synchronisation below
-    int32_t* my = base + (int64_t)wave * p;
-    for (int i = lane; i < p; i += kWave) my[i] = offs[(int64_t)i * ntiles + tile];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    const uint64_t lt = __lanemask_lt();
-    const int64_t tbase = tile * (int64_t)chunks * kWave;
-    for (int c = 0; c < chunks; ++c) {
-        const int64_t q = tbase + (int64_t)c * kWave + lane;
-        bool valid = q < n;
-        uint64_t act = __ballot(valid);
-        if (act == 0) break;
-        const int64_t i = valid ? (order ? (int64_t)order[q] : q) : 0;
-        int32_t id = valid ? part[i] : 0;
-        uint64_t peers = match_any((uint32_t)id, pbits, act);
-        int32_t b = valid ? my[id] : 0;
-        __builtin_amdgcn_wave_barrier();
+    bool bad = false;
+    const int64_t b0 = (int64_t)blockIdx.x * kPRows;
+    for (int it = 0; it < kPPer; ++it) {
+        const int64_t i = b0 + (int64_t)it * kBlock + threadIdx.x;
+        const bool valid = i < a.n;
+        int32_t part = -1;
+        unsigned long long key = ~0ull;
         if (valid) {
-            int32_t pos = b + (int32_t)__popcll(peers & lt);
-            float v[row_stride<D>()];
-            load_row<D>(xa, i, v);
+            float v[RS];
             float f = 0.0f;
 #pragma unroll
+            for (int k = 0; k < RS; ++k) {
+                const float t = k < d ? a.x[(int64_t)k * a.ld + i] : 0.0f;
+                bad |= !in_domain(t);
+                v[k] = canon(t);
+            }
+#pragma unroll
             for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
-                if (k < d) {
-                    xp[(int64_t)k * ldp + pos] = v[k];
-                    f = __fadd_rn(f, v[k]);
-                }
-            rowid[pos] = (int32_t)i;
-            seg[pos] = id;
-            fsum[pos] = f;
-            if ((peers & lt) == 0) my[id] = b + (int32_t)__popcll(peers);
+                if (k < d) f = __fadd_rn(f, v[k]);
+            if (a.scheme == SKY_NONE) part = 0;
+            else if (a.scheme == SKY_SLICED) part = a.part_of_row[i];
+            else if (a.scheme == kSchemeSegments) part = dataset_of(a.seg_off, a.p, i);
+            else part = cell_of<D>(v, d, a.scheme, a.m, a.tan2);
+            if (a.part_of_row && a.scheme != SKY_SLICED) a.part_of_row[i] = part;
+            float4* row = reinterpret_cast<float4*>(a.xa + i * RS);
+#pragma unroll
+            for (int c = 0; c < RS / 4; ++c) row[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+            key = ((unsigned long long)fbits(f) << 32) | (uint32_t)i;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+        // count and minimum per partition in LDS; a wave whose rows share one partition (one
+        // relation, or one dataset of a batch) folds them into one update
+        const uint64_t act = __ballot(valid);
+        const int32_t p0 = __builtin_amdgcn_readfirstlane(part);
+        if ((act & 1ull) && __ballot(valid && part != p0) == 0) {
+            unsigned long long mk = key;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(mk, off, kWave);
+                mk = o < mk ? o : mk;
+            }
+            if (lane_id() == 0) {
+                atomicMin(&lmin[p0], mk);
+                atomicAdd(&lcnt[p0], (int32_t)__popcll(act));
+            }
+        } else if (valid) {
+            atomicMin(&lmin[part], key);
+            atomicAdd(&lcnt[part], 1);
+        }
     }
+    __syncthreads();
+    const int32_t slot = (int32_t)(blockIdx.x % (uint32_t)kKill);
+    for (int32_t j = threadIdx.x; j < a.p; j += kBlock) {
+        const int32_t c = lcnt[j];
+        if (c) {
+            atomicAdd(&a.pcount[j], c);
+            atomicMin(&a.kmin[(int64_t)j * kKill + slot], lmin[j]);
+        }
+    }
+    if (__ballot(bad) != 0 && lane_id() == 0) raise_status(a.dev_status, SKY_ERR_DOMAIN);
 }
 
-__global__ void part_offsets_kernel(const int32_t* __restrict__ offs, int64_t ntiles, int32_t p,
-                                    int64_t n, int32_t* __restrict__ part_off) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < p) part_off[j] = offs[(int64_t)j * ntiles];
-    if (j == p) part_off[p] = (int32_t)n;
+// ---- 2. partition offsets (one workgroup of 1024 threads, p <= 4096) --------------------------------
+__global__ void __launch_bounds__(1024) part_offsets_kernel(const int32_t* __restrict__ pcount, int32_t p,
+                                                            int64_t n, int32_t* __restrict__ part_off) {
+    __shared__ int32_t ws[1024 / kWave];
+    const int per = (p + 1023) / 1024;  // at most 4
+    int32_t loc[4];
+    int32_t s = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int32_t j = threadIdx.x * per + e;
+        loc[e] = (e < per && j < p) ? pcount[j] : 0;
+        s += loc[e];
+    }
+    const int lane = (int)lane_id(), wave = threadIdx.x / kWave;
+    int32_t x = s;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t t = __shfl_up(x, off, kWave);
+        if (lane >= off) x += t;
+    }
+    if (lane == kWave - 1) ws[wave] = x;
+    __syncthreads();
+    int32_t run = x - s;
+    for (int w = 0; w < wave; ++w) run += ws[w];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int32_t j = threadIdx.x * per + e;
+        if (e < per && j < p) part_off[j] = run;
+        run += loc[e];
+    }
+    if (threadIdx.x == 0) part_off[p] = (int32_t)n;
 }
 
-// ---- Grid cell pruning (Def. 3) ---------------------------------------------------------------
+// ---- Grid cell pruning (Def. 3) ------------------------------------------------------------------
 // A[c] = "some non-empty cell lies in the closed lower orthant of c" via prefix-OR along every
 // axis; cell h is pruned iff all its coordinates are >= 1 and A[h - (1,...,1)].
 __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restrict__ part_off,
@@ -256,77 +297,187 @@ __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restr
     }
 }
 
-// ---- Hilbert key of every row (canonical values), with validation ----------------------------
-// Used to order the rows of each partition along a space-filling curve, so that consecutive
-// rows are close in space (tight tile boxes for the dominance tests).
-// Curve key of every row, and the row's canonical values copied row-major (stride
-// row_stride<D>(), zero padded): the gathers into curve order then read one contiguous row
-// per item instead of d scattered values.
+// ---- 3. killers and the prefilter ----------------------------------------------------------------
+// One thread per (partition, slot): the slot's row (-1: none, or a pruned partition) and its
+// canonical values.
 template <int D>
-__global__ void __launch_bounds__(kBlock) curve_rows_kernel(const float* __restrict__ x, int64_t n,
-                                                             int32_t d_rt, int64_t ld, int bits,
-                                                             uint32_t* __restrict__ keys,
-                                                             uint32_t* __restrict__ vals,
-                                                             float* __restrict__ xa,
-                                                             int32_t* dev_status) {
+__global__ void __launch_bounds__(kBlock) kill_rows_kernel(const unsigned long long* __restrict__ kmin,
+                                                            const uint8_t* __restrict__ pruned, int32_t p,
+                                                            const float* __restrict__ xa,
+                                                            int32_t* __restrict__ krow, float* __restrict__ kval) {
+    constexpr int RS = row_stride<D>();
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= (int64_t)p * kKill) return;
+    const int32_t j = (int32_t)(e / kKill);
+    const unsigned long long key = kmin[e];
+    const bool ok = key != ~0ull && !(pruned && pruned[j]);
+    const int32_t r = ok ? (int32_t)(uint32_t)key : -1;
+    krow[e] = r;
+    if (ok) {
+        float v[RS];
+        load_row<D>(xa + (int64_t)r * RS, v);
+        float4* dst = reinterpret_cast<float4*>(kval + e * RS);
+#pragma unroll
+        for (int c = 0; c < RS / 4; ++c) dst[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
+    }
+}
+
+struct FilterArgs {
+    int64_t n; int32_t d; int32_t p;
+    const int32_t* part_of_row;       // null: one partition
+    const uint8_t* pruned;            // null: nothing pruned
+    const float* xa;
+    const int32_t* krow; const float* kval;
+    int32_t killers;                  // 0: every row is kept (no tests)
+    uint8_t* alive;                   // [n] out
+    int32_t* blk;                     // [workgroups] out: rows kept per workgroup
+    unsigned long long* seg_tests;    // [p] += the tests of the partition's rows
+    unsigned long long* tests;        // += all tests
+};
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) filter_kernel(FilterArgs a) {
+    constexpr int RS = row_stride<D>();
+    extern __shared__ unsigned long long ltests[];  // [p]
+    __shared__ int32_t ws[kBlock / kWave];
+    const int d = dget<D>(a.d);
+    if (a.killers) {
+        for (int32_t j = threadIdx.x; j < a.p; j += kBlock) ltests[j] = 0ull;
+        __syncthreads();
+    }
+    int32_t kept = 0;
+    const int64_t b0 = (int64_t)blockIdx.x * kPRows;
+    for (int it = 0; it < kPPer; ++it) {
+        const int64_t i = b0 + (int64_t)it * kBlock + threadIdx.x;
+        const bool valid = i < a.n;
+        bool live = valid;
+        int32_t part = -1;
+        uint32_t nt = 0;
+        if (valid) {
+            part = a.part_of_row ? a.part_of_row[i] : 0;
+            if (a.killers) {
+                if (a.pruned && a.pruned[part]) {
+                    live = false;  // Def. 3: the rows of a pruned cell take no part
+                } else {
+                    float t[RS];
+                    load_row<D>(a.xa + i * RS, t);
+                    const int32_t* kr = a.krow + (int64_t)part * kKill;
+                    const float* kv = a.kval + (int64_t)part * kKill * RS;
+#pragma unroll
+                    for (int s = 0; s < kKill; ++s) {
+                        const int32_t r = kr[s];
+                        if (live && r >= 0 && r != (int32_t)i) {
+                            ++nt;
+                            float sv[RS];
+                            load_row<D>(kv + s * RS, sv);
+                            bool le = true, lt = false;
+#pragma unroll
+                            for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
+                                if (k < d) {
+                                    le &= sv[k] <= t[k];
+                                    lt |= sv[k] < t[k];
+                                }
+                            live = !(le && lt);
+                        }
+                    }
+                }
+            }
+            a.alive[i] = live ? 1 : 0;
+        }
+        kept += live ? 1 : 0;
+        if (a.killers) {
+            // tests per partition in LDS, folded per wave when its rows share one partition
+            const uint64_t act = __ballot(valid);
+            const int32_t p0 = __builtin_amdgcn_readfirstlane(part);
+            if ((act & 1ull) && __ballot(valid && part != p0) == 0) {
+                unsigned long long s = nt;
+#pragma unroll
+                for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+                if (lane_id() == 0 && s) atomicAdd(&ltests[p0], s);
+            } else if (valid && nt) {
+                atomicAdd(&ltests[part], (unsigned long long)nt);
+            }
+        }
+    }
+    int32_t total = 0;
+    (void)block_exscan(kept, ws, &total);
+    if (threadIdx.x == 0) a.blk[blockIdx.x] = total;
+    if (a.killers) {
+        __syncthreads();
+        unsigned long long sum = 0;
+        for (int32_t j = threadIdx.x; j < a.p; j += kBlock) {
+            const unsigned long long c = ltests[j];
+            if (c) {
+                atomicAdd(&a.seg_tests[j], c);
+                sum += c;
+            }
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kWave);
+        if (lane_id() == 0 && sum) atomicAdd(a.tests, sum);
+    }
+}
+
+// ---- 4. the kept rows with their sort keys ---------------------------------------------------------
+struct CompactArgs {
+    int64_t n; int32_t d;
+    const uint8_t* alive;
+    const int32_t* blk_off;           // exclusive offsets of the workgroups' kept rows
+    const int32_t* part_of_row;       // null: one partition
+    const float* xa;
+    int32_t cbits;                    // curve bits per attribute
+    int32_t pshift;                   // the partition's place in the key (cbits * d)
+    uint32_t* keys; uint32_t* rows;   // out, at the kept rows' ranks
+    int32_t* n_live;                  // out: rows kept (written by the last workgroup)
+};
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) compact_kernel(CompactArgs a) {
+    constexpr int RS = row_stride<D>();
+    __shared__ int32_t ws[kBlock / kWave];
+    const int d = dget<D>(a.d);
+    // thread t takes 16 consecutive rows, so ranks follow row order
+    const int64_t r0 = (int64_t)blockIdx.x * kPRows + (int64_t)threadIdx.x * kPPer;
+    uint32_t flags = 0;
+    if (r0 + kPPer <= a.n) {
+        const uint4 q = *reinterpret_cast<const uint4*>(a.alive + r0);
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int e = 0; e < kPPer; ++e) flags |= ((w[e >> 2] >> (8 * (e & 3))) & 1u) << e;
+    } else {
+        for (int e = 0; e < kPPer; ++e)
+            if (r0 + e < a.n) flags |= (uint32_t)(a.alive[r0 + e] & 1u) << e;
+    }
+    int32_t total = 0;
+    int32_t o = a.blk_off[blockIdx.x] + block_exscan(__popc(flags), ws, &total);
+    while (flags) {
+        const int e = __ffs(flags) - 1;
+        flags &= flags - 1;
+        const int64_t i = r0 + e;
+        float v[RS];
+        load_row<D>(a.xa + i * RS, v);
+        uint32_t key = hilbert_key(v, d, a.cbits);
+        if (a.part_of_row) key |= (uint32_t)a.part_of_row[i] << a.pshift;
+        a.keys[o] = key;
+        a.rows[o] = (uint32_t)i;
+        ++o;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *a.n_live = a.blk_off[blockIdx.x] + total;
+}
+
+// ---- 6. the partition-contiguous copy of the kept rows in key order --------------------------------
+template <int D>
+__global__ void __launch_bounds__(kBlock) part_gather_kernel(
+    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ rows, const int32_t* __restrict__ n_live,
+    int32_t d_rt, int32_t pshift, int32_t multi, const float* __restrict__ xa, float* __restrict__ xp,
+    int64_t ldp, int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
     constexpr int RS = row_stride<D>();
     const int d = dget<D>(d_rt);
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool bad = false;
-    if (i < n) {
-        float v[RS];
-#pragma unroll
-        for (int k = 0; k < RS; ++k) {
-            float t = k < d ? x[(int64_t)k * ld + i] : 0.0f;
-            bad |= !in_domain(t);
-            v[k] = canon(t);
-        }
-        keys[i] = hilbert_key(v, d, bits);
-        vals[i] = (uint32_t)i;
-        float4* row = reinterpret_cast<float4*>(xa + i * RS);
-#pragma unroll
-        for (int c = 0; c < RS / 4; ++c) row[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
-    }
-    if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
-}
-
-
-// Sliced: the row at rank q of the (value, row) order goes to partition floor(q p / n)
-__global__ void __launch_bounds__(kBlock) slice_parts_kernel(const uint32_t* __restrict__ order,
-                                                              int64_t n, int32_t p,
-                                                              int32_t* __restrict__ part) {
-    int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < n) part[order[q]] = (int32_t)((q * (int64_t)p) / n);
-}
-
-// ---- Sliced: sort keys, gather ----------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) slice_keys_kernel(const float* __restrict__ x, int64_t n,
-                                                             int32_t d, int64_t ld, int32_t dim,
-                                                             uint32_t* __restrict__ keys,
-                                                             uint32_t* __restrict__ vals,
-                                                             int32_t* dev_status) {
-    int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    bool bad = false;
-    if (i < n) {
-        for (int k = 0; k < d; ++k) bad |= !in_domain(x[(int64_t)k * ld + i]);
-        // canonical non-negative FP32 values: the bit pattern orders like the value
-        keys[i] = fbits(canon(x[(int64_t)dim * ld + i]));
-        vals[i] = (uint32_t)i;
-    }
-    if (__ballot(bad) != 0 && lane_id() == 0) raise_status(dev_status, SKY_ERR_DOMAIN);
-}
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) slice_gather_kernel(
-    const float* __restrict__ xa, int64_t n, int32_t d_rt, int32_t p,
-    const uint32_t* __restrict__ order, float* __restrict__ xp, int64_t ldp,
-    int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
-    const int d = dget<D>(d_rt);
-    int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= n) return;
-    int64_t i = order[q];
-    float v[row_stride<D>()];
-    load_row<D>(xa, i, v);
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q >= *n_live) return;
+    const int64_t i = rows[q];
+    float v[RS];
+    load_row<D>(xa + i * RS, v);
     float f = 0.0f;
 #pragma unroll
     for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
@@ -335,52 +486,36 @@ __global__ void __launch_bounds__(kBlock) slice_gather_kernel(
             f = __fadd_rn(f, v[k]);
         }
     rowid[q] = (int32_t)i;
-    seg[q] = (int32_t)((q * (int64_t)p) / n);
+    seg[q] = multi ? (int32_t)(keys[q] >> pshift) : 0;
     fsum[q] = f;
 }
 
-__global__ void slice_offsets_kernel(int64_t n, int32_t p, int32_t* __restrict__ part_off,
-                                     uint8_t* __restrict__ pruned) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    // first rank q with floor(q p / n) >= j is ceil(j n / p)
-    if (j <= p) part_off[j] = (int32_t)(((int64_t)j * n + p - 1) / p);
-    if (j < p) pruned[j] = 0;
+// ---- Sliced: the order of the slicing attribute ----------------------------------------------------
+__global__ void __launch_bounds__(kBlock) slice_keys_kernel(const float* __restrict__ x, int64_t n,
+                                                             int32_t dim, int64_t ld,
+                                                             uint32_t* __restrict__ keys,
+                                                             uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        // canonical non-negative FP32 values: the bit pattern orders like the value (values
+        // outside the domain are reported by the classify pass)
+        keys[i] = fbits(canon(x[(int64_t)dim * ld + i]));
+        vals[i] = (uint32_t)i;
+    }
+}
+
+// the row at rank q of the (value, row) order goes to partition floor(q p / n)
+__global__ void __launch_bounds__(kBlock) slice_parts_kernel(const uint32_t* __restrict__ order,
+                                                              int64_t n, int32_t p,
+                                                              int32_t* __restrict__ part) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < n) part[order[q]] = (int32_t)((q * (int64_t)p) / n);
 }
 
 __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
 }
-
-}  // namespace
-
-// items per histogram tile for p partitions over n rows
-static int part_chunks(int64_t n, int32_t p) {
-    int64_t min_items = ceil_div((int64_t)p * n, kHistCap);
-    int64_t chunks = ceil_div(min_items, kWave);
-    if (chunks < 16) chunks = 16;
-    return (int)chunks;
-}
-
-int64_t partition_hist_elems(int64_t n, int32_t p) {
-    if (n <= 0 || p <= 0) return 64;
-    const int chunks = part_chunks(n, p);
-    const int64_t ntiles = ceil_div(n, (int64_t)chunks * kWave);
-    return round_up((int64_t)p * ntiles, 64);
-}
-
-#define SKY_DISPATCH_D(d, KERNEL, ...)                                            \
-    switch (d) {                                                                  \
-        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                \
-        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                \
-        case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                \
-        case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                \
-        case 5: hipLaunchKernelGGL(KERNEL<5>, __VA_ARGS__); break;                \
-        case 6: hipLaunchKernelGGL(KERNEL<6>, __VA_ARGS__); break;                \
-        case 7: hipLaunchKernelGGL(KERNEL<7>, __VA_ARGS__); break;                \
-        case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                \
-        default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;               \
-    }
 
 // Angular bucket thresholds (Eq. (1)): tan2[k] = tan^2(k pi / (2m)) in FP64, tan2[0] = 0. A
 // row's bucket along an angle is the number of k in [1, m-1] whose threshold its ratio reaches.
@@ -430,6 +565,35 @@ __global__ void __launch_bounds__(kBlock) partition_stats_kernel(const int32_t* 
     }
 }
 
+}  // namespace
+
+#define SKY_DISPATCH_D(d, KERNEL, ...)                                            \
+    switch (d) {                                                                  \
+        case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                \
+        case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                \
+        case 3: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                \
+        case 4: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                \
+        case 5: hipLaunchKernelGGL(KERNEL<5>, __VA_ARGS__); break;                \
+        case 6: hipLaunchKernelGGL(KERNEL<6>, __VA_ARGS__); break;                \
+        case 7: hipLaunchKernelGGL(KERNEL<7>, __VA_ARGS__); break;                \
+        case 8: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                \
+        default: hipLaunchKernelGGL(KERNEL<0>, __VA_ARGS__); break;               \
+    }
+
+int64_t partition_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kPRows); }
+
+// Sort-key layout: the partition above the curve key, in as few 8-bit radix passes as the
+// default curve resolution (curve_bits) needs, at most four; the curve takes what is left.
+void partition_key_layout(int32_t p, int32_t d, int32_t* cbits, int32_t* key_bits) {
+    const int pbits = p > 1 ? bits_for(p) : 0;
+    int passes = (pbits + curve_bits(d) * d + 7) / 8;
+    if (passes > 4) passes = 4;
+    int cb = (8 * passes - pbits) / d;
+    cb = cb > 16 ? 16 : (cb < 1 ? 1 : cb);
+    *cbits = cb;
+    *key_bits = pbits + cb * d;
+}
+
 sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned, int32_t p, int64_t* out,
                                   hipStream_t st) {
     hipLaunchKernelGGL(partition_stats_kernel, dim3(1), dim3(kBlock), 0, st, part_off, pruned, p, out);
@@ -440,69 +604,84 @@ sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const int64_t n = a.n;
     const uint32_t rblocks = (uint32_t)ceil_div(n, kBlock);
-    // 1. partition of every row (Grid / Angular directly, Sliced from the rank order)
+    const uint32_t pblocks = (uint32_t)partition_blocks(n);
+    const bool multi = a.p > 1;
+    int32_t* const part_of_row = multi ? a.part_of_row : nullptr;
+    // 0. counters of this build
+    hipLaunchKernelGGL(partition_init_kernel, dim3((uint32_t)ceil_div((int64_t)a.p * kKill, kBlock)), dim3(kBlock),
+                       0, st, a.p, a.pcount, a.kmin, a.seg_tests, a.tests);
+    SKY_HIP(hipGetLastError());
     if (a.scheme == SKY_ANGULAR) {
         hipLaunchKernelGGL(angular_table_kernel, dim3(1), dim3(256), 0, st, a.m, a.tan2);
         SKY_HIP(hipGetLastError());
-    }
-    if (a.scheme == SKY_GRID || a.scheme == SKY_ANGULAR) {
-        SKY_DISPATCH_D(a.d, part_id_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld,
-                       a.scheme, a.m, a.tan2, a.part_of_row, a.dev_status);
-        SKY_HIP(hipGetLastError());
-    } else if (a.scheme == SKY_SLICED) {
-        hipLaunchKernelGGL(slice_keys_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld,
-                           a.slice_dim, a.k0, a.v0, a.dev_status);
+    } else if (a.scheme == SKY_SLICED && multi) {
+        // the rank of every row in the (value, row) order of the slicing attribute
+        hipLaunchKernelGGL(slice_keys_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.slice_dim, a.ld,
+                           a.k0, a.v0);
         SKY_HIP(hipGetLastError());
         SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, 32, a.radix_tmp, st));
-        hipLaunchKernelGGL(slice_parts_kernel, dim3(rblocks), dim3(kBlock), 0, st,
-                           (const uint32_t*)a.v0, n, a.p, a.part_of_row);
-        SKY_HIP(hipGetLastError());
-    } else if (a.scheme == kSchemeSegments) {
-        hipLaunchKernelGGL(seg_part_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.seg_off, a.p, n,
+        hipLaunchKernelGGL(slice_parts_kernel, dim3(rblocks), dim3(kBlock), 0, st, (const uint32_t*)a.v0, n, a.p,
                            a.part_of_row);
         SKY_HIP(hipGetLastError());
     }
-    // 2. every row in Hilbert order (stable): the order rows take inside their partition
-    const int bits = curve_bits(a.d);
-    SKY_DISPATCH_D(a.d, curve_rows_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.d, a.ld, bits,
-                   a.k0, a.v0, a.xa, a.dev_status);
+    // 1. classify
+    ClassifyArgs ca{};
+    ca.x = a.x; ca.n = n; ca.d = a.d; ca.ld = a.ld;
+    ca.scheme = multi ? a.scheme : SKY_NONE; ca.p = a.p; ca.m = a.m;
+    ca.tan2 = a.tan2; ca.seg_off = a.seg_off;
+    ca.part_of_row = part_of_row; ca.xa = a.xa; ca.pcount = a.pcount; ca.kmin = a.kmin;
+    ca.dev_status = a.dev_status;
+    const size_t clds = (size_t)a.p * (sizeof(unsigned long long) + sizeof(int32_t));
+    SKY_DISPATCH_D(a.d, classify_kernel, dim3(pblocks), dim3(kBlock), clds, st, ca);
     SKY_HIP(hipGetLastError());
+    // 2. partition offsets; Grid pruning
+    hipLaunchKernelGGL(part_offsets_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)a.pcount, a.p, n,
+                       a.part_off);
+    if (a.scheme == SKY_GRID && multi)
+        hipLaunchKernelGGL(grid_prune_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)a.part_off, a.m, a.d,
+                           a.p, a.pruned);
+    else
+        hipLaunchKernelGGL(fill_u8_kernel, dim3((uint32_t)ceil_div(a.p, 256)), dim3(256), 0, st, a.pruned,
+                           (int64_t)a.p, (uint8_t)0);
+    SKY_HIP(hipGetLastError());
+    // 3. killers and the prefilter (or every row kept)
+    if (a.prefilter) {
+        SKY_DISPATCH_D(a.d, kill_rows_kernel, dim3((uint32_t)ceil_div((int64_t)a.p * kKill, kBlock)), dim3(kBlock),
+                       0, st, (const unsigned long long*)a.kmin, (const uint8_t*)(a.scheme == SKY_GRID ? a.pruned : nullptr),
+                       a.p, (const float*)a.xa, a.krow, a.kval);
+        SKY_HIP(hipGetLastError());
+    }
+    FilterArgs fa{};
+    fa.n = n; fa.d = a.d; fa.p = a.p;
+    fa.part_of_row = part_of_row;
+    fa.pruned = a.scheme == SKY_GRID && multi ? a.pruned : nullptr;
+    fa.xa = a.xa; fa.krow = a.krow; fa.kval = a.kval;
+    fa.killers = a.prefilter ? 1 : 0;
+    fa.alive = a.alive; fa.blk = a.blk;
+    fa.seg_tests = a.seg_tests; fa.tests = a.tests;
+    const size_t flds = a.prefilter ? (size_t)a.p * sizeof(unsigned long long) : 0;
+    SKY_DISPATCH_D(a.d, filter_kernel, dim3(pblocks), dim3(kBlock), flds, st, fa);
+    SKY_HIP(hipGetLastError());
+    // 4. the kept rows with their keys
+    SKY_TRY(launch_exclusive_scan(a.blk, a.blk, pblocks, a.scan_tmp, st));
+    int32_t cbits = 1, key_bits = 1;
+    partition_key_layout(a.p, a.d, &cbits, &key_bits);
+    CompactArgs ka{};
+    ka.n = n; ka.d = a.d; ka.alive = a.alive; ka.blk_off = a.blk;
+    ka.part_of_row = part_of_row; ka.xa = a.xa;
+    ka.cbits = cbits; ka.pshift = cbits * a.d;
+    ka.keys = a.k0; ka.rows = a.v0; ka.n_live = a.n_live;
+    SKY_DISPATCH_D(a.d, compact_kernel, dim3(pblocks), dim3(kBlock), 0, st, ka);
+    SKY_HIP(hipGetLastError());
+    // 5. stable sort of the kept rows by (partition, curve key)
     const uint32_t* sorted_keys = nullptr;
     const uint32_t* order = nullptr;
-    SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, bits * a.d, a.radix_tmp, st, &sorted_keys, &order));
-    if (a.p == 1) {
-        SKY_DISPATCH_D(a.d, slice_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st,
-                       (const float*)a.xa, n, a.d, 1, order, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
-        SKY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(slice_offsets_kernel, dim3(1), dim3(64), 0, st, n, 1, a.part_off, a.pruned);
-        SKY_HIP(hipGetLastError());
-        return SKY_OK;
-    }
-    // 3. stable counting sort by partition over the curve order
-    const int chunks = part_chunks(n, a.p);
-    const int64_t ntiles = ceil_div(n, (int64_t)chunks * kWave);
-    if ((int64_t)a.p * ntiles > a.hist_cap) return SKY_ERR_WORKSPACE;  // never with the API's sizes
-    const uint32_t tblocks = (uint32_t)ceil_div(ntiles, kWavesPerBlock);
-    const size_t lds = sizeof(int32_t) * (size_t)kWavesPerBlock * (size_t)a.p;
-    hipLaunchKernelGGL(part_hist_kernel, dim3(tblocks), dim3(kBlock), lds, st,
-                       (const int32_t*)a.part_of_row, order, n, a.p, chunks, a.hist, ntiles);
-    SKY_HIP(hipGetLastError());
-    SKY_TRY(launch_exclusive_scan(a.hist, a.hist, (int64_t)a.p * ntiles, a.scan_tmp, st));
-    const int pbits = bits_for(a.p);
-    SKY_DISPATCH_D(a.d, part_scatter_kernel, dim3(tblocks), dim3(kBlock), lds, st,
-                   (const float*)a.xa, n, a.d, (const int32_t*)a.part_of_row, order, a.p, pbits, chunks,
-                   (const int32_t*)a.hist, ntiles, a.xp, a.ldp, a.rowid, a.seg, a.fsum);
-    SKY_HIP(hipGetLastError());
-    hipLaunchKernelGGL(part_offsets_kernel, dim3((uint32_t)ceil_div(a.p + 1, 256)), dim3(256), 0,
-                       st, (const int32_t*)a.hist, ntiles, a.p, n, a.part_off);
-    SKY_HIP(hipGetLastError());
-    if (a.scheme == SKY_GRID) {
-        hipLaunchKernelGGL(grid_prune_kernel, dim3(1), dim3(1024), 0, st,
-                           (const int32_t*)a.part_off, a.m, a.d, a.p, a.pruned);
-    } else {
-        hipLaunchKernelGGL(fill_u8_kernel, dim3((uint32_t)ceil_div(a.p, 256)), dim3(256), 0, st,
-                           a.pruned, (int64_t)a.p, (uint8_t)0);
-    }
+    SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, key_bits, a.radix_tmp, st, &sorted_keys, &order,
+                              a.n_live));
+    // 6. the partition-contiguous copy
+    SKY_DISPATCH_D(a.d, part_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st, sorted_keys, order,
+                   (const int32_t*)a.n_live, a.d, cbits * a.d, multi ? 1 : 0, (const float*)a.xa, a.xp, a.ldp,
+                   a.rowid, a.seg, a.fsum);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

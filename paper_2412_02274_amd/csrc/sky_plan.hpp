@@ -20,8 +20,13 @@ struct sky_plan {
     uint8_t* pruned = nullptr;
     double* tan2_dev = nullptr;
     int64_t* seg_off_dev = nullptr;  // kSchemeSegments: dataset row offsets [p+1]
-    int32_t *part_of_row = nullptr, *phist = nullptr, *scan_tmp = nullptr;
-    int64_t phist_cap = 0;
+    int32_t *part_of_row = nullptr, *scan_tmp = nullptr;
+    // the build's prefilter (killer rows per partition) and the kept rows
+    bool prefilter = false;
+    int32_t *pcount = nullptr, *krow = nullptr, *blk = nullptr;
+    unsigned long long* kmin = nullptr;
+    float* kval = nullptr;
+    uint8_t* alive = nullptr;
     uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr;
     float* xa = nullptr;  // row-major staging copy for the gathers into curve order
     int32_t reps = 0;     // Representative Filtering: representatives wanted (0 = off)
@@ -48,10 +53,11 @@ namespace sky {
 // device-side counters of a plan (int64 words of sky_plan::dinfo)
 enum {
     D_PRUNED_CELLS = 0, D_PRUNED_ROWS, D_MAX_PART, D_ROUNDS_LOCAL, D_ROUNDS_MERGE, D_LOCAL_COUNT,
-    D_SKY_COUNT, D_TESTS_LOCAL, D_TESTS_MERGE, D_TESTS_LOCAL_MAX, kDinfo = 16
+    D_SKY_COUNT, D_TESTS_LOCAL, D_TESTS_MERGE, D_TESTS_LOCAL_MAX, D_TESTS_FILTER, kDinfo = 16
 };
-// count_tmp words: the first round's list length, the union's, the skyline's
-enum { CT_LIST = 0, CT_UNION = 1, CT_SKY = 2 };
+// count_tmp words: the first round's list length, the union's, the skyline's, the positions
+// of the partition-contiguous copy (rows the build kept)
+enum { CT_LIST = 0, CT_UNION = 1, CT_SKY = 2, CT_ROWS = 3 };
 
 constexpr int32_t kMaxRows = 0x7FFFFFFF;
 constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset within 32 bits
@@ -60,9 +66,12 @@ constexpr int32_t kMaxBuildRows = 0x3FF00000;  // keeps every engine byte offset
 size_t plan_bytes(int64_t n, int32_t d, int32_t scheme, int32_t p, int32_t m);
 // Carve a plan from ws and (launch) queue its partition step. scheme may be kSchemeSegments,
 // with seg_off_host = the p + 1 dataset row offsets (copied to the device before returning).
+// reps: Representative Filtering's row count (0 = off); prefilter: drop the rows the killer
+// rows of their partition dominate (only without representatives).
 sky_status plan_build(const float* x, int64_t n, int32_t d, int64_t ld, int32_t scheme, int32_t p,
-                      int32_t m, int32_t slice_dim, const int64_t* seg_off_host, void* ws,
-                      size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out, bool launch);
+                      int32_t m, int32_t slice_dim, const int64_t* seg_off_host, int32_t reps, bool prefilter,
+                      void* ws, size_t ws_bytes, int32_t* dev_status, hipStream_t st, sky_plan** out,
+                      bool launch);
 // Queue the partition step of a plan (re-reads its relation).
 sky_status plan_partition(sky_plan* P, hipStream_t st);
 // Sec. 3 phase 1 (the local skylines) and phase 2 (the union's skyline, its positions list

@@ -1088,6 +1088,7 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
 // items, as int64 words for the caller (each output may be null).
 __global__ void __launch_bounds__(kBlock) engine_finish_kernel(const unsigned long long* __restrict__ tests,
                                                                 const unsigned long long* __restrict__ seg_tests,
+                                                                const unsigned long long* __restrict__ extra,
                                                                 int32_t nseg, const int32_t* __restrict__ gcounters,
                                                                 int64_t* __restrict__ out_rounds,
                                                                 int64_t* __restrict__ out_tests,
@@ -1104,27 +1105,27 @@ __global__ void __launch_bounds__(kBlock) engine_finish_kernel(const unsigned lo
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kBlock / kWave; ++w) m = part[w] > m ? part[w] : m;
-        const unsigned long long total = tests[0] + tests[1];
+        const unsigned long long total = tests[0] + tests[1] + (extra ? *extra : 0ull);
         if (out_rounds) *out_rounds = gcounters[G_ROUNDS];
         if (out_tests) *out_tests = (int64_t)total;
         if (out_max) *out_max = (int64_t)(seg_tests ? m : total);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) scatter_rows_i32_kernel(const int32_t* __restrict__ src,
-                                                                   const int32_t* __restrict__ rowid,
-                                                                   int64_t n, int32_t* __restrict__ dst) {
-    int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < n) dst[rowid[q]] = src[q];
-}
-
-// dst[rowid[q]] = src[q], or 0 where drop[q] != 0 (drop may be null)
 __global__ void __launch_bounds__(kBlock) scatter_rows_u8_kernel(const uint8_t* __restrict__ src,
                                                                   const uint8_t* __restrict__ drop,
                                                                   const int32_t* __restrict__ rowid,
-                                                                  int64_t n, uint8_t* __restrict__ dst) {
+                                                                  int64_t n, const int32_t* __restrict__ count,
+                                                                  uint8_t* __restrict__ dst) {
     int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < n) dst[rowid[q]] = (drop && drop[q]) ? 0 : src[q];
+    const int64_t m = count ? (*count < n ? (int64_t)*count : n) : n;
+    if (q < m) dst[rowid[q]] = (drop && drop[q]) ? 0 : src[q];
+}
+__global__ void __launch_bounds__(kBlock) iota_count_kernel(const int32_t* __restrict__ count, int32_t n,
+                                                             int32_t* __restrict__ out) {
+    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const int32_t m = *count < n ? *count : n;
+    if (i < m) out[i] = i;
 }
 
 __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
@@ -1405,7 +1406,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
         }
     }
     hipLaunchKernelGGL(engine_finish_kernel, dim3(1), dim3(kBlock), 0, st, (const unsigned long long*)b.tests,
-                       (const unsigned long long*)pb.seg_tests, nseg, (const int32_t*)gctr, pb.out_rounds,
+                       (const unsigned long long*)pb.seg_tests, pb.extra_tests, nseg, (const int32_t*)gctr, pb.out_rounds,
                        pb.out_tests, pb.out_tests_max);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
@@ -1451,25 +1452,18 @@ sky_status launch_compact_flags(uint8_t* flags, const uint8_t* drop, bool bake, 
                          nullptr, scan_tmp, st);
 }
 
-sky_status launch_scatter_rows(const int32_t* src_i32, const uint8_t* src_u8, const int32_t* rowid,
-                               int64_t n, int32_t* dst_i32, uint8_t* dst_u8, hipStream_t st) {
+sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,
+                                    const int32_t* count, uint8_t* dst, hipStream_t st) {
     if (n <= 0) return SKY_OK;
-    const uint32_t nb = (uint32_t)ceil_div(n, kBlock);
-    if (dst_i32)
-        hipLaunchKernelGGL(scatter_rows_i32_kernel, dim3(nb), dim3(kBlock), 0, st, src_i32, rowid, n,
-                           dst_i32);
-    if (dst_u8)
-        hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3(nb), dim3(kBlock), 0, st, src_u8,
-                           (const uint8_t*)nullptr, rowid, n, dst_u8);
+    hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0, st, src,
+                       drop, rowid, n, count, dst);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
 
-sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,
-                                    uint8_t* dst, hipStream_t st) {
+sky_status launch_iota_count(const int32_t* count, int32_t n, int32_t* out, hipStream_t st) {
     if (n <= 0) return SKY_OK;
-    hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0, st, src,
-                       drop, rowid, n, dst);
+    hipLaunchKernelGGL(iota_count_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0, st, count, n, out);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
-from paper_2412_02274_amd import api, datagen as G  # noqa: E402
+from paper_2412_02274_amd import _lib, api, datagen as G  # noqa: E402
 
 
 def _say(*a):
@@ -42,9 +42,9 @@ def _rows(kind, n, d, seed):
     return G.make(kind, n, d, seed)
 
 
-def run_skyline(dev, x, scheme="none", p=16, slice_dim=0):
+def run_skyline(dev, x, scheme="none", p=16, slice_dim=0, prefilter=True):
     xs = api.ingest(torch.from_numpy(x).to(dev))
-    plan = api.build(xs, scheme, p, slice_dim)
+    plan = api.build(xs, scheme, p, slice_dim, prefilter=prefilter)
     plan.local_skylines()
     part = plan.partitions().cpu().numpy()
     loc = plan.local_members().cpu().numpy().astype(bool)
@@ -78,8 +78,10 @@ def check_partition_tests(info, part, pp, skip, reps_kept=0):
     """The local phase's per-partition test counts (Sec. 4 counts the parallel phase by their
     maximum): they add up to tests_local, their maximum is tests_local_max, a partition without
     live rows has none, one with two or more has some, and no partition exceeds one test per
-    (row, row of the partition) pair plus one per (row, kept representative) pair. Counts
-    depend on the order of the work, so they are checked by these properties only."""
+    (row, row of the partition) pair plus one per (row, kept representative) pair plus one per
+    (row, killer row) pair of the build's prefilter (at most SKY_KILLERS per row; a pair can
+    be tested there and again by the local phase). Counts depend on the order of the work, so
+    they are checked by these properties only."""
     pt = np.asarray(info["partition_tests"], np.int64)
     assert len(pt) == pp
     assert int(pt.sum()) == info["tests_local"]
@@ -90,7 +92,8 @@ def check_partition_tests(info, part, pp, skip, reps_kept=0):
     assert (pt[live == 0] == 0).all()
     if reps_kept == 0:
         assert (pt[live >= 2] > 0).all()
-    assert (pt <= live * live + live * reps_kept).all(), np.flatnonzero(pt > live * live + live * reps_kept)
+    bound = live * live + live * (reps_kept + _lib.SKY_KILLERS)
+    assert (pt <= bound).all(), np.flatnonzero(pt > bound)
 
 
 def angular_ids_agree(part, opart, near, pp, d):
@@ -147,6 +150,17 @@ def test_ingest_domain_error(dev, bad):
 # ------------------------------------------------------------------------------------- skyline
 
 @pytest.mark.parametrize("kind", ["uni", "ant", "ties", "dyadic"])
+@pytest.mark.parametrize("d", [1, 3, 8])
+def test_skyline_none_no_prefilter(dev, kind, d):
+    x = _rows(kind, 3001, d, 11 * d)
+    want = np.flatnonzero(oracle.skyline(x))
+    _, idx, part, loc, info = run_skyline(dev, x, "none", prefilter=False)
+    assert (idx == want).all() and len(idx) == len(want)
+    assert info["rows_kept"] == len(x)
+    check_partition_tests(info, part, 1, None)
+
+
+@pytest.mark.parametrize("kind", ["uni", "ant", "ties", "dyadic"])
 @pytest.mark.parametrize("d", [1, 2, 3, 5, 8])
 @pytest.mark.parametrize("n", [1, 2, 37, 3001])
 def test_skyline_none(dev, kind, d, n):
@@ -164,14 +178,27 @@ def test_skyline_none(dev, kind, d, n):
                                       ("angular", 64), ("sliced", 16), ("sliced", 64)])
 @pytest.mark.parametrize("kind", ["uni", "ant", "ties"])
 @pytest.mark.parametrize("d", [2, 3, 4, 6])
-def test_skyline_partitioned(dev, scheme, p, kind, d):
-    _say("skyline", scheme, p, kind, d)
+@pytest.mark.parametrize("prefilter", [True, False])
+def test_skyline_partitioned(dev, scheme, p, kind, d, prefilter):
+    _say("skyline", scheme, p, kind, d, prefilter)
     n = 5003
     x = _rows(kind, n, d, 7 * d + p)
     want = np.flatnonzero(oracle.skyline(x))
-    _, idx, part, loc, info = run_skyline(dev, x, scheme, p, slice_dim=d - 1)
+    _, idx, part, loc, info = run_skyline(dev, x, scheme, p, slice_dim=d - 1, prefilter=prefilter)
     assert (idx == want).all() and len(idx) == len(want)
     check_partitioned(x, scheme, p, part, loc, info, slice_dim=d - 1)
+    check_rows_kept(x, scheme, p, loc, info, prefilter, slice_dim=d - 1)
+
+
+def check_rows_kept(x, scheme, p, loc, info, prefilter, slice_dim=0):
+    """Without the prefilter every row goes through the local phase. With it, the kept rows
+    are those of unpruned partitions that no killer row dominates: never fewer than the
+    local skylines' rows (a killer never dominates a row of its partition's skyline)."""
+    n = len(x)
+    if not prefilter:
+        assert info["rows_kept"] == n
+        return
+    assert int(loc.sum()) <= info["rows_kept"] <= n
 
 
 def test_skyline_duplicates_and_small_p(dev):
@@ -361,6 +388,9 @@ def test_config_uni_10m_d4_partitioned(dev, scheme):
     xs, idx, part, loc, info = run_skyline(dev, x, scheme, 64, slice_dim=0)
     assert len(idx) == len(want_sky) and (idx == want_sky).all()
     check_partitioned(x, scheme, 64, part, loc, info, slice_dim=0)
+    check_rows_kept(x, scheme, 64, loc, info, True, slice_dim=0)
+    _say("10m", scheme, "rows kept", info["rows_kept"])
+    assert info["rows_kept"] < len(x) // 5  # uniform data: the killer rows take most rows
     ge, _ = api.gres(xs, torch.from_numpy(idx).to(dev), 25)
     want_ge, _ = oracle.gres(x, want_sky, 25)
     assert (ge.cpu().numpy() == want_ge).all()
@@ -419,9 +449,10 @@ def test_plan_gres_all_equal_and_full_size(dev):
 def test_multi_round_segments(dev, kind, n, d, p):
     """Sliced partitions of more than 65,536 rows each: every segment runs several
     head-and-filter rounds (the all-pairs shortcut only ends them), side by side in the same
-    launches. Local skylines and the final skyline against the oracle."""
+    launches. Local skylines and the final skyline against the oracle. The build's prefilter
+    is off, so that every row reaches the rounds (on uniform data it leaves too few)."""
     x = _rows(kind, n, d, 33)
-    xs, idx, part, loc, info = run_skyline(dev, x, "sliced", p)
+    xs, idx, part, loc, info = run_skyline(dev, x, "sliced", p, prefilter=False)
     _say(f"multi-round {kind} {n}x{d} p={p}: rounds {info['rounds_local']}+{info['rounds_merge']}")
     if kind != "ties":  # tied scores can put a whole segment into the first head
         assert info["rounds_local"] >= 2
