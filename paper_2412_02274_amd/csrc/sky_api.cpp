@@ -162,6 +162,7 @@ sky_status plan_partition(sky_plan* P, hipStream_t st) {
     a.xa = P->xa;
     a.seg_tests = P->seg_tests;
     a.tests = reinterpret_cast<unsigned long long*>(P->dinfo + D_TESTS_FILTER);
+    a.smin = P->eng.seg_min; a.smax = P->eng.seg_max;
     a.dev_status = P->dev_status;
     return launch_partition(a, st);
 }
@@ -337,6 +338,7 @@ sky_status plan_local_phase(sky_plan* P, hipStream_t st) {
     // the prefilter's tests are already in seg_tests (the build zeroed them); representatives
     // add theirs above
     pb.zero_seg_tests = P->reps == 0 && !P->prefilter;
+    pb.ranges_ready = P->p > 1;  // the build's copy folded every partition's score range
     pb.extra_tests = reinterpret_cast<const unsigned long long*>(P->dinfo + D_TESTS_FILTER);
     pb.items = P->eng.w1;
     pb.n_items = n;
@@ -361,7 +363,7 @@ sky_status plan_final_phase(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t*
         // the union of the local skylines, in position order (spatially coherent); local_flag
         // becomes exactly the local skylines
         SKY_TRY(launch_compact_flags(P->local_flag, P->eng.dom, true, n, P->eng.w1, P->count_tmp + CT_UNION,
-                                     P->dinfo + D_LOCAL_COUNT, P->eng.scan_tmp, st));
+                                     P->dinfo + D_LOCAL_COUNT, P->eng.scan_tmp, st, P->count_tmp + CT_ROWS));
         EngineProblem pb{};
         pb.xp = P->xp; pb.ldp = P->ldp; pb.d = P->d; pb.n_pos = n; pb.fsum = P->fsum;
         pb.seg_of_pos = nullptr;
@@ -381,7 +383,7 @@ sky_status plan_final_phase(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t*
     // the skyline's positions in curve order (the gres store of sky_gres reads them), with F
     // rewritten to the skyline itself
     SKY_TRY(launch_compact_flags(F, P->eng.dom, true, n, P->final_list, P->count_tmp + CT_SKY,
-                                 P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st));
+                                 P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st, P->count_tmp + CT_ROWS));
     return launch_final_output(P->final_list, P->count_tmp + CT_SKY, P->rowid, P->n, P->member_tmp, member,
                                sky_idx, cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st);
 }

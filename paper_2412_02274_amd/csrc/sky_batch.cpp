@@ -128,7 +128,8 @@ sky_status sky_batch_skylines(sky_batch* B, int64_t* sky_idx, int64_t cap, int64
     // their positions (relation-major, curve order inside each relation), local_flag rewritten
     // to exactly the skylines, and the total
     SKY_TRY(launch_compact_flags(P->local_flag, P->eng.dom, true, (int32_t)P->n, P->final_list,
-                                 P->count_tmp + CT_SKY, P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st));
+                                 P->count_tmp + CT_SKY, P->dinfo + D_SKY_COUNT, P->eng.scan_tmp, st,
+                                 P->count_tmp + CT_ROWS));
     // 3. ascending rows (SKY_ERR_CAPACITY on the device above cap) and the per-relation offsets
     SKY_TRY(launch_final_output(P->final_list, P->count_tmp + CT_SKY, P->rowid, P->n, P->member_tmp, nullptr,
                                 sky_idx, cap, B->dev_count, P->pos_tmp, P->scan_tmp, B->dev_status, st));

@@ -53,9 +53,10 @@ __device__ __forceinline__ uint64_t match_any(uint32_t key, int bits, uint64_t a
     return m;
 }
 
-// Exclusive prefix over a workgroup of kBlock threads of one int32 per thread; *total = the
-// sum. ws: kBlock / kWave int32 of LDS. Every thread of the workgroup must call it.
-__device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* ws, int32_t* total) {
+// Exclusive prefix over a workgroup of NT threads of one int32 per thread; *total = the sum.
+// ws: NT / kWave int32 of LDS. Every thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ int32_t block_exscan_t(int32_t v, int32_t* ws, int32_t* total) {
     const int lane = (int)lane_id(), wave = threadIdx.x / kWave;
     int32_t x = v;
 #pragma unroll
@@ -67,7 +68,7 @@ __device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* ws, int32_t*
     __syncthreads();
     int32_t pre = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) {
+    for (int w = 0; w < NT / kWave; ++w) {
         const int32_t s = ws[w];
         pre += w < wave ? s : 0;
         tot += s;
@@ -75,6 +76,9 @@ __device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* ws, int32_t*
     __syncthreads();  // ws may be reused at once
     *total = tot;
     return pre + x - v;
+}
+__device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* ws, int32_t* total) {
+    return block_exscan_t<kBlock>(v, ws, total);
 }
 
 // Hilbert-curve key of a point of canonical values in [0, 1): `bits` bits per attribute,
@@ -222,6 +226,8 @@ struct PartitionArgs {
     float* xa;                 // [n][partition_row_stride(d)] row-major canonical staging copy
     unsigned long long* seg_tests;  // [p] out: the prefilter's tests per partition
     unsigned long long* tests;      // out: the prefilter's tests in all
+    uint32_t* smin; uint32_t* smax; // [p] out: per partition, the smallest and largest score
+                                    // (bit pattern) of its positions
     int32_t* dev_status;
 };
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
@@ -304,6 +310,8 @@ struct EngineProblem {
     int32_t nseg;
     unsigned long long* seg_tests; // optional [nseg]: tests added per segment
     bool zero_seg_tests;           // the run zeroes seg_tests first (else the caller has)
+    bool ranges_ready;             // the caller has set b.seg_min / b.seg_max: for every segment, a
+                                   // range of score bit patterns holding every item's score
     const int32_t* items;          // initial work list (positions); not one of the engine's buffers
     int32_t n_items;               // its length, when n_items_dev is null
     const int32_t* n_items_dev;    // its length on the device (or null)
@@ -336,9 +344,11 @@ sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, con
                                     const int32_t* count, uint8_t* dst, hipStream_t st);
 // positions i < n with flags[i] != 0 and (drop null or drop[i] == 0), in order, into out; their
 // number into *count32 and *count64 (either may be null); with bake, flags[i] is rewritten to
-// the selection
+// the selection. With bound (a device word), only positions i < min(n, *bound) are read and
+// rewritten (the caller guarantees that no later position is selected).
 sky_status launch_compact_flags(uint8_t* flags, const uint8_t* drop, bool bake, int32_t n, int32_t* out,
-                                int32_t* count32, int64_t* count64, int32_t* scan_tmp, hipStream_t st);
+                                int32_t* count32, int64_t* count64, int32_t* scan_tmp, hipStream_t st,
+                                const int32_t* bound = nullptr);
 // ascending rows of the positions list[0, *count) (count on the device, at most n):
 // sky_idx[0, min(count, cap)), *dev_count = count (SKY_ERR_CAPACITY above cap), member_out[row]
 // (optional), and pos_tmp[row] = the row's index in sky_idx for every skyline row

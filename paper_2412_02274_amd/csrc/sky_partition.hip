@@ -16,9 +16,9 @@
 // The steps, for every scheme:
 //  1. classify (one pass over the relation): validate the domain (SKY_ERR_DOMAIN), take the
 //     canonical values, the partition and the FP32 attribute sum (the monotone score of the
-//     skyline filter, Sec. 2), write a row-major staging copy, count the rows of every
-//     partition, and keep, per partition, the row of smallest score of each workgroup's 4096
-//     rows, folded into SKY_KILLERS slots (slot = workgroup mod SKY_KILLERS, minimum per slot).
+//     skyline filter, Sec. 2), count the rows of every partition, and keep, per partition, the
+//     row of smallest score of each workgroup's 4096 consecutive rows, folded into
+//     SKY_KILLERS slots (slot = workgroup mod SKY_KILLERS, minimum per slot).
 //  2. partition offsets, then Grid pruning (Def. 3) from the partition sizes.
 //  3. prefilter: every row of an unpruned partition is tested against that partition's slot
 //     rows (the "killers"; a row is not tested against itself). A row one of them dominates
@@ -27,7 +27,8 @@
 //     row of their partition (10M x 4 in 81 cells: about 3% of the rows remain); on
 //     anticorrelated data the prefilter keeps most rows and costs one streaming pass. With
 //     Representative Filtering, or when the caller turns it off, every row is kept (the
-//     representatives are drawn from all rows, pruned cells included).
+//     representatives are drawn from all rows, pruned cells included). The kept rows'
+//     canonical values go to a row-major staging copy (at their row index).
 //  4. the kept rows, in row order, with sort keys (partition, Hilbert key of the values);
 //  5. a stable radix sort of those keys over the kept rows only (their count stays on the
 //     device);
@@ -57,8 +58,13 @@ __device__ __forceinline__ void load_row(const float* __restrict__ p, float* v) 
     }
 }
 
-constexpr int kPRows = 4096;              // rows per workgroup of the classify/filter/compact passes
-constexpr int kPPer = kPRows / kBlock;    // 16 rows per thread
+// The classify/filter/compact passes: workgroups of 1024 threads, 4 rows per thread. Wide
+// workgroups keep many waves per CU on a 1M-row relation while the per-workgroup flushes of
+// partition counters into global memory stay at one per 4096 rows (with one partition they all
+// meet on the same few addresses).
+constexpr int kPT = 1024;
+constexpr int kPPer = 4;
+constexpr int kPRows = kPT * kPPer;
 constexpr int kKill = SKY_KILLERS;
 
 int bits_for(int32_t p) {
@@ -128,11 +134,15 @@ __device__ __forceinline__ int32_t dataset_of(const int64_t* __restrict__ seg_of
 __global__ void __launch_bounds__(kBlock) partition_init_kernel(int32_t p, int32_t* __restrict__ pcount,
                                                                 unsigned long long* __restrict__ kmin,
                                                                 unsigned long long* __restrict__ seg_tests,
-                                                                unsigned long long* __restrict__ tests) {
+                                                                unsigned long long* __restrict__ tests,
+                                                                uint32_t* __restrict__ smin,
+                                                                uint32_t* __restrict__ smax) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g < p) {
         pcount[g] = 0;
         seg_tests[g] = 0ull;
+        smin[g] = 0xFFFFFFFFu;
+        smax[g] = 0u;
     }
     if (g < (int64_t)p * kKill) kmin[g] = ~0ull;
     if (g == 0) *tests = 0ull;
@@ -145,19 +155,18 @@ struct ClassifyArgs {
     const double* tan2;             // Angular thresholds
     const int64_t* seg_off;         // batched datasets
     int32_t* part_of_row;           // written (Grid/Angular/datasets), read (Sliced), null (None)
-    float* xa;                      // [n][row stride] staging copy
     int32_t* pcount;                // [p] rows per partition (+=)
     unsigned long long* kmin;       // [p][kKill] minima of (score bits << 32 | row)
     int32_t* dev_status;
 };
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) classify_kernel(ClassifyArgs a) {
-    constexpr int RS = row_stride<D>();
+__global__ void __launch_bounds__(kPT) classify_kernel(ClassifyArgs a) {
+    constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ unsigned long long lmin[];  // [p], then int32 counts [p]
     int32_t* lcnt = reinterpret_cast<int32_t*>(lmin + a.p);
     const int d = dget<D>(a.d);
-    for (int32_t j = threadIdx.x; j < a.p; j += kBlock) {
+    for (int32_t j = threadIdx.x; j < a.p; j += kPT) {
         lmin[j] = ~0ull;
         lcnt[j] = 0;
     }
@@ -165,30 +174,26 @@ __global__ void __launch_bounds__(kBlock) classify_kernel(ClassifyArgs a) {
     bool bad = false;
     const int64_t b0 = (int64_t)blockIdx.x * kPRows;
     for (int it = 0; it < kPPer; ++it) {
-        const int64_t i = b0 + (int64_t)it * kBlock + threadIdx.x;
+        const int64_t i = b0 + (int64_t)it * kPT + threadIdx.x;
         const bool valid = i < a.n;
         int32_t part = -1;
         unsigned long long key = ~0ull;
         if (valid) {
-            float v[RS];
+            float v[DM];
             float f = 0.0f;
 #pragma unroll
-            for (int k = 0; k < RS; ++k) {
-                const float t = k < d ? a.x[(int64_t)k * a.ld + i] : 0.0f;
-                bad |= !in_domain(t);
-                v[k] = canon(t);
-            }
-#pragma unroll
-            for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
-                if (k < d) f = __fadd_rn(f, v[k]);
+            for (int k = 0; k < DM; ++k)
+                if (k < d) {
+                    const float t = a.x[(int64_t)k * a.ld + i];
+                    bad |= !in_domain(t);
+                    v[k] = canon(t);
+                    f = __fadd_rn(f, v[k]);
+                }
             if (a.scheme == SKY_NONE) part = 0;
             else if (a.scheme == SKY_SLICED) part = a.part_of_row[i];
             else if (a.scheme == kSchemeSegments) part = dataset_of(a.seg_off, a.p, i);
             else part = cell_of<D>(v, d, a.scheme, a.m, a.tan2);
             if (a.part_of_row && a.scheme != SKY_SLICED) a.part_of_row[i] = part;
-            float4* row = reinterpret_cast<float4*>(a.xa + i * RS);
-#pragma unroll
-            for (int c = 0; c < RS / 4; ++c) row[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
             key = ((unsigned long long)fbits(f) << 32) | (uint32_t)i;
         }
         // count and minimum per partition in LDS; a wave whose rows share one partition (one
@@ -213,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) classify_kernel(ClassifyArgs a) {
     }
     __syncthreads();
     const int32_t slot = (int32_t)(blockIdx.x % (uint32_t)kKill);
-    for (int32_t j = threadIdx.x; j < a.p; j += kBlock) {
+    for (int32_t j = threadIdx.x; j < a.p; j += kPT) {
         const int32_t c = lcnt[j];
         if (c) {
             atomicAdd(&a.pcount[j], c);
@@ -303,9 +308,10 @@ __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restr
 template <int D>
 __global__ void __launch_bounds__(kBlock) kill_rows_kernel(const unsigned long long* __restrict__ kmin,
                                                             const uint8_t* __restrict__ pruned, int32_t p,
-                                                            const float* __restrict__ xa,
+                                                            const float* __restrict__ x, int32_t d_rt, int64_t ld,
                                                             int32_t* __restrict__ krow, float* __restrict__ kval) {
     constexpr int RS = row_stride<D>();
+    const int d = dget<D>(d_rt);
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= (int64_t)p * kKill) return;
     const int32_t j = (int32_t)(e / kKill);
@@ -313,99 +319,125 @@ __global__ void __launch_bounds__(kBlock) kill_rows_kernel(const unsigned long l
     const bool ok = key != ~0ull && !(pruned && pruned[j]);
     const int32_t r = ok ? (int32_t)(uint32_t)key : -1;
     krow[e] = r;
-    if (ok) {
-        float v[RS];
-        load_row<D>(xa + (int64_t)r * RS, v);
-        float4* dst = reinterpret_cast<float4*>(kval + e * RS);
+    float v[RS];
 #pragma unroll
-        for (int c = 0; c < RS / 4; ++c) dst[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
-    }
+    for (int k = 0; k < RS; ++k) v[k] = (ok && k < d) ? canon(x[(int64_t)k * ld + r]) : 2.0f;
+    float4* dst = reinterpret_cast<float4*>(kval + e * RS);
+#pragma unroll
+    for (int c = 0; c < RS / 4; ++c) dst[c] = make_float4(v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]);
 }
 
 struct FilterArgs {
-    int64_t n; int32_t d; int32_t p;
+    int64_t n; int32_t d; int64_t ld; int32_t p;
+    const float* x;                   // the relation (SoA)
     const int32_t* part_of_row;       // null: one partition
     const uint8_t* pruned;            // null: nothing pruned
-    const float* xa;
     const int32_t* krow; const float* kval;
     int32_t killers;                  // 0: every row is kept (no tests)
     uint8_t* alive;                   // [n] out
+    float* xa;                        // [n][row stride] out: the canonical values of every kept row
     int32_t* blk;                     // [workgroups] out: rows kept per workgroup
     unsigned long long* seg_tests;    // [p] += the tests of the partition's rows
     unsigned long long* tests;        // += all tests
 };
 
+constexpr int kKillLds = 8192;   // floats of killer values a workgroup keeps in LDS (32 KB)
+
+// Every row of an unpruned partition against the partition's killer rows (not itself), until
+// one dominates it; the survivors' canonical values go to the staging copy. Killer values sit
+// in LDS when the whole table fits, else they are read from the (L2-resident) table.
 template <int D>
-__global__ void __launch_bounds__(kBlock) filter_kernel(FilterArgs a) {
+__global__ void __launch_bounds__(kPT) filter_kernel(FilterArgs a) {
     constexpr int RS = row_stride<D>();
-    extern __shared__ unsigned long long ltests[];  // [p]
-    __shared__ int32_t ws[kBlock / kWave];
+    constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    extern __shared__ unsigned int fl[];  // [p] test counters, then (when it fits) the killer table
+    __shared__ int32_t ws[kPT / kWave];
     const int d = dget<D>(a.d);
+    const int64_t tab = (int64_t)a.p * kKill * RS;
+    const bool in_lds = a.killers && tab <= kKillLds;
+    unsigned int* ltests = fl;
+    float* lk = reinterpret_cast<float*>(fl + ((a.p + 3) & ~3));  // 16-byte aligned
+    int32_t* lr = reinterpret_cast<int32_t*>(lk + (in_lds ? tab : 0));
     if (a.killers) {
-        for (int32_t j = threadIdx.x; j < a.p; j += kBlock) ltests[j] = 0ull;
+        for (int32_t j = threadIdx.x; j < a.p; j += kPT) ltests[j] = 0u;
+        if (in_lds) {
+            for (int64_t e = threadIdx.x; e < tab; e += kPT) lk[e] = a.kval[e];
+            for (int64_t e = threadIdx.x; e < (int64_t)a.p * kKill; e += kPT) lr[e] = a.krow[e];
+        }
         __syncthreads();
     }
+    const float* ktab = in_lds ? lk : a.kval;
+    const int32_t* rtab = in_lds ? lr : a.krow;
     int32_t kept = 0;
     const int64_t b0 = (int64_t)blockIdx.x * kPRows;
-    for (int it = 0; it < kPPer; ++it) {
-        const int64_t i = b0 + (int64_t)it * kBlock + threadIdx.x;
-        const bool valid = i < a.n;
-        bool live = valid;
-        int32_t part = -1;
-        uint32_t nt = 0;
-        if (valid) {
-            part = a.part_of_row ? a.part_of_row[i] : 0;
-            if (a.killers) {
-                if (a.pruned && a.pruned[part]) {
+    {
+        // the thread's rows, their loads issued together
+        int32_t part[kPPer];
+        float t[kPPer][DM];
+#pragma unroll
+        for (int u = 0; u < kPPer; ++u) {
+            const int64_t i = b0 + (int64_t)u * kPT + threadIdx.x;
+            const bool valid = i < a.n;
+            part[u] = valid ? (a.part_of_row ? a.part_of_row[i] : 0) : -1;
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                if (k < d) t[u][k] = valid ? canon(a.x[(int64_t)k * a.ld + i]) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kPPer; ++u) {
+            const int64_t i = b0 + (int64_t)u * kPT + threadIdx.x;
+            const bool valid = i < a.n;
+            bool live = valid;
+            uint32_t nt = 0;
+            if (valid && a.killers) {
+                if (a.pruned && a.pruned[part[u]]) {
                     live = false;  // Def. 3: the rows of a pruned cell take no part
                 } else {
-                    float t[RS];
-                    load_row<D>(a.xa + i * RS, t);
-                    const int32_t* kr = a.krow + (int64_t)part * kKill;
-                    const float* kv = a.kval + (int64_t)part * kKill * RS;
+                    const int64_t kb = (int64_t)part[u] * kKill;
 #pragma unroll
                     for (int s = 0; s < kKill; ++s) {
-                        const int32_t r = kr[s];
+                        const int32_t r = rtab[kb + s];
+                        float sv[RS];
+                        load_row<D>(ktab + (kb + s) * RS, sv);
                         if (live && r >= 0 && r != (int32_t)i) {
                             ++nt;
-                            float sv[RS];
-                            load_row<D>(kv + s * RS, sv);
                             bool le = true, lt = false;
 #pragma unroll
-                            for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
+                            for (int k = 0; k < DM; ++k)
                                 if (k < d) {
-                                    le &= sv[k] <= t[k];
-                                    lt |= sv[k] < t[k];
+                                    le &= sv[k] <= t[u][k];
+                                    lt |= sv[k] < t[u][k];
                                 }
                             live = !(le && lt);
                         }
                     }
+                    if (nt) atomicAdd(&ltests[part[u]], nt);
                 }
             }
-            a.alive[i] = live ? 1 : 0;
-        }
-        kept += live ? 1 : 0;
-        if (a.killers) {
-            // tests per partition in LDS, folded per wave when its rows share one partition
-            const uint64_t act = __ballot(valid);
-            const int32_t p0 = __builtin_amdgcn_readfirstlane(part);
-            if ((act & 1ull) && __ballot(valid && part != p0) == 0) {
-                unsigned long long s = nt;
+            if (valid) {
+                a.alive[i] = live ? 1 : 0;
+                if (live) {
+                    float q[RS];
 #pragma unroll
-                for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-                if (lane_id() == 0 && s) atomicAdd(&ltests[p0], s);
-            } else if (valid && nt) {
-                atomicAdd(&ltests[part], (unsigned long long)nt);
+                    for (int k = 0; k < RS; ++k) q[k] = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) q[k] = t[u][k];
+                    float4* row = reinterpret_cast<float4*>(a.xa + i * RS);
+#pragma unroll
+                    for (int c = 0; c < RS / 4; ++c) row[c] = make_float4(q[4 * c], q[4 * c + 1], q[4 * c + 2], q[4 * c + 3]);
+                }
             }
+            kept += live ? 1 : 0;
         }
     }
     int32_t total = 0;
-    (void)block_exscan(kept, ws, &total);
+    (void)block_exscan_t<kPT>(kept, ws, &total);
     if (threadIdx.x == 0) a.blk[blockIdx.x] = total;
     if (a.killers) {
         __syncthreads();
         unsigned long long sum = 0;
-        for (int32_t j = threadIdx.x; j < a.p; j += kBlock) {
+        for (int32_t j = threadIdx.x; j < a.p; j += kPT) {
             const unsigned long long c = ltests[j];
             if (c) {
                 atomicAdd(&a.seg_tests[j], c);
@@ -432,24 +464,23 @@ struct CompactArgs {
 };
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) compact_kernel(CompactArgs a) {
+__global__ void __launch_bounds__(kPT) compact_kernel(CompactArgs a) {
     constexpr int RS = row_stride<D>();
-    __shared__ int32_t ws[kBlock / kWave];
+    __shared__ int32_t ws[kPT / kWave];
     const int d = dget<D>(a.d);
-    // thread t takes 16 consecutive rows, so ranks follow row order
-    const int64_t r0 = (int64_t)blockIdx.x * kPRows + (int64_t)threadIdx.x * kPPer;
+    // thread t takes kPPer consecutive rows, so ranks follow row order
+    const int64_t r0 = ((int64_t)blockIdx.x * kPT + threadIdx.x) * kPPer;
     uint32_t flags = 0;
     if (r0 + kPPer <= a.n) {
-        const uint4 q = *reinterpret_cast<const uint4*>(a.alive + r0);
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(a.alive + r0);
 #pragma unroll
-        for (int e = 0; e < kPPer; ++e) flags |= ((w[e >> 2] >> (8 * (e & 3))) & 1u) << e;
+        for (int e = 0; e < kPPer; ++e) flags |= ((w >> (8 * e)) & 1u) << e;
     } else {
         for (int e = 0; e < kPPer; ++e)
             if (r0 + e < a.n) flags |= (uint32_t)(a.alive[r0 + e] & 1u) << e;
     }
     int32_t total = 0;
-    int32_t o = a.blk_off[blockIdx.x] + block_exscan(__popc(flags), ws, &total);
+    int32_t o = a.blk_off[blockIdx.x] + block_exscan_t<kPT>(__popc(flags), ws, &total);
     while (flags) {
         const int e = __ffs(flags) - 1;
         flags &= flags - 1;
@@ -466,28 +497,76 @@ __global__ void __launch_bounds__(kBlock) compact_kernel(CompactArgs a) {
 }
 
 // ---- 6. the partition-contiguous copy of the kept rows in key order --------------------------------
+// Each wave copies one contiguous run of positions (lanes 64 apart, coalesced) and folds the
+// scores of each partition it meets into that partition's range (smin / smax), which the
+// skyline rounds then use instead of a pass of their own.
 template <int D>
 __global__ void __launch_bounds__(kBlock) part_gather_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ rows, const int32_t* __restrict__ n_live,
     int32_t d_rt, int32_t pshift, int32_t multi, const float* __restrict__ xa, float* __restrict__ xp,
-    int64_t ldp, int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum) {
+    int64_t ldp, int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum,
+    uint32_t* __restrict__ smin, uint32_t* __restrict__ smax) {
     constexpr int RS = row_stride<D>();
     const int d = dget<D>(d_rt);
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q >= *n_live) return;
-    const int64_t i = rows[q];
-    float v[RS];
-    load_row<D>(xa + i * RS, v);
-    float f = 0.0f;
+    const int lane = (int)lane_id();
+    const int64_t m = *n_live;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    const int64_t per = (m + nwaves * kWave - 1) / (nwaves * kWave);
+    const int64_t q0 = ((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * per * kWave;
+    int32_t cs = -1;  // partition of the lane's current run of scores
+    uint32_t cmin = 0xFFFFFFFFu, cmax = 0u;
+    for (int64_t j = 0; j < per; ++j) {
+        const int64_t q = q0 + j * kWave + lane;
+        if (q >= m) break;
+        const int64_t i = rows[q];
+        float v[RS];
+        load_row<D>(xa + i * RS, v);
+        float f = 0.0f;
 #pragma unroll
-    for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
-        if (k < d) {
-            xp[(int64_t)k * ldp + q] = v[k];
-            f = __fadd_rn(f, v[k]);
+        for (int k = 0; k < (D > 0 ? D : SKY_MAX_D); ++k)
+            if (k < d) {
+                xp[(int64_t)k * ldp + q] = v[k];
+                f = __fadd_rn(f, v[k]);
+            }
+        const int32_t sg = multi ? (int32_t)(keys[q] >> pshift) : 0;
+        rowid[q] = (int32_t)i;
+        seg[q] = sg;
+        fsum[q] = f;
+        if (!multi) continue;  // one partition: the skyline rounds take its range themselves
+        const uint32_t fb = fbits(f);  // f >= 0: bit order == value order
+        if (sg != cs) {
+            if (cs >= 0) {
+                atomicMin(&smin[cs], cmin);
+                atomicMax(&smax[cs], cmax);
+            }
+            cs = sg;
+            cmin = fb;
+            cmax = fb;
+        } else {
+            cmin = fb < cmin ? fb : cmin;
+            cmax = fb > cmax ? fb : cmax;
         }
-    rowid[q] = (int32_t)i;
-    seg[q] = multi ? (int32_t)(keys[q] >> pshift) : 0;
-    fsum[q] = f;
+    }
+    // the lanes' last runs, one pair of atomics per partition and wave
+    const bool valid = cs >= 0;
+    uint64_t act = __ballot(valid);
+    while (act) {
+        const int leader = __ffsll((unsigned long long)act) - 1;
+        const int32_t sl = __shfl(cs, leader, kWave);
+        const bool mine = valid && cs == sl;
+        const uint64_t peers = __ballot(mine);
+        uint32_t vmin = mine ? cmin : 0xFFFFFFFFu, vmax = mine ? cmax : 0u;
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const uint32_t x = __shfl_xor(vmin, off, kWave), y = __shfl_xor(vmax, off, kWave);
+            vmin = x < vmin ? x : vmin;
+            vmax = y > vmax ? y : vmax;
+        }
+        if (lane == leader) {
+            atomicMin(&smin[sl], vmin);
+            atomicMax(&smax[sl], vmax);
+        }
+        act &= ~peers;
+    }
 }
 
 // ---- Sliced: the order of the slicing attribute ----------------------------------------------------
@@ -609,7 +688,7 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     int32_t* const part_of_row = multi ? a.part_of_row : nullptr;
     // 0. counters of this build
     hipLaunchKernelGGL(partition_init_kernel, dim3((uint32_t)ceil_div((int64_t)a.p * kKill, kBlock)), dim3(kBlock),
-                       0, st, a.p, a.pcount, a.kmin, a.seg_tests, a.tests);
+                       0, st, a.p, a.pcount, a.kmin, a.seg_tests, a.tests, a.smin, a.smax);
     SKY_HIP(hipGetLastError());
     if (a.scheme == SKY_ANGULAR) {
         hipLaunchKernelGGL(angular_table_kernel, dim3(1), dim3(256), 0, st, a.m, a.tan2);
@@ -629,10 +708,10 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     ca.x = a.x; ca.n = n; ca.d = a.d; ca.ld = a.ld;
     ca.scheme = multi ? a.scheme : SKY_NONE; ca.p = a.p; ca.m = a.m;
     ca.tan2 = a.tan2; ca.seg_off = a.seg_off;
-    ca.part_of_row = part_of_row; ca.xa = a.xa; ca.pcount = a.pcount; ca.kmin = a.kmin;
+    ca.part_of_row = part_of_row; ca.pcount = a.pcount; ca.kmin = a.kmin;
     ca.dev_status = a.dev_status;
     const size_t clds = (size_t)a.p * (sizeof(unsigned long long) + sizeof(int32_t));
-    SKY_DISPATCH_D(a.d, classify_kernel, dim3(pblocks), dim3(kBlock), clds, st, ca);
+    SKY_DISPATCH_D(a.d, classify_kernel, dim3(pblocks), dim3(kPT), clds, st, ca);
     SKY_HIP(hipGetLastError());
     // 2. partition offsets; Grid pruning
     hipLaunchKernelGGL(part_offsets_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)a.pcount, a.p, n,
@@ -648,19 +727,25 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     if (a.prefilter) {
         SKY_DISPATCH_D(a.d, kill_rows_kernel, dim3((uint32_t)ceil_div((int64_t)a.p * kKill, kBlock)), dim3(kBlock),
                        0, st, (const unsigned long long*)a.kmin, (const uint8_t*)(a.scheme == SKY_GRID ? a.pruned : nullptr),
-                       a.p, (const float*)a.xa, a.krow, a.kval);
+                       a.p, a.x, a.d, a.ld, a.krow, a.kval);
         SKY_HIP(hipGetLastError());
     }
     FilterArgs fa{};
-    fa.n = n; fa.d = a.d; fa.p = a.p;
+    fa.n = n; fa.d = a.d; fa.ld = a.ld; fa.p = a.p; fa.x = a.x;
     fa.part_of_row = part_of_row;
     fa.pruned = a.scheme == SKY_GRID && multi ? a.pruned : nullptr;
-    fa.xa = a.xa; fa.krow = a.krow; fa.kval = a.kval;
+    fa.krow = a.krow; fa.kval = a.kval;
     fa.killers = a.prefilter ? 1 : 0;
-    fa.alive = a.alive; fa.blk = a.blk;
+    fa.alive = a.alive; fa.xa = a.xa; fa.blk = a.blk;
     fa.seg_tests = a.seg_tests; fa.tests = a.tests;
-    const size_t flds = a.prefilter ? (size_t)a.p * sizeof(unsigned long long) : 0;
-    SKY_DISPATCH_D(a.d, filter_kernel, dim3(pblocks), dim3(kBlock), flds, st, fa);
+    // LDS: the per-partition test counters, then (when it fits) the killer values and rows
+    const int64_t tab = (int64_t)a.p * kKill * partition_row_stride(a.d);
+    size_t flds = 0;
+    if (a.prefilter) {
+        flds = sizeof(unsigned int) * (size_t)((a.p + 3) & ~3);
+        if (tab <= kKillLds) flds += sizeof(float) * (size_t)tab + sizeof(int32_t) * (size_t)a.p * kKill;
+    }
+    SKY_DISPATCH_D(a.d, filter_kernel, dim3(pblocks), dim3(kPT), flds, st, fa);
     SKY_HIP(hipGetLastError());
     // 4. the kept rows with their keys
     SKY_TRY(launch_exclusive_scan(a.blk, a.blk, pblocks, a.scan_tmp, st));
@@ -671,7 +756,7 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     ka.part_of_row = part_of_row; ka.xa = a.xa;
     ka.cbits = cbits; ka.pshift = cbits * a.d;
     ka.keys = a.k0; ka.rows = a.v0; ka.n_live = a.n_live;
-    SKY_DISPATCH_D(a.d, compact_kernel, dim3(pblocks), dim3(kBlock), 0, st, ka);
+    SKY_DISPATCH_D(a.d, compact_kernel, dim3(pblocks), dim3(kPT), 0, st, ka);
     SKY_HIP(hipGetLastError());
     // 5. stable sort of the kept rows by (partition, curve key)
     const uint32_t* sorted_keys = nullptr;
@@ -679,9 +764,9 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, key_bits, a.radix_tmp, st, &sorted_keys, &order,
                               a.n_live));
     // 6. the partition-contiguous copy
-    SKY_DISPATCH_D(a.d, part_gather_kernel, dim3(rblocks), dim3(kBlock), 0, st, sorted_keys, order,
+    SKY_DISPATCH_D(a.d, part_gather_kernel, dim3(rblocks < 8192u ? rblocks : 8192u), dim3(kBlock), 0, st, sorted_keys, order,
                    (const int32_t*)a.n_live, a.d, cbits * a.d, multi ? 1 : 0, (const float*)a.xa, a.xp, a.ldp,
-                   a.rowid, a.seg, a.fsum);
+                   a.rowid, a.seg, a.fsum, a.smin, a.smax);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

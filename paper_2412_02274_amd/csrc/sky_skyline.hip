@@ -131,8 +131,10 @@ __global__ void __launch_bounds__(kBlock) engine_init_kernel(
     for (int64_t i = g; i < 2 * (int64_t)nseg * kBins; i += gs) hist2[i] = 0;
     for (int64_t i = g; i < 2 * (int64_t)nseg * kInfo; i += gs) info2[i] = 0;
     for (int64_t i = g; i < nseg; i += gs) {
-        smin[i] = 0xFFFFFFFFu;
-        smax[i] = 0u;
+        if (smin) {  // (null: the caller has set the score ranges)
+            smin[i] = 0xFFFFFFFFu;
+            smax[i] = 0u;
+        }
         if (seg_tests) seg_tests[i] = 0ull;
     }
     if (g < 3 * kCounters) counters[g] = 0;
@@ -149,6 +151,14 @@ constexpr int kSegPer = 16;
 __host__ __device__ constexpr int64_t seg_pass_blocks(int64_t n) {
     return (n + (int64_t)kBlock * kSegPer - 1) / ((int64_t)kBlock * kSegPer);
 }
+// Items per lane of a run-folding pass over n items (n read on the device): at most kSegPer,
+// fewer when the grid (sized for an upper bound) has more lanes than needed, so that a short
+// list still spreads over every wave instead of leaving a few waves a long chain of loads.
+__device__ __forceinline__ int seg_per_lane(int64_t n) {
+    const int64_t lanes = (int64_t)gridDim.x * kBlock;
+    const int64_t pl = (n + lanes - 1) / lanes;
+    return pl < 1 ? 1 : (pl > kSegPer ? kSegPer : (int)pl);
+}
 
 // Score range (min and max of f) of every segment over the first round's list.
 __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restrict__ items,
@@ -159,10 +169,11 @@ __global__ void __launch_bounds__(kBlock) minmax_kernel(const int32_t* __restric
                                                          uint32_t* __restrict__ smax) {
     const int32_t n = n_dev ? *n_dev : n_host;
     const int lane = (int)lane_id();
-    const int64_t wbase = ((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (kWave * kSegPer);
+    const int pl = seg_per_lane(n);
+    const int64_t wbase = ((int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) * (kWave * pl);
     int32_t cs = -1;  // segment of the lane's current run
     uint32_t cmin = 0xFFFFFFFFu, cmax = 0u;
-    for (int j = 0; j < kSegPer; ++j) {
+    for (int j = 0; j < pl; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
         if (i >= n) break;
         const int32_t pos = items[i];
@@ -463,7 +474,8 @@ __global__ void __launch_bounds__(kBlock) stats_kernel(StatsArgs a) {
         if (threadIdx.x == 0 && lcnt) atomicAdd(&a.info[SI_LIVE], lcnt);
         return;
     }
-    constexpr int64_t kChunk = (int64_t)kBlock * kSegPer;
+    const int pl = seg_per_lane(n);
+    const int64_t kChunk = (int64_t)kBlock * pl;
     const int64_t nchunk = (n + kChunk - 1) / kChunk;
     const int64_t per = (nchunk + gridDim.x - 1) / gridDim.x;
     const int64_t c_end = ((int64_t)blockIdx.x + 1) * per < nchunk ? ((int64_t)blockIdx.x + 1) * per : nchunk;
@@ -484,9 +496,9 @@ __global__ void __launch_bounds__(kBlock) stats_kernel(StatsArgs a) {
         }
         const float lo0 = __uint_as_float(a.smin[s0]);
         const float sc0 = seg_scale(a.smin[s0], a.smax[s0]);
-        const int64_t wbase = bbase + (int64_t)(threadIdx.x / kWave) * (kWave * kSegPer);
+        const int64_t wbase = bbase + (int64_t)(threadIdx.x / kWave) * (kWave * pl);
         int32_t cs = -1, ccnt = 0;  // the lane's current run of live items of one segment
-        for (int j = 0; j < kSegPer; ++j) {
+        for (int j = 0; j < pl; ++j) {
             const int64_t i = wbase + (int64_t)j * kWave + lane;
             if (i >= n) break;
             const int32_t pos = a.items[i];
@@ -1123,9 +1135,8 @@ __global__ void __launch_bounds__(kBlock) scatter_rows_u8_kernel(const uint8_t* 
 }
 __global__ void __launch_bounds__(kBlock) iota_count_kernel(const int32_t* __restrict__ count, int32_t n,
                                                              int32_t* __restrict__ out) {
-    const int32_t i = blockIdx.x * kBlock + threadIdx.x;
     const int32_t m = *count < n ? *count : n;
-    if (i < m) out[i] = i;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) out[i] = i;
 }
 
 __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
@@ -1173,7 +1184,28 @@ struct SelPred {
     const int32_t* seg;
 };
 
+// bit j = (byte j of the 16 at ptr != 0); ptr 16-byte aligned
+__device__ __forceinline__ uint32_t nonzero16(const uint8_t* ptr) {
+    const uint4 q = *reinterpret_cast<const uint4*>(ptr);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) m |= (((w[j >> 2] >> (8 * (j & 3))) & 0xFFu) != 0u ? 1u : 0u) << j;
+    return m;
+}
+
+__device__ __forceinline__ bool aligned16(const void* ptr) { return ((uintptr_t)ptr & 15u) == 0; }
+
 __device__ __forceinline__ uint32_t sel_bits(const SelPred& p, int64_t base, int64_t n) {
+    if (base + kSelPer <= n && !p.skip_seg && (!p.flags || aligned16(p.flags)) && (!p.keep || aligned16(p.keep)) &&
+        (!p.drop || aligned16(p.drop))) {
+        // whole runs of 16 positions: one 16-byte load per byte array
+        uint32_t m = 0xFFFFu;
+        if (p.flags) m &= nonzero16(p.flags + base);
+        if (p.keep) m &= nonzero16(p.keep + base);
+        if (p.drop) m &= ~nonzero16(p.drop + base) & 0xFFFFu;
+        return m;
+    }
     uint32_t m = 0;
 #pragma unroll
     for (int j = 0; j < kSelPer; ++j) {
@@ -1210,7 +1242,20 @@ __device__ __forceinline__ int32_t sel_block_scan(int32_t v, int32_t* total) {
     return before + inc - v;
 }
 
-__global__ void __launch_bounds__(kBlock) sel_count_kernel(SelPred p, int64_t n, int32_t* __restrict__ blk) {
+// the positions a selection covers: [0, n), or [0, min(n, *bound)) with a device bound
+__device__ __forceinline__ int64_t sel_extent(int64_t n, const int32_t* bound) {
+    if (!bound) return n;
+    const int64_t b = *bound;
+    return b < 0 ? 0 : (b < n ? b : n);
+}
+
+__global__ void __launch_bounds__(kBlock) sel_count_kernel(SelPred p, int64_t n, const int32_t* __restrict__ bound,
+                                                           int32_t* __restrict__ blk) {
+    n = sel_extent(n, bound);
+    if ((int64_t)blockIdx.x * kSelChunk >= n) {  // past the bound (uniform per workgroup)
+        if (threadIdx.x == 0) blk[blockIdx.x] = 0;
+        return;
+    }
     const int64_t base = (int64_t)blockIdx.x * kSelChunk + (int64_t)threadIdx.x * kSelPer;
     int32_t total = 0;
     sel_block_scan(__popc(sel_bits(p, base, n)), &total);
@@ -1222,7 +1267,7 @@ __global__ void __launch_bounds__(kBlock) sel_count_kernel(SelPred p, int64_t n,
 // given) = the selection as bytes (it may be the flags array itself: each thread rewrites only
 // the positions it has read); the last block stores the total in *count32 / *count64 and raises
 // SKY_ERR_CAPACITY when it exceeds cap (int64 output)
-__global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
+__global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n, const int32_t* __restrict__ bound,
                                                             const int32_t* __restrict__ blk_off,
                                                             int32_t* __restrict__ out32,
                                                             int64_t* __restrict__ out64, int64_t cap,
@@ -1231,21 +1276,33 @@ __global__ void __launch_bounds__(kBlock) sel_write_kernel(SelPred p, int64_t n,
                                                             int32_t* __restrict__ count32,
                                                             int64_t* __restrict__ count64,
                                                             int32_t* dev_status) {
+    n = sel_extent(n, bound);
+    const bool past = (int64_t)blockIdx.x * kSelChunk >= n;  // uniform per workgroup
+    if (past && blockIdx.x != gridDim.x - 1) return;
     const int64_t base = (int64_t)blockIdx.x * kSelChunk + (int64_t)threadIdx.x * kSelPer;
-    const uint32_t m = sel_bits(p, base, n);
+    const uint32_t m = past ? 0u : sel_bits(p, base, n);
     int32_t total = 0;
     int32_t k = blk_off[blockIdx.x] + sel_block_scan(__popc(m), &total);
+    if (flags_copy && base + kSelPer <= n && aligned16(flags_copy)) {
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int j = 0; j < kSelPer; ++j) {
-        const int64_t i = base + j;
-        if (i >= n) break;
-        const bool v = (m >> j) & 1u;
-        if (all_idx && v) all_idx[i] = k;
-        if (flags_copy) flags_copy[i] = v ? 1 : 0;
-        if (v) {
-            if (out32) out32[k] = (int32_t)i;
-            if (out64 && k < cap) out64[k] = i;
-            ++k;
+        for (int j = 0; j < kSelPer; ++j) w[j >> 2] |= ((m >> j) & 1u) << (8 * (j & 3));
+        *reinterpret_cast<uint4*>(flags_copy + base) = make_uint4(w[0], w[1], w[2], w[3]);
+        flags_copy = nullptr;  // written
+    }
+    if (m || flags_copy) {
+#pragma unroll
+        for (int j = 0; j < kSelPer; ++j) {
+            const int64_t i = base + j;
+            if (i >= n) break;
+            const bool v = (m >> j) & 1u;
+            if (all_idx && v) all_idx[i] = k;
+            if (flags_copy) flags_copy[i] = v ? 1 : 0;
+            if (v) {
+                if (out32) out32[k] = (int32_t)i;
+                if (out64 && k < cap) out64[k] = i;
+                ++k;
+            }
         }
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
@@ -1302,8 +1359,9 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
         int64_t work = pb.n_pos / 16;
         if (2 * (int64_t)nseg * kBins > work) work = 2 * (int64_t)nseg * kBins;
         hipLaunchKernelGGL(engine_init_kernel, dim3(grid(ceil_div(work, kBlock))), dim3(kBlock), 0, st,
-                           pb.n_pos, pb.flag_out, nseg, b.hist, b.seg_info, b.seg_min, b.seg_max, b.counters,
-                           b.tests, pb.zero_seg_tests ? pb.seg_tests : nullptr);
+                           pb.n_pos, pb.flag_out, nseg, b.hist, b.seg_info, pb.ranges_ready ? nullptr : b.seg_min,
+                           pb.ranges_ready ? nullptr : b.seg_max, b.counters, b.tests,
+                           pb.zero_seg_tests ? pb.seg_tests : nullptr);
         SKY_HIP(hipGetLastError());
     }
     // optional timing hooks around the dominance-test launches
@@ -1328,7 +1386,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
             const int32_t* n_dev = r == 1 ? pb.n_items_dev : ctr(r - 1) + C_RTOT;
             const uint8_t* dead = r == 1 ? nullptr : b.dom;
             const uint32_t iblocks = (uint32_t)ceil_div(ub, kBlock);
-            if (r == 1) {
+            if (r == 1 && !pb.ranges_ready) {
                 if (nseg == 1)
                     hipLaunchKernelGGL(minmax1_kernel, dim3(iblocks < 256 ? iblocks : 256), dim3(kBlock), 0, st,
                                        items, n_host, n_dev, pb.fsum, b.seg_min, b.seg_max);
@@ -1416,13 +1474,13 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
 // outputs). tmp: scan_tmp_elems(n) int32 of scratch.
 static sky_status launch_select(const SelPred& p, int64_t n, int32_t* out32, int64_t* out64, int64_t cap,
                                 int32_t* all_idx, uint8_t* flags_copy, int32_t* count32, int64_t* count64,
-                                int32_t* dev_status, int32_t* tmp, hipStream_t st) {
+                                int32_t* dev_status, int32_t* tmp, hipStream_t st, const int32_t* bound = nullptr) {
     const int64_t nblk = ceil_div(n > 0 ? n : 1, kSelChunk);
     int32_t* blk = tmp;  // block counts, then their exclusive scan (the layout of scan_tmp_elems)
-    hipLaunchKernelGGL(sel_count_kernel, dim3((uint32_t)nblk), dim3(kBlock), 0, st, p, n, blk);
+    hipLaunchKernelGGL(sel_count_kernel, dim3((uint32_t)nblk), dim3(kBlock), 0, st, p, n, bound, blk);
     SKY_HIP(hipGetLastError());
     SKY_TRY(launch_exclusive_scan(blk, blk, nblk, tmp + round_up(nblk, 64), st));
-    hipLaunchKernelGGL(sel_write_kernel, dim3((uint32_t)nblk), dim3(kBlock), 0, st, p, n,
+    hipLaunchKernelGGL(sel_write_kernel, dim3((uint32_t)nblk), dim3(kBlock), 0, st, p, n, bound,
                        (const int32_t*)blk, out32, out64, cap, all_idx, flags_copy, count32, count64,
                        dev_status);
     SKY_HIP(hipGetLastError());
@@ -1446,10 +1504,11 @@ sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_p
 // Positions i with flags[i] != 0 and (drop null or drop[i] == 0), in order (stable); with
 // bake, flags[i] is rewritten to the selection.
 sky_status launch_compact_flags(uint8_t* flags, const uint8_t* drop, bool bake, int32_t n, int32_t* out,
-                                int32_t* count32, int64_t* count64, int32_t* scan_tmp, hipStream_t st) {
+                                int32_t* count32, int64_t* count64, int32_t* scan_tmp, hipStream_t st,
+                                const int32_t* bound) {
     const SelPred p{flags, nullptr, drop, nullptr, nullptr};
     return launch_select(p, n, out, nullptr, (int64_t)n, nullptr, bake ? flags : nullptr, count32, count64,
-                         nullptr, scan_tmp, st);
+                         nullptr, scan_tmp, st, bound);
 }
 
 sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,
@@ -1463,7 +1522,9 @@ sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, con
 
 sky_status launch_iota_count(const int32_t* count, int32_t n, int32_t* out, hipStream_t st) {
     if (n <= 0) return SKY_OK;
-    hipLaunchKernelGGL(iota_count_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0, st, count, n, out);
+    const int64_t nb = ceil_div(n, kBlock);
+    hipLaunchKernelGGL(iota_count_kernel, dim3((uint32_t)(nb < kMaxGrid ? nb : kMaxGrid)), dim3(kBlock), 0, st,
+                       count, n, out);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
