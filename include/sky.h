@@ -133,6 +133,8 @@ typedef struct sky_info {
     int64_t rows_kept;        /* rows the build kept for the local phase: n without the
                                  prefilter (sky_params.prefilter_off), else the rows of unpruned
                                  partitions that no killer row dominates */
+    int64_t tests_prefilter;  /* of tests_local: the tests of the build's prefilter (rows against
+                                 the killer rows of their partition) */
 } sky_info;
 
 typedef struct sky_gres_opts {

@@ -457,6 +457,7 @@ sky_status sky_plan_info(const sky_plan* P, sky_info* out) {
     out->tests_local_max = dv[D_TESTS_LOCAL_MAX];
     out->reps_kept = nk;
     out->rows_kept = kept;
+    out->tests_prefilter = dv[D_TESTS_FILTER];
     if (P->state >= 3) {
         out->sky_count = dv[D_SKY_COUNT];
         if (P->p > 1) {

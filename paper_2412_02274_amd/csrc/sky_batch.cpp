@@ -178,6 +178,7 @@ sky_status sky_batch_info(const sky_batch* B, sky_info* out) {
     out->tests_local = pi.tests_local;
     out->tests_local_max = pi.tests_local_max;  // the costliest relation
     out->rows_kept = pi.rows_kept;
+    out->tests_prefilter = pi.tests_prefilter;
     out->local_count = pi.sky_count;
     out->sky_count = pi.sky_count;
     return SKY_OK;

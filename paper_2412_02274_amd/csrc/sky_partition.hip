@@ -212,7 +212,8 @@ __global__ void __launch_bounds__(kPT) classify_kernel(ClassifyArgs a) {
                 atomicAdd(&lcnt[p0], (int32_t)__popcll(act));
             }
         } else if (valid) {
-            atomicMin(&lmin[part], key);
+            // (the minimum only falls: most rows lose to it without an atomic)
+            if (key < lmin[part]) atomicMin(&lmin[part], key);
             atomicAdd(&lcnt[part], 1);
         }
     }
@@ -470,6 +471,7 @@ __global__ void __launch_bounds__(kPT) compact_kernel(CompactArgs a) {
     const int d = dget<D>(a.d);
     // thread t takes kPPer consecutive rows, so ranks follow row order
     const int64_t r0 = ((int64_t)blockIdx.x * kPT + threadIdx.x) * kPPer;
+    const int32_t boff = a.blk_off[blockIdx.x];
     uint32_t flags = 0;
     if (r0 + kPPer <= a.n) {
         const uint32_t w = *reinterpret_cast<const uint32_t*>(a.alive + r0);
@@ -480,7 +482,7 @@ __global__ void __launch_bounds__(kPT) compact_kernel(CompactArgs a) {
             if (r0 + e < a.n) flags |= (uint32_t)(a.alive[r0 + e] & 1u) << e;
     }
     int32_t total = 0;
-    int32_t o = a.blk_off[blockIdx.x] + block_exscan_t<kPT>(__popc(flags), ws, &total);
+    int32_t o = boff + block_exscan_t<kPT>(__popc(flags), ws, &total);
     while (flags) {
         const int e = __ffs(flags) - 1;
         flags &= flags - 1;
@@ -493,7 +495,7 @@ __global__ void __launch_bounds__(kPT) compact_kernel(CompactArgs a) {
         a.rows[o] = (uint32_t)i;
         ++o;
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *a.n_live = a.blk_off[blockIdx.x] + total;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *a.n_live = boff + total;
 }
 
 // ---- 6. the partition-contiguous copy of the kept rows in key order --------------------------------
