@@ -135,6 +135,8 @@ typedef struct sky_info {
                                  partitions that no killer row dominates */
     int64_t tests_prefilter;  /* of tests_local: the tests of the build's prefilter (rows against
                                  the killer rows of their partition) */
+    int64_t tests_gres;       /* batched plans (sky_batch_info): the candidate tests the last
+                                 sky_batch_gres evaluated; 0 for plain plans */
 } sky_info;
 
 typedef struct sky_gres_opts {
@@ -476,9 +478,10 @@ sky_status sky_batch_gres(sky_batch* batch, int32_t g_max, int32_t* g_exit, floa
 /*
  * sky_batch_info -- n = total rows, d, scheme = SKY_NONE, p = nbatch, max_partition = rows of
  * the largest relation, state (1 created, 2 skylines queued); after sky_batch_skylines also
- * rounds_local / tests_local / tests_local_max of the skyline rounds and local_count =
- * sky_count = the total skyline size, read back on the stream of the last sky_batch_skylines
- * (this call waits for it).
+ * rounds_local / tests_local / tests_local_max / tests_prefilter / rows_kept of the skyline
+ * rounds and local_count = sky_count = the total skyline size, read back on the stream of the
+ * last sky_batch_skylines; after sky_batch_gres also tests_gres, read back on its stream (this
+ * call waits for both).
  */
 sky_status sky_batch_info(const sky_batch* batch, sky_info* out);
 

@@ -60,7 +60,7 @@ class SkyInfo(C.Structure):
                 ("tests_merge", C.c_int64), ("max_partition", C.c_int64),
                 ("events_used", C.c_int32), ("reps_kept", C.c_int32),
                 ("tests_local_max", C.c_int64), ("rows_kept", C.c_int64),
-                ("tests_prefilter", C.c_int64)]
+                ("tests_prefilter", C.c_int64), ("tests_gres", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -360,7 +360,7 @@ def project(x_soa: torch.Tensor, rows: torch.Tensor, g: int, out: torch.Tensor |
 
 
 def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, scheme="none",
-                 target_p: int = 16, slice_dim: int = 0, reps: int = 0):
+                 target_p: int = 16, slice_dim: int = 0, reps: int = 0, prefilter: bool = True):
     """Alg. 1 as written: for g = g_max .. 2, the skyline of the grid projection of the candidate
     set (Sky(r)) is computed through the two-phase partitioned scheme (build, local skylines,
     merge on the projected relation); every candidate not in it that has no value yet gets
@@ -368,7 +368,8 @@ def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, sc
     once none is. Returns (g_exit int32[s] on the host, per-level statistics). Equal to
     ``gres()`` for every input (gres is stable and dominance between projections is the per-tuple
     test); kept to run the paper's own formulation and count its work. reps > 0 applies
-    Representative Filtering (Sec. 3.1) inside every level's skyline."""
+    Representative Filtering (Sec. 3.1) inside every level's skyline; prefilter as in
+    ``build``."""
     lib = _lib.load()
     s = int(sky_idx.numel())
     d = x_soa.shape[0]
@@ -383,7 +384,7 @@ def gres_literal(x_soa: torch.Tensor, sky_idx: torch.Tensor, g_max: int = 25, sc
     sp = _stream_ptr()
     for g in range(int(g_max), 1, -1):
         project(x_soa, sky_idx, g, out=proj, status=status)
-        plan = build(proj, scheme, target_p, slice_dim, status=status, reps=reps)
+        plan = build(proj, scheme, target_p, slice_dim, status=status, reps=reps, prefilter=prefilter)
         plan.local_skylines()
         sky_g, member = plan.merge(member=True)
         inf = plan.info()

@@ -21,9 +21,11 @@ struct sky_batch {
     const float* x = nullptr;
     int32_t* dev_status = nullptr;
     int32_t state = 0;             // 1 created, 2 skylines queued
+    hipStream_t last_stream = nullptr;  // stream of the last sky_batch_gres
     int64_t cap = 0;               // min(sky_idx capacity of the last sky_batch_skylines, total)
     // workspace after the plan's region, sized for the worst case (every row in a skyline)
     int64_t* dev_count = nullptr;  // the skyline total (int64, sky_idx's count)
+    unsigned long long* gtests = nullptr;  // candidate tests of the last gres search
     int32_t* cand_off = nullptr;   // [nbatch + 1] element offsets of every relation's skyline
     int32_t* used = nullptr;       // [2] store slots in use, largest relation's skyline
     int32_t* order = nullptr;      // [nbatch] relations, longest-first
@@ -52,6 +54,7 @@ bool valid_offsets(const int64_t* off, int32_t nbatch) {
 // Regions after the plan, sized for the worst case: every row a skyline row.
 void carve_batch_tail(Carver& c, sky_batch* B, int64_t s, int32_t d, int32_t nbatch) {
     B->dev_count = c.take<int64_t>(8);
+    B->gtests = c.take<unsigned long long>(1);
     B->cand_off = c.take<int32_t>((size_t)nbatch + 1);
     B->used = c.take<int32_t>(64);
     B->order = c.take<int32_t>((size_t)nbatch);
@@ -163,9 +166,12 @@ sky_status sky_batch_gres(sky_batch* B, int32_t g_max, int32_t* g_exit, float* g
                           void* ev_begin, void* ev_end, void* stream) {
     if (!B || g_max < 2 || g_max > SKY_MAX_G || (!ev_begin) != (!ev_end)) return SKY_ERR_INVALID_ARG;
     if (B->state != 2) return SKY_ERR_STATE;
+    B->last_stream = (hipStream_t)stream;
+    SKY_TRY(launch_fill_u8(reinterpret_cast<uint8_t*>(B->gtests), sizeof(unsigned long long), 0,
+                           (hipStream_t)stream));
     return launch_batch_search(B->store, B->d, B->cap, B->cand_off, B->nbatch, B->used, B->near_first != 0,
                                B->lpt != 0, B->order, B->rank_off, B->tord, B->tseg, B->tg, g_max, B->mapping,
-                               g_exit, gres, ev_begin, ev_end, (hipStream_t)stream);
+                               g_exit, gres, ev_begin, ev_end, B->gtests, (hipStream_t)stream);
 }
 
 sky_status sky_batch_info(const sky_batch* B, sky_info* out) {
@@ -181,6 +187,12 @@ sky_status sky_batch_info(const sky_batch* B, sky_info* out) {
     out->tests_prefilter = pi.tests_prefilter;
     out->local_count = pi.sky_count;
     out->sky_count = pi.sky_count;
+    if (B->last_stream) {  // the candidate tests of the last gres search
+        unsigned long long gt = 0;
+        SKY_HIP(hipMemcpyAsync(&gt, B->gtests, sizeof(gt), hipMemcpyDeviceToHost, B->last_stream));
+        SKY_HIP(hipStreamSynchronize(B->last_stream));
+        out->tests_gres = (int64_t)gt;
+    }
     return SKY_OK;
 }
 

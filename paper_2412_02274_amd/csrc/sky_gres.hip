@@ -1219,7 +1219,7 @@ sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, c
                                int32_t nseg, const int32_t* used, bool near_first, bool lpt, int32_t* order,
                                int32_t* rank_off, int32_t* tord, int32_t* tseg, const GresTargets& tg,
                                int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres, void* ev_begin,
-                               void* ev_end, hipStream_t st) {
+                               void* ev_end, unsigned long long* dev_tests, hipStream_t st) {
     if (cap <= 0) return SKY_OK;
     if (lpt) {  // the targets of the relations with the most candidates first
         hipLaunchKernelGGL(batch_rank_kernel, dim3((uint32_t)ceil_div(nseg, kBlock)), dim3(kBlock), 0, st,
@@ -1238,7 +1238,7 @@ sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, c
                        (const int32_t*)store.perm, near_first ? 1 : 0, tg.tval, tg.tvcap, tg.thint, tg.tout, tseg);
     SKY_HIP(hipGetLastError());
     return launch_gres_search(store, d, 0, tg, cap, nullptr, tseg, lpt ? tord : nullptr, g_max, mapping, g_exit,
-                              gres, ev_begin, ev_end, nullptr, st);
+                              gres, ev_begin, ev_end, dev_tests, st);
 }
 
 sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds, int32_t* out) {

@@ -413,7 +413,7 @@ sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, c
                                int32_t nseg, const int32_t* used, bool near_first, bool lpt, int32_t* order,
                                int32_t* rank_off, int32_t* tord, int32_t* tseg, const GresTargets& tg,
                                int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres, void* ev_begin,
-                               void* ev_end, hipStream_t st);
+                               void* ev_end, unsigned long long* dev_tests, hipStream_t st);
 // measured (both mappings with per-target start levels): lanes over 64 levels pay off when
 // many levels lie below the start levels (g_max >= 2^17) or on small skylines with
 // g_max > 1000; otherwise the banded tile walk is faster

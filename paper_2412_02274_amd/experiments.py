@@ -8,8 +8,10 @@ computation, the heaviest partition's local-phase tests plus the final phase's; 
 sum over the levels. The plain method (scheme "none") runs one partition, so its count is all
 of its tests.
 
-The counts are the row-against-row tests the device evaluates. Tile-box pruning removes many
-tests the paper's sequential filter would make, so absolute numbers are this implementation's;
+The counts are the row-against-row tests the device evaluates, with the build's killer
+prefilter off (it is this implementation's addition, not the paper's, and it would count its
+own tests in the local phase). Tile-box pruning removes many tests the paper's sequential filter
+would make, so absolute numbers are this implementation's;
 what carries over is how they move with the scheme, the size, the dimensions, the partitions
 and the representatives. Data come from ``datagen`` (uniform, and the anticorrelated generator
 around the plane sum(x) = d/2), not the paper's generator.
@@ -40,7 +42,7 @@ SWEEPS = {
 
 
 def _skyline(xs, scheme, p, reps):
-    plan = api.build(xs, scheme, p, reps=reps)
+    plan = api.build(xs, scheme, p, reps=reps, prefilter=False)
     plan.local_skylines()
     sky = plan.merge().clone()
     inf = plan.info()
@@ -56,7 +58,7 @@ def point(xs: torch.Tensor, p: int, reps: int, scheme: str, g_max: int = 25) -> 
     torch.cuda.synchronize()
     t_sky = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ge_lit, levels = api.gres_literal(xs, sky, g_max, scheme=scheme, target_p=p, reps=reps)
+    ge_lit, levels = api.gres_literal(xs, sky, g_max, scheme=scheme, target_p=p, reps=reps, prefilter=False)
     torch.cuda.synchronize()
     t_gres = time.perf_counter() - t0
     ge, _ = api.gres(xs, sky, g_max)
