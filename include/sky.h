@@ -488,6 +488,31 @@ sky_status sky_batch_info(const sky_batch* batch, sky_info* out);
 /* Releases a batch (host memory only). Null is accepted. */
 void sky_batch_destroy(sky_batch* batch);
 
+/* ------------------------------------------------------------------------------------------
+ * Measurement aids (not part of the path): probes of the two device rates the kernels'
+ * rooflines are priced against, so that a benchmark can report the rates it measured beside
+ * the published ones.
+ * ------------------------------------------------------------------------------------------ */
+
+/*
+ * sky_probe_valu -- one launch of `grid` workgroups of 256 threads, each thread running `iters`
+ * iterations of four independent chains of 32-bit integer add / xor / max / min (the dominance
+ * test's instruction mix), 24 VALU ops per iteration. *lane_ops (host) = the lane-ops the launch
+ * executes. sink: device uint32[grid] (written, to keep the work live). ev_begin / ev_end:
+ * optional hipEvent_t recorded around the launch (both or neither). SKY_ERR_INVALID_ARG for
+ * iters < 1, grid < 1 or null pointers.
+ */
+sky_status sky_probe_valu(int64_t iters, int32_t grid, uint32_t* sink, void* ev_begin, void* ev_end,
+                          void* stream, int64_t* lane_ops);
+
+/*
+ * sky_probe_copy -- a streaming copy of `bytes` device bytes from src to dst (16-byte
+ * aligned, bytes a positive multiple of 16; the ranges must not overlap): every byte is read
+ * once and written once. ev_begin / ev_end as for sky_probe_valu.
+ */
+sky_status sky_probe_copy(const void* src, void* dst, int64_t bytes, void* ev_begin, void* ev_end,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,7 +44,7 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
            "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
            "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres",
-           "gres_compute_noalloc", "sky_literal_level")
+           "gres_compute_noalloc", "sky_literal_level", "sky_probe_valu", "sky_probe_copy")
 
 
 class SkyParams(C.Structure):
@@ -134,6 +134,8 @@ def load():
         "sky_literal_level": (i32, [vp, i64, i32, vp, vp, vp]),
         "gres_compute_noalloc": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, vp, vp,
                                        C.POINTER(GresOpts), vp]),
+        "sky_probe_valu": (i32, [i64, i32, vp, vp, vp, vp, C.POINTER(i64)]),
+        "sky_probe_copy": (i32, [vp, vp, i64, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libsky.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["sky_api.cpp", "sky_batch.cpp", "sky_ingest.hip", "sky_scan.hip", "sky_radix.hip", "sky_partition.hip",
-           "sky_skyline.hip", "sky_gres.hip", "sky_gbar.hip", "sky_reps.hip", "sky_noalloc.hip"]
+           "sky_skyline.hip", "sky_gres.hip", "sky_gbar.hip", "sky_reps.hip", "sky_noalloc.hip", "sky_probe.hip"]
 
 ARCH = os.environ.get("SKY_OFFLOAD_ARCH", "gfx950")
 

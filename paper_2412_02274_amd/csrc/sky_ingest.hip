@@ -11,11 +11,15 @@ namespace {
 
 constexpr int kRows = 256;  // rows per workgroup tile
 
+// D > 0: d known at compile time (the row/attribute split of an element index is then a
+// division by a constant); D = 0: any d.
+template <int D>
 __global__ void __launch_bounds__(kBlock) ingest_kernel(const float* __restrict__ x_rows,
-                                                         int64_t n, int32_t d,
+                                                         int64_t n, int32_t d_rt,
                                                          float* __restrict__ x_soa, int64_t ld,
                                                          int32_t* dev_status) {
     __shared__ float tile[SKY_MAX_D * (kRows + 1)];
+    const int d = D > 0 ? D : d_rt;
     const int64_t row0 = (int64_t)blockIdx.x * kRows;
     const int rows = (int)((n - row0) < kRows ? (n - row0) : kRows);
     const int elems = rows * d;
@@ -109,8 +113,17 @@ sky_status launch_ingest(const float* x_rows, int64_t n, int32_t d, float* x_soa
                          int32_t* dev_status, hipStream_t st) {
     if (n == 0) return SKY_OK;
     int64_t blocks = ceil_div(n, kRows);
-    hipLaunchKernelGGL(ingest_kernel, dim3((uint32_t)blocks), dim3(kBlock), 0, st, x_rows, n, d,
-                       x_soa, ld, dev_status);
+    switch (d) {
+#define SKY_INGEST_D(DD) \
+        case DD: hipLaunchKernelGGL(ingest_kernel<DD>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, x_rows, n, d, \
+                                    x_soa, ld, dev_status); break;
+        SKY_INGEST_D(1) SKY_INGEST_D(2) SKY_INGEST_D(3) SKY_INGEST_D(4)
+        SKY_INGEST_D(5) SKY_INGEST_D(6) SKY_INGEST_D(7) SKY_INGEST_D(8)
+#undef SKY_INGEST_D
+        default:
+            hipLaunchKernelGGL(ingest_kernel<0>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, x_rows, n, d, x_soa,
+                               ld, dev_status);
+    }
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }

@@ -273,3 +273,17 @@ def test_gbar_arguments(lib):
                          None) == _lib.SKY_ERR_WORKSPACE
     assert lib.gres_gbar(fake, 1000, 2, 1000, fake, fake, None, ws, fake,
                          None) == _lib.SKY_ERR_WORKSPACE
+
+
+def test_probe_arguments(lib):
+    # the measurement probes check their arguments before any device call
+    fake = C.c_void_p(0x1000)  # never dereferenced
+    ops = C.c_int64()
+    assert lib.sky_probe_valu(0, 64, fake, None, None, None, C.byref(ops)) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_probe_valu(10, 0, fake, None, None, None, C.byref(ops)) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_probe_valu(10, 64, None, None, None, None, C.byref(ops)) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_probe_valu(10, 64, fake, fake, None, None, C.byref(ops)) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_probe_copy(fake, fake, 0, None, None, None) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_probe_copy(fake, fake, 24, None, None, None) == _lib.SKY_ERR_INVALID_ARG  # not 16k
+    assert lib.sky_probe_copy(C.c_void_p(0x1004), fake, 32, None, None, None) == _lib.SKY_ERR_INVALID_ARG
+    assert lib.sky_probe_copy(None, fake, 32, None, None, None) == _lib.SKY_ERR_INVALID_ARG

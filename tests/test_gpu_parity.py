@@ -625,3 +625,24 @@ def test_pipeline_device_side_mapping(dev, g_max, mapping):
     assert np.array_equal(ge.cpu().numpy(), oracle.gres(x, want, g_max)[0])
     assert np.array_equal(gr.cpu().numpy(), (1.0 / ge.cpu().numpy().astype(np.float32)))
     pipe.close()
+
+
+def test_probes(dev):
+    """The measurement probes: the copy moves every byte, the VALU probe reports the lane-ops
+    of its launch (grid x 256 threads x iterations x 24) and writes its sink."""
+    import ctypes as C
+    lib = _lib.load()
+    src = torch.randint(0, 255, (1 << 20,), dtype=torch.uint8, device=dev)
+    dst = torch.zeros_like(src)
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(lib.sky_probe_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), src.numel(),
+                                  None, None, st), "sky_probe_copy")
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
+    sink = torch.zeros(64, dtype=torch.int32, device=dev)
+    ops = C.c_int64()
+    _lib.check(lib.sky_probe_valu(1000, 64, C.c_void_p(sink.data_ptr()), None, None, st, C.byref(ops)),
+               "sky_probe_valu")
+    torch.cuda.synchronize()
+    assert ops.value == 64 * 256 * 1000 * 24
+    assert int((sink != 0).sum()) > 0
