@@ -285,7 +285,10 @@ sky_status sky_literal_level(const uint8_t* member, int64_t s, int32_t g, int32_
                              void* stream);
 
 /*
- * Workspace for gres_compute, in bytes. Returns 0 for invalid arguments.
+ * Workspace for gres_compute, in bytes. Returns 0 for invalid arguments. For g_max <= 64 it
+ * includes a table of every candidate's keys at every level, packed into one 64-bit word per
+ * (level, candidate) when the d keys fit (d * (bit length of g_max + 1, plus one) <= 64, e.g.
+ * d <= 10 at g_max 25): (g_max - 1) x (s rounded up, plus padding tiles) x 8 bytes.
  */
 size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max);
 
@@ -311,8 +314,10 @@ sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld,
  * allocation). Same arguments, results and errors as gres_compute, minus ws / ws_bytes: the
  * workspace is a fixed array of SKY_NOALLOC_SCRATCH_BYTES bytes inside this library, one per
  * device, held from the library's first use on that device until the process ends. Calls whose
- * gres_workspace_bytes(s, d, g_max) exceeds it return SKY_ERR_UNSUPPORTED (with no work queued);
- * at d = 6 that is about 700,000 tuples. The array of the CURRENT device is used, so `stream`
+ * workspace without the key table (gres_workspace_bytes(s, d, 65): no table above g_max 64)
+ * exceeds it return SKY_ERR_UNSUPPORTED (with no work queued); at d = 6 that is about 700,000
+ * tuples. The key table is used when the whole gres_workspace_bytes(s, d, g_max) fits (the
+ * results are the same either way). The array of the CURRENT device is used, so `stream`
  * must belong to the current device. Every call on one device shares its array and leaves its
  * contents behind (the call itself depends on none of them): calls that overlap on one device,
  * on different streams or from different threads, race and give undefined results -- queue

@@ -388,6 +388,61 @@ sky_status plan_final_phase(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t*
                                sky_idx, cap, dev_count, P->pos_tmp, P->scan_tmp, P->dev_status, st);
 }
 
+sky_status check_opts(const sky_gres_opts* opts, int32_t* mapping) {
+    *mapping = opts ? opts->mapping : SKY_GRES_AUTO;
+    if (*mapping < SKY_GRES_AUTO || *mapping > SKY_GRES_LEVELS) return SKY_ERR_INVALID_ARG;
+    if (opts && (opts->reserved != 0 || (!opts->ev_begin) != (!opts->ev_end))) return SKY_ERR_INVALID_ARG;
+    return SKY_OK;
+}
+
+namespace {
+
+void carve_gres_compute(Carver& c, GresStore& store, GresPrepTmp& tmp, GresTargets& tg, GresKeys& keys,
+                        int64_t s, int32_t d, int32_t g_max, bool with_keys) {
+    carve_gres_store(c, store, s, d, 1);
+    carve_gres_prep_tmp(c, tmp, s);
+    carve_gres_targets(c, tg, s, d);
+    if (with_keys) carve_gres_keys(c, keys, store.ccap, d, g_max);
+}
+
+}  // namespace
+
+size_t gres_ws_bytes(int64_t s, int32_t d, int32_t g_max, bool with_keys) {
+    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return 0;
+    Carver c(nullptr, 0);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    GresTargets tg{};
+    GresKeys keys{};
+    carve_gres_compute(c, store, tmp, tg, keys, s, d, g_max, with_keys);
+    return c.used;
+}
+
+sky_status gres_compute_ws(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
+                           int64_t s, int32_t g_max, int32_t* g_exit, float* gres, void* ws, size_t ws_bytes,
+                           bool with_keys, int32_t* dev_status, const sky_gres_opts* opts, hipStream_t st) {
+    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
+    if (!dev_status) return SKY_ERR_INVALID_ARG;
+    int32_t mapping = 0;
+    SKY_TRY(check_opts(opts, &mapping));
+    if (s == 0) return SKY_OK;
+    if (!x_soa || !sky_idx || n < 1 || n > kMaxRows || ld < n || !ws) return SKY_ERR_INVALID_ARG;
+    if (ws_bytes < gres_ws_bytes(s, d, g_max, with_keys)) return SKY_ERR_WORKSPACE;
+    Carver c(ws, ws_bytes);
+    GresStore store{};
+    GresPrepTmp tmp{};
+    GresTargets tg{};
+    GresKeys keys{};
+    carve_gres_compute(c, store, tmp, tg, keys, s, d, g_max, with_keys);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
+    SKY_TRY(launch_gres_prepare(x_soa, n, d, ld, sky_idx, s, store, tmp, dev_status, st));
+    SKY_TRY(launch_gres_targets(x_soa, n, d, ld, nullptr, s, s, store, tg, dev_status, st));
+    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, nullptr, nullptr, g_max, mapping, g_exit, gres,
+                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
+                              opts ? opts->dev_tests : nullptr, st, &keys);
+}
+
 }  // namespace sky
 
 extern "C" {
@@ -476,50 +531,16 @@ void sky_plan_destroy(sky_plan* P) {
 }
 
 size_t gres_workspace_bytes(int64_t s, int32_t d, int32_t g_max) {
-    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return 0;
-    Carver c(nullptr, 0);
-    GresStore store{};
-    GresPrepTmp tmp{};
-    GresTargets tg{};
-    carve_gres_store(c, store, s, d, 1);
-    carve_gres_prep_tmp(c, tmp, s);
-    carve_gres_targets(c, tg, s, d);
-    return c.used;
+    return sky::gres_ws_bytes(s, d, g_max, true);
 }
 
-static sky_status check_opts(const sky_gres_opts* opts, int32_t* mapping) {
-    *mapping = opts ? opts->mapping : SKY_GRES_AUTO;
-    if (*mapping < SKY_GRES_AUTO || *mapping > SKY_GRES_LEVELS) return SKY_ERR_INVALID_ARG;
-    if (opts && (opts->reserved != 0 || (!opts->ev_begin) != (!opts->ev_end))) return SKY_ERR_INVALID_ARG;
-    return SKY_OK;
-}
 
 sky_status gres_compute(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
                         int64_t s, int32_t g_max, int32_t* g_exit, float* gres, void* ws,
                         size_t ws_bytes, int32_t* dev_status, const sky_gres_opts* opts,
                         void* stream) {
-    if (s < 0 || s > kMaxBuildRows || !valid_d(d) || g_max < 2 || g_max > SKY_MAX_G) return SKY_ERR_INVALID_ARG;
-    if (!dev_status) return SKY_ERR_INVALID_ARG;
-    int32_t mapping = 0;
-    SKY_TRY(check_opts(opts, &mapping));
-    if (s == 0) return SKY_OK;
-    if (!x_soa || !sky_idx || n < 1 || n > kMaxRows || ld < n || !ws) return SKY_ERR_INVALID_ARG;
-    if (ws_bytes < gres_workspace_bytes(s, d, g_max)) return SKY_ERR_WORKSPACE;
-    Carver c(ws, ws_bytes);
-    GresStore store{};
-    GresPrepTmp tmp{};
-    GresTargets tg{};
-    carve_gres_store(c, store, s, d, 1);
-    carve_gres_prep_tmp(c, tmp, s);
-    carve_gres_targets(c, tg, s, d);
-    if (c.overflow) return SKY_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    if (mapping == SKY_GRES_AUTO) mapping = gres_auto_mapping(s, g_max);
-    SKY_TRY(launch_gres_prepare(x_soa, n, d, ld, sky_idx, s, store, tmp, dev_status, st));
-    SKY_TRY(launch_gres_targets(x_soa, n, d, ld, nullptr, s, s, store, tg, dev_status, st));
-    return launch_gres_search(store, d, (int32_t)s, tg, s, nullptr, nullptr, nullptr, g_max, mapping, g_exit, gres,
-                              opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
-                              opts ? opts->dev_tests : nullptr, st);
+    return sky::gres_compute_ws(x_soa, n, d, ld, sky_idx, s, g_max, g_exit, gres, ws, ws_bytes, true,
+                                dev_status, opts, (hipStream_t)stream);
 }
 
 sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, void* ws, size_t ws_bytes,
@@ -537,9 +558,8 @@ sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, vo
     GresStore store{};
     GresPrepTmp tmp{};
     GresTargets tg{};
-    carve_gres_store(cv, store, c, P->d, 1);
-    carve_gres_prep_tmp(cv, tmp, c);
-    carve_gres_targets(cv, tg, c, P->d);
+    GresKeys keys{};
+    carve_gres_compute(cv, store, tmp, tg, keys, c, P->d, g_max, true);
     if (cv.overflow) return SKY_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     P->last_stream = st;
@@ -551,7 +571,7 @@ sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, vo
     SKY_TRY(launch_gres_targets_all(store, P->d, c, s_dev, tg, st));
     return launch_gres_search(store, P->d, (int32_t)c, tg, c, s_dev, nullptr, nullptr, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
-                              opts ? opts->dev_tests : nullptr, st);
+                              opts ? opts->dev_tests : nullptr, st, &keys);
 }
 
 size_t gres_gbar_workspace_bytes(int64_t n) {

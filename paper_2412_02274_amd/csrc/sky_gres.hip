@@ -186,6 +186,42 @@ __global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restric
     }
 }
 
+// Packed keys of one segment's slots at every level g in [2, levels + 1]: attribute k's key
+// floor(fl32(v g)) at bit k * w of the word at key[(g - 2) * ccap + slot]. Keys are clamped to
+// the field's largest value 2^(w-1) - 1, which only the padding value 2.0 reaches (a value in
+// [0, 1] has keys of at most g <= 2^(w-1) - 2), so padding never dominates a target. Slots: the
+// segment's tiles [0, round_up(seg_cnt[0], 64)) and the store's last tile.
+template <int D>
+__global__ void __launch_bounds__(kBlock) level_keys_kernel(const float* __restrict__ cand, int64_t ccap,
+                                                             int32_t d_rt, const int32_t* __restrict__ seg_cnt,
+                                                             int32_t levels, int32_t w,
+                                                             uint64_t* __restrict__ key) {
+    constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    const int d = dget<D>(d_rt);
+    const int32_t body = (seg_cnt[0] + kTileC - 1) / kTileC * kTileC;
+    const int32_t total = body + kTileC;
+    const uint32_t kmax = (1u << (w - 1)) - 1u;
+    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
+        const int64_t slot = i < body ? (int64_t)i : ccap - kTileC + (i - body);
+        float v[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) v[k] = cand[(int64_t)k * ccap + slot];
+        for (int32_t l = 0; l < levels; ++l) {
+            const float fg = (float)(l + 2);
+            uint64_t kv = 0;
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                if (k < d) {
+                    uint32_t q = (uint32_t)floorf(__fmul_rn(v[k], fg));
+                    q = q < kmax ? q : kmax;
+                    kv |= (uint64_t)q << (k * w);
+                }
+            key[(int64_t)l * ccap + slot] = kv;
+        }
+    }
+}
+
 // largest j in [0, cnt) with off[j] <= q (off non-decreasing; empty segments share their offset
 // with the next one, so the search lands on the segment that holds q)
 __device__ __forceinline__ int32_t find_seg(const int32_t* __restrict__ off, int32_t cnt, int64_t q) {
@@ -587,7 +623,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     int32_t lds_floats, int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests,
     int32_t nblk, int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
     int32_t* __restrict__ work, const int32_t* __restrict__ params, const int32_t* __restrict__ tseg,
-    const int32_t* __restrict__ tord) {
+    const int32_t* __restrict__ tord, const uint64_t* __restrict__ lkey, int32_t kw) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     if (params) {  // target count and mapping decided on the device
@@ -598,6 +634,10 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const uint32_t padslot = (uint32_t)(ccap - kTileC);
+    // packed keys: the guard bit of every field
+    uint64_t guard = 0;
+    if (lkey)
+        for (int k = 0; k < d; ++k) guard |= 1ull << (k * kw + kw - 1);
     // a segment's place in the store (and whether its boxes fit in LDS)
     struct Seg { uint32_t coff; int32_t ntile, nchunk; uint32_t t0; bool use_lds; };
     auto seg_at = [&](int32_t sg, bool lds_ok) -> Seg {
@@ -671,13 +711,19 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             const float fg = (float)g;
             // key(v) <= key(t) <=> fl(v g) < key(t) + 1;  key(v) < key(t) <=> fl(v g) < key(t)
             float tle[DM], tlt[DM];
+            uint64_t tk = 0;  // t's packed keys
 #pragma unroll
             for (int k = 0; k < DM; ++k)
                 if (k < d) {
                     const float kt = floorf(__fmul_rn(tv[k], fg));
                     tlt[k] = kt;
                     tle[k] = kt + 1.0f;
+                    tk |= (uint64_t)(uint32_t)kt << (k * kw);
                 }
+            // (t | guard) - s: no field borrows (t's field plus the guard bit exceeds s's field),
+            // and a field keeps its guard bit exactly when s's key <= t's key
+            const uint64_t tg = tk | guard;
+            const uint64_t* krow = lkey ? lkey + (int64_t)(g - 2) * ccap : nullptr;
             bool found = false;
             uint64_t cmask;
             if (use_lds) {
@@ -733,25 +779,34 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
                                 ntests += kTileC;
                             }
                         }
-                        float sv[kBatch][DM];
-#pragma unroll
-                        for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-                            for (int k = 0; k < DM; ++k)
-                                if (k < d) sv[b][k] = ldf(cand + k * ccap, jb[b]);
                         bool dom = false;
+                        if (krow) {
+                            uint64_t kv[kBatch];
 #pragma unroll
-                        for (int b = 0; b < kBatch; ++b) {
-                            // padding candidates hold 2.0: never below t's keys
-                            bool le = true, lt = false;
+                            for (int b = 0; b < kBatch; ++b) kv[b] = krow[jb[b]];
 #pragma unroll
-                            for (int k = 0; k < DM; ++k)
-                                if (k < d) {
-                                    const float p = __fmul_rn(sv[b][k], fg);
-                                    le &= p < tle[k];
-                                    lt |= p < tlt[k];
-                                }
-                            dom |= le && lt;
+                            for (int b = 0; b < kBatch; ++b)
+                                dom |= ((tg - kv[b]) & guard) == guard && kv[b] != tk;
+                        } else {
+                            float sv[kBatch][DM];
+#pragma unroll
+                            for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+                                for (int k = 0; k < DM; ++k)
+                                    if (k < d) sv[b][k] = ldf(cand + k * ccap, jb[b]);
+#pragma unroll
+                            for (int b = 0; b < kBatch; ++b) {
+                                // padding candidates hold 2.0: never below t's keys
+                                bool le = true, lt = false;
+#pragma unroll
+                                for (int k = 0; k < DM; ++k)
+                                    if (k < d) {
+                                        const float p = __fmul_rn(sv[b][k], fg);
+                                        le &= p < tle[k];
+                                        lt |= p < tlt[k];
+                                    }
+                                dom |= le && lt;
+                            }
                         }
                         if (__ballot(dom)) { found = true; break; }
                     }
@@ -1116,6 +1171,20 @@ void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d) {
     t.params = c.take<int32_t>(16);
 }
 
+int32_t key_width(int32_t d, int32_t g_max) {
+    if (g_max < 2 || g_max > kKeyTableMaxG) return 0;
+    // keys 0..g_max and the clamp value 2^(w-1) - 1 above them: w - 1 = bit length of g_max + 1
+    int32_t b = 0;
+    while ((1 << b) <= g_max + 1) ++b;
+    const int32_t w = b + 1;
+    return d * w <= 64 ? w : 0;
+}
+
+void carve_gres_keys(Carver& c, GresKeys& k, int64_t ccap, int32_t d, int32_t g_max) {
+    k.width = key_width(d, g_max);
+    k.key = k.width ? c.take<uint64_t>((size_t)((int64_t)(g_max - 1) * ccap)) : nullptr;
+}
+
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t s64, const GresStore& store, const GresPrepTmp& tmp,
                                int32_t* dev_status, hipStream_t st) {
@@ -1254,7 +1323,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                               const GresTargets& tg, int64_t nt64, const int32_t* nt_dev, const int32_t* tseg,
                               const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
-                              unsigned long long* dev_tests, hipStream_t st) {
+                              unsigned long long* dev_tests, hipStream_t st, const GresKeys* keys) {
     const int32_t nt = (int32_t)nt64;  // with a count on the device: an upper bound of it
     if (nt <= 0) return SKY_OK;
     const bool batch = tseg != nullptr;
@@ -1338,6 +1407,18 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                            st, work, kWorkCounters * kCounterStride, 0);
         SKY_HIP(hipGetLastError());
     }
+    // packed keys of the one segment at every level, when carved for this g_max
+    const uint64_t* lkey = nullptr;
+    int32_t kw = 0;
+    if (run_tiles && !batch && keys && keys->key && keys->width == key_width(d, g_max)) {
+        const int64_t kb = ceil_div(round_up(max_cnt, kTileC) + kTileC, kBlock);
+        SKY_DISPATCH_D(d, level_keys_kernel, dim3((uint32_t)(kb > 2048 ? 2048 : kb)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, d, (const int32_t*)store.seg_cnt, g_max - 1,
+                       keys->width, keys->key);
+        SKY_HIP(hipGetLastError());
+        lkey = keys->key;
+        kw = keys->width;
+    }
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (run_levels) {
         SKY_DISPATCH_D(d, gres_levels_kernel, dim3(lgrid), dim3(kGresBlock), 0, st,
@@ -1355,7 +1436,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, per_wg, g_max, (int32_t)floats, tg.ge,
                        dev_tests, (int32_t)blocks, band_len, gstart, nbands, work, (const int32_t*)params,
-                       tseg, tord);
+                       tseg, tord, lkey, kw);
         SKY_HIP(hipGetLastError());
     }
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

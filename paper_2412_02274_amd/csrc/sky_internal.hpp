@@ -378,6 +378,18 @@ struct GresTargets {
     int32_t* params;               // [16] the search's shape when its target count is on the device
 };
 void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg);
+// Keys of every candidate slot at every level g in [2, g_max], packed into one 64-bit word per
+// (level, slot): attribute k's key in a field of `width` bits at bit k * width, the field's top
+// bit clear (a guard bit for the dominance test's subtraction). Taken only when the fields hold
+// every key (g_max <= kKeyTableMaxG, d * width <= 64); key == nullptr otherwise.
+constexpr int32_t kKeyTableMaxG = 64;
+struct GresKeys {
+    uint64_t* key = nullptr;       // [g_max - 1][ccap], level g at row g - 2
+    int32_t width = 0;
+};
+// field width for g_max (0: the keys of d attributes do not fit one word)
+int32_t key_width(int32_t d, int32_t g_max);
+void carve_gres_keys(Carver& c, GresKeys& k, int64_t ccap, int32_t d, int32_t g_max);
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);
 void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d);
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -424,11 +436,14 @@ __host__ __device__ inline int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
 // One segment of max_cnt candidates, nt targets. nt_dev: the target count is min(*nt_dev, nt)
 // on the device, nt being an upper bound; the mapping (AUTO included) and the work split are then
 // decided on the device. tseg (a batch): every target q of segment tseg[q] (in the order tord,
-// when given) as persistent work, with tg.params already holding the count and shape.
+// when given) as persistent work, with tg.params already holding the count and shape. keys (one
+// segment, key != nullptr, carved for this g_max): the tile search tests candidates on packed
+// keys, built here for the segment's slots.
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
                               const GresTargets& tg, int64_t nt, const int32_t* nt_dev, const int32_t* tseg,
                               const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
-                              unsigned long long* dev_tests, hipStream_t st);
+                              unsigned long long* dev_tests, hipStream_t st,
+                              const GresKeys* keys = nullptr);
 
 }  // namespace sky

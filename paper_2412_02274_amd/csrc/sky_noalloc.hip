@@ -45,13 +45,16 @@ extern "C" sky_status gres_compute_noalloc(const float* x_soa, int64_t n, int32_
         return SKY_ERR_INVALID_ARG;
     if (s == 0) return gres_compute(x_soa, n, d, ld, sky_idx, s, g_max, g_exit, gres, nullptr, 0,
                                     dev_status, opts, stream);
-    const size_t need = gres_workspace_bytes(s, d, g_max);
+    // the packed key table of the tile search when it fits beside the rest, else without it
+    const size_t need = sky::gres_ws_bytes(s, d, g_max, false);
     if (need == 0) return SKY_ERR_INVALID_ARG;
     if (need > (size_t)SKY_NOALLOC_SCRATCH_BYTES) return SKY_ERR_UNSUPPORTED;
+    const bool keys = sky::gres_ws_bytes(s, d, g_max, true) <= (size_t)SKY_NOALLOC_SCRATCH_BYTES;
     void* ws = nullptr;
     SKY_TRY(scratch_of_current_device(&ws));
     // gres_compute writes every workspace word it reads (the search's work counters are
-    // cleared by a kernel before each launch), so the previous call's contents do not matter
-    return gres_compute(x_soa, n, d, ld, sky_idx, s, g_max, g_exit, gres, ws,
-                        (size_t)SKY_NOALLOC_SCRATCH_BYTES, dev_status, opts, stream);
+    // cleared by a kernel before each launch, the key table is rebuilt by every search), so the
+    // previous call's contents do not matter
+    return sky::gres_compute_ws(x_soa, n, d, ld, sky_idx, s, g_max, g_exit, gres, ws,
+                                (size_t)SKY_NOALLOC_SCRATCH_BYTES, keys, dev_status, opts, (hipStream_t)stream);
 }

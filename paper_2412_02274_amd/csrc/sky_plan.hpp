@@ -80,4 +80,13 @@ sky_status plan_local_phase(sky_plan* P, hipStream_t st);
 sky_status plan_final_phase(sky_plan* P, int64_t* sky_idx, int64_t cap, int64_t* dev_count, uint8_t* member,
                             hipStream_t st);
 
+// gres options: the mapping (AUTO when opts is null); rejects unknown values and a lone event
+sky_status check_opts(const sky_gres_opts* opts, int32_t* mapping);
+// gres_compute's workspace and body; with_keys: also the packed key table of the tile search
+// (taken when g_max and d allow it), which gres_compute always asks for
+size_t gres_ws_bytes(int64_t s, int32_t d, int32_t g_max, bool with_keys);
+sky_status gres_compute_ws(const float* x_soa, int64_t n, int32_t d, int64_t ld, const int64_t* sky_idx,
+                           int64_t s, int32_t g_max, int32_t* g_exit, float* gres, void* ws, size_t ws_bytes,
+                           bool with_keys, int32_t* dev_status, const sky_gres_opts* opts, hipStream_t st);
+
 }  // namespace sky

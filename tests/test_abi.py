@@ -155,12 +155,15 @@ def test_gres_noalloc_limits(lib):
     # device call, and checks its arguments like gres_compute
     fake = C.c_void_p(0x1000)  # never dereferenced: the checks come first
     assert _lib.SKY_NOALLOC_SCRATCH_BYTES == 64 << 20
+    # the limit is the workspace without the packed key table (none above g_max 64)
+    assert lib.gres_workspace_bytes(1000, 6, 25) > lib.gres_workspace_bytes(1000, 6, 65)
+    assert lib.gres_workspace_bytes(1000, 6, 65) == lib.gres_workspace_bytes(1000, 6, 1 << 20)
     s_fit, s_over = 1, 1
-    while lib.gres_workspace_bytes(s_over, 6, 25) <= _lib.SKY_NOALLOC_SCRATCH_BYTES:
+    while lib.gres_workspace_bytes(s_over, 6, 65) <= _lib.SKY_NOALLOC_SCRATCH_BYTES:
         s_fit, s_over = s_over, s_over * 2
     while s_over - s_fit > 1:
         mid = (s_fit + s_over) // 2
-        if lib.gres_workspace_bytes(mid, 6, 25) <= _lib.SKY_NOALLOC_SCRATCH_BYTES:
+        if lib.gres_workspace_bytes(mid, 6, 65) <= _lib.SKY_NOALLOC_SCRATCH_BYTES:
             s_fit = mid
         else:
             s_over = mid
