@@ -402,7 +402,7 @@ void carve_gres_compute(Carver& c, GresStore& store, GresPrepTmp& tmp, GresTarge
     carve_gres_store(c, store, s, d, 1);
     carve_gres_prep_tmp(c, tmp, s);
     carve_gres_targets(c, tg, s, d);
-    if (with_keys) carve_gres_keys(c, keys, store.ccap, d, g_max);
+    if (with_keys) carve_gres_keys(c, keys, store, d, g_max);
 }
 
 }  // namespace

@@ -48,7 +48,8 @@ namespace {
 constexpr int kTileC = 64;               // candidates per tile
 constexpr int kGresBlock = 512;          // threads per workgroup of the search kernels
 constexpr int kWaves = kGresBlock / kWave;
-constexpr int kBatch = 2;                // candidate tiles fetched per round trip (measured best)
+constexpr int kBatch = 4;                // candidate tiles fetched per round trip (measured best)
+constexpr int kChunkBatch = 4;           // chunks' tile boxes fetched per round trip (packed keys)
 constexpr int kGresLdsBytes = 64 * 1024; // tile boxes cached in LDS when they fit
 constexpr float kPadValue = 2.0f;
 constexpr int kBandLevels = 6;           // levels per band of the TILES search
@@ -186,39 +187,84 @@ __global__ void __launch_bounds__(kBlock) tile_box_kernel(const float* __restric
     }
 }
 
-// Packed keys of one segment's slots at every level g in [2, levels + 1]: attribute k's key
-// floor(fl32(v g)) at bit k * w of the word at key[(g - 2) * ccap + slot]. Keys are clamped to
-// the field's largest value 2^(w-1) - 1, which only the padding value 2.0 reaches (a value in
-// [0, 1] has keys of at most g <= 2^(w-1) - 2), so padding never dominates a target. Slots: the
-// segment's tiles [0, round_up(seg_cnt[0], 64)) and the store's last tile.
+// Packed keys at every level g in [2, levels + 1]: attribute k's key floor(fl32(v g)) at bit
+// k * w of one 64-bit word. Keys are clamped to the field's largest value 2^(w-1) - 1, which
+// only the padding value 2.0 reaches (a value in [0, 1) has keys of at most g <= 2^(w-1) - 2),
+// so padding never dominates a target.
+template <int D>
+__device__ __forceinline__ uint64_t pack_keys(const float* v, int d, float fg, int w, uint32_t kmax) {
+    constexpr int DM = D > 0 ? D : SKY_MAX_D;
+    uint64_t kv = 0;
+#pragma unroll
+    for (int k = 0; k < DM; ++k)
+        if (k < d) {
+            uint32_t q = (uint32_t)floorf(__fmul_rn(v[k], fg));
+            q = q < kmax ? q : kmax;
+            kv |= (uint64_t)q << (k * w);
+        }
+    return kv;
+}
+
+// The key tables of one segment (the store's only one), every level:
+//  * blocks [0, cblocks): candidate slots [0, round_up(seg_cnt[0], 64)) and the store's last
+//    tile, key[(g - 2) * ccap + slot];
+//  * blocks from cblocks: one wave per 64 tiles; lane = tile: the packed corners of its box
+//    (tiles past the segment's last get padding corners), tile[(g - 2) * tcap + tile], and, from
+//    the wave's minimum of the lower corners, chunk[(g - 2) * (tcap / 64) + chunk].
 template <int D>
 __global__ void __launch_bounds__(kBlock) level_keys_kernel(const float* __restrict__ cand, int64_t ccap,
+                                                             const float* __restrict__ lo,
+                                                             const float* __restrict__ hi, int64_t tcap,
                                                              int32_t d_rt, const int32_t* __restrict__ seg_cnt,
-                                                             int32_t levels, int32_t w,
-                                                             uint64_t* __restrict__ key) {
+                                                             int32_t levels, int32_t w, int32_t cblocks,
+                                                             uint64_t* __restrict__ key, uint4* __restrict__ tile,
+                                                             uint64_t* __restrict__ chunk) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     const int d = dget<D>(d_rt);
-    const int32_t body = (seg_cnt[0] + kTileC - 1) / kTileC * kTileC;
-    const int32_t total = body + kTileC;
     const uint32_t kmax = (1u << (w - 1)) - 1u;
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += gridDim.x * kBlock) {
-        const int64_t slot = i < body ? (int64_t)i : ccap - kTileC + (i - body);
-        float v[DM];
-#pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k < d) v[k] = cand[(int64_t)k * ccap + slot];
-        for (int32_t l = 0; l < levels; ++l) {
-            const float fg = (float)(l + 2);
-            uint64_t kv = 0;
+    const int32_t cnt = seg_cnt[0];
+    if ((int32_t)blockIdx.x < cblocks) {
+        const int32_t body = (cnt + kTileC - 1) / kTileC * kTileC;
+        const int32_t total = body + kTileC;
+        for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += cblocks * kBlock) {
+            const int64_t slot = i < body ? (int64_t)i : ccap - kTileC + (i - body);
+            float v[DM];
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d) {
-                    uint32_t q = (uint32_t)floorf(__fmul_rn(v[k], fg));
-                    q = q < kmax ? q : kmax;
-                    kv |= (uint64_t)q << (k * w);
-                }
-            key[(int64_t)l * ccap + slot] = kv;
+                if (k < d) v[k] = cand[(int64_t)k * ccap + slot];
+            for (int32_t l = 0; l < levels; ++l)
+                key[(int64_t)l * ccap + slot] = pack_keys<D>(v, d, (float)(l + 2), w, kmax);
         }
+        return;
+    }
+    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
+    const int32_t nchunk = (ntile + kWave - 1) / kWave;
+    const int64_t cstride = tcap / kWave;
+    const int lane = (int)lane_id();
+    const int32_t wpb = kBlock / kWave;
+    for (int32_t c = ((int32_t)blockIdx.x - cblocks) * wpb + (int32_t)(threadIdx.x / kWave); c < nchunk;
+         c += ((int32_t)gridDim.x - cblocks) * wpb) {
+        const int32_t t = c * kWave + lane;
+        const bool real = t < ntile;
+        float vl[DM], vh[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) {
+                vl[k] = real ? lo[(int64_t)k * tcap + t] : kPadValue;
+                vh[k] = real ? hi[(int64_t)k * tcap + t] : kPadValue;
+            }
+        for (int32_t l = 0; l < levels; ++l) {
+            const float fg = (float)(l + 2);
+            const uint64_t a = pack_keys<D>(vl, d, fg, w, kmax), b = pack_keys<D>(vh, d, fg, w, kmax);
+            tile[(int64_t)l * tcap + t] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b,
+                                                     (uint32_t)(b >> 32));
+        }
+        // the chunk's lower corner
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d)
+                for (int off = kWave / 2; off > 0; off >>= 1) vl[k] = fminf(vl[k], __shfl_xor(vl[k], off, kWave));
+        if (lane < levels) chunk[(int64_t)lane * cstride + c] = pack_keys<D>(vl, d, (float)(lane + 2), w, kmax);
     }
 }
 
@@ -623,7 +669,8 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     int32_t lds_floats, int32_t* __restrict__ ge_out, unsigned long long* __restrict__ dev_tests,
     int32_t nblk, int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
     int32_t* __restrict__ work, const int32_t* __restrict__ params, const int32_t* __restrict__ tseg,
-    const int32_t* __restrict__ tord, const uint64_t* __restrict__ lkey, int32_t kw) {
+    const int32_t* __restrict__ tord, const uint64_t* __restrict__ lkey, const uint4* __restrict__ tkey,
+    const uint64_t* __restrict__ ckey, int32_t kw) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     if (params) {  // target count and mapping decided on the device
@@ -658,7 +705,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         if (w.t0 >= w.t1) return;  // uniform
     }
     // one segment: its boxes in LDS when they fit
-    const Seg sv0 = seg_at(0, tseg == nullptr);
+    const Seg sv0 = seg_at(0, tseg == nullptr && tkey == nullptr);
     float* blo = sbox;
     float* bhi = sbox + d * sv0.ntile;
     float* clo = sbox + 2 * d * sv0.ntile;
@@ -711,41 +758,35 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             const float fg = (float)g;
             // key(v) <= key(t) <=> fl(v g) < key(t) + 1;  key(v) < key(t) <=> fl(v g) < key(t)
             float tle[DM], tlt[DM];
-            uint64_t tk = 0;  // t's packed keys
 #pragma unroll
             for (int k = 0; k < DM; ++k)
                 if (k < d) {
                     const float kt = floorf(__fmul_rn(tv[k], fg));
                     tlt[k] = kt;
                     tle[k] = kt + 1.0f;
-                    tk |= (uint64_t)(uint32_t)kt << (k * kw);
                 }
-            // (t | guard) - s: no field borrows (t's field plus the guard bit exceeds s's field),
-            // and a field keeps its guard bit exactly when s's key <= t's key
-            const uint64_t tg = tk | guard;
-            const uint64_t* krow = lkey ? lkey + (int64_t)(g - 2) * ccap : nullptr;
             bool found = false;
-            uint64_t cmask;
-            if (use_lds) {
-                const bool inr = lane < nchunk;
-                const int32_t ci = inr ? lane : 0;
-                bool cp = inr;
-#pragma unroll
-                for (int k = 0; k < DM; ++k)
-                    if (k < d) cp &= __fmul_rn(clo[k * nchunk + ci], fg) < tle[k];
-                cmask = rotr64(__ballot(cp), my_chunk);
-            } else {
-                cmask = nchunk >= 64 ? ~0ull : ((1ull << nchunk) - 1ull);
-                cmask = rotr64(cmask, my_chunk % kWave);
-            }
+            // chunks [cbase, cbase + 64), the first group from the target's own chunk on: bit cb
+            // of the mask is chunk cbase + (cb + rot) mod 64
             for (int32_t cbase = 0; cbase < nchunk && !found; cbase += kWave) {
-                uint64_t cm = use_lds ? cmask : (cbase == 0 ? cmask : ~0ull);
+                const int rot = cbase == 0 ? my_chunk % kWave : 0;
+                uint64_t cm;
+                if (use_lds) {  // (one group: nchunk <= 64)
+                    const bool inr = lane < nchunk;
+                    const int32_t ci = inr ? lane : 0;
+                    bool cp = inr;
+#pragma unroll
+                    for (int k = 0; k < DM; ++k)
+                        if (k < d) cp &= __fmul_rn(clo[k * nchunk + ci], fg) < tle[k];
+                    cm = __ballot(cp);
+                } else {
+                    cm = nchunk - cbase >= kWave ? ~0ull : ((1ull << (nchunk - cbase)) - 1ull);
+                }
+                cm = rotr64(cm, rot);
                 while (cm && !found) {
                     const int cb = __ffsll((unsigned long long)cm) - 1;
                     cm &= cm - 1;
-                    // undo the rotation: bit cb of the rotated mask is chunk (cb + start) mod 64
-                    const int32_t c = use_lds ? (cb + my_chunk) % kWave
-                                              : (cbase == 0 ? (cb + my_chunk % kWave) % kWave : cbase + cb);
+                    const int32_t c = cbase + (cb + rot) % kWave;
                     if (c >= nchunk) continue;
                     const int32_t tile = c * kWave + lane;
                     const bool inr = tile < ntile;
@@ -779,44 +820,160 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
                                 ntests += kTileC;
                             }
                         }
+                        float sv[kBatch][DM];
+#pragma unroll
+                        for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+                            for (int k = 0; k < DM; ++k)
+                                if (k < d) sv[b][k] = ldf(cand + k * ccap, jb[b]);
                         bool dom = false;
-                        if (krow) {
-                            uint64_t kv[kBatch];
 #pragma unroll
-                            for (int b = 0; b < kBatch; ++b) kv[b] = krow[jb[b]];
+                        for (int b = 0; b < kBatch; ++b) {
+                            // padding candidates hold 2.0: never below t's keys
+                            bool le = true, lt = false;
 #pragma unroll
-                            for (int b = 0; b < kBatch; ++b)
-                                dom |= ((tg - kv[b]) & guard) == guard && kv[b] != tk;
-                        } else {
-                            float sv[kBatch][DM];
-#pragma unroll
-                            for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-                                for (int k = 0; k < DM; ++k)
-                                    if (k < d) sv[b][k] = ldf(cand + k * ccap, jb[b]);
-#pragma unroll
-                            for (int b = 0; b < kBatch; ++b) {
-                                // padding candidates hold 2.0: never below t's keys
-                                bool le = true, lt = false;
-#pragma unroll
-                                for (int k = 0; k < DM; ++k)
-                                    if (k < d) {
-                                        const float p = __fmul_rn(sv[b][k], fg);
-                                        le &= p < tle[k];
-                                        lt |= p < tlt[k];
-                                    }
-                                dom |= le && lt;
-                            }
+                            for (int k = 0; k < DM; ++k)
+                                if (k < d) {
+                                    const float p = __fmul_rn(sv[b][k], fg);
+                                    le &= p < tle[k];
+                                    lt |= p < tlt[k];
+                                }
+                            dom |= le && lt;
                         }
                         if (__ballot(dom)) { found = true; break; }
                     }
                 }
-                if (use_lds) break;  // all chunks were covered by the chunk mask
             }
             if (found) { result = g; break; }
             seen = seen_next;
         }
         // ge_out starts at 1 (no exit); each band raises it to its highest exit level
+        if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
+    };
+    // The same scan on the packed key tables (one segment, boxes from L2), arranged for few
+    // dependent round trips per level: the chunk keys, the target's own chunk's tile boxes and
+    // its own tile's candidates are loaded together, the other passing chunks' tile boxes
+    // kChunkBatch at a time, candidates kBatch tiles at a time.
+    auto search_keys = [&](const int32_t q, const int32_t band) {
+        const uint32_t coff = sv0.coff;
+        const int32_t ntile = sv0.ntile, nchunk = sv0.nchunk;
+        const uint32_t t0 = sv0.t0;
+        float tv[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) tv[k] = ldf(tval + k * tvcap, (uint32_t)q);
+        int32_t my_tile = thint[q];
+        my_tile = my_tile < 0 ? 0 : (my_tile >= ntile ? ntile - 1 : my_tile);
+        const int32_t my_chunk = my_tile / kWave;
+        const int r_own = my_tile % kWave;
+        int32_t result = 1;
+        int32_t seen = __hip_atomic_load(&ge_out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t gtop = g_max, blen = band_len;
+        if (gstart) {
+            gtop = gstart[q] < g_max ? gstart[q] : g_max;
+            blen = gtop > 2 ? (gtop - 2 + nbands) / nbands : 1;
+        }
+        const int32_t g_hi = gtop - band * blen;
+        const int32_t g_lo = g_hi - blen + 1 > 2 ? g_hi - blen + 1 : 2;
+        for (int32_t g = g_hi; g >= g_lo && ntile > 0; --g) {
+            if (seen >= g) break;
+            const int32_t seen_next =
+                __hip_atomic_load(&ge_out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const float fg = (float)g;
+            uint64_t tk = 0;  // t's packed keys
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                if (k < d) tk |= (uint64_t)(uint32_t)floorf(__fmul_rn(tv[k], fg)) << (k * kw);
+            // (t | guard) - s: no field borrows (t's field plus the guard bit exceeds s's field),
+            // and a field keeps its guard bit exactly when s's key <= t's key
+            const uint64_t tg = tk | guard;
+            auto keys_le = [&](uint64_t kv) { return ((tg - kv) & guard) == guard; };
+            const uint64_t* krow = lkey + (int64_t)(g - 2) * ccap;
+            const uint4* trow = tkey + (int64_t)(g - 2) * tcap + t0;
+            const uint64_t* crow = ckey + (int64_t)(g - 2) * (tcap / kWave) + t0 / kWave;
+            // candidates of kBatch passing tiles of chunk c per round trip (mask rotated by r)
+            auto test_tiles = [&](uint64_t mask, int32_t c, int r) -> bool {
+                while (mask) {
+                    uint32_t jb[kBatch];
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b) {
+                        jb[b] = padslot + (uint32_t)lane;
+                        if (mask) {
+                            const int tb = ((__ffsll((unsigned long long)mask) - 1) + r) % kWave;
+                            mask &= mask - 1;
+                            jb[b] = coff + (uint32_t)((c * kWave + tb) * kTileC + lane);
+                            ntests += kTileC;
+                        }
+                    }
+                    uint64_t kv[kBatch];
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b) kv[b] = krow[jb[b]];
+                    bool dom = false;
+#pragma unroll
+                    for (int b = 0; b < kBatch; ++b) dom |= keys_le(kv[b]) && kv[b] != tk;
+                    if (__ballot(dom)) return true;
+                }
+                return false;
+            };
+            // pass: the tile's lower corner's keys are all <= t's (some candidate may dominate);
+            // tdom: so are its upper corner's, one of them below t's (every candidate dominates)
+            auto tile_pass = [&](const uint4& b, bool inr, bool* tdom) {
+                const uint64_t kl = ((uint64_t)b.y << 32) | b.x, kh = ((uint64_t)b.w << 32) | b.z;
+                *tdom = inr && keys_le(kh) && kh != tk;
+                return inr && keys_le(kl);
+            };
+            // one round trip: the first 64 chunks' keys, the own chunk's boxes, the own tile
+            const bool c_in = lane < nchunk;
+            const uint64_t ck = crow[c_in ? lane : 0];
+            const int32_t own_t = my_chunk * kWave + lane;
+            const bool own_in = own_t < ntile;
+            const uint4 ob = trow[own_in ? own_t : 0];
+            const uint64_t okv = krow[coff + (uint32_t)my_tile * kTileC + lane];
+            ntests += kTileC;
+            bool found = __ballot(keys_le(okv) && okv != tk) != 0;
+            if (!found) {
+                bool tdom;
+                const bool pass = tile_pass(ob, own_in, &tdom);
+                found = __ballot(tdom) != 0 || test_tiles(rotr64(__ballot(pass), r_own) & ~1ull, my_chunk, r_own);
+            }
+            // the other chunks whose lower corner passes, from the one after the own chunk on
+            for (int32_t cbase = 0; cbase < nchunk && !found; cbase += kWave) {
+                uint64_t cm;
+                if (cbase == 0) {
+                    cm = __ballot(c_in && keys_le(ck));
+                } else {
+                    const int32_t ci = cbase + lane;
+                    cm = __ballot(ci < nchunk && keys_le(crow[ci < nchunk ? ci : 0]));
+                }
+                if (my_chunk >= cbase && my_chunk < cbase + kWave) cm &= ~(1ull << (my_chunk - cbase));
+                const int rot = my_chunk >= cbase && my_chunk < cbase + kWave ? my_chunk - cbase : 0;
+                cm = rotr64(cm, rot);
+                while (cm && !found) {
+                    // up to kChunkBatch chunks' tile boxes per round trip
+                    int32_t cs[kChunkBatch];
+                    uint4 bx[kChunkBatch];
+#pragma unroll
+                    for (int j = 0; j < kChunkBatch; ++j) {
+                        cs[j] = -1;
+                        if (cm) {
+                            cs[j] = cbase + ((__ffsll((unsigned long long)cm) - 1) + rot) % kWave;
+                            cm &= cm - 1;
+                        }
+                        const int32_t t = (cs[j] < 0 ? 0 : cs[j]) * kWave + lane;
+                        bx[j] = trow[t < ntile ? t : 0];
+                    }
+#pragma unroll
+                    for (int j = 0; j < kChunkBatch; ++j) {
+                        if (found || cs[j] < 0) continue;
+                        bool tdom;
+                        const bool pass = tile_pass(bx[j], cs[j] * kWave + lane < ntile, &tdom);
+                        found = __ballot(tdom) != 0 || test_tiles(__ballot(pass), cs[j], 0);
+                    }
+                }
+            }
+            if (found) { result = g; break; }
+            seen = seen_next;
+        }
         if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
     };
     if (work) {
@@ -838,6 +995,8 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             if (tseg) {
                 const int32_t q = tord ? tord[r] : r;
                 search(q, b, seg_at(tseg[q], false));
+            } else if (lkey) {
+                search_keys(r, b);
             } else {
                 search(r, b, sv0);
             }
@@ -852,7 +1011,8 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             if (lane == 0) q = atomicAdd(&next_q, 1);
             q = __builtin_amdgcn_readfirstlane(q);
             if (q >= w.t1) break;
-            search(q, band0, sv0);
+            if (lkey) search_keys(q, band0);
+            else search(q, band0, sv0);
         }
     }
     if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
@@ -1180,9 +1340,13 @@ int32_t key_width(int32_t d, int32_t g_max) {
     return d * w <= 64 ? w : 0;
 }
 
-void carve_gres_keys(Carver& c, GresKeys& k, int64_t ccap, int32_t d, int32_t g_max) {
+void carve_gres_keys(Carver& c, GresKeys& k, const GresStore& store, int32_t d, int32_t g_max) {
     k.width = key_width(d, g_max);
-    k.key = k.width ? c.take<uint64_t>((size_t)((int64_t)(g_max - 1) * ccap)) : nullptr;
+    if (!k.width) return;
+    const int64_t levels = g_max - 1;
+    k.key = c.take<uint64_t>((size_t)(levels * store.ccap));
+    k.tile = c.take<uint4>((size_t)(levels * store.tcap));
+    k.chunk = c.take<uint64_t>((size_t)(levels * (store.tcap / kWave)));
 }
 
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -1328,6 +1492,26 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     if (nt <= 0) return SKY_OK;
     const bool batch = tseg != nullptr;
     const bool on_dev = nt_dev || batch;
+    // packed keys of the one segment at every level, when carved for this g_max
+    const uint64_t* lkey = nullptr;
+    int32_t kw = 0;
+    const uint4* tkey = nullptr;
+    const uint64_t* ckey = nullptr;
+    if (mapping != SKY_GRES_LEVELS && !batch && keys && keys->key && keys->width == key_width(d, g_max)) {
+        const int64_t kb = ceil_div(round_up(max_cnt, kTileC) + kTileC, kBlock);
+        const int32_t cblocks = (int32_t)(kb > 2048 ? 2048 : kb);
+        const int64_t tb = ceil_div(ceil_div(ceil_div(max_cnt, kTileC), kWave), kBlock / kWave);
+        const int32_t tblocks = (int32_t)(tb < 1 ? 1 : (tb > 1024 ? 1024 : tb));
+        SKY_DISPATCH_D(d, level_keys_kernel, dim3((uint32_t)(cblocks + tblocks)), dim3(kBlock), 0, st,
+                       (const float*)store.cand, store.ccap, (const float*)store.lo, (const float*)store.hi,
+                       store.tcap, d, (const int32_t*)store.seg_cnt, g_max - 1, keys->width, cblocks, keys->key,
+                       keys->tile, keys->chunk);
+        SKY_HIP(hipGetLastError());
+        lkey = keys->key;
+        tkey = keys->tile;
+        ckey = keys->chunk;
+        kw = keys->width;
+    }
     // LDS for the tile boxes of the one segment, when they fit; with the count on the device,
     // a fixed 40 KB (the kernel checks the real size), which costs no occupancy at 8 waves per
     // SIMD; a batch reads every relation's boxes from L2
@@ -1336,7 +1520,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     int64_t floats = (int64_t)d * (2 * ntile + nchunk);
     if (floats * 4 > kGresLdsBytes || nchunk > kWave) floats = 0;
     if (nt_dev) floats = kGresLdsDevBytes / 4;
-    if (batch) floats = 0;
+    if (batch || tkey) floats = 0;  // (packed keys: the boxes are read from L2)
     const size_t lds = (size_t)floats * sizeof(float);
     int32_t per_wg = 0, lbands = 1, blocks = 0;
     search_shape(nt, g_max, &per_wg, &blocks, &lbands);
@@ -1407,18 +1591,6 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                            st, work, kWorkCounters * kCounterStride, 0);
         SKY_HIP(hipGetLastError());
     }
-    // packed keys of the one segment at every level, when carved for this g_max
-    const uint64_t* lkey = nullptr;
-    int32_t kw = 0;
-    if (run_tiles && !batch && keys && keys->key && keys->width == key_width(d, g_max)) {
-        const int64_t kb = ceil_div(round_up(max_cnt, kTileC) + kTileC, kBlock);
-        SKY_DISPATCH_D(d, level_keys_kernel, dim3((uint32_t)(kb > 2048 ? 2048 : kb)), dim3(kBlock), 0, st,
-                       (const float*)store.cand, store.ccap, d, (const int32_t*)store.seg_cnt, g_max - 1,
-                       keys->width, keys->key);
-        SKY_HIP(hipGetLastError());
-        lkey = keys->key;
-        kw = keys->width;
-    }
     if (ev_begin) SKY_HIP(hipEventRecord((hipEvent_t)ev_begin, st));
     if (run_levels) {
         SKY_DISPATCH_D(d, gres_levels_kernel, dim3(lgrid), dim3(kGresBlock), 0, st,
@@ -1436,7 +1608,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, per_wg, g_max, (int32_t)floats, tg.ge,
                        dev_tests, (int32_t)blocks, band_len, gstart, nbands, work, (const int32_t*)params,
-                       tseg, tord, lkey, kw);
+                       tseg, tord, lkey, tkey, ckey, kw);
         SKY_HIP(hipGetLastError());
     }
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

@@ -384,12 +384,14 @@ void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t ns
 // every key (g_max <= kKeyTableMaxG, d * width <= 64); key == nullptr otherwise.
 constexpr int32_t kKeyTableMaxG = 64;
 struct GresKeys {
-    uint64_t* key = nullptr;       // [g_max - 1][ccap], level g at row g - 2
+    uint64_t* key = nullptr;       // [g_max - 1][ccap] candidates, level g at row g - 2
+    uint4* tile = nullptr;         // [g_max - 1][tcap] tile boxes: lower corner (x, y), upper (z, w)
+    uint64_t* chunk = nullptr;     // [g_max - 1][tcap / 64] lower corner of every 64 tiles
     int32_t width = 0;
 };
 // field width for g_max (0: the keys of d attributes do not fit one word)
 int32_t key_width(int32_t d, int32_t g_max);
-void carve_gres_keys(Carver& c, GresKeys& k, int64_t ccap, int32_t d, int32_t g_max);
+void carve_gres_keys(Carver& c, GresKeys& k, const GresStore& store, int32_t d, int32_t g_max);
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);
 void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d);
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
