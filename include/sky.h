@@ -416,8 +416,8 @@ sky_status gres_search(const void* prep, int64_t s, int32_t d, const float* x_so
  * serves all of them (one segment per relation), and the gres search of all of their skyline
  * tuples is ONE persistent launch whose waves take (tuple, level band) pairs of any relation.
  *
- * Sequence: sky_batch_workspace_bytes -> sky_batch_create -> (sky_batch_tune) ->
- * sky_batch_skylines -> sky_batch_gres -> ... -> sky_batch_destroy. After sky_batch_create no
+ * Sequence: sky_batch_workspace_bytes -> sky_batch_create -> (sky_batch_tune,
+ * sky_batch_set_keys) -> sky_batch_skylines -> sky_batch_gres -> ... -> sky_batch_destroy. After sky_batch_create no
  * call synchronises or reads anything back (sky_batch_info aside): a step sky_batch_skylines +
  * sky_batch_gres, repeated on new values in x_soa, can be captured in one HIP graph and replayed.
  */
@@ -479,6 +479,26 @@ sky_status sky_batch_tune(sky_batch* batch, const sky_tune* tune, void* stream);
  */
 sky_status sky_batch_gres(sky_batch* batch, int32_t g_max, int32_t* g_exit, float* gres,
                           void* ev_begin, void* ev_end, void* stream);
+
+/*
+ * Workspace for the packed key tables of a batch's gres search (every candidate's keys at every
+ * level g in [2, g_max_keys], one 64-bit word per (level, candidate), plus the tile and chunk
+ * box corners), for skylines of up to sky_total tuples in all. Returns 0 when packed keys do
+ * not apply: g_max_keys above 64, or the batch's d keys too wide for one word (see
+ * gres_workspace_bytes), or invalid arguments.
+ */
+size_t sky_batch_keys_bytes(const sky_batch* batch, int64_t sky_total, int32_t g_max_keys);
+
+/*
+ * sky_batch_set_keys -- attaches a device workspace (caller-owned, at least
+ * sky_batch_keys_bytes(batch, sky_total, g_max_keys) bytes, kept until detached or the batch
+ * is destroyed) for the key tables; ws NULL detaches. Later sky_batch_gres calls with g_max <=
+ * g_max_keys then search on packed keys when the batch's skyline total fits sky_total (checked
+ * on the device; otherwise they search the values). The results are the same either way.
+ * Host-side only; SKY_ERR_WORKSPACE when ws_bytes is too small.
+ */
+sky_status sky_batch_set_keys(sky_batch* batch, void* ws, size_t ws_bytes, int64_t sky_total,
+                              int32_t g_max_keys);
 
 /*
  * sky_batch_info -- n = total rows, d, scheme = SKY_NONE, p = nbatch, max_partition = rows of

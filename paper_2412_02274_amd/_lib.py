@@ -42,7 +42,8 @@ EXPORTS = ("sky_status_string", "sky_version", "sky_ingest", "sky_build_workspac
            "gres_workspace_bytes", "gres_compute", "gres_prepare_bytes", "gres_prepare",
            "gres_search_bytes", "gres_search",
            "sky_batch_workspace_bytes", "sky_batch_create", "sky_batch_skylines", "sky_batch_tune",
-           "sky_batch_gres", "sky_batch_info", "sky_batch_destroy", "sky_project",
+           "sky_batch_gres", "sky_batch_keys_bytes", "sky_batch_set_keys", "sky_batch_info",
+           "sky_batch_destroy", "sky_project",
            "gres_gbar_workspace_bytes", "gres_gbar", "sky_gres",
            "gres_compute_noalloc", "sky_literal_level", "sky_probe_valu", "sky_probe_copy")
 
@@ -125,6 +126,8 @@ def load():
         "sky_batch_skylines": (i32, [vp, vp, i64, vp, vp]),
         "sky_batch_tune": (i32, [vp, C.POINTER(SkyTune), vp]),
         "sky_batch_gres": (i32, [vp, i32, vp, vp, vp, vp, vp]),
+        "sky_batch_keys_bytes": (sz, [vp, i64, i32]),
+        "sky_batch_set_keys": (i32, [vp, vp, sz, i64, i32]),
         "sky_batch_info": (i32, [vp, C.POINTER(SkyInfo)]),
         "sky_batch_destroy": (None, [vp]),
         "sky_project": (i32, [vp, i64, i32, i64, vp, i64, i32, vp, i64, vp, vp]),

@@ -8,9 +8,11 @@ include/sky.h); argument marshalling, packing and scheduling only.
 Relations are grouped by d. Each group is one ``sky_batch``: its rows packed one relation after
 the other in one device buffer, every relation's skyline computed by the same rounds of the
 segmented engine, then the gres of every skyline tuple (Def. 2 via Alg. 1, with the relation's
-own skyline as candidates) in one persistent search launch per group. A step -- ingest,
-skylines and gres of every group -- reads nothing back, so it is captured once in a HIP graph
-and replayed. ``GresTuner`` picks each group's search choices (mapping, tile order, relation
+own skyline as candidates) in one persistent search launch per group. After the first step
+each group gets packed key tables sized by its skyline total (``sky_batch_set_keys``; a later
+skyline that outgrows them is searched on the values, with the same results). A step --
+ingest, skylines and gres of every group -- reads nothing back, so it is captured once in a HIP
+graph and replayed. ``GresTuner`` picks each group's search choices (mapping, tile order, relation
 order) by timing them on the group itself; results never depend on the choice.
 
 ``PlainRunner`` is the one-relation-at-a-time path over the plain entry points (ingest, build,
@@ -99,6 +101,21 @@ class BatchGroup:
         self.tune = tune
         if self.h is not None:
             _lib.check(_lib.load().sky_batch_tune(self.h, C.byref(tune), None), "sky_batch_tune")
+
+    def attach_keys(self, sky_total=None):
+        """Packed key tables for the gres search (sky_batch_set_keys), sized for a skyline total
+        of sky_total tuples (default: the last pass's, read back); nothing when they do not
+        apply to this group's d and g_max."""
+        if self.h is None:
+            return
+        lib = _lib.load()
+        total = self.sky_count if sky_total is None else int(sky_total)
+        nb = int(lib.sky_batch_keys_bytes(self.h, total, self.g_max))
+        if nb == 0:
+            return
+        self.keys_ws = torch.empty(nb, dtype=torch.uint8, device=self.x_soa.device)
+        _lib.check(lib.sky_batch_set_keys(self.h, _ptr(self.keys_ws), nb, total, self.g_max),
+                   "sky_batch_set_keys")
 
     def launch_gres(self, stream, ev_begin=None, ev_end=None):
         if self.h is None:
@@ -200,9 +217,10 @@ class BatchRunner:
     is eager (and tunes the groups when a tuner is given); with use_graph, that step is then
     captured once and every later run replays it."""
 
-    def __init__(self, datasets, g_max=25, device="cuda", tuner=None, use_graph=True):
+    def __init__(self, datasets, g_max=25, device="cuda", tuner=None, use_graph=True, keys=True):
         self.device = torch.device(device)
         self.g_max = int(g_max)
+        self.keys = keys
         self.sizes = [(int(x.shape[0]), int(x.shape[1])) for x in datasets]
         self.groups = [BatchGroup(datasets, mem, self.device, g_max)
                        for mem in pack_by_d(datasets).values()]
@@ -243,11 +261,19 @@ class BatchRunner:
             else:
                 self._step(st, e1)
             e2.record(st)
+            again = False
+            if self.graph is None and self.keys:
+                st.synchronize()
+                for g in self.groups:  # key tables sized by the skylines just computed
+                    g.attach_keys()
+                again = True
             if self.graph is None and tune and self.tuner is not None:
                 for g in self.groups:
                     if g.h is not None and g.sky_count:
                         g.set_tune(self.tuner.choose(g, st))
-                for g in self.groups:  # the results of the tuned choices
+                again = True
+            if again:
+                for g in self.groups:  # the results of the search every later step runs
                     g.launch_gres(st)
             if self.graph is None and self.use_graph:
                 self._capture()

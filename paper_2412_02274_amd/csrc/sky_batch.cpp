@@ -40,6 +40,9 @@ struct sky_batch {
     int32_t near_first = 1;
     int32_t lpt = 1;
     sky_info info{};
+    // packed key tables of the gres search (sky_batch_set_keys), caller-owned
+    GresKeys keys{};
+    int32_t keys_g_max = 0;
 };
 
 namespace {
@@ -64,6 +67,17 @@ void carve_batch_tail(Carver& c, sky_batch* B, int64_t s, int32_t d, int32_t nba
     carve_gres_store(c, B->store, s, d, nbatch);
     carve_gres_prep_tmp(c, B->tmp, s);
     carve_gres_targets(c, B->tg, s, d);
+}
+
+// candidate slots of the key tables for skylines of up to sky_total tuples over nbatch
+// relations: every relation's skyline rounded up to whole tiles, and the padding tile
+int64_t key_slots(int64_t sky_total, int32_t nbatch) {
+    constexpr int64_t tile = 64;  // candidates per tile of the gres store
+    return sky_total + (tile - 1) * nbatch + tile;
+}
+
+void carve_batch_keys(Carver& c, GresKeys& k, int64_t sky_total, int32_t nbatch, int32_t g_max) {
+    carve_gres_keys_slots(c, k, key_slots(sky_total, nbatch), g_max - 1);
 }
 
 size_t tail_bytes(int64_t s, int32_t d, int32_t nbatch) {
@@ -171,7 +185,36 @@ sky_status sky_batch_gres(sky_batch* B, int32_t g_max, int32_t* g_exit, float* g
                            (hipStream_t)stream));
     return launch_batch_search(B->store, B->d, B->cap, B->cand_off, B->nbatch, B->used, B->near_first != 0,
                                B->lpt != 0, B->order, B->rank_off, B->tord, B->tseg, B->tg, g_max, B->mapping,
-                               g_exit, gres, ev_begin, ev_end, B->gtests, (hipStream_t)stream);
+                               g_exit, gres, ev_begin, ev_end, B->gtests, (hipStream_t)stream,
+                               B->keys.key && g_max <= B->keys_g_max ? &B->keys : nullptr);
+}
+
+size_t sky_batch_keys_bytes(const sky_batch* B, int64_t sky_total, int32_t g_max_keys) {
+    if (!B || sky_total < 0 || sky_total > kMaxBuildRows || !key_width(B->d, g_max_keys)) return 0;
+    Carver c(nullptr, 0);
+    GresKeys k{};
+    carve_batch_keys(c, k, sky_total, B->nbatch, g_max_keys);
+    return c.used;
+}
+
+sky_status sky_batch_set_keys(sky_batch* B, void* ws, size_t ws_bytes, int64_t sky_total, int32_t g_max_keys) {
+    if (!B) return SKY_ERR_INVALID_ARG;
+    if (!ws) {  // detach
+        B->keys = GresKeys{};
+        B->keys_g_max = 0;
+        return SKY_OK;
+    }
+    const size_t need = sky_batch_keys_bytes(B, sky_total, g_max_keys);
+    if (need == 0) return SKY_ERR_INVALID_ARG;
+    if (ws_bytes < need) return SKY_ERR_WORKSPACE;
+    Carver c(ws, ws_bytes);
+    GresKeys k{};
+    carve_batch_keys(c, k, sky_total, B->nbatch, g_max_keys);
+    if (c.overflow) return SKY_ERR_WORKSPACE;
+    k.used = B->used;
+    B->keys = k;
+    B->keys_g_max = g_max_keys;
+    return SKY_OK;
 }
 
 sky_status sky_batch_info(const sky_batch* B, sky_info* out) {

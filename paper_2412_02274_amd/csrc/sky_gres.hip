@@ -205,66 +205,84 @@ __device__ __forceinline__ uint64_t pack_keys(const float* v, int d, float fg, i
     return kv;
 }
 
-// The key tables of one segment (the store's only one), every level:
-//  * blocks [0, cblocks): candidate slots [0, round_up(seg_cnt[0], 64)) and the store's last
-//    tile, key[(g - 2) * ccap + slot];
-//  * blocks from cblocks: one wave per 64 tiles; lane = tile: the packed corners of its box
-//    (tiles past the segment's last get padding corners), tile[(g - 2) * tcap + tile], and, from
-//    the wave's minimum of the lower corners, chunk[(g - 2) * (tcap / 64) + chunk].
+// The key tables of a store, every level, when its slots in use (used[0], or the first
+// segment's tiles when used is null) fit them (*ok, written by workgroup 0; nothing else is
+// written otherwise):
+//  * blocks [0, cblocks): candidate slots [0, used) from the store, and the padding tile
+//    [kslots - 64, kslots) (the clamp value in every field), key[(g - 2) * kslots + slot];
+//  * blocks [cblocks, cblocks + tblocks): one thread per tile in use, its packed box corners,
+//    tile[(g - 2) * ktiles + tile];
+//  * the other blocks: one wave per segment, for each chunk of 64 tiles from the segment's first
+//    tile, the packed minimum of their lower corners at chunk[(g - 2) * ktiles + first tile].
 template <int D>
-__global__ void __launch_bounds__(kBlock) level_keys_kernel(const float* __restrict__ cand, int64_t ccap,
-                                                             const float* __restrict__ lo,
-                                                             const float* __restrict__ hi, int64_t tcap,
-                                                             int32_t d_rt, const int32_t* __restrict__ seg_cnt,
-                                                             int32_t levels, int32_t w, int32_t cblocks,
-                                                             uint64_t* __restrict__ key, uint4* __restrict__ tile,
-                                                             uint64_t* __restrict__ chunk) {
+__global__ void __launch_bounds__(kBlock) level_keys_kernel(
+    const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo, const float* __restrict__ hi,
+    int64_t tcap, int32_t d_rt, const int32_t* __restrict__ seg_coff, const int32_t* __restrict__ seg_cnt,
+    int32_t nseg, const int32_t* __restrict__ used_dev, int32_t levels, int32_t w, int32_t cblocks,
+    int32_t tblocks, uint64_t* __restrict__ key, int64_t kslots, uint4* __restrict__ tile,
+    uint64_t* __restrict__ chunk, int64_t ktiles, int32_t* __restrict__ ok) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     const int d = dget<D>(d_rt);
     const uint32_t kmax = (1u << (w - 1)) - 1u;
-    const int32_t cnt = seg_cnt[0];
-    if ((int32_t)blockIdx.x < cblocks) {
-        const int32_t body = (cnt + kTileC - 1) / kTileC * kTileC;
-        const int32_t total = body + kTileC;
-        for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < total; i += cblocks * kBlock) {
-            const int64_t slot = i < body ? (int64_t)i : ccap - kTileC + (i - body);
+    const int64_t used = used_dev ? (int64_t)used_dev[0] : (int64_t)(seg_cnt[0] + kTileC - 1) / kTileC * kTileC;
+    const int64_t ntl = used / kTileC;  // tiles in use
+    const bool fits = used + kTileC <= kslots && ntl <= ktiles;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ok = fits ? 1 : 0;
+    if (!fits) return;
+    const int32_t b = (int32_t)blockIdx.x;
+    if (b < cblocks) {
+        for (int64_t i = (int64_t)b * kBlock + threadIdx.x; i < used + kTileC; i += (int64_t)cblocks * kBlock) {
+            if (i >= used) {  // padding: above every key of a target
+                uint64_t pad = 0;
+                for (int k = 0; k < d; ++k) pad |= (uint64_t)kmax << (k * w);
+                for (int32_t l = 0; l < levels; ++l) key[(int64_t)l * kslots + kslots - kTileC + (i - used)] = pad;
+                continue;
+            }
             float v[DM];
 #pragma unroll
             for (int k = 0; k < DM; ++k)
-                if (k < d) v[k] = cand[(int64_t)k * ccap + slot];
+                if (k < d) v[k] = cand[(int64_t)k * ccap + i];
             for (int32_t l = 0; l < levels; ++l)
-                key[(int64_t)l * ccap + slot] = pack_keys<D>(v, d, (float)(l + 2), w, kmax);
+                key[(int64_t)l * kslots + i] = pack_keys<D>(v, d, (float)(l + 2), w, kmax);
         }
         return;
     }
-    const int32_t ntile = (cnt + kTileC - 1) / kTileC;
-    const int32_t nchunk = (ntile + kWave - 1) / kWave;
-    const int64_t cstride = tcap / kWave;
+    if (b < cblocks + tblocks) {
+        for (int64_t t = (int64_t)(b - cblocks) * kBlock + threadIdx.x; t < ntl; t += (int64_t)tblocks * kBlock) {
+            float vl[DM], vh[DM];
+#pragma unroll
+            for (int k = 0; k < DM; ++k)
+                if (k < d) {
+                    vl[k] = lo[(int64_t)k * tcap + t];
+                    vh[k] = hi[(int64_t)k * tcap + t];
+                }
+            for (int32_t l = 0; l < levels; ++l) {
+                const float fg = (float)(l + 2);
+                const uint64_t a = pack_keys<D>(vl, d, fg, w, kmax), h = pack_keys<D>(vh, d, fg, w, kmax);
+                tile[(int64_t)l * ktiles + t] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)h,
+                                                           (uint32_t)(h >> 32));
+            }
+        }
+        return;
+    }
     const int lane = (int)lane_id();
     const int32_t wpb = kBlock / kWave;
-    for (int32_t c = ((int32_t)blockIdx.x - cblocks) * wpb + (int32_t)(threadIdx.x / kWave); c < nchunk;
-         c += ((int32_t)gridDim.x - cblocks) * wpb) {
-        const int32_t t = c * kWave + lane;
-        const bool real = t < ntile;
-        float vl[DM], vh[DM];
+    const int32_t nwaves = ((int32_t)gridDim.x - cblocks - tblocks) * wpb;
+    for (int32_t sg = (b - cblocks - tblocks) * wpb + (int32_t)(threadIdx.x / kWave); sg < nseg; sg += nwaves) {
+        const int32_t t0 = seg_coff[sg] / kTileC;
+        const int32_t nts = (seg_cnt[sg] + kTileC - 1) / kTileC;
+        for (int32_t c0 = 0; c0 < nts; c0 += kWave) {
+            const bool real = c0 + lane < nts;
+            float vl[DM];
 #pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k < d) {
-                vl[k] = real ? lo[(int64_t)k * tcap + t] : kPadValue;
-                vh[k] = real ? hi[(int64_t)k * tcap + t] : kPadValue;
-            }
-        for (int32_t l = 0; l < levels; ++l) {
-            const float fg = (float)(l + 2);
-            const uint64_t a = pack_keys<D>(vl, d, fg, w, kmax), b = pack_keys<D>(vh, d, fg, w, kmax);
-            tile[(int64_t)l * tcap + t] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b,
-                                                     (uint32_t)(b >> 32));
+            for (int k = 0; k < DM; ++k)
+                if (k < d) {
+                    vl[k] = real ? lo[(int64_t)k * tcap + t0 + c0 + lane] : kPadValue;
+                    for (int off = kWave / 2; off > 0; off >>= 1) vl[k] = fminf(vl[k], __shfl_xor(vl[k], off, kWave));
+                }
+            if (lane < levels)
+                chunk[(int64_t)lane * ktiles + t0 + c0] = pack_keys<D>(vl, d, (float)(lane + 2), w, kmax);
         }
-        // the chunk's lower corner
-#pragma unroll
-        for (int k = 0; k < DM; ++k)
-            if (k < d)
-                for (int off = kWave / 2; off > 0; off >>= 1) vl[k] = fminf(vl[k], __shfl_xor(vl[k], off, kWave));
-        if (lane < levels) chunk[(int64_t)lane * cstride + c] = pack_keys<D>(vl, d, (float)(lane + 2), w, kmax);
     }
 }
 
@@ -670,7 +688,8 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     int32_t nblk, int32_t band_len, const int32_t* __restrict__ gstart, int32_t nbands,
     int32_t* __restrict__ work, const int32_t* __restrict__ params, const int32_t* __restrict__ tseg,
     const int32_t* __restrict__ tord, const uint64_t* __restrict__ lkey, const uint4* __restrict__ tkey,
-    const uint64_t* __restrict__ ckey, int32_t kw) {
+    const uint64_t* __restrict__ ckey, int32_t kw, const int32_t* __restrict__ kok, int64_t kslots,
+    int64_t ktiles) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
     extern __shared__ float sbox[];  // [d][ntile] lo, [d][ntile] hi, [d][nchunk] chunk lo
     if (params) {  // target count and mapping decided on the device
@@ -681,9 +700,10 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
     const uint32_t padslot = (uint32_t)(ccap - kTileC);
-    // packed keys: the guard bit of every field
+    // packed keys, when the store's slots fit the tables: the guard bit of every field
+    const bool use_keys = lkey && *kok;
     uint64_t guard = 0;
-    if (lkey)
+    if (use_keys)
         for (int k = 0; k < d; ++k) guard |= 1ull << (k * kw + kw - 1);
     // a segment's place in the store (and whether its boxes fit in LDS)
     struct Seg { uint32_t coff; int32_t ntile, nchunk; uint32_t t0; bool use_lds; };
@@ -705,7 +725,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         if (w.t0 >= w.t1) return;  // uniform
     }
     // one segment: its boxes in LDS when they fit
-    const Seg sv0 = seg_at(0, tseg == nullptr && tkey == nullptr);
+    const Seg sv0 = seg_at(0, tseg == nullptr && !use_keys);
     float* blo = sbox;
     float* bhi = sbox + d * sv0.ntile;
     float* clo = sbox + 2 * d * sv0.ntile;
@@ -850,14 +870,15 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
         // ge_out starts at 1 (no exit); each band raises it to its highest exit level
         if (lane == 0 && result > 1) atomicMax(&ge_out[q], result);
     };
-    // The same scan on the packed key tables (one segment, boxes from L2), arranged for few
-    // dependent round trips per level: the chunk keys, the target's own chunk's tile boxes and
-    // its own tile's candidates are loaded together, the other passing chunks' tile boxes
-    // kChunkBatch at a time, candidates kBatch tiles at a time.
-    auto search_keys = [&](const int32_t q, const int32_t band) {
-        const uint32_t coff = sv0.coff;
-        const int32_t ntile = sv0.ntile, nchunk = sv0.nchunk;
-        const uint32_t t0 = sv0.t0;
+    // The same scan on the packed key tables (boxes from L2), arranged for few dependent round
+    // trips per level: the chunk keys, the target's own chunk's tile boxes and its own tile's
+    // candidates are loaded together, the other passing chunks' tile boxes kChunkBatch at a
+    // time, candidates kBatch tiles at a time.
+    const uint32_t kpad = (uint32_t)(kslots - kTileC);  // the key table's padding tile
+    auto search_keys = [&](const int32_t q, const int32_t band, const Seg& sv) {
+        const uint32_t coff = sv.coff;
+        const int32_t ntile = sv.ntile, nchunk = sv.nchunk;
+        const uint32_t t0 = sv.t0;
         float tv[DM];
 #pragma unroll
         for (int k = 0; k < DM; ++k)
@@ -888,16 +909,16 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             // and a field keeps its guard bit exactly when s's key <= t's key
             const uint64_t tg = tk | guard;
             auto keys_le = [&](uint64_t kv) { return ((tg - kv) & guard) == guard; };
-            const uint64_t* krow = lkey + (int64_t)(g - 2) * ccap;
-            const uint4* trow = tkey + (int64_t)(g - 2) * tcap + t0;
-            const uint64_t* crow = ckey + (int64_t)(g - 2) * (tcap / kWave) + t0 / kWave;
+            const uint64_t* krow = lkey + (int64_t)(g - 2) * kslots;
+            const uint4* trow = tkey + (int64_t)(g - 2) * ktiles + t0;
+            const uint64_t* crow = ckey + (int64_t)(g - 2) * ktiles + t0;  // chunk c at crow[64 c]
             // candidates of kBatch passing tiles of chunk c per round trip (mask rotated by r)
             auto test_tiles = [&](uint64_t mask, int32_t c, int r) -> bool {
                 while (mask) {
                     uint32_t jb[kBatch];
 #pragma unroll
                     for (int b = 0; b < kBatch; ++b) {
-                        jb[b] = padslot + (uint32_t)lane;
+                        jb[b] = kpad + (uint32_t)lane;
                         if (mask) {
                             const int tb = ((__ffsll((unsigned long long)mask) - 1) + r) % kWave;
                             mask &= mask - 1;
@@ -924,7 +945,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             };
             // one round trip: the first 64 chunks' keys, the own chunk's boxes, the own tile
             const bool c_in = lane < nchunk;
-            const uint64_t ck = crow[c_in ? lane : 0];
+            const uint64_t ck = crow[c_in ? lane * kWave : 0];
             const int32_t own_t = my_chunk * kWave + lane;
             const bool own_in = own_t < ntile;
             const uint4 ob = trow[own_in ? own_t : 0];
@@ -943,7 +964,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
                     cm = __ballot(c_in && keys_le(ck));
                 } else {
                     const int32_t ci = cbase + lane;
-                    cm = __ballot(ci < nchunk && keys_le(crow[ci < nchunk ? ci : 0]));
+                    cm = __ballot(ci < nchunk && keys_le(crow[ci < nchunk ? ci * kWave : 0]));
                 }
                 if (my_chunk >= cbase && my_chunk < cbase + kWave) cm &= ~(1ull << (my_chunk - cbase));
                 const int rot = my_chunk >= cbase && my_chunk < cbase + kWave ? my_chunk - cbase : 0;
@@ -994,9 +1015,10 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             const int32_t r = (int32_t)(item - (int64_t)b * nt);
             if (tseg) {
                 const int32_t q = tord ? tord[r] : r;
-                search(q, b, seg_at(tseg[q], false));
-            } else if (lkey) {
-                search_keys(r, b);
+                if (use_keys) search_keys(q, b, seg_at(tseg[q], false));
+                else search(q, b, seg_at(tseg[q], false));
+            } else if (use_keys) {
+                search_keys(r, b, sv0);
             } else {
                 search(r, b, sv0);
             }
@@ -1011,7 +1033,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             if (lane == 0) q = atomicAdd(&next_q, 1);
             q = __builtin_amdgcn_readfirstlane(q);
             if (q >= w.t1) break;
-            if (lkey) search_keys(q, band0);
+            if (use_keys) search_keys(q, band0, sv0);
             else search(q, band0, sv0);
         }
     }
@@ -1309,6 +1331,7 @@ void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t ns
     st.perm = c.take<int32_t>((size_t)st.ccap);
     st.seg_coff = c.take<int32_t>((size_t)nseg);
     st.seg_cnt = c.take<int32_t>((size_t)nseg);
+    st.nseg = nseg;
 }
 
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s) {
@@ -1340,13 +1363,18 @@ int32_t key_width(int32_t d, int32_t g_max) {
     return d * w <= 64 ? w : 0;
 }
 
+void carve_gres_keys_slots(Carver& c, GresKeys& k, int64_t slots, int32_t levels) {
+    k.kslots = round_up(slots > kTileC ? slots : kTileC + 1, kTileC);
+    k.ktiles = round_up(ceil_div(k.kslots, kTileC), kWave);
+    k.levels = levels;
+    k.key = c.take<uint64_t>((size_t)(levels * k.kslots));
+    k.tile = c.take<uint4>((size_t)(levels * k.ktiles));
+    k.chunk = c.take<uint64_t>((size_t)(levels * k.ktiles));
+    k.ok = c.take<int32_t>(64);
+}
+
 void carve_gres_keys(Carver& c, GresKeys& k, const GresStore& store, int32_t d, int32_t g_max) {
-    k.width = key_width(d, g_max);
-    if (!k.width) return;
-    const int64_t levels = g_max - 1;
-    k.key = c.take<uint64_t>((size_t)(levels * store.ccap));
-    k.tile = c.take<uint4>((size_t)(levels * store.tcap));
-    k.chunk = c.take<uint64_t>((size_t)(levels * (store.tcap / kWave)));
+    if (key_width(d, g_max)) carve_gres_keys_slots(c, k, store.ccap, g_max - 1);
 }
 
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -1452,7 +1480,7 @@ sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, c
                                int32_t nseg, const int32_t* used, bool near_first, bool lpt, int32_t* order,
                                int32_t* rank_off, int32_t* tord, int32_t* tseg, const GresTargets& tg,
                                int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres, void* ev_begin,
-                               void* ev_end, unsigned long long* dev_tests, hipStream_t st) {
+                               void* ev_end, unsigned long long* dev_tests, hipStream_t st, const GresKeys* keys) {
     if (cap <= 0) return SKY_OK;
     if (lpt) {  // the targets of the relations with the most candidates first
         hipLaunchKernelGGL(batch_rank_kernel, dim3((uint32_t)ceil_div(nseg, kBlock)), dim3(kBlock), 0, st,
@@ -1471,7 +1499,7 @@ sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, c
                        (const int32_t*)store.perm, near_first ? 1 : 0, tg.tval, tg.tvcap, tg.thint, tg.tout, tseg);
     SKY_HIP(hipGetLastError());
     return launch_gres_search(store, d, 0, tg, cap, nullptr, tseg, lpt ? tord : nullptr, g_max, mapping, g_exit,
-                              gres, ev_begin, ev_end, dev_tests, st);
+                              gres, ev_begin, ev_end, dev_tests, st, keys);
 }
 
 sky_status resident_workgroups(const void* kernel, int32_t block, size_t dyn_lds, int32_t* out) {
@@ -1492,25 +1520,33 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     if (nt <= 0) return SKY_OK;
     const bool batch = tseg != nullptr;
     const bool on_dev = nt_dev || batch;
-    // packed keys of the one segment at every level, when carved for this g_max
+    // packed key tables, when given for this g_max (whether the store's slots fit them is
+    // decided on the device: the search falls back to the values otherwise)
     const uint64_t* lkey = nullptr;
     int32_t kw = 0;
     const uint4* tkey = nullptr;
     const uint64_t* ckey = nullptr;
-    if (mapping != SKY_GRES_LEVELS && !batch && keys && keys->key && keys->width == key_width(d, g_max)) {
-        const int64_t kb = ceil_div(round_up(max_cnt, kTileC) + kTileC, kBlock);
+    const int32_t* kok = nullptr;
+    if (mapping != SKY_GRES_LEVELS && keys && keys->key && key_width(d, g_max) && g_max - 1 <= keys->levels &&
+        (!batch || keys->used)) {
+        kw = key_width(d, g_max);
+        const int64_t kb = ceil_div(keys->kslots, kBlock);
         const int32_t cblocks = (int32_t)(kb > 2048 ? 2048 : kb);
-        const int64_t tb = ceil_div(ceil_div(ceil_div(max_cnt, kTileC), kWave), kBlock / kWave);
+        const int64_t tb = ceil_div(keys->ktiles, kBlock);
         const int32_t tblocks = (int32_t)(tb < 1 ? 1 : (tb > 1024 ? 1024 : tb));
-        SKY_DISPATCH_D(d, level_keys_kernel, dim3((uint32_t)(cblocks + tblocks)), dim3(kBlock), 0, st,
+        const int32_t nseg = batch ? store.nseg : 1;
+        const int64_t sb = ceil_div(nseg, kBlock / kWave);
+        const int32_t sblocks = (int32_t)(sb > 256 ? 256 : sb);
+        SKY_DISPATCH_D(d, level_keys_kernel, dim3((uint32_t)(cblocks + tblocks + sblocks)), dim3(kBlock), 0, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo, (const float*)store.hi,
-                       store.tcap, d, (const int32_t*)store.seg_cnt, g_max - 1, keys->width, cblocks, keys->key,
-                       keys->tile, keys->chunk);
+                       store.tcap, d, (const int32_t*)store.seg_coff, (const int32_t*)store.seg_cnt, nseg,
+                       batch ? keys->used : nullptr, g_max - 1, kw, cblocks, tblocks, keys->key, keys->kslots,
+                       keys->tile, keys->chunk, keys->ktiles, keys->ok);
         SKY_HIP(hipGetLastError());
         lkey = keys->key;
         tkey = keys->tile;
         ckey = keys->chunk;
-        kw = keys->width;
+        kok = keys->ok;
     }
     // LDS for the tile boxes of the one segment, when they fit; with the count on the device,
     // a fixed 40 KB (the kernel checks the real size), which costs no occupancy at 8 waves per
@@ -1520,7 +1556,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     int64_t floats = (int64_t)d * (2 * ntile + nchunk);
     if (floats * 4 > kGresLdsBytes || nchunk > kWave) floats = 0;
     if (nt_dev) floats = kGresLdsDevBytes / 4;
-    if (batch || tkey) floats = 0;  // (packed keys: the boxes are read from L2)
+    if (batch) floats = 0;
     const size_t lds = (size_t)floats * sizeof(float);
     int32_t per_wg = 0, lbands = 1, blocks = 0;
     search_shape(nt, g_max, &per_wg, &blocks, &lbands);
@@ -1608,7 +1644,8 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                        (const int32_t*)store.seg_cnt, d, (const float*)tg.tval, tg.tvcap, nt,
                        (const int32_t*)tg.thint, per_wg, g_max, (int32_t)floats, tg.ge,
                        dev_tests, (int32_t)blocks, band_len, gstart, nbands, work, (const int32_t*)params,
-                       tseg, tord, lkey, tkey, ckey, kw);
+                       tseg, tord, lkey, tkey, ckey, kw, kok, lkey ? keys->kslots : 0,
+                       lkey ? keys->ktiles : 0);
         SKY_HIP(hipGetLastError());
     }
     if (ev_end) SKY_HIP(hipEventRecord((hipEvent_t)ev_end, st));

@@ -366,6 +366,7 @@ struct GresStore {
     int32_t* perm;                 // [ccap] caller index of each slot (-1 for padding)
     int32_t* seg_coff;             // [nseg] first slot of each segment (multiple of 64)
     int32_t* seg_cnt;              // [nseg] candidates of each segment
+    int32_t nseg;
 };
 struct GresPrepTmp { uint32_t *k0, *v0, *k1, *v1; int32_t* radix_tmp; };
 struct GresTargets {
@@ -378,20 +379,27 @@ struct GresTargets {
     int32_t* params;               // [16] the search's shape when its target count is on the device
 };
 void carve_gres_store(Carver& c, GresStore& st, int64_t s, int32_t d, int32_t nseg);
-// Keys of every candidate slot at every level g in [2, g_max], packed into one 64-bit word per
-// (level, slot): attribute k's key in a field of `width` bits at bit k * width, the field's top
-// bit clear (a guard bit for the dominance test's subtraction). Taken only when the fields hold
-// every key (g_max <= kKeyTableMaxG, d * width <= 64); key == nullptr otherwise.
+// Keys of every candidate slot at every level g in [2, levels + 1], packed into one 64-bit word
+// per (level, slot): attribute k's key in a field of `width` bits at bit k * width, the field's
+// top bit clear (a guard bit for the dominance test's subtraction), width = key_width(d, g_max)
+// of the search. Usable when the fields hold every key (g_max <= kKeyTableMaxG,
+// d * width <= 64) and g_max - 1 <= levels.
 constexpr int32_t kKeyTableMaxG = 64;
 struct GresKeys {
-    uint64_t* key = nullptr;       // [g_max - 1][ccap] candidates, level g at row g - 2
-    uint4* tile = nullptr;         // [g_max - 1][tcap] tile boxes: lower corner (x, y), upper (z, w)
-    uint64_t* chunk = nullptr;     // [g_max - 1][tcap / 64] lower corner of every 64 tiles
-    int32_t width = 0;
+    uint64_t* key = nullptr;       // [levels][kslots] candidates (the last 64 slots of a row: padding)
+    uint4* tile = nullptr;         // [levels][ktiles] tile boxes: lower corner (x, y), upper (z, w)
+    uint64_t* chunk = nullptr;     // [levels][ktiles] lower corner of the 64 tiles from a chunk's first
+    int32_t* ok = nullptr;         // set on the device: the store's slots in use fit the tables
+    int64_t kslots = 0, ktiles = 0;
+    int32_t levels = 0;
+    const int32_t* used = nullptr; // slots in use (device; null: the first segment's tiles)
 };
 // field width for g_max (0: the keys of d attributes do not fit one word)
 int32_t key_width(int32_t d, int32_t g_max);
+// tables for the store's own capacity, g_max - 1 levels (none when key_width is 0)
 void carve_gres_keys(Carver& c, GresKeys& k, const GresStore& store, int32_t d, int32_t g_max);
+// tables for `slots` candidate slots (padding tile included), `levels` levels
+void carve_gres_keys_slots(Carver& c, GresKeys& k, int64_t slots, int32_t levels);
 void carve_gres_prep_tmp(Carver& c, GresPrepTmp& t, int64_t s);
 void carve_gres_targets(Carver& c, GresTargets& t, int64_t nt, int32_t d);
 sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
@@ -427,7 +435,8 @@ sky_status launch_batch_search(const GresStore& store, int32_t d, int64_t cap, c
                                int32_t nseg, const int32_t* used, bool near_first, bool lpt, int32_t* order,
                                int32_t* rank_off, int32_t* tord, int32_t* tseg, const GresTargets& tg,
                                int32_t g_max, int32_t mapping, int32_t* g_exit, float* gres, void* ev_begin,
-                               void* ev_end, unsigned long long* dev_tests, hipStream_t st);
+                               void* ev_end, unsigned long long* dev_tests, hipStream_t st,
+                               const GresKeys* keys = nullptr);
 // measured (both mappings with per-target start levels): lanes over 64 levels pay off when
 // many levels lie below the start levels (g_max >= 2^17) or on small skylines with
 // g_max > 1000; otherwise the banded tile walk is faster
@@ -438,9 +447,10 @@ __host__ __device__ inline int32_t gres_auto_mapping(int64_t s, int32_t g_max) {
 // One segment of max_cnt candidates, nt targets. nt_dev: the target count is min(*nt_dev, nt)
 // on the device, nt being an upper bound; the mapping (AUTO included) and the work split are then
 // decided on the device. tseg (a batch): every target q of segment tseg[q] (in the order tord,
-// when given) as persistent work, with tg.params already holding the count and shape. keys (one
-// segment, key != nullptr, carved for this g_max): the tile search tests candidates on packed
-// keys, built here for the segment's slots.
+// when given) as persistent work, with tg.params already holding the count and shape. keys
+// (tables of at least g_max - 1 levels; for a batch with keys->used set): the tile search runs
+// on packed keys, the tables built here, when key_width(d, g_max) allows them and the store's
+// slots in use fit them (decided on the device; the values are searched otherwise).
 sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt,
                               const GresTargets& tg, int64_t nt, const int32_t* nt_dev, const int32_t* tseg,
                               const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,

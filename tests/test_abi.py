@@ -229,6 +229,8 @@ def test_batch_arguments(lib):
     assert lib.sky_batch_skylines(None, fake, 1, fake, None) == E
     assert lib.sky_batch_tune(None, None, None) == E
     assert lib.sky_batch_gres(None, 25, None, None, None, None, None) == E
+    assert lib.sky_batch_keys_bytes(None, 100, 25) == 0
+    assert lib.sky_batch_set_keys(None, fake, 1 << 20, 100, 25) == E
     assert lib.sky_batch_info(None, None) == E
     lib.sky_batch_destroy(None)
 

@@ -137,6 +137,47 @@ def test_batch_matches_plain_path(dev):
     run.close()
 
 
+def test_batch_keys_and_values_agree(dev):
+    # the gres search on packed key tables, on the values (no tables) and on tables too small
+    # for the skyline total (the device falls back to the values): identical results, and the
+    # oracle's
+    data = [G.ant(3000, 6, 21), G.uni(800, 6, 22), G.ant(12000, 6, 23), G.ties(5000, 6, 24, levels=9),
+            G.dyadic(700, 6, 25, bits=4)]
+    _say("batch keys vs values")
+    ref = BatchRunner(data, g_max=25, device=dev, use_graph=False, keys=False).run()
+    want = [ref.result(i) for i in range(len(data))]
+    ref.close()
+    run = BatchRunner(data, g_max=25, device=dev, use_graph=False).run()
+    g = run.groups[0]
+    assert getattr(g, "keys_ws", None) is not None  # d = 6 at g_max 25: tables attached
+    for i, x in enumerate(data):
+        got = run.result(i)
+        for a, b in zip(got, want[i]):
+            assert np.array_equal(a, b), f"relation {i}"
+        _check_relation(x, *got, 25, f"relation {i}")
+    st = run.stream
+    lib = _lib.load()
+    for total in (g.sky_count - 1, 0):  # too small: searched on the values
+        with torch.cuda.stream(st):
+            g.attach_keys(sky_total=total)
+            g.g_exit.fill_(-7)
+            g.launch_gres(st)
+        st.synchronize()
+        for i in range(len(data)):
+            got = run.result(i)
+            assert np.array_equal(got[1], want[i][1]), (total, i)
+    # argument checks: g_max above the table's levels, no tables for d > 10 at g_max 25
+    assert lib.sky_batch_keys_bytes(g.h, 100, 65) == 0
+    assert lib.sky_batch_keys_bytes(g.h, 100, 25) > 0
+    assert lib.sky_batch_set_keys(g.h, None, 0, 0, 25) == _lib.SKY_OK  # detach
+    with torch.cuda.stream(st):
+        g.g_exit.fill_(-7)
+        g.launch_gres(st)
+    st.synchronize()
+    assert np.array_equal(run.result(2)[1], want[2][1])
+    run.close()
+
+
 def test_batch_capacity_and_state_errors(dev):
     lib = _lib.load()
     x = G.uni(1000, 3, 1)
