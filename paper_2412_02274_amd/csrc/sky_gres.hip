@@ -665,6 +665,21 @@ __device__ __forceinline__ WgWork wg_work(int32_t per_wg, int32_t nt, int32_t bl
     return w;
 }
 
+// The candidate tests of a workgroup of the search kernels, added to *dev_tests with one atomic
+// (every wave's count summed through LDS: thousands of waves adding to one address at the end
+// of a launch would queue behind each other). Every wave of the workgroup calls it.
+__device__ __forceinline__ void add_block_tests(unsigned long long* dev_tests, unsigned long long ntests) {
+    __shared__ unsigned long long wred[kWaves];
+    if (!dev_tests) return;
+    if (lane_id() == 0) wred[threadIdx.x / kWave] = ntests;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kWaves; ++w) t += wred[w];
+        if (t) atomicAdd(dev_tests, t);
+    }
+}
+
 template <int D>
 // 8 waves per SIMD: the search waits on cache round trips, so more waves in flight pay.
 // Three ways to hand out the work, (target, band) pairs in band-major order (every target's
@@ -1037,7 +1052,7 @@ __global__ void __launch_bounds__(kGresBlock) __attribute__((amdgpu_waves_per_eu
             else search(q, band0, sv0);
         }
     }
-    if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
+    add_block_tests(dev_tests, ntests);
 }
 
 // no level g >= g_low can see a candidate whose (lower-bounding) excess over t is delta
@@ -1287,7 +1302,7 @@ __global__ void __launch_bounds__(kGresBlock) gres_levels_kernel(
             for (int32_t q = w.t0 + wave; q < w.t1; q += kWaves) search(q, band, 0);
         }
     }
-    if (dev_tests && lane_id() == 0 && ntests) atomicAdd(dev_tests, ntests);
+    add_block_tests(dev_tests, ntests);
 }
 
 __global__ void __launch_bounds__(kBlock) gres_output_kernel(const int32_t* __restrict__ ge_t,

@@ -1090,8 +1090,19 @@ __global__ void __launch_bounds__(kBlock) test_kernel(
         const int32_t u1 = ((int32_t)blockIdx.x + 1) * per < nunits ? ((int32_t)blockIdx.x + 1) * per : nunits;
         for (int32_t ug = (int32_t)blockIdx.x * per; ug < u1; ++ug) unit(ug, wave);
     }
-    if (lane == 0 && ntests_h) atomicAdd(&tests[0], ntests_h);
-    if (lane == 0 && ntests_r) atomicAdd(&tests[1], ntests_r);
+    // one atomic per workgroup and counter: the waves' counts summed through LDS (thousands of
+    // waves adding to one address at the end of a launch would queue behind each other)
+    __shared__ unsigned long long wred[kBlock / kWave][2];
+    if (lane == 0) {
+        wred[wave][0] = ntests_h;
+        wred[wave][1] = ntests_r;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += wred[w][threadIdx.x];
+        if (t) atomicAdd(&tests[threadIdx.x], t);
+    }
     if (seg_tests && lane == 0 && acc) atomicAdd(&seg_tests[acc_seg], acc);
 }
 
