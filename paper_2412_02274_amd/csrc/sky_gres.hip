@@ -212,8 +212,9 @@ __device__ __forceinline__ uint64_t pack_keys(const float* v, int d, float fg, i
 //    [kslots - 64, kslots) (the clamp value in every field), key[(g - 2) * kslots + slot];
 //  * blocks [cblocks, cblocks + tblocks): one thread per tile in use, its packed box corners,
 //    tile[(g - 2) * ktiles + tile];
-//  * the other blocks: one wave per segment, for each chunk of 64 tiles from the segment's first
-//    tile, the packed minimum of their lower corners at chunk[(g - 2) * ktiles + first tile].
+//  * the other blocks: for each chunk of 64 tiles from a segment's first tile, the packed
+//    minimum of their lower corners at chunk[(g - 2) * ktiles + first tile] (one wave per chunk
+//    of a single segment, one wave per segment of many).
 template <int D>
 __global__ void __launch_bounds__(kBlock) level_keys_kernel(
     const float* __restrict__ cand, int64_t ccap, const float* __restrict__ lo, const float* __restrict__ hi,
@@ -268,21 +269,28 @@ __global__ void __launch_bounds__(kBlock) level_keys_kernel(
     const int lane = (int)lane_id();
     const int32_t wpb = kBlock / kWave;
     const int32_t nwaves = ((int32_t)gridDim.x - cblocks - tblocks) * wpb;
-    for (int32_t sg = (b - cblocks - tblocks) * wpb + (int32_t)(threadIdx.x / kWave); sg < nseg; sg += nwaves) {
+    const int32_t w0 = (b - cblocks - tblocks) * wpb + (int32_t)(threadIdx.x / kWave);
+    // the chunk of tiles [t0 + c0, t0 + c0 + 64) of a segment of nts tiles
+    auto do_chunk = [&](int32_t t0, int32_t nts, int32_t c0) {
+        const bool real = c0 + lane < nts;
+        float vl[DM];
+#pragma unroll
+        for (int k = 0; k < DM; ++k)
+            if (k < d) {
+                vl[k] = real ? lo[(int64_t)k * tcap + t0 + c0 + lane] : kPadValue;
+                for (int off = kWave / 2; off > 0; off >>= 1) vl[k] = fminf(vl[k], __shfl_xor(vl[k], off, kWave));
+            }
+        if (lane < levels) chunk[(int64_t)lane * ktiles + t0 + c0] = pack_keys<D>(vl, d, (float)(lane + 2), w, kmax);
+    };
+    if (nseg == 1) {  // one wave per chunk
+        const int32_t nts = (seg_cnt[0] + kTileC - 1) / kTileC;
+        for (int32_t c = w0; c * kWave < nts; c += nwaves) do_chunk(seg_coff[0] / kTileC, nts, c * kWave);
+        return;
+    }
+    for (int32_t sg = w0; sg < nseg; sg += nwaves) {  // one wave per segment
         const int32_t t0 = seg_coff[sg] / kTileC;
         const int32_t nts = (seg_cnt[sg] + kTileC - 1) / kTileC;
-        for (int32_t c0 = 0; c0 < nts; c0 += kWave) {
-            const bool real = c0 + lane < nts;
-            float vl[DM];
-#pragma unroll
-            for (int k = 0; k < DM; ++k)
-                if (k < d) {
-                    vl[k] = real ? lo[(int64_t)k * tcap + t0 + c0 + lane] : kPadValue;
-                    for (int off = kWave / 2; off > 0; off >>= 1) vl[k] = fminf(vl[k], __shfl_xor(vl[k], off, kWave));
-                }
-            if (lane < levels)
-                chunk[(int64_t)lane * ktiles + t0 + c0] = pack_keys<D>(vl, d, (float)(lane + 2), w, kmax);
-        }
+        for (int32_t c0 = 0; c0 < nts; c0 += kWave) do_chunk(t0, nts, c0);
     }
 }
 
@@ -1550,7 +1558,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
         const int64_t tb = ceil_div(keys->ktiles, kBlock);
         const int32_t tblocks = (int32_t)(tb < 1 ? 1 : (tb > 1024 ? 1024 : tb));
         const int32_t nseg = batch ? store.nseg : 1;
-        const int64_t sb = ceil_div(nseg, kBlock / kWave);
+        const int64_t sb = ceil_div(batch ? nseg : keys->ktiles / kWave, kBlock / kWave);
         const int32_t sblocks = (int32_t)(sb > 256 ? 256 : sb);
         SKY_DISPATCH_D(d, level_keys_kernel, dim3((uint32_t)(cblocks + tblocks + sblocks)), dim3(kBlock), 0, st,
                        (const float*)store.cand, store.ccap, (const float*)store.lo, (const float*)store.hi,
