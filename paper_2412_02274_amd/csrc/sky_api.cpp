@@ -83,6 +83,8 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     P->part_off = c.take<int32_t>((size_t)p + 1);
     P->pruned = c.take<uint8_t>((size_t)p);
     P->tan2_dev = c.take<double>((size_t)(scheme == SKY_ANGULAR ? m + 1 : 1));
+    P->sel_key = c.take<unsigned long long>((size_t)(scheme == SKY_SLICED ? 3 * p : 1));
+    P->sel_i32 = c.take<int32_t>((size_t)(scheme == SKY_SLICED ? slice_select_elems(p) : 1));
     P->seg_off_dev = c.take<int64_t>((size_t)(scheme == kSchemeSegments ? p + 1 : 1));
     P->part_of_row = c.take<int32_t>((size_t)(p > 1 ? n : 1));
     P->pcount = c.take<int32_t>((size_t)p);
@@ -150,6 +152,8 @@ sky_status plan_partition(sky_plan* P, hipStream_t st) {
     a.scheme = P->scheme; a.p = P->p; a.m = P->m; a.slice_dim = P->slice_dim;
     a.seg_off = P->seg_off_dev;
     a.tan2 = P->tan2_dev;
+    a.sel_key = P->sel_key;
+    a.sel_i32 = P->sel_i32;
     a.prefilter = P->prefilter;
     a.xp = P->xp; a.ldp = P->ldp; a.rowid = P->rowid; a.seg = P->seg; a.fsum = P->fsum;
     a.n_live = P->count_tmp + CT_ROWS;

@@ -1594,7 +1594,9 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     nbands = nbands < 1 ? 1 : (nbands > kMaxBands ? kMaxBands : nbands);
     const int32_t band_len = (int32_t)ceil_div(g_max - 1, nbands);
     const bool run_tiles = on_dev ? mapping != SKY_GRES_LEVELS : mapping != SKY_GRES_LEVELS;
-    const bool run_levels = on_dev ? mapping != SKY_GRES_TILES : mapping == SKY_GRES_LEVELS;
+    // (AUTO picks LEVELS only above g_max 1000, gres_auto_mapping)
+    const bool run_levels = on_dev ? mapping == SKY_GRES_LEVELS || (mapping == SKY_GRES_AUTO && g_max > 1000)
+                                   : mapping == SKY_GRES_LEVELS;
     // grids of the kernels that stride over the blocks a device-side count asks for
     const uint32_t stride_grid = (uint32_t)(blocks < kStrideGrid ? (blocks < 1 ? 1 : blocks) : kStrideGrid);
     // many levels: each target's highest level worth searching, from the candidates' bounds

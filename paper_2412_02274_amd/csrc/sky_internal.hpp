@@ -206,6 +206,9 @@ struct PartitionArgs {
     int32_t scheme; int32_t p; int32_t m; int32_t slice_dim;
     const int64_t* seg_off;    // kSchemeSegments: [p+1] row offsets of the datasets (device)
     double* tan2;              // Angular thresholds tan^2(k*pi/(2m)), k = 0..m (device, written here)
+    unsigned long long* sel_key;  // Sliced: [3 p] scratch: boundary keys, active prefixes, and the
+                                  // largest key of each prefix's rows
+    int32_t* sel_i32;          // Sliced: [slice_select_elems(p)] scratch
     bool prefilter;            // drop the rows their partition's killer rows dominate (else keep all)
     float* xp; int64_t ldp;    // partition-contiguous canonical SoA copy of the kept rows
     int32_t* rowid;            // position -> original row
@@ -231,6 +234,9 @@ struct PartitionArgs {
     int32_t* dev_status;
 };
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
+// int32 scratch of the Sliced boundary selection: the first digit's histogram (2^14 bins), one
+// 256-bin histogram per boundary, and per-boundary state
+inline int64_t slice_select_elems(int32_t p) { return 16384 + 256 * (int64_t)p + 4 * (int64_t)p + 64; }
 // workgroups of the per-row passes of launch_partition (4096 rows each)
 int64_t partition_blocks(int64_t n);
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st);

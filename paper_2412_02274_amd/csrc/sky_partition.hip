@@ -149,12 +149,19 @@ __global__ void __launch_bounds__(kBlock) partition_init_kernel(int32_t p, int32
 }
 
 // ---- 1. classify -----------------------------------------------------------------------------------
+// A row's key in the (value, row) order of the slicing attribute: the canonical value's bits
+// above the row index (rows < 2^30)
+__device__ __forceinline__ unsigned long long slice_key(float v, int64_t row) {
+    return ((unsigned long long)fbits(v) << 30) | (unsigned long long)row;
+}
+
 struct ClassifyArgs {
     const float* x; int64_t n; int32_t d; int64_t ld;
-    int32_t scheme; int32_t p; int32_t m;
+    int32_t scheme; int32_t p; int32_t m; int32_t slice_dim;
     const double* tan2;             // Angular thresholds
     const int64_t* seg_off;         // batched datasets
-    int32_t* part_of_row;           // written (Grid/Angular/datasets), read (Sliced), null (None)
+    const unsigned long long* bkey; // Sliced: [p - 1] boundary keys (slice_key order)
+    int32_t* part_of_row;           // written (every scheme but None), null (None)
     int32_t* pcount;                // [p] rows per partition (+=)
     unsigned long long* kmin;       // [p][kKill] minima of (score bits << 32 | row)
     int32_t* dev_status;
@@ -163,12 +170,15 @@ struct ClassifyArgs {
 template <int D>
 __global__ void __launch_bounds__(kPT) classify_kernel(ClassifyArgs a) {
     constexpr int DM = D > 0 ? D : SKY_MAX_D;
-    extern __shared__ unsigned long long lmin[];  // [p], then int32 counts [p]
-    int32_t* lcnt = reinterpret_cast<int32_t*>(lmin + a.p);
+    extern __shared__ unsigned long long lmin[];  // [p], Sliced: [p - 1] boundary keys, then int32 counts [p]
+    unsigned long long* lbk = lmin + a.p;
+    const bool sliced = a.scheme == SKY_SLICED;
+    int32_t* lcnt = reinterpret_cast<int32_t*>(lmin + a.p + (sliced ? a.p - 1 : 0));
     const int d = dget<D>(a.d);
     for (int32_t j = threadIdx.x; j < a.p; j += kPT) {
         lmin[j] = ~0ull;
         lcnt[j] = 0;
+        if (sliced && j < a.p - 1) lbk[j] = a.bkey[j];
     }
     __syncthreads();
     bool bad = false;
@@ -180,7 +190,7 @@ __global__ void __launch_bounds__(kPT) classify_kernel(ClassifyArgs a) {
         unsigned long long key = ~0ull;
         if (valid) {
             float v[DM];
-            float f = 0.0f;
+            float f = 0.0f, vs = 0.0f;
 #pragma unroll
             for (int k = 0; k < DM; ++k)
                 if (k < d) {
@@ -188,12 +198,21 @@ __global__ void __launch_bounds__(kPT) classify_kernel(ClassifyArgs a) {
                     bad |= !in_domain(t);
                     v[k] = canon(t);
                     f = __fadd_rn(f, v[k]);
+                    if (k == a.slice_dim) vs = v[k];
                 }
             if (a.scheme == SKY_NONE) part = 0;
-            else if (a.scheme == SKY_SLICED) part = a.part_of_row[i];
+            else if (sliced) {  // the boundaries at or below the row's key (binary search)
+                const unsigned long long kr = slice_key(vs, i);
+                int32_t lo = 0, hi = a.p - 1;
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi) >> 1;
+                    if (lbk[mid] <= kr) lo = mid + 1; else hi = mid;
+                }
+                part = lo;
+            }
             else if (a.scheme == kSchemeSegments) part = dataset_of(a.seg_off, a.p, i);
             else part = cell_of<D>(v, d, a.scheme, a.m, a.tan2);
-            if (a.part_of_row && a.scheme != SKY_SLICED) a.part_of_row[i] = part;
+            if (a.part_of_row) a.part_of_row[i] = part;
             key = ((unsigned long long)fbits(f) << 32) | (uint32_t)i;
         }
         // count and minimum per partition in LDS; a wave whose rows share one partition (one
@@ -571,26 +590,283 @@ __global__ void __launch_bounds__(kBlock) part_gather_kernel(
     }
 }
 
-// ---- Sliced: the order of the slicing attribute ----------------------------------------------------
-__global__ void __launch_bounds__(kBlock) slice_keys_kernel(const float* __restrict__ x, int64_t n,
-                                                             int32_t dim, int64_t ld,
-                                                             uint32_t* __restrict__ keys,
-                                                             uint32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) {
-        // canonical non-negative FP32 values: the bit pattern orders like the value (values
-        // outside the domain are reported by the classify pass)
-        keys[i] = fbits(canon(x[(int64_t)dim * ld + i]));
-        vals[i] = (uint32_t)i;
+// ---- Sliced: boundary keys by radix selection -----------------------------------------------------
+// A row's place in the (value, row) order of the slicing attribute is the order of its key
+// slice_key = canonical value bits << 30 | row (rows < 2^30). The row at rank q goes to partition
+// floor(q p / n), so partition(row) = #{e in [1, p-1] : rank(row) >= r_e} with r_e = ceil(e n / p):
+// the number of boundary keys (the keys at ranks r_e) at or below the row's key. The boundary
+// keys are found digit by digit from the top (14 bits, then six of 8): a histogram pass over the
+// rows whose key starts with some boundary's prefix found so far, then one workgroup that moves
+// every boundary into its digit. No sort of the relation, and nothing read back.
+constexpr int kSelBins0 = 16384;             // first digit: key bits 61..48
+constexpr int kSelPasses = 6;                // then 8-bit digits at shifts 40, 32, ..., 0
+constexpr int kSelLdsSlots = 64;             // boundary prefixes whose histograms fit LDS
+enum { SEL_H = kSelBins0 };                  // int32 offsets in sel_i32: [SEL_H, +256 p) histograms,
+                                             // then rem [p], slot [p], nact
+__device__ __forceinline__ int64_t sel_rem_off(int32_t p) { return SEL_H + 256 * (int64_t)p; }
+__device__ __forceinline__ int64_t sel_slot_off(int32_t p) { return sel_rem_off(p) + p; }
+__device__ __forceinline__ int64_t sel_nact_off(int32_t p) { return sel_slot_off(p) + p; }
+
+__global__ void __launch_bounds__(kBlock) sel_zero_kernel(int32_t* __restrict__ sel, int64_t cnt) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * kBlock)
+        sel[i] = 0;
+}
+
+// The histogram passes: workgroups of 1024 threads over chunks of 4096 rows (grid-stride, about
+// two workgroups per CU, so that each clears and flushes its LDS histogram once).
+constexpr int kSelChunk = 4096;
+constexpr int kSelBloomBits = 65536;
+
+// 16-bit hash of a key prefix (multiplicative, top bits)
+__device__ __forceinline__ uint32_t sel_hash(unsigned long long pre) {
+    return (uint32_t)((pre * 0x9E3779B97F4A7C15ull) >> 48);
+}
+
+// first digit of every row's key, LDS-privatised
+__global__ void __launch_bounds__(1024) sel_hist0_kernel(const float* __restrict__ x, int64_t n, int32_t dim,
+                                                         int64_t ld, int32_t* __restrict__ sel) {
+    __shared__ int32_t h[kSelBins0];
+    for (int32_t b = threadIdx.x; b < kSelBins0; b += 1024) h[b] = 0;
+    __syncthreads();
+    const int64_t nch = (n + kSelChunk - 1) / kSelChunk;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t r0 = c * kSelChunk + threadIdx.x;
+        float v[kSelChunk / 1024];
+#pragma unroll
+        for (int it = 0; it < kSelChunk / 1024; ++it) {
+            const int64_t i = r0 + (int64_t)it * 1024;
+            v[it] = i < n ? x[(int64_t)dim * ld + i] : 0.0f;
+        }
+#pragma unroll
+        for (int it = 0; it < kSelChunk / 1024; ++it) {
+            const int64_t i = r0 + (int64_t)it * 1024;
+            if (i < n) atomicAdd(&h[(int32_t)(slice_key(canon(v[it]), i) >> 48)], 1);
+        }
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < kSelBins0; b += 1024)
+        if (h[b]) atomicAdd(&sel[b], h[b]);
+}
+
+// the boundaries' active prefixes after a digit: slot[e] = index of bkey[e] among the distinct
+// prefixes (in order; boundaries past the last row keep slot -1, resolved ones -2, their bkey
+// the full key), act = those prefixes, nact
+__device__ void sel_slots(unsigned long long* __restrict__ bkey, int32_t nb, int32_t* __restrict__ slot,
+                          unsigned long long* __restrict__ act, int32_t* __restrict__ nact) {
+    __shared__ int32_t wsum[1024 / kWave];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < nb; base += 1024) {
+        const int32_t e = base + (int32_t)threadIdx.x;
+        const bool live = e < nb && slot[e] >= 0;
+        const bool first = live && (e == 0 || slot[e - 1] < 0 || bkey[e - 1] != bkey[e]);
+        // inclusive count of first flags (wave scan, then across waves)
+        int32_t v = first ? 1 : 0;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t o = __shfl_up(v, off, kWave);
+            if ((int)lane_id() >= off) v += o;
+        }
+        if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = v;
+        __syncthreads();
+        int32_t before = carry;
+        for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) before += wsum[w];
+        const int32_t sl = before + v - 1;
+        __syncthreads();
+        if (live) {
+            slot[e] = sl;
+            if (first) act[sl] = bkey[e];
+        }
+        if (threadIdx.x == 1023) carry = before + v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *nact = carry;
+}
+
+// after the first digit: each boundary's bin, its rank inside it, the active prefixes
+__global__ void __launch_bounds__(1024) sel_find0_kernel(int64_t n, int32_t p, int32_t* __restrict__ sel,
+                                                         unsigned long long* __restrict__ bkey) {
+    __shared__ int32_t cum[kSelBins0];
+    __shared__ int32_t wsum[1024 / kWave];
+    // exclusive prefix of the histogram, 16 bins per thread
+    constexpr int per = kSelBins0 / 1024;
+    int32_t loc[per], t = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        loc[k] = t;
+        t += sel[threadIdx.x * per + k];
+    }
+    int32_t v = t;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int32_t o = __shfl_up(v, off, kWave);
+        if ((int)lane_id() >= off) v += o;
+    }
+    if (lane_id() == kWave - 1) wsum[threadIdx.x / kWave] = v;
+    __syncthreads();
+    int32_t before = 0;
+    for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) before += wsum[w];
+    before += v - t;
+#pragma unroll
+    for (int k = 0; k < per; ++k) cum[threadIdx.x * per + k] = before + loc[k];
+    __syncthreads();
+    const int32_t nb = p - 1;
+    int32_t* rem = sel + sel_rem_off(p);
+    int32_t* slot = sel + sel_slot_off(p);
+    for (int32_t e = threadIdx.x; e < nb; e += 1024) {
+        const int64_t r = ((int64_t)(e + 1) * n + p - 1) / p;
+        if (r >= n) {  // no row has this rank: above every key
+            bkey[e] = ~0ull;
+            slot[e] = -1;
+            continue;
+        }
+        int32_t lo = 0, hi = kSelBins0 - 1;  // the last bin whose prefix count is <= r
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (cum[mid] <= r) lo = mid; else hi = mid - 1;
+        }
+        bkey[e] = (unsigned long long)lo;
+        rem[e] = (int32_t)(r - cum[lo]);
+        slot[e] = 0;
+    }
+    for (int32_t a = threadIdx.x; a < p; a += 1024) bkey[2 * p + a] = 0;  // per-prefix maxima
+    __syncthreads();
+    sel_slots(bkey, nb, slot, bkey + p, sel + sel_nact_off(p));
+}
+
+// one 8-bit digit at `shift` of the rows whose key prefix (the bits above it) is active, and per
+// active prefix the key of one of its rows (the key itself when only one row has the prefix:
+// then exactly one workgroup holds it; a key of 0 is the value left by the clearing);
+// LDS-privatised for up to kSelLdsSlots prefixes
+__global__ void __launch_bounds__(1024) sel_hist_kernel(const float* __restrict__ x, int64_t n, int32_t dim,
+                                                        int64_t ld, int32_t p, int32_t shift,
+                                                        int32_t* __restrict__ sel,
+                                                        unsigned long long* __restrict__ bkey) {
+    __shared__ unsigned long long lact[kSelLdsSlots], lmax[kSelLdsSlots];
+    __shared__ int32_t h[kSelLdsSlots * 256];
+    __shared__ uint32_t bloom[kSelBloomBits / 32];  // hash bits of the active prefixes
+    const int32_t nact = sel[sel_nact_off(p)];
+    if (nact == 0) return;  // every boundary resolved (uniform)
+    const unsigned long long* act = bkey + p;
+    unsigned long long* kmax = bkey + 2 * p;
+    int32_t* gh = sel + SEL_H;
+    const bool in_lds = nact <= kSelLdsSlots;
+    for (int32_t w = threadIdx.x; w < kSelBloomBits / 32; w += 1024) bloom[w] = 0;
+    if (in_lds) {
+        for (int32_t a = threadIdx.x; a < nact; a += 1024) {
+            lact[a] = act[a];
+            lmax[a] = 0;
+        }
+        for (int32_t b = threadIdx.x; b < nact * 256; b += 1024) h[b] = 0;
+    }
+    __syncthreads();
+    for (int32_t a = threadIdx.x; a < nact; a += 1024) {
+        const uint32_t hb = sel_hash(act[a]);
+        atomicOr(&bloom[hb >> 5], 1u << (hb & 31u));
+    }
+    __syncthreads();
+    const unsigned long long* sact = in_lds ? lact : act;
+    const unsigned long long lo_pre = sact[0], hi_pre = sact[nact - 1];
+    int32_t top = 1;  // the largest power of two <= nact
+    while (2 * top <= nact) top *= 2;
+    const int64_t nch = (n + kSelChunk - 1) / kSelChunk;
+    for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int64_t r0 = c * kSelChunk + threadIdx.x;
+        float v[kSelChunk / 1024];
+#pragma unroll
+        for (int it = 0; it < kSelChunk / 1024; ++it) {
+            const int64_t i = r0 + (int64_t)it * 1024;
+            v[it] = i < n ? x[(int64_t)dim * ld + i] : 0.0f;
+        }
+#pragma unroll
+        for (int it = 0; it < kSelChunk / 1024; ++it) {
+            const int64_t i = r0 + (int64_t)it * 1024;
+            const unsigned long long k = slice_key(canon(v[it]), i);
+            const unsigned long long pre = k >> (shift + 8);
+            if (i >= n || pre < lo_pre || pre > hi_pre) continue;
+            const uint32_t hb = sel_hash(pre);  // most rows have no active prefix: one LDS read
+            if (((bloom[hb >> 5] >> (hb & 31u)) & 1u) == 0) continue;
+            // the last active prefix <= pre, in a fixed number of steps (the rows' searches
+            // interleave); the active prefixes are strictly increasing
+            int32_t pos = 0;
+            for (int32_t step = top; step > 0; step >>= 1)
+                if (pos + step < nact && sact[pos + step] <= pre) pos += step;
+            if (sact[pos] != pre) continue;
+            const int32_t b = pos * 256 + (int32_t)((k >> shift) & 255u);
+            // the key of some row with the prefix: a plain store, the one row's key when only one
+            // row has it (with several, the value is never used)
+            if (in_lds) {
+                atomicAdd(&h[b], 1);
+                lmax[pos] = k;
+            } else {
+                atomicAdd(&gh[b], 1);
+                kmax[pos] = k;
+            }
+        }
+    }
+    __syncthreads();
+    if (in_lds) {
+        for (int32_t b = threadIdx.x; b < nact * 256; b += 1024)
+            if (h[b]) atomicAdd(&gh[b], h[b]);
+        for (int32_t a = threadIdx.x; a < nact; a += 1024)
+            if (lmax[a]) kmax[a] = lmax[a];
     }
 }
 
-// the row at rank q of the (value, row) order goes to partition floor(q p / n)
-__global__ void __launch_bounds__(kBlock) slice_parts_kernel(const uint32_t* __restrict__ order,
-                                                              int64_t n, int32_t p,
-                                                              int32_t* __restrict__ part) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < n) part[order[q]] = (int32_t)((q * (int64_t)p) / n);
+// every boundary moves into its digit (one wave per boundary: prefix over the 256 bins of its
+// slot), the histograms are cleared for the next digit, and the active prefixes recomputed
+__global__ void __launch_bounds__(1024) sel_find_kernel(int32_t p, int32_t* __restrict__ sel,
+                                                        unsigned long long* __restrict__ bkey) {
+    const int32_t nb = p - 1;
+    int32_t* rem = sel + sel_rem_off(p);
+    int32_t* slot = sel + sel_slot_off(p);
+    int32_t* gh = sel + SEL_H;
+    const int lane = (int)lane_id();
+    for (int32_t e = threadIdx.x / kWave; e < nb; e += 1024 / kWave) {
+        const int32_t a = slot[e];
+        if (a < 0) continue;  // (uniform per wave)
+        const int32_t* hs = gh + (int64_t)a * 256;
+        int32_t c[4], t = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = hs[lane * 4 + k];
+            t += c[k];
+        }
+        int32_t v = t;  // inclusive prefix of the lanes' sums
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int32_t o = __shfl_up(v, off, kWave);
+            if (lane >= off) v += o;
+        }
+        const int32_t r = rem[e];
+        if (__shfl(v, kWave - 1, kWave) == 1) {  // one row has the prefix: the boundary is its key
+            if (lane == 0) {
+                bkey[e] = bkey[2 * p + a];
+                slot[e] = -2;
+            }
+            continue;
+        }
+        // the digit: the last bin whose exclusive prefix is <= r
+        int32_t ex = v - t, dig = -1, below = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (ex <= r) { dig = lane * 4 + k; below = ex; }
+            ex += c[k];
+        }
+        // the highest lane with a digit holds the answer
+        const uint64_t m = __ballot(dig >= 0);
+        const int src = 63 - __clzll((long long)m);
+        dig = __shfl(dig, src, kWave);
+        below = __shfl(below, src, kWave);
+        if (lane == 0) {
+            bkey[e] = (bkey[e] << 8) | (unsigned long long)dig;
+            rem[e] = r - below;
+        }
+    }
+    __syncthreads();
+    const int32_t nact = sel[sel_nact_off(p)];
+    for (int32_t b = threadIdx.x; b < nact * 256; b += 1024) gh[b] = 0;
+    for (int32_t a = threadIdx.x; a < nact; a += 1024) bkey[2 * p + a] = 0;
+    __syncthreads();
+    sel_slots(bkey, nb, slot, bkey + p, sel + sel_nact_off(p));
 }
 
 __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
@@ -696,13 +972,24 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
         hipLaunchKernelGGL(angular_table_kernel, dim3(1), dim3(256), 0, st, a.m, a.tan2);
         SKY_HIP(hipGetLastError());
     } else if (a.scheme == SKY_SLICED && multi) {
-        // the rank of every row in the (value, row) order of the slicing attribute
-        hipLaunchKernelGGL(slice_keys_kernel, dim3(rblocks), dim3(kBlock), 0, st, a.x, n, a.slice_dim, a.ld,
-                           a.k0, a.v0);
-        SKY_HIP(hipGetLastError());
-        SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, 32, a.radix_tmp, st));
-        hipLaunchKernelGGL(slice_parts_kernel, dim3(rblocks), dim3(kBlock), 0, st, (const uint32_t*)a.v0, n, a.p,
-                           a.part_of_row);
+        // the keys at the boundary ranks of the (value, row) order of the slicing attribute
+        const int64_t zc = slice_select_elems(a.p);
+        hipLaunchKernelGGL(sel_zero_kernel, dim3((uint32_t)(ceil_div(zc, kBlock) < 1024 ? ceil_div(zc, kBlock) : 1024)),
+                           dim3(kBlock), 0, st, a.sel_i32, zc);
+        int dev = 0, cus = 0;
+        SKY_HIP(hipGetDevice(&dev));
+        SKY_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        const int64_t nch = ceil_div(n, kSelChunk);
+        const uint32_t sblocks = (uint32_t)(nch < 1 ? 1 : (nch < 2 * (int64_t)cus ? nch : 2 * (int64_t)cus));
+        hipLaunchKernelGGL(sel_hist0_kernel, dim3(sblocks), dim3(1024), 0, st, a.x, n, a.slice_dim, a.ld,
+                           a.sel_i32);
+        hipLaunchKernelGGL(sel_find0_kernel, dim3(1), dim3(1024), 0, st, n, a.p, a.sel_i32, a.sel_key);
+        for (int k = 0; k < kSelPasses; ++k) {
+            const int32_t shift = 8 * (kSelPasses - 1 - k);
+            hipLaunchKernelGGL(sel_hist_kernel, dim3(sblocks), dim3(1024), 0, st, a.x, n, a.slice_dim, a.ld, a.p,
+                               shift, a.sel_i32, a.sel_key);
+            hipLaunchKernelGGL(sel_find_kernel, dim3(1), dim3(1024), 0, st, a.p, a.sel_i32, a.sel_key);
+        }
         SKY_HIP(hipGetLastError());
     }
     // 1. classify
@@ -710,9 +997,11 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     ca.x = a.x; ca.n = n; ca.d = a.d; ca.ld = a.ld;
     ca.scheme = multi ? a.scheme : SKY_NONE; ca.p = a.p; ca.m = a.m;
     ca.tan2 = a.tan2; ca.seg_off = a.seg_off;
+    ca.slice_dim = a.slice_dim; ca.bkey = a.sel_key;
     ca.part_of_row = part_of_row; ca.pcount = a.pcount; ca.kmin = a.kmin;
     ca.dev_status = a.dev_status;
-    const size_t clds = (size_t)a.p * (sizeof(unsigned long long) + sizeof(int32_t));
+    const size_t clds = (size_t)a.p * (sizeof(unsigned long long) + sizeof(int32_t)) +
+                        (ca.scheme == SKY_SLICED ? (size_t)(a.p - 1) * sizeof(unsigned long long) : 0);
     SKY_DISPATCH_D(a.d, classify_kernel, dim3(pblocks), dim3(kPT), clds, st, ca);
     SKY_HIP(hipGetLastError());
     // 2. partition offsets; Grid pruning

@@ -19,6 +19,8 @@ struct sky_plan {
     int32_t* part_off = nullptr;
     uint8_t* pruned = nullptr;
     double* tan2_dev = nullptr;
+    unsigned long long* sel_key = nullptr;  // Sliced: [3 p] boundary keys, active prefixes, maxima
+    int32_t* sel_i32 = nullptr;             // Sliced: selection histograms and state
     int64_t* seg_off_dev = nullptr;  // kSchemeSegments: dataset row offsets [p+1]
     int32_t *part_of_row = nullptr, *scan_tmp = nullptr;
     // the build's prefilter (killer rows per partition) and the kept rows
