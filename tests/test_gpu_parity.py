@@ -211,6 +211,36 @@ def test_skyline_duplicates_and_small_p(dev):
         check_partitioned(x, scheme, p, part, loc, info)
 
 
+@pytest.mark.parametrize("case", ["ties5", "signed_zeros", "p_eq_n", "adjacent_floats", "p4096",
+                                  "slice_dim2"])
+def test_sliced_boundaries(dev, case):
+    """Sliced ids (Sec. 3.1: the (value, row) order of the slicing attribute cut into p equal
+    runs) where the boundary keys are hard to find: ties across every boundary, -0 and +0 mixed,
+    one row per partition, values a few ulps apart, more boundary prefixes than the selection
+    keeps in LDS, another slicing attribute. Ids against the oracle's, and the skyline."""
+    rng = np.random.default_rng(71)
+    dim = 0
+    if case == "ties5":
+        x, p = (rng.integers(0, 5, (50000, 3)) / 5).astype(np.float32), 64
+    elif case == "signed_zeros":
+        x, p = rng.random((3000, 2), dtype=np.float32), 16
+        x[::3, 0] = 0.0
+        x[1::3, 0] = -0.0
+    elif case == "p_eq_n":
+        x, p = rng.random((200, 3), dtype=np.float32), 200
+    elif case == "adjacent_floats":
+        x, p = rng.random((30000, 3), dtype=np.float32), 32
+        bits = np.float32(0.7).view(np.uint32) + rng.integers(0, 40, 30000).astype(np.uint32)
+        x[:, 0] = bits.view(np.float32)
+    elif case == "p4096":
+        x, p = rng.random((20000, 2), dtype=np.float32), 4096
+    else:
+        x, p, dim = G.ties(40000, 4, 5, levels=30), 64, 2
+    _, idx, part, loc, info = run_skyline(dev, x, "sliced", p, slice_dim=dim)
+    check_partitioned(x, "sliced", p, part, loc, info, slice_dim=dim)
+    assert np.array_equal(idx, np.flatnonzero(oracle.skyline(x)))
+
+
 def test_skyline_all_equal(dev):
     x = np.full((4000, 4), 0.25, np.float32)
     _, idx, _, _, _ = run_skyline(dev, x, "none")
