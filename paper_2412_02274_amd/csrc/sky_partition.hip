@@ -1054,8 +1054,11 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const uint32_t* order = nullptr;
     SKY_TRY(launch_radix_sort(a.k0, a.v0, a.k1, a.v1, n, key_bits, a.radix_tmp, st, &sorted_keys, &order,
                               a.n_live));
-    // 6. the partition-contiguous copy
-    SKY_DISPATCH_D(a.d, part_gather_kernel, dim3(rblocks < 8192u ? rblocks : 8192u), dim3(kBlock), 0, st, sorted_keys, order,
+    // 6. the partition-contiguous copy (with several partitions, fewer and longer wave runs: each
+    // wave adds its runs' score ranges to the partitions' with atomics, which queue when many
+    // waves share a partition)
+    const uint32_t gcap = multi ? 512u : 8192u;
+    SKY_DISPATCH_D(a.d, part_gather_kernel, dim3(rblocks < gcap ? rblocks : gcap), dim3(kBlock), 0, st, sorted_keys, order,
                    (const int32_t*)a.n_live, a.d, cbits * a.d, multi ? 1 : 0, (const float*)a.xa, a.xp, a.ldp,
                    a.rowid, a.seg, a.fsum, a.smin, a.smax);
     SKY_HIP(hipGetLastError());
