@@ -377,17 +377,22 @@ __global__ void __launch_bounds__(kPT) filter_kernel(FilterArgs a) {
     const bool in_lds = a.killers && tab <= kKillLds;
     unsigned int* ltests = fl;
     float* lk = reinterpret_cast<float*>(fl + ((a.p + 3) & ~3));  // 16-byte aligned
-    int32_t* lr = reinterpret_cast<int32_t*>(lk + (in_lds ? tab : 0));
+    // in LDS the partitions' killer blocks are padded (values by 4 floats, row ids by 1): the
+    // lanes of a wave look up different partitions, and unpadded blocks 128 bytes apart would
+    // all start in the same banks
+    constexpr int kVS = kKill * RS + 4, kRS = kKill + 1;
+    int32_t* lr = reinterpret_cast<int32_t*>(lk + (in_lds ? (int64_t)a.p * kVS : 0));
     if (a.killers) {
         for (int32_t j = threadIdx.x; j < a.p; j += kPT) ltests[j] = 0u;
         if (in_lds) {
-            for (int64_t e = threadIdx.x; e < tab; e += kPT) lk[e] = a.kval[e];
-            for (int64_t e = threadIdx.x; e < (int64_t)a.p * kKill; e += kPT) lr[e] = a.krow[e];
+            for (int64_t e = threadIdx.x; e < tab; e += kPT) lk[(e / (kKill * RS)) * kVS + e % (kKill * RS)] = a.kval[e];
+            for (int64_t e = threadIdx.x; e < (int64_t)a.p * kKill; e += kPT) lr[(e / kKill) * kRS + e % kKill] = a.krow[e];
         }
         __syncthreads();
     }
     const float* ktab = in_lds ? lk : a.kval;
     const int32_t* rtab = in_lds ? lr : a.krow;
+    const int64_t vstride = in_lds ? kVS : kKill * RS, rstride = in_lds ? kRS : kKill;
     int32_t kept = 0;
     const int64_t b0 = (int64_t)blockIdx.x * kPRows;
     {
@@ -413,12 +418,11 @@ __global__ void __launch_bounds__(kPT) filter_kernel(FilterArgs a) {
                 if (a.pruned && a.pruned[part[u]]) {
                     live = false;  // Def. 3: the rows of a pruned cell take no part
                 } else {
-                    const int64_t kb = (int64_t)part[u] * kKill;
 #pragma unroll
                     for (int s = 0; s < kKill; ++s) {
-                        const int32_t r = rtab[kb + s];
+                        const int32_t r = rtab[part[u] * rstride + s];
                         float sv[RS];
-                        load_row<D>(ktab + (kb + s) * RS, sv);
+                        load_row<D>(ktab + part[u] * vstride + s * RS, sv);
                         if (live && r >= 0 && r != (int32_t)i) {
                             ++nt;
                             bool le = true, lt = false;
@@ -1034,7 +1038,9 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     size_t flds = 0;
     if (a.prefilter) {
         flds = sizeof(unsigned int) * (size_t)((a.p + 3) & ~3);
-        if (tab <= kKillLds) flds += sizeof(float) * (size_t)tab + sizeof(int32_t) * (size_t)a.p * kKill;
+        if (tab <= kKillLds)  // padded blocks (filter_kernel)
+            flds += sizeof(float) * (size_t)a.p * (size_t)(kKill * partition_row_stride(a.d) + 4) +
+                    sizeof(int32_t) * (size_t)a.p * (kKill + 1);
     }
     SKY_DISPATCH_D(a.d, filter_kernel, dim3(pblocks), dim3(kPT), flds, st, fa);
     SKY_HIP(hipGetLastError());

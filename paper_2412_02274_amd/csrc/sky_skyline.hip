@@ -65,7 +65,8 @@ constexpr int kProbe = 8;     // best-score candidates of a tile tried first aga
 constexpr uint32_t kPad = 0x7FFFFFFFu;  // padding candidates: above every real value, also as int32
 constexpr int kBoxLds = 4096;           // uint32 tile-box values cached in LDS per workgroup
 constexpr uint32_t kMaxGrid = 8192;     // workgroups of the grid-stride kernels
-constexpr uint32_t kTestGridLater = 8192;  // most workgroups of a test launch after the first round
+constexpr uint32_t kTestGridLater = 2048;  // most workgroups of a test launch after the first round
+constexpr uint32_t kGridLater = 1024;      // most workgroups of a row pass after the first round
 
 // seg_info layout per segment (int32 x kInfo)
 enum { SI_LIVE = 0, SI_BSTAR, SI_HEADN, SI_HEADOFF, SI_RESTN, SI_RESTOFF, SI_LISTOFF, SI_HEADPRE, kInfo = 8 };
@@ -1392,6 +1393,10 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
         int32_t* rest_buf[2] = {b.rest, b.w0};
         for (int32_t r = 1; r <= R; ++r) {
             const int64_t ub = ubs[r - 1];
+            // rounds after the first often turn out empty (the host bound cannot see that):
+            // their grid-stride launches use fewer workgroups, which costs little when they are
+            // not
+            auto later = [&](uint32_t g) -> uint32_t { return r > 1 && g > kGridLater ? kGridLater : g; };
             const int32_t* items = r == 1 ? pb.items : rest_buf[(r - 1) & 1];
             const int32_t n_host = r == 1 ? pb.n_items : 0;
             const int32_t* n_dev = r == 1 ? pb.n_items_dev : ctr(r - 1) + C_RTOT;
@@ -1432,7 +1437,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
             if (nseg == 1)
                 hipLaunchKernelGGL(stats_kernel<false>, dim3(iblocks < 256 ? iblocks : 256), dim3(kBlock), 0, st, sa);
             else
-                hipLaunchKernelGGL(stats_kernel<true>, dim3(grid(seg_pass_blocks(ub))), dim3(kBlock), 0, st, sa);
+                hipLaunchKernelGGL(stats_kernel<true>, dim3(later(grid(seg_pass_blocks(ub)))), dim3(kBlock), 0, st, sa);
             SKY_HIP(hipGetLastError());
             const int32_t want_head = (int32_t)round_head(r);
             const int32_t all_below = r == R ? (int32_t)0x7FFFFFFF : (int32_t)round_all(r);
@@ -1457,7 +1462,7 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
             hipLaunchKernelGGL(split_scatter_kernel, dim3(cblocks), dim3(kBlock), 0, st, xa);
             SKY_HIP(hipGetLastError());
             const int64_t slot_bound = ub + (int64_t)kTile * nseg;
-            SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(grid(ceil_div(slot_bound, kTile * (kBlock / kWave)))),
+            SKY_DISPATCH_D(pb.d, head_values_kernel, dim3(later(grid(ceil_div(slot_bound, kTile * (kBlock / kWave))))),
                            dim3(kBlock), 0, st, pb.xp, pb.ldp, pb.d, pb.fsum, nseg, (const int32_t*)info_of(r),
                            (const int32_t*)ctr(r), b.head, b.hval, b.hcap, b.hlo, b.hhi, b.tcap);
             SKY_HIP(hipGetLastError());
