@@ -570,12 +570,12 @@ sky_status sky_gres(sky_plan* P, int32_t g_max, int32_t* g_exit, float* gres, vo
     const int32_t* s_dev = P->count_tmp + CT_SKY;
     // candidates from the partition-contiguous copy at the skyline's positions (ascending, hence
     // curve order inside each partition); pos_tmp maps a row to its index in sky_idx
+    // (every candidate is a target: written with the store, no exit yet)
     SKY_TRY(launch_gres_prepare_positions(P->xp, P->ldp, P->d, P->final_list, c, s_dev, P->rowid, P->pos_tmp,
-                                          store, dev_status, st));
-    SKY_TRY(launch_gres_targets_all(store, P->d, c, s_dev, tg, st));
+                                          store, dev_status, st, &tg));
     return launch_gres_search(store, P->d, (int32_t)c, tg, c, s_dev, nullptr, nullptr, g_max, mapping, g_exit, gres,
                               opts ? opts->ev_begin : nullptr, opts ? opts->ev_end : nullptr,
-                              opts ? opts->dev_tests : nullptr, st, &keys);
+                              opts ? opts->dev_tests : nullptr, st, &keys, true);
 }
 
 size_t gres_gbar_workspace_bytes(int64_t n) {

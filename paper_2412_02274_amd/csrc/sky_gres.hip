@@ -130,6 +130,9 @@ __global__ void __launch_bounds__(kBlock) store_kernel(const float* __restrict__
 // pos[0, s), already in curve order (the copy is), so no sort is needed; the caller index of a
 // slot is idx_of_row[row]. s = min(*s_dev, cap) when s_dev is given. Slots from s to the end of
 // its tile, and the store's last tile, get padding (2.0, ~0, -1); slots beyond are never read.
+// With tval given, every candidate is also a target: its values, its own tile as the hint, its
+// caller index, and no exit yet (ge = 1). With seg_coff given, the store's one segment is
+// recorded (s candidates from slot 0; a device count above s_host raises SKY_ERR_CAPACITY).
 __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restrict__ xp, int64_t ldp,
                                                             int32_t d, const int32_t* __restrict__ pos,
                                                             int32_t s_host, const int32_t* __restrict__ s_dev,
@@ -137,9 +140,18 @@ __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restri
                                                             const int32_t* __restrict__ idx_of_row,
                                                             float* __restrict__ cand, int64_t ccap,
                                                             uint32_t* __restrict__ ckey,
-                                                            int32_t* __restrict__ perm) {
+                                                            int32_t* __restrict__ perm, float* __restrict__ tval,
+                                                            int64_t tvcap, int32_t* __restrict__ thint,
+                                                            int32_t* __restrict__ tout, int32_t* __restrict__ ge,
+                                                            int32_t* __restrict__ seg_coff,
+                                                            int32_t* __restrict__ seg_cnt, int32_t* dev_status) {
     int32_t s = s_host;
     if (s_dev) s = *s_dev < s_host ? *s_dev : s_host;
+    if (seg_coff && blockIdx.x == 0 && threadIdx.x == 0) {  // the store's one segment
+        if (s_dev && *s_dev > s_host) raise_status(dev_status, SKY_ERR_CAPACITY);
+        seg_coff[0] = 0;
+        seg_cnt[0] = s;
+    }
     const int64_t used = ((int64_t)s + kTileC - 1) / kTileC * kTileC;
     const int64_t lim = used + kTileC;  // then the last tile, [ccap - 64, ccap)
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < lim; i += (int64_t)gridDim.x * kBlock) {
@@ -152,7 +164,14 @@ __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restri
             cand[(int64_t)k * ccap + q] = v[k];
         }
         ckey[q] = real ? hilbert_key(v, d, curve_bits(d)) : 0xFFFFFFFFu;
-        perm[q] = real ? idx_of_row[rowid[p]] : -1;
+        const int32_t pm = real ? idx_of_row[rowid[p]] : -1;
+        perm[q] = pm;
+        if (tval && real) {
+            for (int k = 0; k < d; ++k) tval[(int64_t)k * tvcap + q] = v[k];
+            thint[q] = (int32_t)(q / kTileC);
+            tout[q] = pm;
+            ge[q] = 1;
+        }
     }
 }
 
@@ -418,7 +437,9 @@ __host__ __device__ inline void search_shape(int32_t nt, int32_t g_max, int32_t*
 }
 
 __global__ void search_setup_kernel(const int32_t* __restrict__ nt_dev, int32_t nt_cap, int32_t g_max,
-                                    int32_t mapping, int32_t* __restrict__ params) {
+                                    int32_t mapping, int32_t* __restrict__ params, int32_t* __restrict__ work) {
+    if (work)  // the work counters of the persistent search, cleared
+        for (int i = threadIdx.x; i < kWorkCounters * kCounterStride; i += blockDim.x) work[i] = 0;
     if (threadIdx.x != 0) return;
     const int32_t nt = *nt_dev < nt_cap ? *nt_dev : nt_cap;
     int32_t per_wg, blocks, lb;
@@ -1428,30 +1449,20 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
 sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
                                          int64_t cap64, const int32_t* s_dev, const int32_t* rowid,
                                          const int32_t* idx_of_row, const GresStore& store,
-                                         int32_t* dev_status, hipStream_t st) {
+                                         int32_t* dev_status, hipStream_t st, const GresTargets* tg) {
     const int32_t cap = (int32_t)cap64;
     auto grid = [](int64_t want, int64_t most) -> uint32_t {
         return (uint32_t)(want < 1 ? 1 : (want > most ? most : want));
     };
-    hipLaunchKernelGGL(single_segment_kernel, dim3(1), dim3(64), 0, st, store.seg_coff, store.seg_cnt, cap, s_dev,
-                       dev_status);
     hipLaunchKernelGGL(store_pos_kernel, dim3(grid(ceil_div(round_up(cap, kTileC) + kTileC, kBlock), 2048)),
                        dim3(kBlock), 0, st, xp, ldp, d, pos, cap, s_dev, rowid, idx_of_row, store.cand, store.ccap,
-                       store.ckey, store.perm);
+                       store.ckey, store.perm, tg ? tg->tval : nullptr, tg ? tg->tvcap : 0,
+                       tg ? tg->thint : nullptr, tg ? tg->tout : nullptr, tg ? tg->ge : nullptr, store.seg_coff,
+                       store.seg_cnt, dev_status);
     const int64_t ntile = ceil_div(cap, kTileC);
     hipLaunchKernelGGL(tile_box_kernel, dim3(grid(ceil_div(ntile, kBlock / kWave), 2048)), dim3(kBlock), 0, st,
                        (const float*)store.cand, store.ccap, d, (int32_t)ntile, s_dev, cap, store.lo, store.hi,
                        store.tcap);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
-}
-
-sky_status launch_gres_targets_all(const GresStore& store, int32_t d, int64_t cap64, const int32_t* s_dev,
-                                   const GresTargets& tg, hipStream_t st) {
-    const int64_t blocks = ceil_div(cap64 > 0 ? cap64 : 1, kBlock);
-    hipLaunchKernelGGL(targets_all_kernel, dim3((uint32_t)(blocks > 1024 ? 1024 : blocks)), dim3(kBlock), 0, st,
-                       (const float*)store.cand, store.ccap, (int32_t)cap64, s_dev, d,
-                       (const int32_t*)store.perm, tg.tval, tg.tvcap, tg.thint, tg.tout);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
@@ -1538,7 +1549,8 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                               const GresTargets& tg, int64_t nt64, const int32_t* nt_dev, const int32_t* tseg,
                               const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
-                              unsigned long long* dev_tests, hipStream_t st, const GresKeys* keys) {
+                              unsigned long long* dev_tests, hipStream_t st, const GresKeys* keys,
+                              bool ge_ready) {
     const int32_t nt = (int32_t)nt64;  // with a count on the device: an upper bound of it
     if (nt <= 0) return SKY_OK;
     const bool batch = tseg != nullptr;
@@ -1584,10 +1596,12 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
     int32_t per_wg = 0, lbands = 1, blocks = 0;
     search_shape(nt, g_max, &per_wg, &blocks, &lbands);
     int32_t* params = on_dev ? tg.params : nullptr;
-    if (nt_dev) {
-        hipLaunchKernelGGL(search_setup_kernel, dim3(1), dim3(64), 0, st, nt_dev, nt, g_max, mapping, params);
+    if (nt_dev) {  // the shape from the device count; it also clears the work counters of the
+                   // persistent tile search (a batch's own setup has filled params)
+        hipLaunchKernelGGL(search_setup_kernel, dim3(1), dim3(256), 0, st, nt_dev, nt, g_max, mapping, params,
+                           mapping != SKY_GRES_LEVELS ? tg.work : nullptr);
         SKY_HIP(hipGetLastError());
-    }  // (a batch's own setup has filled params)
+    }
     // TILES: the levels are split into bands searched by separate workgroups (band-major
     // order), so a tuple that scans many levels is not one long sequential chain
     int32_t nbands = (int32_t)ceil_div(g_max - 1, kBandLevels);
@@ -1611,7 +1625,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
         gstart = tg.gstart;
     }
     // no exit (1) until a band finds one
-    {
+    if (!ge_ready) {
         const int64_t fb = ceil_div(nt, kBlock);
         hipLaunchKernelGGL(fill_targets_kernel, dim3((uint32_t)(fb > 1024 ? 1024 : fb)), dim3(kBlock), 0, st, tg.ge,
                            nt, (const int32_t*)params, 1);
@@ -1647,7 +1661,7 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                         ? (uint32_t)kStrideGrid : stride_grid * (uint32_t)kMaxLevelBands;
         }
     }
-    if (work) {
+    if (work && !(nt_dev && mapping != SKY_GRES_LEVELS)) {  // (else cleared by the setup)
         hipLaunchKernelGGL(fill_i32_kernel, dim3(kWorkCounters * kCounterStride / kBlock), dim3(kBlock), 0,
                            st, work, kWorkCounters * kCounterStride, 0);
         SKY_HIP(hipGetLastError());

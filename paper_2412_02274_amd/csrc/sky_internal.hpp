@@ -414,13 +414,12 @@ sky_status launch_gres_prepare(const float* x, int64_t n, int32_t d, int64_t ld,
 // Store from a plan's partition-contiguous copy xp: the candidates are the rows at positions
 // pos[0, s) (ascending, hence curve order), s = min(*s_dev, cap) read on the device (more than
 // cap raises SKY_ERR_CAPACITY); perm[slot] = idx_of_row[rowid[pos]]. The store is carved for cap.
+// With tg given, every candidate is also written as a target (values, own tile as the hint,
+// caller index) with no exit yet (tg.ge = 1), so that the search can skip its own fill (ge_ready).
 sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d, const int32_t* pos,
                                          int64_t cap, const int32_t* s_dev, const int32_t* rowid,
                                          const int32_t* idx_of_row, const GresStore& store,
-                                         int32_t* dev_status, hipStream_t st);
-// Targets = every candidate of a one-segment store whose count is on the device (min(*s_dev, cap)).
-sky_status launch_gres_targets_all(const GresStore& store, int32_t d, int64_t cap, const int32_t* s_dev,
-                                   const GresTargets& tg, hipStream_t st);
+                                         int32_t* dev_status, hipStream_t st, const GresTargets* tg = nullptr);
 sky_status launch_gres_targets(const float* x, int64_t n, int32_t d, int64_t ld, const int64_t* rows,
                                int64_t nt, int64_t s, const GresStore& store, const GresTargets& tg,
                                int32_t* dev_status, hipStream_t st);
@@ -462,6 +461,6 @@ sky_status launch_gres_search(const GresStore& store, int32_t d, int32_t max_cnt
                               const int32_t* tord, int32_t g_max, int32_t mapping, int32_t* g_exit,
                               float* gres, void* ev_begin, void* ev_end,
                               unsigned long long* dev_tests, hipStream_t st,
-                              const GresKeys* keys = nullptr);
+                              const GresKeys* keys = nullptr, bool ge_ready = false);
 
 }  // namespace sky
