@@ -947,11 +947,13 @@ int64_t partition_blocks(int64_t n) { return ceil_div(n > 0 ? n : 1, kPRows); }
 // default curve resolution (curve_bits) needs, at most four; the curve takes what is left.
 void partition_key_layout(int32_t p, int32_t d, int32_t* cbits, int32_t* key_bits) {
     const int pbits = p > 1 ? bits_for(p) : 0;
-    // at most three 8-bit passes: with many partitions the curve gets the bits the partition
-    // id leaves (a partition is a small part of the data space; measured: the fourth pass cost
-    // more than the finer order saved)
+    // three 8-bit passes where they leave the curve at least 4 bits per attribute next to the
+    // partition id (a partition is a small part of the data space; measured on 64 partitions
+    // of 4 attributes: the fourth pass cost more than the finer order saved), else up to four
+    // (with hundreds of relations of 8 attributes, 1 bit per attribute loses the order)
     int passes = (pbits + curve_bits(d) * d + 7) / 8;
-    if (passes > 3) passes = 3;
+    if (passes > 4) passes = 4;
+    if (passes == 4 && (24 - pbits) / d >= 4) passes = 3;
     int cb = (8 * passes - pbits) / d;
     cb = cb > 16 ? 16 : (cb < 1 ? 1 : cb);
     *cbits = cb;
