@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="batch/serve: skip the plain path")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch_4096":

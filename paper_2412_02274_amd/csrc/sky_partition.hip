@@ -973,7 +973,7 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const uint32_t pblocks = (uint32_t)partition_blocks(n);
     const bool multi = a.p > 1;
     int32_t* const part_of_row = multi ? a.part_of_row : nullptr;
-    // 0. counters of this build
+    // 0. counters of this partition step
     hipLaunchKernelGGL(partition_init_kernel, dim3((uint32_t)ceil_div((int64_t)a.p * kKill, kBlock)), dim3(kBlock),
                        0, st, a.p, a.pcount, a.kmin, a.seg_tests, a.tests, a.smin, a.smax);
     SKY_HIP(hipGetLastError());
