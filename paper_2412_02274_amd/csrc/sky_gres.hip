@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(1024) batch_layout_kernel(const int32_t* __res
 }
 
 // The search's shape for all S = cand_off[nseg] targets of a batch (as search_setup_kernel
-// gives it; AUTO decided by the largest relation's count, used[1]).
+// gives it; AUTO judged by the largest relation's count, used[1]).
 __global__ void batch_params_kernel(const int32_t* __restrict__ cand_off, int32_t nseg,
                                     const int32_t* __restrict__ used, int32_t g_max, int32_t mapping,
                                     int32_t* __restrict__ params) {
