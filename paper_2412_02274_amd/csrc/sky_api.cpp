@@ -167,6 +167,8 @@ sky_status plan_partition(sky_plan* P, hipStream_t st) {
     a.seg_tests = P->seg_tests;
     a.tests = reinterpret_cast<unsigned long long*>(P->dinfo + D_TESTS_FILTER);
     a.smin = P->eng.seg_min; a.smax = P->eng.seg_max;
+    // with the prefilter the local phase's first list is every position of the copy
+    a.iota_out = P->prefilter ? P->eng.w1 : nullptr;
     a.dev_status = P->dev_status;
     return launch_partition(a, st);
 }
@@ -328,8 +330,7 @@ sky_status plan_local_phase(sky_plan* P, hipStream_t st) {
     // the pruned cells and not filtered out by the representatives
     const int32_t* cnt = P->count_tmp + CT_LIST;
     if (P->prefilter) {
-        cnt = P->count_tmp + CT_ROWS;
-        SKY_TRY(launch_iota_count(cnt, n, P->eng.w1, st));
+        cnt = P->count_tmp + CT_ROWS;  // (the list itself is written by the build's copy)
     } else {
         SKY_TRY(launch_iota_filtered(skip, P->seg, n, P->eng.w1, P->count_tmp + CT_LIST, P->eng.scan_tmp, st,
                                      keep));

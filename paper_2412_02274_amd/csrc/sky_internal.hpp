@@ -231,6 +231,7 @@ struct PartitionArgs {
     unsigned long long* tests;      // out: the prefilter's tests in all
     uint32_t* smin; uint32_t* smax; // [p] out: per partition, the smallest and largest score
                                     // (bit pattern) of its positions
+    int32_t* iota_out;              // optional [n] out: 0, 1, ... for every position of the copy
     int32_t* dev_status;
 };
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }

@@ -136,13 +136,15 @@ __global__ void __launch_bounds__(kBlock) partition_init_kernel(int32_t p, int32
                                                                 unsigned long long* __restrict__ seg_tests,
                                                                 unsigned long long* __restrict__ tests,
                                                                 uint32_t* __restrict__ smin,
-                                                                uint32_t* __restrict__ smax) {
+                                                                uint32_t* __restrict__ smax,
+                                                                uint8_t* __restrict__ pruned) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g < p) {
         pcount[g] = 0;
         seg_tests[g] = 0ull;
         smin[g] = 0xFFFFFFFFu;
         smax[g] = 0u;
+        pruned[g] = 0;  // (Grid rewrites them after the counts)
     }
     if (g < (int64_t)p * kKill) kmin[g] = ~0ull;
     if (g == 0) *tests = 0ull;
@@ -530,7 +532,7 @@ __global__ void __launch_bounds__(kBlock) part_gather_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ rows, const int32_t* __restrict__ n_live,
     int32_t d_rt, int32_t pshift, int32_t multi, const float* __restrict__ xa, float* __restrict__ xp,
     int64_t ldp, int32_t* __restrict__ rowid, int32_t* __restrict__ seg, float* __restrict__ fsum,
-    uint32_t* __restrict__ smin, uint32_t* __restrict__ smax) {
+    uint32_t* __restrict__ smin, uint32_t* __restrict__ smax, int32_t* __restrict__ iota_out) {
     constexpr int RS = row_stride<D>();
     const int d = dget<D>(d_rt);
     const int lane = (int)lane_id();
@@ -557,6 +559,7 @@ __global__ void __launch_bounds__(kBlock) part_gather_kernel(
         rowid[q] = (int32_t)i;
         seg[q] = sg;
         fsum[q] = f;
+        if (iota_out) iota_out[q] = (int32_t)q;
         if (!multi) continue;  // one partition: the skyline rounds take its range themselves
         const uint32_t fb = fbits(f);  // f >= 0: bit order == value order
         if (sg != cs) {
@@ -873,11 +876,6 @@ __global__ void __launch_bounds__(1024) sel_find_kernel(int32_t p, int32_t* __re
     sel_slots(bkey, nb, slot, bkey + p, sel + sel_nact_off(p));
 }
 
-__global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // Angular bucket thresholds (Eq. (1)): tan2[k] = tan^2(k pi / (2m)) in FP64, tan2[0] = 0. A
 // row's bucket along an angle is the number of k in [1, m-1] whose threshold its ratio reaches.
 __global__ void angular_table_kernel(int32_t m, double* __restrict__ tan2) {
@@ -975,7 +973,7 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     int32_t* const part_of_row = multi ? a.part_of_row : nullptr;
     // 0. counters of this partition step
     hipLaunchKernelGGL(partition_init_kernel, dim3((uint32_t)ceil_div((int64_t)a.p * kKill, kBlock)), dim3(kBlock),
-                       0, st, a.p, a.pcount, a.kmin, a.seg_tests, a.tests, a.smin, a.smax);
+                       0, st, a.p, a.pcount, a.kmin, a.seg_tests, a.tests, a.smin, a.smax, a.pruned);
     SKY_HIP(hipGetLastError());
     if (a.scheme == SKY_ANGULAR) {
         hipLaunchKernelGGL(angular_table_kernel, dim3(1), dim3(256), 0, st, a.m, a.tan2);
@@ -1019,9 +1017,6 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     if (a.scheme == SKY_GRID && multi)
         hipLaunchKernelGGL(grid_prune_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)a.part_off, a.m, a.d,
                            a.p, a.pruned);
-    else
-        hipLaunchKernelGGL(fill_u8_kernel, dim3((uint32_t)ceil_div(a.p, 256)), dim3(256), 0, st, a.pruned,
-                           (int64_t)a.p, (uint8_t)0);
     SKY_HIP(hipGetLastError());
     // 3. killers and the prefilter (or every row kept)
     if (a.prefilter) {
@@ -1071,7 +1066,7 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const uint32_t gcap = multi ? 512u : 8192u;
     SKY_DISPATCH_D(a.d, part_gather_kernel, dim3(rblocks < gcap ? rblocks : gcap), dim3(kBlock), 0, st, sorted_keys, order,
                    (const int32_t*)a.n_live, a.d, cbits * a.d, multi ? 1 : 0, (const float*)a.xa, a.xp, a.ldp,
-                   a.rowid, a.seg, a.fsum, a.smin, a.smax);
+                   a.rowid, a.seg, a.fsum, a.smin, a.smax, a.iota_out);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
