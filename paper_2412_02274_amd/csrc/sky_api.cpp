@@ -169,6 +169,8 @@ sky_status plan_partition(sky_plan* P, hipStream_t st) {
     a.smin = P->eng.seg_min; a.smax = P->eng.seg_max;
     // with the prefilter the local phase's first list is every position of the copy
     a.iota_out = P->prefilter ? P->eng.w1 : nullptr;
+    // partition statistics (pruned Grid cells and their rows, the largest partition)
+    a.stats_out = P->dinfo + D_PRUNED_CELLS;
     a.dev_status = P->dev_status;
     return launch_partition(a, st);
 }
@@ -302,8 +304,6 @@ namespace sky {
 sky_status plan_local_phase(sky_plan* P, hipStream_t st) {
     P->last_stream = st;
     const int32_t n = (int32_t)P->n;
-    // partition statistics (pruned Grid cells and their rows, the largest partition)
-    SKY_TRY(launch_partition_stats(P->part_off, P->pruned, P->p, P->dinfo + D_PRUNED_CELLS, st));
     // the local phase's tests per partition (Sec. 4 counts its cost as the largest of them):
     // zeroed here when representatives add to them first, else by the engine run
     // rows of Grid cells pruned by grid dominance take no part (Def. 3)

@@ -232,6 +232,8 @@ struct PartitionArgs {
     uint32_t* smin; uint32_t* smax; // [p] out: per partition, the smallest and largest score
                                     // (bit pattern) of its positions
     int32_t* iota_out;              // optional [n] out: 0, 1, ... for every position of the copy
+    int64_t* stats_out;             // [3] out: pruned non-empty cells, rows inside them, rows of the
+                                    // largest partition
     int32_t* dev_status;
 };
 inline int32_t partition_row_stride(int32_t d) { return d <= 4 ? 4 : (d <= 8 ? 8 : 16); }
@@ -241,9 +243,7 @@ inline int64_t slice_select_elems(int32_t p) { return 16384 + 256 * (int64_t)p +
 // workgroups of the per-row passes of launch_partition (4096 rows each)
 int64_t partition_blocks(int64_t n);
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st);
-// out[0..3) = pruned non-empty cells, rows inside them, rows of the largest partition (int64)
-sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned, int32_t p, int64_t* out,
-                                  hipStream_t st);
+
 
 // sky_reps.hip: Representative Filtering (Sec. 3.1)
 struct RepArgs {

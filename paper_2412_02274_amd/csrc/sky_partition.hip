@@ -250,9 +250,51 @@ __global__ void __launch_bounds__(kPT) classify_kernel(ClassifyArgs a) {
     if (__ballot(bad) != 0 && lane_id() == 0) raise_status(a.dev_status, SKY_ERR_DOMAIN);
 }
 
+// Partition statistics (out[0..3) = pruned non-empty cells, rows inside them, rows of the
+// largest partition) by the whole workgroup (at most 1024 threads), once part_off (and pruned,
+// when given) are written: every thread calls it.
+__device__ void partition_stats_block(const int32_t* __restrict__ part_off, const uint8_t* __restrict__ pruned,
+                                      int32_t p, int64_t* __restrict__ out) {
+    __shared__ int64_t red[3][1024 / kWave];
+    __syncthreads();  // part_off / pruned of the other threads
+    int64_t pc = 0, pr = 0, mx = 0;
+    for (int32_t j = threadIdx.x; j < p; j += blockDim.x) {
+        const int64_t sz = (int64_t)part_off[j + 1] - part_off[j];
+        mx = sz > mx ? sz : mx;
+        if (pruned && pruned[j] && sz > 0) {
+            ++pc;
+            pr += sz;
+        }
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        pc += __shfl_xor(pc, off, kWave);
+        pr += __shfl_xor(pr, off, kWave);
+        const int64_t o = __shfl_xor(mx, off, kWave);
+        mx = o > mx ? o : mx;
+    }
+    if (lane_id() == 0) {
+        red[0][threadIdx.x / kWave] = pc;
+        red[1][threadIdx.x / kWave] = pr;
+        red[2][threadIdx.x / kWave] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) {
+            pc += red[0][w];
+            pr += red[1][w];
+            mx = red[2][w] > mx ? red[2][w] : mx;
+        }
+        out[0] = pc;
+        out[1] = pr;
+        out[2] = mx;
+    }
+}
+
 // ---- 2. partition offsets (one workgroup of 1024 threads, p <= 4096) --------------------------------
+// (stats given: no pruning follows, so the partition statistics are taken here)
 __global__ void __launch_bounds__(1024) part_offsets_kernel(const int32_t* __restrict__ pcount, int32_t p,
-                                                            int64_t n, int32_t* __restrict__ part_off) {
+                                                            int64_t n, int32_t* __restrict__ part_off,
+                                                            int64_t* __restrict__ stats) {
     __shared__ int32_t ws[1024 / kWave];
     const int per = (p + 1023) / 1024;  // at most 4
     int32_t loc[4];
@@ -281,6 +323,7 @@ __global__ void __launch_bounds__(1024) part_offsets_kernel(const int32_t* __res
         run += loc[e];
     }
     if (threadIdx.x == 0) part_off[p] = (int32_t)n;
+    if (stats) partition_stats_block(part_off, nullptr, p, stats);
 }
 
 // ---- Grid cell pruning (Def. 3) ------------------------------------------------------------------
@@ -288,7 +331,8 @@ __global__ void __launch_bounds__(1024) part_offsets_kernel(const int32_t* __res
 // axis; cell h is pruned iff all its coordinates are >= 1 and A[h - (1,...,1)].
 __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restrict__ part_off,
                                                            int32_t m, int32_t d, int32_t cells,
-                                                           uint8_t* __restrict__ pruned) {
+                                                           uint8_t* __restrict__ pruned,
+                                                           int64_t* __restrict__ stats) {
     __shared__ uint8_t A[SKY_MAX_CELLS];
     for (int c = threadIdx.x; c < cells; c += blockDim.x)
         A[c] = part_off[c + 1] > part_off[c] ? 1 : 0;
@@ -322,6 +366,7 @@ __global__ void __launch_bounds__(1024) grid_prune_kernel(const int32_t* __restr
         }
         pruned[h] = (all_pos && A[h - diag]) ? 1 : 0;
     }
+    partition_stats_block(part_off, pruned, cells, stats);
 }
 
 // ---- 3. killers and the prefilter ----------------------------------------------------------------
@@ -887,43 +932,6 @@ __global__ void angular_table_kernel(int32_t m, double* __restrict__ tan2) {
 
 // Partition statistics as int64 words: out[0] = Grid cells pruned by grid dominance that hold
 // rows, out[1] = the rows inside them, out[2] = rows of the largest partition (one workgroup).
-__global__ void __launch_bounds__(kBlock) partition_stats_kernel(const int32_t* __restrict__ part_off,
-                                                                  const uint8_t* __restrict__ pruned,
-                                                                  int32_t p, int64_t* __restrict__ out) {
-    __shared__ int64_t red[3][kBlock / kWave];
-    int64_t pc = 0, pr = 0, mx = 0;
-    for (int32_t j = threadIdx.x; j < p; j += kBlock) {
-        const int64_t sz = (int64_t)part_off[j + 1] - part_off[j];
-        mx = sz > mx ? sz : mx;
-        if (pruned[j] && sz > 0) {
-            ++pc;
-            pr += sz;
-        }
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        pc += __shfl_xor(pc, off, kWave);
-        pr += __shfl_xor(pr, off, kWave);
-        const int64_t o = __shfl_xor(mx, off, kWave);
-        mx = o > mx ? o : mx;
-    }
-    if (lane_id() == 0) {
-        red[0][threadIdx.x / kWave] = pc;
-        red[1][threadIdx.x / kWave] = pr;
-        red[2][threadIdx.x / kWave] = mx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / kWave; ++w) {
-            pc += red[0][w];
-            pr += red[1][w];
-            mx = red[2][w] > mx ? red[2][w] : mx;
-        }
-        out[0] = pc;
-        out[1] = pr;
-        out[2] = mx;
-    }
-}
-
 }  // namespace
 
 #define SKY_DISPATCH_D(d, KERNEL, ...)                                            \
@@ -958,12 +966,6 @@ void partition_key_layout(int32_t p, int32_t d, int32_t* cbits, int32_t* key_bit
     *key_bits = pbits + cb * d;
 }
 
-sky_status launch_partition_stats(const int32_t* part_off, const uint8_t* pruned, int32_t p, int64_t* out,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(partition_stats_kernel, dim3(1), dim3(kBlock), 0, st, part_off, pruned, p, out);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
-}
 
 sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     const int64_t n = a.n;
@@ -1012,11 +1014,12 @@ sky_status launch_partition(const PartitionArgs& a, hipStream_t st) {
     SKY_DISPATCH_D(a.d, classify_kernel, dim3(pblocks), dim3(kPT), clds, st, ca);
     SKY_HIP(hipGetLastError());
     // 2. partition offsets; Grid pruning
+    const bool prune = a.scheme == SKY_GRID && multi;
     hipLaunchKernelGGL(part_offsets_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)a.pcount, a.p, n,
-                       a.part_off);
-    if (a.scheme == SKY_GRID && multi)
+                       a.part_off, prune ? nullptr : a.stats_out);
+    if (prune)
         hipLaunchKernelGGL(grid_prune_kernel, dim3(1), dim3(1024), 0, st, (const int32_t*)a.part_off, a.m, a.d,
-                           a.p, a.pruned);
+                           a.p, a.pruned, a.stats_out);
     SKY_HIP(hipGetLastError());
     // 3. killers and the prefilter (or every row kept)
     if (a.prefilter) {
