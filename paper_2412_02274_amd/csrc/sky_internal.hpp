@@ -343,8 +343,6 @@ sky_status launch_iota_filtered(const uint8_t* skip_seg, const int32_t* seg_of_p
                                 int32_t* out, int32_t* count, int32_t* scan_tmp, hipStream_t st,
                                 const uint8_t* keep = nullptr);
 sky_status launch_fill_u8(uint8_t* p, int64_t n, uint8_t v, hipStream_t st);
-// out[q] = q for q < *count (count on the device, at most n)
-sky_status launch_iota_count(const int32_t* count, int32_t n, int32_t* out, hipStream_t st);
 // dst[rowid[q]] = src[q] && !(drop && drop[q]) for q < n (q < min(n, *count) with count, a
 // device word)
 sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, const int32_t* rowid, int64_t n,

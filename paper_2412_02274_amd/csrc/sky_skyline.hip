@@ -1145,12 +1145,6 @@ __global__ void __launch_bounds__(kBlock) scatter_rows_u8_kernel(const uint8_t* 
     const int64_t m = count ? (*count < n ? (int64_t)*count : n) : n;
     if (q < m) dst[rowid[q]] = (drop && drop[q]) ? 0 : src[q];
 }
-__global__ void __launch_bounds__(kBlock) iota_count_kernel(const int32_t* __restrict__ count, int32_t n,
-                                                             int32_t* __restrict__ out) {
-    const int32_t m = *count < n ? *count : n;
-    for (int32_t i = blockIdx.x * kBlock + threadIdx.x; i < m; i += gridDim.x * kBlock) out[i] = i;
-}
-
 __global__ void fill_u8_kernel(uint8_t* __restrict__ p, int64_t n, uint8_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1532,15 +1526,6 @@ sky_status launch_scatter_rows_live(const uint8_t* src, const uint8_t* drop, con
     if (n <= 0) return SKY_OK;
     hipLaunchKernelGGL(scatter_rows_u8_kernel, dim3((uint32_t)ceil_div(n, kBlock)), dim3(kBlock), 0, st, src,
                        drop, rowid, n, count, dst);
-    SKY_HIP(hipGetLastError());
-    return SKY_OK;
-}
-
-sky_status launch_iota_count(const int32_t* count, int32_t n, int32_t* out, hipStream_t st) {
-    if (n <= 0) return SKY_OK;
-    const int64_t nb = ceil_div(n, kBlock);
-    hipLaunchKernelGGL(iota_count_kernel, dim3((uint32_t)(nb < kMaxGrid ? nb : kMaxGrid)), dim3(kBlock), 0, st,
-                       count, n, out);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
