@@ -144,7 +144,9 @@ __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restri
                                                             int64_t tvcap, int32_t* __restrict__ thint,
                                                             int32_t* __restrict__ tout, int32_t* __restrict__ ge,
                                                             int32_t* __restrict__ seg_coff,
-                                                            int32_t* __restrict__ seg_cnt, int32_t* dev_status) {
+                                                            int32_t* __restrict__ seg_cnt, int32_t* dev_status,
+                                                            float* __restrict__ lo, float* __restrict__ hi,
+                                                            int64_t tcap) {
     int32_t s = s_host;
     if (s_dev) s = *s_dev < s_host ? *s_dev : s_host;
     if (seg_coff && blockIdx.x == 0 && threadIdx.x == 0) {  // the store's one segment
@@ -152,10 +154,14 @@ __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restri
         seg_coff[0] = 0;
         seg_cnt[0] = s;
     }
-    const int64_t used = ((int64_t)s + kTileC - 1) / kTileC * kTileC;
-    const int64_t lim = used + kTileC;  // then the last tile, [ccap - 64, ccap)
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < lim; i += (int64_t)gridDim.x * kBlock) {
-        const int64_t q = i < used ? i : ccap - kTileC + (i - used);
+    // one wave per tile (lane = slot): the tiles holding candidates, then the store's last tile
+    // [ccap - 64, ccap); each candidate tile's box (componentwise minimum and maximum of its real
+    // candidates) as tile_box_kernel takes it
+    const int64_t ntl = ((int64_t)s + kTileC - 1) / kTileC;
+    const int lane = (int)lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; t <= ntl; t += nwaves) {
+        const int64_t q = t < ntl ? t * kTileC + lane : ccap - kTileC + lane;
         const bool real = q < s;
         const int32_t p = real ? pos[q] : 0;
         float v[SKY_MAX_D];
@@ -172,6 +178,18 @@ __global__ void __launch_bounds__(kBlock) store_pos_kernel(const float* __restri
             tout[q] = pm;
             ge[q] = 1;
         }
+        if (t < ntl)  // (uniform per wave)
+            for (int k = 0; k < d; ++k) {
+                float mn = real ? v[k] : 1.0f, mx = real ? v[k] : 0.0f;
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    mn = fminf(mn, __shfl_xor(mn, off, kWave));
+                    mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+                }
+                if (lane == 0) {
+                    lo[(int64_t)k * tcap + t] = mn;
+                    hi[(int64_t)k * tcap + t] = mx;
+                }
+            }
     }
 }
 
@@ -1454,15 +1472,13 @@ sky_status launch_gres_prepare_positions(const float* xp, int64_t ldp, int32_t d
     auto grid = [](int64_t want, int64_t most) -> uint32_t {
         return (uint32_t)(want < 1 ? 1 : (want > most ? most : want));
     };
-    hipLaunchKernelGGL(store_pos_kernel, dim3(grid(ceil_div(round_up(cap, kTileC) + kTileC, kBlock), 2048)),
+    // the store, its tile boxes, and (tg) the targets: one wave per tile
+    const int64_t ntile = ceil_div(cap, kTileC);
+    hipLaunchKernelGGL(store_pos_kernel, dim3(grid(ceil_div(ntile + 1, kBlock / kWave), 2048)),
                        dim3(kBlock), 0, st, xp, ldp, d, pos, cap, s_dev, rowid, idx_of_row, store.cand, store.ccap,
                        store.ckey, store.perm, tg ? tg->tval : nullptr, tg ? tg->tvcap : 0,
                        tg ? tg->thint : nullptr, tg ? tg->tout : nullptr, tg ? tg->ge : nullptr, store.seg_coff,
-                       store.seg_cnt, dev_status);
-    const int64_t ntile = ceil_div(cap, kTileC);
-    hipLaunchKernelGGL(tile_box_kernel, dim3(grid(ceil_div(ntile, kBlock / kWave), 2048)), dim3(kBlock), 0, st,
-                       (const float*)store.cand, store.ccap, d, (int32_t)ntile, s_dev, cap, store.lo, store.hi,
-                       store.tcap);
+                       store.seg_cnt, dev_status, store.lo, store.hi, store.tcap);
     SKY_HIP(hipGetLastError());
     return SKY_OK;
 }
