@@ -124,17 +124,19 @@ __global__ void __launch_bounds__(kBlock) rs_scatter_kernel(
         const uint64_t lt = __lanemask_lt();
 #pragma unroll
         for (int c = 0; c < kRChunks; ++c) {
-            if (c >= nch) break;  // uniform
-            const bool valid = w0 + c * kWave + lane < n;
-            const uint64_t act = __ballot(valid);
-            const uint32_t dg = (k[c] >> shift) & 0xFFu;
-            const uint64_t peers = match_any(dg, 8, act);
-            const int32_t b = valid ? wc[wave][dg] : 0;
-            __builtin_amdgcn_wave_barrier();
-            r[c] = b + (int32_t)__popcll(peers & lt);
-            if (valid && (peers & lt) == 0) wc[wave][dg] = b + (int32_t)__popcll(peers);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_wave_barrier();
+            r[c] = 0;
+            if (c < nch) {  // (uniform)
+                const bool valid = w0 + c * kWave + lane < n;
+                const uint64_t act = __ballot(valid);
+                const uint32_t dg = (k[c] >> shift) & 0xFFu;
+                const uint64_t peers = match_any(dg, 8, act);
+                const int32_t b = valid ? wc[wave][dg] : 0;
+                __builtin_amdgcn_wave_barrier();
+                r[c] = b + (int32_t)__popcll(peers & lt);
+                if (valid && (peers & lt) == 0) wc[wave][dg] = b + (int32_t)__popcll(peers);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         __syncthreads();
         // 2. per digit (thread = digit): wave prefixes, the tile's digit starts, global bases
