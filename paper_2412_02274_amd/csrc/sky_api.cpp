@@ -114,8 +114,8 @@ void carve_plan(Carver& c, sky_plan* P, int64_t n, int32_t d, int32_t scheme, in
     e.hval = c.take<uint32_t>((size_t)(d * e.hcap));
     e.hlo = c.take<uint32_t>((size_t)(d * e.tcap));
     e.hhi = c.take<uint32_t>((size_t)(d * e.tcap));
-    e.seg_min = c.take<uint32_t>((size_t)p);
-    e.seg_max = c.take<uint32_t>((size_t)p);
+    e.seg_min = c.take<uint32_t>((size_t)range_elems(p));
+    e.seg_max = c.take<uint32_t>((size_t)range_elems(p));
     e.hist = c.take<int32_t>((size_t)2 * p * kBins);
     e.seg_info = c.take<int32_t>((size_t)2 * p * 8);
     e.dom = c.take<uint8_t>((size_t)n);
@@ -343,7 +343,10 @@ sky_status plan_local_phase(sky_plan* P, hipStream_t st) {
     // the prefilter's tests are already in seg_tests (the build zeroed them); representatives
     // add theirs above
     pb.zero_seg_tests = P->reps == 0 && !P->prefilter;
-    pb.ranges_ready = P->p > 1;  // the build's copy folded every partition's score range
+    // the build's copy folded the score range of every partition (of one partition, into the
+    // slots); its rows are the first list's unless representatives took some out
+    pb.ranges_ready = P->p > 1 || !keep;
+    pb.range_slots = P->p == 1;
     pb.extra_tests = reinterpret_cast<const unsigned long long*>(P->dinfo + D_TESTS_FILTER);
     pb.items = P->eng.w1;
     pb.n_items = n;

@@ -296,7 +296,7 @@ struct EngineBuffers {
     uint32_t* hlo;                 // [d][tcap] per-tile lower corners
     uint32_t* hhi;                 // [d][tcap] per-tile upper corners
     int64_t hcap, tcap;
-    uint32_t* seg_min; uint32_t* seg_max;   // [nseg]
+    uint32_t* seg_min; uint32_t* seg_max;   // [range_elems(nseg)]
     int32_t* hist;                 // [2][nseg * kBins] (by round parity)
     int32_t* seg_info;             // [2][nseg * 8] per-segment counters / offsets (by round parity)
     uint8_t* dom;                  // [n] dominated flags
@@ -308,6 +308,12 @@ struct EngineBuffers {
     int32_t* scan_tmp;             // scan scratch for n values
 };
 int64_t engine_head_capacity(int64_t n, int32_t nseg);
+// Score ranges of one segment are first gathered in kRangeSlots slots kRangeStride words apart
+// (slot 0 at index 0), so that thousands of workgroups do not queue on one address; the
+// skyline run's first kernel folds them into index 0. Several segments: one word each.
+constexpr int kRangeSlots = 64;
+constexpr int kRangeStride = 32;
+constexpr int64_t range_elems(int64_t nseg) { return nseg > 1 ? nseg : (int64_t)kRangeSlots * kRangeStride; }
 int64_t engine_scan_elems(int64_t n);
 constexpr int kBins = 1024;
 struct EngineProblem {
@@ -319,6 +325,8 @@ struct EngineProblem {
     bool zero_seg_tests;           // the run zeroes seg_tests first (else the caller has)
     bool ranges_ready;             // the caller has set b.seg_min / b.seg_max: for every segment, a
                                    // range of score bit patterns holding every item's score
+    bool range_slots;              // with ranges_ready and one segment: the range is still spread
+                                   // over the kRangeSlots slots
     const int32_t* items;          // initial work list (positions); not one of the engine's buffers
     int32_t n_items;               // its length, when n_items_dev is null
     const int32_t* n_items_dev;    // its length on the device (or null)

@@ -142,9 +142,12 @@ __global__ void __launch_bounds__(kBlock) partition_init_kernel(int32_t p, int32
     if (g < p) {
         pcount[g] = 0;
         seg_tests[g] = 0ull;
-        smin[g] = 0xFFFFFFFFu;
-        smax[g] = 0u;
         pruned[g] = 0;  // (Grid rewrites them after the counts)
+    }
+    if (g < (p > 1 ? p : kRangeSlots)) {  // one partition: its range slots
+        const int64_t at = p > 1 ? g : g * kRangeStride;
+        smin[at] = 0xFFFFFFFFu;
+        smax[at] = 0u;
     }
     if (g < (int64_t)p * kKill) kmin[g] = ~0ull;
     if (g == 0) *tests = 0ull;
@@ -571,7 +574,8 @@ __global__ void __launch_bounds__(kPT) compact_kernel(CompactArgs a) {
 // ---- 6. the partition-contiguous copy of the kept rows in key order --------------------------------
 // Each wave copies one contiguous run of positions (lanes 64 apart, coalesced) and folds the
 // scores of each partition it meets into that partition's range (smin / smax), which the
-// skyline rounds then use instead of a pass of their own.
+// skyline rounds then use instead of a pass of their own. One partition: each workgroup's range
+// goes to one of the kRangeSlots slots, which the skyline run's first kernel folds.
 template <int D>
 __global__ void __launch_bounds__(kBlock) part_gather_kernel(
     const uint32_t* __restrict__ keys, const uint32_t* __restrict__ rows, const int32_t* __restrict__ n_live,
@@ -605,8 +609,12 @@ __global__ void __launch_bounds__(kBlock) part_gather_kernel(
         seg[q] = sg;
         fsum[q] = f;
         if (iota_out) iota_out[q] = (int32_t)q;
-        if (!multi) continue;  // one partition: the skyline rounds take its range themselves
         const uint32_t fb = fbits(f);  // f >= 0: bit order == value order
+        if (!multi) {
+            cmin = fb < cmin ? fb : cmin;
+            cmax = fb > cmax ? fb : cmax;
+            continue;
+        }
         if (sg != cs) {
             if (cs >= 0) {
                 atomicMin(&smin[cs], cmin);
@@ -619,6 +627,32 @@ __global__ void __launch_bounds__(kBlock) part_gather_kernel(
             cmin = fb < cmin ? fb : cmin;
             cmax = fb > cmax ? fb : cmax;
         }
+    }
+    if (!multi) {
+        __shared__ uint32_t wr[2][kBlock / kWave];
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const uint32_t x = __shfl_xor(cmin, off, kWave), y = __shfl_xor(cmax, off, kWave);
+            cmin = x < cmin ? x : cmin;
+            cmax = y > cmax ? y : cmax;
+        }
+        if (lane == 0) {
+            wr[0][threadIdx.x / kWave] = cmin;
+            wr[1][threadIdx.x / kWave] = cmax;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t a0 = wr[0][0], a1 = wr[1][0];
+            for (int w = 1; w < kBlock / kWave; ++w) {
+                a0 = wr[0][w] < a0 ? wr[0][w] : a0;
+                a1 = wr[1][w] > a1 ? wr[1][w] : a1;
+            }
+            if (a0 <= a1) {  // the workgroup copied a row
+                const int64_t at = (int64_t)(blockIdx.x % (uint32_t)kRangeSlots) * kRangeStride;
+                atomicMin(&smin[at], a0);
+                atomicMax(&smax[at], a1);
+            }
+        }
+        return;
     }
     // the lanes' last runs, one pair of atomics per partition and wave
     const bool valid = cs >= 0;

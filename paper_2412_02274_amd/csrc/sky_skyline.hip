@@ -56,7 +56,7 @@ namespace sky {
 
 namespace {
 
-constexpr int kHead = 8192;      // head rows per segment in the first round (target)
+constexpr int kHead = 4096;      // head rows per segment in the first round (target)
 constexpr int kAllHead = 65536;  // first round: a segment with at most this many live rows takes them all
 constexpr int kMaxRounds = 16;   // schedule cap (the last round takes every live row)
 constexpr int kTargetWaves = 8192;  // waves per test launch the item split aims at
@@ -117,12 +117,12 @@ __device__ __forceinline__ int32_t wave_max_i32(int32_t v) {
 }
 
 // Start of a run: output flags cleared, the round records and histograms of both parities
-// cleared, every segment's score range empty, counters zeroed (and the per-segment test
-// counters, when given).
+// cleared, every segment's score range empty (fold: the one segment's range slots folded into
+// its range instead), counters zeroed (and the per-segment test counters, when given).
 __global__ void __launch_bounds__(kBlock) engine_init_kernel(
     int32_t n_pos, uint8_t* __restrict__ flag_out, int32_t nseg, int32_t* __restrict__ hist2,
     int32_t* __restrict__ info2, uint32_t* __restrict__ smin, uint32_t* __restrict__ smax,
-    int32_t* __restrict__ counters, unsigned long long* __restrict__ tests,
+    int32_t fold, int32_t* __restrict__ counters, unsigned long long* __restrict__ tests,
     unsigned long long* __restrict__ seg_tests) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t gs = (int64_t)gridDim.x * kBlock;
@@ -132,11 +132,25 @@ __global__ void __launch_bounds__(kBlock) engine_init_kernel(
     for (int64_t i = g; i < 2 * (int64_t)nseg * kBins; i += gs) hist2[i] = 0;
     for (int64_t i = g; i < 2 * (int64_t)nseg * kInfo; i += gs) info2[i] = 0;
     for (int64_t i = g; i < nseg; i += gs) {
-        if (smin) {  // (null: the caller has set the score ranges)
+        if (smin && !fold) {  // (null: the caller has set the score ranges)
             smin[i] = 0xFFFFFFFFu;
             smax[i] = 0u;
         }
         if (seg_tests) seg_tests[i] = 0ull;
+    }
+    if (fold && g < kWave) {  // one wave: the slots' minimum and maximum into index 0
+        const int lane = (int)g;
+        uint32_t a0 = lane < kRangeSlots ? smin[lane * kRangeStride] : 0xFFFFFFFFu;
+        uint32_t a1 = lane < kRangeSlots ? smax[lane * kRangeStride] : 0u;
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const uint32_t x = __shfl_xor(a0, off, kWave), y = __shfl_xor(a1, off, kWave);
+            a0 = x < a0 ? x : a0;
+            a1 = y > a1 ? y : a1;
+        }
+        if (lane == 0) {
+            smin[0] = a0;
+            smax[0] = a1;
+        }
     }
     if (g < 3 * kCounters) counters[g] = 0;
     if (g < 3) tests[g] = 0ull;
@@ -1362,11 +1376,13 @@ sky_status run_engine(const EngineProblem& pb, const EngineBuffers& b, hipStream
         return (uint32_t)(want < 1 ? 1 : (want > kMaxGrid ? kMaxGrid : want));
     };
     {
+        const bool fold = pb.ranges_ready && pb.range_slots && nseg == 1;
         int64_t work = pb.n_pos / 16;
         if (2 * (int64_t)nseg * kBins > work) work = 2 * (int64_t)nseg * kBins;
         hipLaunchKernelGGL(engine_init_kernel, dim3(grid(ceil_div(work, kBlock))), dim3(kBlock), 0, st,
-                           pb.n_pos, pb.flag_out, nseg, b.hist, b.seg_info, pb.ranges_ready ? nullptr : b.seg_min,
-                           pb.ranges_ready ? nullptr : b.seg_max, b.counters, b.tests,
+                           pb.n_pos, pb.flag_out, nseg, b.hist, b.seg_info,
+                           pb.ranges_ready && !fold ? nullptr : b.seg_min,
+                           pb.ranges_ready && !fold ? nullptr : b.seg_max, fold ? 1 : 0, b.counters, b.tests,
                            pb.zero_seg_tests ? pb.seg_tests : nullptr);
         SKY_HIP(hipGetLastError());
     }
