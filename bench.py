@@ -60,11 +60,23 @@ class HipEvents:
         self.ev = []
 
 
+def source_sha(name):
+    """First 16 hex digits of the SHA-256 of a kernel source file followed by the headers every
+    kernel includes (csrc/sky_internal.hpp, include/sky.h): the key under which the committed
+    profiles store a kernel's counters."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in (os.path.join(ROOT, "paper_2412_02274_amd", "csrc", name),
+                 os.path.join(ROOT, "paper_2412_02274_amd", "csrc", "sky_internal.hpp"),
+                 os.path.join(ROOT, "include", "sky.h")):
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def stored_traffic(workload):
     """HBM bytes per step of the dominance-test kernel and per launch of the gres search kernel
     from the committed PMC summary (profiles/traffic_<workload>.txt); each is None when its
     kernel source changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     out = {"dominance_test": None, "gres_search": None}
     if not os.path.exists(path):
@@ -74,8 +86,7 @@ def stored_traffic(workload):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    csrc = os.path.join(ROOT, "paper_2412_02274_amd", "csrc")
-    sha = lambda f: hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+    sha = source_sha
     if kv.get("src_sha256_16") == sha("sky_skyline.hip"):
         out["dominance_test"] = int(kv["fetch_bytes_per_step"]) + int(kv["write_bytes_per_step"])
     if "gres_search_fetch_bytes" in kv and kv.get("gres_search_src_sha256_16") == sha("sky_gres.hip"):
@@ -88,7 +99,6 @@ def stored_valu(workload):
     (profiles/valu_<workload>.txt): per kernel, the VALU instructions issued per launch and the
     share of the chip's VALU issue slots they fill over the kernel's traced duration; None for a
     kernel whose source changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"valu_{workload}.txt")
     out = {"dominance_test": None, "gres_search": None}
     if not os.path.exists(path):
@@ -98,8 +108,7 @@ def stored_valu(workload):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    csrc = os.path.join(ROOT, "paper_2412_02274_amd", "csrc")
-    sha = lambda f: hashlib.sha256(open(os.path.join(csrc, f), "rb").read()).hexdigest()[:16]
+    sha = source_sha
     for name, src in (("dominance_test", "sky_skyline.hip"), ("gres_search", "sky_gres.hip")):
         if kv.get(f"{name}.src_sha256_16") == sha(src):
             out[name] = {"valu_insts_per_launch": float(kv[f"{name}.valu_insts_per_launch"]),

@@ -265,7 +265,7 @@ sky_status launch_representatives(const RepArgs& a, hipStream_t st);
 // Persistent launches: workgroups draw work from kWorkCounters counters kCounterStride int32
 // apart (one 128-byte line each), so that no single address takes every atomic (measured on
 // the gres search: 8 and 128 counters were slower than 32).
-constexpr int kWorkCounters = 32;
+constexpr int kWorkCounters = 64;
 constexpr int kCounterStride = 32;
 // Workgroups of `kernel` (block threads, dyn_lds bytes of dynamic LDS) that the current device
 // holds at once, from the runtime's occupancy calculation.
