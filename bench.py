@@ -397,7 +397,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(x, g_max, n if args.cpu_rows <= 0 else min(args.cpu_rows, n))
     pool.close()
     if args.workload == "ant_1m_d6" and args.scheme == "none" and not args.no_sub:
-        # the other single-GPU workloads, compact: partitioned (three schemes) and serving
+        # the other single-GPU workloads, compact: partitioned (three schemes), serving, the
+        # small relation at a large g_max, and the 4096-relation batch
         pipe.close()
         del pipe, xr
         torch.cuda.empty_cache()
@@ -406,6 +407,9 @@ def main():
         line["sub_results"]["serving"] = {k: m[k] for k in (
             "rate_per_s", "seconds", "latency", "plain_latency", "saturation", "plain_saturation",
             "same_results_as_plain", "max_in_flight", "sky_sizes")}
+        torch.cuda.empty_cache()
+        line["sub_results"]["small"] = sub_small()
+        line["sub_results"]["batch"] = sub_batch()
     print(json.dumps(line), flush=True)
 
 
@@ -416,42 +420,90 @@ def _base_line(args, value, unit, ms, dtype, config, higher=True):
             "config": config}
 
 
-def bench_batch(args):
-    """Many-dataset workload: 4096 relations (log-normal N in [1k, 200k], d in 2..8, uniform and
-    anticorrelated alternating, seed 0); one step = skyline and gres of every relation through
-    the batched path (groups by d, tuned work tables, graph-replayed gres launches)."""
-    import numpy as np
+def batch_measure(steps, warmup):
+    """The 4096-relation batch through the batched path: the relations, the runner (open), the
+    graph-replayed step time in seconds, the skyline total (checked against the oracle's
+    stored total), the phases of one eager step and the stored oracle counts."""
     import torch
     from paper_2412_02274_amd import datagen as G
-    from paper_2412_02274_amd.batch import BatchRunner, GresTuner, PlainRunner
+    from paper_2412_02274_amd.api import check_status
+    from paper_2412_02274_amd.batch import BatchRunner, GresTuner
     from tests.golden import workloads as W
 
     specs = G.batch_specs()
     data = [G.batch_dataset(sp) for sp in specs]
-    dev = torch.device("cuda:0")
-    tuner = GresTuner()
-    run = BatchRunner(data, g_max=25, device=dev, tuner=tuner)
-    for _ in range(max(args.warmup, 1)):  # the first run tunes and captures the step
+    run = BatchRunner(data, g_max=25, device=torch.device("cuda:0"), tuner=GresTuner())
+    for _ in range(max(warmup, 1)):  # the first run tunes and captures the step
         run.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         run.run(check=False)  # graph replay of the whole step
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt = (time.perf_counter() - t0) / steps
     for g in run.groups:
-        from paper_2412_02274_amd.api import check_status
         check_status(g.status, "batch")
     s_total = run.sky_total()
     run.run(timing=True)  # one eager step with an event between the phases
     phases = run.phase_ms()
-    rows = sum(x.shape[0] for x in data)
     counts = None
     if os.path.exists(W.BATCH_COUNTS):
         with open(W.BATCH_COUNTS) as f:
             counts = json.load(f)
         if counts["sky_total"] != s_total:
             raise SystemExit(f"skyline total {s_total} differs from the oracle's {counts['sky_total']}")
+    return specs, data, run, dt, s_total, phases, counts
+
+
+def sub_batch(steps=5):
+    """The 4096-relation batch, compact: graph-replayed step time, skyline tuples per second and
+    the phases of one eager step (the full line: --workload batch_4096)."""
+    specs, data, run, dt, s_total, phases, counts = batch_measure(steps, 1)
+    run.close()
+    return {"workload": "batch_4096", "relations": len(data), "rows": sum(x.shape[0] for x in data),
+            "ms_per_step": dt * 1e3, "sky_total": s_total, "tuples_per_s": s_total / dt,
+            "phase_ms": phases, "sky_total_matches_oracle": counts is not None}
+
+
+def sub_small(steps=20):
+    """The small relation at a large level range (uniform 10,000 x 4, seed 0, g_max 10^4),
+    compact: graph-replayed step time and the skyline size checked against the oracle's."""
+    import torch
+    from paper_2412_02274_amd import api
+    from tests.golden import workloads as W
+    counts = W.load_counts()["uni_10k_d4"]
+    kind, n, d, seed, g_max = W.WORKLOADS["uni_10k_d4"]
+    x = torch.from_numpy(W.make("uni_10k_d4")).to("cuda:0")
+    pipe = api.Pipeline(n, d, "none", 1, 0, g_max, "auto", "cuda:0")
+    pipe.run(x)
+    sky, ge, _ = pipe.result()
+    if int(sky.numel()) != counts["sky_size"]:
+        raise SystemExit(f"small: skyline size {int(sky.numel())} differs from the oracle's")
+    graph = pipe.capture(x)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    del graph
+    pipe.close()
+    return {"workload": "uni_10k_d4", "n": n, "d": d, "g_max": g_max, "ms_per_step": dt * 1e3,
+            "sky_size": int(sky.numel())}
+
+
+def bench_batch(args):
+    """Many-dataset workload: 4096 relations (log-normal N in [1k, 200k], d in 2..8, uniform and
+    anticorrelated alternating, seed 0); one step = skyline and gres of every relation through
+    the batched path (groups by d, tuned work tables, graph-replayed gres launches)."""
+    import numpy as np
+    import torch
+    from paper_2412_02274_amd.batch import PlainRunner
+
+    dev = torch.device("cuda:0")
+    specs, data, run, dt, s_total, phases, counts = batch_measure(args.steps, args.warmup)
+    rows = sum(x.shape[0] for x in data)
     line = _base_line(args, s_total / dt, "skyline tuples/s", dt * 1e3, "f32",
                       {"workload": "batch_4096", "relations": len(data), "rows": rows,
                        "d": "2..8", "kinds": "uni/ant alternating", "seed": 0, "g_max": 25})
