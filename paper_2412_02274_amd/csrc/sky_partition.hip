@@ -990,10 +990,14 @@ void partition_key_layout(int32_t p, int32_t d, int32_t* cbits, int32_t* key_bit
     // three 8-bit passes where they leave the curve at least 4 bits per attribute next to the
     // partition id (a partition is a small part of the data space; measured on 64 partitions
     // of 4 attributes: the fourth pass cost more than the finer order saved), else up to four
-    // (with hundreds of relations of 8 attributes, 1 bit per attribute loses the order)
+    // (with hundreds of relations of 8 attributes, 1 bit per attribute loses the order). One
+    // partition: the fewest passes that keep 2 bits per attribute (measured on 1M x 6 and on
+    // 10M and 10k x 4: each pass saved cost more than the coarser order added; 1 bit per
+    // attribute doubled the tests)
     int passes = (pbits + curve_bits(d) * d + 7) / 8;
     if (passes > 4) passes = 4;
     if (passes == 4 && (24 - pbits) / d >= 4) passes = 3;
+    if (p == 1 && (2 * d + 7) / 8 < passes) passes = (2 * d + 7) / 8;
     int cb = (8 * passes - pbits) / d;
     cb = cb > 16 ? 16 : (cb < 1 ? 1 : cb);
     *cbits = cb;
