@@ -360,12 +360,15 @@ __device__ void round_layout(int32_t nseg, int32_t* __restrict__ info, int32_t* 
         gr += red[1][w];
         mt = red[2][w] > mt ? red[2][w] : mt;
     }
+    // rest groups aim at a quarter of the units: their items mostly fall to the first tiles
+    // they meet, so tile ranges tested side by side repeat tests more than they gain in
+    // parallelism (measured on 10M x 4 rows, one partition: 3% off the step)
     constexpr int64_t kWantUnits = kTargetWaves / (kBlock / kWave);
-    auto tpu_of = [&](int64_t groups) -> int32_t {
-        const int64_t t = (groups * mt + kWantUnits - 1) / kWantUnits;
+    auto tpu_of = [&](int64_t groups, int64_t want) -> int32_t {
+        const int64_t t = (groups * mt + want - 1) / want;
         return (int32_t)(t < 1 ? 1 : (t > mt ? mt : t));
     };
-    const int32_t tpu_h = tpu_of(gh), tpu_r = tpu_of(gr);
+    const int32_t tpu_h = tpu_of(gh, kWantUnits), tpu_r = tpu_of(gr, kWantUnits / 4);
     constexpr int Q = 6;
     __shared__ int32_t carry[Q];
     __shared__ int32_t wsum[Q][kBlock / kWave];
